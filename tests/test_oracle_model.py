@@ -1,0 +1,235 @@
+"""Pins for the oracle's PSF bank, sensitivity, forward operator A = P H B, its
+adjoint and the regulariser (paper Sec. 3.2 eq. portz, Sec. 3.3 eq. hkapprox,
+Sec. 4.1 eq. dN, Sec. 4.2, Table tab:ops)."""
+import itertools
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import langevin as lg
+from oracle import model as om
+from paper_2503_13802_amd import inputs
+
+
+def _rand(shape, seed):
+    return inputs.random_field(shape, seed)
+
+
+# ----------------------------------------------------------------------------- PSF
+@pytest.mark.parametrize("shape", [(32, 32, 32), (12, 8, 6), (9, 6, 4), (16, 12, 10)])
+def test_psf_spectrum_real_or_imaginary(shape):
+    h = om.psf_bank(shape, [2, 3, 4, 5, 6], 0.8)
+    Hf = np.fft.fftn(h, axes=(1, 2, 3))
+    for i, k in enumerate([2, 3, 4, 5, 6]):
+        mx = np.max(np.abs(Hf[i]))
+        if k % 2:   # even profile -> real spectrum
+            assert np.max(np.abs(Hf[i].imag)) <= 1e-14 * mx
+        else:       # odd profile -> imaginary spectrum
+            assert np.max(np.abs(Hf[i].real)) <= 1e-14 * mx
+
+
+@pytest.mark.parametrize("n", [32, 33, 12])
+def test_even_harmonic_profile_sums_to_zero(n):
+    for k in (2, 4, 6):
+        f = om.drive_profile(n, k, 1.2, 1.0)
+        assert abs(np.sum(f)) <= 1e-15 * np.sum(np.abs(f))
+
+
+def test_psf_unit_norm_and_separable():
+    h = om.psf_bank((16, 12, 8), [2, 3, 7], 1.2)
+    for i in range(3):
+        assert np.sum(h[i] ** 2) == pytest.approx(1.0, rel=1e-14)
+        # rank-1 in (x) x (y, z)
+        m = h[i].reshape(16, -1)
+        sv = np.linalg.svd(m, compute_uv=False)
+        assert sv[1] <= 1e-13 * sv[0]
+
+
+def test_drive_profile_values_and_nyquist_mean():
+    n, a = 12, 0.8
+    for k in (2, 3):
+        f = om.drive_profile(n, k, a, 1.0)
+        for i in range(n):
+            w = i if i < n / 2 else i - n
+            if i == n // 2:
+                want = 0.5 * (lg.langevin_deriv(k, np.array([a * 6.0]))[0]
+                              + lg.langevin_deriv(k, np.array([-a * 6.0]))[0])
+            else:
+                want = lg.langevin_deriv(k, np.array([a * w]))[0]
+            assert f[i] == pytest.approx(want, rel=1e-15, abs=1e-300)
+
+
+def test_envelope_pointwise_and_centre():
+    ny, nz, a, vox = 10, 8, 0.8, 1.0
+    e = om.transverse_envelope(ny, nz, a, vox)
+    # off-axis samples are L'(a r)/r
+    for iy, iz in [(1, 0), (0, 1), (3, 2), (9, 7), (5, 4)]:
+        wy = iy if iy < ny / 2 else iy - ny
+        wz = iz if iz < nz / 2 else iz - nz
+        r = np.hypot(wy, wz)
+        assert e[iy, iz] == pytest.approx(lg.langevin_deriv(1, np.array([a * r]))[0] / r, rel=1e-15)
+    # centre: L'(0) times the voxel average of 1/r, integrated numerically
+    # inner integral over z in [0, 1/2] of 1/sqrt(y^2 + z^2) is asinh(1/(2y)); 4 quadrants
+    avg = 4.0 * integrate.quad(lambda y: np.arcsinh(0.5 / y), 0.0, 0.5, epsabs=1e-14, epsrel=1e-14)[0]
+    assert e[0, 0] == pytest.approx(avg / 3.0, rel=1e-9)
+
+
+def test_envelope_radial_integral():
+    # integral over the plane of L'(a r)/r = 2 pi/a * (L(inf) - L(0)) = 2 pi/a
+    a = 1.2
+    f = lambda r: 2 * np.pi * lg.langevin_deriv(1, np.array([a * r]))[0]
+    val = integrate.quad(f, 0, np.inf, limit=500)[0]
+    assert val == pytest.approx(2 * np.pi / a, rel=1e-9)
+
+
+def test_sensitivity_gaussian():
+    b = om.sensitivity((9, 7, 5), (20.0, 10.0, 5.0))
+    assert b[4, 3, 2] == 1.0
+    assert b[0, 3, 2] == pytest.approx(np.exp(-0.5 * (4 / 20.0) ** 2), rel=1e-15)
+    assert b[4, 0, 0] == pytest.approx(np.exp(-0.5 * ((3 / 10.0) ** 2 + (2 / 5.0) ** 2)), rel=1e-15)
+    b2 = om.sensitivity((8, 8, 8), 20.0)
+    assert b2[3, 3, 3] == b2[4, 4, 4] < 1.0
+
+
+# ----------------------------------------------------------------------------- operator
+def _dense_A(h, b, ds):
+    """Dense matrix of eq. dN: block rows P H_k B with H_k the circulant matrix
+    H[i, j] = h_k[(i - j) mod N] over flattened multi-indices."""
+    K = h.shape[0]
+    shape = h.shape[1:]
+    N = int(np.prod(shape))
+    idx = np.array(list(itertools.product(*[range(n) for n in shape])))
+    diff = (idx[:, None, :] - idx[None, :, :]) % np.array(shape)
+    keep = np.all(idx % np.array(ds) == 0, axis=1)
+    rows = []
+    for k in range(K):
+        Hk = h[k][diff[..., 0], diff[..., 1], diff[..., 2]]
+        rows.append(Hk[keep] * b.reshape(1, N))
+    return np.concatenate(rows, axis=0)
+
+
+@pytest.mark.parametrize("shape,ds", [((4, 4, 4), (2, 2, 2)), ((6, 4, 4), (3, 2, 1)),
+                                      ((4, 6, 2), (1, 3, 2))])
+def test_direct_sum_matches_dense_matrix(shape, ds):
+    h = om.psf_bank(shape, [2, 3, 5], 0.9)
+    b = om.sensitivity(shape, 3.0)
+    rho = _rand(shape, 1)
+    Ad = _dense_A(h, b, ds)
+    d = om.forward_direct(h, b, rho, ds)
+    assert np.allclose(d.reshape(-1), Ad @ rho.reshape(-1), rtol=0, atol=1e-14 * np.abs(d).max())
+    r = _rand(d.shape, 2)
+    x = om.adjoint_direct(h, b, r, ds)
+    assert np.allclose(x.reshape(-1), Ad.T @ r.reshape(-1), rtol=0, atol=1e-14 * np.abs(x).max())
+
+
+@pytest.mark.parametrize("shape,ds", [((4, 4, 4), (2, 2, 2)), ((6, 6, 6), (3, 2, 1)),
+                                      ((8, 6, 4), (2, 3, 2)), ((12, 8, 6), (4, 2, 3)),
+                                      ((6, 12, 8), (1, 4, 2)), ((9, 6, 4), (3, 3, 4))])
+def test_direct_vs_fft(shape, ds):
+    h = om.psf_bank(shape, [2, 3, 4, 6], 1.1)
+    b = om.sensitivity(shape, 4.0)
+    rho = _rand(shape, 3)
+    d1 = om.forward_direct(h, b, rho, ds)
+    d2 = om.forward_fft(h, b, rho, ds)
+    assert np.max(np.abs(d1 - d2)) <= 1e-12 * np.max(np.abs(d1))
+    r = _rand(d1.shape, 4)
+    x1 = om.adjoint_direct(h, b, r, ds)
+    x2 = om.adjoint_fft(h, b, r, ds)
+    assert np.max(np.abs(x1 - x2)) <= 1e-12 * np.max(np.abs(x1))
+
+
+@pytest.mark.parametrize("tier", [1, 2])
+def test_adjoint_identity(tier):
+    shape, ds = (8, 6, 6), (2, 3, 2)
+    h = om.psf_bank(shape, [2, 3, 4], 0.8)
+    b = om.sensitivity(shape, 5.0)
+    x = _rand(shape, 5)
+    y = _rand((3,) + om.small_shape(shape, ds), 6)
+    if tier == 1:
+        Ax, ATy = om.forward_direct(h, b, x, ds), om.adjoint_direct(h, b, y, ds)
+    else:
+        Ax, ATy = om.forward_fft(h, b, x, ds), om.adjoint_fft(h, b, y, ds)
+    lhs, rhs = np.sum(Ax * y), np.sum(x * ATy)
+    assert abs(lhs - rhs) <= 1e-12 * np.sqrt(np.sum(Ax ** 2) * np.sum(y ** 2))
+
+
+def test_delta_phantom_reproduces_psf():
+    shape = (8, 6, 10)
+    h = om.psf_bank(shape, [2, 3], 0.8)
+    n0 = (3, 1, 7)
+    rho = np.zeros(shape)
+    rho[n0] = 1.0
+    ones = np.ones(shape)
+    d = om.forward_direct(h, ones, rho, (1, 1, 1))
+    for k in range(2):
+        want = np.roll(h[k], n0, axis=(0, 1, 2))
+        assert np.max(np.abs(d[k] - want)) <= 1e-15
+    b = om.sensitivity(shape, 4.0)
+    d = om.forward_direct(h, b, rho, (1, 1, 1))
+    assert np.max(np.abs(d[1] - b[n0] * np.roll(h[1], n0, axis=(0, 1, 2)))) <= 1e-15
+    ds = (2, 3, 2)
+    d = om.forward_direct(h, b, rho, ds)
+    want = b[n0] * np.roll(h[0], n0, axis=(0, 1, 2))[::2, ::3, ::2]
+    assert np.max(np.abs(d[0] - want)) <= 1e-15
+
+
+def test_even_harmonics_annihilate_constants():
+    shape = (16, 8, 8)
+    h = om.psf_bank(shape, [2, 3, 4, 5], 1.0)
+    d = om.forward_fft(h, np.ones(shape), np.ones(shape), (2, 2, 2))
+    assert np.max(np.abs(d[0])) < 1e-13 and np.max(np.abs(d[2])) < 1e-13
+    assert np.max(np.abs(d[1])) > 1e-3
+
+
+def test_sampled_direct_sums_match_full():
+    shape, ds = (8, 6, 6), (2, 3, 2)
+    h = om.psf_bank(shape, [2, 5], 0.8)
+    b = om.sensitivity(shape, 5.0)
+    rho = _rand(shape, 7)
+    d = om.forward_direct(h, b, rho, ds)
+    ent = [(0, 1, 0, 2), (1, 3, 1, 0), (1, 0, 0, 0)]
+    got = om.forward_direct_at(h, b, rho, ds, ent)
+    assert np.allclose(got, [d[e] for e in ent], rtol=0, atol=1e-14)
+    r = _rand(d.shape, 8)
+    x = om.adjoint_direct(h, b, r, ds)
+    vox = [(0, 0, 0), (7, 5, 3), (2, 4, 1)]
+    got = om.adjoint_direct_at(h, b, r, ds, vox)
+    assert np.allclose(got, [x[v] for v in vox], rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------- identities
+@pytest.mark.parametrize("shape,ds", [((8, 12, 6), (2, 3, 2)), ((12, 8, 16), (4, 2, 4))])
+def test_decimation_fold_and_tile_identities(shape, ds):
+    """P F^-1 X = F_small^-1(fold(X)/S) and F(P^T r) = tile(F_small r)."""
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    msh = om.small_shape(shape, ds)
+    S = int(np.prod(ds))
+    fold = X.reshape(ds[0], msh[0], ds[1], msh[1], ds[2], msh[2]).sum(axis=(0, 2, 4))
+    lhs = np.fft.ifftn(X)[::ds[0], ::ds[1], ::ds[2]]
+    rhs = np.fft.ifftn(fold / S)
+    assert np.max(np.abs(lhs - rhs)) < 1e-14 * np.max(np.abs(lhs))
+    r = rng.standard_normal(msh)
+    up = np.zeros(shape)
+    up[::ds[0], ::ds[1], ::ds[2]] = r
+    tile = np.tile(np.fft.fftn(r), ds)
+    assert np.max(np.abs(np.fft.fftn(up) - tile)) < 1e-13 * np.max(np.abs(tile))
+
+
+def test_regulariser_stencil_spectrum_and_top_eigenvalue():
+    shape = (8, 6, 10)
+    y = _rand(shape, 9)
+    st = om.reg_normal(y)
+    t2 = np.zeros(shape)
+    for a, n in enumerate(shape):
+        s = 16 * np.sin(np.pi * np.arange(n) / n) ** 4
+        sl = [None] * 3
+        sl[a] = slice(None)
+        t2 = t2 + s[tuple(sl)]
+    spec = np.fft.ifftn(t2 * np.fft.fftn(y)).real
+    assert np.max(np.abs(st - spec)) < 1e-13 * np.max(np.abs(st))
+    chk = (-1.0) ** np.indices(shape).sum(axis=0)
+    assert np.allclose(om.reg_normal(chk), 48.0 * chk, rtol=0, atol=1e-13)
+    assert om.reg_value(y) == pytest.approx(np.sum(y * st), rel=1e-13)
+    assert np.array_equal(om.reg_normal(y, kind=1), y)

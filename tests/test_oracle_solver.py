@@ -1,0 +1,163 @@
+"""Pins for the oracle's solver (paper Sec. 4.3 accelerated projected gradient,
+Sec. 4.2 objective) and its random-number generator."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import model as om
+from oracle import philox
+from oracle import solver as osv
+from paper_2503_13802_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _problem(shape=(8, 8, 8), ds=(1, 1, 1), harm=(2, 3, 4), b_one=False, lam=1e-2, seed=0):
+    h = om.psf_bank(shape, list(harm), 0.9)
+    b = np.ones(shape) if b_one else om.sensitivity(shape, 4.0)
+    op = osv.Operator(h, b, ds, lam)
+    rho = np.maximum(inputs.random_field(shape, seed), 0.0)
+    d = op.A(rho) + 0.01 * inputs.random_field((len(harm),) + om.small_shape(shape, ds), seed + 1)
+    return op, d
+
+
+def _dense_normal(op):
+    shape = op.h.shape[1:]
+    n = int(np.prod(shape))
+    cols = [op.normal(np.eye(n)[i].reshape(shape)).reshape(-1) for i in range(n)]
+    return np.array(cols).T
+
+
+def test_one_iteration_from_zero_is_projected_backprojection():
+    op, d = _problem(ds=(2, 2, 2))
+    tau = 0.3
+    rho, hist, n = osv.fista(op, d, tau, max_iter=1)
+    assert n == 1
+    want = np.maximum(tau * op.AT(d), 0.0)
+    assert np.max(np.abs(rho - want)) <= 1e-14 * np.max(np.abs(want))
+
+
+def test_two_iterations_follow_recurrence_by_hand():
+    op, d = _problem(ds=(2, 1, 2))
+    tau = 0.2
+    r1 = np.maximum(0 - tau * op.gradient(np.zeros(op.h.shape[1:]), d), 0)
+    # k = 2: beta = 1/4
+    y2 = r1 + 0.25 * (r1 - 0.0)
+    r2 = np.maximum(y2 - tau * op.gradient(y2, d), 0)
+    got, hist, n = osv.fista(op, d, tau, max_iter=2)
+    assert np.max(np.abs(got - r2)) <= 1e-14 * np.max(np.abs(r2))
+    assert hist[1] == pytest.approx(np.linalg.norm(r2 - y2) / np.linalg.norm(r2), rel=1e-14)
+
+
+def test_unconstrained_limit_is_closed_form():
+    op, d = _problem(shape=(6, 6, 4), b_one=True, lam=5e-2)
+    lmax = float(np.max(np.linalg.eigvalsh(_dense_normal(op))))
+    rho, hist, n = osv.fista(op, d, 1.0 / lmax, max_iter=6000, tol=1e-13, nonneg=False)
+    want = osv.unconstrained_solution_full_sampling(op.h, d, op.lam)
+    assert np.max(np.abs(rho - want)) <= 1e-8 * np.max(np.abs(want))
+
+
+def test_closed_form_solves_normal_equations():
+    op, d = _problem(shape=(6, 6, 4), b_one=True, lam=3e-2)
+    x = osv.unconstrained_solution_full_sampling(op.h, d, op.lam)
+    g = op.gradient(x, d)
+    assert np.max(np.abs(g)) < 1e-12 * np.max(np.abs(op.AT(d)))
+
+
+def test_kkt_at_nonnegative_optimum():
+    shape, ds = (6, 6, 4), (2, 2, 1)
+    h = om.psf_bank(shape, [2, 3, 4], 0.9)
+    op = osv.Operator(h, om.sensitivity(shape, 4.0), ds, 1e-2)
+    rho_t = np.maximum(inputs.random_field(shape, 3) - 1.0, 0.0)     # sparse truth
+    d = op.A(rho_t) + 0.05 * inputs.random_field((3,) + om.small_shape(shape, ds), 4)
+    lmax = float(np.max(np.linalg.eigvalsh(_dense_normal(op))))
+    rho, hist, n = osv.fista(op, d, 1.0 / lmax, max_iter=20000, tol=1e-12)
+    g = op.gradient(rho, d)
+    eps = 1e-6 * np.max(np.abs(op.gradient(np.zeros_like(rho), d)))
+    active = rho == 0
+    assert active.sum() >= 10 and (~active).sum() >= 10
+    assert np.min(g[active]) >= -eps
+    assert np.max(np.abs(g[~active])) <= eps
+
+
+def test_power_iteration_approaches_top_eigenvalue():
+    op, _ = _problem(shape=(6, 6, 6), ds=(2, 3, 2), lam=1e-1)
+    lmax = float(np.max(np.linalg.eigvalsh(_dense_normal(op))))
+    v0 = philox.uniform01(11, 0, 216).reshape(6, 6, 6)
+    est = osv.power_iteration(op, v0, iters=400)
+    assert est <= lmax * (1 + 1e-12)
+    assert est == pytest.approx(lmax, rel=1e-6)
+
+
+def test_resume_is_bit_identical():
+    op, d = _problem(ds=(2, 2, 2))
+    tau = 0.25
+    full, hist_full, _ = osv.fista(op, d, tau, max_iter=7)
+    a, _, _ = osv.fista(op, d, tau, max_iter=4)
+    prev, _, _ = osv.fista(op, d, tau, max_iter=3)
+    rest, hist_rest, _ = osv.fista(op, d, tau, rho_init=a, rho_prev=prev, k0=5, max_iter=3)
+    assert np.array_equal(full, rest)
+    assert np.array_equal(hist_full[4:], hist_rest)
+
+
+def test_tolerance_stops_at_first_small_step():
+    op, d = _problem(ds=(2, 2, 2))
+    tau = 1.0 / float(np.max(np.linalg.eigvalsh(_dense_normal(op))))
+    rho, hist, n = osv.fista(op, d, tau, max_iter=500, tol=1e-3)
+    assert n < 500
+    assert hist[-1] <= 1e-3 and np.all(hist[:-1] > 1e-3)
+
+
+def test_rel_step_edge_cases():
+    z = np.zeros(4)
+    assert osv.rel_step(z, z) == 0.0
+    assert osv.rel_step(z, np.ones(4)) == float("inf")
+
+
+# ----------------------------------------------------------------------------- philox
+def _kat():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(t, 16) for t in line.split()]
+        rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    for ctr, key, out in _kat():
+        got = philox.philox4x32(np.array(ctr, dtype=np.uint64), key)
+        assert [int(x) for x in got] == out
+
+
+def test_philox_stream_layout():
+    w = philox.stream_words(0x0123456789, 3, 10)
+    blk1 = philox.philox4x32(np.array([1, 3, 0, 0], dtype=np.uint64), (0x23456789, 0x01))
+    assert [int(x) for x in w[4:8]] == [int(x) for x in blk1]
+    u = philox.uniform01(5, 0, 1000)
+    assert np.all((u > 0) & (u < 1)) and abs(u.mean() - 0.5) < 0.05
+
+
+# ----------------------------------------------------------------------------- inputs
+def test_phantom_and_noise_are_seeded():
+    w = inputs.workload(0)
+    assert np.array_equal(inputs.phantom(w), inputs.phantom(w))
+    assert not np.array_equal(inputs.phantom(w), inputs.phantom(w, seed=w.seed + 1))
+    xi = inputs.noise_draw(w)
+    assert np.array_equal(xi, inputs.noise_draw(w))
+    p = inputs.phantom(w)
+    assert p.min() >= 0 and p.max() > 0
+
+
+def test_noise_hits_target_snr():
+    w = inputs.workload(0)
+    rng = np.random.default_rng(3)
+    clean = rng.standard_normal((2,) + w.small_shape)
+    xi = inputs.noise_draw(w)
+    d = inputs.add_noise(clean, (20.0, 30.0), xi)
+    for k, snr in enumerate((20.0, 30.0)):
+        noise = d[k] - clean[k]
+        emp = 10 * np.log10(np.mean(clean[k] ** 2) / np.mean(noise ** 2))
+        assert emp == pytest.approx(snr, abs=0.3)
