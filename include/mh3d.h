@@ -1,0 +1,180 @@
+/*
+ * mh3d.h -- C ABI of the MH3D reconstruction hot path on MI355X (gfx950).
+ *
+ * What is computed (Sanders, Konkle, Mason, Goodwill, "Multi-Harmonic Gridded 3D
+ * Deconvolution (MH3D)", arXiv 2503.13802):
+ *   forward   d_k = P ( h_k (*) (b . rho) ),  k in the harmonic list
+ *             -- Sec. 3.2 eq. portz / matrixModelz (z-only sensitivity, scalar b),
+ *                Sec. 4.1 eq. dN (high-resolution model, final row-selector P),
+ *                Table tab:ops (B Hadamard, H_k by FFT with precomputed spectrum,
+ *                P a gather).  (*) is circular 3D convolution (H_k circulant).
+ *   adjoint   rho = A^T d = b . sum_k h_k (x) (P^T d_k)   ((x): correlation)
+ *   solve     argmin_{rho >= 0} 1/2 ||A rho - d||^2 + 1/2 lambda ||T rho||^2
+ *             -- Sec. 4.2 eq. Amodel with the second-order Tikhonov term, solved by
+ *                the accelerated projected gradient of Sec. 4.3.
+ *
+ * PSF model used when no PSF array is supplied (Sec. 3.3 eq. hkapprox; the
+ * transverse envelope and normalisation are readings, see the repository notes):
+ *   h_k(x, y, z) = c_k L^(k + order_offset)(a x) E(r),  r = sqrt(y^2 + z^2),
+ *   E(r) = L'(a r)/r (r > 0), E(0) = L'(0) * 4 asinh(1) / voxel,  ||h_k||_2 = 1,
+ * with L(u) = coth u - 1/u (Sec. 2), samples at voxel centres, periodic, centred
+ * at index 0, the drive axis being array axis 0 (x).
+ *
+ * Conventions
+ *  - Volumes are FP32, C order [nx][ny][nz] (z fastest).  Portraits are FP32
+ *    [n_harm][nx/ds0][ny/ds1][nz/ds2].  P keeps indices 0, ds, 2ds, ... per axis.
+ *  - Every array argument is a DEVICE pointer owned by the caller, 16-byte aligned.
+ *    The library never frees caller memory.  Input and output arrays must not
+ *    overlap.
+ *  - Calls are asynchronous on the plan's stream unless stated otherwise.
+ *  - Errors are returned as mh3d_status; mh3d_last_error() gives a thread-local
+ *    message.  Validation errors are detected on the host before any launch.
+ *  - A plan is immutable and may be used from one host thread / stream at a time.
+ */
+#ifndef MH3D_H
+#define MH3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MH3D_VERSION_MAJOR 0
+#define MH3D_VERSION_MINOR 1
+
+typedef enum {
+  MH3D_OK = 0,
+  MH3D_ERR_INVALID = 1,       /* bad argument or geometry                          */
+  MH3D_ERR_UNSUPPORTED = 2,   /* valid per the paper but not built (padding, alpha) */
+  MH3D_ERR_OOM = 3,           /* device allocation failed                           */
+  MH3D_ERR_HIP = 4,           /* a HIP runtime call failed                          */
+  MH3D_ERR_NOT_CONVERGED = 5, /* solve hit max_iter before the tolerance            */
+  MH3D_ERR_NONFINITE = 6      /* a reduction produced NaN/Inf                       */
+} mh3d_status;
+
+typedef struct mh3d_plan_s* mh3d_plan_t;
+
+/* Geometry and model of one reconstruction problem. */
+typedef struct {
+  int32_t nx, ny, nz;        /* grid; each of the form 2^a 3^b, 4 <= n <= 256, nz even */
+  double voxel_mm;           /* voxel edge (mm), > 0                                     */
+  int32_t ds[3];             /* decimation per axis (P), divides the grid; nz/ds2 even   */
+  int32_t n_harm;            /* number of harmonics, 1..32                               */
+  const int32_t* harm;       /* HOST array of harmonic indices k >= 2, strictly increasing */
+  int32_t order_offset;      /* PSF uses L^(k + order_offset); 0 by default              */
+  double a_per_mm;           /* Langevin argument scale a (1/mm), > 0                    */
+  const float* psf;          /* optional DEVICE [n_harm][nx][ny][nz]; NULL -> analytic    */
+  const float* sens;         /* optional DEVICE [nx][ny][nz]; NULL -> Gaussian sigma_mm  */
+  double sigma_mm[3];        /* Gaussian sensitivity widths (mm), peak 1 at the centre   */
+  double lambda;             /* Tikhonov weight, >= 0                                    */
+  int32_t reg_kind;          /* 0: stacked periodic second differences; 1: T = I         */
+  double alpha;              /* boundary prior weight (eq. finalR); must be 0            */
+  int32_t alpha_width;       /* must be 0                                                */
+  int32_t pad[3];            /* boundary padding (Sec. 4.1.1); must be 0                 */
+  void* stream;              /* hipStream_t all calls on this plan are enqueued on        */
+} mh3d_plan_desc;
+
+/* Solver options (Sec. 4.3). */
+typedef struct {
+  int32_t max_iter;          /* maximum number of updates, >= 1                          */
+  double rel_tol;            /* stop after the first update with r_k <= rel_tol; 0: never */
+  double tau;                /* step size; <= 0 -> 1/(1.05 L), L by power iteration      */
+  int32_t power_iters;       /* power iterations when tau <= 0 (default 50 if 0)         */
+  uint64_t power_seed;       /* Philox4x32-10 seed of the power-iteration start vector   */
+  const float* rho_prev;     /* optional DEVICE rho^{k0-1} to resume; NULL -> rho_inout  */
+  int32_t k0;                /* iteration counter of rho_inout (1 for a fresh start)     */
+  int32_t check_every;       /* host reads the convergence flag every this many updates  */
+  double* history;           /* optional HOST array receiving r_k, length history_len    */
+  int32_t history_len;
+} mh3d_solve_opts;
+
+typedef struct {
+  int32_t iters;             /* updates performed                                        */
+  double rel_step;           /* last r_k = ||rho^{k+1} - y^k|| / ||rho^{k+1}||           */
+  double tau;                /* step size used                                           */
+  double lmax;               /* power-iteration estimate (0 if tau was given)            */
+  float ms_total;            /* wall time of the solve on the stream (ms)                */
+  float ms_per_iter;
+  mh3d_status status;
+} mh3d_solve_info;
+
+/* Sizes the plan would use.  Host only: validates the descriptor and never touches
+ * a GPU.  Any output pointer may be NULL. */
+mh3d_status mh3d_plan_describe(const mh3d_plan_desc* desc, size_t* device_bytes,
+                               int64_t* n_volume, int64_t* n_portrait);
+
+/* Builds a plan: validates, allocates device memory, generates the PSF spectra in
+ * FP64 (analytic model) or from desc->psf, and the sensitivity map.  Synchronous. */
+mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out);
+
+/* Releases the plan's device memory (synchronises its stream). NULL is a no-op. */
+void mh3d_destroy(mh3d_plan_t plan);
+
+/* d = A rho (Sec. 4.1 eq. dN).  rho: [nx][ny][nz], d: [n_harm][mx][my][mz]. */
+mh3d_status mh3d_forward(mh3d_plan_t plan, const float* rho, float* d);
+
+/* rho = A^T d (adjoint of eq. dN).  d: portraits, rho: volume. */
+mh3d_status mh3d_adjoint(mh3d_plan_t plan, const float* d, float* rho);
+
+/* out = (A^T A + lambda T^T T) x, the normal operator of Sec. 4.3's stacked M. */
+mh3d_status mh3d_normal(mh3d_plan_t plan, const float* x, float* out);
+
+/* Power iteration on A^T A + lambda T^T T from a Philox4x32-10 uniform start vector
+ * (counter (i/4, 0, 0, 0), key (seed lo, seed hi), word i%4, value (w+0.5)/2^32).
+ * v_0 = x0/||x0||; w = N v; L = <v, w>; v = w/||w||, iters times.  FP32 operator
+ * applications, FP64 dot products.  Writes L to *lmax (host).  Synchronous. */
+mh3d_status mh3d_power_iteration(mh3d_plan_t plan, int32_t iters, uint64_t seed, double* lmax);
+
+/* Nonnegative Tikhonov least squares by accelerated projected gradient (Sec. 4.3):
+ * rho^0 = rho^1 = rho_inout (or rho_prev for rho^{k0-1}), for k = k0, k0+1, ...
+ *   y^k = rho^k + (k-1)/(k+2) (rho^k - rho^{k-1}),
+ *   rho^{k+1} = max(y^k - tau (A^T (A y^k - d) + lambda T^T T y^k), 0),
+ * r_k = ||rho^{k+1} - y^k|| / ||rho^{k+1}|| (FP64).  On return rho_inout holds the
+ * last iterate (also on MH3D_ERR_NOT_CONVERGED).  Synchronous. */
+mh3d_status mh3d_solve(mh3d_plan_t plan, const float* d, float* rho_inout,
+                       const mh3d_solve_opts* opts, mh3d_solve_info* info);
+
+/* Copies internal plan data to a caller DEVICE buffer, for tests and tools.
+ *   MH3D_FIELD_PROFILE   FP64 [n_harm][nx]      drive-axis profiles L^(k)(a x), raw
+ *   MH3D_FIELD_ENVELOPE  FP64 [ny][nz]          transverse envelope E, raw
+ *   MH3D_FIELD_SENS      FP32 [nx][ny][nz]      sensitivity b
+ *   MH3D_FIELD_SPECTRUM  FP32 complex [n_harm][nx][ny][nz/2+1]  fft(h_k) (unnormalised
+ *                        DFT of the unit-norm PSF), read back from the plan's layout
+ * *bytes receives the size needed; dst may be NULL to query it. */
+typedef enum {
+  MH3D_FIELD_PROFILE = 0,
+  MH3D_FIELD_ENVELOPE = 1,
+  MH3D_FIELD_SENS = 2,
+  MH3D_FIELD_SPECTRUM = 3
+} mh3d_field;
+mh3d_status mh3d_plan_export(mh3d_plan_t plan, mh3d_field field, void* dst, size_t* bytes);
+
+/* Per-kernel timing with HIP events around every launch of the plan's kernels
+ * (enable = 1 starts and clears, 0 stops).  mh3d_profile_read synchronises and
+ * returns the cumulative milliseconds and launch counts per kernel id, plus names. */
+#define MH3D_NKERNEL 8
+typedef struct {
+  double ms[MH3D_NKERNEL];
+  int64_t launches[MH3D_NKERNEL];
+  const char* name[MH3D_NKERNEL];
+} mh3d_profile_data;
+mh3d_status mh3d_profile(mh3d_plan_t plan, int32_t enable);
+mh3d_status mh3d_profile_read(mh3d_plan_t plan, mh3d_profile_data* out);
+
+/* One Philox4x32-10 block computed on the device (known-answer checks of the
+ * generator used by mh3d_power_iteration).  ctr[4], key[2], out[4] are HOST
+ * arrays.  Synchronous. */
+mh3d_status mh3d_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+
+/* Thread-local text of the last error (never NULL). */
+const char* mh3d_last_error(void);
+
+/* Library version as MAJOR*100 + MINOR. */
+int32_t mh3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MH3D_H */

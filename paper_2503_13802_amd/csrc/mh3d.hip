@@ -1,0 +1,787 @@
+// Host side of the MH3D C ABI (include/mh3d.h): plan construction, launch-shape
+// selection with host-side fit checks, operator application, power iteration and
+// the accelerated projected gradient solver (paper Sec. 4.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mh3d.h"
+#include "kernels.hpp"
+
+using namespace mh3d;
+
+// ============================================================================ errors
+static thread_local std::string g_err = "no error";
+
+static mh3d_status fail(mh3d_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(MH3D_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                 \
+  } while (0)
+
+extern "C" const char* mh3d_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t mh3d_version(void) { return MH3D_VERSION_MAJOR * 100 + MH3D_VERSION_MINOR; }
+
+// ============================================================================ geometry
+static bool is_23_smooth(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+static const size_t kLdsLimit = 160 * 1024;
+
+struct Launch {
+  int T_plane, T_class, T_small;
+  size_t lds_plane, lds_class, lds_small;
+};
+
+// Elements per thread in the class kernel: largest e <= 8 dividing S with S/e a
+// power of two <= 64 (so the fold reduction stays inside aligned lane groups).
+static int pick_E(int S) {
+  const int opts[6] = {8, 6, 4, 3, 2, 1};
+  for (int e : opts) {
+    if (S % e) continue;
+    int lg = S / e;
+    if (lg <= 64 && (lg & (lg - 1)) == 0) return e;
+  }
+  return -1;
+}
+
+static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
+  if (!d) return fail(MH3D_ERR_INVALID, "descriptor is NULL");
+  const int n[3] = {d->nx, d->ny, d->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 4 || n[a] > 256 || !is_23_smooth(n[a]))
+      return fail(MH3D_ERR_INVALID, "grid axis %d = %d must be 2^a 3^b in [4, 256]", a, n[a]);
+    if (d->ds[a] < 1 || n[a] % d->ds[a])
+      return fail(MH3D_ERR_INVALID, "decimation ds[%d] = %d must divide %d", a, d->ds[a], n[a]);
+    if (n[a] / d->ds[a] < 2)
+      return fail(MH3D_ERR_INVALID, "decimated axis %d has fewer than 2 samples", a);
+  }
+  if (d->nz % 2) return fail(MH3D_ERR_INVALID, "nz must be even");
+  if ((d->nz / d->ds[2]) % 2) return fail(MH3D_ERR_INVALID, "nz/ds[2] must be even");
+  if (!(d->voxel_mm > 0)) return fail(MH3D_ERR_INVALID, "voxel_mm must be > 0");
+  if (d->n_harm < 1 || d->n_harm > 32) return fail(MH3D_ERR_INVALID, "n_harm must be in [1, 32]");
+  if (!d->harm) return fail(MH3D_ERR_INVALID, "harm is NULL");
+  for (int i = 0; i < d->n_harm; ++i) {
+    if (d->harm[i] < 2) return fail(MH3D_ERR_INVALID, "harmonic %d < 2", d->harm[i]);
+    if (i && d->harm[i] <= d->harm[i - 1]) return fail(MH3D_ERR_INVALID, "harmonics must increase strictly");
+    if (d->harm[i] + d->order_offset < 1 || d->harm[i] + d->order_offset > 24)
+      return fail(MH3D_ERR_INVALID, "derivative order k + order_offset must be in [1, 24]");
+  }
+  if (!d->psf && !(d->a_per_mm > 0)) return fail(MH3D_ERR_INVALID, "a_per_mm must be > 0");
+  if (!d->sens)
+    for (int a = 0; a < 3; ++a)
+      if (!(d->sigma_mm[a] > 0)) return fail(MH3D_ERR_INVALID, "sigma_mm[%d] must be > 0", a);
+  if (!(d->lambda >= 0)) return fail(MH3D_ERR_INVALID, "lambda must be >= 0");
+  if (d->reg_kind != 0 && d->reg_kind != 1) return fail(MH3D_ERR_INVALID, "reg_kind must be 0 or 1");
+  if (d->alpha != 0.0 || d->alpha_width != 0)
+    return fail(MH3D_ERR_UNSUPPORTED, "boundary prior alpha (eq. finalR) is not built; use alpha = 0");
+  if (d->pad[0] || d->pad[1] || d->pad[2])
+    return fail(MH3D_ERR_UNSUPPORTED, "boundary padding is not built; use pad = 0");
+
+  memset(&g, 0, sizeof g);
+  g.nx = d->nx; g.ny = d->ny; g.nz = d->nz; g.nzh = g.nz / 2 + 1;
+  g.sx = d->ds[0]; g.sy = d->ds[1]; g.sz = d->ds[2];
+  g.mx = g.nx / g.sx; g.my = g.ny / g.sy; g.mz = g.nz / g.sz; g.mzh = g.mz / 2 + 1;
+  g.S = g.sx * g.sy * g.sz;
+  g.nmem = g.sy * g.sz;
+  g.ncls = g.my * g.mzh;
+  g.plane = g.ncls * g.nmem;
+  g.K = d->n_harm;
+  g.npairs = (g.ny + 1) / 2;
+  g.N = (long long)g.nx * g.ny * g.nz;
+  g.M = (long long)g.mx * g.my * g.mz;
+  g.hsz = (long long)g.plane * g.nx;
+  g.E = pick_E(g.S);
+  if (g.E < 0) return fail(MH3D_ERR_UNSUPPORTED, "decimation product %d has no supported fold split", g.S);
+
+  // ---- class kernel: classes per workgroup (cpw divides ncls; T = cpw*mx*S/E)
+  int best_cpw = 0;
+  for (int c = 1; c <= g.ncls; ++c) {
+    if (g.ncls % c) continue;
+    const long T = (long)c * g.mx * g.S / g.E;
+    if (T > 1024) break;
+    Geo t = g;
+    t.cpw = c;
+    if (class_lds_elems(t) * sizeof(float2) > 64 * 1024) break;
+    best_cpw = c;
+    if (T >= 256 && T % 64 == 0) break;
+  }
+  if (!best_cpw) return fail(MH3D_ERR_UNSUPPORTED, "no class-kernel shape fits (mx*S/E or LDS too large)");
+  g.cpw = best_cpw;
+  L.T_class = g.cpw * g.mx * g.S / g.E;
+  L.lds_class = class_lds_elems(g) * sizeof(float2);
+
+  // ---- small kernel: x' planes per workgroup (aim for >= 256 workgroups)
+  g.xb = 1;
+  for (int xb : {8, 4, 2, 1}) {
+    if (g.mx % xb) continue;
+    if ((long)g.K * (g.mx / xb) >= 256 || xb == 1) { g.xb = xb; break; }
+  }
+  g.spairs = (g.xb * g.my + 1) / 2;
+  L.T_small = 256;
+  L.lds_small = sizeof(float2) * ((size_t)g.my + g.mz + 2 * (size_t)small_lds(g));
+  if (L.lds_small > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "small-grid plane does not fit in LDS");
+
+  // ---- plane kernels
+  L.T_plane = 1024;
+  L.lds_plane = sizeof(float2) * ((size_t)g.ny + g.nz + 2 * (size_t)plane_lds(g));
+  if (L.lds_plane > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "x-plane of %dx%d does not fit in LDS", g.ny, g.nz);
+  return MH3D_OK;
+}
+
+// ============================================================================ plan
+enum { KID_PLANE_FWD = 0, KID_CLASS_FWD, KID_SMALL_INV, KID_SMALL_FWD, KID_CLASS_ADJ, KID_PLANE_ADJ, KID_AUX, KID_SOLVE_ITER };
+static const char* kKernelNames[MH3D_NKERNEL] = {"plane_fwd", "class_fwd", "small_inv", "small_fwd",
+                                                  "class_adj", "plane_adj", "aux", "solve_iter"};
+
+struct mh3d_plan_s {
+  mh3d_plan_desc desc;
+  std::vector<int> harm;
+  Geo g;
+  Launch L;
+  hipStream_t stream;
+  int compact;
+  uint32_t imag_mask;
+  // device memory
+  void* hs = nullptr;          // spectra in class layout
+  float* b = nullptr;          // sensitivity
+  float2* uperm = nullptr;     // class-layout yz spectra of one volume (also adjoint V)
+  float2* G = nullptr;         // decimated spectra (forward)
+  float2* Gp = nullptr;        // decimated spectra (adjoint)
+  float* vol[3] = {nullptr, nullptr, nullptr};  // solver iterates / power vectors
+  float* port = nullptr;       // portrait scratch
+  float2* tw32 = nullptr;
+  double2* tw64 = nullptr;
+  int off[6];                  // table offsets for nx, ny, nz, mx, my, mz
+  double* prof = nullptr;      // [K][nx]
+  double* env = nullptr;       // [ny][nz]
+  double* partials = nullptr;
+  DevState* st = nullptr;      // solver / power state
+  size_t bytes = 0;
+  // profiling
+  bool prof_on = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> free_events;
+  double ms[MH3D_NKERNEL];
+  int64_t launches[MH3D_NKERNEL];
+};
+
+static mh3d_status dalloc(mh3d_plan_t p, void** ptr, size_t bytes) {
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    *ptr = nullptr;
+    return fail(MH3D_ERR_OOM, "hipMalloc(%zu) failed", bytes);
+  }
+  p->bytes += bytes;
+  return MH3D_OK;
+}
+
+static size_t plan_bytes(const Geo& g, bool compact) {
+  size_t s = 0;
+  s += (size_t)g.K * g.hsz * (compact ? 4 : 8);
+  s += (size_t)g.N * 4;                               // b
+  s += (size_t)g.nx * g.plane * 8;                    // uperm
+  s += 2 * (size_t)g.K * g.mx * g.ncls * 8;           // G, Gp
+  s += 3 * (size_t)g.N * 4;                           // vol
+  s += (size_t)g.K * g.M * 4;                         // port
+  s += (size_t)(2 * (g.nx + g.ny + g.nz) + g.mx + g.my + g.mz) * 24;
+  s += ((size_t)g.K * g.nx + (size_t)g.ny * g.nz) * 8;
+  return s;
+}
+
+extern "C" mh3d_status mh3d_plan_describe(const mh3d_plan_desc* desc, size_t* device_bytes,
+                                          int64_t* n_volume, int64_t* n_portrait) {
+  Geo g;
+  Launch L;
+  mh3d_status s = build_geo(desc, g, L);
+  if (s != MH3D_OK) return s;
+  if (device_bytes) *device_bytes = plan_bytes(g, desc->psf == nullptr);
+  if (n_volume) *n_volume = g.N;
+  if (n_portrait) *n_portrait = (int64_t)g.K * g.M;
+  return MH3D_OK;
+}
+
+// ---------------------------------------------------------------------------- profiling helpers
+struct Timer {
+  mh3d_plan_t p;
+  int kid;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer(mh3d_plan_t p_, int kid_) : p(p_), kid(kid_) {
+    if (!p->prof_on) return;
+    if (p->free_events.size() >= 2) {
+      a = p->free_events.back(); p->free_events.pop_back();
+      b = p->free_events.back(); p->free_events.pop_back();
+    } else {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+    }
+    hipEventRecord(a, p->stream);
+  }
+  ~Timer() {
+    if (!a) return;
+    hipEventRecord(b, p->stream);
+    p->pending.push_back({kid, {a, b}});
+    if (p->pending.size() > 4096) {
+      for (auto& e : p->pending) {
+        float ms = 0.f;
+        hipEventSynchronize(e.second.second);
+        hipEventElapsedTime(&ms, e.second.first, e.second.second);
+        p->ms[e.first] += ms;
+        p->launches[e.first] += 1;
+        p->free_events.push_back(e.second.first);
+        p->free_events.push_back(e.second.second);
+      }
+      p->pending.clear();
+    }
+  }
+};
+
+static mh3d_status last_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MH3D_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return MH3D_OK;
+}
+
+// ---------------------------------------------------------------------------- dispatchers
+static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a, const float* a2, float coef, DevState* st) {
+  const Geo& g = p->g;
+  Timer t(p, KID_PLANE_FWD);
+  dim3 grid(g.nx), block(p->L.T_plane);
+  const size_t lds = p->L.lds_plane;
+  const float2* twy = p->tw32 + p->off[1];
+  const float2* twz = p->tw32 + p->off[2];
+  switch (src) {
+    case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
+    case SRC_RAW: k_plane_fwd<SRC_RAW><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
+    case SRC_FISTA_Y: k_plane_fwd<SRC_FISTA_Y><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
+    default: k_plane_fwd<SRC_SCALED><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
+  }
+  return last_launch("k_plane_fwd");
+}
+
+template <int HC, int E>
+static void class_fwd_t(mh3d_plan_t p, DevState* st) {
+  const Geo& g = p->g;
+  k_class_fwd<HC, E><<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->stream>>>(
+      g, p->uperm, p->hs, p->imag_mask, st, p->G, p->tw32 + p->off[0], p->tw32 + p->off[3]);
+}
+template <int HC, int E>
+static void class_adj_t(mh3d_plan_t p, DevState* st) {
+  const Geo& g = p->g;
+  k_class_adj<HC, E><<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->stream>>>(
+      g, p->Gp, p->hs, p->imag_mask, st, p->uperm, p->tw32 + p->off[0], p->tw32 + p->off[3]);
+}
+
+#define E_DISPATCH(HCV, FN)                       \
+  switch (p->g.E) {                               \
+    case 8: FN<HCV, 8>(p, st); break;             \
+    case 6: FN<HCV, 6>(p, st); break;             \
+    case 4: FN<HCV, 4>(p, st); break;             \
+    case 3: FN<HCV, 3>(p, st); break;             \
+    case 2: FN<HCV, 2>(p, st); break;             \
+    default: FN<HCV, 1>(p, st); break;            \
+  }
+
+static mh3d_status launch_class_fwd(mh3d_plan_t p, DevState* st) {
+  Timer t(p, KID_CLASS_FWD);
+  if (p->compact) { E_DISPATCH(0, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
+  return last_launch("k_class_fwd");
+}
+static mh3d_status launch_class_adj(mh3d_plan_t p, DevState* st) {
+  Timer t(p, KID_CLASS_ADJ);
+  if (p->compact) { E_DISPATCH(0, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
+  return last_launch("k_class_adj");
+}
+
+static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d, const float* dmeas, DevState* st) {
+  const Geo& g = p->g;
+  Timer t(p, KID_SMALL_INV);
+  dim3 grid(g.K * (g.mx / g.xb)), block(p->L.T_small);
+  const size_t lds = p->L.lds_small;
+  const float2* twy = p->tw32 + p->off[4];
+  const float2* twz = p->tw32 + p->off[5];
+  switch (epi) {
+    case EPI_STORE: k_small_inv<EPI_STORE><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
+    case EPI_RESID: k_small_inv<EPI_RESID><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
+    case EPI_RESID_BACK: k_small_inv<EPI_RESID_BACK><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
+    default: k_small_inv<EPI_BACK><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
+  }
+  return last_launch("k_small_inv");
+}
+
+static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r) {
+  const Geo& g = p->g;
+  Timer t(p, KID_SMALL_FWD);
+  k_small_fwd<<<dim3(g.K * (g.mx / g.xb)), dim3(p->L.T_small), p->L.lds_small, p->stream>>>(
+      g, r, p->Gp, p->tw32 + p->off[4], p->tw32 + p->off[5]);
+  return last_launch("k_small_fwd");
+}
+
+static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, const AdjOut& ao) {
+  const Geo& g = p->g;
+  Timer t(p, KID_PLANE_ADJ);
+  dim3 grid(g.nx), block(p->L.T_plane);
+  const size_t lds = p->L.lds_plane;
+  const float2* twy = p->tw32 + p->off[1];
+  const float2* twz = p->tw32 + p->off[2];
+  switch (out) {
+    case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->stream>>>(g, p->uperm, p->b, ao, twy, twz); break;
+    case OUT_NORMAL: k_plane_adj<OUT_NORMAL><<<grid, block, lds, p->stream>>>(g, p->uperm, p->b, ao, twy, twz); break;
+    default: k_plane_adj<OUT_FISTA><<<grid, block, lds, p->stream>>>(g, p->uperm, p->b, ao, twy, twz); break;
+  }
+  return last_launch("k_plane_adj");
+}
+
+#define CHK(x)                          \
+  do {                                  \
+    mh3d_status s_ = (x);               \
+    if (s_ != MH3D_OK) return s_;       \
+  } while (0)
+
+// ---------------------------------------------------------------------------- state init
+__global__ void k_state_set(DevState* st, DevState v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *st = v;
+}
+
+static mh3d_status state_set(mh3d_plan_t p, const DevState& v) {
+  Timer t(p, KID_AUX);
+  hipLaunchKernelGGL(k_state_set, dim3(1), dim3(64), 0, p->stream, p->st, v);
+  return last_launch("k_state_set");
+}
+
+// ---------------------------------------------------------------------------- plan build
+static mh3d_status build_tables(mh3d_plan_t p) {
+  const Geo& g = p->g;
+  const int lens[6] = {g.nx, g.ny, g.nz, g.mx, g.my, g.mz};
+  int total = 0;
+  for (int i = 0; i < 6; ++i) { p->off[i] = total; total += lens[i]; }
+  CHK(dalloc(p, (void**)&p->tw32, sizeof(float2) * total));
+  CHK(dalloc(p, (void**)&p->tw64, sizeof(double2) * total));
+  for (int i = 0; i < 6; ++i) {
+    hipLaunchKernelGGL(k_twiddles, dim3(1), dim3(256), 0, p->stream, lens[i], p->tw32 + p->off[i], p->tw64 + p->off[i]);
+    CHK(last_launch("k_twiddles"));
+  }
+  return MH3D_OK;
+}
+
+static mh3d_status build_spectra_analytic(mh3d_plan_t p) {
+  const Geo& g = p->g;
+  const mh3d_plan_desc& d = p->desc;
+  std::vector<int> order(g.K);
+  p->imag_mask = 0;
+  for (int k = 0; k < g.K; ++k) {
+    order[k] = p->harm[k] + d.order_offset;
+    if (order[k] % 2 == 0) p->imag_mask |= (1u << k);   // odd profile -> imaginary spectrum
+  }
+  int* d_order = nullptr;
+  double2 *fhat = nullptr, *tmp = nullptr, *ehat = nullptr;
+  double *fn2 = nullptr, *rows = nullptr, *scale = nullptr;
+  size_t keep = p->bytes;
+  CHK(dalloc(p, (void**)&d_order, sizeof(int) * g.K));
+  CHK(dalloc(p, (void**)&fhat, sizeof(double2) * g.K * g.nx));
+  CHK(dalloc(p, (void**)&tmp, sizeof(double2) * g.ny * g.nz));
+  CHK(dalloc(p, (void**)&ehat, sizeof(double2) * g.ny * g.nzh));
+  CHK(dalloc(p, (void**)&fn2, sizeof(double) * g.K));
+  CHK(dalloc(p, (void**)&rows, sizeof(double) * g.ny));
+  CHK(dalloc(p, (void**)&scale, sizeof(double) * g.K));
+  HIPCHK(hipMemcpyAsync(d_order, order.data(), sizeof(int) * g.K, hipMemcpyHostToDevice, p->stream));
+  const int T = 256;
+  hipLaunchKernelGGL(k_psf_profile, dim3(g.K), dim3(T), sizeof(double2) * 3 * g.nx, p->stream, g.nx, d_order,
+                     d.a_per_mm * d.voxel_mm, p->tw64 + p->off[0], p->prof, fhat, fn2);
+  CHK(last_launch("k_psf_profile"));
+  hipLaunchKernelGGL(k_psf_env_rows, dim3(g.ny), dim3(T), sizeof(double2) * 3 * g.nz, p->stream, g.ny, g.nz,
+                     d.a_per_mm, d.voxel_mm, p->tw64 + p->off[2], p->env, tmp, rows);
+  CHK(last_launch("k_psf_env_rows"));
+  hipLaunchKernelGGL(k_psf_env_cols, dim3(g.nzh), dim3(T), sizeof(double2) * 3 * g.ny, p->stream, g.ny, g.nz,
+                     p->tw64 + p->off[1], tmp, ehat);
+  CHK(last_launch("k_psf_env_cols"));
+  hipLaunchKernelGGL(k_psf_scales, dim3(1), dim3(64), 0, p->stream, g.K, g.ny, g.N, fn2, rows, scale);
+  CHK(last_launch("k_psf_scales"));
+  hipLaunchKernelGGL(k_psf_assemble, dim3(2048), dim3(256), 0, p->stream, g, fhat, ehat, scale, p->imag_mask, 1, p->hs);
+  CHK(last_launch("k_psf_assemble"));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  hipFree(d_order); hipFree(fhat); hipFree(tmp); hipFree(ehat); hipFree(fn2); hipFree(rows); hipFree(scale);
+  p->bytes = keep;
+  return MH3D_OK;
+}
+
+static mh3d_status build_spectra_user(mh3d_plan_t p) {
+  const Geo& g = p->g;
+  p->imag_mask = 0;
+  size_t lds = sizeof(float2) * ((size_t)g.nx + 2 * (size_t)g.nx * g.cpw * g.nmem);
+  for (int k = 0; k < g.K; ++k) {
+    CHK(launch_plane_fwd(p, SRC_RAW, p->desc.psf + (long long)k * g.N, nullptr, 1.f, nullptr));
+    k_class_hcopy<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), lds, p->stream>>>(g, k, p->uperm,
+                         reinterpret_cast<float2*>(p->hs), p->tw32 + p->off[0]);
+    CHK(last_launch("k_class_hcopy"));
+  }
+  return MH3D_OK;
+}
+
+extern "C" void mh3d_destroy(mh3d_plan_t p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  for (auto& e : p->pending) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
+  for (auto e : p->free_events) hipEventDestroy(e);
+  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->port,
+                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st};
+  for (void* q : bufs)
+    if (q) hipFree(q);
+  delete p;
+}
+
+extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
+  if (!out) return fail(MH3D_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  Geo g;
+  Launch L;
+  CHK(build_geo(desc, g, L));
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
+    return fail(MH3D_ERR_HIP, "no HIP device available");
+  mh3d_plan_t p = new mh3d_plan_s();
+  p->desc = *desc;
+  p->harm.assign(desc->harm, desc->harm + desc->n_harm);
+  p->desc.harm = p->harm.data();
+  p->g = g;
+  p->L = L;
+  p->stream = reinterpret_cast<hipStream_t>(desc->stream);
+  p->compact = desc->psf ? 0 : 1;
+  memset(p->ms, 0, sizeof p->ms);
+  memset(p->launches, 0, sizeof p->launches);
+  auto bail = [&](mh3d_status s) { mh3d_destroy(p); return s; };
+  mh3d_status s;
+  const size_t hbytes = (size_t)g.K * g.hsz * (p->compact ? sizeof(float) : sizeof(float2));
+  if ((s = dalloc(p, &p->hs, hbytes)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->b, sizeof(float) * g.N)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->uperm, sizeof(float2) * (size_t)g.nx * g.plane)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->G, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->Gp, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
+  for (int i = 0; i < 3; ++i)
+    if ((s = dalloc(p, (void**)&p->vol[i], sizeof(float) * g.N)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->port, sizeof(float) * (size_t)g.K * g.M)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->prof, sizeof(double) * (size_t)g.K * g.nx)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->env, sizeof(double) * (size_t)g.ny * g.nz)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->partials, sizeof(double) * 2 * 4096)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->st, sizeof(DevState))) != MH3D_OK) return bail(s);
+  if ((s = build_tables(p)) != MH3D_OK) return bail(s);
+  // sensitivity
+  if (desc->sens) {
+    if (hipMemcpyAsync(p->b, desc->sens, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+      return bail(fail(MH3D_ERR_HIP, "copy of the sensitivity map failed"));
+  } else {
+    hipLaunchKernelGGL(k_sensitivity, dim3(1024), dim3(256), 0, p->stream, g, desc->voxel_mm, desc->sigma_mm[0],
+                       desc->sigma_mm[1], desc->sigma_mm[2], p->b);
+    if ((s = last_launch("k_sensitivity")) != MH3D_OK) return bail(s);
+  }
+  DevState z;
+  memset(&z, 0, sizeof z);
+  if ((s = state_set(p, z)) != MH3D_OK) return bail(s);
+  if (p->compact) s = build_spectra_analytic(p);
+  else s = build_spectra_user(p);
+  if (s != MH3D_OK) return bail(s);
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(fail(MH3D_ERR_HIP, "plan build failed on the device"));
+  *out = p;
+  return MH3D_OK;
+}
+
+// ============================================================================ operators
+static mh3d_status check_plan(mh3d_plan_t p) {
+  if (!p) return fail(MH3D_ERR_INVALID, "plan is NULL");
+  return MH3D_OK;
+}
+
+static mh3d_status apply_A(mh3d_plan_t p, const float* rho, float* d) {
+  CHK(launch_plane_fwd(p, SRC_PLAIN, rho, nullptr, 1.f, nullptr));
+  CHK(launch_class_fwd(p, nullptr));
+  CHK(launch_small_inv(p, EPI_STORE, d, nullptr, nullptr));
+  return MH3D_OK;
+}
+
+static mh3d_status apply_AT(mh3d_plan_t p, const float* d, float* rho) {
+  CHK(launch_small_fwd(p, d));
+  CHK(launch_class_adj(p, nullptr));
+  AdjOut ao;
+  memset(&ao, 0, sizeof ao);
+  ao.out = rho;
+  CHK(launch_plane_adj(p, OUT_SCALE_B, ao));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
+  CHK(check_plan(p));
+  if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
+  return apply_A(p, rho, d);
+}
+
+extern "C" mh3d_status mh3d_adjoint(mh3d_plan_t p, const float* d, float* rho) {
+  CHK(check_plan(p));
+  if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
+  return apply_AT(p, d, rho);
+}
+
+// normal operator on x (scale 1): out = A^T A x + lambda T^T T x
+static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out) {
+  CHK(launch_plane_fwd(p, SRC_SCALED, w, nullptr, 1.f, p->st));
+  CHK(launch_class_fwd(p, p->st));
+  CHK(launch_small_inv(p, EPI_BACK, nullptr, nullptr, p->st));
+  CHK(launch_class_adj(p, p->st));
+  AdjOut ao;
+  memset(&ao, 0, sizeof ao);
+  ao.out = out;
+  ao.vin = w;
+  ao.partials = p->partials;
+  ao.st = p->st;
+  ao.reg_kind = p->desc.reg_kind;
+  ao.lam = (float)p->desc.lambda;
+  CHK(launch_plane_adj(p, OUT_NORMAL, ao));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_normal(mh3d_plan_t p, const float* x, float* out) {
+  CHK(check_plan(p));
+  if (!x || !out) return fail(MH3D_ERR_INVALID, "NULL array");
+  DevState z;
+  memset(&z, 0, sizeof z);
+  z.scale = 1.0;
+  CHK(state_set(p, z));
+  return apply_normal_scaled(p, x, out);
+}
+
+static mh3d_status read_state(mh3d_plan_t p, DevState& h) {
+  HIPCHK(hipMemcpyAsync(&h, p->st, sizeof h, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return MH3D_OK;
+}
+
+static mh3d_status power_iteration(mh3d_plan_t p, int iters, uint64_t seed, double* lmax) {
+  const Geo& g = p->g;
+  DevState z;
+  memset(&z, 0, sizeof z);
+  CHK(state_set(p, z));
+  {
+    Timer t(p, KID_AUX);
+    hipLaunchKernelGGL(k_philox_uniform, dim3(256), dim3(256), 0, p->stream, (long long)g.N, seed, 0u, p->vol[0],
+                       p->partials, p->st);
+    CHK(last_launch("k_philox_uniform"));
+  }
+  int cur = 0;
+  for (int t = 0; t < iters; ++t) {
+    CHK(apply_normal_scaled(p, p->vol[cur], p->vol[1 - cur]));
+    cur = 1 - cur;
+  }
+  DevState h;
+  CHK(read_state(p, h));
+  if (h.nonfinite != 0.0 || !std::isfinite(h.lmax)) return fail(MH3D_ERR_NONFINITE, "power iteration produced a non-finite value");
+  *lmax = h.lmax;
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64_t seed, double* lmax) {
+  CHK(check_plan(p));
+  if (!lmax || iters < 1) return fail(MH3D_ERR_INVALID, "bad power-iteration arguments");
+  return power_iteration(p, iters, seed, lmax);
+}
+
+// ============================================================================ solver
+extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
+                                  mh3d_solve_info* info) {
+  CHK(check_plan(p));
+  if (!d || !rho_inout || !opts) return fail(MH3D_ERR_INVALID, "NULL argument");
+  if (opts->max_iter < 1) return fail(MH3D_ERR_INVALID, "max_iter must be >= 1");
+  if (opts->k0 < 1) return fail(MH3D_ERR_INVALID, "k0 must be >= 1");
+  if (!(opts->rel_tol >= 0)) return fail(MH3D_ERR_INVALID, "rel_tol must be >= 0");
+  const Geo& g = p->g;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, p->stream));
+  double tau = opts->tau, lmax = 0.0;
+  if (!(tau > 0)) {
+    const int it = opts->power_iters > 0 ? opts->power_iters : 50;
+    CHK(power_iteration(p, it, opts->power_seed, &lmax));
+    if (!(lmax > 0)) return fail(MH3D_ERR_NONFINITE, "power iteration gave L = %g", lmax);
+    tau = 1.0 / (1.05 * lmax);
+  }
+  const int k0 = opts->k0;
+  // iterates: rho^k in vol[k % 3], rho^{k-1} in vol[(k-1) % 3]
+  HIPCHK(hipMemcpyAsync(p->vol[k0 % 3], rho_inout, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->vol[(k0 - 1) % 3], opts->rho_prev ? opts->rho_prev : rho_inout, sizeof(float) * g.N,
+                        hipMemcpyDeviceToDevice, p->stream));
+  DevState s0;
+  memset(&s0, 0, sizeof s0);
+  s0.k = k0;
+  s0.tau = tau;
+  s0.lam = p->desc.lambda;
+  s0.tol = opts->rel_tol;
+  s0.kmax = k0 + opts->max_iter - 1;
+  s0.last_k = k0 - 1;
+  CHK(state_set(p, s0));
+  double* hist_dev = nullptr;
+  const int hlen = opts->max_iter;
+  HIPCHK(hipMalloc(&hist_dev, sizeof(double) * hlen));
+  const int chunk = opts->check_every > 0 ? opts->check_every : 25;
+  DevState h;
+  memset(&h, 0, sizeof h);
+  int issued = 0;
+  mh3d_status status = MH3D_OK;
+  while (issued < opts->max_iter) {
+    const int n = std::min(chunk, opts->max_iter - issued);
+    for (int i = 0; i < n; ++i) {
+      const int k = k0 + issued + i;   // host-side index only selects buffers
+      const float* rk = p->vol[k % 3];
+      const float* rkm1 = p->vol[(k + 2) % 3];
+      float* rnext = p->vol[(k + 1) % 3];
+      Timer t(p, KID_SOLVE_ITER);
+      CHK(launch_plane_fwd(p, SRC_FISTA_Y, rk, rkm1, 0.f, p->st));
+      CHK(launch_class_fwd(p, p->st));
+      CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr, d, p->st));
+      CHK(launch_class_adj(p, p->st));
+      AdjOut ao;
+      memset(&ao, 0, sizeof ao);
+      ao.vin = rk;
+      ao.vprev = rkm1;
+      ao.rho_next = rnext;
+      ao.partials = p->partials;
+      ao.st = p->st;
+      ao.reg_kind = p->desc.reg_kind;
+      ao.lam = (float)p->desc.lambda;
+      ao.hist64 = hist_dev;
+      ao.k_first = k0;
+      ao.hist_len = hlen;
+      CHK(launch_plane_adj(p, OUT_FISTA, ao));
+    }
+    issued += n;
+    CHK(read_state(p, h));
+    if (h.done) break;
+  }
+  const int last = h.last_k;
+  const int iters = last - k0 + 1;
+  if (iters >= 1) {
+    HIPCHK(hipMemcpyAsync(rho_inout, p->vol[(last + 1) % 3], sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
+  }
+  HIPCHK(hipEventRecord(e1, p->stream));
+  if (opts->history && opts->history_len > 0 && iters > 0) {
+    std::vector<double> hh(iters);
+    HIPCHK(hipMemcpyAsync(hh.data(), hist_dev, sizeof(double) * iters, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int i = 0; i < std::min(iters, (int)opts->history_len); ++i) opts->history[i] = hh[i];
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(hist_dev);
+  if (h.nonfinite != 0.0) status = fail(MH3D_ERR_NONFINITE, "non-finite value in the solver reductions");
+  else if (!(opts->rel_tol > 0 && h.rel_step <= opts->rel_tol) && opts->rel_tol > 0)
+    status = fail(MH3D_ERR_NOT_CONVERGED, "r_k = %g > tol after %d updates", h.rel_step, iters);
+  if (info) {
+    info->iters = iters;
+    info->rel_step = h.rel_step;
+    info->tau = tau;
+    info->lmax = lmax;
+    info->ms_total = ms;
+    info->ms_per_iter = iters > 0 ? ms / iters : 0.f;
+    info->status = status;
+  }
+  return status;
+}
+
+// ============================================================================ export / profile
+extern "C" mh3d_status mh3d_plan_export(mh3d_plan_t p, mh3d_field field, void* dst, size_t* bytes) {
+  CHK(check_plan(p));
+  const Geo& g = p->g;
+  size_t need = 0;
+  switch (field) {
+    case MH3D_FIELD_PROFILE: need = sizeof(double) * g.K * g.nx; break;
+    case MH3D_FIELD_ENVELOPE: need = sizeof(double) * (size_t)g.ny * g.nz; break;
+    case MH3D_FIELD_SENS: need = sizeof(float) * g.N; break;
+    case MH3D_FIELD_SPECTRUM: need = sizeof(float2) * (size_t)g.K * g.nx * g.ny * g.nzh; break;
+    default: return fail(MH3D_ERR_INVALID, "unknown field %d", (int)field);
+  }
+  if (bytes) *bytes = need;
+  if (!dst) return MH3D_OK;
+  if ((field == MH3D_FIELD_PROFILE || field == MH3D_FIELD_ENVELOPE) && !p->compact)
+    return fail(MH3D_ERR_INVALID, "plan uses a user PSF; no analytic profile/envelope");
+  switch (field) {
+    case MH3D_FIELD_PROFILE: HIPCHK(hipMemcpyAsync(dst, p->prof, need, hipMemcpyDeviceToDevice, p->stream)); break;
+    case MH3D_FIELD_ENVELOPE: HIPCHK(hipMemcpyAsync(dst, p->env, need, hipMemcpyDeviceToDevice, p->stream)); break;
+    case MH3D_FIELD_SENS: HIPCHK(hipMemcpyAsync(dst, p->b, need, hipMemcpyDeviceToDevice, p->stream)); break;
+    default:
+      hipLaunchKernelGGL(k_spectrum_export, dim3(1024), dim3(256), 0, p->stream, g, p->hs, p->imag_mask, p->compact,
+                         reinterpret_cast<float2*>(dst));
+      CHK(last_launch("k_spectrum_export"));
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  if (!ctr || !key || !out) return fail(MH3D_ERR_INVALID, "NULL argument");
+  uint32_t* d = nullptr;
+  HIPCHK(hipMalloc(&d, 4 * sizeof(uint32_t)));
+  hipLaunchKernelGGL(k_philox_words, dim3(1), dim3(64), 0, 0, ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1], d);
+  mh3d_status s = last_launch("k_philox_words");
+  if (s == MH3D_OK && hipMemcpy(out, d, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    s = fail(MH3D_ERR_HIP, "copy of Philox words failed");
+  hipFree(d);
+  return s;
+}
+
+static void drain_events(mh3d_plan_t p) {
+  for (auto& e : p->pending) {
+    float ms = 0.f;
+    hipEventSynchronize(e.second.second);
+    hipEventElapsedTime(&ms, e.second.first, e.second.second);
+    p->ms[e.first] += ms;
+    p->launches[e.first] += 1;
+    p->free_events.push_back(e.second.first);
+    p->free_events.push_back(e.second.second);
+  }
+  p->pending.clear();
+}
+
+extern "C" mh3d_status mh3d_profile(mh3d_plan_t p, int32_t enable) {
+  CHK(check_plan(p));
+  drain_events(p);
+  p->prof_on = enable != 0;
+  memset(p->ms, 0, sizeof p->ms);
+  memset(p->launches, 0, sizeof p->launches);
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_profile_read(mh3d_plan_t p, mh3d_profile_data* out) {
+  CHK(check_plan(p));
+  if (!out) return fail(MH3D_ERR_INVALID, "out is NULL");
+  HIPCHK(hipStreamSynchronize(p->stream));
+  drain_events(p);
+  for (int i = 0; i < MH3D_NKERNEL; ++i) {
+    out->ms[i] = p->ms[i];
+    out->launches[i] = p->launches[i];
+    out->name[i] = kKernelNames[i];
+  }
+  return MH3D_OK;
+}

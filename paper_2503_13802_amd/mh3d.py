@@ -1,0 +1,281 @@
+"""ctypes binding of libmh3d.so (C ABI in include/mh3d.h).
+
+Argument marshalling only: every step of the operator and the solver runs in the
+library's HIP kernels.  PyTorch provides device memory and the current stream.
+Importing this module does not touch a GPU; creating a Plan does.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_PKG)
+LIB_PATH = os.path.join(_PKG, "libmh3d.so")
+HEADER = os.path.join(_ROOT, "include", "mh3d.h")
+
+OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
+FIELD_PROFILE, FIELD_ENVELOPE, FIELD_SENS, FIELD_SPECTRUM = range(4)
+NKERNEL = 8
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("voxel_mm", ctypes.c_double),
+                ("ds", ctypes.c_int32 * 3),
+                ("n_harm", ctypes.c_int32),
+                ("harm", ctypes.POINTER(ctypes.c_int32)),
+                ("order_offset", ctypes.c_int32),
+                ("a_per_mm", ctypes.c_double),
+                ("psf", ctypes.c_void_p),
+                ("sens", ctypes.c_void_p),
+                ("sigma_mm", ctypes.c_double * 3),
+                ("lambda_", ctypes.c_double),
+                ("reg_kind", ctypes.c_int32),
+                ("alpha", ctypes.c_double),
+                ("alpha_width", ctypes.c_int32),
+                ("pad", ctypes.c_int32 * 3),
+                ("stream", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("tau", ctypes.c_double),
+                ("power_iters", ctypes.c_int32), ("power_seed", ctypes.c_uint64),
+                ("rho_prev", ctypes.c_void_p), ("k0", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rel_step", ctypes.c_double), ("tau", ctypes.c_double),
+                ("lmax", ctypes.c_double), ("ms_total", ctypes.c_float), ("ms_per_iter", ctypes.c_float),
+                ("status", ctypes.c_int)]
+
+
+class ProfileData(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NKERNEL), ("launches", ctypes.c_int64 * NKERNEL),
+                ("name", ctypes.c_char_p * NKERNEL)]
+
+
+class MH3DError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("mh3d status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def library():
+    """Load libmh3d.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmh3d.so is not built (run `python -m paper_2503_13802_amd.build`); "
+                           "there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    st = ctypes.c_int
+    lib.mh3d_plan_describe.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.mh3d_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    lib.mh3d_destroy.argtypes = [vp]
+    lib.mh3d_destroy.restype = None
+    lib.mh3d_forward.argtypes = [vp, vp, vp]
+    lib.mh3d_adjoint.argtypes = [vp, vp, vp]
+    lib.mh3d_normal.argtypes = [vp, vp, vp]
+    lib.mh3d_power_iteration.argtypes = [vp, i32, ctypes.c_uint64, ctypes.POINTER(dbl)]
+    lib.mh3d_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
+    lib.mh3d_plan_export.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.mh3d_profile.argtypes = [vp, i32]
+    lib.mh3d_profile_read.argtypes = [vp, ctypes.POINTER(ProfileData)]
+    lib.mh3d_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+    lib.mh3d_last_error.restype = ctypes.c_char_p
+    lib.mh3d_version.restype = i32
+    for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
+                 "mh3d_power_iteration", "mh3d_solve", "mh3d_plan_export", "mh3d_profile",
+                 "mh3d_profile_read", "mh3d_philox4x32_10"):
+        getattr(lib, name).restype = st
+    _lib = lib
+    return lib
+
+
+def declared_functions(header=HEADER):
+    """Names of the functions the public header declares."""
+    txt = open(header).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mh3d_\w+)\s*\(", txt)) - {"mh3d_plan_t"})
+
+
+def _check(status):
+    if status != OK:
+        raise MH3DError(status, library().mh3d_last_error().decode())
+
+
+def _desc(shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=0, order_offset=0,
+          psf_ptr=None, sens_ptr=None, stream=None, alpha=0.0, pad=(0, 0, 0)):
+    harm = (ctypes.c_int32 * len(harmonics))(*[int(k) for k in harmonics])
+    d = PlanDesc()
+    d.nx, d.ny, d.nz = [int(n) for n in shape]
+    d.voxel_mm = float(voxel_mm)
+    d.ds = (ctypes.c_int32 * 3)(*[int(s) for s in ds])
+    d.n_harm = len(harmonics)
+    d.harm = ctypes.cast(harm, ctypes.POINTER(ctypes.c_int32))
+    d.order_offset = int(order_offset)
+    d.a_per_mm = float(a_per_mm)
+    d.psf = psf_ptr
+    d.sens = sens_ptr
+    d.sigma_mm = (ctypes.c_double * 3)(*np.broadcast_to(np.asarray(sigma_mm, dtype=float), (3,)))
+    d.lambda_ = float(lam)
+    d.reg_kind = int(reg_kind)
+    d.alpha = float(alpha)
+    d.alpha_width = 0
+    d.pad = (ctypes.c_int32 * 3)(*[int(x) for x in pad])
+    d.stream = stream
+    return d, harm
+
+
+def describe(shape, harmonics, a_per_mm=1.0, ds=(1, 1, 1), sigma_mm=20.0, lam=0.0, **kw):
+    """Host-only validation; returns (device_bytes, n_volume, n_portrait)."""
+    d, keep = _desc(shape, harmonics, a_per_mm, ds, sigma_mm, lam, **kw)
+    nb, nv, npo = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+    _check(library().mh3d_plan_describe(ctypes.byref(d), ctypes.byref(nb), ctypes.byref(nv), ctypes.byref(npo)))
+    return nb.value, nv.value, npo.value
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block computed on the device."""
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    _check(library().mh3d_philox4x32_10(c, k, o))
+    return [int(x) for x in o]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One MH3D reconstruction geometry on one GPU (see include/mh3d.h)."""
+
+    def __init__(self, shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=0,
+                 order_offset=0, psf=None, sens=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = tuple(int(n) for n in shape)
+        self.harmonics = tuple(int(k) for k in harmonics)
+        self.ds = tuple(int(s) for s in ds)
+        self.small = tuple(n // s for n, s in zip(self.shape, self.ds))
+        self.K = len(self.harmonics)
+        self._keep = []
+        psf_ptr = sens_ptr = None
+        if psf is not None:
+            psf = torch.as_tensor(psf, dtype=torch.float32, device=self.device).contiguous()
+            assert psf.shape == (self.K,) + self.shape
+            self._keep.append(psf)
+            psf_ptr = psf.data_ptr()
+        if sens is not None:
+            sens = torch.as_tensor(sens, dtype=torch.float32, device=self.device).contiguous()
+            assert sens.shape == self.shape
+            self._keep.append(sens)
+            sens_ptr = sens.data_ptr()
+        self.stream = torch.cuda.current_stream(self.device)
+        d, harm = _desc(self.shape, self.harmonics, a_per_mm, self.ds, sigma_mm, lam, voxel_mm, reg_kind,
+                        order_offset, psf_ptr, sens_ptr, self.stream.cuda_stream)
+        h = ctypes.c_void_p()
+        _check(library().mh3d_plan(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().mh3d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def _vol(self, x):
+        t = self.torch.as_tensor(x, dtype=self.torch.float32, device=self.device).contiguous()
+        assert tuple(t.shape) == self.shape, (t.shape, self.shape)
+        return t
+
+    def _port(self, x):
+        t = self.torch.as_tensor(x, dtype=self.torch.float32, device=self.device).contiguous()
+        assert tuple(t.shape) == (self.K,) + self.small, (t.shape, self.small)
+        return t
+
+    # -------------------------------------------------------------- operators
+    def forward(self, rho, out=None):
+        rho = self._vol(rho)
+        out = self.torch.empty((self.K,) + self.small, device=self.device) if out is None else out
+        _check(library().mh3d_forward(self._h, _ptr(rho), _ptr(out)))
+        return out
+
+    def adjoint(self, d, out=None):
+        d = self._port(d)
+        out = self.torch.empty(self.shape, device=self.device) if out is None else out
+        _check(library().mh3d_adjoint(self._h, _ptr(d), _ptr(out)))
+        return out
+
+    def normal(self, x, out=None):
+        x = self._vol(x)
+        out = self.torch.empty(self.shape, device=self.device) if out is None else out
+        _check(library().mh3d_normal(self._h, _ptr(x), _ptr(out)))
+        return out
+
+    def power_iteration(self, iters=50, seed=0):
+        lm = ctypes.c_double()
+        _check(library().mh3d_power_iteration(self._h, int(iters), int(seed), ctypes.byref(lm)))
+        return lm.value
+
+    def solve(self, d, rho0=None, max_iter=500, tol=1e-4, tau=0.0, power_iters=50, power_seed=0,
+              rho_prev=None, k0=1, check_every=25, raise_on_not_converged=False):
+        """Returns (rho, info dict with 'history')."""
+        d = self._port(d)
+        rho = self.torch.zeros(self.shape, device=self.device) if rho0 is None else self._vol(rho0).clone()
+        prev = None if rho_prev is None else self._vol(rho_prev)
+        hist = (ctypes.c_double * max_iter)()
+        o = SolveOpts(int(max_iter), float(tol), float(tau), int(power_iters), int(power_seed),
+                      None if prev is None else prev.data_ptr(), int(k0), int(check_every),
+                      ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(max_iter))
+        info = SolveInfo()
+        s = library().mh3d_solve(self._h, _ptr(d), _ptr(rho), ctypes.byref(o), ctypes.byref(info))
+        if s not in (OK, ERR_NOT_CONVERGED) or (s == ERR_NOT_CONVERGED and raise_on_not_converged):
+            _check(s)
+        out = {"iters": info.iters, "rel_step": info.rel_step, "tau": info.tau, "lmax": info.lmax,
+               "ms_total": info.ms_total, "ms_per_iter": info.ms_per_iter, "status": s,
+               "history": np.array(hist[:info.iters])}
+        return rho, out
+
+    def export(self, field):
+        torch = self.torch
+        nb = ctypes.c_size_t()
+        _check(library().mh3d_plan_export(self._h, field, None, ctypes.byref(nb)))
+        if field == FIELD_PROFILE:
+            t = torch.empty((self.K, self.shape[0]), dtype=torch.float64, device=self.device)
+        elif field == FIELD_ENVELOPE:
+            t = torch.empty(self.shape[1:], dtype=torch.float64, device=self.device)
+        elif field == FIELD_SENS:
+            t = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        else:
+            t = torch.empty((self.K, self.shape[0], self.shape[1], self.shape[2] // 2 + 1),
+                            dtype=torch.complex64, device=self.device)
+        assert t.numel() * t.element_size() == nb.value
+        _check(library().mh3d_plan_export(self._h, field, _ptr(t), ctypes.byref(nb)))
+        return t
+
+    def profile(self, enable=True):
+        _check(library().mh3d_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        pd = ProfileData()
+        _check(library().mh3d_profile_read(self._h, ctypes.byref(pd)))
+        return {pd.name[i].decode(): (pd.ms[i], pd.launches[i]) for i in range(NKERNEL)}

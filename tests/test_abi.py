@@ -1,0 +1,82 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports every
+function include/mh3d.h declares, and rejects invalid descriptors on the host."""
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_2503_13802_amd import mh3d
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = mh3d.library()
+    names = mh3d.declared_functions()
+    assert "mh3d_forward" in names and "mh3d_solve" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", mh3d.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in names:
+        assert n in exported, n
+        assert getattr(lib, n) is not None
+    assert lib.mh3d_version() == 1
+
+
+@pytest.mark.parametrize("shape,harm,ds,sig", [
+    ((32, 32, 32), (2, 3), (2, 2, 2), 20.0),
+    ((96, 96, 64), tuple(range(2, 9)), (2, 2, 2), 20.0),
+    ((128, 128, 128), tuple(range(2, 13)), (2, 4, 4), (25.0, 25.0, 40.0)),
+    ((48, 48, 48), (2, 3, 4), (2, 2, 2), 20.0),
+    ((128, 128, 96), tuple(range(2, 12)), (2, 2, 2), 20.0),
+    ((18, 12, 8), (2, 3, 4), (3, 2, 2), 5.0),
+    ((8, 9, 8), (2, 3), (2, 3, 2), 5.0),
+])
+def test_describe_valid(shape, harm, ds, sig):
+    nb, nv, npo = mh3d.describe(shape, harm, 1.2, ds, sig, 1e-3)
+    n = shape[0] * shape[1] * shape[2]
+    m = n // (ds[0] * ds[1] * ds[2])
+    assert nv == n and npo == len(harm) * m and nb > 4 * n
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(shape=(100, 96, 64)), mh3d.ERR_INVALID),           # 100 = 2^2 5^2
+    (dict(shape=(96, 96, 63)), mh3d.ERR_INVALID),            # nz odd / not 2^a 3^b
+    (dict(ds=(5, 2, 2)), mh3d.ERR_INVALID),                  # does not divide
+    (dict(ds=(2, 2, 64)), mh3d.ERR_INVALID),                 # nz/ds odd
+    (dict(harmonics=(1, 2)), mh3d.ERR_INVALID),
+    (dict(harmonics=(3, 2)), mh3d.ERR_INVALID),
+    (dict(harmonics=()), mh3d.ERR_INVALID),
+    (dict(lam=-1.0), mh3d.ERR_INVALID),
+    (dict(a_per_mm=0.0), mh3d.ERR_INVALID),
+    (dict(sigma_mm=0.0), mh3d.ERR_INVALID),
+    (dict(voxel_mm=0.0), mh3d.ERR_INVALID),
+    (dict(reg_kind=3), mh3d.ERR_INVALID),
+    (dict(alpha=4.0), mh3d.ERR_UNSUPPORTED),                 # boundary prior not built
+    (dict(pad=(4, 4, 4)), mh3d.ERR_UNSUPPORTED),             # padding not built
+    (dict(shape=(18, 18, 8), ds=(3, 3, 2)), mh3d.ERR_UNSUPPORTED),   # S = 18 has no power-of-two fold split
+    (dict(shape=(256, 256, 256)), mh3d.ERR_UNSUPPORTED),     # x-plane exceeds LDS
+])
+def test_describe_rejects(kw, status):
+    args = dict(shape=(96, 96, 64), harmonics=tuple(range(2, 9)), a_per_mm=1.2, ds=(2, 2, 2),
+                sigma_mm=20.0, lam=1e-3)
+    args.update(kw)
+    with pytest.raises(mh3d.MH3DError) as e:
+        mh3d.describe(args.pop("shape"), args.pop("harmonics"), **args)
+    assert e.value.status == status
+    assert len(mh3d.library().mh3d_last_error()) > 0
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = mh3d.library()
+    assert lib.mh3d_plan_describe(None, None, None, None) == mh3d.ERR_INVALID
+    assert lib.mh3d_forward(None, None, None) == mh3d.ERR_INVALID
+    assert lib.mh3d_solve(None, None, None, None, None) == mh3d.ERR_INVALID
+    h = ctypes.c_void_p()
+    assert lib.mh3d_plan(None, ctypes.byref(h)) == mh3d.ERR_INVALID
+
+
+def test_product_path_has_no_oracle_dependency():
+    import pathlib
+    pkg = pathlib.Path(mh3d.__file__).parent
+    for f in list(pkg.glob("*.py")) + list(pkg.glob("csrc/*")):
+        txt = f.read_text()
+        assert "import oracle" not in txt and "from oracle" not in txt, f
