@@ -630,6 +630,7 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
       const float r = rk[i];
       return r + beta * (r - rkm1[i]);
     };
+    double acc3[3] = {0.0, 0.0, 0.0};
     for (int p = threadIdx.x; p < nyz; p += blockDim.x) {
       const int y = p / g.nz, z = p % g.nz;
       const float yk = yv(x, y, z);
@@ -637,18 +638,22 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
       const float nx = fmaxf(yk - tau * gr, 0.f);
       ao.rho_next[pbase + p] = nx;
       const double dd = (double)nx - (double)yk;
-      acc[0] += dd * dd;
-      acc[1] += (double)nx * (double)nx;
+      acc3[0] += dd * dd;
+      acc3[1] += (double)nx * (double)nx;
+      if (!isfinite(gr) || !isfinite(yk)) acc3[2] += 1.0;   // max(NaN, 0) would hide it
     }
-    if (grid_reduce_last<2>(acc, ao.partials, ao.st, red)) {
+    if (grid_reduce_last<3>(acc3, ao.partials, ao.st, red)) {
       double r;
-      if (acc[1] == 0.0) r = (acc[0] == 0.0) ? 0.0 : __builtin_inf();
-      else r = sqrt(acc[0]) / sqrt(acc[1]);
+      if (acc3[1] == 0.0) r = (acc3[0] == 0.0) ? 0.0 : __builtin_inf();
+      else r = sqrt(acc3[0]) / sqrt(acc3[1]);
       st->rel_step = r;
       st->last_k = kk;
       const int hi = kk - ao.k_first;
       if (ao.hist64 && hi >= 0 && hi < ao.hist_len) ao.hist64[hi] = r;
-      if (!(acc[0] == acc[0]) || !(acc[1] == acc[1]) || acc[1] > 1e300) { st->nonfinite = 1.0; st->done = 1; }
+      if (acc3[2] != 0.0 || !(acc3[0] == acc3[0]) || !(acc3[1] == acc3[1]) || acc3[1] > 1e300) {
+        st->nonfinite = 1.0;
+        st->done = 1;
+      }
       if (r <= st->tol || kk >= st->kmax) st->done = 1;
       st->k = kk + 1;
     }

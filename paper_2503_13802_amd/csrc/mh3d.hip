@@ -56,10 +56,10 @@ struct Launch {
   size_t lds_plane, lds_class, lds_small;
 };
 
-// Elements per thread in the class kernel: largest e <= 8 dividing S with S/e a
-// power of two <= 64 (so the fold reduction stays inside aligned lane groups).
+// Elements per thread in the class kernel: the first e of the list dividing S with
+// S/e a power of two <= 64 (so the fold reduction stays inside aligned lane groups).
 static int pick_E(int S) {
-  const int opts[6] = {8, 6, 4, 3, 2, 1};
+  const int opts[7] = {8, 6, 4, 3, 2, 1, 9};
   for (int e : opts) {
     if (S % e) continue;
     int lg = S / e;
@@ -296,6 +296,7 @@ static void class_adj_t(mh3d_plan_t p, DevState* st) {
 
 #define E_DISPATCH(HCV, FN)                       \
   switch (p->g.E) {                               \
+    case 9: FN<HCV, 9>(p, st); break;             \
     case 8: FN<HCV, 8>(p, st); break;             \
     case 6: FN<HCV, 6>(p, st); break;             \
     case 4: FN<HCV, 4>(p, st); break;             \

@@ -29,6 +29,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     ((128, 128, 96), tuple(range(2, 12)), (2, 2, 2), 20.0),
     ((18, 12, 8), (2, 3, 4), (3, 2, 2), 5.0),
     ((8, 9, 8), (2, 3), (2, 3, 2), 5.0),
+    ((18, 18, 8), (2, 3), (3, 3, 2), 5.0),
 ])
 def test_describe_valid(shape, harm, ds, sig):
     nb, nv, npo = mh3d.describe(shape, harm, 1.2, ds, sig, 1e-3)
@@ -52,7 +53,7 @@ def test_describe_valid(shape, harm, ds, sig):
     (dict(reg_kind=3), mh3d.ERR_INVALID),
     (dict(alpha=4.0), mh3d.ERR_UNSUPPORTED),                 # boundary prior not built
     (dict(pad=(4, 4, 4)), mh3d.ERR_UNSUPPORTED),             # padding not built
-    (dict(shape=(18, 18, 8), ds=(3, 3, 2)), mh3d.ERR_UNSUPPORTED),   # S = 18 has no power-of-two fold split
+    (dict(shape=(18, 18, 12), ds=(3, 3, 3)), mh3d.ERR_UNSUPPORTED),  # S = 27 has no power-of-two fold split
     (dict(shape=(256, 256, 256)), mh3d.ERR_UNSUPPORTED),     # x-plane exceeds LDS
 ])
 def test_describe_rejects(kw, status):

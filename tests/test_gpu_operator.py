@@ -80,6 +80,7 @@ CASES = [
     ((32, 32, 32), (2, 3), (2, 2, 2), 0.8, 20.0),      # workload 0 geometry
     ((24, 16, 12), tuple(range(2, 9)), (1, 1, 1), 1.2, 6.0),   # no decimation, K = 7
     ((48, 24, 32), tuple(range(2, 13)), (2, 4, 4), 1.2, 10.0), # workload-2 decimation, K = 11
+    ((18, 18, 8), (2, 3), (3, 3, 2), 1.0, 5.0),        # S = 18: nine elements per thread
 ]
 
 
