@@ -175,6 +175,74 @@ __device__ C* fft_lds(C* a, C* b, const C* tw, int n, int nlines, const LineMap&
   return a;
 }
 
+// ------------------------------------------------------------------ compile-time lengths
+// Radix of stage s for length N (same order as radix_code: 8s, 4s, 2s, 3s).
+__host__ __device__ constexpr int ct_radix(int n, int s) {
+  int i = 0;
+  while (n % 8 == 0) { if (i == s) return 8; n /= 8; ++i; }
+  while (n % 4 == 0) { if (i == s) return 4; n /= 4; ++i; }
+  while (n % 2 == 0) { if (i == s) return 2; n /= 2; ++i; }
+  while (n % 3 == 0) { if (i == s) return 3; n /= 3; ++i; }
+  return 0;
+}
+
+// One out-of-place stage for compile-time N, radix R and NS (product of previous
+// radices).  Lines are contiguous: element p of line l at l*ls + p.  Consecutive
+// butterflies of a line go to consecutive lanes.
+template <int N, int R, int NS, int SGN, typename C>
+__device__ __forceinline__ void ct_stage(const C* __restrict__ in, C* __restrict__ out, const C* tw,
+                                         int nlines, int ls) {
+  constexpr int NB = N / R;
+  constexpr int TWS = N / (NS * R);
+  const int total = nlines * NB;
+  for (int b = threadIdx.x; b < total; b += blockDim.x) {
+    const int l = b / NB, j = b - (b / NB) * NB;
+    const int k = j % NS;
+    const int base = l * ls;
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[base + j + r * NB];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const C w = tw[k * r * TWS];
+        v[r] = SGN < 0 ? cmul(v[r], w) : cmulcj(w, v[r]);
+      }
+    }
+    dft<R, SGN>(v);
+    const int o = base + (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[o + r * NS] = v[r];
+  }
+}
+
+template <int N, int S, int NS, int SGN, typename C>
+__device__ __forceinline__ C* ct_stages(C* a, C* b, const C* tw, int nlines, int ls) {
+  constexpr int R = ct_radix(N, S);
+  if constexpr (R == 0) {
+    return a;
+  } else {
+    ct_stage<N, R, NS, SGN>(a, b, tw, nlines, ls);
+    __syncthreads();
+    return ct_stages<N, S + 1, NS * R, SGN>(b, a, tw, nlines, ls);
+  }
+}
+
+// Length-n transform of nlines contiguous lines (line stride ls) with the length
+// dispatched to a compile-time instantiation when it is one of the common sizes,
+// else to the runtime engine.  Same contract as fft_lds.
+template <int SGN, typename C>
+__device__ C* fft_lines(C* a, C* b, const C* tw, int n, int nlines, int ls) {
+  __syncthreads();
+  switch (n) {
+#define MH3D_CT(NN) case NN: return ct_stages<NN, 0, 1, SGN>(a, b, tw, nlines, ls);
+    MH3D_CT(2) MH3D_CT(3) MH3D_CT(4) MH3D_CT(6) MH3D_CT(8) MH3D_CT(12) MH3D_CT(16) MH3D_CT(24)
+    MH3D_CT(32) MH3D_CT(48) MH3D_CT(64) MH3D_CT(96) MH3D_CT(128) MH3D_CT(192) MH3D_CT(256)
+#undef MH3D_CT
+    default: return fft_lds<SGN>(a, b, tw, n, nlines, LineMap{nlines, 0, ls, 1}, false);
+  }
+}
+
 // Copy a length-n twiddle table from global memory into LDS (then barrier by caller).
 template <typename C>
 __device__ __forceinline__ void load_table(C* dst, const C* src, int n) {

@@ -10,8 +10,31 @@
 // conjugate of the in-plane Hermitian partner (ny - qy, nz - qz), which is exact for
 // the y-z spectrum of a real x-plane.
 #pragma once
+#include <stdint.h>
 
 namespace mh3d {
+
+// Division by a per-plan constant d >= 1 for 0 <= n < 2^31 with one 32x64-bit
+// multiply: q = (n * m) >> s, m = ceil(2^(31+l) / d), l = ceil(log2 d)
+// (Granlund & Montgomery, PLDI 1994, round-up variant).
+struct FastDiv {
+  uint64_t m;
+  uint32_t s, d;
+  __host__ __device__ inline uint32_t div(uint32_t n) const { return (uint32_t)(((uint64_t)n * m) >> s); }
+  __host__ __device__ inline uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.d = d;
+  f.s = 31 + l;
+  const unsigned __int128 one = 1;
+  const unsigned __int128 p = one << (31 + l);
+  f.m = (uint64_t)((p + d - 1) / d);
+  return f;
+}
 
 struct Geo {
   int nx, ny, nz, nzh;     // grid, nzh = nz/2 + 1
@@ -26,8 +49,12 @@ struct Geo {
   int xb;                  // x' planes per small-grid workgroup (divides mx)
   int npairs;              // (ny + 1)/2 row pairs of one full x-plane
   int spairs;              // (xb*my + 1)/2 row pairs of one small-grid workgroup
+  int lsy;                 // LDS line stride of y-transforms in the plane kernels (ny + pad)
+  int lsx;                 // LDS line stride of x-transforms in the class kernels (nx + pad)
+  int lsmy;                // LDS line stride of y'-transforms in the small kernels (my + pad)
   long long N, M;          // nx*ny*nz, mx*my*mz
   long long hsz;           // spectrum elements per harmonic = ncls*mx*S = plane*nx
+  FastDiv f_nz, f_nzh, f_nmem, f_mzh, f_sz, f_mz, f_W, f_xb, f_S, f_mxS, f_cpwmx, f_cpwxb, f_ny, f_my;
 };
 
 }  // namespace mh3d

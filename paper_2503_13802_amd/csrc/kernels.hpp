@@ -51,13 +51,21 @@ __device__ __forceinline__ int halfplane_of_member(const Geo& g, int e, bool& cj
   return ((g.ny - qy) % g.ny) * g.nzh + (g.nz - qz);
 }
 
-// Complex elements of one LDS plane buffer (x-plane kernels) / small-grid buffer.
+// LDS line strides: transforms run on contiguous lines padded to an odd length so
+// that the transposing passes between them hit distinct banks.
+__host__ __device__ inline int pad_odd(int n) { return (n & 1) ? n : n + 1; }
+
+// Complex elements of one LDS buffer of the x-plane kernels: packed row pairs
+// [npairs][lsz], half-spectrum columns [nzh][lsy], or a staged class-layout plane.
 __host__ __device__ inline int plane_lds(const Geo& g) {
-  const int a = g.npairs * g.nz, b = g.ny * g.nzh;
-  return a > b ? a : b;
+  const int a = g.npairs * pad_odd(g.nz), b = g.nzh * g.lsy, c = g.plane;
+  const int m = a > b ? a : b;
+  return m > c ? m : c;
 }
+// One LDS buffer of the small-grid kernels: row pairs [spairs][lsmz] or
+// columns [xb*mzh][lsmy].
 __host__ __device__ inline int small_lds(const Geo& g) {
-  const int a = g.spairs * g.mz, b = g.xb * g.my * g.mzh;
+  const int a = g.spairs * pad_odd(g.mz), b = g.xb * g.mzh * g.lsmy;
   return a > b ? a : b;
 }
 
@@ -89,6 +97,34 @@ __device__ __forceinline__ void block_reduce_f64(double* v, double* sh) {
   __syncthreads();
 }
 
+// Strided block loop with U independent loads in flight per thread: all loads of a
+// batch are issued before any result is used (a plain strided loop would wait for
+// each load in turn).
+template <int U, typename T, typename LD, typename ST>
+__device__ __forceinline__ void batched(int n, LD ld, ST st) {
+  const int nt = blockDim.x;
+  for (int p0 = threadIdx.x; p0 < n; p0 += U * nt) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * nt;
+      if (p < n) v[u] = ld(p);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * nt;
+      if (p < n) st(p, v[u]);
+    }
+  }
+}
+
+// x-plane handled by block b: consecutive planes go to the same XCD (blocks are
+// dealt round-robin over the 8 XCDs), so stencil neighbours share an L2.
+__device__ __forceinline__ int plane_of_block(int b, int nx) {
+  if (nx % 8) return b;
+  return (b & 7) * (nx >> 3) + (b >> 3);
+}
+
 // Solver / power-iteration state kept in device memory so that a captured
 // sequence of launches can be replayed.
 struct DevState {
@@ -115,55 +151,77 @@ __device__ __forceinline__ float plane_source(long long i, const float* __restri
                                               const float* __restrict__ b, float coef) {
   if constexpr (SRC == SRC_PLAIN) return b[i] * a[i];
   else if constexpr (SRC == SRC_RAW) return a[i];
-  else if constexpr (SRC == SRC_FISTA_Y) {     // y = rho^k + beta (rho^k - rho^{k-1})
-    float r = a[i];
-    return b[i] * (r + coef * (r - a2[i]));
-  } else return b[i] * (coef * a[i]);          // SRC_SCALED
+  else if constexpr (SRC == SRC_FISTA_Y) return b[i] * a[i];   // a = y^k, skipped once done
+  else return b[i] * (coef * a[i]);                             // SRC_SCALED
 }
 
-// R2C along z of nrows real rows held as packed pairs Z[j][nz] in *a (row 2j in .x,
-// row 2j+1 in .y): FFT each pair, then split into half spectra X[row][0..nz/2]
-// (row stride row_stride_out).  Returns the buffer holding X (a or b).
+// Row <-> column addressing of the R2C/C2R helpers.  Row r of the real data maps
+// to the half-spectrum column layout X[col(r, q)]: col(r, q) = colbase(r) + q * qstride.
+struct RowCols {
+  int qstride;        // stride between consecutive q of one row
+  int per_blk;        // rows per block (my for the small kernels, nrows otherwise)
+  FastDiv f_blk;      // divides by per_blk
+  int blk_stride;     // offset between blocks (mzh*lsmy for the small kernels)
+  __device__ __forceinline__ int base(int r) const {
+    const int b = (int)f_blk.div((uint32_t)r);
+    return b * blk_stride + (r - b * per_blk);
+  }
+};
+
+// R2C along z of nrows real rows held as packed pairs Z[j][lsz] in *a (row 2j in
+// .x, row 2j+1 in .y): FFT each pair, then split into the half spectra written to
+// X[rc.base(row) + q * rc.qstride], q in [0, nz/2].  Returns the buffer holding X.
 __device__ float2* r2c_rows(float2* a, float2* b, const float2* twz, int nrows, int nz, int nzh,
-                            int row_stride_out, int npairs) {
-  float2* Z = fft_lds<-1>(a, b, twz, nz, npairs, LineMap{npairs, 0, nz, 1}, false);
+                            int npairs, const RowCols& rc, const FastDiv& f_nzh) {
+  const int lsz = pad_odd(nz);
+  float2* Z = fft_lines<-1>(a, b, twz, nz, npairs, lsz);
   float2* X = (Z == a) ? b : a;
   const int items = npairs * nzh;
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int j = it / nzh, q = it % nzh;
-    const float2 zq = Z[j * nz + q];
-    const float2 zm = Z[j * nz + (nz - q) % nz];
+    const int j = (int)f_nzh.div((uint32_t)it), q = it - j * nzh;
+    const float2 zq = Z[j * lsz + q];
+    const float2 zm = Z[j * lsz + (q == 0 ? 0 : nz - q)];
     // A = (Z(q) + conj Z(-q))/2 ; B = (Z(q) - conj Z(-q))/(2i)
-    X[(2 * j) * row_stride_out + q] = make_float2(0.5f * (zq.x + zm.x), 0.5f * (zq.y - zm.y));
+    X[rc.base(2 * j) + q * rc.qstride] = make_float2(0.5f * (zq.x + zm.x), 0.5f * (zq.y - zm.y));
     if (2 * j + 1 < nrows)
-      X[(2 * j + 1) * row_stride_out + q] = make_float2(0.5f * (zq.y + zm.y), -0.5f * (zq.x - zm.x));
+      X[rc.base(2 * j + 1) + q * rc.qstride] = make_float2(0.5f * (zq.y + zm.y), -0.5f * (zq.x - zm.x));
   }
   __syncthreads();
   return X;
 }
 
-// C2R along z: half spectra X[row][nzh] (row stride row_stride_in) in *a -> packed
-// pairs Z[j][nz] (Z = A + iB with Hermitian extension), inverse FFT.  The
-// imaginary parts of the q = 0 and q = nz/2 bins are dropped (they vanish for a
-// Hermitian input).  Returns the buffer holding the packed real rows.
-__device__ float2* c2r_rows(float2* a, float2* b, const float2* twz, int nrows, int nz, int nzh,
-                            int row_stride_in, int npairs) {
+// C2R along z: half spectra X[rc.base(row) + q * rc.qstride] in *a -> packed pairs
+// Z[j][lsz] (Z = A + iB with the Hermitian extension), inverse FFT.  The imaginary
+// parts of the q = 0 and q = nz/2 bins are dropped (they vanish for a Hermitian
+// input).  Returns the buffer holding the packed real rows.
+__device__ float2* c2r_rows(float2* a, float2* b, const float2* twz, int nrows, int nz, int npairs,
+                            const RowCols& rc, const FastDiv& f_nz) {
+  const int lsz = pad_odd(nz);
   const int items = npairs * nz;
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int j = it / nz, q = it % nz;
+    const int j = (int)f_nz.div((uint32_t)it), q = it - j * nz;
     const bool up = 2 * q > nz;
     const int qq = up ? nz - q : q;
-    float2 x = a[(2 * j) * row_stride_in + qq];
-    float2 y = (2 * j + 1 < nrows) ? a[(2 * j + 1) * row_stride_in + qq] : make_float2(0.f, 0.f);
+    float2 x = a[rc.base(2 * j) + qq * rc.qstride];
+    float2 y = (2 * j + 1 < nrows) ? a[rc.base(2 * j + 1) + qq * rc.qstride] : make_float2(0.f, 0.f);
     if (qq == 0 || 2 * qq == nz) { x.y = 0.f; y.y = 0.f; }
     if (up) { x.y = -x.y; y.y = -y.y; }
-    b[it] = make_float2(x.x - y.y, x.y + y.x);      // x + i y
+    b[j * lsz + q] = make_float2(x.x - y.y, x.y + y.x);      // x + i y
   }
-  return fft_lds<+1>(b, a, twz, nz, npairs, LineMap{npairs, 0, nz, 1}, false);
+  return fft_lines<+1>(b, a, twz, nz, npairs, lsz);
+}
+
+__device__ __forceinline__ RowCols plane_rowcols(const Geo& g) {
+  RowCols rc;
+  rc.qstride = g.lsy;
+  rc.per_blk = g.ny;
+  rc.f_blk = g.f_ny;
+  rc.blk_stride = 0;
+  return rc;
 }
 
 // Forward pass 1.  grid = nx blocks (block -> plane).
-// LDS: tables (nz + ny) + two plane buffers of max(npairs*nz, ny*nzh) complex.
+// LDS: tables (nz + ny) + two buffers of plane_lds complex.
 template <int SRC>
 __global__ __launch_bounds__(1024) void k_plane_fwd(Geo g, const float* __restrict__ a,
                                                     const float* __restrict__ a2,
@@ -181,30 +239,40 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(Geo g, const float* __restri
   float2* twy = twz + g.nz;
   float2* P0 = twy + g.ny;
   float2* P1 = P0 + pl;
-  const int x = blockIdx.x;
+  const int x = plane_of_block(blockIdx.x, g.nx);
   load_table(twz, tw_z, g.nz);
   load_table(twy, tw_y, g.ny);
   float c = coef;
-  if constexpr (SRC == SRC_FISTA_Y) c = (float)((st->k - 1.0) / (st->k + 2.0));
   if constexpr (SRC == SRC_SCALED) c = (float)st->scale;
   const long long pbase = (long long)x * g.ny * g.nz;
   const int nyz = g.ny * g.nz;
+  const int lsz = pad_odd(g.nz);
   float* Zf = reinterpret_cast<float*>(P0);
-  for (int p = threadIdx.x; p < nyz; p += blockDim.x) {
-    const int y = p / g.nz, z = p % g.nz;
-    Zf[2 * ((y >> 1) * g.nz + z) + (y & 1)] = plane_source<SRC>(pbase + p, a, a2, b, c);
-  }
+  batched<8, float>(nyz, [&](int p) { return plane_source<SRC>(pbase + p, a, a2, b, c); },
+                    [&](int p, float v) {
+                      const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
+                      Zf[2 * ((y >> 1) * lsz + z) + (y & 1)] = v;
+                    });
   if (g.ny & 1) {
-    for (int z = threadIdx.x; z < g.nz; z += blockDim.x) Zf[2 * ((g.ny >> 1) * g.nz + z) + 1] = 0.f;
+    for (int z = threadIdx.x; z < g.nz; z += blockDim.x) Zf[2 * ((g.ny >> 1) * lsz + z) + 1] = 0.f;
   }
-  float2* X = r2c_rows(P0, P1, twz, g.ny, g.nz, g.nzh, g.nzh, g.npairs);
-  float2* Y = fft_lds<-1>(X, X == P0 ? P1 : P0, twy, g.ny, g.nzh, LineMap{g.nzh, 0, 1, g.nzh}, true);
+  const RowCols rc = plane_rowcols(g);
+  float2* X = r2c_rows(P0, P1, twz, g.ny, g.nz, g.nzh, g.npairs, rc, g.f_nzh);   // X[qz][lsy]
+  float2* Y = fft_lines<-1>(X, X == P0 ? P1 : P0, twy, g.ny, g.nzh, g.lsy);
   float2* dst = uperm + (long long)x * g.plane;
   for (int e = threadIdx.x; e < g.plane; e += blockDim.x) {
-    bool cj;
-    const int src = halfplane_of_member(g, e, cj);
-    const float2 v = Y[src];
-    dst[e] = cj ? make_float2(v.x, -v.y) : v;
+    const int cc = (int)g.f_nmem.div((uint32_t)e), m = e - cc * g.nmem;
+    const int cy = (int)g.f_mzh.div((uint32_t)cc), cz = cc - cy * g.mzh;
+    const int jy = (int)g.f_sz.div((uint32_t)m), jz = m - jy * g.sz;
+    const int qy = cy + jy * g.my, qz = cz + jz * g.mz;
+    float2 v;
+    if (2 * qz <= g.nz) {
+      v = Y[qz * g.lsy + qy];
+    } else {
+      v = Y[(g.nz - qz) * g.lsy + (qy == 0 ? 0 : g.ny - qy)];
+      v.y = -v.y;
+    }
+    dst[e] = v;
   }
 }
 
@@ -212,49 +280,71 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(Geo g, const float* __restri
 // HC = 0: compact spectra (one float per element; harmonic k is real if bit k of
 // imag_mask is clear, purely imaginary if set).  HC = 1: complex spectra.
 template <int HC, int E>
-struct HLoad {
-  float2 v[E];
+struct HLoad;
+
+// Compact spectra: one float per element.
+template <int E>
+struct HLoad<0, E> {
+  float v[E];
   __device__ __forceinline__ void load(const void* base, long long off) {
-    if constexpr (HC == 0) {
-      const float* p = reinterpret_cast<const float*>(base) + off;
-      if constexpr (E % 4 == 0) {
+    const float* p = reinterpret_cast<const float*>(base) + off;
+    if constexpr (E % 4 == 0) {
 #pragma unroll
-        for (int i = 0; i < E; i += 4) {
-          float4 t = *reinterpret_cast<const float4*>(p + i);
-          v[i] = make_float2(t.x, 0.f); v[i + 1] = make_float2(t.y, 0.f);
-          v[i + 2] = make_float2(t.z, 0.f); v[i + 3] = make_float2(t.w, 0.f);
-        }
-      } else if constexpr (E % 2 == 0) {
+      for (int i = 0; i < E; i += 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p + i);
+        v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
+      }
+    } else if constexpr (E % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < E; i += 2) {
-          float2 t = *reinterpret_cast<const float2*>(p + i);
-          v[i] = make_float2(t.x, 0.f); v[i + 1] = make_float2(t.y, 0.f);
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = make_float2(p[i], 0.f);
+      for (int i = 0; i < E; i += 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p + i);
+        v[i] = t.x; v[i + 1] = t.y;
       }
     } else {
-      const float2* p = reinterpret_cast<const float2*>(base) + off;
-      if constexpr (E % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < E; i += 2) {
-          float4 t = *reinterpret_cast<const float4*>(p + i);
-          v[i] = make_float2(t.x, t.y); v[i + 1] = make_float2(t.z, t.w);
-        }
-      } else {
+      for (int i = 0; i < E; ++i) v[i] = p[i];
+    }
+  }
+  __device__ __forceinline__ float re(int i) const { return v[i]; }
+};
+
+// Complex spectra.
+template <int E>
+struct HLoad<1, E> {
+  float2 v[E];
+  __device__ __forceinline__ void load(const void* base, long long off) {
+    const float2* p = reinterpret_cast<const float2*>(base) + off;
+    if constexpr (E % 2 == 0) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = p[i];
+      for (int i = 0; i < E; i += 2) {
+        const float4 t = *reinterpret_cast<const float4*>(p + i);
+        v[i] = make_float2(t.x, t.y); v[i + 1] = make_float2(t.z, t.w);
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = p[i];
     }
   }
 };
 
-// LDS layout of the class kernels: tables (nx + mx), U0/U1 (nx*W each), F0/F1
-// (K*cpw*mx each), W = cpw*nmem.
+// LDS layout of the class kernels: tables (nx + mx), U0/U1 (W lines of lsx, the
+// x-transforms of the W = cpw*nmem member columns), F0/F1 (K*cpw lines of mx).
 __host__ __device__ inline size_t class_lds_elems(const Geo& g) {
   const size_t W = (size_t)g.cpw * g.nmem;
-  return (size_t)g.nx + g.mx + 2 * (size_t)g.nx * W + 2 * (size_t)g.K * g.cpw * g.mx;
+  return (size_t)g.nx + g.mx + 2 * W * g.lsx + 2 * (size_t)g.K * g.cpw * g.mx;
+}
+
+constexpr int HPF = 4;   // harmonics of spectra prefetched ahead in the class kernels
+
+// Position of class-layout element p of a (k, x'-block, class, x'-in-block) store,
+// p over K*cpw*mx, as offsets into F ((k*cpw + c)*mx + x') and G.
+__device__ __forceinline__ void class_g_index(const Geo& g, int p, int c0, int& fo, long long& go) {
+  const int k = (int)g.f_cpwmx.div((uint32_t)p), r = p - k * g.cpw * g.mx;
+  const int xbi = (int)g.f_cpwxb.div((uint32_t)r), r2 = r - xbi * g.cpw * g.xb;
+  const int c = (int)g.f_xb.div((uint32_t)r2), xi = r2 - c * g.xb;
+  const int nxb = g.mx / g.xb;
+  fo = (k * g.cpw + c) * g.mx + xbi * g.xb + xi;
+  go = (((long long)k * nxb + xbi) * g.ncls + c0 + c) * g.xb + xi;
 }
 
 // Forward pass 2.  grid = ncls/cpw blocks of cpw*mx*S/E threads.
@@ -271,61 +361,72 @@ __global__ __launch_bounds__(1024) void k_class_fwd(Geo g, const float2* __restr
   float2* twx = lds;
   float2* twm = twx + g.nx;
   float2* U0 = twm + g.mx;
-  float2* U1 = U0 + g.nx * W;
-  float2* F0 = U1 + g.nx * W;
+  float2* U1 = U0 + W * g.lsx;
+  float2* F0 = U1 + W * g.lsx;
   float2* F1 = F0 + g.K * g.cpw * g.mx;
-  load_table(twx, tw_x, g.nx);
-  load_table(twm, tw_mx, g.mx);
   const int c0 = blockIdx.x * g.cpw;
-  for (int p = threadIdx.x; p < g.nx * W; p += blockDim.x) {
-    const int xx = p / W, e = p % W;
-    U0[p] = uperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e];
-  }
-  const float2* U = fft_lds<-1>(U0, U1, twx, g.nx, W, LineMap{W, 0, 1, W}, true);
   // this thread's E spectrum elements: all share class cl and folded frequency qxp
   const int e0 = threadIdx.x * E;
   const int per_cls = g.mx * g.S;
-  const int cl = e0 / per_cls;
-  const int rem = e0 % per_cls;
-  const int qxp = rem / g.S;
-  const int within = rem % g.S;
+  const int cl = (int)g.f_mxS.div((uint32_t)e0);
+  const int rem = e0 - cl * per_cls;
+  const int qxp = (int)g.f_S.div((uint32_t)rem);
+  const int within = rem - qxp * g.S;
+  const long long hoff0 = (long long)c0 * per_cls + e0;
+  // spectra do not depend on the data: start streaming them first
+  HLoad<HC, E> hb[HPF];
+#pragma unroll
+  for (int i = 0; i < HPF; ++i)
+    if (i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  load_table(twx, tw_x, g.nx);
+  load_table(twm, tw_mx, g.mx);
+  batched<8, float2>(g.nx * W,
+                     [&](int p) {
+                       const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+                       return uperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e];
+                     },
+                     [&](int p, float2 v) {
+                       const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+                       U0[e * g.lsx + xx] = v;
+                     });
+  const float2* U = fft_lines<-1>(U0, U1, twx, g.nx, W, g.lsx);
   float2 ur[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int w = within + i;
-    const int jx = w / g.nmem, m = w % g.nmem;
-    ur[i] = U[(qxp + jx * g.mx) * W + cl * g.nmem + m];
+    const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
+    ur[i] = U[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx];
   }
   const int LG = g.S / E;
-  const long long hoff0 = (long long)c0 * per_cls + e0;
-  HLoad<HC, E> hc, hn;
-  hc.load(hs, hoff0);
-  for (int k = 0; k < g.K; ++k) {
-    if (k + 1 < g.K) hn.load(hs, (long long)(k + 1) * g.hsz + hoff0);
-    float2 acc = make_float2(0.f, 0.f);
-    if constexpr (HC == 0) {
+  for (int k0 = 0; k0 < g.K; k0 += HPF) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) { acc.x += hc.v[i].x * ur[i].x; acc.y += hc.v[i].x * ur[i].y; }
-      if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
-    } else {
+    for (int i = 0; i < HPF; ++i) {
+      const int k = k0 + i;
+      if (k < g.K) {
+        float2 acc = make_float2(0.f, 0.f);
+        if constexpr (HC == 0) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) acc = cadd(acc, cmul(hc.v[i], ur[i]));
+          for (int t = 0; t < E; ++t) { acc.x += hb[i].v[t] * ur[t].x; acc.y += hb[i].v[t] * ur[t].y; }
+          if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
+        } else {
+#pragma unroll
+          for (int t = 0; t < E; ++t) acc = cadd(acc, cmul(hb[i].v[t], ur[t]));
+        }
+        if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
+        for (int o = LG >> 1; o >= 1; o >>= 1) {
+          acc.x += __shfl_xor(acc.x, o, 64);
+          acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if ((threadIdx.x & (LG - 1)) == 0) F0[(k * g.cpw + cl) * g.mx + qxp] = acc;
+      }
     }
-    for (int o = LG >> 1; o >= 1; o >>= 1) {
-      acc.x += __shfl_xor(acc.x, o, 64);
-      acc.y += __shfl_xor(acc.y, o, 64);
-    }
-    if ((threadIdx.x % LG) == 0) F0[(k * g.cpw + cl) * g.mx + qxp] = acc;
-    hc = hn;
   }
-  const float2* F = fft_lds<+1>(F0, F1, twm, g.mx, g.K * g.cpw, LineMap{g.K * g.cpw, 0, g.mx, 1}, false);
-  const int nxb = g.mx / g.xb;
-  const int per_k = g.cpw * g.mx;
-  for (int p = threadIdx.x; p < g.K * per_k; p += blockDim.x) {
-    const int k = p / per_k, r = p % per_k;
-    const int xbi = r / (g.cpw * g.xb), r2 = r % (g.cpw * g.xb);
-    const int c = r2 / g.xb, xi = r2 % g.xb;
-    G[(((long long)k * nxb + xbi) * g.ncls + c0 + c) * g.xb + xi] = F[(k * g.cpw + c) * g.mx + xbi * g.xb + xi];
+  const float2* F = fft_lines<+1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
+  for (int p = threadIdx.x; p < g.K * g.cpw * g.mx; p += blockDim.x) {
+    int fo;
+    long long go;
+    class_g_index(g, p, c0, fo, go);
+    G[go] = F[fo];
   }
 }
 
@@ -343,76 +444,100 @@ __global__ __launch_bounds__(1024) void k_class_adj(Geo g, const float2* __restr
   float2* twx = lds;
   float2* twm = twx + g.nx;
   float2* U0 = twm + g.mx;
-  float2* U1 = U0 + g.nx * W;
-  float2* F0 = U1 + g.nx * W;
+  float2* U1 = U0 + W * g.lsx;
+  float2* F0 = U1 + W * g.lsx;
   float2* F1 = F0 + g.K * g.cpw * g.mx;
-  load_table(twx, tw_x, g.nx);
-  load_table(twm, tw_mx, g.mx);
   const int c0 = blockIdx.x * g.cpw;
-  const int nxb = g.mx / g.xb;
-  const int per_k = g.cpw * g.mx;
-  for (int p = threadIdx.x; p < g.K * per_k; p += blockDim.x) {
-    const int k = p / per_k, r = p % per_k;
-    const int xbi = r / (g.cpw * g.xb), r2 = r % (g.cpw * g.xb);
-    const int c = r2 / g.xb, xi = r2 % g.xb;
-    F0[(k * g.cpw + c) * g.mx + xbi * g.xb + xi] = Gp[(((long long)k * nxb + xbi) * g.ncls + c0 + c) * g.xb + xi];
-  }
-  const float2* F = fft_lds<-1>(F0, F1, twm, g.mx, g.K * g.cpw, LineMap{g.K * g.cpw, 0, g.mx, 1}, false);
   const int e0 = threadIdx.x * E;
   const int per_cls = g.mx * g.S;
-  const int cl = e0 / per_cls;
-  const int rem = e0 % per_cls;
-  const int qxp = rem / g.S;
-  const int within = rem % g.S;
+  const int cl = (int)g.f_mxS.div((uint32_t)e0);
+  const int rem = e0 - cl * per_cls;
+  const int qxp = (int)g.f_S.div((uint32_t)rem);
+  const int within = rem - qxp * g.S;
+  const long long hoff0 = (long long)c0 * per_cls + e0;
+  HLoad<HC, E> hb[HPF];
+#pragma unroll
+  for (int i = 0; i < HPF; ++i)
+    if (i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  load_table(twx, tw_x, g.nx);
+  load_table(twm, tw_mx, g.mx);
+  batched<8, float2>(g.K * g.cpw * g.mx,
+                     [&](int p) {
+                       int fo;
+                       long long go;
+                       class_g_index(g, p, c0, fo, go);
+                       return Gp[go];
+                     },
+                     [&](int p, float2 v) {
+                       int fo;
+                       long long go;
+                       class_g_index(g, p, c0, fo, go);
+                       F0[fo] = v;
+                     });
+  const float2* F = fft_lines<-1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
   float2 acc[E];
 #pragma unroll
-  for (int i = 0; i < E; ++i) acc[i] = make_float2(0.f, 0.f);
-  const long long hoff0 = (long long)c0 * per_cls + e0;
-  HLoad<HC, E> hc, hn;
-  hc.load(hs, hoff0);
-  for (int k = 0; k < g.K; ++k) {
-    if (k + 1 < g.K) hn.load(hs, (long long)(k + 1) * g.hsz + hoff0);
-    float2 R = F[(k * g.cpw + cl) * g.mx + qxp];
-    if constexpr (HC == 0) {
-      // conj(i h) R = -i h R
-      if ((imag_mask >> k) & 1u) R = make_float2(R.y, -R.x);
+  for (int t = 0; t < E; ++t) acc[t] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < g.K; k0 += HPF) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) { acc[i].x += hc.v[i].x * R.x; acc[i].y += hc.v[i].x * R.y; }
-    } else {
+    for (int i = 0; i < HPF; ++i) {
+      const int k = k0 + i;
+      if (k < g.K) {
+        float2 R = F[(k * g.cpw + cl) * g.mx + qxp];
+        if constexpr (HC == 0) {
+          // conj(i h) R = -i h R
+          if ((imag_mask >> k) & 1u) R = make_float2(R.y, -R.x);
 #pragma unroll
-      for (int i = 0; i < E; ++i) acc[i] = cadd(acc[i], cmulcj(hc.v[i], R));
+          for (int t = 0; t < E; ++t) { acc[t].x += hb[i].v[t] * R.x; acc[t].y += hb[i].v[t] * R.y; }
+        } else {
+#pragma unroll
+          for (int t = 0; t < E; ++t) acc[t] = cadd(acc[t], cmulcj(hb[i].v[t], R));
+        }
+        if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
+      }
     }
-    hc = hn;
   }
   // every element of the group is written exactly once
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int w = within + i;
-    const int jx = w / g.nmem, m = w % g.nmem;
-    U0[(qxp + jx * g.mx) * W + cl * g.nmem + m] = acc[i];
+  for (int t = 0; t < E; ++t) {
+    const int w = within + t;
+    const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
+    U0[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] = acc[t];
   }
-  const float2* V = fft_lds<+1>(U0, U1, twx, g.nx, W, LineMap{W, 0, 1, W}, true);
+  const float2* V = fft_lines<+1>(U0, U1, twx, g.nx, W, g.lsx);
   for (int p = threadIdx.x; p < g.nx * W; p += blockDim.x) {
-    const int xx = p / W, e = p % W;
-    vperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e] = V[p];
+    const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+    vperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e] = V[e * g.lsx + xx];
   }
 }
 
 // ============================================================================ pass 3: small grid
 enum { EPI_STORE = 0, EPI_RESID = 1, EPI_RESID_BACK = 2, EPI_BACK = 3 };
 
+// Small-grid LDS layout: column (xi, q'z) holds the y' line at
+// X[(xi*mzh + q'z)*lsmy + y'], rows r = xi*my + y' of real data are packed in pairs.
+__device__ __forceinline__ RowCols small_rowcols(const Geo& g) {
+  RowCols rc;
+  rc.qstride = g.lsmy;
+  rc.per_blk = g.my;
+  rc.f_blk = g.f_my;
+  rc.blk_stride = g.mzh * g.lsmy;
+  return rc;
+}
+
 // 2-D R2C over (y', z') of the small-grid rows held as packed pairs in *a, then
 // store the class layout G[k][xbi][class][xi].
 __device__ void small_r2c_and_store(const Geo& g, float2* a, float2* b, const float2* twy, const float2* twz,
                                     float2* __restrict__ Gout, int k, int xbi) {
   const int rows = g.xb * g.my;
-  float2* X = r2c_rows(a, b, twz, rows, g.mz, g.mzh, g.mzh, g.spairs);   // X[xi][class]
-  float2* Y = fft_lds<-1>(X, X == a ? b : a, twy, g.my, g.xb * g.mzh, LineMap{g.mzh, g.ncls, 1, g.mzh}, true);
+  float2* X = r2c_rows(a, b, twz, rows, g.mz, g.mzh, g.spairs, small_rowcols(g), g.f_mzh);
+  float2* Y = fft_lines<-1>(X, X == a ? b : a, twy, g.my, g.xb * g.mzh, g.lsmy);
   const int nxb = g.mx / g.xb;
   float2* dst = Gout + ((long long)k * nxb + xbi) * g.ncls * g.xb;
   for (int p = threadIdx.x; p < g.ncls * g.xb; p += blockDim.x) {
-    const int c = p / g.xb, xi = p % g.xb;
-    dst[p] = Y[xi * g.ncls + c];
+    const int c = (int)g.f_xb.div((uint32_t)p), xi = p - c * g.xb;
+    const int qy = (int)g.f_mzh.div((uint32_t)c), qz = c - qy * g.mzh;
+    dst[p] = Y[(xi * g.mzh + qz) * g.lsmy + qy];
   }
 }
 
@@ -436,31 +561,39 @@ __global__ __launch_bounds__(1024) void k_small_inv(Geo g, const float2* __restr
   load_table(twy, tw_my, g.my);
   load_table(twz, tw_mz, g.mz);
   const int nxb = g.mx / g.xb;
-  const int k = blockIdx.x / nxb, xbi = blockIdx.x % nxb;
+  const int k = blockIdx.x / nxb, xbi = blockIdx.x - (blockIdx.x / nxb) * nxb;
   const float2* src = G + ((long long)k * nxb + xbi) * g.ncls * g.xb;
-  for (int p = threadIdx.x; p < g.ncls * g.xb; p += blockDim.x) {
-    const int c = p / g.xb, xi = p % g.xb;
-    P0[xi * g.ncls + c] = src[p];
-  }
-  float2* X = fft_lds<+1>(P0, P1, twy, g.my, g.xb * g.mzh, LineMap{g.mzh, g.ncls, 1, g.mzh}, true);
+  batched<8, float2>(g.ncls * g.xb, [&](int p) { return src[p]; },
+                     [&](int p, float2 v) {
+                       const int c = (int)g.f_xb.div((uint32_t)p), xi = p - c * g.xb;
+                       const int qy = (int)g.f_mzh.div((uint32_t)c), qz = c - qy * g.mzh;
+                       P0[(xi * g.mzh + qz) * g.lsmy + qy] = v;
+                     });
+  float2* X = fft_lines<+1>(P0, P1, twy, g.my, g.xb * g.mzh, g.lsmy);
   const int rows = g.xb * g.my;
-  float2* Z = c2r_rows(X, X == P0 ? P1 : P0, twz, rows, g.mz, g.mzh, g.mzh, g.spairs);
-  // Z holds packed real rows: row r at pair r/2, .x (even) / .y (odd)
+  float2* Z = c2r_rows(X, X == P0 ? P1 : P0, twz, rows, g.mz, g.spairs, small_rowcols(g), g.f_mz);
+  // Z holds packed real rows: row r at pair r/2, .x (even) / .y (odd), line stride lsmz
+  const int lsmz = pad_odd(g.mz);
   float* Zf = reinterpret_cast<float*>(Z);
   const long long obase = (long long)k * g.M + (long long)xbi * g.xb * g.my * g.mz;
   const int n = rows * g.mz;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const int r = p / g.mz, z = p % g.mz;
-    const int li = 2 * ((r >> 1) * g.mz + z) + (r & 1);
-    const float v = Zf[li];
-    if constexpr (EPI == EPI_STORE) d[obase + p] = v;
-    else if constexpr (EPI == EPI_RESID) d[obase + p] = v - dmeas[obase + p];
-    else if constexpr (EPI == EPI_RESID_BACK) Zf[li] = v - dmeas[obase + p];
-    // EPI_BACK keeps v in place
+  auto lidx = [&](int p) {
+    const int r = (int)g.f_mz.div((uint32_t)p), z = p - r * g.mz;
+    return 2 * ((r >> 1) * lsmz + z) + (r & 1);
+  };
+  if constexpr (EPI == EPI_STORE) {
+    for (int p = threadIdx.x; p < n; p += blockDim.x) d[obase + p] = Zf[lidx(p)];
+  } else if constexpr (EPI == EPI_RESID) {
+    batched<8, float>(n, [&](int p) { return dmeas[obase + p]; },
+                      [&](int p, float m) { d[obase + p] = Zf[lidx(p)] - m; });
+  } else if constexpr (EPI == EPI_RESID_BACK) {
+    batched<8, float>(n, [&](int p) { return dmeas[obase + p]; },
+                      [&](int p, float m) { const int li = lidx(p); Zf[li] = Zf[li] - m; });
   }
+  // EPI_BACK keeps the values in place
   if constexpr (EPI == EPI_RESID_BACK || EPI == EPI_BACK) {
     if (rows & 1) {
-      for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * g.mz + z) + 1] = 0.f;
+      for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * lsmz + z) + 1] = 0.f;
     }
     small_r2c_and_store(g, Z, Z == P0 ? P1 : P0, twy, twz, Gp, k, xbi);
   }
@@ -480,17 +613,19 @@ __global__ __launch_bounds__(1024) void k_small_fwd(Geo g, const float* __restri
   load_table(twy, tw_my, g.my);
   load_table(twz, tw_mz, g.mz);
   const int nxb = g.mx / g.xb;
-  const int k = blockIdx.x / nxb, xbi = blockIdx.x % nxb;
+  const int k = blockIdx.x / nxb, xbi = blockIdx.x - (blockIdx.x / nxb) * nxb;
   const int rows = g.xb * g.my;
+  const int lsmz = pad_odd(g.mz);
   const long long ibase = (long long)k * g.M + (long long)xbi * g.xb * g.my * g.mz;
   float* Zf = reinterpret_cast<float*>(P0);
   const int n = rows * g.mz;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const int rr = p / g.mz, z = p % g.mz;
-    Zf[2 * ((rr >> 1) * g.mz + z) + (rr & 1)] = r[ibase + p];
-  }
+  batched<8, float>(n, [&](int p) { return r[ibase + p]; },
+                    [&](int p, float v) {
+                      const int rr = (int)g.f_mz.div((uint32_t)p), z = p - rr * g.mz;
+                      Zf[2 * ((rr >> 1) * lsmz + z) + (rr & 1)] = v;
+                    });
   if (rows & 1) {
-    for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * g.mz + z) + 1] = 0.f;
+    for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * lsmz + z) + 1] = 0.f;
   }
   small_r2c_and_store(g, P0, P1, twy, twz, Gp, k, xbi);
 }
@@ -498,30 +633,16 @@ __global__ __launch_bounds__(1024) void k_small_fwd(Geo g, const float* __restri
 // ============================================================================ pass 1 adjoint
 enum { OUT_SCALE_B = 0, OUT_NORMAL = 1, OUT_FISTA = 2 };
 
-// T^T T y at (x, y, z) for stacked periodic second differences: sum over axes of
-// y[+2] - 4 y[+1] + 6 y - 4 y[-1] + y[-2]; reg_kind 1 gives T = I.
-template <typename F>
-__device__ __forceinline__ float reg_stencil(const Geo& g, int reg_kind, int x, int y, int z, F val) {
-  const float c = val(x, y, z);
-  if (reg_kind == 1) return c;
-  auto wrap = [](int i, int n) { i %= n; return i < 0 ? i + n : i; };
-  float s = 18.f * c;
-  s += val(wrap(x + 2, g.nx), y, z) + val(wrap(x - 2, g.nx), y, z) - 4.f * (val(wrap(x + 1, g.nx), y, z) + val(wrap(x - 1, g.nx), y, z));
-  s += val(x, wrap(y + 2, g.ny), z) + val(x, wrap(y - 2, g.ny), z) - 4.f * (val(x, wrap(y + 1, g.ny), z) + val(x, wrap(y - 1, g.ny), z));
-  s += val(x, y, wrap(z + 2, g.nz)) + val(x, y, wrap(z - 2, g.nz)) - 4.f * (val(x, y, wrap(z + 1, g.nz)) + val(x, y, wrap(z - 1, g.nz)));
-  return s;
-}
-
 struct AdjOut {
   float* out;              // OUT_SCALE_B / OUT_NORMAL: result
-  const float* vin;        // OUT_NORMAL: w_{t-1} (v = scale * w_{t-1});  OUT_FISTA: rho^k
-  const float* vprev;      // OUT_FISTA: rho^{k-1}
+  const float* yin;        // OUT_NORMAL: w_{t-1} (v = scale * w_{t-1});  OUT_FISTA: y^k
+  const float* rk;         // OUT_FISTA: rho^k
   float* rho_next;         // OUT_FISTA: rho^{k+1}
-  double* partials;        // per-block FP64 partial sums [gridDim][2]
+  float* y_next;           // OUT_FISTA: y^{k+1} = rho^{k+1} + beta_{k+1} (rho^{k+1} - rho^k)
+  double* partials;        // per-block FP64 partial sums
   DevState* st;
   int reg_kind;
   float lam;
-  float* hist;             // unused placeholder
   double* hist64;          // FISTA: history of r_k indexed by (k - k_first)
   int k_first;
   int hist_len;
@@ -556,13 +677,21 @@ __device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, De
   return threadIdx.x == 0;
 }
 
+// Values of one voxel's stencil that live outside the block's x-plane.
+struct XNb {
+  float b, xm2, xm1, xp1, xp2, rk;
+};
+
 // Adjoint pass 1: gather the class layout into a half plane, inverse y FFT, C2R
 // along z, then the epilogue:
 //   OUT_SCALE_B  out = b . v                                  (A^T)
 //   OUT_NORMAL   out = b . v + lam T^T T (s w_prev); FP64 <s w_prev, out>, ||out||^2
 //   OUT_FISTA    g = b . v + lam T^T T y^k; rho^{k+1} = max(y^k - tau g, 0);
-//                FP64 ||rho^{k+1} - y^k||^2, ||rho^{k+1}||^2
-// grid = nx blocks.
+//                y^{k+1} = rho^{k+1} + k/(k+3) (rho^{k+1} - rho^k);
+//                FP64 ||rho^{k+1} - y^k||^2, ||rho^{k+1}||^2, count of non-finite g
+// T^T T is the periodic 13-point stencil sum_a (y[+2] - 4y[+1] + 6y - 4y[-1] + y[-2])
+// of stacked second differences (reg_kind 1: T = I).  In-plane neighbours come from
+// the plane staged in LDS, x-neighbours from global memory.  grid = nx blocks.
 template <int OUT>
 __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restrict__ vperm,
                                                     const float* __restrict__ b, AdjOut ao,
@@ -580,83 +709,126 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
   __shared__ double red[64];
   load_table(twz, tw_z, g.nz);
   load_table(twy, tw_y, g.ny);
-  const int x = blockIdx.x;
+  const int x = plane_of_block(blockIdx.x, g.nx);
   const float2* src = vperm + (long long)x * g.plane;
+  batched<8, float2>(g.plane, [&](int e) { return src[e]; }, [&](int e, float2 v) { P1[e] = v; });
+  __syncthreads();
   for (int p = threadIdx.x; p < g.ny * g.nzh; p += blockDim.x) {
-    const int qy = p / g.nzh, qz = p % g.nzh;
+    const int qz = (int)g.f_ny.div((uint32_t)p), qy = p - qz * g.ny;
     bool cj;
     const int e = class_index_of(g, qy, qz, cj);
-    const float2 v = src[e];
-    P0[p] = cj ? make_float2(v.x, -v.y) : v;
+    const float2 v = P1[e];
+    P0[qz * g.lsy + qy] = cj ? make_float2(v.x, -v.y) : v;
   }
-  float2* X = fft_lds<+1>(P0, P1, twy, g.ny, g.nzh, LineMap{g.nzh, 0, 1, g.nzh}, true);
-  float2* Z = c2r_rows(X, X == P0 ? P1 : P0, twz, g.ny, g.nz, g.nzh, g.nzh, g.npairs);
+  float2* X = fft_lines<+1>(P0, P1, twy, g.ny, g.nzh, g.lsy);
+  float2* Z = c2r_rows(X, X == P0 ? P1 : P0, twz, g.ny, g.nz, g.npairs, plane_rowcols(g), g.f_nz);
+  const int lsz = pad_odd(g.nz);
   const float* Xf = reinterpret_cast<const float*>(Z);
+  auto vidx = [&](int p) {
+    const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
+    return 2 * ((y >> 1) * lsz + z) + (y & 1);
+  };
   const long long pbase = (long long)x * g.ny * g.nz;
   const int nyz = g.ny * g.nz;
-  double acc[2] = {0.0, 0.0};
   if constexpr (OUT == OUT_SCALE_B) {
-    for (int p = threadIdx.x; p < nyz; p += blockDim.x) {
-      const int y = p / g.nz, z = p % g.nz;
-      ao.out[pbase + p] = b[pbase + p] * Xf[2 * ((y >> 1) * g.nz + z) + (y & 1)];
-    }
+    batched<8, float>(nyz, [&](int p) { return b[pbase + p]; },
+                      [&](int p, float bv) { ao.out[pbase + p] = bv * Xf[vidx(p)]; });
     return;
-  } else if constexpr (OUT == OUT_NORMAL) {
-    const float s = (float)ao.st->scale;
-    const float* w = ao.vin;
-    auto val = [&](int xx, int yy, int zz) { return s * w[((long long)xx * g.ny + yy) * g.nz + zz]; };
-    for (int p = threadIdx.x; p < nyz; p += blockDim.x) {
-      const int y = p / g.nz, z = p % g.nz;
-      const float o = b[pbase + p] * Xf[2 * ((y >> 1) * g.nz + z) + (y & 1)] + ao.lam * reg_stencil(g, ao.reg_kind, x, y, z, val);
-      ao.out[pbase + p] = o;
-      acc[0] += (double)val(x, y, z) * (double)o;
-      acc[1] += (double)o * (double)o;
-    }
-    if (grid_reduce_last<2>(acc, ao.partials, ao.st, red)) {
-      DevState* st = ao.st;
-      st->lmax = acc[0];
-      st->scale = 1.0 / sqrt(acc[1]);
-      if (!(acc[0] == acc[0]) || !(acc[1] < 1e300)) st->nonfinite = 1.0;
-    }
   } else {
-    DevState* st = ao.st;
-    const int kk = st->k;
-    const float beta = (float)((kk - 1.0) / (kk + 2.0));
-    const float tau = (float)st->tau;
-    const float* rk = ao.vin;
-    const float* rkm1 = ao.vprev;
-    auto yv = [&](int xx, int yy, int zz) {
-      const long long i = ((long long)xx * g.ny + yy) * g.nz + zz;
-      const float r = rk[i];
-      return r + beta * (r - rkm1[i]);
-    };
-    double acc3[3] = {0.0, 0.0, 0.0};
-    for (int p = threadIdx.x; p < nyz; p += blockDim.x) {
-      const int y = p / g.nz, z = p % g.nz;
-      const float yk = yv(x, y, z);
-      const float gr = b[pbase + p] * Xf[2 * ((y >> 1) * g.nz + z) + (y & 1)] + ao.lam * reg_stencil(g, ao.reg_kind, x, y, z, yv);
-      const float nx = fmaxf(yk - tau * gr, 0.f);
-      ao.rho_next[pbase + p] = nx;
-      const double dd = (double)nx - (double)yk;
-      acc3[0] += dd * dd;
-      acc3[1] += (double)nx * (double)nx;
-      if (!isfinite(gr) || !isfinite(yk)) acc3[2] += 1.0;   // max(NaN, 0) would hide it
-    }
-    if (grid_reduce_last<3>(acc3, ao.partials, ao.st, red)) {
-      double r;
-      if (acc3[1] == 0.0) r = (acc3[0] == 0.0) ? 0.0 : __builtin_inf();
-      else r = sqrt(acc3[0]) / sqrt(acc3[1]);
-      st->rel_step = r;
-      st->last_k = kk;
-      const int hi = kk - ao.k_first;
-      if (ao.hist64 && hi >= 0 && hi < ao.hist_len) ao.hist64[hi] = r;
-      if (acc3[2] != 0.0 || !(acc3[0] == acc3[0]) || !(acc3[1] == acc3[1]) || acc3[1] > 1e300) {
-        st->nonfinite = 1.0;
-        st->done = 1;
+    // stage the regularised vector of this plane in the free LDS buffer
+    float* Yl = reinterpret_cast<float*>(Z == P0 ? P1 : P0);
+    const float s = (OUT == OUT_NORMAL) ? (float)ao.st->scale : 1.f;
+    const float* yv = ao.yin;
+    batched<8, float>(nyz, [&](int p) { return yv[pbase + p]; }, [&](int p, float v) { Yl[p] = s * v; });
+    __syncthreads();
+    const long long plane_sz = (long long)g.ny * g.nz;
+    const long long xm2 = (long long)((x - 2 + 2 * g.nx) % g.nx) * plane_sz;
+    const long long xm1 = (long long)((x - 1 + g.nx) % g.nx) * plane_sz;
+    const long long xp1 = (long long)((x + 1) % g.nx) * plane_sz;
+    const long long xp2 = (long long)((x + 2) % g.nx) * plane_sz;
+    const bool stencil = ao.reg_kind == 0;
+    auto ld = [&](int p) {
+      XNb v;
+      v.b = b[pbase + p];
+      if (stencil) {
+        v.xm2 = yv[xm2 + p]; v.xm1 = yv[xm1 + p]; v.xp1 = yv[xp1 + p]; v.xp2 = yv[xp2 + p];
+      } else {
+        v.xm2 = v.xm1 = v.xp1 = v.xp2 = 0.f;
       }
-      if (r <= st->tol || kk >= st->kmax) st->done = 1;
-      st->k = kk + 1;
+      if constexpr (OUT == OUT_FISTA) v.rk = ao.rk[pbase + p];
+      else v.rk = 0.f;
+      return v;
+    };
+    auto reg = [&](int p, const XNb& v) {
+      const float c = Yl[p];
+      if (!stencil) return c;
+      const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
+      const int ym2 = (y - 2 + 2 * g.ny) % g.ny, ym1 = (y - 1 + g.ny) % g.ny;
+      const int yp1 = (y + 1) % g.ny, yp2 = (y + 2) % g.ny;
+      const int zm2 = (z - 2 + 2 * g.nz) % g.nz, zm1 = (z - 1 + g.nz) % g.nz;
+      const int zp1 = (z + 1) % g.nz, zp2 = (z + 2) % g.nz;
+      float t = 18.f * c;
+      t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
+      t += Yl[yp2 * g.nz + z] + Yl[ym2 * g.nz + z] - 4.f * (Yl[yp1 * g.nz + z] + Yl[ym1 * g.nz + z]);
+      t += Yl[y * g.nz + zp2] + Yl[y * g.nz + zm2] - 4.f * (Yl[y * g.nz + zp1] + Yl[y * g.nz + zm1]);
+      return t;
+    };
+    if constexpr (OUT == OUT_NORMAL) {
+      double acc[2] = {0.0, 0.0};
+      batched<4, XNb>(nyz, ld, [&](int p, const XNb& v) {
+        const float o = v.b * Xf[vidx(p)] + ao.lam * reg(p, v);
+        ao.out[pbase + p] = o;
+        acc[0] += (double)Yl[p] * (double)o;
+        acc[1] += (double)o * (double)o;
+      });
+      if (grid_reduce_last<2>(acc, ao.partials, ao.st, red)) {
+        DevState* st = ao.st;
+        st->lmax = acc[0];
+        st->scale = 1.0 / sqrt(acc[1]);
+        if (!(acc[0] == acc[0]) || !(acc[1] < 1e300)) st->nonfinite = 1.0;
+      }
+    } else {
+      DevState* st = ao.st;
+      const int kk = st->k;
+      const float tau = (float)st->tau;
+      const float beta1 = (float)((double)kk / (kk + 3.0));      // (k+1-1)/(k+1+2)
+      double acc[3] = {0.0, 0.0, 0.0};
+      batched<4, XNb>(nyz, ld, [&](int p, const XNb& v) {
+        const float yk = Yl[p];
+        const float gr = v.b * Xf[vidx(p)] + ao.lam * reg(p, v);
+        const float rn = fmaxf(yk - tau * gr, 0.f);
+        ao.rho_next[pbase + p] = rn;
+        ao.y_next[pbase + p] = rn + beta1 * (rn - v.rk);
+        const double dd = (double)rn - (double)yk;
+        acc[0] += dd * dd;
+        acc[1] += (double)rn * (double)rn;
+        if (!isfinite(gr) || !isfinite(yk)) acc[2] += 1.0;   // max(NaN, 0) would hide it
+      });
+      if (grid_reduce_last<3>(acc, ao.partials, ao.st, red)) {
+        double r;
+        if (acc[1] == 0.0) r = (acc[0] == 0.0) ? 0.0 : __builtin_inf();
+        else r = sqrt(acc[0]) / sqrt(acc[1]);
+        st->rel_step = r;
+        st->last_k = kk;
+        const int hi = kk - ao.k_first;
+        if (ao.hist64 && hi >= 0 && hi < ao.hist_len) ao.hist64[hi] = r;
+        if (acc[2] != 0.0 || !(acc[0] == acc[0]) || !(acc[1] == acc[1]) || acc[1] > 1e300) {
+          st->nonfinite = 1.0;
+          st->done = 1;
+        }
+        if (r <= st->tol || kk >= st->kmax) st->done = 1;
+        st->k = kk + 1;
+      }
     }
+  }
+}
+
+// y^{k0} = rho^{k0} + (k0-1)/(k0+2) (rho^{k0} - rho^{k0-1}) for a (re)started solve.
+__global__ void k_fista_init(long long n, const float* __restrict__ rk, const float* __restrict__ rkm1,
+                             float beta, float* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float r = rk[i];
+    y[i] = r + beta * (r - rkm1[i]);
   }
 }
 
@@ -714,7 +886,7 @@ __global__ __launch_bounds__(256) void k_psf_profile(int nx, const int* __restri
     X[i] = make_double2(f, 0.0);
     acc[0] += f * f;
   }
-  const double2* F = fft_lds<-1>(X, X1, tw, nx, 1, LineMap{1, 0, nx, 1}, false);
+  const double2* F = fft_lines<-1>(X, X1, tw, nx, 1, nx);
   for (int i = threadIdx.x; i < nx; i += blockDim.x) fhat[(long long)k * nx + i] = F[i];
   block_reduce_f64<1>(acc, red);
   if (threadIdx.x == 0) fnorm2[k] = acc[0];
@@ -745,7 +917,7 @@ __global__ __launch_bounds__(256) void k_psf_env_rows(int ny, int nz, double a, 
     X[z] = make_double2(e, 0.0);
     acc[0] += e * e;
   }
-  const double2* F = fft_lds<-1>(X, X1, tw, nz, 1, LineMap{1, 0, nz, 1}, false);
+  const double2* F = fft_lines<-1>(X, X1, tw, nz, 1, nz);
   for (int z = threadIdx.x; z < nz; z += blockDim.x) tmp[(long long)y * nz + z] = F[z];
   block_reduce_f64<1>(acc, red);
   if (threadIdx.x == 0) rowsum[y] = acc[0];
@@ -761,7 +933,7 @@ __global__ __launch_bounds__(256) void k_psf_env_cols(int ny, int nz, const doub
   const int qz = blockIdx.x;
   load_table(tw, tw64y, ny);
   for (int y = threadIdx.x; y < ny; y += blockDim.x) X[y] = tmp[(long long)y * nz + qz];
-  const double2* F = fft_lds<-1>(X, X1, tw, ny, 1, LineMap{1, 0, ny, 1}, false);
+  const double2* F = fft_lines<-1>(X, X1, tw, ny, 1, ny);
   for (int y = threadIdx.x; y < ny; y += blockDim.x) ehat[(long long)y * (nz / 2 + 1) + qz] = F[y];
 }
 
@@ -813,21 +985,26 @@ __global__ __launch_bounds__(1024) void k_class_hcopy(Geo g, int k, const float2
   float2* twx = lds;
   const int W = g.cpw * g.nmem;
   float2* U0 = twx + g.nx;
-  float2* U1 = U0 + g.nx * W;
+  float2* U1 = U0 + W * g.lsx;
   load_table(twx, tw_x, g.nx);
   const int c0 = blockIdx.x * g.cpw;
-  for (int p = threadIdx.x; p < g.nx * W; p += blockDim.x) {
-    const int xx = p / W, e = p % W;
-    U0[p] = uperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e];
-  }
-  const float2* Ul = fft_lds<-1>(U0, U1, twx, g.nx, W, LineMap{W, 0, 1, W}, true);
+  batched<8, float2>(g.nx * W,
+                     [&](int p) {
+                       const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+                       return uperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e];
+                     },
+                     [&](int p, float2 v) {
+                       const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+                       U0[e * g.lsx + xx] = v;
+                     });
+  const float2* Ul = fft_lines<-1>(U0, U1, twx, g.nx, W, g.lsx);
   const float invN = (float)(1.0 / (double)g.N);
   const int per_cls = g.mx * g.S;
   for (int t = threadIdx.x; t < g.cpw * per_cls; t += blockDim.x) {
-    const int cl = t / per_cls, r2 = t % per_cls;
-    const int qxp = r2 / g.S, w = r2 % g.S;
-    const int jx = w / g.nmem, m = w % g.nmem;
-    const float2 v = Ul[(qxp + jx * g.mx) * W + cl * g.nmem + m];
+    const int cl = (int)g.f_mxS.div((uint32_t)t), r2 = t - cl * per_cls;
+    const int qxp = (int)g.f_S.div((uint32_t)r2), w = r2 - qxp * g.S;
+    const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
+    const float2 v = Ul[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx];
     hs[(long long)k * g.hsz + (long long)c0 * per_cls + t] = make_float2(v.x * invN, v.y * invN);
   }
 }

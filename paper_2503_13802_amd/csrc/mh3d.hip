@@ -114,10 +114,27 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
   g.N = (long long)g.nx * g.ny * g.nz;
   g.M = (long long)g.mx * g.my * g.mz;
   g.hsz = (long long)g.plane * g.nx;
-  g.E = pick_E(g.S);
-  if (g.E < 0) return fail(MH3D_ERR_UNSUPPORTED, "decimation product %d has no supported fold split", g.S);
+  g.lsy = pad_odd(g.ny);
+  g.lsx = pad_odd(g.nx);
+  g.lsmy = pad_odd(g.my);
 
-  // ---- class kernel: classes per workgroup (cpw divides ncls; T = cpw*mx*S/E)
+  // ---- class kernel: elements per thread E (S/E a power of two <= 64) chosen so
+  // the launch has enough waves in flight, then classes per workgroup cpw
+  g.E = -1;
+  {
+    const int opts[7] = {8, 6, 4, 3, 2, 1, 9};
+    const long elems = (long)g.ncls * g.mx * g.S;
+    int fallback = -1;
+    for (int e : opts) {
+      if (g.S % e) continue;
+      const int lg = g.S / e;
+      if (lg > 64 || (lg & (lg - 1))) continue;
+      if (fallback < 0 || e < fallback) fallback = e;
+      if (elems / e >= 128 * 1024 && g.E < 0) g.E = e;
+    }
+    if (g.E < 0) g.E = fallback;
+  }
+  if (g.E < 0) return fail(MH3D_ERR_UNSUPPORTED, "decimation product %d has no supported fold split", g.S);
   int best_cpw = 0;
   for (int c = 1; c <= g.ncls; ++c) {
     if (g.ncls % c) continue;
@@ -127,7 +144,7 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
     t.cpw = c;
     if (class_lds_elems(t) * sizeof(float2) > 64 * 1024) break;
     best_cpw = c;
-    if (T >= 256 && T % 64 == 0) break;
+    if (T >= 128 && T % 64 == 0) break;
   }
   if (!best_cpw) return fail(MH3D_ERR_UNSUPPORTED, "no class-kernel shape fits (mx*S/E or LDS too large)");
   g.cpw = best_cpw;
@@ -141,6 +158,11 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
     if ((long)g.K * (g.mx / xb) >= 256 || xb == 1) { g.xb = xb; break; }
   }
   g.spairs = (g.xb * g.my + 1) / 2;
+  g.f_nz = make_fastdiv(g.nz); g.f_nzh = make_fastdiv(g.nzh); g.f_nmem = make_fastdiv(g.nmem);
+  g.f_mzh = make_fastdiv(g.mzh); g.f_sz = make_fastdiv(g.sz); g.f_mz = make_fastdiv(g.mz);
+  g.f_W = make_fastdiv(g.cpw * g.nmem); g.f_xb = make_fastdiv(g.xb); g.f_S = make_fastdiv(g.S);
+  g.f_mxS = make_fastdiv(g.mx * g.S); g.f_cpwmx = make_fastdiv(g.cpw * g.mx);
+  g.f_cpwxb = make_fastdiv(g.cpw * g.xb); g.f_ny = make_fastdiv(g.ny); g.f_my = make_fastdiv(g.my);
   L.T_small = 256;
   L.lds_small = sizeof(float2) * ((size_t)g.my + g.mz + 2 * (size_t)small_lds(g));
   if (L.lds_small > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "small-grid plane does not fit in LDS");
@@ -171,7 +193,7 @@ struct mh3d_plan_s {
   float2* uperm = nullptr;     // class-layout yz spectra of one volume (also adjoint V)
   float2* G = nullptr;         // decimated spectra (forward)
   float2* Gp = nullptr;        // decimated spectra (adjoint)
-  float* vol[3] = {nullptr, nullptr, nullptr};  // solver iterates / power vectors
+  float* vol[4] = {nullptr, nullptr, nullptr, nullptr};  // rho^k, rho^{k+1}, y^k, y^{k+1} / power vectors
   float* port = nullptr;       // portrait scratch
   float2* tw32 = nullptr;
   double2* tw64 = nullptr;
@@ -204,7 +226,7 @@ static size_t plan_bytes(const Geo& g, bool compact) {
   s += (size_t)g.N * 4;                               // b
   s += (size_t)g.nx * g.plane * 8;                    // uperm
   s += 2 * (size_t)g.K * g.mx * g.ncls * 8;           // G, Gp
-  s += 3 * (size_t)g.N * 4;                           // vol
+  s += 4 * (size_t)g.N * 4;                           // vol
   s += (size_t)g.K * g.M * 4;                         // port
   s += (size_t)(2 * (g.nx + g.ny + g.nz) + g.mx + g.my + g.mz) * 24;
   s += ((size_t)g.K * g.nx + (size_t)g.ny * g.nz) * 8;
@@ -431,7 +453,7 @@ static mh3d_status build_spectra_analytic(mh3d_plan_t p) {
 static mh3d_status build_spectra_user(mh3d_plan_t p) {
   const Geo& g = p->g;
   p->imag_mask = 0;
-  size_t lds = sizeof(float2) * ((size_t)g.nx + 2 * (size_t)g.nx * g.cpw * g.nmem);
+  size_t lds = sizeof(float2) * ((size_t)g.nx + 2 * (size_t)g.lsx * g.cpw * g.nmem);
   for (int k = 0; k < g.K; ++k) {
     CHK(launch_plane_fwd(p, SRC_RAW, p->desc.psf + (long long)k * g.N, nullptr, 1.f, nullptr));
     k_class_hcopy<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), lds, p->stream>>>(g, k, p->uperm,
@@ -446,7 +468,7 @@ extern "C" void mh3d_destroy(mh3d_plan_t p) {
   if (p->stream) hipStreamSynchronize(p->stream);
   for (auto& e : p->pending) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
   for (auto e : p->free_events) hipEventDestroy(e);
-  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->port,
+  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3], p->port,
                   p->tw32, p->tw64, p->prof, p->env, p->partials, p->st};
   for (void* q : bufs)
     if (q) hipFree(q);
@@ -480,7 +502,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = dalloc(p, (void**)&p->uperm, sizeof(float2) * (size_t)g.nx * g.plane)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->G, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->Gp, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 4; ++i)
     if ((s = dalloc(p, (void**)&p->vol[i], sizeof(float) * g.N)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->port, sizeof(float) * (size_t)g.K * g.M)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->prof, sizeof(double) * (size_t)g.K * g.nx)) != MH3D_OK) return bail(s);
@@ -552,7 +574,7 @@ static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out
   AdjOut ao;
   memset(&ao, 0, sizeof ao);
   ao.out = out;
-  ao.vin = w;
+  ao.yin = w;
   ao.partials = p->partials;
   ao.st = p->st;
   ao.reg_kind = p->desc.reg_kind;
@@ -627,10 +649,15 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
     tau = 1.0 / (1.05 * lmax);
   }
   const int k0 = opts->k0;
-  // iterates: rho^k in vol[k % 3], rho^{k-1} in vol[(k-1) % 3]
-  HIPCHK(hipMemcpyAsync(p->vol[k0 % 3], rho_inout, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
-  HIPCHK(hipMemcpyAsync(p->vol[(k0 - 1) % 3], opts->rho_prev ? opts->rho_prev : rho_inout, sizeof(float) * g.N,
-                        hipMemcpyDeviceToDevice, p->stream));
+  // rho^k in vol[k % 2], y^k in vol[2 + k % 2]
+  HIPCHK(hipMemcpyAsync(p->vol[k0 % 2], rho_inout, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
+  {
+    Timer t(p, KID_AUX);
+    const float* prev = opts->rho_prev ? opts->rho_prev : rho_inout;
+    k_fista_init<<<dim3(1024), dim3(256), 0, p->stream>>>(g.N, rho_inout, prev, (float)((k0 - 1.0) / (k0 + 2.0)),
+                                                            p->vol[2 + k0 % 2]);
+    CHK(last_launch("k_fista_init"));
+  }
   DevState s0;
   memset(&s0, 0, sizeof s0);
   s0.k = k0;
@@ -652,19 +679,17 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
     const int n = std::min(chunk, opts->max_iter - issued);
     for (int i = 0; i < n; ++i) {
       const int k = k0 + issued + i;   // host-side index only selects buffers
-      const float* rk = p->vol[k % 3];
-      const float* rkm1 = p->vol[(k + 2) % 3];
-      float* rnext = p->vol[(k + 1) % 3];
       Timer t(p, KID_SOLVE_ITER);
-      CHK(launch_plane_fwd(p, SRC_FISTA_Y, rk, rkm1, 0.f, p->st));
+      CHK(launch_plane_fwd(p, SRC_FISTA_Y, p->vol[2 + k % 2], nullptr, 0.f, p->st));
       CHK(launch_class_fwd(p, p->st));
       CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr, d, p->st));
       CHK(launch_class_adj(p, p->st));
       AdjOut ao;
       memset(&ao, 0, sizeof ao);
-      ao.vin = rk;
-      ao.vprev = rkm1;
-      ao.rho_next = rnext;
+      ao.yin = p->vol[2 + k % 2];
+      ao.rk = p->vol[k % 2];
+      ao.rho_next = p->vol[(k + 1) % 2];
+      ao.y_next = p->vol[2 + (k + 1) % 2];
       ao.partials = p->partials;
       ao.st = p->st;
       ao.reg_kind = p->desc.reg_kind;
@@ -681,7 +706,7 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
   const int last = h.last_k;
   const int iters = last - k0 + 1;
   if (iters >= 1) {
-    HIPCHK(hipMemcpyAsync(rho_inout, p->vol[(last + 1) % 3], sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(rho_inout, p->vol[(last + 1) % 2], sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
   }
   HIPCHK(hipEventRecord(e1, p->stream));
   if (opts->history && opts->history_len > 0 && iters > 0) {
