@@ -136,6 +136,21 @@ mh3d_status mh3d_power_iteration(mh3d_plan_t plan, int32_t iters, uint64_t seed,
 mh3d_status mh3d_solve(mh3d_plan_t plan, const float* d, float* rho_inout,
                        const mh3d_solve_opts* opts, mh3d_solve_info* info);
 
+/* Batched solves of many volumes (each with its own plan: uneven grids and harmonic
+ * counts allowed; analytic-PSF plans only; all on the first plan's stream).  Every
+ * update of every volume runs as one launch per pass over a task table of
+ * (volume, block) pairs, a chunk of updates is captured once as a hipGraph and
+ * replayed, and each volume stops at its own r_k <= rel_tol (its blocks exit at
+ * once afterwards).  Results equal mh3d_solve on each plan with the same options.
+ * A plan may belong to one batch at a time and must not be used concurrently. */
+typedef struct mh3d_batch_s* mh3d_batch_t;
+mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh3d_batch_t* out);
+void mh3d_batch_destroy(mh3d_batch_t batch);
+/* d[v], rho_inout[v]: DEVICE arrays of volume v; infos: HOST array of n (may be NULL).
+ * opts applies to every volume (tau <= 0: a power iteration per volume). */
+mh3d_status mh3d_solve_batch(mh3d_batch_t batch, const float* const* d, float* const* rho_inout,
+                             const mh3d_solve_opts* opts, mh3d_solve_info* infos);
+
 /* Copies internal plan data to a caller DEVICE buffer, for tests and tools.
  *   MH3D_FIELD_PROFILE   FP64 [n_harm][nx]      drive-axis profiles L^(k)(a x), raw
  *   MH3D_FIELD_ENVELOPE  FP64 [ny][nz]          transverse envelope E, raw

@@ -141,6 +141,45 @@ struct DevState {
   double nonfinite;
 };
 
+// Everything a pass needs about one volume, in device memory.  The solver's
+// iterates rotate by the parity of the device-side iteration counter st->k, so a
+// recorded sequence of launches stays valid on replay.
+struct VolDesc {
+  Geo g;
+  const void* hs;          // spectra in the class layout (scaled by 1/N)
+  uint32_t imag_mask;      // compact spectra: bit k set -> harmonic k is imaginary
+  int compact;
+  const float* b;          // sensitivity
+  float2* uperm;           // class-layout yz spectra (forward) / adjoint spectra
+  float2* G;               // decimated spectra (forward)
+  float2* Gp;              // decimated spectra (adjoint)
+  float* rho[2];           // FISTA iterates rho^k in rho[k & 1]
+  float* y[2];             // FISTA extrapolated points y^k in y[k & 1]
+  const float* d;          // FISTA data
+  const float2* tw;        // FP32 twiddle tables, offsets off[] for nx, ny, nz, mx, my, mz
+  int off[6];
+  DevState* st;
+  double* partials;        // per-block FP64 partial sums of the x-plane passes
+  double* hist;            // FISTA r_k history, index k - k_first
+  int hist_len, k_first;
+  int reg_kind;
+  float lam;
+  int T_class;             // threads of the class passes doing element work
+};
+
+// Volume and local block index of this block: task table (batched launches) or
+// the single volume vds[0].
+__device__ __forceinline__ const VolDesc& vol_of(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                 int& lb) {
+  if (tasks) {
+    const int2 t = tasks[blockIdx.x];
+    lb = t.y;
+    return vds[t.x];
+  }
+  lb = blockIdx.x;
+  return vds[0];
+}
+
 // ============================================================================ pass 1: x-plane R2C
 enum { SRC_PLAIN = 0, SRC_RAW = 1, SRC_FISTA_Y = 2, SRC_SCALED = 3 };
 
@@ -220,18 +259,21 @@ __device__ __forceinline__ RowCols plane_rowcols(const Geo& g) {
   return rc;
 }
 
-// Forward pass 1.  grid = nx blocks (block -> plane).
+// Forward pass 1.  One block per x-plane.  SRC_FISTA_Y reads y^k of the volume
+// (a ignored) and is skipped once the volume's solve is done.
 // LDS: tables (nz + ny) + two buffers of plane_lds complex.
 template <int SRC>
-__global__ __launch_bounds__(1024) void k_plane_fwd(Geo g, const float* __restrict__ a,
-                                                    const float* __restrict__ a2,
-                                                    const float* __restrict__ b, float coef,
-                                                    const DevState* __restrict__ st,
-                                                    float2* __restrict__ uperm,
-                                                    const float2* __restrict__ tw_y,
-                                                    const float2* __restrict__ tw_z) {
+__global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    const float* __restrict__ a) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  const Geo& g = vd.g;
   if constexpr (SRC == SRC_FISTA_Y || SRC == SRC_SCALED) {
-    if (st->done) return;
+    if (vd.st->done) return;
+  }
+  if constexpr (SRC == SRC_FISTA_Y) a = vd.y[vd.st->k & 1];
+  if constexpr (SRC == SRC_SCALED) {
+    if (!a) a = vd.rho[vd.st->k & 1];
   }
   extern __shared__ float2 lds[];
   const int pl = plane_lds(g);
@@ -239,16 +281,17 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(Geo g, const float* __restri
   float2* twy = twz + g.nz;
   float2* P0 = twy + g.ny;
   float2* P1 = P0 + pl;
-  const int x = plane_of_block(blockIdx.x, g.nx);
-  load_table(twz, tw_z, g.nz);
-  load_table(twy, tw_y, g.ny);
-  float c = coef;
-  if constexpr (SRC == SRC_SCALED) c = (float)st->scale;
+  const int x = plane_of_block(lb, g.nx);
+  load_table(twz, vd.tw + vd.off[2], g.nz);
+  load_table(twy, vd.tw + vd.off[1], g.ny);
+  float c = 1.f;
+  if constexpr (SRC == SRC_SCALED) c = (float)vd.st->scale;
+  const float* __restrict__ b = vd.b;
   const long long pbase = (long long)x * g.ny * g.nz;
   const int nyz = g.ny * g.nz;
   const int lsz = pad_odd(g.nz);
   float* Zf = reinterpret_cast<float*>(P0);
-  batched<8, float>(nyz, [&](int p) { return plane_source<SRC>(pbase + p, a, a2, b, c); },
+  batched<8, float>(nyz, [&](int p) { return plane_source<SRC>(pbase + p, a, nullptr, b, c); },
                     [&](int p, float v) {
                       const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
                       Zf[2 * ((y >> 1) * lsz + z) + (y & 1)] = v;
@@ -259,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(Geo g, const float* __restri
   const RowCols rc = plane_rowcols(g);
   float2* X = r2c_rows(P0, P1, twz, g.ny, g.nz, g.nzh, g.npairs, rc, g.f_nzh);   // X[qz][lsy]
   float2* Y = fft_lines<-1>(X, X == P0 ? P1 : P0, twy, g.ny, g.nzh, g.lsy);
-  float2* dst = uperm + (long long)x * g.plane;
+  float2* dst = vd.uperm + (long long)x * g.plane;
   for (int e = threadIdx.x; e < g.plane; e += blockDim.x) {
     const int cc = (int)g.f_nmem.div((uint32_t)e), m = e - cc * g.nmem;
     const int cy = (int)g.f_mzh.div((uint32_t)cc), cz = cc - cy * g.mzh;
@@ -347,15 +390,11 @@ __device__ __forceinline__ void class_g_index(const Geo& g, int p, int c0, int& 
   go = (((long long)k * nxb + xbi) * g.ncls + c0 + c) * g.xb + xi;
 }
 
-// Forward pass 2.  grid = ncls/cpw blocks of cpw*mx*S/E threads.
+// Forward pass 2 of one block (cpw classes).  Threads beyond vd.T_class only take
+// part in the barriers and shuffles (batched launches use the largest block size).
 template <int HC, int E>
-__global__ __launch_bounds__(1024) void k_class_fwd(Geo g, const float2* __restrict__ uperm,
-                                                    const void* __restrict__ hs, uint32_t imag_mask,
-                                                    const DevState* __restrict__ st,
-                                                    float2* __restrict__ G,
-                                                    const float2* __restrict__ tw_x,
-                                                    const float2* __restrict__ tw_mx) {
-  if (st && st->done) return;
+__device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
+  const Geo& g = vd.g;
   extern __shared__ float2 lds[];
   const int W = g.cpw * g.nmem;
   float2* twx = lds;
@@ -364,22 +403,25 @@ __global__ __launch_bounds__(1024) void k_class_fwd(Geo g, const float2* __restr
   float2* U1 = U0 + W * g.lsx;
   float2* F0 = U1 + W * g.lsx;
   float2* F1 = F0 + g.K * g.cpw * g.mx;
-  const int c0 = blockIdx.x * g.cpw;
+  const int c0 = lb * g.cpw;
+  const bool act = (int)threadIdx.x < vd.T_class;
   // this thread's E spectrum elements: all share class cl and folded frequency qxp
-  const int e0 = threadIdx.x * E;
+  const int e0 = act ? (int)threadIdx.x * E : 0;
   const int per_cls = g.mx * g.S;
   const int cl = (int)g.f_mxS.div((uint32_t)e0);
   const int rem = e0 - cl * per_cls;
   const int qxp = (int)g.f_S.div((uint32_t)rem);
   const int within = rem - qxp * g.S;
   const long long hoff0 = (long long)c0 * per_cls + e0;
+  const void* hs = vd.hs;
   // spectra do not depend on the data: start streaming them first
   HLoad<HC, E> hb[HPF];
 #pragma unroll
   for (int i = 0; i < HPF; ++i)
-    if (i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
-  load_table(twx, tw_x, g.nx);
-  load_table(twm, tw_mx, g.mx);
+    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  load_table(twx, vd.tw + vd.off[0], g.nx);
+  load_table(twm, vd.tw + vd.off[3], g.mx);
+  const float2* __restrict__ uperm = vd.uperm;
   batched<8, float2>(g.nx * W,
                      [&](int p) {
                        const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
@@ -395,33 +437,37 @@ __global__ __launch_bounds__(1024) void k_class_fwd(Geo g, const float2* __restr
   for (int i = 0; i < E; ++i) {
     const int w = within + i;
     const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
-    ur[i] = U[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx];
+    ur[i] = act ? U[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] : make_float2(0.f, 0.f);
   }
   const int LG = g.S / E;
+  const uint32_t imag_mask = vd.imag_mask;
   for (int k0 = 0; k0 < g.K; k0 += HPF) {
 #pragma unroll
     for (int i = 0; i < HPF; ++i) {
       const int k = k0 + i;
       if (k < g.K) {
         float2 acc = make_float2(0.f, 0.f);
-        if constexpr (HC == 0) {
+        if (act) {
+          if constexpr (HC == 0) {
 #pragma unroll
-          for (int t = 0; t < E; ++t) { acc.x += hb[i].v[t] * ur[t].x; acc.y += hb[i].v[t] * ur[t].y; }
-          if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
-        } else {
+            for (int t = 0; t < E; ++t) { acc.x += hb[i].v[t] * ur[t].x; acc.y += hb[i].v[t] * ur[t].y; }
+            if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
+          } else {
 #pragma unroll
-          for (int t = 0; t < E; ++t) acc = cadd(acc, cmul(hb[i].v[t], ur[t]));
+            for (int t = 0; t < E; ++t) acc = cadd(acc, cmul(hb[i].v[t], ur[t]));
+          }
+          if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
         }
-        if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
         for (int o = LG >> 1; o >= 1; o >>= 1) {
           acc.x += __shfl_xor(acc.x, o, 64);
           acc.y += __shfl_xor(acc.y, o, 64);
         }
-        if ((threadIdx.x & (LG - 1)) == 0) F0[(k * g.cpw + cl) * g.mx + qxp] = acc;
+        if (act && (threadIdx.x & (LG - 1)) == 0) F0[(k * g.cpw + cl) * g.mx + qxp] = acc;
       }
     }
   }
   const float2* F = fft_lines<+1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
+  float2* __restrict__ G = vd.G;
   for (int p = threadIdx.x; p < g.K * g.cpw * g.mx; p += blockDim.x) {
     int fo;
     long long go;
@@ -430,15 +476,10 @@ __global__ __launch_bounds__(1024) void k_class_fwd(Geo g, const float2* __restr
   }
 }
 
-// Adjoint pass 2.  Same grid and LDS as k_class_fwd.
+// Adjoint pass 2 of one block.
 template <int HC, int E>
-__global__ __launch_bounds__(1024) void k_class_adj(Geo g, const float2* __restrict__ Gp,
-                                                    const void* __restrict__ hs, uint32_t imag_mask,
-                                                    const DevState* __restrict__ st,
-                                                    float2* __restrict__ vperm,
-                                                    const float2* __restrict__ tw_x,
-                                                    const float2* __restrict__ tw_mx) {
-  if (st && st->done) return;
+__device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
+  const Geo& g = vd.g;
   extern __shared__ float2 lds[];
   const int W = g.cpw * g.nmem;
   float2* twx = lds;
@@ -447,20 +488,23 @@ __global__ __launch_bounds__(1024) void k_class_adj(Geo g, const float2* __restr
   float2* U1 = U0 + W * g.lsx;
   float2* F0 = U1 + W * g.lsx;
   float2* F1 = F0 + g.K * g.cpw * g.mx;
-  const int c0 = blockIdx.x * g.cpw;
-  const int e0 = threadIdx.x * E;
+  const int c0 = lb * g.cpw;
+  const bool act = (int)threadIdx.x < vd.T_class;
+  const int e0 = act ? (int)threadIdx.x * E : 0;
   const int per_cls = g.mx * g.S;
   const int cl = (int)g.f_mxS.div((uint32_t)e0);
   const int rem = e0 - cl * per_cls;
   const int qxp = (int)g.f_S.div((uint32_t)rem);
   const int within = rem - qxp * g.S;
   const long long hoff0 = (long long)c0 * per_cls + e0;
+  const void* hs = vd.hs;
   HLoad<HC, E> hb[HPF];
 #pragma unroll
   for (int i = 0; i < HPF; ++i)
-    if (i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
-  load_table(twx, tw_x, g.nx);
-  load_table(twm, tw_mx, g.mx);
+    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  load_table(twx, vd.tw + vd.off[0], g.nx);
+  load_table(twm, vd.tw + vd.off[3], g.mx);
+  const float2* __restrict__ Gp = vd.Gp;
   batched<8, float2>(g.K * g.cpw * g.mx,
                      [&](int p) {
                        int fo;
@@ -478,11 +522,12 @@ __global__ __launch_bounds__(1024) void k_class_adj(Geo g, const float2* __restr
   float2 acc[E];
 #pragma unroll
   for (int t = 0; t < E; ++t) acc[t] = make_float2(0.f, 0.f);
+  const uint32_t imag_mask = vd.imag_mask;
   for (int k0 = 0; k0 < g.K; k0 += HPF) {
 #pragma unroll
     for (int i = 0; i < HPF; ++i) {
       const int k = k0 + i;
-      if (k < g.K) {
+      if (act && k < g.K) {
         float2 R = F[(k * g.cpw + cl) * g.mx + qxp];
         if constexpr (HC == 0) {
           // conj(i h) R = -i h R
@@ -498,18 +543,64 @@ __global__ __launch_bounds__(1024) void k_class_adj(Geo g, const float2* __restr
     }
   }
   // every element of the group is written exactly once
+  if (act) {
 #pragma unroll
-  for (int t = 0; t < E; ++t) {
-    const int w = within + t;
-    const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
-    U0[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] = acc[t];
+    for (int t = 0; t < E; ++t) {
+      const int w = within + t;
+      const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
+      U0[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] = acc[t];
+    }
   }
   const float2* V = fft_lines<+1>(U0, U1, twx, g.nx, W, g.lsx);
+  float2* __restrict__ vperm = vd.uperm;
   for (int p = threadIdx.x; p < g.nx * W; p += blockDim.x) {
     const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
     vperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e] = V[e * g.lsx + xx];
   }
 }
+
+// Single-volume class passes, grid = ncls/cpw blocks of T_class threads.
+// check_done skips the launch once the volume's solve is done.
+template <int HC, int E>
+__global__ __launch_bounds__(1024) void k_class_fwd(const VolDesc* __restrict__ vds, int check_done) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, nullptr, lb);
+  if (check_done && vd.st->done) return;
+  class_fwd_body<HC, E>(vd, lb);
+}
+template <int HC, int E>
+__global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ vds, int check_done) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, nullptr, lb);
+  if (check_done && vd.st->done) return;
+  class_adj_body<HC, E>(vd, lb);
+}
+
+// Batched class passes over a task table (compact spectra), the element split E
+// of each volume dispatched per block.  Volumes whose solve is done are skipped.
+#define MH3D_E_SWITCH(BODY)                 \
+  switch (vd.g.E) {                         \
+    case 8: BODY<0, 8>(vd, lb); break;      \
+    case 6: BODY<0, 6>(vd, lb); break;      \
+    case 4: BODY<0, 4>(vd, lb); break;      \
+    case 3: BODY<0, 3>(vd, lb); break;      \
+    case 2: BODY<0, 2>(vd, lb); break;      \
+    case 9: BODY<0, 9>(vd, lb); break;      \
+    default: BODY<0, 1>(vd, lb); break;     \
+  }
+__global__ __launch_bounds__(1024) void k_class_fwd_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  if (vd.st->done) return;
+  MH3D_E_SWITCH(class_fwd_body)
+}
+__global__ __launch_bounds__(1024) void k_class_adj_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  if (vd.st->done) return;
+  MH3D_E_SWITCH(class_adj_body)
+}
+#undef MH3D_E_SWITCH
 
 // ============================================================================ pass 3: small grid
 enum { EPI_STORE = 0, EPI_RESID = 1, EPI_RESID_BACK = 2, EPI_BACK = 3 };
@@ -542,27 +633,29 @@ __device__ void small_r2c_and_store(const Geo& g, float2* a, float2* b, const fl
 }
 
 // Forward pass 3 (and, with EPI_RESID_BACK / EPI_BACK, the first adjoint pass on
-// the result).  grid = K * (mx/xb) blocks.  LDS: tables (my + mz) + 2 * small_lds.
+// the result).  One block per (k, x'-block).  EPI_RESID_BACK uses the volume's data
+// and is skipped once its solve is done.  LDS: tables (my + mz) + 2 * small_lds.
 template <int EPI>
-__global__ __launch_bounds__(1024) void k_small_inv(Geo g, const float2* __restrict__ G,
-                                                    float* __restrict__ d,
-                                                    const float* __restrict__ dmeas,
-                                                    const DevState* __restrict__ st,
-                                                    float2* __restrict__ Gp,
-                                                    const float2* __restrict__ tw_my,
-                                                    const float2* __restrict__ tw_mz) {
-  if (st && st->done) return;
+__global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    float* __restrict__ d) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  const Geo& g = vd.g;
+  if constexpr (EPI == EPI_RESID_BACK || EPI == EPI_BACK) {
+    if (vd.st->done) return;
+  }
+  const float* __restrict__ dmeas = vd.d;
   extern __shared__ float2 lds[];
   const int sl = small_lds(g);
   float2* twy = lds;
   float2* twz = twy + g.my;
   float2* P0 = twz + g.mz;
   float2* P1 = P0 + sl;
-  load_table(twy, tw_my, g.my);
-  load_table(twz, tw_mz, g.mz);
+  load_table(twy, vd.tw + vd.off[4], g.my);
+  load_table(twz, vd.tw + vd.off[5], g.mz);
   const int nxb = g.mx / g.xb;
-  const int k = blockIdx.x / nxb, xbi = blockIdx.x - (blockIdx.x / nxb) * nxb;
-  const float2* src = G + ((long long)k * nxb + xbi) * g.ncls * g.xb;
+  const int k = lb / nxb, xbi = lb - (lb / nxb) * nxb;
+  const float2* src = vd.G + ((long long)k * nxb + xbi) * g.ncls * g.xb;
   batched<8, float2>(g.ncls * g.xb, [&](int p) { return src[p]; },
                      [&](int p, float2 v) {
                        const int c = (int)g.f_xb.div((uint32_t)p), xi = p - c * g.xb;
@@ -595,25 +688,25 @@ __global__ __launch_bounds__(1024) void k_small_inv(Geo g, const float2* __restr
     if (rows & 1) {
       for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * lsmz + z) + 1] = 0.f;
     }
-    small_r2c_and_store(g, Z, Z == P0 ? P1 : P0, twy, twz, Gp, k, xbi);
+    small_r2c_and_store(g, Z, Z == P0 ? P1 : P0, twy, twz, vd.Gp, k, xbi);
   }
 }
 
-// Adjoint pass 3: R2C of the portraits.  grid = K * (mx/xb) blocks.
-__global__ __launch_bounds__(1024) void k_small_fwd(Geo g, const float* __restrict__ r,
-                                                    float2* __restrict__ Gp,
-                                                    const float2* __restrict__ tw_my,
-                                                    const float2* __restrict__ tw_mz) {
+// Adjoint pass 3: R2C of the portraits r.  One block per (k, x'-block).
+__global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ r) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, nullptr, lb);
+  const Geo& g = vd.g;
   extern __shared__ float2 lds[];
   const int sl = small_lds(g);
   float2* twy = lds;
   float2* twz = twy + g.my;
   float2* P0 = twz + g.mz;
   float2* P1 = P0 + sl;
-  load_table(twy, tw_my, g.my);
-  load_table(twz, tw_mz, g.mz);
+  load_table(twy, vd.tw + vd.off[4], g.my);
+  load_table(twz, vd.tw + vd.off[5], g.mz);
   const int nxb = g.mx / g.xb;
-  const int k = blockIdx.x / nxb, xbi = blockIdx.x - (blockIdx.x / nxb) * nxb;
+  const int k = lb / nxb, xbi = lb - (lb / nxb) * nxb;
   const int rows = g.xb * g.my;
   const int lsmz = pad_odd(g.mz);
   const long long ibase = (long long)k * g.M + (long long)xbi * g.xb * g.my * g.mz;
@@ -627,7 +720,7 @@ __global__ __launch_bounds__(1024) void k_small_fwd(Geo g, const float* __restri
   if (rows & 1) {
     for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * lsmz + z) + 1] = 0.f;
   }
-  small_r2c_and_store(g, P0, P1, twy, twz, Gp, k, xbi);
+  small_r2c_and_store(g, P0, P1, twy, twz, vd.Gp, k, xbi);
 }
 
 // ============================================================================ pass 1 adjoint
@@ -635,31 +728,22 @@ enum { OUT_SCALE_B = 0, OUT_NORMAL = 1, OUT_FISTA = 2 };
 
 struct AdjOut {
   float* out;              // OUT_SCALE_B / OUT_NORMAL: result
-  const float* yin;        // OUT_NORMAL: w_{t-1} (v = scale * w_{t-1});  OUT_FISTA: y^k
-  const float* rk;         // OUT_FISTA: rho^k
-  float* rho_next;         // OUT_FISTA: rho^{k+1}
-  float* y_next;           // OUT_FISTA: y^{k+1} = rho^{k+1} + beta_{k+1} (rho^{k+1} - rho^k)
-  double* partials;        // per-block FP64 partial sums
-  DevState* st;
-  int reg_kind;
-  float lam;
-  double* hist64;          // FISTA: history of r_k indexed by (k - k_first)
-  int k_first;
-  int hist_len;
+  const float* yin;        // OUT_NORMAL: w_{t-1} (v = scale * w_{t-1})
 };
 
 // Deterministic grid reduction: every block writes NV partials; the last block to
 // arrive sums them in block order.  Returns true in thread 0 of the last block.
 template <int NV>
-__device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, DevState* st, double* sh) {
+__device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, DevState* st, double* sh,
+                                                 int blk, int nblk) {
   block_reduce_f64<NV>(v, sh);
   __shared__ int is_last;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) partials[blockIdx.x * NV + j] = v[j];
+    for (int j = 0; j < NV; ++j) partials[blk * NV + j] = v[j];
     __threadfence();
     const int prev = atomicAdd(&st->counter, 1);
-    is_last = (prev == (int)gridDim.x - 1);
+    is_last = (prev == nblk - 1);
   }
   __syncthreads();
   if (!is_last) return false;
@@ -669,7 +753,7 @@ __device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, De
     for (int j = 0; j < NV; ++j) {
       double s = 0.0;
       const volatile double* vp = partials;
-      for (int bidx = 0; bidx < (int)gridDim.x; ++bidx) s += vp[bidx * NV + j];
+      for (int bidx = 0; bidx < nblk; ++bidx) s += vp[bidx * NV + j];
       v[j] = s;
     }
     st->counter = 0;
@@ -693,12 +777,14 @@ struct XNb {
 // of stacked second differences (reg_kind 1: T = I).  In-plane neighbours come from
 // the plane staged in LDS, x-neighbours from global memory.  grid = nx blocks.
 template <int OUT>
-__global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restrict__ vperm,
-                                                    const float* __restrict__ b, AdjOut ao,
-                                                    const float2* __restrict__ tw_y,
-                                                    const float2* __restrict__ tw_z) {
+__global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    AdjOut ao) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  const Geo& g = vd.g;
+  DevState* st = vd.st;
   if constexpr (OUT != OUT_SCALE_B) {
-    if (ao.st->done) return;
+    if (st->done) return;
   }
   extern __shared__ float2 lds[];
   const int pl = plane_lds(g);
@@ -707,10 +793,10 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
   float2* P0 = twy + g.ny;
   float2* P1 = P0 + pl;
   __shared__ double red[64];
-  load_table(twz, tw_z, g.nz);
-  load_table(twy, tw_y, g.ny);
-  const int x = plane_of_block(blockIdx.x, g.nx);
-  const float2* src = vperm + (long long)x * g.plane;
+  load_table(twz, vd.tw + vd.off[2], g.nz);
+  load_table(twy, vd.tw + vd.off[1], g.ny);
+  const int x = plane_of_block(lb, g.nx);
+  const float2* src = vd.uperm + (long long)x * g.plane;
   batched<8, float2>(g.plane, [&](int e) { return src[e]; }, [&](int e, float2 v) { P1[e] = v; });
   __syncthreads();
   for (int p = threadIdx.x; p < g.ny * g.nzh; p += blockDim.x) {
@@ -728,6 +814,7 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
     const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
     return 2 * ((y >> 1) * lsz + z) + (y & 1);
   };
+  const float* __restrict__ b = vd.b;
   const long long pbase = (long long)x * g.ny * g.nz;
   const int nyz = g.ny * g.nz;
   if constexpr (OUT == OUT_SCALE_B) {
@@ -735,10 +822,15 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
                       [&](int p, float bv) { ao.out[pbase + p] = bv * Xf[vidx(p)]; });
     return;
   } else {
-    // stage the regularised vector of this plane in the free LDS buffer
+    const int kk = st->k;
+    // the vector the regulariser acts on: s w_{t-1} (power iteration; w_{t-1} in
+    // rho[k & 1] when no buffers are given) or y^k
+    const float* yv = (OUT == OUT_NORMAL) ? (ao.yin ? ao.yin : vd.rho[kk & 1]) : vd.y[kk & 1];
+    float* out = (OUT == OUT_NORMAL) ? (ao.out ? ao.out : vd.rho[(kk + 1) & 1]) : nullptr;
+    const float* rk = vd.rho[kk & 1];
+    // stage that vector's plane in the free LDS buffer
     float* Yl = reinterpret_cast<float*>(Z == P0 ? P1 : P0);
-    const float s = (OUT == OUT_NORMAL) ? (float)ao.st->scale : 1.f;
-    const float* yv = ao.yin;
+    const float s = (OUT == OUT_NORMAL) ? (float)st->scale : 1.f;
     batched<8, float>(nyz, [&](int p) { return yv[pbase + p]; }, [&](int p, float v) { Yl[p] = s * v; });
     __syncthreads();
     const long long plane_sz = (long long)g.ny * g.nz;
@@ -746,7 +838,8 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
     const long long xm1 = (long long)((x - 1 + g.nx) % g.nx) * plane_sz;
     const long long xp1 = (long long)((x + 1) % g.nx) * plane_sz;
     const long long xp2 = (long long)((x + 2) % g.nx) * plane_sz;
-    const bool stencil = ao.reg_kind == 0;
+    const bool stencil = vd.reg_kind == 0;
+    const float lam = vd.lam;
     auto ld = [&](int p) {
       XNb v;
       v.b = b[pbase + p];
@@ -755,7 +848,7 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
       } else {
         v.xm2 = v.xm1 = v.xp1 = v.xp2 = 0.f;
       }
-      if constexpr (OUT == OUT_FISTA) v.rk = ao.rk[pbase + p];
+      if constexpr (OUT == OUT_FISTA) v.rk = rk[pbase + p];
       else v.rk = 0.f;
       return v;
     };
@@ -763,10 +856,11 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
       const float c = Yl[p];
       if (!stencil) return c;
       const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
-      const int ym2 = (y - 2 + 2 * g.ny) % g.ny, ym1 = (y - 1 + g.ny) % g.ny;
-      const int yp1 = (y + 1) % g.ny, yp2 = (y + 2) % g.ny;
-      const int zm2 = (z - 2 + 2 * g.nz) % g.nz, zm1 = (z - 1 + g.nz) % g.nz;
-      const int zp1 = (z + 1) % g.nz, zp2 = (z + 2) % g.nz;
+      // periodic neighbours (grid axes are >= 4 long, so one wrap suffices)
+      const int ym1 = y >= 1 ? y - 1 : y - 1 + g.ny, ym2 = y >= 2 ? y - 2 : y - 2 + g.ny;
+      const int yp1 = y + 1 < g.ny ? y + 1 : y + 1 - g.ny, yp2 = y + 2 < g.ny ? y + 2 : y + 2 - g.ny;
+      const int zm1 = z >= 1 ? z - 1 : z - 1 + g.nz, zm2 = z >= 2 ? z - 2 : z - 2 + g.nz;
+      const int zp1 = z + 1 < g.nz ? z + 1 : z + 1 - g.nz, zp2 = z + 2 < g.nz ? z + 2 : z + 2 - g.nz;
       float t = 18.f * c;
       t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
       t += Yl[yp2 * g.nz + z] + Yl[ym2 * g.nz + z] - 4.f * (Yl[yp1 * g.nz + z] + Yl[ym1 * g.nz + z]);
@@ -776,42 +870,43 @@ __global__ __launch_bounds__(1024) void k_plane_adj(Geo g, const float2* __restr
     if constexpr (OUT == OUT_NORMAL) {
       double acc[2] = {0.0, 0.0};
       batched<4, XNb>(nyz, ld, [&](int p, const XNb& v) {
-        const float o = v.b * Xf[vidx(p)] + ao.lam * reg(p, v);
-        ao.out[pbase + p] = o;
+        const float o = v.b * Xf[vidx(p)] + lam * reg(p, v);
+        out[pbase + p] = o;
         acc[0] += (double)Yl[p] * (double)o;
         acc[1] += (double)o * (double)o;
       });
-      if (grid_reduce_last<2>(acc, ao.partials, ao.st, red)) {
-        DevState* st = ao.st;
+      if (grid_reduce_last<2>(acc, vd.partials, st, red, lb, g.nx)) {
         st->lmax = acc[0];
         st->scale = 1.0 / sqrt(acc[1]);
         if (!(acc[0] == acc[0]) || !(acc[1] < 1e300)) st->nonfinite = 1.0;
+        st->k = kk + 1;
+        if (kk >= st->kmax) st->done = 1;
       }
     } else {
-      DevState* st = ao.st;
-      const int kk = st->k;
       const float tau = (float)st->tau;
       const float beta1 = (float)((double)kk / (kk + 3.0));      // (k+1-1)/(k+1+2)
+      float* rho_next = vd.rho[(kk + 1) & 1];
+      float* y_next = vd.y[(kk + 1) & 1];
       double acc[3] = {0.0, 0.0, 0.0};
       batched<4, XNb>(nyz, ld, [&](int p, const XNb& v) {
         const float yk = Yl[p];
-        const float gr = v.b * Xf[vidx(p)] + ao.lam * reg(p, v);
+        const float gr = v.b * Xf[vidx(p)] + lam * reg(p, v);
         const float rn = fmaxf(yk - tau * gr, 0.f);
-        ao.rho_next[pbase + p] = rn;
-        ao.y_next[pbase + p] = rn + beta1 * (rn - v.rk);
+        rho_next[pbase + p] = rn;
+        y_next[pbase + p] = rn + beta1 * (rn - v.rk);
         const double dd = (double)rn - (double)yk;
         acc[0] += dd * dd;
         acc[1] += (double)rn * (double)rn;
         if (!isfinite(gr) || !isfinite(yk)) acc[2] += 1.0;   // max(NaN, 0) would hide it
       });
-      if (grid_reduce_last<3>(acc, ao.partials, ao.st, red)) {
+      if (grid_reduce_last<3>(acc, vd.partials, st, red, lb, g.nx)) {
         double r;
         if (acc[1] == 0.0) r = (acc[0] == 0.0) ? 0.0 : __builtin_inf();
         else r = sqrt(acc[0]) / sqrt(acc[1]);
         st->rel_step = r;
         st->last_k = kk;
-        const int hi = kk - ao.k_first;
-        if (ao.hist64 && hi >= 0 && hi < ao.hist_len) ao.hist64[hi] = r;
+        const int hi = kk - vd.k_first;
+        if (vd.hist && hi >= 0 && hi < vd.hist_len) vd.hist[hi] = r;
         if (acc[2] != 0.0 || !(acc[0] == acc[0]) || !(acc[1] == acc[1]) || acc[1] > 1e300) {
           st->nonfinite = 1.0;
           st->done = 1;
@@ -1070,7 +1165,7 @@ __global__ void k_philox_uniform(long long n, uint64_t seed, uint32_t stream, fl
       }
     }
   }
-  if (grid_reduce_last<1>(acc, partials, st, red)) st->scale = 1.0 / sqrt(acc[0]);
+  if (grid_reduce_last<1>(acc, partials, st, red, blockIdx.x, gridDim.x)) st->scale = 1.0 / sqrt(acc[0]);
 }
 
 // Raw Philox words for the known-answer test.

@@ -184,7 +184,9 @@ struct mh3d_plan_s {
   std::vector<int> harm;
   Geo g;
   Launch L;
-  hipStream_t stream;
+  hipStream_t stream;          // caller's stream: every operation is ordered on it
+  hipStream_t ls;              // stream kernels are enqueued on (cap_stream while capturing)
+  hipStream_t cap_stream = nullptr;   // side stream used only to record graphs
   int compact;
   uint32_t imag_mask;
   // device memory
@@ -193,16 +195,24 @@ struct mh3d_plan_s {
   float2* uperm = nullptr;     // class-layout yz spectra of one volume (also adjoint V)
   float2* G = nullptr;         // decimated spectra (forward)
   float2* Gp = nullptr;        // decimated spectra (adjoint)
-  float* vol[4] = {nullptr, nullptr, nullptr, nullptr};  // rho^k, rho^{k+1}, y^k, y^{k+1} / power vectors
-  float* port = nullptr;       // portrait scratch
+  float* vol[4] = {nullptr, nullptr, nullptr, nullptr};  // rho[0], rho[1], y[0], y[1]
   float2* tw32 = nullptr;
   double2* tw64 = nullptr;
   int off[6];                  // table offsets for nx, ny, nz, mx, my, mz
   double* prof = nullptr;      // [K][nx]
   double* env = nullptr;       // [ny][nz]
   double* partials = nullptr;
+  double* hist = nullptr;      // solver history (device), capacity hist_cap
+  int hist_cap = 0;
   DevState* st = nullptr;      // solver / power state
+  VolDesc vdh;                 // host copy of the descriptor
+  VolDesc* vdd = nullptr;      // device descriptor
   size_t bytes = 0;
+  // captured solver chunk
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_chunk = 0;
+  bool capturing = false;
   // profiling
   bool prof_on = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -227,7 +237,6 @@ static size_t plan_bytes(const Geo& g, bool compact) {
   s += (size_t)g.nx * g.plane * 8;                    // uperm
   s += 2 * (size_t)g.K * g.mx * g.ncls * 8;           // G, Gp
   s += 4 * (size_t)g.N * 4;                           // vol
-  s += (size_t)g.K * g.M * 4;                         // port
   s += (size_t)(2 * (g.nx + g.ny + g.nz) + g.mx + g.my + g.mz) * 24;
   s += ((size_t)g.K * g.nx + (size_t)g.ny * g.nz) * 8;
   return s;
@@ -246,37 +255,39 @@ extern "C" mh3d_status mh3d_plan_describe(const mh3d_plan_desc* desc, size_t* de
 }
 
 // ---------------------------------------------------------------------------- profiling helpers
+static void drain_events(mh3d_plan_t p) {
+  for (auto& e : p->pending) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(e.second.second);
+    (void)hipEventElapsedTime(&ms, e.second.first, e.second.second);
+    p->ms[e.first] += ms;
+    p->launches[e.first] += 1;
+    p->free_events.push_back(e.second.first);
+    p->free_events.push_back(e.second.second);
+  }
+  p->pending.clear();
+}
+
 struct Timer {
   mh3d_plan_t p;
   int kid;
   hipEvent_t a = nullptr, b = nullptr;
   Timer(mh3d_plan_t p_, int kid_) : p(p_), kid(kid_) {
-    if (!p->prof_on) return;
+    if (!p->prof_on || p->capturing) return;
     if (p->free_events.size() >= 2) {
       a = p->free_events.back(); p->free_events.pop_back();
       b = p->free_events.back(); p->free_events.pop_back();
     } else {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
     }
-    hipEventRecord(a, p->stream);
+    (void)hipEventRecord(a, p->ls);
   }
   ~Timer() {
     if (!a) return;
-    hipEventRecord(b, p->stream);
+    (void)hipEventRecord(b, p->ls);
     p->pending.push_back({kid, {a, b}});
-    if (p->pending.size() > 4096) {
-      for (auto& e : p->pending) {
-        float ms = 0.f;
-        hipEventSynchronize(e.second.second);
-        hipEventElapsedTime(&ms, e.second.first, e.second.second);
-        p->ms[e.first] += ms;
-        p->launches[e.first] += 1;
-        p->free_events.push_back(e.second.first);
-        p->free_events.push_back(e.second.second);
-      }
-      p->pending.clear();
-    }
+    if (p->pending.size() > 4096) drain_events(p);
   }
 };
 
@@ -286,112 +297,105 @@ static mh3d_status last_launch(const char* what) {
   return MH3D_OK;
 }
 
-// ---------------------------------------------------------------------------- dispatchers
-static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a, const float* a2, float coef, DevState* st) {
-  const Geo& g = p->g;
-  Timer t(p, KID_PLANE_FWD);
-  dim3 grid(g.nx), block(p->L.T_plane);
-  const size_t lds = p->L.lds_plane;
-  const float2* twy = p->tw32 + p->off[1];
-  const float2* twz = p->tw32 + p->off[2];
-  switch (src) {
-    case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
-    case SRC_RAW: k_plane_fwd<SRC_RAW><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
-    case SRC_FISTA_Y: k_plane_fwd<SRC_FISTA_Y><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
-    default: k_plane_fwd<SRC_SCALED><<<grid, block, lds, p->stream>>>(g, a, a2, p->b, coef, st, p->uperm, twy, twz); break;
-  }
-  return last_launch("k_plane_fwd");
-}
-
-template <int HC, int E>
-static void class_fwd_t(mh3d_plan_t p, DevState* st) {
-  const Geo& g = p->g;
-  k_class_fwd<HC, E><<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->stream>>>(
-      g, p->uperm, p->hs, p->imag_mask, st, p->G, p->tw32 + p->off[0], p->tw32 + p->off[3]);
-}
-template <int HC, int E>
-static void class_adj_t(mh3d_plan_t p, DevState* st) {
-  const Geo& g = p->g;
-  k_class_adj<HC, E><<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->stream>>>(
-      g, p->Gp, p->hs, p->imag_mask, st, p->uperm, p->tw32 + p->off[0], p->tw32 + p->off[3]);
-}
-
-#define E_DISPATCH(HCV, FN)                       \
-  switch (p->g.E) {                               \
-    case 9: FN<HCV, 9>(p, st); break;             \
-    case 8: FN<HCV, 8>(p, st); break;             \
-    case 6: FN<HCV, 6>(p, st); break;             \
-    case 4: FN<HCV, 4>(p, st); break;             \
-    case 3: FN<HCV, 3>(p, st); break;             \
-    case 2: FN<HCV, 2>(p, st); break;             \
-    default: FN<HCV, 1>(p, st); break;            \
-  }
-
-static mh3d_status launch_class_fwd(mh3d_plan_t p, DevState* st) {
-  Timer t(p, KID_CLASS_FWD);
-  if (p->compact) { E_DISPATCH(0, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
-  return last_launch("k_class_fwd");
-}
-static mh3d_status launch_class_adj(mh3d_plan_t p, DevState* st) {
-  Timer t(p, KID_CLASS_ADJ);
-  if (p->compact) { E_DISPATCH(0, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
-  return last_launch("k_class_adj");
-}
-
-static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d, const float* dmeas, DevState* st) {
-  const Geo& g = p->g;
-  Timer t(p, KID_SMALL_INV);
-  dim3 grid(g.K * (g.mx / g.xb)), block(p->L.T_small);
-  const size_t lds = p->L.lds_small;
-  const float2* twy = p->tw32 + p->off[4];
-  const float2* twz = p->tw32 + p->off[5];
-  switch (epi) {
-    case EPI_STORE: k_small_inv<EPI_STORE><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
-    case EPI_RESID: k_small_inv<EPI_RESID><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
-    case EPI_RESID_BACK: k_small_inv<EPI_RESID_BACK><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
-    default: k_small_inv<EPI_BACK><<<grid, block, lds, p->stream>>>(g, p->G, d, dmeas, st, p->Gp, twy, twz); break;
-  }
-  return last_launch("k_small_inv");
-}
-
-static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r) {
-  const Geo& g = p->g;
-  Timer t(p, KID_SMALL_FWD);
-  k_small_fwd<<<dim3(g.K * (g.mx / g.xb)), dim3(p->L.T_small), p->L.lds_small, p->stream>>>(
-      g, r, p->Gp, p->tw32 + p->off[4], p->tw32 + p->off[5]);
-  return last_launch("k_small_fwd");
-}
-
-static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, const AdjOut& ao) {
-  const Geo& g = p->g;
-  Timer t(p, KID_PLANE_ADJ);
-  dim3 grid(g.nx), block(p->L.T_plane);
-  const size_t lds = p->L.lds_plane;
-  const float2* twy = p->tw32 + p->off[1];
-  const float2* twz = p->tw32 + p->off[2];
-  switch (out) {
-    case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->stream>>>(g, p->uperm, p->b, ao, twy, twz); break;
-    case OUT_NORMAL: k_plane_adj<OUT_NORMAL><<<grid, block, lds, p->stream>>>(g, p->uperm, p->b, ao, twy, twz); break;
-    default: k_plane_adj<OUT_FISTA><<<grid, block, lds, p->stream>>>(g, p->uperm, p->b, ao, twy, twz); break;
-  }
-  return last_launch("k_plane_adj");
-}
-
 #define CHK(x)                          \
   do {                                  \
     mh3d_status s_ = (x);               \
     if (s_ != MH3D_OK) return s_;       \
   } while (0)
 
-// ---------------------------------------------------------------------------- state init
+// ---------------------------------------------------------------------------- single-volume launchers
+static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
+  Timer t(p, KID_PLANE_FWD);
+  dim3 grid(p->g.nx), block(p->L.T_plane);
+  const size_t lds = p->L.lds_plane;
+  switch (src) {
+    case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
+    case SRC_RAW: k_plane_fwd<SRC_RAW><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
+    case SRC_FISTA_Y: k_plane_fwd<SRC_FISTA_Y><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
+    default: k_plane_fwd<SRC_SCALED><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
+  }
+  return last_launch("k_plane_fwd");
+}
+
+template <int HC, int E>
+static void class_fwd_t(mh3d_plan_t p, int chk) {
+  k_class_fwd<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vdd, chk);
+}
+template <int HC, int E>
+static void class_adj_t(mh3d_plan_t p, int chk) {
+  k_class_adj<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vdd, chk);
+}
+
+#define E_DISPATCH(HCV, FN)                       \
+  switch (p->g.E) {                               \
+    case 9: FN<HCV, 9>(p, chk); break;            \
+    case 8: FN<HCV, 8>(p, chk); break;            \
+    case 6: FN<HCV, 6>(p, chk); break;            \
+    case 4: FN<HCV, 4>(p, chk); break;            \
+    case 3: FN<HCV, 3>(p, chk); break;            \
+    case 2: FN<HCV, 2>(p, chk); break;            \
+    default: FN<HCV, 1>(p, chk); break;           \
+  }
+
+static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk) {
+  Timer t(p, KID_CLASS_FWD);
+  if (p->compact) { E_DISPATCH(0, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
+  return last_launch("k_class_fwd");
+}
+static mh3d_status launch_class_adj(mh3d_plan_t p, int chk) {
+  Timer t(p, KID_CLASS_ADJ);
+  if (p->compact) { E_DISPATCH(0, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
+  return last_launch("k_class_adj");
+}
+
+static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d) {
+  Timer t(p, KID_SMALL_INV);
+  dim3 grid(p->g.K * (p->g.mx / p->g.xb)), block(p->L.T_small);
+  const size_t lds = p->L.lds_small;
+  switch (epi) {
+    case EPI_STORE: k_small_inv<EPI_STORE><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
+    case EPI_RESID_BACK: k_small_inv<EPI_RESID_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
+    default: k_small_inv<EPI_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
+  }
+  return last_launch("k_small_inv");
+}
+
+static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r) {
+  Timer t(p, KID_SMALL_FWD);
+  k_small_fwd<<<dim3(p->g.K * (p->g.mx / p->g.xb)), dim3(p->L.T_small), p->L.lds_small, p->ls>>>(p->vdd, r);
+  return last_launch("k_small_fwd");
+}
+
+static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const float* yin) {
+  Timer t(p, KID_PLANE_ADJ);
+  dim3 grid(p->g.nx), block(p->L.T_plane);
+  const size_t lds = p->L.lds_plane;
+  AdjOut ao;
+  ao.out = o;
+  ao.yin = yin;
+  switch (out) {
+    case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, ao); break;
+    case OUT_NORMAL: k_plane_adj<OUT_NORMAL><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, ao); break;
+    default: k_plane_adj<OUT_FISTA><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, ao); break;
+  }
+  return last_launch("k_plane_adj");
+}
+
+// ---------------------------------------------------------------------------- state
 __global__ void k_state_set(DevState* st, DevState v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *st = v;
 }
 
 static mh3d_status state_set(mh3d_plan_t p, const DevState& v) {
   Timer t(p, KID_AUX);
-  hipLaunchKernelGGL(k_state_set, dim3(1), dim3(64), 0, p->stream, p->st, v);
+  hipLaunchKernelGGL(k_state_set, dim3(1), dim3(64), 0, p->ls, p->st, v);
   return last_launch("k_state_set");
+}
+
+static mh3d_status upload_desc(mh3d_plan_t p) {
+  HIPCHK(hipMemcpyAsync(p->vdd, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return MH3D_OK;
 }
 
 // ---------------------------------------------------------------------------- plan build
@@ -445,7 +449,8 @@ static mh3d_status build_spectra_analytic(mh3d_plan_t p) {
   hipLaunchKernelGGL(k_psf_assemble, dim3(2048), dim3(256), 0, p->stream, g, fhat, ehat, scale, p->imag_mask, 1, p->hs);
   CHK(last_launch("k_psf_assemble"));
   HIPCHK(hipStreamSynchronize(p->stream));
-  hipFree(d_order); hipFree(fhat); hipFree(tmp); hipFree(ehat); hipFree(fn2); hipFree(rows); hipFree(scale);
+  (void)hipFree(d_order); (void)hipFree(fhat); (void)hipFree(tmp); (void)hipFree(ehat);
+  (void)hipFree(fn2); (void)hipFree(rows); (void)hipFree(scale);
   p->bytes = keep;
   return MH3D_OK;
 }
@@ -455,8 +460,8 @@ static mh3d_status build_spectra_user(mh3d_plan_t p) {
   p->imag_mask = 0;
   size_t lds = sizeof(float2) * ((size_t)g.nx + 2 * (size_t)g.lsx * g.cpw * g.nmem);
   for (int k = 0; k < g.K; ++k) {
-    CHK(launch_plane_fwd(p, SRC_RAW, p->desc.psf + (long long)k * g.N, nullptr, 1.f, nullptr));
-    k_class_hcopy<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), lds, p->stream>>>(g, k, p->uperm,
+    CHK(launch_plane_fwd(p, SRC_RAW, p->desc.psf + (long long)k * g.N));
+    k_class_hcopy<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), lds, p->ls>>>(g, k, p->uperm,
                          reinterpret_cast<float2*>(p->hs), p->tw32 + p->off[0]);
     CHK(last_launch("k_class_hcopy"));
   }
@@ -465,14 +470,45 @@ static mh3d_status build_spectra_user(mh3d_plan_t p) {
 
 extern "C" void mh3d_destroy(mh3d_plan_t p) {
   if (!p) return;
-  if (p->stream) hipStreamSynchronize(p->stream);
-  for (auto& e : p->pending) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
-  for (auto e : p->free_events) hipEventDestroy(e);
-  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3], p->port,
-                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st};
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (auto& e : p->pending) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
+  for (auto e : p->free_events) (void)hipEventDestroy(e);
+  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3],
+                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st, p->vdd, p->hist};
   for (void* q : bufs)
-    if (q) hipFree(q);
+    if (q) (void)hipFree(q);
   delete p;
+}
+
+static void fill_desc(mh3d_plan_t p) {
+  VolDesc& v = p->vdh;
+  memset(&v, 0, sizeof v);
+  v.g = p->g;
+  v.hs = p->hs;
+  v.imag_mask = p->imag_mask;
+  v.compact = p->compact;
+  v.b = p->b;
+  v.uperm = p->uperm;
+  v.G = p->G;
+  v.Gp = p->Gp;
+  v.rho[0] = p->vol[0];
+  v.rho[1] = p->vol[1];
+  v.y[0] = p->vol[2];
+  v.y[1] = p->vol[3];
+  v.d = nullptr;
+  v.tw = p->tw32;
+  for (int i = 0; i < 6; ++i) v.off[i] = p->off[i];
+  v.st = p->st;
+  v.partials = p->partials;
+  v.hist = p->hist;
+  v.hist_len = 0;
+  v.k_first = 1;
+  v.reg_kind = p->desc.reg_kind;
+  v.lam = (float)p->desc.lambda;
+  v.T_class = p->L.T_class;
 }
 
 extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
@@ -491,6 +527,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   p->g = g;
   p->L = L;
   p->stream = reinterpret_cast<hipStream_t>(desc->stream);
+  p->ls = p->stream;
   p->compact = desc->psf ? 0 : 1;
   memset(p->ms, 0, sizeof p->ms);
   memset(p->launches, 0, sizeof p->launches);
@@ -504,13 +541,14 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = dalloc(p, (void**)&p->Gp, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   for (int i = 0; i < 4; ++i)
     if ((s = dalloc(p, (void**)&p->vol[i], sizeof(float) * g.N)) != MH3D_OK) return bail(s);
-  if ((s = dalloc(p, (void**)&p->port, sizeof(float) * (size_t)g.K * g.M)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->prof, sizeof(double) * (size_t)g.K * g.nx)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->env, sizeof(double) * (size_t)g.ny * g.nz)) != MH3D_OK) return bail(s);
-  if ((s = dalloc(p, (void**)&p->partials, sizeof(double) * 2 * 4096)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->partials, sizeof(double) * 4 * 1024)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->st, sizeof(DevState))) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->vdd, sizeof(VolDesc))) != MH3D_OK) return bail(s);
   if ((s = build_tables(p)) != MH3D_OK) return bail(s);
-  // sensitivity
+  fill_desc(p);
+  if ((s = upload_desc(p)) != MH3D_OK) return bail(s);
   if (desc->sens) {
     if (hipMemcpyAsync(p->b, desc->sens, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
       return bail(fail(MH3D_ERR_HIP, "copy of the sensitivity map failed"));
@@ -525,6 +563,8 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if (p->compact) s = build_spectra_analytic(p);
   else s = build_spectra_user(p);
   if (s != MH3D_OK) return bail(s);
+  fill_desc(p);   // imag_mask is known now
+  if ((s = upload_desc(p)) != MH3D_OK) return bail(s);
   if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(fail(MH3D_ERR_HIP, "plan build failed on the device"));
   *out = p;
   return MH3D_OK;
@@ -536,50 +576,31 @@ static mh3d_status check_plan(mh3d_plan_t p) {
   return MH3D_OK;
 }
 
-static mh3d_status apply_A(mh3d_plan_t p, const float* rho, float* d) {
-  CHK(launch_plane_fwd(p, SRC_PLAIN, rho, nullptr, 1.f, nullptr));
-  CHK(launch_class_fwd(p, nullptr));
-  CHK(launch_small_inv(p, EPI_STORE, d, nullptr, nullptr));
-  return MH3D_OK;
-}
-
-static mh3d_status apply_AT(mh3d_plan_t p, const float* d, float* rho) {
-  CHK(launch_small_fwd(p, d));
-  CHK(launch_class_adj(p, nullptr));
-  AdjOut ao;
-  memset(&ao, 0, sizeof ao);
-  ao.out = rho;
-  CHK(launch_plane_adj(p, OUT_SCALE_B, ao));
-  return MH3D_OK;
-}
-
 extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
   CHK(check_plan(p));
   if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
-  return apply_A(p, rho, d);
+  CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
+  CHK(launch_class_fwd(p, 0));
+  CHK(launch_small_inv(p, EPI_STORE, d));
+  return MH3D_OK;
 }
 
 extern "C" mh3d_status mh3d_adjoint(mh3d_plan_t p, const float* d, float* rho) {
   CHK(check_plan(p));
   if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
-  return apply_AT(p, d, rho);
+  CHK(launch_small_fwd(p, d));
+  CHK(launch_class_adj(p, 0));
+  CHK(launch_plane_adj(p, OUT_SCALE_B, rho, nullptr));
+  return MH3D_OK;
 }
 
-// normal operator on x (scale 1): out = A^T A x + lambda T^T T x
+// out = (A^T A + lambda T^T T)(s w): s from the state (1/||w|| in power iteration).
 static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out) {
-  CHK(launch_plane_fwd(p, SRC_SCALED, w, nullptr, 1.f, p->st));
-  CHK(launch_class_fwd(p, p->st));
-  CHK(launch_small_inv(p, EPI_BACK, nullptr, nullptr, p->st));
-  CHK(launch_class_adj(p, p->st));
-  AdjOut ao;
-  memset(&ao, 0, sizeof ao);
-  ao.out = out;
-  ao.yin = w;
-  ao.partials = p->partials;
-  ao.st = p->st;
-  ao.reg_kind = p->desc.reg_kind;
-  ao.lam = (float)p->desc.lambda;
-  CHK(launch_plane_adj(p, OUT_NORMAL, ao));
+  CHK(launch_plane_fwd(p, SRC_SCALED, w));
+  CHK(launch_class_fwd(p, 1));
+  CHK(launch_small_inv(p, EPI_BACK, nullptr));
+  CHK(launch_class_adj(p, 1));
+  CHK(launch_plane_adj(p, OUT_NORMAL, out, w));
   return MH3D_OK;
 }
 
@@ -589,6 +610,7 @@ extern "C" mh3d_status mh3d_normal(mh3d_plan_t p, const float* x, float* out) {
   DevState z;
   memset(&z, 0, sizeof z);
   z.scale = 1.0;
+  z.kmax = 1 << 30;
   CHK(state_set(p, z));
   return apply_normal_scaled(p, x, out);
 }
@@ -599,10 +621,13 @@ static mh3d_status read_state(mh3d_plan_t p, DevState& h) {
   return MH3D_OK;
 }
 
+// Power iteration with start vector x0 of Philox uniforms in vol[0] (v_0 = x0/||x0||).
 static mh3d_status power_iteration(mh3d_plan_t p, int iters, uint64_t seed, double* lmax) {
   const Geo& g = p->g;
   DevState z;
   memset(&z, 0, sizeof z);
+  z.k = 0;
+  z.kmax = 1 << 30;
   CHK(state_set(p, z));
   {
     Timer t(p, KID_AUX);
@@ -629,35 +654,71 @@ extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64
 }
 
 // ============================================================================ solver
-extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
-                                  mh3d_solve_info* info) {
-  CHK(check_plan(p));
-  if (!d || !rho_inout || !opts) return fail(MH3D_ERR_INVALID, "NULL argument");
-  if (opts->max_iter < 1) return fail(MH3D_ERR_INVALID, "max_iter must be >= 1");
-  if (opts->k0 < 1) return fail(MH3D_ERR_INVALID, "k0 must be >= 1");
-  if (!(opts->rel_tol >= 0)) return fail(MH3D_ERR_INVALID, "rel_tol must be >= 0");
+// One accelerated projected gradient update of the plan's volume; buffers and the
+// step come from the device state, so the same launches serve every iteration.
+static mh3d_status enqueue_update(mh3d_plan_t p) {
+  Timer t(p, KID_SOLVE_ITER);
+  CHK(launch_plane_fwd(p, SRC_FISTA_Y, nullptr));
+  CHK(launch_class_fwd(p, 1));
+  CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr));
+  CHK(launch_class_adj(p, 1));
+  CHK(launch_plane_adj(p, OUT_FISTA, nullptr, nullptr));
+  return MH3D_OK;
+}
+
+// Captures `chunk` updates as a graph once per plan (replays are valid for any
+// data, iterate and iteration index since they live in the descriptor/state).
+static mh3d_status ensure_graph(mh3d_plan_t p, int chunk) {
+  if (p->gexec && p->graph_chunk == chunk) return MH3D_OK;
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  p->capturing = true;
+  p->ls = p->cap_stream;
+  mh3d_status s = MH3D_OK;
+  for (int i = 0; i < chunk && s == MH3D_OK; ++i) s = enqueue_update(p);
+  p->capturing = false;
+  p->ls = p->stream;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap_stream, &gr);
+  if (s != MH3D_OK) { if (gr) (void)hipGraphDestroy(gr); return s; }
+  if (e != hipSuccess) return fail(MH3D_ERR_HIP, "stream capture failed: %s", hipGetErrorString(e));
+  p->graph = gr;
+  HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+  p->graph_chunk = chunk;
+  return MH3D_OK;
+}
+
+static mh3d_status ensure_hist(mh3d_plan_t p, int n) {
+  if (p->hist_cap >= n) return MH3D_OK;
+  if (p->hist) (void)hipFree(p->hist);
+  p->hist = nullptr;
+  p->hist_cap = 0;
+  HIPCHK(hipMalloc(&p->hist, sizeof(double) * n));
+  p->hist_cap = n;
+  return MH3D_OK;
+}
+
+// Prepares rho^{k0}, y^{k0}, the descriptor and the state of a solve.
+static mh3d_status solve_setup(mh3d_plan_t p, const float* d, const float* rho0, const mh3d_solve_opts* opts,
+                               double tau) {
   const Geo& g = p->g;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, p->stream));
-  double tau = opts->tau, lmax = 0.0;
-  if (!(tau > 0)) {
-    const int it = opts->power_iters > 0 ? opts->power_iters : 50;
-    CHK(power_iteration(p, it, opts->power_seed, &lmax));
-    if (!(lmax > 0)) return fail(MH3D_ERR_NONFINITE, "power iteration gave L = %g", lmax);
-    tau = 1.0 / (1.05 * lmax);
-  }
   const int k0 = opts->k0;
-  // rho^k in vol[k % 2], y^k in vol[2 + k % 2]
-  HIPCHK(hipMemcpyAsync(p->vol[k0 % 2], rho_inout, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
+  CHK(ensure_hist(p, opts->max_iter));
+  HIPCHK(hipMemcpyAsync(p->vol[k0 & 1], rho0, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
   {
     Timer t(p, KID_AUX);
-    const float* prev = opts->rho_prev ? opts->rho_prev : rho_inout;
-    k_fista_init<<<dim3(1024), dim3(256), 0, p->stream>>>(g.N, rho_inout, prev, (float)((k0 - 1.0) / (k0 + 2.0)),
-                                                            p->vol[2 + k0 % 2]);
+    const float* prev = opts->rho_prev ? opts->rho_prev : rho0;
+    k_fista_init<<<dim3(1024), dim3(256), 0, p->ls>>>(g.N, rho0, prev, (float)((k0 - 1.0) / (k0 + 2.0)),
+                                                            p->vol[2 + (k0 & 1)]);
     CHK(last_launch("k_fista_init"));
   }
+  p->vdh.d = d;
+  p->vdh.hist = p->hist;
+  p->vdh.hist_len = opts->max_iter;
+  p->vdh.k_first = k0;
+  CHK(upload_desc(p));
   DevState s0;
   memset(&s0, 0, sizeof s0);
   s0.k = k0;
@@ -667,62 +728,43 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
   s0.kmax = k0 + opts->max_iter - 1;
   s0.last_k = k0 - 1;
   CHK(state_set(p, s0));
-  double* hist_dev = nullptr;
-  const int hlen = opts->max_iter;
-  HIPCHK(hipMalloc(&hist_dev, sizeof(double) * hlen));
-  const int chunk = opts->check_every > 0 ? opts->check_every : 25;
-  DevState h;
-  memset(&h, 0, sizeof h);
-  int issued = 0;
-  mh3d_status status = MH3D_OK;
-  while (issued < opts->max_iter) {
-    const int n = std::min(chunk, opts->max_iter - issued);
-    for (int i = 0; i < n; ++i) {
-      const int k = k0 + issued + i;   // host-side index only selects buffers
-      Timer t(p, KID_SOLVE_ITER);
-      CHK(launch_plane_fwd(p, SRC_FISTA_Y, p->vol[2 + k % 2], nullptr, 0.f, p->st));
-      CHK(launch_class_fwd(p, p->st));
-      CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr, d, p->st));
-      CHK(launch_class_adj(p, p->st));
-      AdjOut ao;
-      memset(&ao, 0, sizeof ao);
-      ao.yin = p->vol[2 + k % 2];
-      ao.rk = p->vol[k % 2];
-      ao.rho_next = p->vol[(k + 1) % 2];
-      ao.y_next = p->vol[2 + (k + 1) % 2];
-      ao.partials = p->partials;
-      ao.st = p->st;
-      ao.reg_kind = p->desc.reg_kind;
-      ao.lam = (float)p->desc.lambda;
-      ao.hist64 = hist_dev;
-      ao.k_first = k0;
-      ao.hist_len = hlen;
-      CHK(launch_plane_adj(p, OUT_FISTA, ao));
-    }
-    issued += n;
-    CHK(read_state(p, h));
-    if (h.done) break;
+  return MH3D_OK;
+}
+
+static mh3d_status validate_opts(const mh3d_solve_opts* opts) {
+  if (!opts) return fail(MH3D_ERR_INVALID, "opts is NULL");
+  if (opts->max_iter < 1) return fail(MH3D_ERR_INVALID, "max_iter must be >= 1");
+  if (opts->k0 < 1) return fail(MH3D_ERR_INVALID, "k0 must be >= 1");
+  if (!(opts->rel_tol >= 0)) return fail(MH3D_ERR_INVALID, "rel_tol must be >= 0");
+  return MH3D_OK;
+}
+
+static mh3d_status resolve_tau(mh3d_plan_t p, const mh3d_solve_opts* opts, double* tau, double* lmax) {
+  *tau = opts->tau;
+  *lmax = 0.0;
+  if (!(*tau > 0)) {
+    const int it = opts->power_iters > 0 ? opts->power_iters : 50;
+    CHK(power_iteration(p, it, opts->power_seed, lmax));
+    if (!(*lmax > 0)) return fail(MH3D_ERR_NONFINITE, "power iteration gave L = %g", *lmax);
+    *tau = 1.0 / (1.05 * *lmax);
   }
-  const int last = h.last_k;
-  const int iters = last - k0 + 1;
-  if (iters >= 1) {
-    HIPCHK(hipMemcpyAsync(rho_inout, p->vol[(last + 1) % 2], sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
-  }
-  HIPCHK(hipEventRecord(e1, p->stream));
+  return MH3D_OK;
+}
+
+static mh3d_status finish_solve(mh3d_plan_t p, float* rho_inout, const mh3d_solve_opts* opts, const DevState& h,
+                                double tau, double lmax, float ms, mh3d_solve_info* info) {
+  const int iters = h.last_k - opts->k0 + 1;
+  if (iters >= 1)
+    HIPCHK(hipMemcpyAsync(rho_inout, p->vol[(h.last_k + 1) & 1], sizeof(float) * p->g.N, hipMemcpyDeviceToDevice,
+                          p->stream));
   if (opts->history && opts->history_len > 0 && iters > 0) {
-    std::vector<double> hh(iters);
-    HIPCHK(hipMemcpyAsync(hh.data(), hist_dev, sizeof(double) * iters, hipMemcpyDeviceToHost, p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
-    for (int i = 0; i < std::min(iters, (int)opts->history_len); ++i) opts->history[i] = hh[i];
+    const int n = std::min(iters, (int)opts->history_len);
+    HIPCHK(hipMemcpyAsync(opts->history, p->hist, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
   }
   HIPCHK(hipStreamSynchronize(p->stream));
-  float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipFree(hist_dev);
+  mh3d_status status = MH3D_OK;
   if (h.nonfinite != 0.0) status = fail(MH3D_ERR_NONFINITE, "non-finite value in the solver reductions");
-  else if (!(opts->rel_tol > 0 && h.rel_step <= opts->rel_tol) && opts->rel_tol > 0)
+  else if (opts->rel_tol > 0 && !(h.rel_step <= opts->rel_tol))
     status = fail(MH3D_ERR_NOT_CONVERGED, "r_k = %g > tol after %d updates", h.rel_step, iters);
   if (info) {
     info->iters = iters;
@@ -734,6 +776,194 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
     info->status = status;
   }
   return status;
+}
+
+extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
+                                  mh3d_solve_info* info) {
+  CHK(check_plan(p));
+  if (!d || !rho_inout) return fail(MH3D_ERR_INVALID, "NULL argument");
+  CHK(validate_opts(opts));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, p->stream));
+  double tau, lmax;
+  CHK(resolve_tau(p, opts, &tau, &lmax));
+  CHK(solve_setup(p, d, rho_inout, opts, tau));
+  const int chunk = opts->check_every > 0 ? opts->check_every : 16;
+  const bool use_graph = !p->prof_on;   // per-launch timing needs plain launches
+  if (use_graph) CHK(ensure_graph(p, chunk));
+  DevState h;
+  memset(&h, 0, sizeof h);
+  int issued = 0;
+  while (issued < opts->max_iter) {
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(p->gexec, p->stream));
+      issued += chunk;
+    } else {
+      const int n = std::min(chunk, opts->max_iter - issued);
+      for (int i = 0; i < n; ++i) CHK(enqueue_update(p));
+      issued += n;
+    }
+    CHK(read_state(p, h));
+    if (h.done) break;
+  }
+  HIPCHK(hipEventRecord(e1, p->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return finish_solve(p, rho_inout, opts, h, tau, lmax, ms, info);
+}
+
+// ============================================================================ batch
+struct mh3d_batch_s {
+  std::vector<mh3d_plan_t> plans;
+  hipStream_t stream;
+  VolDesc* vds = nullptr;            // device descriptors of all volumes
+  int2* tasks[3] = {nullptr, nullptr, nullptr};   // plane, class, small task tables
+  int ntask[3] = {0, 0, 0};
+  int T_class = 0;
+  size_t lds_plane = 0, lds_class = 0, lds_small = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int chunk = 0;
+};
+
+extern "C" void mh3d_batch_destroy(mh3d_batch_t b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->vds) (void)hipFree(b->vds);
+  for (int i = 0; i < 3; ++i)
+    if (b->tasks[i]) (void)hipFree(b->tasks[i]);
+  delete b;
+}
+
+extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh3d_batch_t* out) {
+  if (!out) return fail(MH3D_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !plans) return fail(MH3D_ERR_INVALID, "empty batch");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(MH3D_ERR_INVALID, "plan %d is NULL", i);
+    if (!plans[i]->compact) return fail(MH3D_ERR_UNSUPPORTED, "batched solves need analytic-PSF plans (plan %d)", i);
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(MH3D_ERR_INVALID, "plan %d appears twice in the batch", i);
+  }
+  mh3d_batch_t b = new mh3d_batch_s();
+  b->plans.assign(plans, plans + n);
+  b->stream = plans[0]->stream;
+  std::vector<int2> t[3];
+  for (int v = 0; v < n; ++v) {
+    const mh3d_plan_t p = plans[v];
+    for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
+    for (int i = 0; i < p->g.ncls / p->g.cpw; ++i) t[1].push_back(make_int2(v, i));
+    for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
+    b->T_class = std::max(b->T_class, p->L.T_class);
+    b->lds_plane = std::max(b->lds_plane, p->L.lds_plane);
+    b->lds_class = std::max(b->lds_class, p->L.lds_class);
+    b->lds_small = std::max(b->lds_small, p->L.lds_small);
+  }
+  auto bail = [&](mh3d_status s) { mh3d_batch_destroy(b); return s; };
+  if (hipMalloc(&b->vds, sizeof(VolDesc) * n) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch descriptors"));
+  for (int i = 0; i < 3; ++i) {
+    b->ntask[i] = (int)t[i].size();
+    if (hipMalloc(&b->tasks[i], sizeof(int2) * t[i].size()) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch tasks"));
+    if (hipMemcpy(b->tasks[i], t[i].data(), sizeof(int2) * t[i].size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(MH3D_ERR_HIP, "upload of batch tasks failed"));
+  }
+  *out = b;
+  return MH3D_OK;
+}
+
+// One update of every volume of the batch: five launches over the task tables.
+static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
+  k_plane_fwd<SRC_FISTA_Y><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
+  CHK(last_launch("k_plane_fwd (batch)"));
+  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+  CHK(last_launch("k_class_fwd_batch"));
+  k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+  CHK(last_launch("k_small_inv (batch)"));
+  k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+  CHK(last_launch("k_class_adj_batch"));
+  AdjOut ao;
+  ao.out = nullptr;
+  ao.yin = nullptr;
+  k_plane_adj<OUT_FISTA><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  CHK(last_launch("k_plane_adj (batch)"));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, float* const* rho_inout,
+                                        const mh3d_solve_opts* opts, mh3d_solve_info* infos) {
+  if (!b) return fail(MH3D_ERR_INVALID, "batch is NULL");
+  if (!d || !rho_inout) return fail(MH3D_ERR_INVALID, "NULL argument");
+  CHK(validate_opts(opts));
+  const int n = (int)b->plans.size();
+  for (int v = 0; v < n; ++v)
+    if (!d[v] || !rho_inout[v]) return fail(MH3D_ERR_INVALID, "NULL array for volume %d", v);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, b->stream));
+  std::vector<double> tau(n), lmax(n);
+  for (int v = 0; v < n; ++v) {
+    mh3d_plan_t p = b->plans[v];
+    CHK(resolve_tau(p, opts, &tau[v], &lmax[v]));
+    CHK(solve_setup(p, d[v], rho_inout[v], opts, tau[v]));
+    HIPCHK(hipMemcpyAsync(b->vds + v, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
+  }
+  const int chunk = opts->check_every > 0 ? opts->check_every : 16;
+  if (!b->gexec || b->chunk != chunk) {
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    mh3d_status s = MH3D_OK;
+    for (int i = 0; i < chunk && s == MH3D_OK; ++i) s = batch_update(b, b->cap_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &gr);
+    if (s != MH3D_OK) { if (gr) (void)hipGraphDestroy(gr); return s; }
+    if (e != hipSuccess) return fail(MH3D_ERR_HIP, "stream capture failed: %s", hipGetErrorString(e));
+    b->graph = gr;
+    HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    b->chunk = chunk;
+  }
+  // per-volume state snapshots after each replay; the graph is replayed until every
+  // volume reports done (each volume stops updating at its own r_k <= tol)
+  std::vector<DevState> hs(n);
+  int issued = 0;
+  while (issued < opts->max_iter) {
+    HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+    issued += chunk;
+    bool all = true;
+    for (int v = 0; v < n; ++v)
+      HIPCHK(hipMemcpyAsync(&hs[v], b->plans[v]->st, sizeof(DevState), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int v = 0; v < n; ++v) all = all && hs[v].done;
+    if (all) break;
+  }
+  HIPCHK(hipEventRecord(e1, b->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  mh3d_status worst = MH3D_OK;
+  for (int v = 0; v < n; ++v) {
+    mh3d_solve_info inf;
+    mh3d_solve_opts o = *opts;
+    o.history = nullptr;
+    o.history_len = 0;
+    mh3d_status s = finish_solve(b->plans[v], rho_inout[v], &o, hs[v], tau[v], lmax[v], ms, &inf);
+    if (infos) infos[v] = inf;
+    if (s != MH3D_OK && worst == MH3D_OK) worst = s;
+  }
+  return worst;
 }
 
 // ============================================================================ export / profile
@@ -773,21 +1003,8 @@ extern "C" mh3d_status mh3d_philox4x32_10(const uint32_t* ctr, const uint32_t* k
   mh3d_status s = last_launch("k_philox_words");
   if (s == MH3D_OK && hipMemcpy(out, d, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
     s = fail(MH3D_ERR_HIP, "copy of Philox words failed");
-  hipFree(d);
+  (void)hipFree(d);
   return s;
-}
-
-static void drain_events(mh3d_plan_t p) {
-  for (auto& e : p->pending) {
-    float ms = 0.f;
-    hipEventSynchronize(e.second.second);
-    hipEventElapsedTime(&ms, e.second.first, e.second.second);
-    p->ms[e.first] += ms;
-    p->launches[e.first] += 1;
-    p->free_events.push_back(e.second.first);
-    p->free_events.push_back(e.second.second);
-  }
-  p->pending.clear();
 }
 
 extern "C" mh3d_status mh3d_profile(mh3d_plan_t p, int32_t enable) {

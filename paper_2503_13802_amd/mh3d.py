@@ -91,11 +91,16 @@ def library():
     lib.mh3d_profile.argtypes = [vp, i32]
     lib.mh3d_profile_read.argtypes = [vp, ctypes.POINTER(ProfileData)]
     lib.mh3d_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+    lib.mh3d_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.mh3d_batch_destroy.argtypes = [vp]
+    lib.mh3d_batch_destroy.restype = None
+    lib.mh3d_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
+                                     ctypes.POINTER(SolveInfo)]
     lib.mh3d_last_error.restype = ctypes.c_char_p
     lib.mh3d_version.restype = i32
     for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
                  "mh3d_power_iteration", "mh3d_solve", "mh3d_plan_export", "mh3d_profile",
-                 "mh3d_profile_read", "mh3d_philox4x32_10"):
+                 "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -279,3 +284,45 @@ class Plan:
         pd = ProfileData()
         _check(library().mh3d_profile_read(self._h, ctypes.byref(pd)))
         return {pd.name[i].decode(): (pd.ms[i], pd.launches[i]) for i in range(NKERNEL)}
+
+
+class Batch:
+    """Batched solve of several plans (uneven volumes) through mh3d_solve_batch."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(library().mh3d_batch_create(len(self.plans), arr, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().mh3d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, ds, rho0s=None, max_iter=500, tol=1e-4, tau=0.0, power_iters=50, power_seed=0,
+              check_every=16):
+        """ds: list of portrait tensors; returns (list of rho, list of info dicts)."""
+        torch = self.plans[0].torch
+        ds = [p._port(d) for p, d in zip(self.plans, ds)]
+        rhos = [torch.zeros(p.shape, device=p.device) if rho0s is None else p._vol(r).clone()
+                for p, r in zip(self.plans, rho0s if rho0s is not None else [None] * len(self.plans))]
+        n = len(self.plans)
+        dp = (ctypes.c_void_p * n)(*[d.data_ptr() for d in ds])
+        rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhos])
+        o = SolveOpts(int(max_iter), float(tol), float(tau), int(power_iters), int(power_seed), None, 1,
+                      int(check_every), None, 0)
+        infos = (SolveInfo * n)()
+        s = library().mh3d_solve_batch(self._h, dp, rp, ctypes.byref(o), infos)
+        if s not in (OK, ERR_NOT_CONVERGED):
+            _check(s)
+        out = [{"iters": i.iters, "rel_step": i.rel_step, "tau": i.tau, "lmax": i.lmax, "ms_total": i.ms_total,
+                "status": i.status} for i in infos]
+        return rhos, out
