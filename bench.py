@@ -7,7 +7,12 @@ applications per second, the HBM roofline of the dominant kernel (measured with
 HIP events around its launches), the FP64 CPU oracle timed on a bounded sample of
 the same workload, and the time to reconstruct at r_k <= 1e-4 with the plain solver.
 
+The batched leg solves the 64 uneven volumes of the batch workload (sizes 48^3 ..
+128x128x96, 2..10 harmonics) to r_k <= 1e-4 each, once as 64 sequential plain
+solves and once as one batched solve, and reports both wall times.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1|2] [--no-cpu] [--no-solve]
+                       [--no-batch]
 """
 import argparse
 import json
@@ -65,6 +70,47 @@ def cpu_baseline(w, rho, r, budget_s=15.0):
                       "same workload; PSF/sensitivity setup %.1f s excluded" % (n, os.cpu_count(), setup)}
 
 
+def batched_leg(batch_inputs, tol, max_iter):
+    """64 uneven volumes to r_k <= tol: sequential plain solves vs one batched solve."""
+    import numpy as np
+    import torch
+    from paper_2503_13802_amd import inputs, mh3d
+    bws, phantoms, _ = batch_inputs
+    dev = torch.device("cuda:0")
+    plans, ds = [], []
+    for bw, ph in zip(bws, phantoms):
+        p = mh3d.Plan(bw.shape, bw.harmonics, bw.a_per_mm, bw.ds, bw.sigma_mm, bw.lam, bw.voxel_mm)
+        clean = p.forward(torch.tensor(ph, dtype=torch.float32, device=dev)).cpu().numpy().astype(np.float64)
+        d = inputs.add_noise(clean, bw.snr_db, inputs.noise_draw(bw))
+        plans.append(p)
+        ds.append(torch.tensor(d, dtype=torch.float32, device=dev))
+    torch.cuda.synchronize()
+    log("batched leg: %d plans built" % len(plans))
+    # sequential plain solves (warm the captured graphs once on the first volume)
+    plans[0].solve(ds[0], max_iter=20, tol=0.0, tau=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [p.solve(d, max_iter=max_iter, tol=tol, tau=0.0) for p, d in zip(plans, ds)]
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    batch = mh3d.Batch(plans)
+    batch.solve(ds, max_iter=16, tol=0.0, tau=0.0)       # records the graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rhos, infos = batch.solve(ds, max_iter=max_iter, tol=tol, tau=0.0)
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - t0
+    same = all(torch.equal(r, s[0]) for r, s in zip(rhos, seq))
+    iters_seq = [s[1]["iters"] for s in seq]
+    iters_bat = [i["iters"] for i in infos]
+    conv = sum(1 for i in infos if i["rel_step"] <= tol)
+    vox = sum(int(np.prod(bw.shape)) for bw in bws)
+    return {"volumes": len(plans), "voxels": vox, "sequential_s": round(seq_s, 4), "batched_s": round(bat_s, 4),
+            "speedup": round(seq_s / bat_s, 3), "converged": conv, "iters_max": max(iters_bat),
+            "iters_mean": round(float(np.mean(iters_bat)), 1), "identical_to_sequential": bool(same),
+            "iters_match": iters_seq == iters_bat}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +119,8 @@ def main():
     ap.add_argument("--workload", type=int, default=1, choices=[1, 2])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-volumes", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; a multi-GPU run is not part of it "
@@ -80,8 +128,22 @@ def main():
         sys.exit(2)
 
     import numpy as np
+    from paper_2503_13802_amd import inputs
+
+    batch_inputs = None
+    if not args.no_batch:
+        # host phantoms of the batch workload, drawn in worker processes before the
+        # GPU is touched
+        from multiprocessing import Pool
+        bws = inputs.batch_workloads(args.batch_volumes)
+        t0 = time.perf_counter()
+        with Pool(min(16, os.cpu_count() or 1)) as pool:
+            phantoms = pool.map(inputs.phantom, bws)
+        batch_inputs = (bws, phantoms, time.perf_counter() - t0)
+        log("batch phantoms: %d volumes in %.1f s" % (len(bws), batch_inputs[2]))
+
     import torch
-    from paper_2503_13802_amd import inputs, mh3d
+    from paper_2503_13802_amd import mh3d
 
     w = inputs.workload(args.workload)
     log("workload %s" % w.name)
@@ -167,6 +229,9 @@ def main():
         out["time_to_recon"] = {"plain_s": round(time.perf_counter() - t0, 4), "iters": info["iters"],
                                 "rel_step": info["rel_step"], "ms_per_iter": round(info["ms_per_iter"], 4),
                                 "tau": info["tau"], "status": info["status"]}
+
+    if batch_inputs is not None:
+        out["batched"] = batched_leg(batch_inputs, w.tol, w.max_iter)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -898,6 +898,54 @@ static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
   return MH3D_OK;
 }
 
+// One power-iteration step of every volume: w_{t+1} = N (s w_t), w_t in rho[k & 1].
+static mh3d_status batch_power_step(mh3d_batch_t b, hipStream_t st) {
+  k_plane_fwd<SRC_SCALED><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
+  CHK(last_launch("k_plane_fwd (batch power)"));
+  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+  CHK(last_launch("k_class_fwd_batch (power)"));
+  k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+  CHK(last_launch("k_small_inv (batch power)"));
+  k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+  CHK(last_launch("k_class_adj_batch (power)"));
+  AdjOut ao;
+  ao.out = nullptr;
+  ao.yin = nullptr;
+  k_plane_adj<OUT_NORMAL><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  CHK(last_launch("k_plane_adj (batch power)"));
+  return MH3D_OK;
+}
+
+// Step sizes of every volume from batched power iterations (same start vectors and
+// recurrence as mh3d_power_iteration on each plan).
+static mh3d_status batch_power(mh3d_batch_t b, int iters, uint64_t seed, std::vector<double>& lmax) {
+  const int n = (int)b->plans.size();
+  for (int v = 0; v < n; ++v) {
+    mh3d_plan_t p = b->plans[v];
+    DevState z;
+    memset(&z, 0, sizeof z);
+    z.k = 0;
+    z.kmax = iters - 1;
+    CHK(state_set(p, z));
+    hipLaunchKernelGGL(k_philox_uniform, dim3(256), dim3(256), 0, p->stream, (long long)p->g.N, seed, 0u, p->vol[0],
+                       p->partials, p->st);
+    CHK(last_launch("k_philox_uniform"));
+    HIPCHK(hipMemcpyAsync(b->vds + v, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
+  }
+  for (int t = 0; t < iters; ++t) CHK(batch_power_step(b, b->stream));
+  std::vector<DevState> hs(n);
+  for (int v = 0; v < n; ++v)
+    HIPCHK(hipMemcpyAsync(&hs[v], b->plans[v]->st, sizeof(DevState), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  lmax.assign(n, 0.0);
+  for (int v = 0; v < n; ++v) {
+    if (hs[v].nonfinite != 0.0 || !(hs[v].lmax > 0) || !std::isfinite(hs[v].lmax))
+      return fail(MH3D_ERR_NONFINITE, "power iteration of volume %d gave L = %g", v, hs[v].lmax);
+    lmax[v] = hs[v].lmax;
+  }
+  return MH3D_OK;
+}
+
 extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, float* const* rho_inout,
                                         const mh3d_solve_opts* opts, mh3d_solve_info* infos) {
   if (!b) return fail(MH3D_ERR_INVALID, "batch is NULL");
@@ -910,10 +958,13 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, b->stream));
-  std::vector<double> tau(n), lmax(n);
+  std::vector<double> tau(n, opts->tau), lmax(n, 0.0);
+  if (!(opts->tau > 0)) {
+    CHK(batch_power(b, opts->power_iters > 0 ? opts->power_iters : 50, opts->power_seed, lmax));
+    for (int v = 0; v < n; ++v) tau[v] = 1.0 / (1.05 * lmax[v]);
+  }
   for (int v = 0; v < n; ++v) {
     mh3d_plan_t p = b->plans[v];
-    CHK(resolve_tau(p, opts, &tau[v], &lmax[v]));
     CHK(solve_setup(p, d[v], rho_inout[v], opts, tau[v]));
     HIPCHK(hipMemcpyAsync(b->vds + v, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
   }
