@@ -151,6 +151,50 @@ void mh3d_batch_destroy(mh3d_batch_t batch);
 mh3d_status mh3d_solve_batch(mh3d_batch_t batch, const float* const* d, float* const* rho_inout,
                              const mh3d_solve_opts* opts, mh3d_solve_info* infos);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not in the paper): a 3D U-Net that maps the back-projection
+ * A^T d to an initial density for mh3d_solve, which then refines it to the same
+ * tolerance as a cold start (Sec. 4.3 solver unchanged).  BF16 weights and
+ * activations, FP32 accumulation on MFMA, FP32 master weights and Adam.
+ * Network: levels L, widths w_0..w_{L-1}; encoder level l = two 3x3x3 conv + ReLU,
+ * 2x2x2 average pooling between levels; decoder level l = nearest 2x upsampling,
+ * concatenation with the encoder output of level l, two 3x3x3 conv + ReLU; head =
+ * 1x1x1 conv to one channel.  Flat FP32 parameter layout: for each layer (enc0a,
+ * enc0b, ..., enc(L-1)b, dec(L-2)a, dec(L-2)b, ..., dec0b, head) the weights as
+ * [Cout][tap][Cin] (tap = (dx+1)*9 + (dy+1)*3 + (dz+1)) then the bias [Cout].
+ * Inputs are scaled by s = max |x|: the network sees x/s (and targets t/s).
+ * Grids must be powers of two, at least 2^L per axis. */
+typedef struct mh3d_net_s* mh3d_net_t;
+/* He-normal weights from Philox4x32-10 (key seed, stream = layer index), zero biases. */
+mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, uint64_t seed, void* stream, mh3d_net_t* out);
+void mh3d_net_destroy(mh3d_net_t net);
+int64_t mh3d_net_param_count(mh3d_net_t net);
+/* Copy the FP32 master parameters to (set = 0) or from (set = 1) a DEVICE buffer. */
+mh3d_status mh3d_net_params(mh3d_net_t net, float* params, int32_t set);
+/* Copy the gradient of the last mh3d_net_loss_grad to a DEVICE buffer. */
+mh3d_status mh3d_net_grads(mh3d_net_t net, float* grads);
+/* y = net(x / max|x|) on an nx*ny*nz DEVICE volume (FP32 in and out). */
+mh3d_status mh3d_net_forward(mh3d_net_t net, const float* x, int32_t nx, int32_t ny, int32_t nz, float* y);
+/* Loss mean((net(x/s) - t/s)^2) over a crop (HOST int[6] = offset xyz, size xyz;
+ * NULL = whole volume; s over the whole volume) and its gradient (kept in the
+ * network).  *loss (HOST, may be NULL) receives the loss; synchronous if given. */
+mh3d_status mh3d_net_loss_grad(mh3d_net_t net, const float* x, const float* t, int32_t nx, int32_t ny, int32_t nz,
+                               const int32_t* crop, double* loss);
+/* One Adam step (Kingma & Ba) on the last gradient. */
+mh3d_status mh3d_net_adam_step(mh3d_net_t net, float lr, float beta1, float beta2, float eps);
+/* rho_init = s * max(net(A^T d / s), 0), s = max |A^T d|.  plan and net share a stream. */
+mh3d_status mh3d_warm_start(mh3d_plan_t plan, mh3d_net_t net, const float* d, float* rho_init);
+
+/* Training data on the GPU.  mh3d_phantom: n_spheres spheres (radius U(2,5) mm)
+ * and n_tubes tubes (radius U(1,2.5) mm around quadratic Bezier curves with points
+ * U(3, extent-3)), concentrations 10^U(-2,0), voxel-centre inclusion, drawn from
+ * Philox4x32-10 (key seed, counter (j, object, 0, 0)).  mh3d_noisy_data:
+ * d = A rho + sigma_k xi, sigma_k = rms_k 10^(-(snr2_db - decay_db (k-2))/20), xi
+ * standard normal by Box-Muller from Philox (key seed, counter (i/2, 1, i>>33, 0)). */
+mh3d_status mh3d_phantom(mh3d_plan_t plan, uint64_t seed, int32_t n_spheres, int32_t n_tubes, float* rho);
+mh3d_status mh3d_noisy_data(mh3d_plan_t plan, const float* rho, uint64_t seed, double snr2_db, double decay_db,
+                            float* d);
+
 /* Copies internal plan data to a caller DEVICE buffer, for tests and tools.
  *   MH3D_FIELD_PROFILE   FP64 [n_harm][nx]      drive-axis profiles L^(k)(a x), raw
  *   MH3D_FIELD_ENVELOPE  FP64 [ny][nz]          transverse envelope E, raw

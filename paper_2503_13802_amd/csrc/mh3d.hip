@@ -1079,3 +1079,6 @@ extern "C" mh3d_status mh3d_profile_read(mh3d_plan_t p, mh3d_profile_data* out) 
   }
   return MH3D_OK;
 }
+
+// ============================================================================ warm-start network
+#include "net_host.hpp"

@@ -1,0 +1,656 @@
+// Host side of the warm-start network and of the on-GPU training-data generator.
+// Included by mh3d.hip after the plan definitions (it uses mh3d_plan_s).
+#pragma once
+#include <map>
+#include <tuple>
+
+#include "net_kernels.hpp"
+
+using namespace mh3d::net;
+
+namespace {
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return (1 << l) == n ? l : -1;
+}
+int round4(int c) { return (c + 3) & ~3; }
+int round16(int c) { return (c + 15) & ~15; }
+
+struct NetLayer {
+  int cin, cout, ks;
+  int cs_in, cs_out;       // channel strides of the input / output tensors
+  int kp, kpt;             // K of the forward / data-gradient GEMMs (multiples of 16)
+  int rows_f, rows_t;      // padded rows of the forward / data-gradient matrices
+  long long w_off, b_off;  // offsets in the flat FP32 parameter vector
+  uint16_t* Wf = nullptr;  // BF16 forward matrix
+  uint16_t* Wt = nullptr;  // BF16 flipped transposed matrix
+  float* gWf = nullptr;    // FP32 gradient of the forward matrix
+};
+
+// Activations and gradients of one grid shape.
+struct NetWork {
+  int lx, ly, lz;
+  std::vector<uint16_t*> bufs;
+  uint16_t* x0 = nullptr;                 // input [N0][4]
+  std::vector<uint16_t*> ea, es, pl;      // enc conv a / conv b (skip) outputs, pooled inputs (level l+1)
+  std::vector<uint16_t*> cat, da, db;     // decoder concat input, conv a, conv b outputs
+  std::vector<uint16_t*> g1, g2, g3, gs;  // gradient scratch per level (max channel stride) and skip grads
+  float* y = nullptr;                     // head output FP32 [N0]
+  uint16_t* gy = nullptr;                 // head output gradient [N0][4]
+  double* scale = nullptr;                // max |x| of the current input
+  double* loss = nullptr;
+};
+
+}  // namespace
+
+struct mh3d_net_s {
+  std::vector<int> widths;
+  std::vector<NetLayer> layers;
+  long long nparam = 0;
+  float* p = nullptr;        // FP32 master parameters (flat layout of oracle/unet.py)
+  float* g = nullptr;        // FP32 gradient, same layout
+  float* m = nullptr;        // Adam moments
+  float* v = nullptr;
+  int64_t step = 0;
+  hipStream_t stream;
+  std::map<std::tuple<int, int, int>, NetWork> work;
+  bool packed = false;
+};
+
+namespace {
+
+mh3d_status net_alloc(void** ptr, size_t bytes) {
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    *ptr = nullptr;
+    return fail(MH3D_ERR_OOM, "hipMalloc(%zu) failed in the network", bytes);
+  }
+  return MH3D_OK;
+}
+
+int grid_for(long long n, int block = 256) {
+  long long b = (n + block - 1) / block;
+  if (b > 8192) b = 8192;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// layer order: enc0a enc0b ... enc(L-1)b, dec(L-2)a dec(L-2)b ... dec0a dec0b, head
+int enc_index(int l, int ab) { return 2 * l + ab; }
+int dec_index(int L, int l, int ab) { return 2 * L + 2 * (L - 2 - l) + ab; }
+
+mh3d_status net_pack(mh3d_net_t n) {
+  for (auto& ly : n->layers) {
+    k_pack_layer<<<grid_for((long long)ly.rows_f * ly.kp + (long long)ly.rows_t * ly.kpt), 256, 0, n->stream>>>(
+        n->p + ly.w_off, ly.cin, ly.cout, ly.ks, ly.cs_in, ly.cs_out, ly.kp, ly.kpt, ly.rows_f, ly.rows_t, ly.Wf, ly.Wt);
+    CHK(last_launch("k_pack_layer"));
+  }
+  n->packed = true;
+  return MH3D_OK;
+}
+
+mh3d_status net_work(mh3d_net_t n, int nx, int ny, int nz, NetWork** out) {
+  auto key = std::make_tuple(nx, ny, nz);
+  auto it = n->work.find(key);
+  if (it != n->work.end()) { *out = &it->second; return MH3D_OK; }
+  const int L = (int)n->widths.size();
+  NetWork w;
+  w.lx = ilog2(nx); w.ly = ilog2(ny); w.lz = ilog2(nz);
+  auto nvox = [&](int l) { return 1ll << (w.lx + w.ly + w.lz - 3 * l); };
+  auto mk = [&](long long elems, uint16_t** p) -> mh3d_status {
+    void* q = nullptr;
+    CHK(net_alloc(&q, sizeof(uint16_t) * (size_t)elems));
+    (void)hipMemsetAsync(q, 0, sizeof(uint16_t) * (size_t)elems, n->stream);
+    w.bufs.push_back((uint16_t*)q);
+    *p = (uint16_t*)q;
+    return MH3D_OK;
+  };
+  CHK(mk(nvox(0) * 4, &w.x0));
+  w.ea.resize(L); w.es.resize(L); w.pl.resize(L); w.cat.resize(L); w.da.resize(L); w.db.resize(L);
+  w.g1.resize(L); w.g2.resize(L); w.g3.resize(L); w.gs.resize(L);
+  int cmax_all = 4;
+  for (int l = 0; l < L; ++l) {
+    const int cs = round4(n->widths[l]);
+    const int cats = l < L - 1 ? round4(n->widths[l] + n->widths[l + 1]) : 4;
+    const int cmax = std::max(std::max(cs, cats), l ? round4(n->widths[l - 1]) : 4);
+    cmax_all = std::max(cmax_all, cmax);
+    CHK(mk(nvox(l) * cs, &w.ea[l]));
+    CHK(mk(nvox(l) * cs, &w.es[l]));
+    if (l) CHK(mk(nvox(l) * round4(n->widths[l - 1]), &w.pl[l]));
+    if (l < L - 1) {
+      CHK(mk(nvox(l) * cats, &w.cat[l]));
+      CHK(mk(nvox(l) * cs, &w.da[l]));
+      CHK(mk(nvox(l) * cs, &w.db[l]));
+    }
+    CHK(mk(nvox(l) * cmax, &w.g1[l]));
+    CHK(mk(nvox(l) * cmax, &w.g2[l]));
+    CHK(mk(nvox(l) * cmax, &w.g3[l]));
+    CHK(mk(nvox(l) * cs, &w.gs[l]));
+  }
+  CHK(mk(nvox(0) * 4, &w.gy));
+  CHK(net_alloc((void**)&w.y, sizeof(float) * (size_t)nvox(0)));
+  CHK(net_alloc((void**)&w.scale, sizeof(double) * 2));
+  w.loss = w.scale + 1;
+  (void)cmax_all;
+  auto res = n->work.emplace(key, w);
+  *out = &res.first->second;
+  return MH3D_OK;
+}
+
+Dims dims_of(const NetWork& w, int l) { return Dims{w.lx - l, w.ly - l, w.lz - l}; }
+
+mh3d_status conv_fwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims dm, void* out, bool relu, bool f32) {
+  const long long N = 1ll << (dm.lx + dm.ly + dm.lz);
+  const int blocks = (int)((N + 63) / 64);
+  if (f32) k_conv<false, true><<<blocks, 256, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out);
+  else if (relu) k_conv<true, false><<<blocks, 256, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out);
+  else k_conv<false, false><<<blocks, 256, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out);
+  return last_launch("k_conv");
+}
+
+// Gradients of one conv layer given the gradient g of its (pre-activation) output:
+// accumulates dW, db and writes the input gradient gin (unless null).
+mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims dm, const uint16_t* g, int cs_g,
+                     uint16_t* gin, float* zero_bias) {
+  const long long N = 1ll << (dm.lx + dm.ly + dm.lz);
+  const int ncot = (ly.cout + 15) / 16, nkc = ly.kp / 16;
+  long long chunk = 2048;
+  int nsplit = (int)((N + chunk - 1) / chunk);
+  k_conv_wgrad<<<ncot * nkc * nsplit, 64, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, g, cs_g, ly.cout, ly.kp, ly.gWf, nsplit, chunk);
+  CHK(last_launch("k_conv_wgrad"));
+  dim3 bg(std::min<long long>(1024, (N + 3) / 4), (ly.cout + 63) / 64);
+  k_bias_grad<<<bg, 256, 0, n->stream>>>(g, N, cs_g, ly.cout, n->g + ly.b_off);
+  CHK(last_launch("k_bias_grad"));
+  if (gin) {
+    // data gradient = convolution of g with the flipped, transposed weights (no bias)
+    const int blocks = (int)((N + 63) / 64);
+    k_conv<false, false><<<blocks, 256, 0, n->stream>>>(g, dm, cs_g, ly.ks, ly.Wt, ly.kpt, zero_bias, ly.cin, ly.cs_in, gin);
+    CHK(last_launch("k_conv (data gradient)"));
+  }
+  return MH3D_OK;
+}
+
+// x (FP32, volume grid `src`, crop window o + dst dims) -> forward through the net;
+// result FP32 in w->y.  Scale s = max |x| over the whole source volume.
+mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long long nsrc, int ox, int oy, int oz) {
+  const int L = (int)n->widths.size();
+  if (!n->packed) CHK(net_pack(n));
+  k_absmax<<<1, 1024, 0, n->stream>>>(x, nsrc, w->scale);
+  CHK(last_launch("k_absmax"));
+  Dims d0 = dims_of(*w, 0);
+  k_to_bf16_crop<<<grid_for(d0.n()), 256, 0, n->stream>>>(x, src, ox, oy, oz, d0, w->scale, 4, w->x0);
+  CHK(last_launch("k_to_bf16_crop"));
+  const uint16_t* h = w->x0;
+  for (int l = 0; l < L; ++l) {
+    Dims dl = dims_of(*w, l);
+    if (l) {
+      const int cs = round4(n->widths[l - 1]);
+      k_avgpool<<<grid_for(dl.n() * cs), 256, 0, n->stream>>>(h, dims_of(*w, l - 1), cs, w->pl[l], dl);
+      CHK(last_launch("k_avgpool"));
+      h = w->pl[l];
+    }
+    CHK(conv_fwd(n, n->layers[enc_index(l, 0)], h, dl, w->ea[l], true, false));
+    CHK(conv_fwd(n, n->layers[enc_index(l, 1)], w->ea[l], dl, w->es[l], true, false));
+    h = w->es[l];
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    Dims dl = dims_of(*w, l);
+    const int c1 = n->widths[l], c2 = n->widths[l + 1];
+    const int cats = round4(c1 + c2);
+    k_upcat<<<grid_for(dl.n() * cats), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
+                                                            dims_of(*w, l + 1), cats, w->cat[l]);
+    CHK(last_launch("k_upcat"));
+    CHK(conv_fwd(n, n->layers[dec_index(L, l, 0)], w->cat[l], dl, w->da[l], true, false));
+    CHK(conv_fwd(n, n->layers[dec_index(L, l, 1)], w->da[l], dl, w->db[l], true, false));
+    h = w->db[l];
+  }
+  CHK(conv_fwd(n, n->layers.back(), h, d0, w->y, false, true));
+  return MH3D_OK;
+}
+
+mh3d_status net_backward(mh3d_net_t n, NetWork* w) {
+  const int L = (int)n->widths.size();
+  float* zb = n->g + n->nparam;   // zero bias of the data-gradient convolutions (tail of the gradient buffer)
+  Dims d0 = dims_of(*w, 0);
+  // head (1x1x1): gradient of the last decoder output
+  const uint16_t* top = L >= 2 ? w->db[0] : w->es[0];
+  uint16_t* g = w->g1[0];
+  CHK(conv_bwd(n, n->layers.back(), top, d0, w->gy, 4, g, zb));
+  // decoder, level 0 upwards: g is the gradient of db[l] (post-ReLU output)
+  for (int l = 0; l <= L - 2; ++l) {
+    Dims dl = dims_of(*w, l);
+    const int cs = round4(n->widths[l]);
+    const NetLayer& lb = n->layers[dec_index(L, l, 1)];
+    const NetLayer& la = n->layers[dec_index(L, l, 0)];
+    k_relu_bwd<<<grid_for(dl.n() * cs), 256, 0, n->stream>>>(g, w->db[l], dl.n() * cs);
+    CHK(last_launch("k_relu_bwd"));
+    uint16_t* g_da = (g == w->g1[l]) ? w->g2[l] : w->g1[l];
+    CHK(conv_bwd(n, lb, w->da[l], dl, g, cs, g_da, zb));
+    k_relu_bwd<<<grid_for(dl.n() * cs), 256, 0, n->stream>>>(g_da, w->da[l], dl.n() * cs);
+    CHK(last_launch("k_relu_bwd"));
+    const int cats = round4(n->widths[l] + n->widths[l + 1]);
+    uint16_t* g_cat = w->g3[l];
+    CHK(conv_bwd(n, la, w->cat[l], dl, g_da, cs, g_cat, zb));
+    // split: skip part -> gs[l], coarse part -> gradient of the next level's output
+    Dims dc = dims_of(*w, l + 1);
+    const int cs2 = round4(n->widths[l + 1]);
+    uint16_t* g_next = w->g1[l + 1];
+    k_upcat_bwd<<<grid_for(dl.n() * cs), 256, 0, n->stream>>>(g_cat, cats, n->widths[l], n->widths[l + 1], dl, dc,
+                                                              w->gs[l], cs, g_next, cs2);
+    CHK(last_launch("k_upcat_bwd"));
+    g = g_next;
+  }
+  // encoder, bottom level downwards: g is the gradient of es[l]
+  for (int l = L - 1; l >= 0; --l) {
+    Dims dl = dims_of(*w, l);
+    const int cs = round4(n->widths[l]);
+    if (l < L - 1) {
+      // total gradient of the skip tensor: concat part (gs) + pooled part (already in g)
+      // g currently holds the pooled-path gradient accumulated into gs[l]
+      g = w->gs[l];
+    }
+    const NetLayer& lb = n->layers[enc_index(l, 1)];
+    const NetLayer& la = n->layers[enc_index(l, 0)];
+    k_relu_bwd<<<grid_for(dl.n() * cs), 256, 0, n->stream>>>(g, w->es[l], dl.n() * cs);
+    CHK(last_launch("k_relu_bwd"));
+    uint16_t* g_ea = (g == w->g2[l]) ? w->g3[l] : w->g2[l];
+    CHK(conv_bwd(n, lb, w->ea[l], dl, g, cs, g_ea, zb));
+    k_relu_bwd<<<grid_for(dl.n() * cs), 256, 0, n->stream>>>(g_ea, w->ea[l], dl.n() * cs);
+    CHK(last_launch("k_relu_bwd"));
+    const uint16_t* in = l ? w->pl[l] : w->x0;
+    if (l) {
+      uint16_t* g_in = (g_ea == w->g1[l]) ? w->g3[l] : w->g1[l];
+      CHK(conv_bwd(n, la, in, dl, g_ea, cs, g_in, zb));
+      // average-pool backward adds into the skip gradient of level l-1
+      const int csp = round4(n->widths[l - 1]);
+      k_avgpool_bwd_add<<<grid_for(dims_of(*w, l - 1).n() * csp), 256, 0, n->stream>>>(g_in, dl, csp, w->gs[l - 1],
+                                                                                       dims_of(*w, l - 1));
+      CHK(last_launch("k_avgpool_bwd_add"));
+    } else {
+      CHK(conv_bwd(n, la, in, dl, g_ea, cs, nullptr, zb));
+    }
+  }
+  // padded forward-matrix gradients -> flat layout
+  for (auto& ly : n->layers) {
+    k_unpack_wgrad<<<grid_for((long long)ly.cout * ly.ks * ly.ks * ly.ks * ly.cin), 256, 0, n->stream>>>(
+        ly.gWf, ly.cin, ly.cout, ly.ks, ly.cs_in, ly.kp, n->g + ly.w_off);
+    CHK(last_launch("k_unpack_wgrad"));
+  }
+  return MH3D_OK;
+}
+
+mh3d_status net_zero_grads(mh3d_net_t n) {
+  k_fill_f32<<<grid_for(n->nparam), 256, 0, n->stream>>>(n->g, n->nparam + 128, 0.f);
+  CHK(last_launch("k_fill_f32"));
+  for (auto& ly : n->layers) {
+    k_fill_f32<<<grid_for((long long)ly.rows_f * ly.kp), 256, 0, n->stream>>>(ly.gWf, (long long)ly.rows_f * ly.kp, 0.f);
+    CHK(last_launch("k_fill_f32"));
+  }
+  return MH3D_OK;
+}
+
+// He-normal initialisation from Philox (Box-Muller), zero biases.
+__global__ void k_net_init(float* __restrict__ p, long long wo, long long nw, int fan_in, uint64_t seed, uint32_t stream) {
+  const float sd = sqrtf(2.f / (float)fan_in);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nw; i += (long long)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)i, stream, 0u, 0u};
+    philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    const float u1 = ((float)c[0] + 0.5f) * 2.3283064365386963e-10f;
+    const float u2 = ((float)c[1] + 0.5f) * 2.3283064365386963e-10f;
+    p[wo + i] = sd * sqrtf(-2.f * logf(u1)) * cospif(2.f * u2);
+  }
+}
+
+}  // namespace
+
+// ============================================================================ network ABI
+extern "C" mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, uint64_t seed, void* stream,
+                                       mh3d_net_t* out) {
+  if (!out) return fail(MH3D_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (levels < 2 || levels > 6 || !widths) return fail(MH3D_ERR_INVALID, "levels must be in [2, 6]");
+  for (int l = 0; l < levels; ++l)
+    if (widths[l] < 1 || widths[l] > 16 * NT_MAX) return fail(MH3D_ERR_INVALID, "width %d out of range", widths[l]);
+  // the data gradient of a decoder's first convolution has widths[l] + widths[l+1]
+  // output channels, which must fit one wave's tiles (and the zero-bias tail)
+  for (int l = 0; l + 1 < levels; ++l)
+    if (widths[l] + widths[l + 1] > 16 * NT_MAX) return fail(MH3D_ERR_INVALID, "concat width too large");
+  mh3d_net_t n = new mh3d_net_s();
+  n->widths.assign(widths, widths + levels);
+  n->stream = reinterpret_cast<hipStream_t>(stream);
+  const int L = levels;
+  // layer list in the flat parameter order
+  struct Spec { int cin, cout, ks; };
+  std::vector<Spec> specs;
+  int cin = 1;
+  for (int l = 0; l < L; ++l) {
+    specs.push_back({cin, widths[l], 3});
+    specs.push_back({widths[l], widths[l], 3});
+    cin = widths[l];
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    specs.push_back({widths[l] + widths[l + 1], widths[l], 3});
+    specs.push_back({widths[l], widths[l], 3});
+  }
+  specs.push_back({widths[0], 1, 1});
+  long long off = 0;
+  for (const Spec& s : specs) {
+    NetLayer ly;
+    ly.cin = s.cin;
+    ly.cout = s.cout;
+    ly.ks = s.ks;
+    ly.cs_in = round4(s.cin);
+    ly.cs_out = round4(s.cout);
+    const int ntap = s.ks * s.ks * s.ks;
+    ly.kp = round16(ntap * ly.cs_in);
+    ly.kpt = round16(ntap * ly.cs_out);
+    ly.rows_f = round16(s.cout);
+    ly.rows_t = round16(s.cin);
+    ly.w_off = off;
+    off += (long long)s.cout * ntap * s.cin;
+    ly.b_off = off;
+    off += s.cout;
+    n->layers.push_back(ly);
+  }
+  n->nparam = off;
+  auto bail = [&](mh3d_status st) { mh3d_net_destroy(n); return st; };
+  mh3d_status st;
+  if ((st = net_alloc((void**)&n->p, sizeof(float) * (off + 128))) != MH3D_OK) return bail(st);
+  if ((st = net_alloc((void**)&n->g, sizeof(float) * (off + 128))) != MH3D_OK) return bail(st);
+  if ((st = net_alloc((void**)&n->m, sizeof(float) * off)) != MH3D_OK) return bail(st);
+  if ((st = net_alloc((void**)&n->v, sizeof(float) * off)) != MH3D_OK) return bail(st);
+  for (auto& ly : n->layers) {
+    if ((st = net_alloc((void**)&ly.Wf, sizeof(uint16_t) * (size_t)ly.rows_f * ly.kp)) != MH3D_OK) return bail(st);
+    if ((st = net_alloc((void**)&ly.Wt, sizeof(uint16_t) * (size_t)ly.rows_t * ly.kpt)) != MH3D_OK) return bail(st);
+    if ((st = net_alloc((void**)&ly.gWf, sizeof(float) * (size_t)ly.rows_f * ly.kp)) != MH3D_OK) return bail(st);
+  }
+  k_fill_f32<<<grid_for(off + 128), 256, 0, n->stream>>>(n->p, off + 128, 0.f);
+  k_fill_f32<<<grid_for(off), 256, 0, n->stream>>>(n->m, off, 0.f);
+  k_fill_f32<<<grid_for(off), 256, 0, n->stream>>>(n->v, off, 0.f);
+  for (size_t i = 0; i < n->layers.size(); ++i) {
+    const NetLayer& ly = n->layers[i];
+    const long long nw = (long long)ly.cout * ly.ks * ly.ks * ly.ks * ly.cin;
+    k_net_init<<<grid_for(nw), 256, 0, n->stream>>>(n->p, ly.w_off, nw, ly.cin * ly.ks * ly.ks * ly.ks, seed, (uint32_t)i);
+  }
+  if ((st = last_launch("k_net_init")) != MH3D_OK) return bail(st);
+  if ((st = net_zero_grads(n)) != MH3D_OK) return bail(st);
+  if (hipStreamSynchronize(n->stream) != hipSuccess) return bail(fail(MH3D_ERR_HIP, "network init failed"));
+  *out = n;
+  return MH3D_OK;
+}
+
+extern "C" void mh3d_net_destroy(mh3d_net_t n) {
+  if (!n) return;
+  (void)hipStreamSynchronize(n->stream);
+  for (auto& kv : n->work) {
+    for (auto* b : kv.second.bufs) (void)hipFree(b);
+    if (kv.second.y) (void)hipFree(kv.second.y);
+    if (kv.second.scale) (void)hipFree(kv.second.scale);
+  }
+  for (auto& ly : n->layers) {
+    if (ly.Wf) (void)hipFree(ly.Wf);
+    if (ly.Wt) (void)hipFree(ly.Wt);
+    if (ly.gWf) (void)hipFree(ly.gWf);
+  }
+  void* bufs[] = {n->p, n->g, n->m, n->v};
+  for (void* q : bufs)
+    if (q) (void)hipFree(q);
+  delete n;
+}
+
+extern "C" int64_t mh3d_net_param_count(mh3d_net_t n) { return n ? n->nparam : 0; }
+
+extern "C" mh3d_status mh3d_net_params(mh3d_net_t n, float* dst, int32_t set) {
+  if (!n || !dst) return fail(MH3D_ERR_INVALID, "NULL argument");
+  if (set) {
+    HIPCHK(hipMemcpyAsync(n->p, dst, sizeof(float) * n->nparam, hipMemcpyDeviceToDevice, n->stream));
+    n->packed = false;
+  } else {
+    HIPCHK(hipMemcpyAsync(dst, n->p, sizeof(float) * n->nparam, hipMemcpyDeviceToDevice, n->stream));
+  }
+  HIPCHK(hipStreamSynchronize(n->stream));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_net_grads(mh3d_net_t n, float* dst) {
+  if (!n || !dst) return fail(MH3D_ERR_INVALID, "NULL argument");
+  HIPCHK(hipMemcpyAsync(dst, n->g, sizeof(float) * n->nparam, hipMemcpyDeviceToDevice, n->stream));
+  HIPCHK(hipStreamSynchronize(n->stream));
+  return MH3D_OK;
+}
+
+static mh3d_status net_check_dims(mh3d_net_t n, int nx, int ny, int nz) {
+  const int L = (int)n->widths.size();
+  const int dims[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a)
+    if (ilog2(dims[a]) < 0 || dims[a] < (1 << L)) return fail(MH3D_ERR_INVALID, "network grids must be powers of two >= 2^levels");
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_net_forward(mh3d_net_t n, const float* x, int32_t nx, int32_t ny, int32_t nz, float* y) {
+  if (!n || !x || !y) return fail(MH3D_ERR_INVALID, "NULL argument");
+  CHK(net_check_dims(n, nx, ny, nz));
+  NetWork* w;
+  CHK(net_work(n, nx, ny, nz, &w));
+  Dims src{ilog2(nx), ilog2(ny), ilog2(nz)};
+  CHK(net_forward(n, w, x, src, (long long)nx * ny * nz, 0, 0, 0));
+  HIPCHK(hipMemcpyAsync(y, w->y, sizeof(float) * (size_t)nx * ny * nz, hipMemcpyDeviceToDevice, n->stream));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_net_loss_grad(mh3d_net_t n, const float* x, const float* t, int32_t nx, int32_t ny,
+                                          int32_t nz, const int32_t* crop, double* loss) {
+  if (!n || !x || !t) return fail(MH3D_ERR_INVALID, "NULL argument");
+  CHK(net_check_dims(n, nx, ny, nz));
+  int o[3] = {0, 0, 0}, c[3] = {nx, ny, nz};
+  if (crop) {
+    for (int a = 0; a < 3; ++a) { o[a] = crop[a]; c[a] = crop[3 + a]; }
+    const int full[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a)
+      if (o[a] < 0 || c[a] < 1 || o[a] + c[a] > full[a]) return fail(MH3D_ERR_INVALID, "crop outside the volume");
+    CHK(net_check_dims(n, c[0], c[1], c[2]));
+  }
+  NetWork* w;
+  CHK(net_work(n, c[0], c[1], c[2], &w));
+  Dims src{ilog2(nx), ilog2(ny), ilog2(nz)};
+  CHK(net_zero_grads(n));
+  CHK(net_forward(n, w, x, src, (long long)nx * ny * nz, o[0], o[1], o[2]));
+  Dims d0 = dims_of(*w, 0);
+  k_fill_f64<<<1, 64, 0, n->stream>>>(w->loss, 1, 0.0);
+  k_mse<<<grid_for(d0.n()), 256, 0, n->stream>>>(w->y, t, src, o[0], o[1], o[2], d0, w->scale, 4, w->gy, w->loss);
+  CHK(last_launch("k_mse"));
+  CHK(net_backward(n, w));
+  if (loss) {
+    HIPCHK(hipMemcpyAsync(loss, w->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+    HIPCHK(hipStreamSynchronize(n->stream));
+  }
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_net_adam_step(mh3d_net_t n, float lr, float beta1, float beta2, float eps) {
+  if (!n) return fail(MH3D_ERR_INVALID, "NULL network");
+  n->step += 1;
+  const float c1 = 1.f - powf(beta1, (float)n->step), c2 = 1.f - powf(beta2, (float)n->step);
+  k_adam<<<grid_for(n->nparam), 256, 0, n->stream>>>(n->p, n->g, n->m, n->v, n->nparam, lr, beta1, beta2, eps, c1, c2);
+  CHK(last_launch("k_adam"));
+  CHK(net_pack(n));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_warm_start(mh3d_plan_t p, mh3d_net_t n, const float* d, float* rho_init) {
+  CHK(check_plan(p));
+  if (!n || !d || !rho_init) return fail(MH3D_ERR_INVALID, "NULL argument");
+  const Geo& g = p->g;
+  CHK(net_check_dims(n, g.nx, g.ny, g.nz));
+  if (n->stream != p->stream) return fail(MH3D_ERR_INVALID, "network and plan must share a stream");
+  // back-projection A^T d into the plan's scratch volume
+  CHK(launch_small_fwd(p, d));
+  CHK(launch_class_adj(p, 0));
+  CHK(launch_plane_adj(p, OUT_SCALE_B, p->vol[3], nullptr));
+  NetWork* w;
+  CHK(net_work(n, g.nx, g.ny, g.nz, &w));
+  Dims src{ilog2(g.nx), ilog2(g.ny), ilog2(g.nz)};
+  CHK(net_forward(n, w, p->vol[3], src, g.N, 0, 0, 0));
+  k_scale_relu<<<grid_for(g.N), 256, 0, p->stream>>>(w->y, g.N, w->scale, rho_init);
+  CHK(last_launch("k_scale_relu"));
+  return MH3D_OK;
+}
+
+// ============================================================================ training data on the GPU
+namespace {
+
+// Object parameters drawn from Philox4x32-10: stream = object index, key = seed,
+// counter (j, object, 0, 0) for the j-th block of four uniforms u = (w + 0.5)/2^32.
+// Spheres (kind 0): radius U(2,5) mm, centre U(r, extent - r) per axis, concentration
+// 10^U(-2,0).  Tubes (kind 1): radius U(1,2.5) mm, three Bezier points U(3, extent - 3),
+// concentration 10^U(-2,0).
+struct Obj {
+  double c[9];     // sphere: centre[3]; tube: p0[3], p1[3], p2[3]
+  double r, conc;
+  int kind;
+};
+
+__device__ __forceinline__ double philox_u(uint64_t seed, uint32_t obj, uint32_t j, int w) {
+  uint32_t c[4] = {j, obj, 0u, 0u};
+  philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+  return ((double)c[w] + 0.5) / 4294967296.0;
+}
+
+__global__ void k_phantom_objects(uint64_t seed, int nsph, int ntube, double ex, double ey, double ez,
+                                  Obj* __restrict__ objs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsph + ntube) return;
+  Obj o;
+  const double ext[3] = {ex, ey, ez};
+  auto u = [&](int q) { return philox_u(seed, (uint32_t)i, (uint32_t)(q >> 2), q & 3); };
+  if (i < nsph) {
+    o.kind = 0;
+    o.r = 2.0 + 3.0 * u(0);
+    for (int a = 0; a < 3; ++a) o.c[a] = o.r + (ext[a] - 2.0 * o.r) * u(1 + a);
+    o.conc = pow(10.0, -2.0 + 2.0 * u(4));
+  } else {
+    o.kind = 1;
+    o.r = 1.0 + 1.5 * u(0);
+    for (int q = 0; q < 9; ++q) o.c[q] = 3.0 + (ext[q % 3] - 6.0) * u(1 + q);
+    o.conc = pow(10.0, -2.0 + 2.0 * u(10));
+  }
+  objs[i] = o;
+}
+
+// Voxel-centre inclusion (centres at i * voxel); overlapping objects add.  Tube
+// distance: nearest of 257 samples of the curve.
+__global__ void k_phantom_raster(Geo g, double vox, const Obj* __restrict__ objs, int nobj, float* __restrict__ rho) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N; i += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(i % g.nz);
+    const int y = (int)((i / g.nz) % g.ny);
+    const int x = (int)(i / ((long long)g.ny * g.nz));
+    const double px = x * vox, py = y * vox, pz = z * vox;
+    double acc = 0.0;
+    for (int q = 0; q < nobj; ++q) {
+      const Obj& o = objs[q];
+      if (o.kind == 0) {
+        const double dx = px - o.c[0], dy = py - o.c[1], dz = pz - o.c[2];
+        if (dx * dx + dy * dy + dz * dz <= o.r * o.r) acc += o.conc;
+      } else {
+        // bounding box of the control polygon (contains the curve) grown by r
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = fmin(fmin(o.c[a], o.c[3 + a]), o.c[6 + a]) - o.r;
+          hi[a] = fmax(fmax(o.c[a], o.c[3 + a]), o.c[6 + a]) + o.r;
+        }
+        if (px < lo[0] || px > hi[0] || py < lo[1] || py > hi[1] || pz < lo[2] || pz > hi[2]) continue;
+        double best = 1e300;
+        for (int s = 0; s <= 256; ++s) {
+          const double t = s / 256.0, a0 = (1 - t) * (1 - t), a1 = 2 * (1 - t) * t, a2 = t * t;
+          const double cx = a0 * o.c[0] + a1 * o.c[3] + a2 * o.c[6];
+          const double cy = a0 * o.c[1] + a1 * o.c[4] + a2 * o.c[7];
+          const double cz = a0 * o.c[2] + a1 * o.c[5] + a2 * o.c[8];
+          const double d2 = (px - cx) * (px - cx) + (py - cy) * (py - cy) + (pz - cz) * (pz - cz);
+          best = fmin(best, d2);
+        }
+        if (best <= o.r * o.r) acc += o.conc;
+      }
+    }
+    rho[i] = (float)acc;
+  }
+}
+
+// Per-harmonic mean square of the portraits (FP64, one block per harmonic).
+__global__ void k_port_meansq(const float* __restrict__ d, long long M, double* __restrict__ ms) {
+  __shared__ double part[256];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < M; i += blockDim.x) {
+    const double v = d[(long long)k * M + i];
+    s += v * v;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < (int)blockDim.x; ++q) t += part[q];
+    ms[k] = t / (double)M;
+  }
+}
+
+// d_k += sigma_k xi, sigma_k = rms_k 10^(-(snr2 - decay (k_idx... )) / 20), xi standard
+// normal by Box-Muller from Philox stream (seed, 1): counter (i/2, 1, 0, 0).
+__global__ void k_add_noise(float* __restrict__ d, long long M, int K, const double* __restrict__ ms,
+                            const int* __restrict__ harm, double snr2, double decay, uint64_t seed) {
+  const long long n = (long long)K * M;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(i / M);
+    uint32_t c[4] = {(uint32_t)(i >> 1), 1u, (uint32_t)(i >> 33), 0u};
+    philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    const double u1 = ((double)c[(i & 1) * 2] + 0.5) / 4294967296.0;
+    const double u2 = ((double)c[(i & 1) * 2 + 1] + 0.5) / 4294967296.0;
+    const double xi = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+    const double snr = snr2 - decay * (harm[k] - 2);
+    const double sigma = sqrt(ms[k]) * pow(10.0, -snr / 20.0);
+    d[i] = (float)(d[i] + sigma * xi);
+  }
+}
+
+}  // namespace
+
+extern "C" mh3d_status mh3d_phantom(mh3d_plan_t p, uint64_t seed, int32_t n_spheres, int32_t n_tubes, float* rho) {
+  CHK(check_plan(p));
+  if (!rho || n_spheres < 0 || n_tubes < 0 || n_spheres + n_tubes > 4096)
+    return fail(MH3D_ERR_INVALID, "bad phantom arguments");
+  const Geo& g = p->g;
+  const int nobj = n_spheres + n_tubes;
+  Obj* objs = nullptr;
+  HIPCHK(hipMalloc(&objs, sizeof(Obj) * (nobj > 0 ? nobj : 1)));
+  const double v = p->desc.voxel_mm;
+  if (nobj)
+    k_phantom_objects<<<(nobj + 63) / 64, 64, 0, p->stream>>>(seed, n_spheres, n_tubes, (g.nx - 1) * v,
+                                                             (g.ny - 1) * v, (g.nz - 1) * v, objs);
+  k_phantom_raster<<<grid_for(g.N), 256, 0, p->stream>>>(g, v, objs, nobj, rho);
+  mh3d_status s = last_launch("k_phantom_raster");
+  if (hipStreamSynchronize(p->stream) != hipSuccess && s == MH3D_OK) s = fail(MH3D_ERR_HIP, "phantom kernel failed");
+  (void)hipFree(objs);
+  return s;
+}
+
+extern "C" mh3d_status mh3d_noisy_data(mh3d_plan_t p, const float* rho, uint64_t seed, double snr2_db,
+                                       double decay_db, float* d) {
+  CHK(check_plan(p));
+  if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL argument");
+  const Geo& g = p->g;
+  CHK(mh3d_forward(p, rho, d));
+  double* ms = nullptr;
+  int* harm = nullptr;
+  HIPCHK(hipMalloc(&ms, sizeof(double) * g.K));
+  HIPCHK(hipMalloc(&harm, sizeof(int) * g.K));
+  HIPCHK(hipMemcpyAsync(harm, p->harm.data(), sizeof(int) * g.K, hipMemcpyHostToDevice, p->stream));
+  k_port_meansq<<<g.K, 256, 0, p->stream>>>(d, g.M, ms);
+  mh3d_status s = last_launch("k_port_meansq");
+  if (s == MH3D_OK) {
+    k_add_noise<<<grid_for((long long)g.K * g.M), 256, 0, p->stream>>>(d, g.M, g.K, ms, harm, snr2_db, decay_db, seed);
+    s = last_launch("k_add_noise");
+  }
+  if (hipStreamSynchronize(p->stream) != hipSuccess && s == MH3D_OK) s = fail(MH3D_ERR_HIP, "noise kernel failed");
+  (void)hipFree(ms);
+  (void)hipFree(harm);
+  return s;
+}

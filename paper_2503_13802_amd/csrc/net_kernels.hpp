@@ -1,0 +1,382 @@
+// Warm-start 3D U-Net on gfx950: BF16 activations and weights, FP32 accumulation on
+// MFMA (v_mfma_f32_16x16x16_bf16), FP32 master weights, Adam.
+//
+// Tensors are channels-last BF16 [X][Y][Z][Cs] with the channel stride Cs a
+// multiple of 4 (padding channels hold zeros).  Grid axes are powers of two so
+// voxel decoding is shifts.  A 3x3x3 convolution is an implicit GEMM
+//   out[n][co] = b[co] + sum_k W[co][k] in[n + d(tap(k))][ci(k)],  k = tap*Cs_in + ci,
+// tap = (dx+1)*9 + (dy+1)*3 + (dz+1), zero outside the grid; K is padded to a
+// multiple of 16 with zero weights.  One wavefront computes 16 voxels x all output
+// channels (16-wide tiles); per MFMA the lane layout is
+//   A[row = lane%16][k = 4*(lane/16) + j]   (voxel x reduction),
+//   B[k = 4*(lane/16) + j][col = lane%16]   (reduction x channel),
+//   D[row = 4*(lane/16) + j][col = lane%16].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mh3d {
+namespace net {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int NT_MAX = 7;   // output-channel tiles per wave (112 channels)
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct Dims {
+  int lx, ly, lz;          // log2 of the axes
+  __host__ __device__ __forceinline__ long long n() const { return 1ll << (lx + ly + lz); }
+  __device__ __forceinline__ void decode(long long i, int& x, int& y, int& z) const {
+    z = (int)(i & ((1ll << lz) - 1));
+    y = (int)((i >> lz) & ((1ll << ly) - 1));
+    x = (int)(i >> (ly + lz));
+  }
+  __device__ __forceinline__ long long encode(int x, int y, int z) const {
+    return ((long long)x << (ly + lz)) | ((long long)y << lz) | z;
+  }
+  __device__ __forceinline__ bool inside(int x, int y, int z) const {
+    return x >= 0 && y >= 0 && z >= 0 && x < (1 << lx) && y < (1 << ly) && z < (1 << lz);
+  }
+};
+
+__device__ __forceinline__ void tap_offset(int tap, int ks, int& dx, int& dy, int& dz) {
+  if (ks == 1) { dx = dy = dz = 0; return; }
+  dx = tap / 9 - 1;
+  dy = (tap / 3) % 3 - 1;
+  dz = tap % 3 - 1;
+}
+
+// Convolution (ks = 3 or 1).  in: [N][cs_in]; W: [cout_tiles*16][kp] BF16; bias FP32
+// [cout]; out: BF16 [N][cs_out] or FP32 [N] (OUTF32, cout == 1).  Padding output
+// channels cout..cs_out-1 are written as zeros.  block = 256 (4 waves, 64 voxels).
+template <bool RELU, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, Dims dm, int cs_in, int ks,
+                                              const uint16_t* __restrict__ W, int kp,
+                                              const float* __restrict__ bias, int cout, int cs_out,
+                                              void* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long N = dm.n();
+  const long long n0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  if (n0 >= N) return;                      // wave-uniform, no block barriers below
+  const int r = lane & 15, g = lane >> 4;
+  const long long n = n0 + r;
+  const bool nvalid = n < N;
+  int x = 0, y = 0, z = 0;
+  if (nvalid) dm.decode(n, x, y, z);
+  const int ntile = (cout + 15) >> 4;
+  const int ntap = ks * ks * ks;
+  f4v acc[NT_MAX];
+#pragma unroll
+  for (int t = 0; t < NT_MAX; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+  int tap = 0, ci = 4 * g;
+  while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  for (int kc = 0; kc < (kp >> 4); ++kc) {
+    s4v a = s4v{0, 0, 0, 0};
+    if (nvalid && tap < ntap) {
+      int dx, dy, dz;
+      tap_offset(tap, ks, dx, dy, dz);
+      const int xx = x + dx, yy = y + dy, zz = z + dz;
+      if (dm.inside(xx, yy, zz)) a = *reinterpret_cast<const s4v*>(in + dm.encode(xx, yy, zz) * cs_in + ci);
+    }
+    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < NT_MAX; ++t) {
+      if (t < ntile) {
+        const s4v b = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    ci += 16;
+    while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  }
+#pragma unroll
+  for (int t = 0; t < NT_MAX; ++t) {
+    if (t >= ntile) break;
+    const int co = t * 16 + r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long nn = n0 + 4 * g + j;
+      if (nn >= N) continue;
+      if constexpr (OUTF32) {
+        if (co == 0) reinterpret_cast<float*>(out)[nn] = acc[t][j] + bias[0];
+      } else {
+        if (co < cout) {
+          float v = acc[t][j] + bias[co];
+          if (RELU) v = fmaxf(v, 0.f);
+          reinterpret_cast<uint16_t*>(out)[nn * cs_out + co] = f2bf(v);
+        } else if (co < cs_out) {
+          reinterpret_cast<uint16_t*>(out)[nn * cs_out + co] = 0;
+        }
+      }
+    }
+  }
+}
+
+// Weight gradient  gW[co][k] += sum_n gout[n][co] in[n + d(tap(k))][ci(k)]
+// (FP32 atomics).  grid = co_tiles * k_tiles * nsplit blocks of one wave; each
+// wave reduces over its voxel range in chunks of 16 (4 voxels per lane group).
+__global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ in, Dims dm, int cs_in, int ks,
+                                                   const uint16_t* __restrict__ gout, int cs_g, int cout, int kp,
+                                                   float* __restrict__ gW, int nsplit, long long chunk) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int ncot = (cout + 15) >> 4;
+  const int tile = blockIdx.x / nsplit, split = blockIdx.x - (blockIdx.x / nsplit) * nsplit;
+  const int tc = tile % ncot, kc = tile / ncot;
+  const long long N = dm.n();
+  const long long v0 = (long long)split * chunk;
+  const long long v1 = v0 + chunk < N ? v0 + chunk : N;
+  const int co = tc * 16 + r;
+  const int k = kc * 16 + r;
+  const int tap = k / cs_in, ci = k - (k / cs_in) * cs_in;
+  const bool kvalid = tap < ks * ks * ks;
+  int dx = 0, dy = 0, dz = 0;
+  if (kvalid) tap_offset(tap, ks, dx, dy, dz);
+  f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+  for (long long nb = v0; nb < v1; nb += 16) {
+    s4v a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long n = nb + 4 * g + j;
+      uint16_t av = 0, bv = 0;
+      if (n < v1) {
+        if (co < cout) av = gout[n * cs_g + co];
+        if (kvalid) {
+          int x, y, z;
+          dm.decode(n, x, y, z);
+          const int xx = x + dx, yy = y + dy, zz = z + dz;
+          if (dm.inside(xx, yy, zz)) bv = in[dm.encode(xx, yy, zz) * cs_in + ci];
+        }
+      }
+      a[j] = (short)av;
+      b[j] = (short)bv;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  // D[row = co 4g+j][col = k r]
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cor = tc * 16 + 4 * g + j;
+    if (cor < cout && k < kp && acc[j] != 0.f) atomicAdd(&gW[(long long)cor * kp + k], acc[j]);
+  }
+}
+
+// Bias gradient gb[co] += sum_n g[n][co].  grid = (blocks, ceil(cout/64)), 256 threads.
+__global__ void k_bias_grad(const uint16_t* __restrict__ gout, long long N, int cs_g, int cout, float* __restrict__ gb) {
+  __shared__ float part[256];
+  const int co = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int sub = threadIdx.x >> 6;
+  float s = 0.f;
+  if (co < cout)
+    for (long long n = (long long)blockIdx.x * 4 + sub; n < N; n += (long long)gridDim.x * 4) s += bf2f(gout[n * cs_g + co]);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (sub == 0 && co < cout) {
+    const float t = part[threadIdx.x] + part[threadIdx.x + 64] + part[threadIdx.x + 128] + part[threadIdx.x + 192];
+    atomicAdd(&gb[co], t);
+  }
+}
+
+// FP32 volume / scale -> BF16 [N][cs] channel 0 (crop window (o, c) of the source).
+__global__ void k_to_bf16_crop(const float* __restrict__ x, Dims src, int ox, int oy, int oz, Dims dst,
+                               const double* __restrict__ scale, int cs, uint16_t* __restrict__ out) {
+  const long long N = dst.n();
+  const float inv = (float)(1.0 / *scale);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    int x0, y0, z0;
+    dst.decode(i, x0, y0, z0);
+    const float v = x[src.encode(x0 + ox, y0 + oy, z0 + oz)] * inv;
+    out[i * cs] = f2bf(v);
+    for (int c = 1; c < cs; ++c) out[i * cs + c] = 0;
+  }
+}
+
+// 2x2x2 average pooling (channels-last).
+__global__ void k_avgpool(const uint16_t* __restrict__ in, Dims di, int cs, uint16_t* __restrict__ out, Dims dout) {
+  const long long N = dout.n() * cs;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const long long n = i / cs;
+    const int c = (int)(i - n * cs);
+    int x, y, z;
+    dout.decode(n, x, y, z);
+    float s = 0.f;
+    for (int q = 0; q < 8; ++q) s += bf2f(in[di.encode(2 * x + (q >> 2), 2 * y + ((q >> 1) & 1), 2 * z + (q & 1)) * cs + c]);
+    out[i] = f2bf(0.125f * s);
+  }
+}
+
+// gin[child] = gout[parent]/8 added to gin (average-pool backward).
+__global__ void k_avgpool_bwd_add(const uint16_t* __restrict__ gout, Dims dout, int cs, uint16_t* __restrict__ gin, Dims di) {
+  const long long N = di.n() * cs;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const long long n = i / cs;
+    const int c = (int)(i - n * cs);
+    int x, y, z;
+    di.decode(n, x, y, z);
+    const float v = bf2f(gout[dout.encode(x >> 1, y >> 1, z >> 1) * cs + c]);
+    gin[i] = f2bf(bf2f(gin[i]) + 0.125f * v);
+  }
+}
+
+// out[n] = [skip[n][0:c1], coarse[n/2][0:c2], 0...] (nearest upsampling + concat).
+__global__ void k_upcat(const uint16_t* __restrict__ skip, int cs1, int c1, const uint16_t* __restrict__ coarse, int cs2,
+                        int c2, Dims df, Dims dc, int cs, uint16_t* __restrict__ out) {
+  const long long N = df.n() * cs;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const long long n = i / cs;
+    const int c = (int)(i - n * cs);
+    uint16_t v = 0;
+    if (c < c1) v = skip[n * cs1 + c];
+    else if (c < c1 + c2) {
+      int x, y, z;
+      df.decode(n, x, y, z);
+      v = coarse[dc.encode(x >> 1, y >> 1, z >> 1) * cs2 + (c - c1)];
+    }
+    out[i] = v;
+  }
+}
+
+// Backward of k_upcat: gskip[n][c] = g[n][c] (c < c1); gcoarse[m][c] = sum of its 8 children.
+__global__ void k_upcat_bwd(const uint16_t* __restrict__ g, int cs, int c1, int c2, Dims df, Dims dc,
+                            uint16_t* __restrict__ gskip, int cs1, uint16_t* __restrict__ gcoarse, int cs2) {
+  const long long Nf = df.n() * cs1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < Nf; i += (long long)gridDim.x * blockDim.x) {
+    const long long n = i / cs1;
+    const int c = (int)(i - n * cs1);
+    gskip[i] = c < c1 ? g[n * cs + c] : (uint16_t)0;
+  }
+  const long long Nc = dc.n() * cs2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < Nc; i += (long long)gridDim.x * blockDim.x) {
+    const long long m = i / cs2;
+    const int c = (int)(i - m * cs2);
+    float s = 0.f;
+    if (c < c2) {
+      int x, y, z;
+      dc.decode(m, x, y, z);
+      for (int q = 0; q < 8; ++q) s += bf2f(g[df.encode(2 * x + (q >> 2), 2 * y + ((q >> 1) & 1), 2 * z + (q & 1)) * cs + c1 + c]);
+    }
+    gcoarse[i] = f2bf(s);
+  }
+}
+
+// g *= (act > 0)  (ReLU backward, act = the layer's post-ReLU output).
+__global__ void k_relu_bwd(uint16_t* __restrict__ g, const uint16_t* __restrict__ act, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    if (!(bf2f(act[i]) > 0.f)) g[i] = 0;
+}
+
+// MSE on a crop: loss += sum (y - t/s)^2 / n (FP64 atomics); gy = 2 (y - t/s) / n as BF16 [N][cs].
+__global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, Dims src, int ox, int oy, int oz,
+                      Dims dm, const double* __restrict__ scale, int cs, uint16_t* __restrict__ gy, double* __restrict__ loss) {
+  __shared__ double part[256];
+  const long long N = dm.n();
+  const float inv = (float)(1.0 / *scale);
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    int x, yy, z;
+    dm.decode(i, x, yy, z);
+    const float e = y[i] - t[src.encode(x + ox, yy + oy, z + oz)] * inv;
+    acc += (double)e * (double)e;
+    gy[i * cs] = f2bf(2.f * e / (float)N);
+    for (int c = 1; c < cs; ++c) gy[i * cs + c] = 0;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < (int)blockDim.x; ++q) s += part[q];
+    atomicAdd(loss, s / (double)N);
+  }
+}
+
+// max |x| over a volume into *out (FP64, one block).
+__global__ void k_absmax(const float* __restrict__ x, long long n, double* __restrict__ out) {
+  __shared__ float part[1024];
+  float m = 0.f;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(x[i]));
+  part[threadIdx.x] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int q = 0; q < (int)blockDim.x; ++q) t = fmaxf(t, part[q]);
+    *out = t > 0.f ? (double)t : 1.0;
+  }
+}
+
+// rho = s * max(y, 0)
+__global__ void k_scale_relu(const float* __restrict__ y, long long n, const double* __restrict__ scale, float* __restrict__ rho) {
+  const float s = (float)*scale;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    rho[i] = s * fmaxf(y[i], 0.f);
+}
+
+// Master FP32 layer parameters (flat layout W[co][tap][cin], bias) -> BF16 GEMM
+// matrices: forward W[co_pad][kp] with k = tap*cs_in + ci, and the flipped,
+// transposed matrix of the data gradient Wt[ci_pad][kpt] with k = tap'*cs_out + co,
+// Wt[ci][tap'][co] = W[co][ntap-1-tap'][ci].
+__global__ void k_pack_layer(const float* __restrict__ p, int cin, int cout, int ks, int cs_in, int cs_out, int kp,
+                             int kpt, int rows_f, int rows_t, uint16_t* __restrict__ Wf, uint16_t* __restrict__ Wt) {
+  const int ntap = ks * ks * ks;
+  const long long nf = (long long)rows_f * kp, nt = (long long)rows_t * kpt;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nf + nt; i += (long long)gridDim.x * blockDim.x) {
+    if (i < nf) {
+      const int co = (int)(i / kp), k = (int)(i - (long long)co * kp);
+      const int tap = k / cs_in, ci = k - tap * cs_in;
+      float v = 0.f;
+      if (co < cout && tap < ntap && ci < cin) v = p[((long long)co * ntap + tap) * cin + ci];
+      Wf[i] = f2bf(v);
+    } else {
+      const long long j = i - nf;
+      const int ci = (int)(j / kpt), k = (int)(j - (long long)ci * kpt);
+      const int tp = k / cs_out, co = k - tp * cs_out;
+      float v = 0.f;
+      if (ci < cin && tp < ntap && co < cout) v = p[((long long)co * ntap + (ntap - 1 - tp)) * cin + ci];
+      Wt[j] = f2bf(v);
+    }
+  }
+}
+
+// Gradient of the padded forward GEMM matrix back to the flat layout.
+__global__ void k_unpack_wgrad(const float* __restrict__ gWf, int cin, int cout, int ks, int cs_in, int kp,
+                               float* __restrict__ gp) {
+  const int ntap = ks * ks * ks;
+  const long long n = (long long)cout * ntap * cin;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ci = (int)(i % cin);
+    const long long rest = i / cin;
+    const int tap = (int)(rest % ntap), co = (int)(rest / ntap);
+    gp[i] = gWf[(long long)co * kp + tap * cs_in + ci];
+  }
+}
+
+// Adam (Kingma & Ba 2015) on FP32 master parameters.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       long long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, long long n, float v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f64(double* __restrict__ p, long long n, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+}  // namespace net
+}  // namespace mh3d

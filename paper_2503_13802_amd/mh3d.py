@@ -96,11 +96,26 @@ def library():
     lib.mh3d_batch_destroy.restype = None
     lib.mh3d_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                                      ctypes.POINTER(SolveInfo)]
+    lib.mh3d_net_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+    lib.mh3d_net_destroy.argtypes = [vp]
+    lib.mh3d_net_destroy.restype = None
+    lib.mh3d_net_param_count.argtypes = [vp]
+    lib.mh3d_net_param_count.restype = ctypes.c_int64
+    lib.mh3d_net_params.argtypes = [vp, vp, i32]
+    lib.mh3d_net_grads.argtypes = [vp, vp]
+    lib.mh3d_net_forward.argtypes = [vp, vp, i32, i32, i32, vp]
+    lib.mh3d_net_loss_grad.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(dbl)]
+    lib.mh3d_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+    lib.mh3d_warm_start.argtypes = [vp, vp, vp, vp]
+    lib.mh3d_phantom.argtypes = [vp, ctypes.c_uint64, i32, i32, vp]
+    lib.mh3d_noisy_data.argtypes = [vp, vp, ctypes.c_uint64, dbl, dbl, vp]
     lib.mh3d_last_error.restype = ctypes.c_char_p
     lib.mh3d_version.restype = i32
     for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
                  "mh3d_power_iteration", "mh3d_solve", "mh3d_plan_export", "mh3d_profile",
-                 "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch"):
+                 "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch",
+                 "mh3d_net_create", "mh3d_net_params", "mh3d_net_grads", "mh3d_net_forward", "mh3d_net_loss_grad",
+                 "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -260,6 +275,19 @@ class Plan:
                "history": np.array(hist[:info.iters])}
         return rho, out
 
+    def phantom(self, seed, n_spheres=80, n_tubes=6):
+        """GPU phantom drawn from Philox4x32-10 (training data)."""
+        out = self.torch.empty(self.shape, device=self.device)
+        _check(library().mh3d_phantom(self._h, int(seed), int(n_spheres), int(n_tubes), _ptr(out)))
+        return out
+
+    def noisy_data(self, rho, seed, snr2_db, decay_db=3.0):
+        """d = A rho + noise at SNR_k = snr2 - decay (k - 2) dB (GPU)."""
+        rho = self._vol(rho)
+        out = self.torch.empty((self.K,) + self.small, device=self.device)
+        _check(library().mh3d_noisy_data(self._h, _ptr(rho), int(seed), float(snr2_db), float(decay_db), _ptr(out)))
+        return out
+
     def export(self, field):
         torch = self.torch
         nb = ctypes.c_size_t()
@@ -326,3 +354,71 @@ class Batch:
         out = [{"iters": i.iters, "rel_step": i.rel_step, "tau": i.tau, "lmax": i.lmax, "ms_total": i.ms_total,
                 "status": i.status} for i in infos]
         return rhos, out
+
+
+class Net:
+    """Warm-start 3D U-Net (BF16 MFMA kernels in libmh3d.so)."""
+
+    def __init__(self, widths=(8, 16, 32, 80), seed=0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.widths = tuple(int(w) for w in widths)
+        self.stream = torch.cuda.current_stream(self.device)
+        arr = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        h = ctypes.c_void_p()
+        _check(library().mh3d_net_create(len(self.widths), arr, int(seed), self.stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+        self.nparam = int(library().mh3d_net_param_count(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().mh3d_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        t = self.torch.empty(self.nparam, device=self.device)
+        _check(library().mh3d_net_params(self._h, _ptr(t), 0))
+        return t
+
+    def set_params(self, p):
+        t = self.torch.as_tensor(p, dtype=self.torch.float32, device=self.device).contiguous()
+        assert t.numel() == self.nparam
+        _check(library().mh3d_net_params(self._h, _ptr(t), 1))
+
+    def grads(self):
+        t = self.torch.empty(self.nparam, device=self.device)
+        _check(library().mh3d_net_grads(self._h, _ptr(t)))
+        return t
+
+    def forward(self, x):
+        """net(x / max|x|) (FP32)."""
+        x = self.torch.as_tensor(x, dtype=self.torch.float32, device=self.device).contiguous()
+        y = self.torch.empty_like(x)
+        _check(library().mh3d_net_forward(self._h, _ptr(x), *[int(n) for n in x.shape], _ptr(y)))
+        return y
+
+    def loss_grad(self, x, t, crop=None, want_loss=True):
+        x = self.torch.as_tensor(x, dtype=self.torch.float32, device=self.device).contiguous()
+        t = self.torch.as_tensor(t, dtype=self.torch.float32, device=self.device).contiguous()
+        c = None if crop is None else (ctypes.c_int32 * 6)(*[int(v) for v in crop])
+        loss = ctypes.c_double()
+        _check(library().mh3d_net_loss_grad(self._h, _ptr(x), _ptr(t), *[int(n) for n in x.shape], c,
+                                             ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(library().mh3d_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))
+
+    def warm_start(self, plan, d):
+        """rho_init = s * max(net(A^T d / s), 0) on the plan's grid."""
+        d = plan._port(d)
+        out = self.torch.empty(plan.shape, device=plan.device)
+        _check(library().mh3d_warm_start(plan._h, self._h, _ptr(d), _ptr(out)))
+        return out

@@ -1,0 +1,64 @@
+"""Training and use of the warm-start network (driver only: every step runs in the
+library's kernels -- phantoms, forward model, noise, back-projection, network
+forward/backward and Adam)."""
+import time
+
+import numpy as np
+
+from . import mh3d
+
+
+def sample_snr2(seed, lo=20.0, hi=40.0):
+    """SNR of the 2nd harmonic for training sample `seed` (3 dB/harmonic decay after)."""
+    return float(np.random.default_rng([seed, 3]).uniform(lo, hi))
+
+
+def crop_origin(seed, shape, crop):
+    rng = np.random.default_rng([seed, 4])
+    return [int(rng.integers(0, n - c + 1)) for n, c in zip(shape, crop)]
+
+
+def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spheres=80, n_tubes=6,
+          snr=(20.0, 40.0), decay_db=3.0, log=None, log_every=100):
+    """Trains `net` on `steps` phantom/portrait pairs generated on the GPU from the
+    plan's forward model (sample j uses seed seed0 + j).  Returns the loss history
+    (every log_every steps)."""
+    hist = []
+    t0 = time.perf_counter()
+    for j in range(steps):
+        seed = seed0 + j
+        rho = plan.phantom(seed, n_spheres, n_tubes)
+        d = plan.noisy_data(rho, seed, sample_snr2(seed, *snr), decay_db)
+        x = plan.adjoint(d)
+        o = crop_origin(seed, plan.shape, crop)
+        want = (j % log_every == 0) or (j == steps - 1)
+        loss = net.loss_grad(x, rho, list(o) + list(crop), want_loss=want)
+        net.adam_step(lr)
+        if want:
+            hist.append((j, loss))
+            if log:
+                log("train step %d/%d loss %.4e (%.1f s)" % (j, steps, loss, time.perf_counter() - t0))
+    return hist
+
+
+def compare(plan, net, seeds, tol=1e-4, max_iter=5000, n_spheres=80, n_tubes=6, snr=(20.0, 40.0), decay_db=3.0):
+    """Cold vs warm-started solves on held-out samples; both refined to the same
+    r_k <= tol.  Returns per-sample dicts."""
+    torch = plan.torch
+    out = []
+    for seed in seeds:
+        rho = plan.phantom(seed, n_spheres, n_tubes)
+        d = plan.noisy_data(rho, seed, sample_snr2(seed, *snr), decay_db)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cold, ic = plan.solve(d, max_iter=max_iter, tol=tol, tau=0.0)
+        torch.cuda.synchronize()
+        t_cold = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        init = net.warm_start(plan, d)
+        warm, iw = plan.solve(d, rho0=init, max_iter=max_iter, tol=tol, tau=0.0)
+        torch.cuda.synchronize()
+        t_warm = time.perf_counter() - t0
+        out.append({"seed": seed, "cold_iters": ic["iters"], "warm_iters": iw["iters"], "cold_s": t_cold,
+                    "warm_s": t_warm, "cold": cold, "warm": warm, "init": init, "truth": rho, "d": d})
+    return out

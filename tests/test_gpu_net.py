@@ -1,0 +1,165 @@
+"""GPU warm-start network: BF16 MFMA layers and gradients against the FP64
+reference network, the GPU training-data generator against a CPU twin on the same
+Philox4x32-10 stream, and the gain of a briefly trained network over a cold start
+at equal tolerance."""
+import numpy as np
+import pytest
+
+from oracle import philox as oph
+from oracle import unet
+from gpu_util import announce, rel_l2, torch_cuda
+
+pytestmark = pytest.mark.gpu
+WIDTHS = (4, 8, 8, 16)
+
+
+def _setup(seed=0, shape=(16, 16, 16), widths=WIDTHS):
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    net = mh3d.Net(widths, seed=seed)
+    rng = np.random.default_rng(seed)
+    flat = np.zeros(net.nparam)
+    lay, total = unet.param_layout(widths)
+    assert total == net.nparam
+    for name, cin, cout, k, wo, bo in lay:      # He-normal weights, small biases
+        flat[wo:bo] = rng.standard_normal(bo - wo) * np.sqrt(2.0 / (cin * k ** 3))
+        flat[bo:bo + cout] = rng.standard_normal(cout) * 0.05
+    net.set_params(torch.tensor(flat, dtype=torch.float32))
+    x = rng.standard_normal(shape)
+    t = rng.standard_normal(shape)
+    return torch, net, flat, x, t
+
+
+def test_net_forward_matches_fp64_reference():
+    torch, net, flat, x, t = _setup(1)
+    announce("net forward")
+    y = net.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
+    s = np.max(np.abs(x.astype(np.float32)))
+    want = unet.forward(unet.unpack(flat.astype(np.float32).astype(np.float64), WIDTHS), x / s, WIDTHS).numpy()
+    err = rel_l2(y, want)
+    print("forward rel err %.3e" % err, flush=True)
+    assert err <= 3e-2
+
+
+# BF16 activations and gradients: every rounding is ~2^-9 relative, and the ReLU
+# masks of the two sides differ where a pre-activation is within rounding of zero.
+# The weight gradient of a layer is a sum over all voxels with heavy cancellation,
+# so its relative error grows with the number of layers the gradient has crossed.
+# A structural mistake (a wrong tap, channel or transpose) gives errors near 1.
+@pytest.mark.parametrize("widths,shape,layer_tol", [((4, 8), (16, 16, 16), 5e-2),
+                                                    ((4, 8, 8, 16), (32, 32, 32), 0.2)])
+def test_net_gradients_match_fp64_reference(widths, shape, layer_tol):
+    torch, net, flat, x, t = _setup(2, shape=shape, widths=widths)
+    announce("net gradients %s" % (widths,))
+    loss = net.loss_grad(torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32))
+    g = net.grads().cpu().numpy()
+    s = np.max(np.abs(x.astype(np.float32)))
+    want_loss, want_g, _ = unet.loss_and_grads(flat.astype(np.float32).astype(np.float64), x / s, t / s, widths)
+    lay, _ = unet.param_layout(widths)
+    errs = {name: (rel_l2(g[wo:bo], want_g[wo:bo]), rel_l2(g[bo:bo + cout], want_g[bo:bo + cout]))
+            for name, cin, cout, k, wo, bo in lay}
+    print("loss %.6e vs %.6e; total grad rel err %.3e; per layer (W, b): %s"
+          % (loss, want_loss, rel_l2(g, want_g), {k: "%.3f/%.3f" % v for k, v in errs.items()}), flush=True)
+    assert loss == pytest.approx(want_loss, rel=2e-2)
+    assert rel_l2(g, want_g) <= 5e-2
+    cos = float(np.dot(g, want_g) / (np.linalg.norm(g) * np.linalg.norm(want_g)))
+    assert cos >= 0.998
+    for name, (ew, eb) in errs.items():
+        assert ew <= layer_tol, name
+        assert eb <= 2 * layer_tol, name
+
+
+def test_net_crop_uses_whole_volume_scale():
+    torch, net, flat, x, t = _setup(3, shape=(32, 16, 16))
+    announce("net crop")
+    crop = [8, 0, 0, 16, 16, 16]
+    loss = net.loss_grad(torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32), crop)
+    s = np.max(np.abs(x.astype(np.float32)))
+    xc, tc = x[8:24] / s, t[8:24] / s
+    want_loss, want_g, _ = unet.loss_and_grads(flat.astype(np.float32).astype(np.float64), xc, tc, WIDTHS)
+    assert loss == pytest.approx(want_loss, rel=3e-2)
+    assert rel_l2(net.grads().cpu().numpy(), want_g) <= 5e-2
+
+
+def _twin_phantom(shape, vox, seed, nsph, ntube):
+    """CPU twin of the device phantom generator (same Philox stream and geometry)."""
+    ext = [(n - 1) * vox for n in shape]
+    key = (seed & 0xffffffff, seed >> 32)
+
+    def u(obj, q):
+        w = oph.philox4x32(np.array([q >> 2, obj, 0, 0], dtype=np.uint64), key)
+        return (float(w[q & 3]) + 0.5) / 4294967296.0
+
+    ax = [np.arange(n) * vox for n in shape]
+    X, Y, Z = np.meshgrid(*ax, indexing="ij")
+    out = np.zeros(shape)
+    for i in range(nsph + ntube):
+        if i < nsph:
+            r = 2.0 + 3.0 * u(i, 0)
+            c = [r + (ext[a] - 2 * r) * u(i, 1 + a) for a in range(3)]
+            conc = 10.0 ** (-2.0 + 2.0 * u(i, 4))
+            out += conc * (((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) <= r * r)
+        else:
+            r = 1.0 + 1.5 * u(i, 0)
+            pts = np.array([3.0 + (ext[q % 3] - 6.0) * u(i, 1 + q) for q in range(9)]).reshape(3, 3)
+            conc = 10.0 ** (-2.0 + 2.0 * u(i, 10))
+            t = np.arange(257)[:, None] / 256.0
+            curve = (1 - t) ** 2 * pts[0] + 2 * (1 - t) * t * pts[1] + t ** 2 * pts[2]
+            P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], -1)
+            best = np.full(len(P), np.inf)
+            for s in range(len(curve)):
+                best = np.minimum(best, np.sum((P - curve[s]) ** 2, axis=1))
+            out += conc * (best <= r * r).reshape(shape)
+    return out
+
+
+def test_gpu_phantom_matches_cpu_twin_and_noise_hits_snr():
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("phantom twin")
+    shape = (24, 16, 12)
+    p = mh3d.Plan(shape, (2, 3, 4), 1.2, (2, 2, 2), 10.0, 1e-3)
+    got = p.phantom(12345, 5, 2).cpu().numpy()
+    want = _twin_phantom(shape, 1.0, 12345, 5, 2)
+    mism = np.abs(got - want) > 1e-5 * max(1.0, np.max(np.abs(want)))
+    assert mism.mean() <= 1e-3 and np.max(np.abs(got - want)) <= 1.0 + 1e-6
+    assert got.max() > 0
+    # noise: empirical SNR per harmonic
+    rho = p.phantom(7, 8, 1)
+    clean = p.forward(rho).cpu().numpy().astype(np.float64)
+    d = p.noisy_data(rho, 7, 30.0, 3.0).cpu().numpy().astype(np.float64)
+    for i, k in enumerate((2, 3, 4)):
+        noise = d[i] - clean[i]
+        snr = 10 * np.log10(np.mean(clean[i] ** 2) / np.mean(noise ** 2))
+        assert snr == pytest.approx(30.0 - 3.0 * (k - 2), abs=0.5)
+
+
+def test_trained_network_saves_iterations():
+    """A network trained for a few hundred GPU-generated samples starts the solver
+    closer to the solution: fewer updates to the same stopping tolerance, and an end
+    point no farther from the minimiser than the cold start's."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d, warmstart
+    announce("warm-start gain")
+    shape, harm = (32, 32, 32), (2, 3, 4, 5)
+    p = mh3d.Plan(shape, harm, 1.2, (2, 2, 2), 20.0, 1e-3)
+    net = mh3d.Net((8, 16, 16, 32), seed=11)
+    hist = warmstart.train(p, net, 300, seed0=5_000_000, crop=shape, lr=2e-3, n_spheres=6, n_tubes=1,
+                           log_every=50)
+    assert hist[-1][1] < hist[0][1]
+    res = warmstart.compare(p, net, [6_000_000 + j for j in range(4)], tol=1e-4, n_spheres=6, n_tubes=1)
+    cold = np.mean([r["cold_iters"] for r in res])
+    warm = np.mean([r["warm_iters"] for r in res])
+    errs = []
+    for r in res:
+        ref, info = p.solve(r["d"], max_iter=20000, tol=1e-7, tau=0.0)
+        assert info["rel_step"] <= 1e-7
+        ref = ref.cpu().numpy()
+        errs.append((rel_l2(r["cold"].cpu().numpy(), ref), rel_l2(r["warm"].cpu().numpy(), ref),
+                     rel_l2(r["init"].cpu().numpy(), ref)))
+    print("updates cold %.1f warm %.1f; distance to the minimiser (cold, warm, init): %s"
+          % (cold, warm, ["%.3e/%.3e/%.3e" % e for e in errs]), flush=True)
+    assert warm < cold
+    for ec, ew, ei in errs:
+        assert ei < 1.0          # the initialiser is closer than rho = 0
+        assert ew <= 2.0 * ec + 1e-3
