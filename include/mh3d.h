@@ -118,6 +118,11 @@ mh3d_status mh3d_forward(mh3d_plan_t plan, const float* rho, float* d);
 /* rho = A^T d (adjoint of eq. dN).  d: portraits, rho: volume. */
 mh3d_status mh3d_adjoint(mh3d_plan_t plan, const float* d, float* rho);
 
+/* Per-harmonic back-projections c_k = b (H_k^T P^T d_k), the terms of A^T d before
+ * the sum over harmonics (adjoint of eq. dN, one harmonic at a time); sum_k c_k =
+ * A^T d.  d: portraits, c: DEVICE [n_harm][nx][ny][nz]. */
+mh3d_status mh3d_backproject(mh3d_plan_t plan, const float* d, float* c);
+
 /* out = (A^T A + lambda T^T T) x, the normal operator of Sec. 4.3's stacked M. */
 mh3d_status mh3d_normal(mh3d_plan_t plan, const float* x, float* out);
 
@@ -152,9 +157,10 @@ mh3d_status mh3d_solve_batch(mh3d_batch_t batch, const float* const* d, float* c
                              const mh3d_solve_opts* opts, mh3d_solve_info* infos);
 
 /* ---------------------------------------------------------------------------
- * Learned warm start (not in the paper): a 3D U-Net that maps the back-projection
- * A^T d to an initial density for mh3d_solve, which then refines it to the same
- * tolerance as a cold start (Sec. 4.3 solver unchanged).  BF16 weights and
+ * Learned warm start (not in the paper): a 3D U-Net that maps the per-harmonic
+ * back-projections c_k (mh3d_backproject) to an initial density for mh3d_solve,
+ * which then refines it to the same tolerance as a cold start (Sec. 4.3 solver
+ * unchanged).  BF16 weights and
  * activations, FP32 accumulation on MFMA, FP32 master weights and Adam.
  * Network: levels L, widths w_0..w_{L-1}; encoder level l = two 3x3x3 conv + ReLU,
  * 2x2x2 average pooling between levels; decoder level l = nearest 2x upsampling,
@@ -162,27 +168,31 @@ mh3d_status mh3d_solve_batch(mh3d_batch_t batch, const float* const* d, float* c
  * 1x1x1 conv to one channel.  Flat FP32 parameter layout: for each layer (enc0a,
  * enc0b, ..., enc(L-1)b, dec(L-2)a, dec(L-2)b, ..., dec0b, head) the weights as
  * [Cout][tap][Cin] (tap = (dx+1)*9 + (dy+1)*3 + (dz+1)) then the bias [Cout].
- * Inputs are scaled by s = max |x|: the network sees x/s (and targets t/s).
- * Grids must be powers of two, at least 2^L per axis. */
+ * Inputs x have C channels, channel-major [C][nx][ny][nz] (C = n_harm for the warm
+ * start).  They are scaled by s = max_i |sum_c x[c][i]| (= max |A^T d| for the
+ * back-projections): the network sees x/s (and targets t/s).  Grids must be powers
+ * of two, at least 2^L per axis.  Calls on one network must not overlap. */
 typedef struct mh3d_net_s* mh3d_net_t;
 /* He-normal weights from Philox4x32-10 (key seed, stream = layer index), zero biases. */
-mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, uint64_t seed, void* stream, mh3d_net_t* out);
+mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, int32_t in_channels, uint64_t seed, void* stream,
+                            mh3d_net_t* out);
 void mh3d_net_destroy(mh3d_net_t net);
 int64_t mh3d_net_param_count(mh3d_net_t net);
 /* Copy the FP32 master parameters to (set = 0) or from (set = 1) a DEVICE buffer. */
 mh3d_status mh3d_net_params(mh3d_net_t net, float* params, int32_t set);
 /* Copy the gradient of the last mh3d_net_loss_grad to a DEVICE buffer. */
 mh3d_status mh3d_net_grads(mh3d_net_t net, float* grads);
-/* y = net(x / max|x|) on an nx*ny*nz DEVICE volume (FP32 in and out). */
+/* y = net(x / s) for DEVICE x [C][nx][ny][nz] (FP32), y [nx][ny][nz] (FP32). */
 mh3d_status mh3d_net_forward(mh3d_net_t net, const float* x, int32_t nx, int32_t ny, int32_t nz, float* y);
-/* Loss mean((net(x/s) - t/s)^2) over a crop (HOST int[6] = offset xyz, size xyz;
+/* Loss mean((net(x/s) - t/s)^2), t [nx][ny][nz], over a crop (HOST int[6] = offset xyz, size xyz;
  * NULL = whole volume; s over the whole volume) and its gradient (kept in the
  * network).  *loss (HOST, may be NULL) receives the loss; synchronous if given. */
 mh3d_status mh3d_net_loss_grad(mh3d_net_t net, const float* x, const float* t, int32_t nx, int32_t ny, int32_t nz,
                                const int32_t* crop, double* loss);
 /* One Adam step (Kingma & Ba) on the last gradient. */
 mh3d_status mh3d_net_adam_step(mh3d_net_t net, float lr, float beta1, float beta2, float eps);
-/* rho_init = s * max(net(A^T d / s), 0), s = max |A^T d|.  plan and net share a stream. */
+/* rho_init = s * max(net(c / s), 0), c = mh3d_backproject(d), s = max |A^T d|.  The
+ * network has n_harm input channels; plan and net share a stream. */
 mh3d_status mh3d_warm_start(mh3d_plan_t plan, mh3d_net_t net, const float* d, float* rho_init);
 
 /* Training data on the GPU.  mh3d_phantom: n_spheres spheres (radius U(2,5) mm)

@@ -75,11 +75,13 @@ def pack_grads(grads, widths, in_ch=1):
 
 
 def forward(params, x, widths):
-    """x: [X, Y, Z] (or torch [1, Cin, X, Y, Z]) -> output [X, Y, Z], all float64."""
+    """x: [X, Y, Z] or [Cin, X, Y, Z] -> output [X, Y, Z], all float64."""
     L = len(widths)
     h = torch.as_tensor(x, dtype=torch.float64)
     if h.dim() == 3:
         h = h[None, None]
+    elif h.dim() == 4:
+        h = h[None]
 
     def conv(name, t, relu=True):
         W, b = params[name]
@@ -101,8 +103,10 @@ def forward(params, x, widths):
 
 
 def loss_and_grads(flat, x, target, widths):
-    """MSE loss mean((net(x) - t)^2) and its gradient in the flat layout."""
-    params = unpack(flat, widths)
+    """MSE loss mean((net(x) - t)^2) and its gradient in the flat layout
+    (x: [X, Y, Z] or [Cin, X, Y, Z]; t: [X, Y, Z])."""
+    in_ch = 1 if np.ndim(x) == 3 else np.shape(x)[0]
+    params = unpack(flat, widths, in_ch)
     leaves = {}
     for k, (W, b) in params.items():
         W = W.clone().requires_grad_(True)
@@ -113,7 +117,7 @@ def loss_and_grads(flat, x, target, widths):
     loss = torch.mean((y - t) ** 2)
     loss.backward()
     grads = {k: (W.grad, b.grad) for k, (W, b) in leaves.items()}
-    return float(loss), pack_grads(grads, widths), y.detach().numpy()
+    return float(loss.detach()), pack_grads(grads, widths, in_ch), y.detach().numpy()
 
 
 def conv3d_direct(x, W, b):

@@ -207,6 +207,7 @@ struct mh3d_plan_s {
   DevState* st = nullptr;      // solver / power state
   VolDesc vdh;                 // host copy of the descriptor
   VolDesc* vdd = nullptr;      // device descriptor
+  VolDesc* vdk = nullptr;      // device descriptors of the single harmonics (K of them)
   size_t bytes = 0;
   // captured solver chunk
   hipGraph_t graph = nullptr;
@@ -318,32 +319,35 @@ static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
 }
 
 template <int HC, int E>
-static void class_fwd_t(mh3d_plan_t p, int chk) {
-  k_class_fwd<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vdd, chk);
+static void class_fwd_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
+  k_class_fwd<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
 }
 template <int HC, int E>
-static void class_adj_t(mh3d_plan_t p, int chk) {
-  k_class_adj<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vdd, chk);
+static void class_adj_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
+  k_class_adj<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
 }
 
 #define E_DISPATCH(HCV, FN)                       \
   switch (p->g.E) {                               \
-    case 9: FN<HCV, 9>(p, chk); break;            \
-    case 8: FN<HCV, 8>(p, chk); break;            \
-    case 6: FN<HCV, 6>(p, chk); break;            \
-    case 4: FN<HCV, 4>(p, chk); break;            \
-    case 3: FN<HCV, 3>(p, chk); break;            \
-    case 2: FN<HCV, 2>(p, chk); break;            \
-    default: FN<HCV, 1>(p, chk); break;           \
+    case 9: FN<HCV, 9>(p, chk, vd); break;            \
+    case 8: FN<HCV, 8>(p, chk, vd); break;            \
+    case 6: FN<HCV, 6>(p, chk, vd); break;            \
+    case 4: FN<HCV, 4>(p, chk, vd); break;            \
+    case 3: FN<HCV, 3>(p, chk, vd); break;            \
+    case 2: FN<HCV, 2>(p, chk, vd); break;            \
+    default: FN<HCV, 1>(p, chk, vd); break;           \
   }
 
 static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk) {
   Timer t(p, KID_CLASS_FWD);
+  const VolDesc* vd = p->vdd;
   if (p->compact) { E_DISPATCH(0, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
   return last_launch("k_class_fwd");
 }
-static mh3d_status launch_class_adj(mh3d_plan_t p, int chk) {
+// vd: a single-harmonic descriptor (per-harmonic back-projection) or NULL for the plan's.
+static mh3d_status launch_class_adj(mh3d_plan_t p, int chk, const VolDesc* vd = nullptr) {
   Timer t(p, KID_CLASS_ADJ);
+  if (!vd) vd = p->vdd;
   if (p->compact) { E_DISPATCH(0, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
   return last_launch("k_class_adj");
 }
@@ -366,17 +370,19 @@ static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r) {
   return last_launch("k_small_fwd");
 }
 
-static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const float* yin) {
+static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const float* yin,
+                                    const VolDesc* vd = nullptr) {
   Timer t(p, KID_PLANE_ADJ);
+  if (!vd) vd = p->vdd;
   dim3 grid(p->g.nx), block(p->L.T_plane);
   const size_t lds = p->L.lds_plane;
   AdjOut ao;
   ao.out = o;
   ao.yin = yin;
   switch (out) {
-    case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, ao); break;
-    case OUT_NORMAL: k_plane_adj<OUT_NORMAL><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, ao); break;
-    default: k_plane_adj<OUT_FISTA><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, ao); break;
+    case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
+    case OUT_NORMAL: k_plane_adj<OUT_NORMAL><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
+    default: k_plane_adj<OUT_FISTA><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
   }
   return last_launch("k_plane_adj");
 }
@@ -477,7 +483,7 @@ extern "C" void mh3d_destroy(mh3d_plan_t p) {
   for (auto& e : p->pending) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
   for (auto e : p->free_events) (void)hipEventDestroy(e);
   void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3],
-                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st, p->vdd, p->hist};
+                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st, p->vdd, p->vdk, p->hist};
   for (void* q : bufs)
     if (q) (void)hipFree(q);
   delete p;
@@ -509,6 +515,24 @@ static void fill_desc(mh3d_plan_t p) {
   v.reg_kind = p->desc.reg_kind;
   v.lam = (float)p->desc.lambda;
   v.T_class = p->L.T_class;
+}
+
+// Descriptor of harmonic k alone: the same buffers with K = 1, the spectra and the
+// decimated adjoint spectra offset to harmonic k.  The adjoint passes run with it
+// give the harmonic's back-projection b (H_k^T P^T d_k) without the sum over k.
+static mh3d_status upload_harmonic_descs(mh3d_plan_t p) {
+  const Geo& g = p->g;
+  std::vector<VolDesc> h(g.K, p->vdh);
+  const size_t esz = p->compact ? sizeof(float) : sizeof(float2);
+  for (int k = 0; k < g.K; ++k) {
+    h[k].g.K = 1;
+    h[k].hs = (const char*)p->vdh.hs + (size_t)k * g.hsz * esz;
+    h[k].Gp = p->vdh.Gp + (size_t)k * g.mx * g.ncls;
+    h[k].imag_mask = (p->vdh.imag_mask >> k) & 1u;
+  }
+  HIPCHK(hipMemcpyAsync(p->vdk, h.data(), sizeof(VolDesc) * g.K, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return MH3D_OK;
 }
 
 extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
@@ -546,6 +570,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = dalloc(p, (void**)&p->partials, sizeof(double) * 4 * 1024)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->st, sizeof(DevState))) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->vdd, sizeof(VolDesc))) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->vdk, sizeof(VolDesc) * g.K)) != MH3D_OK) return bail(s);
   if ((s = build_tables(p)) != MH3D_OK) return bail(s);
   fill_desc(p);
   if ((s = upload_desc(p)) != MH3D_OK) return bail(s);
@@ -565,6 +590,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if (s != MH3D_OK) return bail(s);
   fill_desc(p);   // imag_mask is known now
   if ((s = upload_desc(p)) != MH3D_OK) return bail(s);
+  if ((s = upload_harmonic_descs(p)) != MH3D_OK) return bail(s);
   if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(fail(MH3D_ERR_HIP, "plan build failed on the device"));
   *out = p;
   return MH3D_OK;
@@ -591,6 +617,17 @@ extern "C" mh3d_status mh3d_adjoint(mh3d_plan_t p, const float* d, float* rho) {
   CHK(launch_small_fwd(p, d));
   CHK(launch_class_adj(p, 0));
   CHK(launch_plane_adj(p, OUT_SCALE_B, rho, nullptr));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_backproject(mh3d_plan_t p, const float* d, float* c) {
+  CHK(check_plan(p));
+  if (!c || !d) return fail(MH3D_ERR_INVALID, "NULL array");
+  CHK(launch_small_fwd(p, d));
+  for (int k = 0; k < p->g.K; ++k) {
+    CHK(launch_class_adj(p, 0, p->vdk + k));
+    CHK(launch_plane_adj(p, OUT_SCALE_B, c + (size_t)k * p->g.N, nullptr, p->vdk + k));
+  }
   return MH3D_OK;
 }
 

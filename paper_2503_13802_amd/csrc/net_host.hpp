@@ -38,6 +38,7 @@ struct NetWork {
   std::vector<uint16_t*> cat, da, db;     // decoder concat input, conv a, conv b outputs
   std::vector<uint16_t*> g1, g2, g3, gs;  // gradient scratch per level (max channel stride) and skip grads
   float* y = nullptr;                     // head output FP32 [N0]
+  float* xin = nullptr;                   // warm start: per-harmonic back-projections [C][N0] (lazy)
   uint16_t* gy = nullptr;                 // head output gradient [N0][4]
   double* scale = nullptr;                // max |x| of the current input
   double* loss = nullptr;
@@ -47,6 +48,7 @@ struct NetWork {
 
 struct mh3d_net_s {
   std::vector<int> widths;
+  int in_ch = 1;
   std::vector<NetLayer> layers;
   long long nparam = 0;
   float* p = nullptr;        // FP32 master parameters (flat layout of oracle/unet.py)
@@ -105,7 +107,7 @@ mh3d_status net_work(mh3d_net_t n, int nx, int ny, int nz, NetWork** out) {
     *p = (uint16_t*)q;
     return MH3D_OK;
   };
-  CHK(mk(nvox(0) * 4, &w.x0));
+  CHK(mk(nvox(0) * round4(n->in_ch), &w.x0));
   w.ea.resize(L); w.es.resize(L); w.pl.resize(L); w.cat.resize(L); w.da.resize(L); w.db.resize(L);
   w.g1.resize(L); w.g2.resize(L); w.g3.resize(L); w.gs.resize(L);
   int cmax_all = 4;
@@ -175,10 +177,11 @@ mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
 mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long long nsrc, int ox, int oy, int oz) {
   const int L = (int)n->widths.size();
   if (!n->packed) CHK(net_pack(n));
-  k_absmax<<<1, 1024, 0, n->stream>>>(x, nsrc, w->scale);
+  k_absmax<<<1, 1024, 0, n->stream>>>(x, nsrc, n->in_ch, w->scale);
   CHK(last_launch("k_absmax"));
   Dims d0 = dims_of(*w, 0);
-  k_to_bf16_crop<<<grid_for(d0.n()), 256, 0, n->stream>>>(x, src, ox, oy, oz, d0, w->scale, 4, w->x0);
+  k_to_bf16_crop<<<grid_for(d0.n()), 256, 0, n->stream>>>(x, n->in_ch, src, ox, oy, oz, d0, w->scale,
+                                                          round4(n->in_ch), w->x0);
   CHK(last_launch("k_to_bf16_crop"));
   const uint16_t* h = w->x0;
   for (int l = 0; l < L; ++l) {
@@ -304,11 +307,12 @@ __global__ void k_net_init(float* __restrict__ p, long long wo, long long nw, in
 }  // namespace
 
 // ============================================================================ network ABI
-extern "C" mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, uint64_t seed, void* stream,
-                                       mh3d_net_t* out) {
+extern "C" mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, int32_t in_channels, uint64_t seed,
+                                       void* stream, mh3d_net_t* out) {
   if (!out) return fail(MH3D_ERR_INVALID, "out is NULL");
   *out = nullptr;
   if (levels < 2 || levels > 6 || !widths) return fail(MH3D_ERR_INVALID, "levels must be in [2, 6]");
+  if (in_channels < 1 || in_channels > 32) return fail(MH3D_ERR_INVALID, "in_channels must be in [1, 32]");
   for (int l = 0; l < levels; ++l)
     if (widths[l] < 1 || widths[l] > 16 * NT_MAX) return fail(MH3D_ERR_INVALID, "width %d out of range", widths[l]);
   // the data gradient of a decoder's first convolution has widths[l] + widths[l+1]
@@ -317,12 +321,13 @@ extern "C" mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, ui
     if (widths[l] + widths[l + 1] > 16 * NT_MAX) return fail(MH3D_ERR_INVALID, "concat width too large");
   mh3d_net_t n = new mh3d_net_s();
   n->widths.assign(widths, widths + levels);
+  n->in_ch = in_channels;
   n->stream = reinterpret_cast<hipStream_t>(stream);
   const int L = levels;
   // layer list in the flat parameter order
   struct Spec { int cin, cout, ks; };
   std::vector<Spec> specs;
-  int cin = 1;
+  int cin = in_channels;
   for (int l = 0; l < L; ++l) {
     specs.push_back({cin, widths[l], 3});
     specs.push_back({widths[l], widths[l], 3});
@@ -386,6 +391,7 @@ extern "C" void mh3d_net_destroy(mh3d_net_t n) {
     for (auto* b : kv.second.bufs) (void)hipFree(b);
     if (kv.second.y) (void)hipFree(kv.second.y);
     if (kv.second.scale) (void)hipFree(kv.second.scale);
+    if (kv.second.xin) (void)hipFree(kv.second.xin);
   }
   for (auto& ly : n->layers) {
     if (ly.Wf) (void)hipFree(ly.Wf);
@@ -483,14 +489,14 @@ extern "C" mh3d_status mh3d_warm_start(mh3d_plan_t p, mh3d_net_t n, const float*
   const Geo& g = p->g;
   CHK(net_check_dims(n, g.nx, g.ny, g.nz));
   if (n->stream != p->stream) return fail(MH3D_ERR_INVALID, "network and plan must share a stream");
-  // back-projection A^T d into the plan's scratch volume
-  CHK(launch_small_fwd(p, d));
-  CHK(launch_class_adj(p, 0));
-  CHK(launch_plane_adj(p, OUT_SCALE_B, p->vol[3], nullptr));
+  if (n->in_ch != g.K) return fail(MH3D_ERR_INVALID, "network has %d input channels, plan %d harmonics", n->in_ch, g.K);
   NetWork* w;
   CHK(net_work(n, g.nx, g.ny, g.nz, &w));
+  if (!w->xin) CHK(net_alloc((void**)&w->xin, sizeof(float) * (size_t)g.K * g.N));
+  // per-harmonic back-projections c_k = b (H_k^T P^T d_k), the network's channels
+  CHK(mh3d_backproject(p, d, w->xin));
   Dims src{ilog2(g.nx), ilog2(g.ny), ilog2(g.nz)};
-  CHK(net_forward(n, w, p->vol[3], src, g.N, 0, 0, 0));
+  CHK(net_forward(n, w, w->xin, src, g.N, 0, 0, 0));
   k_scale_relu<<<grid_for(g.N), 256, 0, p->stream>>>(w->y, g.N, w->scale, rho_init);
   CHK(last_launch("k_scale_relu"));
   return MH3D_OK;

@@ -186,17 +186,17 @@ __global__ void k_bias_grad(const uint16_t* __restrict__ gout, long long N, int 
   }
 }
 
-// FP32 volume / scale -> BF16 [N][cs] channel 0 (crop window (o, c) of the source).
-__global__ void k_to_bf16_crop(const float* __restrict__ x, Dims src, int ox, int oy, int oz, Dims dst,
+// FP32 channel-major volumes [C][src] / scale -> BF16 channels-last [N][cs] (crop
+// window (o, dst) of the source; channels C..cs-1 zero).
+__global__ void k_to_bf16_crop(const float* __restrict__ x, int C, Dims src, int ox, int oy, int oz, Dims dst,
                                const double* __restrict__ scale, int cs, uint16_t* __restrict__ out) {
-  const long long N = dst.n();
+  const long long N = dst.n(), ns = src.n();
   const float inv = (float)(1.0 / *scale);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
     int x0, y0, z0;
     dst.decode(i, x0, y0, z0);
-    const float v = x[src.encode(x0 + ox, y0 + oy, z0 + oz)] * inv;
-    out[i * cs] = f2bf(v);
-    for (int c = 1; c < cs; ++c) out[i * cs + c] = 0;
+    const long long j = src.encode(x0 + ox, y0 + oy, z0 + oz);
+    for (int c = 0; c < cs; ++c) out[i * cs + c] = c < C ? f2bf(x[c * ns + j] * inv) : (uint16_t)0;
   }
 }
 
@@ -298,11 +298,16 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
   }
 }
 
-// max |x| over a volume into *out (FP64, one block).
-__global__ void k_absmax(const float* __restrict__ x, long long n, double* __restrict__ out) {
+// max_i |sum_c x[c][i]| over C channel-major volumes of n voxels into *out (FP64,
+// one block; 1 if the maximum is 0).
+__global__ void k_absmax(const float* __restrict__ x, long long n, int C, double* __restrict__ out) {
   __shared__ float part[1024];
   float m = 0.f;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(x[i]));
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    float v = 0.f;
+    for (int c = 0; c < C; ++c) v += x[c * n + i];
+    m = fmaxf(m, fabsf(v));
+  }
   part[threadIdx.x] = m;
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -96,7 +96,9 @@ def library():
     lib.mh3d_batch_destroy.restype = None
     lib.mh3d_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                                      ctypes.POINTER(SolveInfo)]
-    lib.mh3d_net_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+    lib.mh3d_net_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), i32, ctypes.c_uint64, vp,
+                                    ctypes.POINTER(vp)]
+    lib.mh3d_backproject.argtypes = [vp, vp, vp]
     lib.mh3d_net_destroy.argtypes = [vp]
     lib.mh3d_net_destroy.restype = None
     lib.mh3d_net_param_count.argtypes = [vp]
@@ -115,7 +117,7 @@ def library():
                  "mh3d_power_iteration", "mh3d_solve", "mh3d_plan_export", "mh3d_profile",
                  "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch",
                  "mh3d_net_create", "mh3d_net_params", "mh3d_net_grads", "mh3d_net_forward", "mh3d_net_loss_grad",
-                 "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data"):
+                 "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data", "mh3d_backproject"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -275,6 +277,13 @@ class Plan:
                "history": np.array(hist[:info.iters])}
         return rho, out
 
+    def backproject(self, d, out=None):
+        """Per-harmonic back-projections c_k = b (H_k^T P^T d_k), [K][X][Y][Z]."""
+        d = self._port(d)
+        out = self.torch.empty((self.K,) + self.shape, device=self.device) if out is None else out
+        _check(library().mh3d_backproject(self._h, _ptr(d), _ptr(out)))
+        return out
+
     def phantom(self, seed, n_spheres=80, n_tubes=6):
         """GPU phantom drawn from Philox4x32-10 (training data)."""
         out = self.torch.empty(self.shape, device=self.device)
@@ -359,15 +368,17 @@ class Batch:
 class Net:
     """Warm-start 3D U-Net (BF16 MFMA kernels in libmh3d.so)."""
 
-    def __init__(self, widths=(8, 16, 32, 80), seed=0, device="cuda"):
+    def __init__(self, widths=(8, 16, 32, 80), in_channels=1, seed=0, device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.widths = tuple(int(w) for w in widths)
+        self.in_channels = int(in_channels)
         self.stream = torch.cuda.current_stream(self.device)
         arr = (ctypes.c_int32 * len(self.widths))(*self.widths)
         h = ctypes.c_void_p()
-        _check(library().mh3d_net_create(len(self.widths), arr, int(seed), self.stream.cuda_stream, ctypes.byref(h)))
+        _check(library().mh3d_net_create(len(self.widths), arr, self.in_channels, int(seed), self.stream.cuda_stream,
+                                         ctypes.byref(h)))
         self._h = h
         self.nparam = int(library().mh3d_net_param_count(h))
 
@@ -397,19 +408,27 @@ class Net:
         _check(library().mh3d_net_grads(self._h, _ptr(t)))
         return t
 
-    def forward(self, x):
-        """net(x / max|x|) (FP32)."""
+    def _input(self, x):
         x = self.torch.as_tensor(x, dtype=self.torch.float32, device=self.device).contiguous()
-        y = self.torch.empty_like(x)
-        _check(library().mh3d_net_forward(self._h, _ptr(x), *[int(n) for n in x.shape], _ptr(y)))
+        if x.dim() == 3:
+            x = x[None]
+        assert x.dim() == 4 and x.shape[0] == self.in_channels, (tuple(x.shape), self.in_channels)
+        return x
+
+    def forward(self, x):
+        """net(x / s), s = max |sum_c x[c]| (FP32); x [C][X][Y][Z] (or [X][Y][Z] if C = 1)."""
+        x = self._input(x)
+        y = self.torch.empty(x.shape[1:], device=self.device)
+        _check(library().mh3d_net_forward(self._h, _ptr(x), *[int(n) for n in x.shape[1:]], _ptr(y)))
         return y
 
     def loss_grad(self, x, t, crop=None, want_loss=True):
-        x = self.torch.as_tensor(x, dtype=self.torch.float32, device=self.device).contiguous()
+        x = self._input(x)
         t = self.torch.as_tensor(t, dtype=self.torch.float32, device=self.device).contiguous()
+        assert tuple(t.shape) == tuple(x.shape[1:])
         c = None if crop is None else (ctypes.c_int32 * 6)(*[int(v) for v in crop])
         loss = ctypes.c_double()
-        _check(library().mh3d_net_loss_grad(self._h, _ptr(x), _ptr(t), *[int(n) for n in x.shape], c,
+        _check(library().mh3d_net_loss_grad(self._h, _ptr(x), _ptr(t), *[int(n) for n in x.shape[1:]], c,
                                              ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 

@@ -29,7 +29,7 @@ def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spher
         seed = seed0 + j
         rho = plan.phantom(seed, n_spheres, n_tubes)
         d = plan.noisy_data(rho, seed, sample_snr2(seed, *snr), decay_db)
-        x = plan.adjoint(d)
+        x = plan.backproject(d)
         o = crop_origin(seed, plan.shape, crop)
         want = (j % log_every == 0) or (j == steps - 1)
         loss = net.loss_grad(x, rho, list(o) + list(crop), want_loss=want)

@@ -13,28 +13,34 @@ pytestmark = pytest.mark.gpu
 WIDTHS = (4, 8, 8, 16)
 
 
-def _setup(seed=0, shape=(16, 16, 16), widths=WIDTHS):
+def _setup(seed=0, shape=(16, 16, 16), widths=WIDTHS, in_ch=1):
     torch = torch_cuda()
     from paper_2503_13802_amd import mh3d
-    net = mh3d.Net(widths, seed=seed)
+    net = mh3d.Net(widths, in_channels=in_ch, seed=seed)
     rng = np.random.default_rng(seed)
     flat = np.zeros(net.nparam)
-    lay, total = unet.param_layout(widths)
+    lay, total = unet.param_layout(widths, in_ch)
     assert total == net.nparam
     for name, cin, cout, k, wo, bo in lay:      # He-normal weights, small biases
         flat[wo:bo] = rng.standard_normal(bo - wo) * np.sqrt(2.0 / (cin * k ** 3))
         flat[bo:bo + cout] = rng.standard_normal(cout) * 0.05
     net.set_params(torch.tensor(flat, dtype=torch.float32))
-    x = rng.standard_normal(shape)
+    x = rng.standard_normal(shape if in_ch == 1 else (in_ch,) + tuple(shape))
     t = rng.standard_normal(shape)
     return torch, net, flat, x, t
+
+
+def _scale(x):
+    """s = max |sum over channels| of the FP32 input."""
+    x32 = x.astype(np.float32).astype(np.float64)
+    return float(np.max(np.abs(x32 if x32.ndim == 3 else x32.sum(axis=0))))
 
 
 def test_net_forward_matches_fp64_reference():
     torch, net, flat, x, t = _setup(1)
     announce("net forward")
     y = net.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
-    s = np.max(np.abs(x.astype(np.float32)))
+    s = _scale(x)
     want = unet.forward(unet.unpack(flat.astype(np.float32).astype(np.float64), WIDTHS), x / s, WIDTHS).numpy()
     err = rel_l2(y, want)
     print("forward rel err %.3e" % err, flush=True)
@@ -46,16 +52,17 @@ def test_net_forward_matches_fp64_reference():
 # The weight gradient of a layer is a sum over all voxels with heavy cancellation,
 # so its relative error grows with the number of layers the gradient has crossed.
 # A structural mistake (a wrong tap, channel or transpose) gives errors near 1.
-@pytest.mark.parametrize("widths,shape,layer_tol", [((4, 8), (16, 16, 16), 5e-2),
-                                                    ((4, 8, 8, 16), (32, 32, 32), 0.2)])
-def test_net_gradients_match_fp64_reference(widths, shape, layer_tol):
-    torch, net, flat, x, t = _setup(2, shape=shape, widths=widths)
-    announce("net gradients %s" % (widths,))
+@pytest.mark.parametrize("widths,shape,in_ch,layer_tol", [((4, 8), (16, 16, 16), 1, 5e-2),
+                                                          ((4, 8), (16, 8, 16), 5, 5e-2),
+                                                          ((4, 8, 8, 16), (32, 32, 32), 3, 0.2)])
+def test_net_gradients_match_fp64_reference(widths, shape, in_ch, layer_tol):
+    torch, net, flat, x, t = _setup(2, shape=shape, widths=widths, in_ch=in_ch)
+    announce("net gradients %s C=%d" % (widths, in_ch))
     loss = net.loss_grad(torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32))
     g = net.grads().cpu().numpy()
-    s = np.max(np.abs(x.astype(np.float32)))
+    s = _scale(x)
     want_loss, want_g, _ = unet.loss_and_grads(flat.astype(np.float32).astype(np.float64), x / s, t / s, widths)
-    lay, _ = unet.param_layout(widths)
+    lay, _ = unet.param_layout(widths, in_ch)
     errs = {name: (rel_l2(g[wo:bo], want_g[wo:bo]), rel_l2(g[bo:bo + cout], want_g[bo:bo + cout]))
             for name, cin, cout, k, wo, bo in lay}
     print("loss %.6e vs %.6e; total grad rel err %.3e; per layer (W, b): %s"
@@ -70,12 +77,12 @@ def test_net_gradients_match_fp64_reference(widths, shape, layer_tol):
 
 
 def test_net_crop_uses_whole_volume_scale():
-    torch, net, flat, x, t = _setup(3, shape=(32, 16, 16))
+    torch, net, flat, x, t = _setup(3, shape=(32, 16, 16), in_ch=2)
     announce("net crop")
     crop = [8, 0, 0, 16, 16, 16]
     loss = net.loss_grad(torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32), crop)
-    s = np.max(np.abs(x.astype(np.float32)))
-    xc, tc = x[8:24] / s, t[8:24] / s
+    s = _scale(x)
+    xc, tc = x[:, 8:24] / s, t[8:24] / s
     want_loss, want_g, _ = unet.loss_and_grads(flat.astype(np.float32).astype(np.float64), xc, tc, WIDTHS)
     assert loss == pytest.approx(want_loss, rel=3e-2)
     assert rel_l2(net.grads().cpu().numpy(), want_g) <= 5e-2
@@ -143,7 +150,7 @@ def test_trained_network_saves_iterations():
     announce("warm-start gain")
     shape, harm = (32, 32, 32), (2, 3, 4, 5)
     p = mh3d.Plan(shape, harm, 1.2, (2, 2, 2), 20.0, 1e-3)
-    net = mh3d.Net((8, 16, 16, 32), seed=11)
+    net = mh3d.Net((8, 16, 16, 32), in_channels=len(harm), seed=11)
     hist = warmstart.train(p, net, 300, seed0=5_000_000, crop=shape, lr=2e-3, n_spheres=6, n_tubes=1,
                            log_every=50)
     assert hist[-1][1] < hist[0][1]

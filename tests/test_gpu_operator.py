@@ -102,6 +102,25 @@ def test_forward_adjoint_vs_oracle(shape, harm, ds, a, sig):
     assert rel_l2(x, x_ref) <= TOL
 
 
+@pytest.mark.parametrize("shape,harm,ds,a,sig", [CASES[1], CASES[9], CASES[10]])
+def test_per_harmonic_backprojection(shape, harm, ds, a, sig):
+    """c_k = b (H_k^T P^T d_k): each term against the oracle's adjoint restricted to
+    harmonic k, and their sum against the plan's own A^T."""
+    torch = torch_cuda()
+    announce("backproject %s ds=%s K=%d" % (shape, ds, len(harm)))
+    h = om.psf_bank(shape, list(harm), a)
+    b = om.sensitivity(shape, sig)
+    small = tuple(n // s for n, s in zip(shape, ds))
+    r = inputs.random_field((len(harm),) + small, 21)
+    p = _plan(shape, harm, a, ds, sig)
+    c = p.backproject(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    assert c.shape == (len(harm),) + tuple(shape)
+    for k in range(len(harm)):
+        assert rel_l2(c[k], om.adjoint_fft(h[k:k + 1], b, r[k:k + 1], ds)) <= TOL
+    x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(c.sum(axis=0), x) <= 2e-6
+
+
 def test_adjoint_identity_fp32():
     torch = torch_cuda()
     announce("adjoint identity")

@@ -59,3 +59,24 @@ def test_shapes_and_skips():
     flat = _flat(5)
     y = unet.forward(unet.unpack(flat, WIDTHS), np.ones((16, 8, 8)), WIDTHS)
     assert tuple(y.shape) == (16, 8, 8)
+
+
+def test_multichannel_input_gradient_matches_finite_differences():
+    widths = (2, 4)
+    lay, tot = unet.param_layout(widths, in_ch=3)
+    assert lay[0][1] == 3 and tot == unet.param_layout(widths)[1] + 2 * 27 * 2
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((3, 8, 4, 8))
+    t = rng.standard_normal((8, 4, 8))
+    flat = rng.standard_normal(tot) * 0.3
+    loss, grad, y = unet.loss_and_grads(flat, x, t, widths)
+    assert y.shape == (8, 4, 8)
+    # channel c of the input only meets the weights W[:, c] of the first layer
+    idx = list(rng.choice(lay[0][5] - lay[0][4], 12, replace=False)) + list(rng.choice(tot, 12, replace=False))
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(flat)
+        e[i] = h
+        lp, _, _ = unet.loss_and_grads(flat + e, x, t, widths)
+        lm, _, _ = unet.loss_and_grads(flat - e, x, t, widths)
+        assert (lp - lm) / (2 * h) == pytest.approx(grad[i], rel=1e-6, abs=1e-9)
