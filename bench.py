@@ -11,8 +11,14 @@ The batched leg solves the 64 uneven volumes of the batch workload (sizes 48^3 .
 128x128x96, 2..10 harmonics) to r_k <= 1e-4 each, once as 64 sequential plain
 solves and once as one batched solve, and reports both wall times.
 
+The warm-start leg trains the 3D U-Net on GPU-generated phantom/portrait pairs of
+the warm-start workload (128^3, k = 2..12, SNR_2 ~ U(20, 40) dB, 64^3 crops), then
+solves held-out samples to r_k <= 1e-4 from rho = 0 and from the network's output
+(inference included in the warm wall time), and reports iterations, wall times and
+the FP64 oracle's objective value of both end points.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1|2] [--no-cpu] [--no-solve]
-                       [--no-batch]
+                       [--no-batch] [--no-warm] [--warm-train-steps T] [--warm-eval E]
 """
 import argparse
 import json
@@ -111,6 +117,52 @@ def batched_leg(batch_inputs, tol, max_iter):
             "iters_match": iters_seq == iters_bat}
 
 
+def warm_leg(train_steps, n_eval, tol, max_iter, with_oracle=True):
+    """Warm-start workload: GPU training, then cold vs warm solves on held-out seeds."""
+    import numpy as np
+    import torch
+    from paper_2503_13802_amd import inputs, mh3d, warmstart
+    w = inputs.workload(4)
+    plan = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
+    net = mh3d.Net((8, 16, 32, 80), in_channels=len(w.harmonics), seed=w.seed)
+    log("warm leg: %s, network %d parameters, training %d steps" % (w.name, net.nparam, train_steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = warmstart.train(plan, net, train_steps, seed0=w.seed * 1000, crop=(64, 64, 64), lr=1e-3,
+                           n_spheres=w.n_blobs, n_tubes=w.n_tubes, log=log, log_every=max(1, train_steps // 10))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # warm the captured solver graphs before timing
+    d0 = plan.noisy_data(plan.phantom(1), 1, 30.0, 3.0)
+    plan.solve(d0, max_iter=20, tol=0.0, tau=0.0)
+    net.warm_start(plan, d0)
+    torch.cuda.synchronize()
+    res = warmstart.compare(plan, net, [w.seed * 1000 + 10_000_000 + j for j in range(n_eval)], tol=tol,
+                            max_iter=max_iter, n_spheres=w.n_blobs, n_tubes=w.n_tubes)
+    out = {"workload": w.name, "network_params": net.nparam, "train_steps": train_steps,
+           "train_s": round(train_s, 2), "train_ms_per_step": round(1e3 * train_s / max(1, train_steps), 3),
+           "loss_first_last": [hist[0][1], hist[-1][1]], "eval_samples": n_eval,
+           "cold_iters": [r["cold_iters"] for r in res], "warm_iters": [r["warm_iters"] for r in res],
+           "cold_s": [round(r["cold_s"], 4) for r in res], "warm_s": [round(r["warm_s"], 4) for r in res]}
+    out["iters_ratio"] = round(float(np.sum(out["warm_iters"]) / np.sum(out["cold_iters"])), 4)
+    out["speedup"] = round(float(np.sum(out["cold_s"]) / np.sum(out["warm_s"])), 4)
+    out["warm_vs_cold_rel_l2"] = [round(float((r["warm"] - r["cold"]).norm() / r["cold"].norm()), 5) for r in res]
+    out["truth_rel_l2_cold_warm_init"] = [
+        [round(float((r[k] - r["truth"]).norm() / r["truth"].norm()), 5) for k in ("cold", "warm", "init")]
+        for r in res]
+    if with_oracle and res:
+        # FP64 oracle objective 1/2 ||A rho - d||^2 + lambda/2 ||T rho||^2 of both end points (first sample)
+        from oracle import model as om
+        from oracle import solver as osv
+        op = osv.Operator(om.psf_bank(w.shape, list(w.harmonics), w.a_per_mm, w.voxel_mm),
+                          om.sensitivity(w.shape, w.sigma_mm, w.voxel_mm), w.ds, w.lam)
+        r = res[0]
+        d = r["d"].cpu().numpy().astype(np.float64)
+        out["oracle_objective_sample0"] = {k: op.objective(r[k].cpu().numpy().astype(np.float64), d)
+                                           for k in ("cold", "warm")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +173,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-volumes", type=int, default=64)
+    ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--warm-train-steps", type=int, default=1500)
+    ap.add_argument("--warm-eval", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; a multi-GPU run is not part of it "
@@ -232,6 +287,10 @@ def main():
 
     if batch_inputs is not None:
         out["batched"] = batched_leg(batch_inputs, w.tol, w.max_iter)
+
+    if not args.no_warm:
+        out["warm_start"] = warm_leg(args.warm_train_steps, args.warm_eval, w.tol, w.max_iter,
+                                     with_oracle=not args.no_cpu)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

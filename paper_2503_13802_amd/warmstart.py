@@ -19,20 +19,36 @@ def crop_origin(seed, shape, crop):
 
 
 def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spheres=80, n_tubes=6,
-          snr=(20.0, 40.0), decay_db=3.0, log=None, log_every=100):
-    """Trains `net` on `steps` phantom/portrait pairs generated on the GPU from the
-    plan's forward model (sample j uses seed seed0 + j).  Returns the loss history
-    (every log_every steps)."""
+          snr=(20.0, 40.0), decay_db=3.0, log=None, log_every=100, target="phantom", crops_per_sample=1,
+          solve_tol=1e-4, solve_max_iter=5000):
+    """Trains `net` on `steps` crops of phantom/portrait pairs generated on the GPU from
+    the plan's forward model (sample j uses seed seed0 + j; each sample serves
+    crops_per_sample consecutive steps).  target "phantom" regresses the phantom;
+    "solution" regresses the plain solver's end point at solve_tol from rho = 0 (the
+    point a warm-started solve converges to); "objective" trains on the full volume
+    against the solver's objective at the network's output (mh3d_net_objective_grad;
+    the logged value is ||grad F|| / ||A^T d||).  Returns the loss history (every
+    log_every steps)."""
     hist = []
     t0 = time.perf_counter()
+    x = tgt = None
     for j in range(steps):
-        seed = seed0 + j
-        rho = plan.phantom(seed, n_spheres, n_tubes)
-        d = plan.noisy_data(rho, seed, sample_snr2(seed, *snr), decay_db)
-        x = plan.backproject(d)
-        o = crop_origin(seed, plan.shape, crop)
+        sample = j // crops_per_sample
+        seed = seed0 + sample
+        if j % crops_per_sample == 0:
+            rho = plan.phantom(seed, n_spheres, n_tubes)
+            d = plan.noisy_data(rho, seed, sample_snr2(seed, *snr), decay_db)
+            x = plan.backproject(d) if target != "objective" else None
+            if target == "solution":
+                tgt, _ = plan.solve(d, max_iter=solve_max_iter, tol=solve_tol, tau=0.0)
+            else:
+                tgt = rho
         want = (j % log_every == 0) or (j == steps - 1)
-        loss = net.loss_grad(x, rho, list(o) + list(crop), want_loss=want)
+        if target == "objective":
+            loss = net.objective_grad(plan, d, want=want)
+        else:
+            o = crop_origin(seed * 131 + j % crops_per_sample, plan.shape, crop)
+            loss = net.loss_grad(x, tgt, list(o) + list(crop), want_loss=want)
         net.adam_step(lr)
         if want:
             hist.append((j, loss))
