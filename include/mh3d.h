@@ -80,7 +80,8 @@ typedef struct {
 typedef struct {
   int32_t max_iter;          /* maximum number of updates, >= 1                          */
   double rel_tol;            /* stop after the first update with r_k <= rel_tol; 0: never */
-  double tau;                /* step size; <= 0 -> 1/(1.05 L), L by power iteration      */
+  double tau;                /* step size; <= 0 -> 1/(1.05 L), L by power iteration,     */
+                             /* computed once per plan and (power_iters, power_seed)     */
   int32_t power_iters;       /* power iterations when tau <= 0 (default 50 if 0)         */
   uint64_t power_seed;       /* Philox4x32-10 seed of the power-iteration start vector   */
   const float* rho_prev;     /* optional DEVICE rho^{k0-1} to resume; NULL -> rho_inout  */
@@ -229,7 +230,7 @@ mh3d_status mh3d_plan_export(mh3d_plan_t plan, mh3d_field field, void* dst, size
 /* Per-kernel timing with HIP events around every launch of the plan's kernels
  * (enable = 1 starts and clears, 0 stops).  mh3d_profile_read synchronises and
  * returns the cumulative milliseconds and launch counts per kernel id, plus names. */
-#define MH3D_NKERNEL 8
+#define MH3D_NKERNEL 9
 typedef struct {
   double ms[MH3D_NKERNEL];
   int64_t launches[MH3D_NKERNEL];

@@ -165,6 +165,8 @@ struct VolDesc {
   int reg_kind;
   float lam;
   int T_class;             // threads of the class passes doing element work
+  float* u;                // A^T A part of the current step (k_plane_adj<OUT_U> -> k_vol_update)
+  int nb_upd;              // blocks of k_vol_update for this volume
 };
 
 // Volume and local block index of this block: task table (batched launches) or
@@ -724,11 +726,12 @@ __global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ 
 }
 
 // ============================================================================ pass 1 adjoint
-enum { OUT_SCALE_B = 0, OUT_NORMAL = 1, OUT_FISTA = 2 };
+enum { OUT_SCALE_B = 0, OUT_U = 1 };
+enum { UPD_NORMAL = 1, UPD_FISTA = 2 };
 
 struct AdjOut {
-  float* out;              // OUT_SCALE_B / OUT_NORMAL: result
-  const float* yin;        // OUT_NORMAL: w_{t-1} (v = scale * w_{t-1})
+  float* out;              // OUT_SCALE_B / UPD_NORMAL: result (UPD_NORMAL: NULL -> rho[(k+1) & 1])
+  const float* yin;        // UPD_NORMAL: w_{t-1} (v = scale * w_{t-1}); NULL -> rho[k & 1]
 };
 
 // Deterministic grid reduction: every block writes NV partials; the last block to
@@ -747,44 +750,40 @@ __device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, De
   }
   __syncthreads();
   if (!is_last) return false;
-  if (threadIdx.x == 0) {
-    __threadfence();
+  // the last block sums the partials: thread t takes blocks t, t + blockDim, ... in
+  // order, then the fixed-order block reduction (the same result for any arrival order)
+  __threadfence();
+  double w[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-      double s = 0.0;
-      const volatile double* vp = partials;
-      for (int bidx = 0; bidx < nblk; ++bidx) s += vp[bidx * NV + j];
-      v[j] = s;
-    }
+  for (int j = 0; j < NV; ++j) w[j] = 0.0;
+  const volatile double* vp = partials;
+  for (int bidx = threadIdx.x; bidx < nblk; bidx += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) w[j] += vp[bidx * NV + j];
+  }
+  block_reduce_f64<NV>(w, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = w[j];
     st->counter = 0;
   }
   return threadIdx.x == 0;
 }
 
-// Values of one voxel's stencil that live outside the block's x-plane.
-struct XNb {
-  float b, xm2, xm1, xp1, xp2, rk;
-};
-
 // Adjoint pass 1: gather the class layout into a half plane, inverse y FFT, C2R
-// along z, then the epilogue:
-//   OUT_SCALE_B  out = b . v                                  (A^T)
-//   OUT_NORMAL   out = b . v + lam T^T T (s w_prev); FP64 <s w_prev, out>, ||out||^2
-//   OUT_FISTA    g = b . v + lam T^T T y^k; rho^{k+1} = max(y^k - tau g, 0);
-//                y^{k+1} = rho^{k+1} + k/(k+3) (rho^{k+1} - rho^k);
-//                FP64 ||rho^{k+1} - y^k||^2, ||rho^{k+1}||^2, count of non-finite g
-// T^T T is the periodic 13-point stencil sum_a (y[+2] - 4y[+1] + 6y - 4y[-1] + y[-2])
-// of stacked second differences (reg_kind 1: T = I).  In-plane neighbours come from
-// the plane staged in LDS, x-neighbours from global memory.  grid = nx blocks.
+// along z, times the sensitivity:
+//   OUT_SCALE_B  ao.out = b . v                          (A^T)
+//   OUT_U        vd.u = b . v  (the A^T A part of a solver step; skipped once the
+//                volume's solve is done; k_vol_update finishes the step)
+// grid = nx blocks (one x-plane each).
 template <int OUT>
 __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
                                                     AdjOut ao) {
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   const Geo& g = vd.g;
-  DevState* st = vd.st;
-  if constexpr (OUT != OUT_SCALE_B) {
-    if (st->done) return;
+  if constexpr (OUT == OUT_U) {
+    if (vd.st->done) return;
   }
   extern __shared__ float2 lds[];
   const int pl = plane_lds(g);
@@ -792,7 +791,6 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   float2* twy = twz + g.nz;
   float2* P0 = twy + g.ny;
   float2* P1 = P0 + pl;
-  __shared__ double red[64];
   load_table(twz, vd.tw + vd.off[2], g.nz);
   load_table(twy, vd.tw + vd.off[1], g.ny);
   const int x = plane_of_block(lb, g.nx);
@@ -816,105 +814,192 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   };
   const float* __restrict__ b = vd.b;
   const long long pbase = (long long)x * g.ny * g.nz;
-  const int nyz = g.ny * g.nz;
-  if constexpr (OUT == OUT_SCALE_B) {
-    batched<8, float>(nyz, [&](int p) { return b[pbase + p]; },
-                      [&](int p, float bv) { ao.out[pbase + p] = bv * Xf[vidx(p)]; });
-    return;
-  } else {
-    const int kk = st->k;
-    // the vector the regulariser acts on: s w_{t-1} (power iteration; w_{t-1} in
-    // rho[k & 1] when no buffers are given) or y^k
-    const float* yv = (OUT == OUT_NORMAL) ? (ao.yin ? ao.yin : vd.rho[kk & 1]) : vd.y[kk & 1];
-    float* out = (OUT == OUT_NORMAL) ? (ao.out ? ao.out : vd.rho[(kk + 1) & 1]) : nullptr;
-    const float* rk = vd.rho[kk & 1];
-    // stage that vector's plane in the free LDS buffer
-    float* Yl = reinterpret_cast<float*>(Z == P0 ? P1 : P0);
-    const float s = (OUT == OUT_NORMAL) ? (float)st->scale : 1.f;
-    batched<8, float>(nyz, [&](int p) { return yv[pbase + p]; }, [&](int p, float v) { Yl[p] = s * v; });
-    __syncthreads();
-    const long long plane_sz = (long long)g.ny * g.nz;
-    const long long xm2 = (long long)((x - 2 + 2 * g.nx) % g.nx) * plane_sz;
-    const long long xm1 = (long long)((x - 1 + g.nx) % g.nx) * plane_sz;
-    const long long xp1 = (long long)((x + 1) % g.nx) * plane_sz;
-    const long long xp2 = (long long)((x + 2) % g.nx) * plane_sz;
-    const bool stencil = vd.reg_kind == 0;
-    const float lam = vd.lam;
-    auto ld = [&](int p) {
-      XNb v;
-      v.b = b[pbase + p];
-      if (stencil) {
-        v.xm2 = yv[xm2 + p]; v.xm1 = yv[xm1 + p]; v.xp1 = yv[xp1 + p]; v.xp2 = yv[xp2 + p];
-      } else {
-        v.xm2 = v.xm1 = v.xp1 = v.xp2 = 0.f;
-      }
-      if constexpr (OUT == OUT_FISTA) v.rk = rk[pbase + p];
-      else v.rk = 0.f;
-      return v;
-    };
-    auto reg = [&](int p, const XNb& v) {
-      const float c = Yl[p];
-      if (!stencil) return c;
-      const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
-      // periodic neighbours (grid axes are >= 4 long, so one wrap suffices)
-      const int ym1 = y >= 1 ? y - 1 : y - 1 + g.ny, ym2 = y >= 2 ? y - 2 : y - 2 + g.ny;
-      const int yp1 = y + 1 < g.ny ? y + 1 : y + 1 - g.ny, yp2 = y + 2 < g.ny ? y + 2 : y + 2 - g.ny;
-      const int zm1 = z >= 1 ? z - 1 : z - 1 + g.nz, zm2 = z >= 2 ? z - 2 : z - 2 + g.nz;
-      const int zp1 = z + 1 < g.nz ? z + 1 : z + 1 - g.nz, zp2 = z + 2 < g.nz ? z + 2 : z + 2 - g.nz;
-      float t = 18.f * c;
-      t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
-      t += Yl[yp2 * g.nz + z] + Yl[ym2 * g.nz + z] - 4.f * (Yl[yp1 * g.nz + z] + Yl[ym1 * g.nz + z]);
-      t += Yl[y * g.nz + zp2] + Yl[y * g.nz + zm2] - 4.f * (Yl[y * g.nz + zp1] + Yl[y * g.nz + zm1]);
-      return t;
-    };
-    if constexpr (OUT == OUT_NORMAL) {
-      double acc[2] = {0.0, 0.0};
-      batched<4, XNb>(nyz, ld, [&](int p, const XNb& v) {
-        const float o = v.b * Xf[vidx(p)] + lam * reg(p, v);
-        out[pbase + p] = o;
-        acc[0] += (double)Yl[p] * (double)o;
+  float* __restrict__ out = (OUT == OUT_U) ? vd.u : ao.out;
+  batched<8, float>(g.ny * g.nz, [&](int p) { return b[pbase + p]; },
+                    [&](int p, float bv) { out[pbase + p] = bv * Xf[vidx(p)]; });
+}
+
+// Blocks of the volume-wide update pass, each a contiguous run of whole 1024-voxel
+// tiles (at most 256 blocks: one arrival atomic per block on the volume's counter).
+constexpr int UPD_THREADS = 1024;
+__host__ __device__ inline int update_blocks(long long n) {
+  long long b = (n + 8191) / 8192;
+  return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+// The 13 values of one voxel's regulariser stencil and the values its update reads.
+struct StencilVals {
+  float c, zm2, zm1, zp1, zp2, ym2, ym1, yp1, yp2, xm2, xm1, xp1, xp2, u, rk;
+};
+
+// Finishes a solver step after k_plane_adj<OUT_U> left u = b . v (the A^T A part):
+//   UPD_NORMAL  out = u + lam T^T T (s w_prev); FP64 <s w_prev, out>, ||out||^2
+//               (power iteration: lmax, next scale 1/||out||)
+//   UPD_FISTA   g = u + lam T^T T y^k; rho^{k+1} = max(y^k - tau g, 0);
+//               y^{k+1} = rho^{k+1} + k/(k+3) (rho^{k+1} - rho^k);
+//               FP64 ||rho^{k+1} - y^k||^2, ||rho^{k+1}||^2, count of non-finite g
+// T^T T is the periodic 13-point stencil sum_a (v[+2] - 4v[+1] + 6v - 4v[-1] + v[-2])
+// of stacked second differences (reg_kind 1: T = I); neighbours are read from global
+// memory (cache resident).  Each block leaves its FP64 sums in vd.partials;
+// k_vol_finish reduces them and updates the state.  grid = vd.nb_upd blocks of
+// UPD_THREADS threads per volume.
+template <int UPD>
+__global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    AdjOut ao) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  const Geo& g = vd.g;
+  DevState* st = vd.st;
+  if (st->done) return;
+  __shared__ double red[64];
+  const int kk = st->k;
+  const float* __restrict__ yv = (UPD == UPD_NORMAL) ? (ao.yin ? ao.yin : vd.rho[kk & 1]) : vd.y[kk & 1];
+  const float* __restrict__ u = vd.u;
+  const float* __restrict__ rk = vd.rho[kk & 1];
+  const float s = (UPD == UPD_NORMAL) ? (float)st->scale : 1.f;
+  const float lam = vd.lam;
+  const bool stencil = vd.reg_kind == 0;
+  const long long N = g.N;
+  const int nb = vd.nb_upd;
+  constexpr int T = UPD_THREADS;
+  const long long chunk = ((N + nb - 1) / nb + T - 1) / T * T;
+  // XCD-aware: blocks of one XCD take consecutive chunks (the planes k_plane_adj
+  // wrote on that XCD, and their x-neighbours)
+  const long long i0 = (long long)plane_of_block(lb, nb) * chunk;
+  const long long i1 = i0 + chunk < N ? i0 + chunk : N;
+  const long long pl = (long long)g.ny * g.nz;
+  auto load = [&](long long i) {
+    StencilVals v;
+    v.c = yv[i];
+    v.u = u[i];
+    v.rk = (UPD == UPD_FISTA) ? rk[i] : 0.f;
+    if (stencil) {
+      const uint32_t r = g.f_nz.div((uint32_t)i);
+      const int z = (int)((uint32_t)i - r * (uint32_t)g.nz);
+      const int y = (int)g.f_ny.mod(r), x = (int)g.f_ny.div(r);
+      const long long row = i - z;
+      // periodic neighbours (every axis is >= 4 long, so one wrap suffices)
+      auto wz = [&](int d) { int q = z + d; q += q < 0 ? g.nz : 0; q -= q >= g.nz ? g.nz : 0; return yv[row + q]; };
+      auto wy = [&](int d) {
+        int q = y + d; q += q < 0 ? g.ny : 0; q -= q >= g.ny ? g.ny : 0;
+        return yv[i + (long long)(q - y) * g.nz];
+      };
+      auto wx = [&](int d) {
+        int q = x + d; q += q < 0 ? g.nx : 0; q -= q >= g.nx ? g.nx : 0;
+        return yv[i + (long long)(q - x) * pl];
+      };
+      v.zm2 = wz(-2); v.zm1 = wz(-1); v.zp1 = wz(1); v.zp2 = wz(2);
+      v.ym2 = wy(-2); v.ym1 = wy(-1); v.yp1 = wy(1); v.yp2 = wy(2);
+      v.xm2 = wx(-2); v.xm1 = wx(-1); v.xp1 = wx(1); v.xp2 = wx(2);
+    }
+    return v;
+  };
+  auto reg = [&](const StencilVals& v) {
+    if (!stencil) return s * v.c;
+    float t = 18.f * (s * v.c);
+    t += s * (v.zp2 + v.zm2) - 4.f * s * (v.zp1 + v.zm1);
+    t += s * (v.yp2 + v.ym2) - 4.f * s * (v.yp1 + v.ym1);
+    t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
+    return t;
+  };
+  constexpr int U = 4;
+  if constexpr (UPD == UPD_NORMAL) {
+    float* __restrict__ out = ao.out ? ao.out : vd.rho[(kk + 1) & 1];
+    double acc[2] = {0.0, 0.0};
+    for (long long i = i0 + threadIdx.x; i < i1; i += U * T) {
+      StencilVals v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (i + q * T < i1) v[q] = load(i + q * T);
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (i + q * T >= i1) break;
+        const float o = v[q].u + lam * reg(v[q]);
+        out[i + q * T] = o;
+        acc[0] += (double)(s * v[q].c) * (double)o;
         acc[1] += (double)o * (double)o;
-      });
-      if (grid_reduce_last<2>(acc, vd.partials, st, red, lb, g.nx)) {
-        st->lmax = acc[0];
-        st->scale = 1.0 / sqrt(acc[1]);
-        if (!(acc[0] == acc[0]) || !(acc[1] < 1e300)) st->nonfinite = 1.0;
-        st->k = kk + 1;
-        if (kk >= st->kmax) st->done = 1;
       }
-    } else {
-      const float tau = (float)st->tau;
-      const float beta1 = (float)((double)kk / (kk + 3.0));      // (k+1-1)/(k+1+2)
-      float* rho_next = vd.rho[(kk + 1) & 1];
-      float* y_next = vd.y[(kk + 1) & 1];
-      double acc[3] = {0.0, 0.0, 0.0};
-      batched<4, XNb>(nyz, ld, [&](int p, const XNb& v) {
-        const float yk = Yl[p];
-        const float gr = v.b * Xf[vidx(p)] + lam * reg(p, v);
+    }
+    block_reduce_f64<2>(acc, red);
+    if (threadIdx.x == 0) {
+      vd.partials[2 * lb] = acc[0];
+      vd.partials[2 * lb + 1] = acc[1];
+    }
+  } else {
+    const float tau = (float)st->tau;
+    const float beta1 = (float)((double)kk / (kk + 3.0));      // (k+1-1)/(k+1+2)
+    float* __restrict__ rho_next = vd.rho[(kk + 1) & 1];
+    float* __restrict__ y_next = vd.y[(kk + 1) & 1];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = i0 + threadIdx.x; i < i1; i += U * T) {
+      StencilVals v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (i + q * T < i1) v[q] = load(i + q * T);
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (i + q * T >= i1) break;
+        const float yk = v[q].c;
+        const float gr = v[q].u + lam * reg(v[q]);
         const float rn = fmaxf(yk - tau * gr, 0.f);
-        rho_next[pbase + p] = rn;
-        y_next[pbase + p] = rn + beta1 * (rn - v.rk);
+        rho_next[i + q * T] = rn;
+        y_next[i + q * T] = rn + beta1 * (rn - v[q].rk);
         const double dd = (double)rn - (double)yk;
         acc[0] += dd * dd;
         acc[1] += (double)rn * (double)rn;
         if (!isfinite(gr) || !isfinite(yk)) acc[2] += 1.0;   // max(NaN, 0) would hide it
-      });
-      if (grid_reduce_last<3>(acc, vd.partials, st, red, lb, g.nx)) {
-        double r;
-        if (acc[1] == 0.0) r = (acc[0] == 0.0) ? 0.0 : __builtin_inf();
-        else r = sqrt(acc[0]) / sqrt(acc[1]);
-        st->rel_step = r;
-        st->last_k = kk;
-        const int hi = kk - vd.k_first;
-        if (vd.hist && hi >= 0 && hi < vd.hist_len) vd.hist[hi] = r;
-        if (acc[2] != 0.0 || !(acc[0] == acc[0]) || !(acc[1] == acc[1]) || acc[1] > 1e300) {
-          st->nonfinite = 1.0;
-          st->done = 1;
-        }
-        if (r <= st->tol || kk >= st->kmax) st->done = 1;
-        st->k = kk + 1;
       }
     }
+    block_reduce_f64<3>(acc, red);
+    if (threadIdx.x == 0) {
+      vd.partials[3 * lb] = acc[0];
+      vd.partials[3 * lb + 1] = acc[1];
+      vd.partials[3 * lb + 2] = acc[2];
+    }
+  }
+}
+
+// Sums the block partials of k_vol_update in a fixed order (thread t takes blocks
+// t, t + 256, ..., then the fixed-order block reduction) and advances the state.
+// One block per volume; the kernel boundary orders it after every partial store.
+template <int UPD>
+__global__ __launch_bounds__(256) void k_vol_finish(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  DevState* st = vd.st;
+  if (st->done) return;
+  __shared__ double red[64];
+  constexpr int NV = UPD == UPD_NORMAL ? 2 : 3;
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  for (int b = threadIdx.x; b < vd.nb_upd; b += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] += vd.partials[b * NV + j];
+  }
+  block_reduce_f64<NV>(acc, red);
+  if (threadIdx.x != 0) return;
+  const int kk = st->k;
+  if constexpr (UPD == UPD_NORMAL) {
+    st->lmax = acc[0];
+    st->scale = 1.0 / sqrt(acc[1]);
+    if (!(acc[0] == acc[0]) || !(acc[1] < 1e300)) st->nonfinite = 1.0;
+    st->k = kk + 1;
+    if (kk >= st->kmax) st->done = 1;
+  } else {
+    double r;
+    if (acc[1] == 0.0) r = (acc[0] == 0.0) ? 0.0 : __builtin_inf();
+    else r = sqrt(acc[0]) / sqrt(acc[1]);
+    st->rel_step = r;
+    st->last_k = kk;
+    const int hi = kk - vd.k_first;
+    if (vd.hist && hi >= 0 && hi < vd.hist_len) vd.hist[hi] = r;
+    if (acc[2] != 0.0 || !(acc[0] == acc[0]) || !(acc[1] == acc[1]) || acc[1] > 1e300) {
+      st->nonfinite = 1.0;
+      st->done = 1;
+    }
+    if (r <= st->tol || kk >= st->kmax) st->done = 1;
+    st->k = kk + 1;
   }
 }
 

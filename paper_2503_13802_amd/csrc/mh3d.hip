@@ -175,9 +175,10 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
 }
 
 // ============================================================================ plan
-enum { KID_PLANE_FWD = 0, KID_CLASS_FWD, KID_SMALL_INV, KID_SMALL_FWD, KID_CLASS_ADJ, KID_PLANE_ADJ, KID_AUX, KID_SOLVE_ITER };
-static const char* kKernelNames[MH3D_NKERNEL] = {"plane_fwd", "class_fwd", "small_inv", "small_fwd",
-                                                  "class_adj", "plane_adj", "aux", "solve_iter"};
+enum { KID_PLANE_FWD = 0, KID_CLASS_FWD, KID_SMALL_INV, KID_SMALL_FWD, KID_CLASS_ADJ, KID_PLANE_ADJ, KID_AUX, KID_SOLVE_ITER,
+       KID_UPDATE };
+static const char* kKernelNames[MH3D_NKERNEL] = {"plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj",
+                                                  "plane_adj", "aux", "solve_iter", "vol_update"};
 
 struct mh3d_plan_s {
   mh3d_plan_desc desc;
@@ -195,7 +196,7 @@ struct mh3d_plan_s {
   float2* uperm = nullptr;     // class-layout yz spectra of one volume (also adjoint V)
   float2* G = nullptr;         // decimated spectra (forward)
   float2* Gp = nullptr;        // decimated spectra (adjoint)
-  float* vol[4] = {nullptr, nullptr, nullptr, nullptr};  // rho[0], rho[1], y[0], y[1]
+  float* vol[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // rho[0], rho[1], y[0], y[1], u
   float2* tw32 = nullptr;
   double2* tw64 = nullptr;
   int off[6];                  // table offsets for nx, ny, nz, mx, my, mz
@@ -208,6 +209,9 @@ struct mh3d_plan_s {
   VolDesc vdh;                 // host copy of the descriptor
   VolDesc* vdd = nullptr;      // device descriptor
   VolDesc* vdk = nullptr;      // device descriptors of the single harmonics (K of them)
+  int pi_iters = 0;            // cached step-size estimate: power iterations (0: none), seed, L
+  uint64_t pi_seed = 0;
+  double pi_lmax = 0.0;
   size_t bytes = 0;
   // captured solver chunk
   hipGraph_t graph = nullptr;
@@ -237,7 +241,7 @@ static size_t plan_bytes(const Geo& g, bool compact) {
   s += (size_t)g.N * 4;                               // b
   s += (size_t)g.nx * g.plane * 8;                    // uperm
   s += 2 * (size_t)g.K * g.mx * g.ncls * 8;           // G, Gp
-  s += 4 * (size_t)g.N * 4;                           // vol
+  s += 5 * (size_t)g.N * 4;                           // vol
   s += (size_t)(2 * (g.nx + g.ny + g.nz) + g.mx + g.my + g.mz) * 24;
   s += ((size_t)g.K * g.nx + (size_t)g.ny * g.nz) * 8;
   return s;
@@ -381,10 +385,25 @@ static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const floa
   ao.yin = yin;
   switch (out) {
     case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
-    case OUT_NORMAL: k_plane_adj<OUT_NORMAL><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
-    default: k_plane_adj<OUT_FISTA><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
+    default: k_plane_adj<OUT_U><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
   }
   return last_launch("k_plane_adj");
+}
+
+static mh3d_status launch_update(mh3d_plan_t p, int upd, float* o, const float* yin) {
+  Timer t(p, KID_UPDATE);
+  AdjOut ao;
+  ao.out = o;
+  ao.yin = yin;
+  const dim3 grid(update_blocks(p->g.N)), block(UPD_THREADS);
+  if (upd == UPD_NORMAL) {
+    k_vol_update<UPD_NORMAL><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
+    k_vol_finish<UPD_NORMAL><<<1, 256, 0, p->ls>>>(p->vdd, nullptr);
+  } else {
+    k_vol_update<UPD_FISTA><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
+    k_vol_finish<UPD_FISTA><<<1, 256, 0, p->ls>>>(p->vdd, nullptr);
+  }
+  return last_launch("k_vol_update");
 }
 
 // ---------------------------------------------------------------------------- state
@@ -482,7 +501,7 @@ extern "C" void mh3d_destroy(mh3d_plan_t p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto& e : p->pending) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
   for (auto e : p->free_events) (void)hipEventDestroy(e);
-  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3],
+  void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3], p->vol[4],
                   p->tw32, p->tw64, p->prof, p->env, p->partials, p->st, p->vdd, p->vdk, p->hist};
   for (void* q : bufs)
     if (q) (void)hipFree(q);
@@ -515,6 +534,8 @@ static void fill_desc(mh3d_plan_t p) {
   v.reg_kind = p->desc.reg_kind;
   v.lam = (float)p->desc.lambda;
   v.T_class = p->L.T_class;
+  v.u = p->vol[4];
+  v.nb_upd = update_blocks(p->g.N);
 }
 
 // Descriptor of harmonic k alone: the same buffers with K = 1, the spectra and the
@@ -563,7 +584,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = dalloc(p, (void**)&p->uperm, sizeof(float2) * (size_t)g.nx * g.plane)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->G, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->Gp, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 5; ++i)
     if ((s = dalloc(p, (void**)&p->vol[i], sizeof(float) * g.N)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->prof, sizeof(double) * (size_t)g.K * g.nx)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->env, sizeof(double) * (size_t)g.ny * g.nz)) != MH3D_OK) return bail(s);
@@ -637,7 +658,8 @@ static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out
   CHK(launch_class_fwd(p, 1));
   CHK(launch_small_inv(p, EPI_BACK, nullptr));
   CHK(launch_class_adj(p, 1));
-  CHK(launch_plane_adj(p, OUT_NORMAL, out, w));
+  CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
+  CHK(launch_update(p, UPD_NORMAL, out, w));
   return MH3D_OK;
 }
 
@@ -699,7 +721,8 @@ static mh3d_status enqueue_update(mh3d_plan_t p) {
   CHK(launch_class_fwd(p, 1));
   CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr));
   CHK(launch_class_adj(p, 1));
-  CHK(launch_plane_adj(p, OUT_FISTA, nullptr, nullptr));
+  CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
+  CHK(launch_update(p, UPD_FISTA, nullptr, nullptr));
   return MH3D_OK;
 }
 
@@ -780,9 +803,17 @@ static mh3d_status resolve_tau(mh3d_plan_t p, const mh3d_solve_opts* opts, doubl
   *tau = opts->tau;
   *lmax = 0.0;
   if (!(*tau > 0)) {
+    // L depends on the operator only: computed once per plan and (iterations, seed)
     const int it = opts->power_iters > 0 ? opts->power_iters : 50;
-    CHK(power_iteration(p, it, opts->power_seed, lmax));
-    if (!(*lmax > 0)) return fail(MH3D_ERR_NONFINITE, "power iteration gave L = %g", *lmax);
+    if (p->pi_iters == it && p->pi_seed == opts->power_seed) {
+      *lmax = p->pi_lmax;
+    } else {
+      CHK(power_iteration(p, it, opts->power_seed, lmax));
+      if (!(*lmax > 0)) return fail(MH3D_ERR_NONFINITE, "power iteration gave L = %g", *lmax);
+      p->pi_iters = it;
+      p->pi_seed = opts->power_seed;
+      p->pi_lmax = *lmax;
+    }
     *tau = 1.0 / (1.05 * *lmax);
   }
   return MH3D_OK;
@@ -859,8 +890,8 @@ struct mh3d_batch_s {
   std::vector<mh3d_plan_t> plans;
   hipStream_t stream;
   VolDesc* vds = nullptr;            // device descriptors of all volumes
-  int2* tasks[3] = {nullptr, nullptr, nullptr};   // plane, class, small task tables
-  int ntask[3] = {0, 0, 0};
+  int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // plane, class, small, update, per-volume
+  int ntask[5] = {0, 0, 0, 0, 0};
   int T_class = 0;
   size_t lds_plane = 0, lds_class = 0, lds_small = 0;
   hipGraphExec_t gexec = nullptr;
@@ -876,7 +907,7 @@ extern "C" void mh3d_batch_destroy(mh3d_batch_t b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->vds) (void)hipFree(b->vds);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 5; ++i)
     if (b->tasks[i]) (void)hipFree(b->tasks[i]);
   delete b;
 }
@@ -894,12 +925,14 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   mh3d_batch_t b = new mh3d_batch_s();
   b->plans.assign(plans, plans + n);
   b->stream = plans[0]->stream;
-  std::vector<int2> t[3];
+  std::vector<int2> t[5];
   for (int v = 0; v < n; ++v) {
     const mh3d_plan_t p = plans[v];
     for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
     for (int i = 0; i < p->g.ncls / p->g.cpw; ++i) t[1].push_back(make_int2(v, i));
     for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
+    for (int i = 0; i < update_blocks(p->g.N); ++i) t[3].push_back(make_int2(v, i));
+    t[4].push_back(make_int2(v, 0));
     b->T_class = std::max(b->T_class, p->L.T_class);
     b->lds_plane = std::max(b->lds_plane, p->L.lds_plane);
     b->lds_class = std::max(b->lds_class, p->L.lds_class);
@@ -907,7 +940,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   }
   auto bail = [&](mh3d_status s) { mh3d_batch_destroy(b); return s; };
   if (hipMalloc(&b->vds, sizeof(VolDesc) * n) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch descriptors"));
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 5; ++i) {
     b->ntask[i] = (int)t[i].size();
     if (hipMalloc(&b->tasks[i], sizeof(int2) * t[i].size()) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch tasks"));
     if (hipMemcpy(b->tasks[i], t[i].data(), sizeof(int2) * t[i].size(), hipMemcpyHostToDevice) != hipSuccess)
@@ -930,8 +963,12 @@ static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
-  k_plane_adj<OUT_FISTA><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  k_plane_adj<OUT_U><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
   CHK(last_launch("k_plane_adj (batch)"));
+  k_vol_update<UPD_FISTA><<<dim3(b->ntask[3]), dim3(UPD_THREADS), 0, st>>>(b->vds, b->tasks[3], ao);
+  CHK(last_launch("k_vol_update (batch)"));
+  k_vol_finish<UPD_FISTA><<<dim3(b->ntask[4]), dim3(256), 0, st>>>(b->vds, b->tasks[4]);
+  CHK(last_launch("k_vol_finish (batch)"));
   return MH3D_OK;
 }
 
@@ -948,8 +985,12 @@ static mh3d_status batch_power_step(mh3d_batch_t b, hipStream_t st) {
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
-  k_plane_adj<OUT_NORMAL><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  k_plane_adj<OUT_U><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
   CHK(last_launch("k_plane_adj (batch power)"));
+  k_vol_update<UPD_NORMAL><<<dim3(b->ntask[3]), dim3(UPD_THREADS), 0, st>>>(b->vds, b->tasks[3], ao);
+  CHK(last_launch("k_vol_update (batch power)"));
+  k_vol_finish<UPD_NORMAL><<<dim3(b->ntask[4]), dim3(256), 0, st>>>(b->vds, b->tasks[4]);
+  CHK(last_launch("k_vol_finish (batch power)"));
   return MH3D_OK;
 }
 
@@ -997,7 +1038,21 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
   HIPCHK(hipEventRecord(e0, b->stream));
   std::vector<double> tau(n, opts->tau), lmax(n, 0.0);
   if (!(opts->tau > 0)) {
-    CHK(batch_power(b, opts->power_iters > 0 ? opts->power_iters : 50, opts->power_seed, lmax));
+    const int it = opts->power_iters > 0 ? opts->power_iters : 50;
+    bool cached = true;
+    for (int v = 0; v < n; ++v) {
+      const mh3d_plan_t p = b->plans[v];
+      if (p->pi_iters == it && p->pi_seed == opts->power_seed) lmax[v] = p->pi_lmax;
+      else cached = false;
+    }
+    if (!cached) {
+      CHK(batch_power(b, it, opts->power_seed, lmax));
+      for (int v = 0; v < n; ++v) {
+        b->plans[v]->pi_iters = it;
+        b->plans[v]->pi_seed = opts->power_seed;
+        b->plans[v]->pi_lmax = lmax[v];
+      }
+    }
     for (int v = 0; v < n; ++v) tau[v] = 1.0 / (1.05 * lmax[v]);
   }
   for (int v = 0; v < n; ++v) {

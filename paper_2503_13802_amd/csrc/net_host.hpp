@@ -131,7 +131,9 @@ mh3d_status net_work(mh3d_net_t n, int nx, int ny, int nz, NetWork** out) {
   }
   CHK(mk(nvox(0) * 4, &w.gy));
   CHK(net_alloc((void**)&w.y, sizeof(float) * (size_t)nvox(0)));
-  CHK(net_alloc((void**)&w.scale, sizeof(double) * 4));
+  // [scale, loss, objective-gradient norms (2), absmax slot]
+  CHK(net_alloc((void**)&w.scale, sizeof(double) * 5));
+  (void)hipMemsetAsync(w.scale, 0, sizeof(double) * 5, n->stream);
   w.loss = w.scale + 1;
   (void)cmax_all;
   auto res = n->work.emplace(key, w);
@@ -177,8 +179,11 @@ mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
 mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long long nsrc, int ox, int oy, int oz) {
   const int L = (int)n->widths.size();
   if (!n->packed) CHK(net_pack(n));
-  k_absmax<<<1, 1024, 0, n->stream>>>(x, nsrc, n->in_ch, w->scale);
+  unsigned* slot = reinterpret_cast<unsigned*>(w->scale + 4);
+  k_absmax<<<grid_for(nsrc, 256) < 1024 ? grid_for(nsrc, 256) : 1024, 256, 0, n->stream>>>(x, nsrc, n->in_ch, slot);
   CHK(last_launch("k_absmax"));
+  k_absmax_final<<<1, 64, 0, n->stream>>>(slot, w->scale);
+  CHK(last_launch("k_absmax_final"));
   Dims d0 = dims_of(*w, 0);
   k_to_bf16_crop<<<grid_for(d0.n()), 256, 0, n->stream>>>(x, n->in_ch, src, ox, oy, oz, d0, w->scale,
                                                           round4(n->in_ch), w->x0);

@@ -298,22 +298,31 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
   }
 }
 
-// max_i |sum_c x[c][i]| over C channel-major volumes of n voxels into *out (FP64,
-// one block; 1 if the maximum is 0).
-__global__ void k_absmax(const float* __restrict__ x, long long n, int C, double* __restrict__ out) {
-  __shared__ float part[1024];
+// max_i |sum_c x[c][i]| over C channel-major volumes of n voxels: per-block maxima
+// folded into *slot with an integer atomic max (the bit patterns of non-negative
+// floats order like their values), then k_absmax_final writes it as FP64 to *out
+// (1 if the maximum is 0) and clears the slot for the next call.
+__global__ void k_absmax(const float* __restrict__ x, long long n, int C, unsigned* __restrict__ slot) {
+  __shared__ float part[256];
   float m = 0.f;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     float v = 0.f;
     for (int c = 0; c < C; ++c) v += x[c * n + i];
     m = fmaxf(m, fabsf(v));
   }
   part[threadIdx.x] = m;
   __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(slot, __float_as_uint(part[0]));
+}
+__global__ void k_absmax_final(unsigned* __restrict__ slot, double* __restrict__ out) {
   if (threadIdx.x == 0) {
-    float t = 0.f;
-    for (int q = 0; q < (int)blockDim.x; ++q) t = fmaxf(t, part[q]);
+    const float t = __uint_as_float(*slot);
     *out = t > 0.f ? (double)t : 1.0;
+    *slot = 0u;
   }
 }
 

@@ -17,7 +17,7 @@ HEADER = os.path.join(_ROOT, "include", "mh3d.h")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 FIELD_PROFILE, FIELD_ENVELOPE, FIELD_SENS, FIELD_SPECTRUM = range(4)
-NKERNEL = 8
+NKERNEL = 9
 
 
 class PlanDesc(ctypes.Structure):
