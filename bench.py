@@ -76,7 +76,7 @@ def cpu_baseline(w, rho, r, budget_s=15.0):
                       "same workload; PSF/sensitivity setup %.1f s excluded" % (n, os.cpu_count(), setup)}
 
 
-def batched_leg(batch_inputs, tol, max_iter):
+def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
     """64 uneven volumes to r_k <= tol: sequential plain solves vs one batched solve."""
     import numpy as np
     import torch
@@ -86,6 +86,8 @@ def batched_leg(batch_inputs, tol, max_iter):
     plans, ds = [], []
     for bw, ph in zip(bws, phantoms):
         p = mh3d.Plan(bw.shape, bw.harmonics, bw.a_per_mm, bw.ds, bw.sigma_mm, bw.lam, bw.voxel_mm)
+        if tile_cache is not None:
+            p.autotune(tile_cache)
         clean = p.forward(torch.tensor(ph, dtype=torch.float32, device=dev)).cpu().numpy().astype(np.float64)
         d = inputs.add_noise(clean, bw.snr_db, inputs.noise_draw(bw))
         plans.append(p)
@@ -178,6 +180,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
+    ap.add_argument("--tile-cache", default=None, help="autotuner JSON cache (default: a file in the temp dir)")
     ap.add_argument("--warm-train-steps", type=int, default=1500)
     ap.add_argument("--warm-eval", type=int, default=4)
     args = ap.parse_args()
@@ -213,6 +217,16 @@ def main():
     plan = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
+    tile_cache = None
+    tuning = {"heuristic_tiles": list(plan.tiles())}
+    if not args.no_tune:
+        import tempfile
+        tile_cache = args.tile_cache or os.path.join(tempfile.gettempdir(), "mh3d_tiles.json")
+        t0 = time.perf_counter()
+        tiles, us = plan.autotune(tile_cache)
+        tuning.update({"tiles": list(tiles), "tuned_us_per_application": round(us, 3),
+                       "tune_s": round(time.perf_counter() - t0, 3)})
+        log("autotuned tiles %s (%.2f us per A+A^T)" % (tiles, us))
     rho_t = torch.tensor(rho_true, dtype=torch.float32, device=dev)
     clean = plan.forward(rho_t).cpu().numpy().astype(np.float64)
     d = torch.tensor(inputs.add_noise(clean, w.snr_db, xi), dtype=torch.float32, device=dev)
@@ -277,6 +291,7 @@ def main():
         "kernels_us": {k: round(v["avg_us"], 3) for k, v in kernels.items()},
         "ms_per_step_profiled": round(1e3 * wall_prof / args.steps, 4),
         "plan_s": round(plan_s, 3),
+        "tiles": tuning,
     }
 
     if not args.no_solve:
@@ -295,7 +310,7 @@ def main():
                                 "status": info["status"], "identical_rerun": bool(torch.equal(rec, rec2))}
 
     if batch_inputs is not None:
-        out["batched"] = batched_leg(batch_inputs, w.tol, w.max_iter)
+        out["batched"] = batched_leg(batch_inputs, w.tol, w.max_iter, tile_cache)
 
     if not args.no_warm:
         out["warm_start"] = warm_leg(args.warm_train_steps, args.warm_eval, w.tol, w.max_iter,

@@ -142,6 +142,28 @@ mh3d_status mh3d_power_iteration(mh3d_plan_t plan, int32_t iters, uint64_t seed,
 mh3d_status mh3d_solve(mh3d_plan_t plan, const float* d, float* rho_inout,
                        const mh3d_solve_opts* opts, mh3d_solve_info* info);
 
+/* Tile shapes of the spectral passes: E spectrum elements per thread and cpw alias
+ * classes per workgroup in the class passes (E in {1, 2, 3, 4, 6, 8, 9} divides
+ * S = ds0 ds1 ds2 with S/E a power of two <= 64; cpw divides the class count, at
+ * most 1024 threads = cpw (nx/ds0) S / E), xb decimated x-planes per
+ * workgroup in the small-grid passes (divides nx/ds0).  0 = built-in heuristic.
+ * Results do not depend on the tiles (only the launch shapes change). */
+typedef struct {
+  int32_t E, cpw, xb;
+} mh3d_tiles;
+/* Sets the plan's tiles (NULL: heuristic).  Fails if a shape is invalid or does not
+ * fit, or if the plan belongs to a batch.  Synchronous. */
+mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
+mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
+/* Autotuner: times one A + A^T application (HIP events) for candidate class tiles
+ * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for the
+ * small-grid xb with the best class tiles, and leaves the fastest on the plan.
+ * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
+ * kind"; a hit applies the stored tiles without timing, a miss stores the result.
+ * tiles / us_per_application (HOST, may be NULL) receive the choice and its time.
+ * Overwrites the plan's solver volumes; synchronous. */
+mh3d_status mh3d_autotune(mh3d_plan_t plan, const char* cache_path, mh3d_tiles* tiles, double* us_per_application);
+
 /* Batched solves of many volumes (each with its own plan: uneven grids and harmonic
  * counts allowed; analytic-PSF plans only; all on the first plan's stream).  Every
  * update of every volume runs as one launch per pass over a task table of

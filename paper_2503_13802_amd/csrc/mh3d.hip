@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,12 @@ static mh3d_status fail(mh3d_status s, const char* fmt, ...) {
   g_err = buf;
   return s;
 }
+
+#define CHK(x)                          \
+  do {                                  \
+    mh3d_status s_ = (x);               \
+    if (s_ != MH3D_OK) return s_;       \
+  } while (0)
 
 #define HIPCHK(call)                                                                   \
   do {                                                                                 \
@@ -56,19 +63,88 @@ struct Launch {
   size_t lds_plane, lds_class, lds_small;
 };
 
-// Elements per thread in the class kernel: the first e of the list dividing S with
-// S/e a power of two <= 64 (so the fold reduction stays inside aligned lane groups).
-static int pick_E(int S) {
-  const int opts[7] = {8, 6, 4, 3, 2, 1, 9};
-  for (int e : opts) {
-    if (S % e) continue;
-    int lg = S / e;
-    if (lg <= 64 && (lg & (lg - 1)) == 0) return e;
-  }
-  return -1;
+// A class-kernel element split e is valid when it is one of the compiled splits
+// (1, 2, 3, 4, 6, 8, 9), divides S, and S/e is a power of two <= 64 (the fold
+// reduction then stays inside aligned lane groups).
+static bool valid_E(int S, int e) {
+  if (!(e == 1 || e == 2 || e == 3 || e == 4 || e == 6 || e == 8 || e == 9)) return false;
+  if (S % e) return false;
+  const int lg = S / e;
+  return lg <= 64 && (lg & (lg - 1)) == 0;
 }
 
-static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
+// Tile shapes of the class and small-grid kernels: E elements per thread and cpw
+// classes per workgroup (class passes), xb x' planes per workgroup (small-grid
+// passes).  A value <= 0 asks for the built-in heuristic.  Fills the derived fields
+// of g and L; fails if a requested shape is invalid or does not fit.
+static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int xb_req) {
+  // ---- class kernel: E so the launch has enough waves in flight, then cpw
+  if (E_req > 0) {
+    if (!valid_E(g.S, E_req)) return fail(MH3D_ERR_INVALID, "E = %d is not a valid split of S = %d", E_req, g.S);
+    g.E = E_req;
+  } else {
+    g.E = -1;
+    const int opts[7] = {8, 6, 4, 3, 2, 1, 9};
+    const long elems = (long)g.ncls * g.mx * g.S;
+    int fallback = -1;
+    for (int e : opts) {
+      if (!valid_E(g.S, e)) continue;
+      if (fallback < 0 || e < fallback) fallback = e;
+      if (elems / e >= 128 * 1024 && g.E < 0) g.E = e;
+    }
+    if (g.E < 0) g.E = fallback;
+    if (g.E < 0) return fail(MH3D_ERR_UNSUPPORTED, "decimation product %d has no supported fold split", g.S);
+  }
+  if (cpw_req > 0) {
+    if (g.ncls % cpw_req) return fail(MH3D_ERR_INVALID, "cpw = %d does not divide %d classes", cpw_req, g.ncls);
+    const long T = (long)cpw_req * g.mx * g.S / g.E;
+    Geo t = g;
+    t.cpw = cpw_req;
+    if (T > 1024 || class_lds_elems(t) * sizeof(float2) > 64 * 1024)
+      return fail(MH3D_ERR_INVALID, "cpw = %d gives %ld threads / too much LDS", cpw_req, T);
+    g.cpw = cpw_req;
+  } else {
+    int best_cpw = 0;
+    for (int c = 1; c <= g.ncls; ++c) {
+      if (g.ncls % c) continue;
+      const long T = (long)c * g.mx * g.S / g.E;
+      if (T > 1024) break;
+      Geo t = g;
+      t.cpw = c;
+      if (class_lds_elems(t) * sizeof(float2) > 64 * 1024) break;
+      best_cpw = c;
+      if (T >= 128 && T % 64 == 0) break;
+    }
+    if (!best_cpw) return fail(MH3D_ERR_UNSUPPORTED, "no class-kernel shape fits (mx*S/E or LDS too large)");
+    g.cpw = best_cpw;
+  }
+  L.T_class = g.cpw * g.mx * g.S / g.E;
+  L.lds_class = class_lds_elems(g) * sizeof(float2);
+
+  // ---- small kernel: x' planes per workgroup (aim for >= 256 workgroups)
+  if (xb_req > 0) {
+    if (g.mx % xb_req || xb_req > 64) return fail(MH3D_ERR_INVALID, "xb = %d does not divide mx = %d", xb_req, g.mx);
+    g.xb = xb_req;
+  } else {
+    g.xb = 1;
+    for (int xb : {8, 4, 2, 1}) {
+      if (g.mx % xb) continue;
+      if ((long)g.K * (g.mx / xb) >= 256 || xb == 1) { g.xb = xb; break; }
+    }
+  }
+  g.spairs = (g.xb * g.my + 1) / 2;
+  g.f_nz = make_fastdiv(g.nz); g.f_nzh = make_fastdiv(g.nzh); g.f_nmem = make_fastdiv(g.nmem);
+  g.f_mzh = make_fastdiv(g.mzh); g.f_sz = make_fastdiv(g.sz); g.f_mz = make_fastdiv(g.mz);
+  g.f_W = make_fastdiv(g.cpw * g.nmem); g.f_xb = make_fastdiv(g.xb); g.f_S = make_fastdiv(g.S);
+  g.f_mxS = make_fastdiv(g.mx * g.S); g.f_cpwmx = make_fastdiv(g.cpw * g.mx);
+  g.f_cpwxb = make_fastdiv(g.cpw * g.xb); g.f_ny = make_fastdiv(g.ny); g.f_my = make_fastdiv(g.my);
+  L.T_small = 256;
+  L.lds_small = sizeof(float2) * ((size_t)g.my + g.mz + 2 * (size_t)small_lds(g));
+  if (L.lds_small > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "small-grid plane does not fit in LDS");
+  return MH3D_OK;
+}
+
+static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const mh3d_tiles* tiles = nullptr) {
   if (!d) return fail(MH3D_ERR_INVALID, "descriptor is NULL");
   const int n[3] = {d->nx, d->ny, d->nz};
   for (int a = 0; a < 3; ++a) {
@@ -118,54 +194,7 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L) {
   g.lsx = pad_odd(g.nx);
   g.lsmy = pad_odd(g.my);
 
-  // ---- class kernel: elements per thread E (S/E a power of two <= 64) chosen so
-  // the launch has enough waves in flight, then classes per workgroup cpw
-  g.E = -1;
-  {
-    const int opts[7] = {8, 6, 4, 3, 2, 1, 9};
-    const long elems = (long)g.ncls * g.mx * g.S;
-    int fallback = -1;
-    for (int e : opts) {
-      if (g.S % e) continue;
-      const int lg = g.S / e;
-      if (lg > 64 || (lg & (lg - 1))) continue;
-      if (fallback < 0 || e < fallback) fallback = e;
-      if (elems / e >= 128 * 1024 && g.E < 0) g.E = e;
-    }
-    if (g.E < 0) g.E = fallback;
-  }
-  if (g.E < 0) return fail(MH3D_ERR_UNSUPPORTED, "decimation product %d has no supported fold split", g.S);
-  int best_cpw = 0;
-  for (int c = 1; c <= g.ncls; ++c) {
-    if (g.ncls % c) continue;
-    const long T = (long)c * g.mx * g.S / g.E;
-    if (T > 1024) break;
-    Geo t = g;
-    t.cpw = c;
-    if (class_lds_elems(t) * sizeof(float2) > 64 * 1024) break;
-    best_cpw = c;
-    if (T >= 128 && T % 64 == 0) break;
-  }
-  if (!best_cpw) return fail(MH3D_ERR_UNSUPPORTED, "no class-kernel shape fits (mx*S/E or LDS too large)");
-  g.cpw = best_cpw;
-  L.T_class = g.cpw * g.mx * g.S / g.E;
-  L.lds_class = class_lds_elems(g) * sizeof(float2);
-
-  // ---- small kernel: x' planes per workgroup (aim for >= 256 workgroups)
-  g.xb = 1;
-  for (int xb : {8, 4, 2, 1}) {
-    if (g.mx % xb) continue;
-    if ((long)g.K * (g.mx / xb) >= 256 || xb == 1) { g.xb = xb; break; }
-  }
-  g.spairs = (g.xb * g.my + 1) / 2;
-  g.f_nz = make_fastdiv(g.nz); g.f_nzh = make_fastdiv(g.nzh); g.f_nmem = make_fastdiv(g.nmem);
-  g.f_mzh = make_fastdiv(g.mzh); g.f_sz = make_fastdiv(g.sz); g.f_mz = make_fastdiv(g.mz);
-  g.f_W = make_fastdiv(g.cpw * g.nmem); g.f_xb = make_fastdiv(g.xb); g.f_S = make_fastdiv(g.S);
-  g.f_mxS = make_fastdiv(g.mx * g.S); g.f_cpwmx = make_fastdiv(g.cpw * g.mx);
-  g.f_cpwxb = make_fastdiv(g.cpw * g.xb); g.f_ny = make_fastdiv(g.ny); g.f_my = make_fastdiv(g.my);
-  L.T_small = 256;
-  L.lds_small = sizeof(float2) * ((size_t)g.my + g.mz + 2 * (size_t)small_lds(g));
-  if (L.lds_small > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "small-grid plane does not fit in LDS");
+  CHK(derive_tiles(g, L, tiles ? tiles->E : 0, tiles ? tiles->cpw : 0, tiles ? tiles->xb : 0));
 
   // ---- plane kernels
   L.T_plane = 1024;
@@ -209,6 +238,7 @@ struct mh3d_plan_s {
   VolDesc vdh;                 // host copy of the descriptor
   VolDesc* vdd = nullptr;      // device descriptor
   VolDesc* vdk = nullptr;      // device descriptors of the single harmonics (K of them)
+  int batch_refs = 0;          // batches holding this plan (tiles are frozen while > 0)
   int pi_iters = 0;            // cached step-size estimate: power iterations (0: none), seed, L
   uint64_t pi_seed = 0;
   double pi_lmax = 0.0;
@@ -301,12 +331,6 @@ static mh3d_status last_launch(const char* what) {
   if (e != hipSuccess) return fail(MH3D_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
   return MH3D_OK;
 }
-
-#define CHK(x)                          \
-  do {                                  \
-    mh3d_status s_ = (x);               \
-    if (s_ != MH3D_OK) return s_;       \
-  } while (0)
 
 // ---------------------------------------------------------------------------- single-volume launchers
 static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
@@ -903,6 +927,7 @@ struct mh3d_batch_s {
 extern "C" void mh3d_batch_destroy(mh3d_batch_t b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (auto* p : b->plans) p->batch_refs--;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -924,6 +949,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   }
   mh3d_batch_t b = new mh3d_batch_s();
   b->plans.assign(plans, plans + n);
+  for (auto* p : b->plans) p->batch_refs++;
   b->stream = plans[0]->stream;
   std::vector<int2> t[5];
   for (int v = 0; v < n; ++v) {
@@ -1173,4 +1199,199 @@ extern "C" mh3d_status mh3d_profile_read(mh3d_plan_t p, mh3d_profile_data* out) 
 }
 
 // ============================================================================ warm-start network
+// ============================================================================ tiles and autotuning
+static mh3d_status apply_tiles(mh3d_plan_t p, const mh3d_tiles* t) {
+  if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; set its tiles before creating the batch");
+  Geo g = p->g;
+  Launch L = p->L;
+  CHK(derive_tiles(g, L, t ? t->E : 0, t ? t->cpw : 0, t ? t->xb : 0));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->g = g;
+  p->L = L;
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  p->graph_chunk = 0;
+  fill_desc(p);
+  CHK(upload_desc(p));
+  CHK(upload_harmonic_descs(p));
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_plan_set_tiles(mh3d_plan_t p, const mh3d_tiles* tiles) {
+  CHK(check_plan(p));
+  return apply_tiles(p, tiles);
+}
+
+extern "C" mh3d_status mh3d_plan_get_tiles(mh3d_plan_t p, mh3d_tiles* tiles) {
+  CHK(check_plan(p));
+  if (!tiles) return fail(MH3D_ERR_INVALID, "tiles is NULL");
+  tiles->E = p->g.E;
+  tiles->cpw = p->g.cpw;
+  tiles->xb = p->g.xb;
+  return MH3D_OK;
+}
+
+// Cache key: device architecture, grid, harmonic count, decimation, spectrum form.
+static std::string tune_key(mh3d_plan_t p) {
+  int dev = 0;
+  std::string arch = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch = arch.substr(0, c);
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s|%dx%dx%d|K%d|ds%dx%dx%d|%s", arch.c_str(), p->g.nx, p->g.ny, p->g.nz, p->g.K, p->g.sx,
+           p->g.sy, p->g.sz, p->compact ? "analytic" : "user");
+  return buf;
+}
+
+struct TuneEntry {
+  int E, cpw, xb;
+  double us;
+};
+
+// The cache is a JSON object, one entry per line:
+//   "key": {"E": e, "cpw": c, "xb": x, "us": t},
+// Lines that do not parse are ignored (the file is rewritten on the next store).
+static std::map<std::string, TuneEntry> tune_read(const char* path) {
+  std::map<std::string, TuneEntry> m;
+  FILE* f = fopen(path, "r");
+  if (!f) return m;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    char key[256];
+    TuneEntry e;
+    if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"us\": %lf}", key, &e.E, &e.cpw, &e.xb,
+               &e.us) == 5)
+      m[key] = e;
+  }
+  fclose(f);
+  return m;
+}
+
+static void tune_write(const char* path, const std::map<std::string, TuneEntry>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : m) {
+    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"us\": %.3f}%s\n", kv.first.c_str(), kv.second.E,
+            kv.second.cpw, kv.second.xb, kv.second.us, ++i < m.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  fclose(f);
+  (void)rename(tmp.c_str(), path);
+}
+
+// Microseconds per A + A^T application with the plan's current tiles (HIP events,
+// best of two batches of 8 after 2 warm-up applications).
+static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
+  for (int i = 0; i < 2; ++i) {
+    CHK(mh3d_forward(p, p->vol[0], dtmp));
+    CHK(mh3d_adjoint(p, dtmp, p->vol[1]));
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = 1e30;
+  mh3d_status s = MH3D_OK;
+  for (int r = 0; r < 2 && s == MH3D_OK; ++r) {
+    (void)hipEventRecord(e0, p->stream);
+    for (int i = 0; i < 8 && s == MH3D_OK; ++i) {
+      s = mh3d_forward(p, p->vol[0], dtmp);
+      if (s == MH3D_OK) s = mh3d_adjoint(p, dtmp, p->vol[1]);
+    }
+    (void)hipEventRecord(e1, p->stream);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      s = fail(MH3D_ERR_HIP, "timing events failed");
+    best = std::min(best, 1e3 * ms / 8.0);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = best;
+  return s;
+}
+
+extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d_tiles* tiles, double* us_out) {
+  CHK(check_plan(p));
+  if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; tune it before creating the batch");
+  const std::string key = tune_key(p);
+  if (cache_path) {
+    const auto m = tune_read(cache_path);
+    const auto it = m.find(key);
+    if (it != m.end()) {
+      mh3d_tiles t{it->second.E, it->second.cpw, it->second.xb};
+      if (apply_tiles(p, &t) == MH3D_OK) {
+        if (tiles) *tiles = t;
+        if (us_out) *us_out = it->second.us;
+        return MH3D_OK;
+      }
+      // a stale entry (shape rules changed): tune again below
+    }
+  }
+  const Geo g0 = p->g;
+  float* dtmp = nullptr;
+  HIPCHK(hipMalloc(&dtmp, sizeof(float) * (size_t)g0.K * g0.M));
+  (void)hipMemsetAsync(p->vol[0], 0, sizeof(float) * g0.N, p->stream);
+  auto run = [&]() -> mh3d_status {
+    // phase 1: class tiles (E, cpw) with the heuristic xb; per E the smallest cpw
+    // reaching 64, 128, 256 and 512 threads
+    std::vector<mh3d_tiles> cands;
+    for (int e = 1; e <= g0.S; ++e) {
+      if (!valid_E(g0.S, e)) continue;
+      int last = 0;
+      for (int thr : {64, 128, 256, 512}) {
+        for (int c = 1; c <= g0.ncls; ++c) {
+          if (g0.ncls % c) continue;
+          const long T = (long)c * g0.mx * g0.S / e;
+          if (T > 1024) break;
+          if (T >= thr || (thr == 64 && c == g0.ncls)) {
+            if (c != last) cands.push_back(mh3d_tiles{e, c, 0});
+            last = c;
+            break;
+          }
+        }
+      }
+    }
+    mh3d_tiles best{0, 0, 0};
+    double best_us = 1e30;
+    auto trial = [&](const mh3d_tiles& t) -> mh3d_status {
+      if (apply_tiles(p, &t) != MH3D_OK) return MH3D_OK;       // shape does not fit: skip
+      double us = 0;
+      CHK(time_application(p, dtmp, &us));
+      if (us < best_us) { best_us = us; best = t; best.xb = p->g.xb; }
+      return MH3D_OK;
+    };
+    for (const auto& t : cands) CHK(trial(t));
+    // phase 2: small-grid tiles xb with the best class tiles
+    const mh3d_tiles cls = best;
+    for (int xb : {1, 2, 4, 8, 16, 32}) {
+      if (g0.mx % xb || xb == cls.xb) continue;
+      CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb}));
+    }
+    if (best_us >= 1e30) return fail(MH3D_ERR_UNSUPPORTED, "no tile shape could be timed");
+    CHK(apply_tiles(p, &best));
+    if (tiles) *tiles = best;
+    if (us_out) *us_out = best_us;
+    if (cache_path) {
+      auto m = tune_read(cache_path);
+      m[key] = TuneEntry{best.E, best.cpw, best.xb, best_us};
+      tune_write(cache_path, m);
+    }
+    return MH3D_OK;
+  };
+  mh3d_status s = run();
+  (void)hipStreamSynchronize(p->stream);
+  (void)hipFree(dtmp);
+  if (s != MH3D_OK) {
+    mh3d_tiles h{g0.E, g0.cpw, g0.xb};
+    (void)apply_tiles(p, &h);
+  }
+  return s;
+}
+
 #include "net_host.hpp"

@@ -57,6 +57,10 @@ class ProfileData(ctypes.Structure):
                 ("name", ctypes.c_char_p * NKERNEL)]
 
 
+class Tiles(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_int32), ("cpw", ctypes.c_int32), ("xb", ctypes.c_int32)]
+
+
 class MH3DError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("mh3d status %d: %s" % (status, msg))
@@ -112,6 +116,9 @@ def library():
     lib.mh3d_net_objective_grad.argtypes = [vp, vp, vp, ctypes.POINTER(dbl)]
     lib.mh3d_phantom.argtypes = [vp, ctypes.c_uint64, i32, i32, vp]
     lib.mh3d_noisy_data.argtypes = [vp, vp, ctypes.c_uint64, dbl, dbl, vp]
+    lib.mh3d_plan_set_tiles.argtypes = [vp, ctypes.POINTER(Tiles)]
+    lib.mh3d_plan_get_tiles.argtypes = [vp, ctypes.POINTER(Tiles)]
+    lib.mh3d_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tiles), ctypes.POINTER(dbl)]
     lib.mh3d_last_error.restype = ctypes.c_char_p
     lib.mh3d_version.restype = i32
     for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
@@ -119,7 +126,7 @@ def library():
                  "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch",
                  "mh3d_net_create", "mh3d_net_params", "mh3d_net_grads", "mh3d_net_forward", "mh3d_net_loss_grad",
                  "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data", "mh3d_backproject",
-                 "mh3d_net_objective_grad"):
+                 "mh3d_net_objective_grad", "mh3d_plan_set_tiles", "mh3d_plan_get_tiles", "mh3d_autotune"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -278,6 +285,24 @@ class Plan:
                "ms_total": info.ms_total, "ms_per_iter": info.ms_per_iter, "status": s,
                "history": np.array(hist[:info.iters])}
         return rho, out
+
+    def tiles(self):
+        """(E, cpw, xb) tile shapes of the spectral passes."""
+        t = Tiles()
+        _check(library().mh3d_plan_get_tiles(self._h, ctypes.byref(t)))
+        return (t.E, t.cpw, t.xb)
+
+    def set_tiles(self, E=0, cpw=0, xb=0):
+        t = Tiles(int(E), int(cpw), int(xb))
+        _check(library().mh3d_plan_set_tiles(self._h, ctypes.byref(t)))
+
+    def autotune(self, cache_path=None):
+        """Times candidate tiles and keeps the fastest; returns ((E, cpw, xb), us per A+A^T)."""
+        t = Tiles()
+        us = ctypes.c_double()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(library().mh3d_autotune(self._h, path, ctypes.byref(t), ctypes.byref(us)))
+        return (t.E, t.cpw, t.xb), us.value
 
     def backproject(self, d, out=None):
         """Per-harmonic back-projections c_k = b (H_k^T P^T d_k), [K][X][Y][Z]."""
