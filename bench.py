@@ -134,7 +134,7 @@ def warm_leg(train_steps, n_eval, tol, max_iter, with_oracle=True):
     log("warm leg: %s, network %d parameters, training %d steps" % (w.name, net.nparam, train_steps))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = warmstart.train(plan, net, train_steps, seed0=w.seed * 1000, crop=(64, 64, 64), lr=1e-3,
+    hist = warmstart.train(plan, net, train_steps, seed0=w.seed * 1000, crop=(64, 64, 64), lr=1e-3, lr_final=1e-5,
                            n_spheres=w.n_blobs, n_tubes=w.n_tubes, log=log, log_every=max(1, train_steps // 10))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
     ap.add_argument("--tile-cache", default=None, help="autotuner JSON cache (default: a file in the temp dir)")
-    ap.add_argument("--warm-train-steps", type=int, default=1500)
+    ap.add_argument("--warm-train-steps", type=int, default=20000)
     ap.add_argument("--warm-eval", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -143,13 +143,43 @@ mh3d_status net_work(mh3d_net_t n, int nx, int ny, int nz, NetWork** out) {
 
 Dims dims_of(const NetWork& w, int l) { return Dims{w.lx - l, w.ly - l, w.lz - l}; }
 
-mh3d_status conv_fwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims dm, void* out, bool relu, bool f32) {
+// One convolution out = act(conv(in, W) + bias), BF16 channels-last output with
+// channel stride cs_out (or FP32 single-channel for the head).  3x3x3 layers with at
+// most 32 output channels on grids of at least 4 x 4 x 16 run the LDS-tiled kernel.
+mh3d_status launch_conv(mh3d_net_t n, const uint16_t* in, Dims dm, int cs_in, int ks, const uint16_t* W, int kp,
+                        const float* bias, int cout, int cs_out, void* out, bool relu, bool f32) {
   const long long N = 1ll << (dm.lx + dm.ly + dm.lz);
+  const int ntile = (cout + 15) / 16;
+  const size_t halo = sizeof(uint16_t) * 648 * (size_t)cs_in;
+  if (!f32 && ks == 3 && ntile <= 2 && dm.lz >= 4 && dm.ly >= 2 && dm.lx >= 2 && halo <= 64 * 1024) {
+    const int blocks = (int)(N / 256);
+    uint16_t* o = reinterpret_cast<uint16_t*>(out);
+    if (relu) {
+      if (ntile == 1) k_conv_tiled<true, 1><<<blocks, 256, halo, n->stream>>>(in, dm, cs_in, W, kp, bias, cout, cs_out, o);
+      else k_conv_tiled<true, 2><<<blocks, 256, halo, n->stream>>>(in, dm, cs_in, W, kp, bias, cout, cs_out, o);
+    } else {
+      if (ntile == 1) k_conv_tiled<false, 1><<<blocks, 256, halo, n->stream>>>(in, dm, cs_in, W, kp, bias, cout, cs_out, o);
+      else k_conv_tiled<false, 2><<<blocks, 256, halo, n->stream>>>(in, dm, cs_in, W, kp, bias, cout, cs_out, o);
+    }
+    return last_launch("k_conv_tiled");
+  }
+  if (!f32 && (kp >> 4) >= 32 && N <= (1ll << 17)) {
+    // deep reduction on a small grid: split K over the block's waves
+    const int blocks = (int)((N + 15) / 16);
+    uint16_t* o = reinterpret_cast<uint16_t*>(out);
+    if (relu) k_conv_splitk<true><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
+    else k_conv_splitk<false><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
+    return last_launch("k_conv_splitk");
+  }
   const int blocks = (int)((N + 63) / 64);
-  if (f32) k_conv<false, true><<<blocks, 256, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out);
-  else if (relu) k_conv<true, false><<<blocks, 256, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out);
-  else k_conv<false, false><<<blocks, 256, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out);
+  if (f32) k_conv<false, true><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, out);
+  else if (relu) k_conv<true, false><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, out);
+  else k_conv<false, false><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, out);
   return last_launch("k_conv");
+}
+
+mh3d_status conv_fwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims dm, void* out, bool relu, bool f32) {
+  return launch_conv(n, in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out, relu, f32);
 }
 
 // Gradients of one conv layer given the gradient g of its (pre-activation) output:
@@ -158,18 +188,28 @@ mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
                      uint16_t* gin, float* zero_bias) {
   const long long N = 1ll << (dm.lx + dm.ly + dm.lz);
   const int ncot = (ly.cout + 15) / 16, nkc = ly.kp / 16;
-  long long chunk = 2048;
-  int nsplit = (int)((N + chunk - 1) / chunk);
-  k_conv_wgrad<<<ncot * nkc * nsplit, 64, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, g, cs_g, ly.cout, ly.kp, ly.gWf, nsplit, chunk);
-  CHK(last_launch("k_conv_wgrad"));
+  const size_t wlds = sizeof(uint16_t) * (648 * (size_t)ly.cs_in + 256 * 16 * (size_t)ncot);
+  if (ly.ks == 3 && dm.lz >= 4 && dm.ly >= 2 && dm.lx >= 2 && wlds <= 96 * 1024) {
+    const int ntiles = (int)(N >> 8);
+    const int nbg = (ncot * nkc + 15) / 16;
+    int tpb = (int)((ntiles * (long long)nbg + 767) / 768);
+    tpb = std::max(1, std::min(tpb, 64));
+    const dim3 grid((ntiles + tpb - 1) / tpb, nbg);
+    k_conv_wgrad_tiled<<<grid, 256, wlds, n->stream>>>(in, dm, ly.cs_in, g, cs_g, ly.cout, ly.kp, ly.gWf, tpb);
+    CHK(last_launch("k_conv_wgrad_tiled"));
+  } else {
+    long long chunk = 2048;
+    int nsplit = (int)((N + chunk - 1) / chunk);
+    k_conv_wgrad<<<ncot * nkc * nsplit, 64, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, g, cs_g, ly.cout, ly.kp, ly.gWf,
+                                                            nsplit, chunk);
+    CHK(last_launch("k_conv_wgrad"));
+  }
   dim3 bg(std::min<long long>(1024, (N + 3) / 4), (ly.cout + 63) / 64);
   k_bias_grad<<<bg, 256, 0, n->stream>>>(g, N, cs_g, ly.cout, n->g + ly.b_off);
   CHK(last_launch("k_bias_grad"));
   if (gin) {
     // data gradient = convolution of g with the flipped, transposed weights (no bias)
-    const int blocks = (int)((N + 63) / 64);
-    k_conv<false, false><<<blocks, 256, 0, n->stream>>>(g, dm, cs_g, ly.ks, ly.Wt, ly.kpt, zero_bias, ly.cin, ly.cs_in, gin);
-    CHK(last_launch("k_conv (data gradient)"));
+    CHK(launch_conv(n, g, dm, cs_g, ly.ks, ly.Wt, ly.kpt, zero_bias, ly.cin, ly.cs_in, gin, false, false));
   }
   return MH3D_OK;
 }
@@ -611,9 +651,44 @@ __global__ void k_phantom_objects(uint64_t seed, int nsph, int ntube, double ex,
   objs[i] = o;
 }
 
-// Voxel-centre inclusion (centres at i * voxel); overlapping objects add.  Tube
-// distance: nearest of 257 samples of the curve.
-__global__ void k_phantom_raster(Geo g, double vox, const Obj* __restrict__ objs, int nobj, float* __restrict__ rho) {
+// Tube membership by stamping: a voxel belongs to tube t when some sample of the
+// curve (t = s/256, s = 0..256) lies within r of it, i.e. the nearest of the 257
+// samples does.  One thread per (tube, sample) visits the voxels of the sample's
+// r-box and sets bit t of the voxel's flag word.  tubes <= 32; tube t is object
+// nsph + t.
+__global__ void k_phantom_stamp(Geo g, double vox, const Obj* __restrict__ objs, int nsph, int ntube,
+                                unsigned* __restrict__ flags) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ntube * 257) return;
+  const int t = id / 257, s = id - t * 257;
+  const Obj& o = objs[nsph + t];
+  const double u = s / 256.0, a0 = (1 - u) * (1 - u), a1 = 2 * (1 - u) * u, a2 = u * u;
+  const double cx = a0 * o.c[0] + a1 * o.c[3] + a2 * o.c[6];
+  const double cy = a0 * o.c[1] + a1 * o.c[4] + a2 * o.c[7];
+  const double cz = a0 * o.c[2] + a1 * o.c[5] + a2 * o.c[8];
+  const int dims[3] = {g.nx, g.ny, g.nz};
+  const double c[3] = {cx, cy, cz};
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (int)ceil((c[a] - o.r) / vox) - 1;      // one voxel of slack each side: the
+    hi[a] = (int)floor((c[a] + o.r) / vox) + 1;     // distance test below decides
+    lo[a] = lo[a] < 0 ? 0 : lo[a];
+    hi[a] = hi[a] > dims[a] - 1 ? dims[a] - 1 : hi[a];
+  }
+  for (int x = lo[0]; x <= hi[0]; ++x)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+      for (int z = lo[2]; z <= hi[2]; ++z) {
+        const double px = x * vox, py = y * vox, pz = z * vox;
+        const double d2 = (px - cx) * (px - cx) + (py - cy) * (py - cy) + (pz - cz) * (pz - cz);
+        if (d2 <= o.r * o.r) atomicOr(&flags[((long long)x * g.ny + y) * g.nz + z], 1u << t);
+      }
+}
+
+// Voxel-centre inclusion (centres at i * voxel); overlapping objects add, in object
+// order, in FP64.  Tube distance: nearest of 257 samples of the curve (from the
+// stamped flags when given, else by direct search).
+__global__ void k_phantom_raster(Geo g, double vox, const Obj* __restrict__ objs, int nobj,
+                                 const unsigned* __restrict__ flags, int nsph, float* __restrict__ rho) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N; i += (long long)gridDim.x * blockDim.x) {
     const int z = (int)(i % g.nz);
     const int y = (int)((i / g.nz) % g.ny);
@@ -625,6 +700,8 @@ __global__ void k_phantom_raster(Geo g, double vox, const Obj* __restrict__ objs
       if (o.kind == 0) {
         const double dx = px - o.c[0], dy = py - o.c[1], dz = pz - o.c[2];
         if (dx * dx + dy * dy + dz * dz <= o.r * o.r) acc += o.conc;
+      } else if (flags) {
+        if ((flags[i] >> (q - nsph)) & 1u) acc += o.conc;
       } else {
         // bounding box of the control polygon (contains the curve) grown by r
         double lo[3], hi[3];
@@ -695,14 +772,24 @@ extern "C" mh3d_status mh3d_phantom(mh3d_plan_t p, uint64_t seed, int32_t n_sphe
   const int nobj = n_spheres + n_tubes;
   Obj* objs = nullptr;
   HIPCHK(hipMalloc(&objs, sizeof(Obj) * (nobj > 0 ? nobj : 1)));
+  unsigned* flags = nullptr;
+  if (n_tubes > 0 && n_tubes <= 32) {
+    if (hipMalloc(&flags, sizeof(unsigned) * (size_t)g.N) != hipSuccess) {
+      (void)hipFree(objs);
+      return fail(MH3D_ERR_OOM, "phantom flags");
+    }
+    (void)hipMemsetAsync(flags, 0, sizeof(unsigned) * (size_t)g.N, p->stream);
+  }
   const double v = p->desc.voxel_mm;
   if (nobj)
     k_phantom_objects<<<(nobj + 63) / 64, 64, 0, p->stream>>>(seed, n_spheres, n_tubes, (g.nx - 1) * v,
                                                              (g.ny - 1) * v, (g.nz - 1) * v, objs);
-  k_phantom_raster<<<grid_for(g.N), 256, 0, p->stream>>>(g, v, objs, nobj, rho);
+  if (flags) k_phantom_stamp<<<(n_tubes * 257 + 63) / 64, 64, 0, p->stream>>>(g, v, objs, n_spheres, n_tubes, flags);
+  k_phantom_raster<<<grid_for(g.N), 256, 0, p->stream>>>(g, v, objs, nobj, flags, n_spheres, rho);
   mh3d_status s = last_launch("k_phantom_raster");
   if (hipStreamSynchronize(p->stream) != hipSuccess && s == MH3D_OK) s = fail(MH3D_ERR_HIP, "phantom kernel failed");
   (void)hipFree(objs);
+  if (flags) (void)hipFree(flags);
   return s;
 }
 

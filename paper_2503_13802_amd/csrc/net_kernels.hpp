@@ -121,6 +121,258 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, D
   }
 }
 
+// Convolution with the reduction split over the 4 waves of a block (for deep K on
+// small grids, where k_conv has too few waves to hide its load latency): the block
+// owns 16 voxels, wave w takes the K chunks w, w+4, ..., the partial tiles are
+// summed in LDS in wave order and wave 0 writes the result.  Same operands, output
+// and padding rules as k_conv (BF16 output).  grid = ceil(N/16), block = 256.
+template <bool RELU>
+__global__ __launch_bounds__(256) void k_conv_splitk(const uint16_t* __restrict__ in, Dims dm, int cs_in, int ks,
+                                                     const uint16_t* __restrict__ W, int kp,
+                                                     const float* __restrict__ bias, int cout, int cs_out,
+                                                     uint16_t* __restrict__ out) {
+  __shared__ f4v part[3][NT_MAX][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long N = dm.n();
+  const long long n0 = (long long)blockIdx.x * 16;
+  const int r = lane & 15, g = lane >> 4;
+  const long long n = n0 + r;
+  const bool nvalid = n < N;
+  int x = 0, y = 0, z = 0;
+  if (nvalid) dm.decode(n, x, y, z);
+  const int ntile = (cout + 15) >> 4;
+  const int ntap = ks * ks * ks;
+  f4v acc[NT_MAX];
+#pragma unroll
+  for (int t = 0; t < NT_MAX; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+  // k = kc*16 + 4g: start at chunk `wave`, step 4 chunks (64 k) at a time
+  int tap = 0, ci = wave * 16 + 4 * g;
+  while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  for (int kc = wave; kc < (kp >> 4); kc += 4) {
+    s4v a = s4v{0, 0, 0, 0};
+    if (nvalid && tap < ntap) {
+      int dx, dy, dz;
+      tap_offset(tap, ks, dx, dy, dz);
+      const int xx = x + dx, yy = y + dy, zz = z + dz;
+      if (dm.inside(xx, yy, zz)) a = *reinterpret_cast<const s4v*>(in + dm.encode(xx, yy, zz) * cs_in + ci);
+    }
+    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < NT_MAX; ++t) {
+      if (t < ntile) {
+        const s4v b = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    ci += 64;
+    while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  }
+  if (wave) {
+#pragma unroll
+    for (int t = 0; t < NT_MAX; ++t)
+      if (t < ntile) part[wave - 1][t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (wave) return;
+#pragma unroll
+  for (int t = 0; t < NT_MAX; ++t) {
+    if (t >= ntile) break;
+    f4v v = acc[t];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) v += part[w][t][lane];
+    const int co = t * 16 + r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long nn = n0 + 4 * g + j;
+      if (nn >= N) continue;
+      if (co < cout) {
+        float o = v[j] + bias[co];
+        if (RELU) o = fmaxf(o, 0.f);
+        out[nn * cs_out + co] = f2bf(o);
+      } else if (co < cs_out) {
+        out[nn * cs_out + co] = 0;
+      }
+    }
+  }
+}
+
+// 3x3x3 convolution on an LDS-staged input tile (the same implicit GEMM as k_conv).
+// A workgroup of 4 waves computes a 4 (x) x 4 (y) x 16 (z) output tile: the input
+// block with its one-voxel halo, 6 x 6 x 18 voxels x cs_in channels (zero outside
+// the grid), is loaded once into LDS and every tap reads the A operand from there;
+// wave w takes x = x0 + w and four 16-voxel z rows (y = y0 .. y0+3), so each weight
+// fragment feeds 4 x NT MFMAs.  Needs lz >= 4, ly >= 2, lx >= 2 and NT*16 >= cout.
+// grid = (X/4)(Y/4)(Z/16), block = 256, dynamic LDS = 648 cs_in BF16.
+template <bool RELU, int NT>
+__global__ __launch_bounds__(256) void k_conv_tiled(const uint16_t* __restrict__ in, Dims dm, int cs_in,
+                                                    const uint16_t* __restrict__ W, int kp,
+                                                    const float* __restrict__ bias, int cout, int cs_out,
+                                                    uint16_t* __restrict__ out) {
+  extern __shared__ uint16_t tile[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nzt = dm.lz - 4, nyt = dm.ly - 2;
+  const int tz = blockIdx.x & ((1 << nzt) - 1);
+  const int rest = blockIdx.x >> nzt;
+  const int ty = rest & ((1 << nyt) - 1);
+  const int tx = rest >> nyt;
+  const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 16;
+  // halo load, 4 channels (8 bytes) per item; z-runs are contiguous in global memory
+  const int cq = cs_in >> 2;
+  const int nitem = 648 * cq;
+  for (int q = threadIdx.x; q < nitem; q += 256) {
+    const int v = q / cq, c4 = q - v * cq;
+    const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
+    const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
+    s4v val = s4v{0, 0, 0, 0};
+    if (dm.inside(gx, gy, gz)) val = *reinterpret_cast<const s4v*>(in + dm.encode(gx, gy, gz) * cs_in + 4 * c4);
+    *reinterpret_cast<s4v*>(tile + v * cs_in + 4 * c4) = val;
+  }
+  __syncthreads();
+  const int r = lane & 15, g = lane >> 4;
+  f4v acc[4][NT];
+#pragma unroll
+  for (int yy = 0; yy < 4; ++yy)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[yy][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  int tap = 0, ci = 4 * g;
+  while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  const int row_stride = 18 * cs_in;            // one (x, y) row of the tile
+  for (int kc = 0; kc < (kp >> 4); ++kc) {
+    s4v b[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      b[t] = *reinterpret_cast<const s4v*>(W + (long long)(t * 16 + r) * kp + kc * 16 + 4 * g);
+    // taps past 26 only meet the zero padding rows of W: their A values stay 0
+    int off = 0;
+    const bool tv = tap < 27;
+    if (tv) {
+      const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
+      off = ((wave + dx) * 6 + dy) * row_stride + (r + dz) * cs_in + ci;
+    }
+#pragma unroll
+    for (int yy = 0; yy < 4; ++yy) {
+      s4v a = s4v{0, 0, 0, 0};
+      if (tv) a = *reinterpret_cast<const s4v*>(tile + off + yy * row_stride);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[yy][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[yy][t], 0, 0, 0);
+    }
+    ci += 16;
+    while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  }
+  // D[row = 4g + j][col = r]: voxel z0 + 4g + j of row (x0 + wave, y0 + yy), channel t*16 + r
+#pragma unroll
+  for (int yy = 0; yy < 4; ++yy) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long long nn = dm.encode(x0 + wave, y0 + yy, z0 + 4 * g + j);
+        if (co < cout) {
+          float v = acc[yy][t][j] + bias[co];
+          if (RELU) v = fmaxf(v, 0.f);
+          out[nn * cs_out + co] = f2bf(v);
+        } else if (co < cs_out) {
+          out[nn * cs_out + co] = 0;
+        }
+      }
+    }
+  }
+}
+
+// Weight gradient of a 3x3x3 layer on LDS-staged tiles:
+//   gW[co][k] += sum_n gout[n][co] in[n + d(tap(k))][ci(k)].
+// A block walks tpb consecutive 4 x 4 x 16 voxel tiles; per tile it stages the input
+// block with its halo (as k_conv_tiled) and the output gradient transposed to
+// [co][voxel] (rows up to 16*ceil(cout/16), the padding rows zero).  Its 16 output
+// blocks of 16 (co) x 16 (k) -- blockIdx.y selects which -- are spread 4 per wave;
+// per 16-voxel row an MFMA takes A[co][v] = gout[v][co], B[v][k] = in-patch[v][k].
+// The FP32 sums stay in registers over the tiles, then one atomic add per value.
+// grid = (ceil(tiles / tpb), ceil(blocks / 16)), block = 256,
+// dynamic LDS = (648 cs_in + 256 * 16 ceil(cout/16)) BF16.
+__global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t* __restrict__ in, Dims dm, int cs_in,
+                                                          const uint16_t* __restrict__ gout, int cs_g, int cout,
+                                                          int kp, float* __restrict__ gW, int tpb) {
+  extern __shared__ uint16_t sm[];
+  const int ncot = (cout + 15) >> 4, nkc = kp >> 4, nblk = ncot * nkc;
+  uint16_t* halo = sm;
+  uint16_t* gT = sm + 648 * cs_in;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g4 = lane >> 4;
+  const int nzt = dm.lz - 4, nyt = dm.ly - 2;
+  const int ntiles = (int)(dm.n() >> 8);
+  // this wave's four blocks and, per lane, the column k = kc*16 + r of each
+  int bco[4], bkc[4], boff[4];
+  bool bval[4], tval[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = blockIdx.y * 16 + wave * 4 + i;
+    bval[i] = b < nblk;
+    bco[i] = bval[i] ? b % ncot : 0;
+    bkc[i] = bval[i] ? b / ncot : 0;
+    const int k = bkc[i] * 16 + r;
+    const int tap = k / cs_in, ci = k - tap * cs_in;
+    tval[i] = bval[i] && tap < 27;
+    boff[i] = tval[i] ? (((tap / 9) * 6 + (tap / 3) % 3) * 18 + tap % 3) * cs_in + ci : 0;
+  }
+  f4v acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = f4v{0.f, 0.f, 0.f, 0.f};
+  // padding rows of the transposed gradient stay zero for every tile
+  for (int q = threadIdx.x; q < (ncot * 16 - cs_g) * 256; q += 256) gT[cs_g * 256 + q] = 0;
+  const int cq = cs_in >> 2, cqg = cs_g >> 2;
+  for (int it = 0; it < tpb; ++it) {
+    const int tile = blockIdx.x * tpb + it;
+    if (tile >= ntiles) break;
+    const int tz = tile & ((1 << nzt) - 1), rest = tile >> nzt;
+    const int ty = rest & ((1 << nyt) - 1), tx = rest >> nyt;
+    const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 16;
+    __syncthreads();      // the previous tile's reads are done
+    for (int q = threadIdx.x; q < 648 * cq; q += 256) {
+      const int v = q / cq, c4 = q - v * cq;
+      const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
+      const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
+      s4v val = s4v{0, 0, 0, 0};
+      if (dm.inside(gx, gy, gz)) val = *reinterpret_cast<const s4v*>(in + dm.encode(gx, gy, gz) * cs_in + 4 * c4);
+      *reinterpret_cast<s4v*>(halo + v * cs_in + 4 * c4) = val;
+    }
+    for (int q = threadIdx.x; q < 256 * cqg; q += 256) {
+      const int v = q % 256, c4 = q / 256;
+      const long long nn = dm.encode(x0 + (v >> 6), y0 + ((v >> 4) & 3), z0 + (v & 15));
+      const s4v val = *reinterpret_cast<const s4v*>(gout + nn * cs_g + 4 * c4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gT[(4 * c4 + j) * 256 + v] = (uint16_t)val[j];
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int vc = 0; vc < 16; ++vc) {
+      // voxels v = vc*16 + 4*g4 + j: row (xl, yl) = (vc / 4, vc % 4), z = 4*g4 + j
+      const int rowoff = ((vc >> 2) * 6 + (vc & 3)) * 18 * cs_in + 4 * g4 * cs_in;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (!bval[i]) continue;
+        const s4v a = *reinterpret_cast<const s4v*>(gT + (bco[i] * 16 + r) * 256 + vc * 16 + 4 * g4);
+        s4v b = s4v{0, 0, 0, 0};
+        if (tval[i]) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = (short)halo[boff[i] + rowoff + j * cs_in];
+        }
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+      }
+    }
+  }
+  // D[row = 4*g4 + j][col = r] -> (co = bco*16 + 4*g4 + j, k = bkc*16 + r)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (!bval[i]) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = bco[i] * 16 + 4 * g4 + j;
+      if (co < cout && acc[i][j] != 0.f) atomicAdd(&gW[(long long)co * kp + bkc[i] * 16 + r], acc[i][j]);
+    }
+  }
+}
+
 // Weight gradient  gW[co][k] += sum_n gout[n][co] in[n + d(tap(k))][ci(k)]
 // (FP32 atomics).  grid = co_tiles * k_tiles * nsplit blocks of one wave; each
 // wave reduces over its voxel range in chunks of 16 (4 voxels per lane group).

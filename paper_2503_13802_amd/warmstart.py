@@ -1,6 +1,7 @@
 """Training and use of the warm-start network (driver only: every step runs in the
 library's kernels -- phantoms, forward model, noise, back-projection, network
 forward/backward and Adam)."""
+import math
 import time
 
 import numpy as np
@@ -20,7 +21,7 @@ def crop_origin(seed, shape, crop):
 
 def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spheres=80, n_tubes=6,
           snr=(20.0, 40.0), decay_db=3.0, log=None, log_every=100, target="phantom", crops_per_sample=1,
-          solve_tol=1e-4, solve_max_iter=5000):
+          solve_tol=1e-4, solve_max_iter=5000, lr_final=None):
     """Trains `net` on `steps` crops of phantom/portrait pairs generated on the GPU from
     the plan's forward model (sample j uses seed seed0 + j; each sample serves
     crops_per_sample consecutive steps).  target "phantom" regresses the phantom;
@@ -28,7 +29,8 @@ def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spher
     point a warm-started solve converges to); "objective" trains on the full volume
     against the solver's objective at the network's output (mh3d_net_objective_grad;
     the logged value is ||grad F|| / ||A^T d||).  Returns the loss history (every
-    log_every steps)."""
+    log_every steps).  lr_final: cosine decay of the learning rate from lr to lr_final
+    over the steps (constant lr if None)."""
     hist = []
     t0 = time.perf_counter()
     x = tgt = None
@@ -49,7 +51,11 @@ def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spher
         else:
             o = crop_origin(seed * 131 + j % crops_per_sample, plan.shape, crop)
             loss = net.loss_grad(x, tgt, list(o) + list(crop), want_loss=want)
-        net.adam_step(lr)
+        if lr_final is None:
+            lr_j = lr
+        else:
+            lr_j = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * j / max(1, steps - 1)))
+        net.adam_step(lr_j)
         if want:
             hist.append((j, loss))
             if log:
