@@ -123,13 +123,15 @@ def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
             "note": "step sizes (50 batched power iterations per volume) computed once, untimed, for both forms"}
 
 
-def warm_leg(train_steps, n_eval, tol, max_iter, with_oracle=True):
+def warm_leg(train_steps, n_eval, tol, max_iter, with_oracle=True, tile_cache=None):
     """Warm-start workload: GPU training, then cold vs warm solves on held-out seeds."""
     import numpy as np
     import torch
     from paper_2503_13802_amd import inputs, mh3d, warmstart
     w = inputs.workload(4)
     plan = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
+    if tile_cache is not None:
+        plan.autotune(tile_cache)
     net = mh3d.Net((8, 16, 32, 80), in_channels=len(w.harmonics), seed=w.seed)
     log("warm leg: %s, network %d parameters, training %d steps" % (w.name, net.nparam, train_steps))
     torch.cuda.synchronize()
@@ -169,6 +171,73 @@ def warm_leg(train_steps, n_eval, tol, max_iter, with_oracle=True):
     return out
 
 
+SHIPPED_TILES = os.path.join(ROOT, "paper_2503_13802_amd", "tiles_gfx950.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_class_workload1.md")
+
+
+def tile_cache_path(arg):
+    """The autotuner cache: the given path, else a temp copy of the shipped one."""
+    if arg:
+        return arg
+    import shutil
+    import tempfile
+    path = os.path.join(tempfile.gettempdir(), "mh3d_tiles.json")
+    if os.path.exists(SHIPPED_TILES) and not os.path.exists(path):
+        shutil.copyfile(SHIPPED_TILES, path)
+    return path
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources; counter results are only valid for the code they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2503_13802_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload_name, tiles):
+    """HBM bytes per class-kernel launch from the committed counter summary, if it was
+    taken on the current kernel sources, workload and tiles (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("traffic-json: "):
+                    t = json.loads(line[len("traffic-json: "):])
+                    if (t["source_hash"] == kernel_source_hash() and t["workload"] == workload_name
+                            and list(t["tiles"]) == list(tiles)):
+                        return t
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def pmc_driver(args):
+    """Counter-run driver: tuned plan of the workload, 20 A+A^T steps, then a 256 MiB
+    device copy (the calibration kernel of known size)."""
+    import torch
+    from paper_2503_13802_amd import inputs, mh3d
+    w = inputs.workload(args.workload)
+    plan = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
+    if not args.no_tune:
+        plan.autotune(tile_cache_path(args.tile_cache))
+    dev = torch.device("cuda:0")
+    src = torch.tensor(inputs.random_field(w.shape, 1), dtype=torch.float32, device=dev)
+    y = torch.empty((len(w.harmonics),) + w.small_shape, device=dev)
+    x = torch.empty(w.shape, device=dev)
+    for _ in range(20):
+        plan.forward(src, out=y)
+        plan.adjoint(y, out=x)
+    a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("pmc driver: %s tiles %s, 20 A+A^T steps, 5 copies of 256 MiB" % (w.name, plan.tiles()), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,14 +253,20 @@ def main():
     ap.add_argument("--tile-cache", default=None, help="autotuner JSON cache (default: a file in the temp dir)")
     ap.add_argument("--warm-train-steps", type=int, default=20000)
     ap.add_argument("--warm-eval", type=int, default=4)
+    ap.add_argument("--pmc-driver", action="store_true",
+                    help="only run the workload's A+A^T steps and a copy of known size (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU; a multi-GPU run is not part of it "
-              "(volumes would shard one per GPU with no exchange)", file=sys.stderr)
+        print("bench.py runs on one GPU only; more GPUs would each take whole volumes of a batch "
+              "with no exchange between them, which is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     from paper_2503_13802_amd import inputs
+
+    if args.pmc_driver:
+        pmc_driver(args)
+        return
 
     batch_inputs = None
     if not args.no_batch:
@@ -220,8 +295,7 @@ def main():
     tile_cache = None
     tuning = {"heuristic_tiles": list(plan.tiles())}
     if not args.no_tune:
-        import tempfile
-        tile_cache = args.tile_cache or os.path.join(tempfile.gettempdir(), "mh3d_tiles.json")
+        tile_cache = tile_cache_path(args.tile_cache)
         t0 = time.perf_counter()
         tiles, us = plan.autotune(tile_cache)
         tuning.update({"tiles": list(tiles), "tuned_us_per_application": round(us, 3),
@@ -260,11 +334,14 @@ def main():
     prof = plan.profile_read()
     plan.profile(False)
     op_bytes, spec_bytes = algorithmic_bytes(w)
-    ms_f, n_f = prof["class_fwd"]
-    ms_a, n_a = prof["class_adj"]
-    avg_s = (ms_f + ms_a) / max(1, n_f + n_a) / 1e3
+    # the dominant kernels' launch duration: back-to-back launches between two HIP
+    # events on the plan's stream (per-launch events would add their own overhead)
+    pass_us = {k: plan.time_pass(k, reps=200) for k in mh3d.Plan.PASSES}
+    avg_s = 0.5 * (pass_us["class_fwd"] + pass_us["class_adj"]) * 1e-6
     achieved = spec_bytes / avg_s / 1e9
     kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in prof.items() if v[1]}
+    st = stored_traffic(w.name, plan.tiles())
+    traffic = None if st is None else st["bytes_per_launch"]
     log("kernels: " + json.dumps(kernels))
 
     out = {
@@ -284,11 +361,12 @@ def main():
                    "decimation": list(w.ds), "a_per_mm": w.a_per_mm, "lambda": w.lam},
         "roofline": {"bound": "hbm", "kernel": "class_fwd+class_adj (spectral multiply + alias fold)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": spec_bytes, "avg_launch_us": round(avg_s * 1e6, 3)},
         "operator_GBps": round(2 * op_bytes / (ms_per_step / 1e3) / 1e9, 1),
         "operator_bytes_per_application": op_bytes,
-        "kernels_us": {k: round(v["avg_us"], 3) for k, v in kernels.items()},
+        "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
+        "kernels_us_event_per_launch": {k: round(v["avg_us"], 3) for k, v in kernels.items()},
         "ms_per_step_profiled": round(1e3 * wall_prof / args.steps, 4),
         "plan_s": round(plan_s, 3),
         "tiles": tuning,
@@ -314,7 +392,7 @@ def main():
 
     if not args.no_warm:
         out["warm_start"] = warm_leg(args.warm_train_steps, args.warm_eval, w.tol, w.max_iter,
-                                     with_oracle=not args.no_cpu)
+                                     with_oracle=not args.no_cpu, tile_cache=tile_cache)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

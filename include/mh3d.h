@@ -260,6 +260,11 @@ typedef struct {
 } mh3d_profile_data;
 mh3d_status mh3d_profile(mh3d_plan_t plan, int32_t enable);
 mh3d_status mh3d_profile_read(mh3d_plan_t plan, mh3d_profile_data* out);
+/* Average microseconds per launch of one pass (0 plane_fwd, 1 class_fwd, 2 small_inv,
+ * 3 small_fwd, 4 class_adj, 5 plane_adj) over reps back-to-back launches between two
+ * HIP events on the plan's stream, after one A and A^T to set its inputs.  Overwrites
+ * the plan's solver volumes; profiling must be off; synchronous. */
+mh3d_status mh3d_time_pass(mh3d_plan_t plan, int32_t pass, int32_t reps, double* us);
 
 /* One Philox4x32-10 block computed on the device (known-answer checks of the
  * generator used by mh3d_power_iteration).  ctr[4], key[2], out[4] are HOST

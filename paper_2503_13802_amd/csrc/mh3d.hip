@@ -1199,6 +1199,49 @@ extern "C" mh3d_status mh3d_profile_read(mh3d_plan_t p, mh3d_profile_data* out) 
 }
 
 // ============================================================================ warm-start network
+// ============================================================================ pass timing
+extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps, double* us) {
+  CHK(check_plan(p));
+  if (pass < 0 || pass > 5 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");
+  if (p->prof_on) return fail(MH3D_ERR_INVALID, "disable mh3d_profile before timing passes");
+  float* dtmp = nullptr;
+  HIPCHK(hipMalloc(&dtmp, sizeof(float) * (size_t)p->g.K * p->g.M));
+  (void)hipMemsetAsync(p->vol[0], 0, sizeof(float) * p->g.N, p->stream);
+  (void)hipMemsetAsync(dtmp, 0, sizeof(float) * (size_t)p->g.K * p->g.M, p->stream);
+  auto launch = [&]() -> mh3d_status {
+    switch (pass) {
+      case 0: return launch_plane_fwd(p, SRC_PLAIN, p->vol[0]);
+      case 1: return launch_class_fwd(p, 0);
+      case 2: return launch_small_inv(p, EPI_STORE, dtmp);
+      case 3: return launch_small_fwd(p, dtmp);
+      case 4: return launch_class_adj(p, 0);
+      default: return launch_plane_adj(p, OUT_SCALE_B, p->vol[1], nullptr);
+    }
+  };
+  mh3d_status s = MH3D_OK;
+  // the passes' inputs: one full A and A^T first so every intermediate buffer is set
+  s = mh3d_forward(p, p->vol[0], dtmp);
+  if (s == MH3D_OK) s = mh3d_adjoint(p, dtmp, p->vol[1]);
+  for (int i = 0; i < 3 && s == MH3D_OK; ++i) s = launch();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s == MH3D_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    s = fail(MH3D_ERR_HIP, "event creation failed");
+  if (s == MH3D_OK) {
+    (void)hipEventRecord(e0, p->stream);
+    for (int i = 0; i < reps && s == MH3D_OK; ++i) s = launch();
+    (void)hipEventRecord(e1, p->stream);
+    float ms = 0.f;
+    if (s == MH3D_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      s = fail(MH3D_ERR_HIP, "timing events failed");
+    *us = 1e3 * (double)ms / reps;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(p->stream);
+  (void)hipFree(dtmp);
+  return s;
+}
+
 // ============================================================================ tiles and autotuning
 static mh3d_status apply_tiles(mh3d_plan_t p, const mh3d_tiles* t) {
   if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; set its tiles before creating the batch");

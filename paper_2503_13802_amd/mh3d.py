@@ -119,6 +119,7 @@ def library():
     lib.mh3d_plan_set_tiles.argtypes = [vp, ctypes.POINTER(Tiles)]
     lib.mh3d_plan_get_tiles.argtypes = [vp, ctypes.POINTER(Tiles)]
     lib.mh3d_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tiles), ctypes.POINTER(dbl)]
+    lib.mh3d_time_pass.argtypes = [vp, i32, i32, ctypes.POINTER(dbl)]
     lib.mh3d_last_error.restype = ctypes.c_char_p
     lib.mh3d_version.restype = i32
     for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
@@ -126,7 +127,7 @@ def library():
                  "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch",
                  "mh3d_net_create", "mh3d_net_params", "mh3d_net_grads", "mh3d_net_forward", "mh3d_net_loss_grad",
                  "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data", "mh3d_backproject",
-                 "mh3d_net_objective_grad", "mh3d_plan_set_tiles", "mh3d_plan_get_tiles", "mh3d_autotune"):
+                 "mh3d_net_objective_grad", "mh3d_plan_set_tiles", "mh3d_plan_get_tiles", "mh3d_autotune", "mh3d_time_pass"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -285,6 +286,14 @@ class Plan:
                "ms_total": info.ms_total, "ms_per_iter": info.ms_per_iter, "status": s,
                "history": np.array(hist[:info.iters])}
         return rho, out
+
+    PASSES = ("plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj", "plane_adj")
+
+    def time_pass(self, name, reps=200):
+        """Average microseconds per launch of one pass, back to back between two events."""
+        us = ctypes.c_double()
+        _check(library().mh3d_time_pass(self._h, self.PASSES.index(name), int(reps), ctypes.byref(us)))
+        return us.value
 
     def tiles(self):
         """(E, cpw, xb) tile shapes of the spectral passes."""
