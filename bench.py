@@ -1,8 +1,10 @@
 """Benchmark of the MH3D hot path on one MI355X.
 
 A step is one application of the forward operator A followed by its adjoint A^T
-(Sec. 4.1 eq. dN; each accelerated-projected-gradient update of Sec. 4.3 costs one
-of each) on the workload's resident inputs.  The JSON line reports A+A^T
+applied to A's output (Sec. 4.1 eq. dN; each accelerated-projected-gradient update of
+Sec. 4.3 costs one of each) on the workload's resident inputs: d = A rho is written to
+HBM and x = A^T d is computed by the five-pass sequence whose third pass writes d and
+starts A^T on it.  The rate of the two separate calls (six passes) is reported beside it.  The JSON line reports A+A^T
 applications per second, the HBM roofline of the dominant kernel (measured with
 HIP events around its launches), the FP64 CPU oracle timed on a bounded sample of
 the same workload, and the time to reconstruct at r_k <= 1e-4 with the plain solver.
@@ -74,6 +76,31 @@ def cpu_baseline(w, rho, r, budget_s=15.0):
     return {"value": n / el, "unit": "A+A^T applications/s", "cores": os.cpu_count(), "kind": "oracle",
             "sample": "%d full A+A^T applications of the FP64 FFT-tier oracle (scipy.fft, workers=%d) on the "
                       "same workload; PSF/sensitivity setup %.1f s excluded" % (n, os.cpu_count(), setup)}
+
+
+def parity_leg(w, plan, rho_true, xi):
+    """The reconstruction against the FP64 oracle (a11): the oracle forward model makes
+    the data, the oracle's own power iteration gives tau, both solvers stop at
+    r_k <= tol; the relative L2 difference and both update counts are reported."""
+    import numpy as np
+    import torch
+    from oracle import model as om
+    from oracle import philox as oph
+    from oracle import solver as osv
+    from paper_2503_13802_amd import inputs
+    t0 = time.perf_counter()
+    op = osv.Operator(om.psf_bank(w.shape, list(w.harmonics), w.a_per_mm, w.voxel_mm),
+                      om.sensitivity(w.shape, w.sigma_mm, w.voxel_mm), w.ds, w.lam)
+    d = inputs.add_noise(op.A(rho_true), w.snr_db, xi)
+    tau = osv.step_size(osv.power_iteration(op, oph.uniform01(0, 0, w.n_voxels).reshape(w.shape), 50))
+    want, _, n_o = osv.fista(op, d, tau, max_iter=w.max_iter, tol=w.tol)
+    cpu_s = time.perf_counter() - t0
+    got, info = plan.solve(torch.tensor(d, dtype=torch.float32, device="cuda"), max_iter=w.max_iter, tol=w.tol,
+                           tau=tau)
+    got = got.cpu().numpy().astype(np.float64)
+    return {"rel_l2_vs_oracle": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+            "gpu_iters": info["iters"], "oracle_iters": int(n_o), "tau": tau, "oracle_s": round(cpu_s, 1),
+            "note": "oracle data, oracle tau, both stop at r_k <= %g" % w.tol}
 
 
 def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
@@ -309,11 +336,16 @@ def main():
     src = rho_t.clone()
 
     def step():
+        # d = A src and x = A^T d (five passes: the pass writing d starts A^T on it)
+        plan.forward_adjoint(src, d_out=y, x_out=x)
+
+    def step_separate():
         plan.forward(src, out=y)
         plan.adjoint(y, out=x)
 
     for _ in range(args.warmup):
         step()
+        step_separate()
     torch.cuda.synchronize()
     log("timing %d steps" % args.steps)
     t0 = time.perf_counter()
@@ -323,6 +355,11 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps / wall
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_separate()
+    torch.cuda.synchronize()
+    separate_per_s = args.steps / (time.perf_counter() - t0)
 
     # per-kernel HIP-event timing over a second pass of the same steps
     plan.profile(True)
@@ -363,6 +400,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": spec_bytes, "avg_launch_us": round(avg_s * 1e6, 3)},
+        "separate_calls_per_s": round(separate_per_s, 2),
         "operator_GBps": round(2 * op_bytes / (ms_per_step / 1e3) / 1e9, 1),
         "operator_bytes_per_application": op_bytes,
         "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
@@ -393,6 +431,10 @@ def main():
     if not args.no_warm:
         out["warm_start"] = warm_leg(args.warm_train_steps, args.warm_eval, w.tol, w.max_iter,
                                      with_oracle=not args.no_cpu, tile_cache=tile_cache)
+
+    if not args.no_cpu and not args.no_solve:
+        log("parity of the reconstruction against the FP64 oracle")
+        out["parity"] = parity_leg(w, plan, rho_true, xi)
 
     if not args.no_cpu:
         log("cpu baseline (oracle)")

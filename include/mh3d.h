@@ -119,6 +119,10 @@ mh3d_status mh3d_forward(mh3d_plan_t plan, const float* rho, float* d);
 /* rho = A^T d (adjoint of eq. dN).  d: portraits, rho: volume. */
 mh3d_status mh3d_adjoint(mh3d_plan_t plan, const float* d, float* rho);
 
+/* d = A rho and x = A^T d in one sequence of five passes: the pass that writes d also
+ * starts A^T on it (the same arithmetic as mh3d_forward then mh3d_adjoint, bitwise). */
+mh3d_status mh3d_forward_adjoint(mh3d_plan_t plan, const float* rho, float* d, float* x);
+
 /* Per-harmonic back-projections c_k = b (H_k^T P^T d_k), the terms of A^T d before
  * the sum over harmonics (adjoint of eq. dN, one harmonic at a time); sum_k c_k =
  * A^T d.  d: portraits, c: DEVICE [n_harm][nx][ny][nz]. */
@@ -216,12 +220,7 @@ mh3d_status mh3d_net_loss_grad(mh3d_net_t net, const float* x, const float* t, i
 mh3d_status mh3d_net_adam_step(mh3d_net_t net, float lr, float beta1, float beta2, float eps);
 /* rho_init = s * max(net(c / s), 0), c = mh3d_backproject(d), s = max |A^T d|.  The
  * network has n_harm input channels; plan and net share a stream. */
-/* Gradient of the Sec. 4.3 objective F(rho_init) = 1/2 ||A rho_init - d||^2 +
- * lambda/2 ||T rho_init||^2 with respect to the network parameters (kept in the
- * network, as mh3d_net_loss_grad does; scaled by 1/N).  Uses the plan's solver
- * volumes as scratch.  *rel_grad (HOST, may be NULL; synchronous if given) receives
- * ||grad_rho F|| / ||A^T d|| at rho_init. */
-mh3d_status mh3d_net_objective_grad(mh3d_plan_t plan, mh3d_net_t net, const float* d, double* rel_grad);
+
 mh3d_status mh3d_warm_start(mh3d_plan_t plan, mh3d_net_t net, const float* d, float* rho_init);
 
 /* Training data on the GPU.  mh3d_phantom: n_spheres spheres (radius U(2,5) mm)

@@ -605,7 +605,7 @@ __global__ __launch_bounds__(1024) void k_class_adj_batch(const VolDesc* __restr
 #undef MH3D_E_SWITCH
 
 // ============================================================================ pass 3: small grid
-enum { EPI_STORE = 0, EPI_RESID = 1, EPI_RESID_BACK = 2, EPI_BACK = 3 };
+enum { EPI_STORE = 0, EPI_RESID = 1, EPI_RESID_BACK = 2, EPI_BACK = 3, EPI_STORE_BACK = 4 };
 
 // Small-grid LDS layout: column (xi, q'z) holds the y' line at
 // X[(xi*mzh + q'z)*lsmy + y'], rows r = xi*my + y' of real data are packed in pairs.
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ 
     const int r = (int)g.f_mz.div((uint32_t)p), z = p - r * g.mz;
     return 2 * ((r >> 1) * lsmz + z) + (r & 1);
   };
-  if constexpr (EPI == EPI_STORE) {
+  if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_BACK) {
     for (int p = threadIdx.x; p < n; p += blockDim.x) d[obase + p] = Zf[lidx(p)];
   } else if constexpr (EPI == EPI_RESID) {
     batched<8, float>(n, [&](int p) { return dmeas[obase + p]; },
@@ -685,8 +685,8 @@ __global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ 
     batched<8, float>(n, [&](int p) { return dmeas[obase + p]; },
                       [&](int p, float m) { const int li = lidx(p); Zf[li] = Zf[li] - m; });
   }
-  // EPI_BACK keeps the values in place
-  if constexpr (EPI == EPI_RESID_BACK || EPI == EPI_BACK) {
+  // EPI_BACK keeps the values in place; EPI_STORE_BACK stores them and transforms them back
+  if constexpr (EPI == EPI_RESID_BACK || EPI == EPI_BACK || EPI == EPI_STORE_BACK) {
     if (rows & 1) {
       for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * lsmz + z) + 1] = 0.f;
     }

@@ -387,6 +387,7 @@ static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d) {
   switch (epi) {
     case EPI_STORE: k_small_inv<EPI_STORE><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
     case EPI_RESID_BACK: k_small_inv<EPI_RESID_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
+    case EPI_STORE_BACK: k_small_inv<EPI_STORE_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
     default: k_small_inv<EPI_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
   }
   return last_launch("k_small_inv");
@@ -644,6 +645,17 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
 // ============================================================================ operators
 static mh3d_status check_plan(mh3d_plan_t p) {
   if (!p) return fail(MH3D_ERR_INVALID, "plan is NULL");
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, float* d, float* x) {
+  CHK(check_plan(p));
+  if (!rho || !d || !x) return fail(MH3D_ERR_INVALID, "NULL array");
+  CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
+  CHK(launch_class_fwd(p, 0));
+  CHK(launch_small_inv(p, EPI_STORE_BACK, d));   // stores d and starts A^T on it in place
+  CHK(launch_class_adj(p, 0));
+  CHK(launch_plane_adj(p, OUT_SCALE_B, x, nullptr));
   return MH3D_OK;
 }
 

@@ -41,7 +41,7 @@ struct NetWork {
   float* xin = nullptr;                   // warm start: per-harmonic back-projections [C][N0] (lazy)
   uint16_t* gy = nullptr;                 // head output gradient [N0][4]
   double* scale = nullptr;                // max |x| of the current input
-  double* loss = nullptr;                 // loss; loss[1], loss[2]: objective-gradient norms
+  double* loss = nullptr;
 };
 
 }  // namespace
@@ -131,7 +131,7 @@ mh3d_status net_work(mh3d_net_t n, int nx, int ny, int nz, NetWork** out) {
   }
   CHK(mk(nvox(0) * 4, &w.gy));
   CHK(net_alloc((void**)&w.y, sizeof(float) * (size_t)nvox(0)));
-  // [scale, loss, objective-gradient norms (2), absmax slot]
+  // [scale, loss, (unused), (unused), absmax slot]
   CHK(net_alloc((void**)&w.scale, sizeof(double) * 5));
   (void)hipMemsetAsync(w.scale, 0, sizeof(double) * 5, n->stream);
   w.loss = w.scale + 1;
@@ -349,34 +349,6 @@ __global__ void k_net_init(float* __restrict__ p, long long wo, long long nw, in
   }
 }
 
-// Objective training: rho = s max(y, 0), g = (A^T A + lambda T^T T) rho - A^T d (the
-// gradient of the Sec. 4.3 objective at rho); the output gradient is
-// gy = s [y > 0] g / N (BF16, channel 0 of [N][cs]).  acc[0] += ||g||^2,
-// acc[1] += ||A^T d||^2 (FP64, one atomic per block).
-__global__ void k_objective_grad(const float* __restrict__ y, const float* __restrict__ nrho,
-                                 const float* __restrict__ atd, const double* __restrict__ scale, long long n, int cs,
-                                 uint16_t* __restrict__ gy, double* __restrict__ acc) {
-  __shared__ double part[2][256];
-  const float s = (float)*scale, inv_n = 1.f / (float)n;
-  double a0 = 0.0, a1 = 0.0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const float g = nrho[i] - atd[i];
-    a0 += (double)g * g;
-    a1 += (double)atd[i] * atd[i];
-    gy[i * cs] = f2bf(y[i] > 0.f ? s * g * inv_n : 0.f);
-    for (int c = 1; c < cs; ++c) gy[i * cs + c] = 0;
-  }
-  part[0][threadIdx.x] = a0;
-  part[1][threadIdx.x] = a1;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t0 = 0.0, t1 = 0.0;
-    for (int q = 0; q < (int)blockDim.x; ++q) { t0 += part[0][q]; t1 += part[1][q]; }
-    atomicAdd(&acc[0], t0);
-    atomicAdd(&acc[1], t1);
-  }
-}
-
 }  // namespace
 
 // ============================================================================ network ABI
@@ -553,41 +525,6 @@ extern "C" mh3d_status mh3d_net_adam_step(mh3d_net_t n, float lr, float beta1, f
   k_adam<<<grid_for(n->nparam), 256, 0, n->stream>>>(n->p, n->g, n->m, n->v, n->nparam, lr, beta1, beta2, eps, c1, c2);
   CHK(last_launch("k_adam"));
   CHK(net_pack(n));
-  return MH3D_OK;
-}
-
-extern "C" mh3d_status mh3d_net_objective_grad(mh3d_plan_t p, mh3d_net_t n, const float* d, double* rel_grad) {
-  CHK(check_plan(p));
-  if (!n || !d) return fail(MH3D_ERR_INVALID, "NULL argument");
-  const Geo& g = p->g;
-  CHK(net_check_dims(n, g.nx, g.ny, g.nz));
-  if (n->stream != p->stream) return fail(MH3D_ERR_INVALID, "network and plan must share a stream");
-  if (n->in_ch != g.K) return fail(MH3D_ERR_INVALID, "network has %d input channels, plan %d harmonics", n->in_ch, g.K);
-  NetWork* w;
-  CHK(net_work(n, g.nx, g.ny, g.nz, &w));
-  if (!w->xin) CHK(net_alloc((void**)&w->xin, sizeof(float) * (size_t)g.K * g.N));
-  CHK(mh3d_backproject(p, d, w->xin));
-  CHK(net_zero_grads(n));
-  Dims src{ilog2(g.nx), ilog2(g.ny), ilog2(g.nz)};
-  CHK(net_forward(n, w, w->xin, src, g.N, 0, 0, 0));
-  // the plan's solver volumes serve as scratch (no solve is in flight on this stream)
-  float* rho = p->vol[0];
-  float* nrho = p->vol[1];
-  float* atd = p->vol[2];
-  k_scale_relu<<<grid_for(g.N), 256, 0, p->stream>>>(w->y, g.N, w->scale, rho);
-  CHK(last_launch("k_scale_relu"));
-  CHK(mh3d_normal(p, rho, nrho));
-  CHK(mh3d_adjoint(p, d, atd));
-  k_fill_f64<<<1, 64, 0, n->stream>>>(w->loss, 3, 0.0);
-  k_objective_grad<<<grid_for(g.N), 256, 0, p->stream>>>(w->y, nrho, atd, w->scale, g.N, 4, w->gy, w->loss + 1);
-  CHK(last_launch("k_objective_grad"));
-  CHK(net_backward(n, w));
-  if (rel_grad) {
-    double h[2];
-    HIPCHK(hipMemcpyAsync(h, w->loss + 1, sizeof(h), hipMemcpyDeviceToHost, n->stream));
-    HIPCHK(hipStreamSynchronize(n->stream));
-    *rel_grad = h[1] > 0 ? sqrt(h[0] / h[1]) : 0.0;
-  }
   return MH3D_OK;
 }
 

@@ -113,13 +113,13 @@ def library():
     lib.mh3d_net_loss_grad.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(dbl)]
     lib.mh3d_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
     lib.mh3d_warm_start.argtypes = [vp, vp, vp, vp]
-    lib.mh3d_net_objective_grad.argtypes = [vp, vp, vp, ctypes.POINTER(dbl)]
     lib.mh3d_phantom.argtypes = [vp, ctypes.c_uint64, i32, i32, vp]
     lib.mh3d_noisy_data.argtypes = [vp, vp, ctypes.c_uint64, dbl, dbl, vp]
     lib.mh3d_plan_set_tiles.argtypes = [vp, ctypes.POINTER(Tiles)]
     lib.mh3d_plan_get_tiles.argtypes = [vp, ctypes.POINTER(Tiles)]
     lib.mh3d_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tiles), ctypes.POINTER(dbl)]
     lib.mh3d_time_pass.argtypes = [vp, i32, i32, ctypes.POINTER(dbl)]
+    lib.mh3d_forward_adjoint.argtypes = [vp, vp, vp, vp]
     lib.mh3d_last_error.restype = ctypes.c_char_p
     lib.mh3d_version.restype = i32
     for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
@@ -127,7 +127,8 @@ def library():
                  "mh3d_profile_read", "mh3d_philox4x32_10", "mh3d_batch_create", "mh3d_solve_batch",
                  "mh3d_net_create", "mh3d_net_params", "mh3d_net_grads", "mh3d_net_forward", "mh3d_net_loss_grad",
                  "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data", "mh3d_backproject",
-                 "mh3d_net_objective_grad", "mh3d_plan_set_tiles", "mh3d_plan_get_tiles", "mh3d_autotune", "mh3d_time_pass"):
+                 "mh3d_plan_set_tiles", "mh3d_plan_get_tiles", "mh3d_autotune", "mh3d_time_pass",
+                 "mh3d_forward_adjoint"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -250,6 +251,14 @@ class Plan:
         out = self.torch.empty((self.K,) + self.small, device=self.device) if out is None else out
         _check(library().mh3d_forward(self._h, _ptr(rho), _ptr(out)))
         return out
+
+    def forward_adjoint(self, rho, d_out=None, x_out=None):
+        """(A rho, A^T A rho) in one five-pass sequence."""
+        rho = self._vol(rho)
+        d = self.torch.empty((self.K,) + self.small, device=self.device) if d_out is None else d_out
+        x = self.torch.empty(self.shape, device=self.device) if x_out is None else x_out
+        _check(library().mh3d_forward_adjoint(self._h, _ptr(rho), _ptr(d), _ptr(x)))
+        return d, x
 
     def adjoint(self, d, out=None):
         d = self._port(d)
@@ -470,14 +479,6 @@ class Net:
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         _check(library().mh3d_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))
-
-    def objective_grad(self, plan, d, want=True):
-        """Parameter gradient of the solver objective at the network's initialiser;
-        returns ||grad F|| / ||A^T d|| if want."""
-        d = plan._port(d)
-        g = ctypes.c_double()
-        _check(library().mh3d_net_objective_grad(plan._h, self._h, _ptr(d), ctypes.byref(g) if want else None))
-        return g.value if want else None
 
     def warm_start(self, plan, d):
         """rho_init = s * max(net(A^T d / s), 0) on the plan's grid."""

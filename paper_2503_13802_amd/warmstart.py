@@ -19,6 +19,13 @@ def crop_origin(seed, shape, crop):
     return [int(rng.integers(0, n - c + 1)) for n, c in zip(shape, crop)]
 
 
+def learning_rate(j, steps, lr, lr_final=None):
+    """Step j of `steps`: lr, or a cosine decay from lr (j = 0) to lr_final (last step)."""
+    if lr_final is None:
+        return lr
+    return lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * j / max(1, steps - 1)))
+
+
 def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spheres=80, n_tubes=6,
           snr=(20.0, 40.0), decay_db=3.0, log=None, log_every=100, target="phantom", crops_per_sample=1,
           solve_tol=1e-4, solve_max_iter=5000, lr_final=None):
@@ -26,9 +33,7 @@ def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spher
     the plan's forward model (sample j uses seed seed0 + j; each sample serves
     crops_per_sample consecutive steps).  target "phantom" regresses the phantom;
     "solution" regresses the plain solver's end point at solve_tol from rho = 0 (the
-    point a warm-started solve converges to); "objective" trains on the full volume
-    against the solver's objective at the network's output (mh3d_net_objective_grad;
-    the logged value is ||grad F|| / ||A^T d||).  Returns the loss history (every
+    point a warm-started solve converges to).  Returns the loss history (every
     log_every steps).  lr_final: cosine decay of the learning rate from lr to lr_final
     over the steps (constant lr if None)."""
     hist = []
@@ -40,22 +45,15 @@ def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spher
         if j % crops_per_sample == 0:
             rho = plan.phantom(seed, n_spheres, n_tubes)
             d = plan.noisy_data(rho, seed, sample_snr2(seed, *snr), decay_db)
-            x = plan.backproject(d) if target != "objective" else None
+            x = plan.backproject(d)
             if target == "solution":
                 tgt, _ = plan.solve(d, max_iter=solve_max_iter, tol=solve_tol, tau=0.0)
             else:
                 tgt = rho
         want = (j % log_every == 0) or (j == steps - 1)
-        if target == "objective":
-            loss = net.objective_grad(plan, d, want=want)
-        else:
-            o = crop_origin(seed * 131 + j % crops_per_sample, plan.shape, crop)
-            loss = net.loss_grad(x, tgt, list(o) + list(crop), want_loss=want)
-        if lr_final is None:
-            lr_j = lr
-        else:
-            lr_j = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * j / max(1, steps - 1)))
-        net.adam_step(lr_j)
+        o = crop_origin(seed * 131 + j % crops_per_sample, plan.shape, crop)
+        loss = net.loss_grad(x, tgt, list(o) + list(crop), want_loss=want)
+        net.adam_step(learning_rate(j, steps, lr, lr_final))
         if want:
             hist.append((j, loss))
             if log:

@@ -218,3 +218,18 @@ def test_deterministic_bitwise():
     u = p.adjoint(a).clone()
     v = p.adjoint(a).clone()
     assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("shape,harm,ds,a,sig", [CASES[1], CASES[5], CASES[10], ((96, 96, 64), tuple(range(2, 9)),
+                                                                                  (2, 2, 2), 1.2, 20.0)])
+def test_forward_adjoint_fused_equals_separate_calls(shape, harm, ds, a, sig):
+    """The five-pass A-then-A^T sequence gives bitwise the separate calls' results."""
+    torch = torch_cuda()
+    announce("forward_adjoint %s" % (shape,))
+    p = _plan(shape, harm, a, ds, sig)
+    x = torch.tensor(inputs.random_field(shape, 13), dtype=torch.float32, device="cuda")
+    d1 = p.forward(x).clone()
+    x1 = p.adjoint(d1).clone()
+    d2, x2 = p.forward_adjoint(x)
+    assert torch.equal(d1, d2)
+    assert torch.equal(x1, x2)
