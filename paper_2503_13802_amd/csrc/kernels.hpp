@@ -379,7 +379,9 @@ __host__ __device__ inline size_t class_lds_elems(const Geo& g) {
   return (size_t)g.nx + g.mx + 2 * W * g.lsx + 2 * (size_t)g.K * g.cpw * g.mx;
 }
 
-constexpr int HPF = 4;   // harmonics of spectra prefetched ahead in the class kernels
+// Harmonics of spectra prefetched ahead in the class kernels: 8 for compact spectra
+// with up to 4 elements per thread (the whole ring costs <= 32 registers), else 4.
+__host__ __device__ constexpr int hpf_of(int HC, int E) { return (HC == 0 && E <= 4) ? 8 : 4; }
 
 // Position of class-layout element p of a (k, x'-block, class, x'-in-block) store,
 // p over K*cpw*mx, as offsets into F ((k*cpw + c)*mx + x') and G.
@@ -396,6 +398,7 @@ __device__ __forceinline__ void class_g_index(const Geo& g, int p, int c0, int& 
 // part in the barriers and shuffles (batched launches use the largest block size).
 template <int HC, int E>
 __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
+  constexpr int HPF = hpf_of(HC, E);
   const Geo& g = vd.g;
   extern __shared__ float2 lds[];
   const int W = g.cpw * g.nmem;
@@ -481,6 +484,7 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
 // Adjoint pass 2 of one block.
 template <int HC, int E>
 __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
+  constexpr int HPF = hpf_of(HC, E);
   const Geo& g = vd.g;
   extern __shared__ float2 lds[];
   const int W = g.cpw * g.nmem;
@@ -820,10 +824,11 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
 }
 
 // Blocks of the volume-wide update pass, each a contiguous run of whole 1024-voxel
-// tiles (at most 256 blocks: one arrival atomic per block on the volume's counter).
+// tiles: about 2048 voxels per block, at most 256 blocks (one per CU; their FP64
+// partials are summed by k_vol_finish).
 constexpr int UPD_THREADS = 1024;
 __host__ __device__ inline int update_blocks(long long n) {
-  long long b = (n + 8191) / 8192;
+  long long b = (n + 2047) / 2048;
   return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
 }
 

@@ -170,3 +170,13 @@ def test_trained_network_saves_iterations():
     for ec, ew, ei in errs:
         assert ei < 1.0          # the initialiser is closer than rho = 0
         assert ew <= 2.0 * ec + 1e-3
+    # both end points reach the same objective level (FP64 oracle evaluation)
+    from oracle import model as om
+    from oracle import solver as osv
+    op = osv.Operator(om.psf_bank(shape, list(harm), 1.2), om.sensitivity(shape, 20.0), (2, 2, 2), 1e-3)
+    for r in res:
+        d = r["d"].cpu().numpy().astype(np.float64)
+        fc = op.objective(r["cold"].cpu().numpy().astype(np.float64), d)
+        fw = op.objective(r["warm"].cpu().numpy().astype(np.float64), d)
+        print("objective cold %.6e warm %.6e" % (fc, fw), flush=True)
+        assert fw <= 1.05 * fc
