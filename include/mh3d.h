@@ -151,9 +151,13 @@ mh3d_status mh3d_solve(mh3d_plan_t plan, const float* d, float* rho_inout,
  * S = ds0 ds1 ds2 with S/E a power of two <= 64; cpw divides the class count, at
  * most 1024 threads = cpw (nx/ds0) S / E), xb decimated x-planes per
  * workgroup in the small-grid passes (divides nx/ds0).  0 = built-in heuristic.
- * Results do not depend on the tiles (only the launch shapes change). */
+ * ps > 1 splits each x-plane over ps workgroups: all transform the whole plane along
+ * its first axis, each takes a share of the second-axis transforms (at most
+ * min(nz/2 + 1, (ny + 1)/2) workgroups).  Results do not depend on the tiles (only
+ * the launch shapes change). */
 typedef struct {
   int32_t E, cpw, xb;
+  int32_t ps;                /* workgroups per x-plane in the plane passes: 1 to 4 */
 } mh3d_tiles;
 /* Sets the plan's tiles (NULL: heuristic).  Fails if a shape is invalid or does not
  * fit, or if the plan belongs to a batch.  Synchronous. */
@@ -161,7 +165,8 @@ mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
 mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
 /* Autotuner: times one A + A^T application (HIP events) for candidate class tiles
  * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for the
- * small-grid xb with the best class tiles, and leaves the fastest on the plan.
+ * small-grid xb with the best class tiles, then for ps, and leaves the fastest on
+ * the plan.
  * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
  * kind"; a hit applies the stored tiles without timing, a miss stores the result.
  * tiles / us_per_application (HOST, may be NULL) receive the choice and its time.

@@ -47,6 +47,7 @@ struct Geo {
   int cpw;                 // classes per class-kernel workgroup (divides ncls)
   int E;                   // spectrum elements per thread in the class kernel (divides S)
   int xb;                  // x' planes per small-grid workgroup (divides mx)
+  int ps;                  // workgroups per x-plane in the plane passes (1 or 2)
   int npairs;              // (ny + 1)/2 row pairs of one full x-plane
   int spairs;              // (xb*my + 1)/2 row pairs of one small-grid workgroup
   int lsy;                 // LDS line stride of y-transforms in the plane kernels (ny + pad)

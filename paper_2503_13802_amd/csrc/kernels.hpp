@@ -252,6 +252,25 @@ __device__ float2* c2r_rows(float2* a, float2* b, const float2* twz, int nrows, 
   return fft_lines<+1>(b, a, twz, nz, npairs, lsz);
 }
 
+// c2r_rows restricted to the row pairs [j0, j1): pair j lands at line j - j0.
+__device__ float2* c2r_rows_range(float2* a, float2* b, const float2* twz, int nrows, int nz, int j0, int j1,
+                                  const RowCols& rc, const FastDiv& f_nz) {
+  const int lsz = pad_odd(nz);
+  const int items = (j1 - j0) * nz;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int jl = (int)f_nz.div((uint32_t)it), q = it - jl * nz;
+    const int j = j0 + jl;
+    const bool up = 2 * q > nz;
+    const int qq = up ? nz - q : q;
+    float2 x = a[rc.base(2 * j) + qq * rc.qstride];
+    float2 y = (2 * j + 1 < nrows) ? a[rc.base(2 * j + 1) + qq * rc.qstride] : make_float2(0.f, 0.f);
+    if (qq == 0 || 2 * qq == nz) { x.y = 0.f; y.y = 0.f; }
+    if (up) { x.y = -x.y; y.y = -y.y; }
+    b[jl * lsz + q] = make_float2(x.x - y.y, x.y + y.x);      // x + i y
+  }
+  return fft_lines<+1>(b, a, twz, nz, j1 - j0, lsz);
+}
+
 __device__ __forceinline__ RowCols plane_rowcols(const Geo& g) {
   RowCols rc;
   rc.qstride = g.lsy;
@@ -283,7 +302,11 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
   float2* twy = twz + g.nz;
   float2* P0 = twy + g.ny;
   float2* P1 = P0 + pl;
-  const int x = plane_of_block(lb, g.nx);
+  // ps workgroups per plane: all of them transform every row along z, workgroup h
+  // then takes the y-transforms of the columns qz in [q0, q1)
+  const int h = lb / g.nx;
+  const int x = plane_of_block(lb - h * g.nx, g.nx);
+  const int q0 = h * g.nzh / g.ps, q1 = (h + 1) * g.nzh / g.ps;
   load_table(twz, vd.tw + vd.off[2], g.nz);
   load_table(twy, vd.tw + vd.off[1], g.ny);
   float c = 1.f;
@@ -303,18 +326,22 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
   }
   const RowCols rc = plane_rowcols(g);
   float2* X = r2c_rows(P0, P1, twz, g.ny, g.nz, g.nzh, g.npairs, rc, g.f_nzh);   // X[qz][lsy]
-  float2* Y = fft_lines<-1>(X, X == P0 ? P1 : P0, twy, g.ny, g.nzh, g.lsy);
+  // column qz of the result at Y[(qz - q0) * lsy]
+  float2* Y = fft_lines<-1>(X + q0 * g.lsy, (X == P0 ? P1 : P0) + q0 * g.lsy, twy, g.ny, q1 - q0, g.lsy);
   float2* dst = vd.uperm + (long long)x * g.plane;
   for (int e = threadIdx.x; e < g.plane; e += blockDim.x) {
     const int cc = (int)g.f_nmem.div((uint32_t)e), m = e - cc * g.nmem;
     const int cy = (int)g.f_mzh.div((uint32_t)cc), cz = cc - cy * g.mzh;
     const int jy = (int)g.f_sz.div((uint32_t)m), jz = m - jy * g.sz;
     const int qy = cy + jy * g.my, qz = cz + jz * g.mz;
+    const bool direct = 2 * qz <= g.nz;
+    const int col = direct ? qz : g.nz - qz;
+    if (col < q0 || col >= q1) continue;
     float2 v;
-    if (2 * qz <= g.nz) {
-      v = Y[qz * g.lsy + qy];
+    if (direct) {
+      v = Y[(col - q0) * g.lsy + qy];
     } else {
-      v = Y[(g.nz - qz) * g.lsy + (qy == 0 ? 0 : g.ny - qy)];
+      v = Y[(col - q0) * g.lsy + (qy == 0 ? 0 : g.ny - qy)];
       v.y = -v.y;
     }
     dst[e] = v;
@@ -779,7 +806,7 @@ __device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, De
 //   OUT_SCALE_B  ao.out = b . v                          (A^T)
 //   OUT_U        vd.u = b . v  (the A^T A part of a solver step; skipped once the
 //                volume's solve is done; k_vol_update finishes the step)
-// grid = nx blocks (one x-plane each).
+// grid = ps * nx blocks (ps per x-plane).
 template <int OUT>
 __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
                                                     AdjOut ao) {
@@ -797,7 +824,11 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   float2* P1 = P0 + pl;
   load_table(twz, vd.tw + vd.off[2], g.nz);
   load_table(twy, vd.tw + vd.off[1], g.ny);
-  const int x = plane_of_block(lb, g.nx);
+  // ps workgroups per plane: all of them transform every column along y, workgroup h
+  // then takes the z-transforms of the row pairs [j0, j1)
+  const int h = lb / g.nx;
+  const int x = plane_of_block(lb - h * g.nx, g.nx);
+  const int j0 = h * g.npairs / g.ps, j1 = (h + 1) * g.npairs / g.ps;
   const float2* src = vd.uperm + (long long)x * g.plane;
   batched<8, float2>(g.plane, [&](int e) { return src[e]; }, [&](int e, float2 v) { P1[e] = v; });
   __syncthreads();
@@ -809,18 +840,20 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
     P0[qz * g.lsy + qy] = cj ? make_float2(v.x, -v.y) : v;
   }
   float2* X = fft_lines<+1>(P0, P1, twy, g.ny, g.nzh, g.lsy);
-  float2* Z = c2r_rows(X, X == P0 ? P1 : P0, twz, g.ny, g.nz, g.npairs, plane_rowcols(g), g.f_nz);
+  float2* Z = c2r_rows_range(X, X == P0 ? P1 : P0, twz, g.ny, g.nz, j0, j1, plane_rowcols(g), g.f_nz);
   const int lsz = pad_odd(g.nz);
   const float* Xf = reinterpret_cast<const float*>(Z);
+  // rows [2 j0, min(2 j1, ny)) of the plane; row y is in line (y >> 1) - j0
+  const int y0 = 2 * j0, y1 = 2 * j1 < g.ny ? 2 * j1 : g.ny;
   auto vidx = [&](int p) {
     const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
-    return 2 * ((y >> 1) * lsz + z) + (y & 1);
+    return 2 * (((y >> 1) - j0) * lsz + z) + (y & 1);
   };
   const float* __restrict__ b = vd.b;
-  const long long pbase = (long long)x * g.ny * g.nz;
+  const long long pbase = (long long)x * g.ny * g.nz + (long long)y0 * g.nz;
   float* __restrict__ out = (OUT == OUT_U) ? vd.u : ao.out;
-  batched<8, float>(g.ny * g.nz, [&](int p) { return b[pbase + p]; },
-                    [&](int p, float bv) { out[pbase + p] = bv * Xf[vidx(p)]; });
+  batched<8, float>((y1 - y0) * g.nz, [&](int p) { return b[pbase + p]; },
+                    [&](int p, float bv) { out[pbase + p] = bv * Xf[vidx(p + y0 * g.nz)]; });
 }
 
 // Blocks of the volume-wide update pass, each a contiguous run of whole 1024-voxel

@@ -77,7 +77,7 @@ static bool valid_E(int S, int e) {
 // classes per workgroup (class passes), xb x' planes per workgroup (small-grid
 // passes).  A value <= 0 asks for the built-in heuristic.  Fills the derived fields
 // of g and L; fails if a requested shape is invalid or does not fit.
-static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int xb_req) {
+static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int xb_req, int ps_req) {
   // ---- class kernel: E so the launch has enough waves in flight, then cpw
   if (E_req > 0) {
     if (!valid_E(g.S, E_req)) return fail(MH3D_ERR_INVALID, "E = %d is not a valid split of S = %d", E_req, g.S);
@@ -133,6 +133,12 @@ static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int x
     }
   }
   g.spairs = (g.xb * g.my + 1) / 2;
+  // ---- plane passes: workgroups per x-plane (2 unless asked otherwise; each takes a
+  // share of the columns / row pairs, so at most min(nz/2 + 1, (ny + 1)/2) of them)
+  if (ps_req > 4 || ps_req > g.nzh || ps_req > g.npairs)
+    return fail(MH3D_ERR_INVALID, "ps = %d: the plane passes take 1 to 4 workgroups per plane (at most "
+                "min(nz/2+1, (ny+1)/2))", ps_req);
+  g.ps = ps_req > 0 ? ps_req : 2;
   g.f_nz = make_fastdiv(g.nz); g.f_nzh = make_fastdiv(g.nzh); g.f_nmem = make_fastdiv(g.nmem);
   g.f_mzh = make_fastdiv(g.mzh); g.f_sz = make_fastdiv(g.sz); g.f_mz = make_fastdiv(g.mz);
   g.f_W = make_fastdiv(g.cpw * g.nmem); g.f_xb = make_fastdiv(g.xb); g.f_S = make_fastdiv(g.S);
@@ -194,7 +200,7 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   g.lsx = pad_odd(g.nx);
   g.lsmy = pad_odd(g.my);
 
-  CHK(derive_tiles(g, L, tiles ? tiles->E : 0, tiles ? tiles->cpw : 0, tiles ? tiles->xb : 0));
+  CHK(derive_tiles(g, L, tiles ? tiles->E : 0, tiles ? tiles->cpw : 0, tiles ? tiles->xb : 0, tiles ? tiles->ps : 0));
 
   // ---- plane kernels
   L.T_plane = 1024;
@@ -335,7 +341,7 @@ static mh3d_status last_launch(const char* what) {
 // ---------------------------------------------------------------------------- single-volume launchers
 static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
   Timer t(p, KID_PLANE_FWD);
-  dim3 grid(p->g.nx), block(p->L.T_plane);
+  dim3 grid(p->g.ps * p->g.nx), block(p->L.T_plane);
   const size_t lds = p->L.lds_plane;
   switch (src) {
     case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
@@ -403,7 +409,7 @@ static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const floa
                                     const VolDesc* vd = nullptr) {
   Timer t(p, KID_PLANE_ADJ);
   if (!vd) vd = p->vdd;
-  dim3 grid(p->g.nx), block(p->L.T_plane);
+  dim3 grid(p->g.ps * p->g.nx), block(p->L.T_plane);
   const size_t lds = p->L.lds_plane;
   AdjOut ao;
   ao.out = o;
@@ -966,7 +972,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   std::vector<int2> t[5];
   for (int v = 0; v < n; ++v) {
     const mh3d_plan_t p = plans[v];
-    for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
+    for (int i = 0; i < p->g.ps * p->g.nx; ++i) t[0].push_back(make_int2(v, i));
     for (int i = 0; i < p->g.ncls / p->g.cpw; ++i) t[1].push_back(make_int2(v, i));
     for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
     for (int i = 0; i < update_blocks(p->g.N); ++i) t[3].push_back(make_int2(v, i));
@@ -1259,7 +1265,7 @@ static mh3d_status apply_tiles(mh3d_plan_t p, const mh3d_tiles* t) {
   if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; set its tiles before creating the batch");
   Geo g = p->g;
   Launch L = p->L;
-  CHK(derive_tiles(g, L, t ? t->E : 0, t ? t->cpw : 0, t ? t->xb : 0));
+  CHK(derive_tiles(g, L, t ? t->E : 0, t ? t->cpw : 0, t ? t->xb : 0, t ? t->ps : 0));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->g = g;
   p->L = L;
@@ -1283,6 +1289,7 @@ extern "C" mh3d_status mh3d_plan_get_tiles(mh3d_plan_t p, mh3d_tiles* tiles) {
   tiles->E = p->g.E;
   tiles->cpw = p->g.cpw;
   tiles->xb = p->g.xb;
+  tiles->ps = p->g.ps;
   return MH3D_OK;
 }
 
@@ -1303,12 +1310,12 @@ static std::string tune_key(mh3d_plan_t p) {
 }
 
 struct TuneEntry {
-  int E, cpw, xb;
+  int E, cpw, xb, ps;
   double us;
 };
 
 // The cache is a JSON object, one entry per line:
-//   "key": {"E": e, "cpw": c, "xb": x, "us": t},
+//   "key": {"E": e, "cpw": c, "xb": x, "ps": s, "us": t},
 // Lines that do not parse are ignored (the file is rewritten on the next store).
 static std::map<std::string, TuneEntry> tune_read(const char* path) {
   std::map<std::string, TuneEntry> m;
@@ -1318,8 +1325,8 @@ static std::map<std::string, TuneEntry> tune_read(const char* path) {
   while (fgets(line, sizeof line, f)) {
     char key[256];
     TuneEntry e;
-    if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"us\": %lf}", key, &e.E, &e.cpw, &e.xb,
-               &e.us) == 5)
+    if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"us\": %lf}", key, &e.E,
+               &e.cpw, &e.xb, &e.ps, &e.us) == 6)
       m[key] = e;
   }
   fclose(f);
@@ -1333,8 +1340,8 @@ static void tune_write(const char* path, const std::map<std::string, TuneEntry>&
   fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m) {
-    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"us\": %.3f}%s\n", kv.first.c_str(), kv.second.E,
-            kv.second.cpw, kv.second.xb, kv.second.us, ++i < m.size() ? "," : "");
+    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
+            kv.second.E, kv.second.cpw, kv.second.xb, kv.second.ps, kv.second.us, ++i < m.size() ? "," : "");
   }
   fprintf(f, "}\n");
   fclose(f);
@@ -1379,7 +1386,7 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     const auto m = tune_read(cache_path);
     const auto it = m.find(key);
     if (it != m.end()) {
-      mh3d_tiles t{it->second.E, it->second.cpw, it->second.xb};
+      mh3d_tiles t{it->second.E, it->second.cpw, it->second.xb, it->second.ps};
       if (apply_tiles(p, &t) == MH3D_OK) {
         if (tiles) *tiles = t;
         if (us_out) *us_out = it->second.us;
@@ -1405,20 +1412,20 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
           const long T = (long)c * g0.mx * g0.S / e;
           if (T > 1024) break;
           if (T >= thr || (thr == 64 && c == g0.ncls)) {
-            if (c != last) cands.push_back(mh3d_tiles{e, c, 0});
+            if (c != last) cands.push_back(mh3d_tiles{e, c, 0, 0});
             last = c;
             break;
           }
         }
       }
     }
-    mh3d_tiles best{0, 0, 0};
+    mh3d_tiles best{0, 0, 0, 0};
     double best_us = 1e30;
     auto trial = [&](const mh3d_tiles& t) -> mh3d_status {
       if (apply_tiles(p, &t) != MH3D_OK) return MH3D_OK;       // shape does not fit: skip
       double us = 0;
       CHK(time_application(p, dtmp, &us));
-      if (us < best_us) { best_us = us; best = t; best.xb = p->g.xb; }
+      if (us < best_us) { best_us = us; best = t; best.xb = p->g.xb; best.ps = p->g.ps; }
       return MH3D_OK;
     };
     for (const auto& t : cands) CHK(trial(t));
@@ -1426,15 +1433,19 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     const mh3d_tiles cls = best;
     for (int xb : {1, 2, 4, 8, 16, 32}) {
       if (g0.mx % xb || xb == cls.xb) continue;
-      CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb}));
+      CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb, cls.ps}));
     }
+    // phase 3: workgroups per x-plane in the plane passes
+    const mh3d_tiles sm = best;
+    for (int ps : {1, 2, 4})
+      if (ps != sm.ps && ps <= g0.nzh && ps <= g0.npairs) CHK(trial(mh3d_tiles{sm.E, sm.cpw, sm.xb, ps}));
     if (best_us >= 1e30) return fail(MH3D_ERR_UNSUPPORTED, "no tile shape could be timed");
     CHK(apply_tiles(p, &best));
     if (tiles) *tiles = best;
     if (us_out) *us_out = best_us;
     if (cache_path) {
       auto m = tune_read(cache_path);
-      m[key] = TuneEntry{best.E, best.cpw, best.xb, best_us};
+      m[key] = TuneEntry{best.E, best.cpw, best.xb, best.ps, best_us};
       tune_write(cache_path, m);
     }
     return MH3D_OK;
@@ -1443,7 +1454,7 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
   (void)hipStreamSynchronize(p->stream);
   (void)hipFree(dtmp);
   if (s != MH3D_OK) {
-    mh3d_tiles h{g0.E, g0.cpw, g0.xb};
+    mh3d_tiles h{g0.E, g0.cpw, g0.xb, g0.ps};
     (void)apply_tiles(p, &h);
   }
   return s;

@@ -58,7 +58,7 @@ class ProfileData(ctypes.Structure):
 
 
 class Tiles(ctypes.Structure):
-    _fields_ = [("E", ctypes.c_int32), ("cpw", ctypes.c_int32), ("xb", ctypes.c_int32)]
+    _fields_ = [("E", ctypes.c_int32), ("cpw", ctypes.c_int32), ("xb", ctypes.c_int32), ("ps", ctypes.c_int32)]
 
 
 class MH3DError(RuntimeError):
@@ -305,22 +305,22 @@ class Plan:
         return us.value
 
     def tiles(self):
-        """(E, cpw, xb) tile shapes of the spectral passes."""
+        """(E, cpw, xb, ps) tile shapes of the spectral and plane passes."""
         t = Tiles()
         _check(library().mh3d_plan_get_tiles(self._h, ctypes.byref(t)))
-        return (t.E, t.cpw, t.xb)
+        return (t.E, t.cpw, t.xb, t.ps)
 
-    def set_tiles(self, E=0, cpw=0, xb=0):
-        t = Tiles(int(E), int(cpw), int(xb))
+    def set_tiles(self, E=0, cpw=0, xb=0, ps=0):
+        t = Tiles(int(E), int(cpw), int(xb), int(ps))
         _check(library().mh3d_plan_set_tiles(self._h, ctypes.byref(t)))
 
     def autotune(self, cache_path=None):
-        """Times candidate tiles and keeps the fastest; returns ((E, cpw, xb), us per A+A^T)."""
+        """Times candidate tiles and keeps the fastest; returns ((E, cpw, xb, ps), us per A+A^T)."""
         t = Tiles()
         us = ctypes.c_double()
         path = None if cache_path is None else str(cache_path).encode()
         _check(library().mh3d_autotune(self._h, path, ctypes.byref(t), ctypes.byref(us)))
-        return (t.E, t.cpw, t.xb), us.value
+        return (t.E, t.cpw, t.xb, t.ps), us.value
 
     def backproject(self, d, out=None):
         """Per-harmonic back-projections c_k = b (H_k^T P^T d_k), [K][X][Y][Z]."""

@@ -50,12 +50,13 @@ def test_every_tile_shape_matches_oracle(shape, harm, ds, a, sig):
             for xb in [x for x in (1, 2, 4) if mx % x == 0]:
                 if cpw * mx * S // E > 1024:
                     continue
+                ps = (1, 2, 4)[tried % 3]
                 try:
-                    p.set_tiles(E, cpw, xb)
+                    p.set_tiles(E, cpw, xb, ps)
                 except mh3d.MH3DError as e:       # shape exceeds the LDS budget
                     assert "LDS" in str(e)
                     continue
-                assert p.tiles() == (E, cpw, xb)
+                assert p.tiles() == (E, cpw, xb, ps)
                 d = p.forward(torch.tensor(rho, dtype=torch.float32)).cpu().numpy()
                 x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
                 assert rel_l2(d, d_ref) <= TOL, (E, cpw, xb)
@@ -65,6 +66,8 @@ def test_every_tile_shape_matches_oracle(shape, harm, ds, a, sig):
     from paper_2503_13802_amd.mh3d import MH3DError
     with pytest.raises(MH3DError):
         p.set_tiles(E=5 if S % 5 else 7)       # not a valid split of S
+    with pytest.raises(MH3DError):
+        p.set_tiles(ps=5)
 
 
 def test_autotune_cache_round_trip(tmp_path):
@@ -80,7 +83,7 @@ def test_autotune_cache_round_trip(tmp_path):
     stored = json.loads(cache.read_text())
     (key, ent), = stored.items()
     assert key.endswith("|96x96x64|K7|ds2x2x2|analytic")
-    assert (ent["E"], ent["cpw"], ent["xb"]) == tiles
+    assert (ent["E"], ent["cpw"], ent["xb"], ent["ps"]) == tiles
     # a second plan of the same geometry reads the cache without timing
     q = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam)
     tiles2, us2 = q.autotune(str(cache))
