@@ -932,6 +932,7 @@ struct mh3d_batch_s {
   std::vector<mh3d_plan_t> plans;
   hipStream_t stream;
   VolDesc* vds = nullptr;            // device descriptors of all volumes
+  std::vector<VolDesc> hvd;          // their host copies (plane passes at one workgroup per plane)
   int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // plane, class, small, update, per-volume
   int ntask[5] = {0, 0, 0, 0, 0};
   int T_class = 0;
@@ -972,7 +973,9 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   std::vector<int2> t[5];
   for (int v = 0; v < n; ++v) {
     const mh3d_plan_t p = plans[v];
-    for (int i = 0; i < p->g.ps * p->g.nx; ++i) t[0].push_back(make_int2(v, i));
+    // one workgroup per x-plane: the batch already fills the chip with the planes of
+    // many volumes, so splitting planes would only add work
+    for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
     for (int i = 0; i < p->g.ncls / p->g.cpw; ++i) t[1].push_back(make_int2(v, i));
     for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
     for (int i = 0; i < update_blocks(p->g.N); ++i) t[3].push_back(make_int2(v, i));
@@ -984,6 +987,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   }
   auto bail = [&](mh3d_status s) { mh3d_batch_destroy(b); return s; };
   if (hipMalloc(&b->vds, sizeof(VolDesc) * n) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch descriptors"));
+  b->hvd.resize(n);
   for (int i = 0; i < 5; ++i) {
     b->ntask[i] = (int)t[i].size();
     if (hipMalloc(&b->tasks[i], sizeof(int2) * t[i].size()) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch tasks"));
@@ -991,6 +995,14 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
       return bail(fail(MH3D_ERR_HIP, "upload of batch tasks failed"));
   }
   *out = b;
+  return MH3D_OK;
+}
+
+// Device descriptor of volume v: the plan's, with one workgroup per x-plane.
+static mh3d_status batch_upload(mh3d_batch_t b, int v) {
+  b->hvd[v] = b->plans[v]->vdh;
+  b->hvd[v].g.ps = 1;
+  HIPCHK(hipMemcpyAsync(b->vds + v, &b->hvd[v], sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
   return MH3D_OK;
 }
 
@@ -1052,7 +1064,7 @@ static mh3d_status batch_power(mh3d_batch_t b, int iters, uint64_t seed, std::ve
     hipLaunchKernelGGL(k_philox_uniform, dim3(256), dim3(256), 0, p->stream, (long long)p->g.N, seed, 0u, p->vol[0],
                        p->partials, p->st);
     CHK(last_launch("k_philox_uniform"));
-    HIPCHK(hipMemcpyAsync(b->vds + v, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
+    CHK(batch_upload(b, v));
   }
   for (int t = 0; t < iters; ++t) CHK(batch_power_step(b, b->stream));
   std::vector<DevState> hs(n);
@@ -1102,7 +1114,7 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
   for (int v = 0; v < n; ++v) {
     mh3d_plan_t p = b->plans[v];
     CHK(solve_setup(p, d[v], rho_inout[v], opts, tau[v]));
-    HIPCHK(hipMemcpyAsync(b->vds + v, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
+    CHK(batch_upload(b, v));
   }
   const int chunk = opts->check_every > 0 ? opts->check_every : 16;
   if (!b->gexec || b->chunk != chunk) {
