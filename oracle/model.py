@@ -198,19 +198,43 @@ def second_difference(y, axis):
     return np.roll(y, -1, axis) - 2.0 * y + np.roll(y, 1, axis)
 
 
-def reg_normal(y, kind=0):
-    """T^T T y.  kind 0: T = stacked periodic second differences along x, y, z
-    (second-order Tikhonov, Sec. 4.2), so T^T T = sum_a D_a D_a.  kind 1: T = I."""
+def boundary_mask(shape, width):
+    """P_alpha^T P_alpha of the boundary prior (Sec. 4.2, eq. finalR): 1 on the voxels
+    within `width` voxels of a face of the grid, 0 elsewhere."""
+    m = np.zeros(shape)
+    if width <= 0:
+        return m
+    for a, n in enumerate(shape):
+        idx = [slice(None)] * 3
+        idx[a] = slice(0, width)
+        m[tuple(idx)] = 1.0
+        idx[a] = slice(n - width, n)
+        m[tuple(idx)] = 1.0
+    return m
+
+
+def reg_normal(y, kind=0, alpha=0.0, width=0):
+    """T^T T y + alpha P_alpha^T P_alpha y.  kind 0: T = stacked periodic second
+    differences along x, y, z (second-order Tikhonov, Sec. 4.2), so
+    T^T T = sum_a D_a D_a.  kind 1: T = I.  The alpha term is the boundary prior of
+    eq. finalR over a shell `width` voxels deep."""
     if kind == 1:
-        return y.copy()
-    out = np.zeros_like(y)
-    for a in range(3):
-        out += second_difference(second_difference(y, a), a)
+        out = y.copy()
+    else:
+        out = np.zeros_like(y)
+        for a in range(3):
+            out += second_difference(second_difference(y, a), a)
+    if alpha:
+        out += alpha * boundary_mask(y.shape, width) * y
     return out
 
 
-def reg_value(y, kind=0):
-    """||T y||^2."""
+def reg_value(y, kind=0, alpha=0.0, width=0):
+    """||T y||^2 + alpha ||P_alpha y||^2."""
     if kind == 1:
-        return float(np.sum(y * y))
-    return float(sum(np.sum(second_difference(y, a) ** 2) for a in range(3)))
+        v = float(np.sum(y * y))
+    else:
+        v = float(sum(np.sum(second_difference(y, a) ** 2) for a in range(3)))
+    if alpha:
+        v += alpha * float(np.sum(boundary_mask(y.shape, width) * y * y))
+    return v

@@ -1,9 +1,10 @@
 """Regularised nonnegative least squares for MH3D, FP64 (paper Sec. 4.2-4.3).
 
-Problem (eq. Amodel with R = ||T rho||^2, alpha = 0 in eq. finalR), written as
-    minimise F(rho) = 1/2 ||A rho - d||^2 + 1/2 lambda ||T rho||^2  over rho >= 0,
-which has the same minimiser as the paper's unhalved form; the gradient step uses
-M^*(M y - b) with M = [A; sqrt(lambda) T], b = [d; 0] exactly as Sec. 4.3 does.
+Problem (eq. Amodel with the regulariser of eq. finalR), written as
+    minimise F(rho) = 1/2 ||A rho - d||^2 + 1/2 lambda (||T rho||^2 + alpha ||P_alpha rho||^2)
+over rho >= 0, which has the same minimiser as the paper's unhalved form; the gradient
+step uses M^*(M y - b) with M = [A; sqrt(lambda) T; sqrt(lambda alpha) P_alpha],
+b = [d; 0; 0] exactly as Sec. 4.3 does.  alpha = 0 unless given.
 
 Accelerated projected gradient (Sec. 4.3): with rho^0 = rho^1 = rho_init and
 k = 1, 2, ...
@@ -23,10 +24,14 @@ from . import model
 class Operator:
     """Bundles the FP64 operator pieces (tier 2 FFT evaluation by default)."""
 
-    def __init__(self, h, b, ds, lam, reg_kind=0, tier=2):
+    def __init__(self, h, b, ds, lam, reg_kind=0, tier=2, alpha=0.0, alpha_width=0):
         self.h, self.b, self.ds = h, b, tuple(ds)
         self.lam, self.reg_kind = float(lam), reg_kind
+        self.alpha, self.alpha_width = float(alpha), int(alpha_width)
         self.tier = tier
+
+    def reg_normal(self, x):
+        return model.reg_normal(x, self.reg_kind, self.alpha, self.alpha_width)
 
     def A(self, x):
         if self.tier == 1:
@@ -40,14 +45,15 @@ class Operator:
 
     def normal(self, x):
         """(A^T A + lambda T^T T) x"""
-        return self.AT(self.A(x)) + self.lam * model.reg_normal(x, self.reg_kind)
+        return self.AT(self.A(x)) + self.lam * self.reg_normal(x)
 
     def gradient(self, y, d):
-        return self.AT(self.A(y) - d) + self.lam * model.reg_normal(y, self.reg_kind)
+        return self.AT(self.A(y) - d) + self.lam * self.reg_normal(y)
 
     def objective(self, x, d):
         res = self.A(x) - d
-        return 0.5 * float(np.sum(res * res)) + 0.5 * self.lam * model.reg_value(x, self.reg_kind)
+        return 0.5 * float(np.sum(res * res)) + 0.5 * self.lam * model.reg_value(x, self.reg_kind, self.alpha,
+                                                                                 self.alpha_width)
 
 
 def power_iteration(op, v0, iters=50):

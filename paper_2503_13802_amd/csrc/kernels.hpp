@@ -166,6 +166,8 @@ struct VolDesc {
   float lam;
   int T_class;             // threads of the class passes doing element work
   float* u;                // A^T A part of the current step (k_plane_adj<OUT_U> -> k_vol_update)
+  float alpha;             // boundary prior weight (eq. finalR), 0 = off
+  int aw;                  // its shell depth in voxels
   int nb_upd;              // blocks of k_vol_update for this volume
 };
 
@@ -868,6 +870,7 @@ __host__ __device__ inline int update_blocks(long long n) {
 // The 13 values of one voxel's regulariser stencil and the values its update reads.
 struct StencilVals {
   float c, zm2, zm1, zp1, zp2, ym2, ym1, yp1, yp2, xm2, xm1, xp1, xp2, u, rk;
+  bool shell;              // on the boundary prior's shell
 };
 
 // Finishes a solver step after k_plane_adj<OUT_U> left u = b . v (the A^T A part):
@@ -897,6 +900,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __res
   const float s = (UPD == UPD_NORMAL) ? (float)st->scale : 1.f;
   const float lam = vd.lam;
   const bool stencil = vd.reg_kind == 0;
+  const float alpha = vd.alpha;
+  const int aw = vd.aw;
   const long long N = g.N;
   const int nb = vd.nb_upd;
   constexpr int T = UPD_THREADS;
@@ -911,10 +916,13 @@ __global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __res
     v.c = yv[i];
     v.u = u[i];
     v.rk = (UPD == UPD_FISTA) ? rk[i] : 0.f;
-    if (stencil) {
+    v.shell = false;
+    if (stencil || alpha > 0.f) {
       const uint32_t r = g.f_nz.div((uint32_t)i);
       const int z = (int)((uint32_t)i - r * (uint32_t)g.nz);
       const int y = (int)g.f_ny.mod(r), x = (int)g.f_ny.div(r);
+      v.shell = x < aw || x >= g.nx - aw || y < aw || y >= g.ny - aw || z < aw || z >= g.nz - aw;
+      if (!stencil) return v;
       const long long row = i - z;
       // periodic neighbours (every axis is >= 4 long, so one wrap suffices)
       auto wz = [&](int d) { int q = z + d; q += q < 0 ? g.nz : 0; q -= q >= g.nz ? g.nz : 0; return yv[row + q]; };
@@ -932,12 +940,18 @@ __global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __res
     }
     return v;
   };
+  // T^T T (s y) + alpha P_alpha^T P_alpha (s y)
   auto reg = [&](const StencilVals& v) {
-    if (!stencil) return s * v.c;
-    float t = 18.f * (s * v.c);
-    t += s * (v.zp2 + v.zm2) - 4.f * s * (v.zp1 + v.zm1);
-    t += s * (v.yp2 + v.ym2) - 4.f * s * (v.yp1 + v.ym1);
-    t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
+    float t;
+    if (!stencil) {
+      t = s * v.c;
+    } else {
+      t = 18.f * (s * v.c);
+      t += s * (v.zp2 + v.zm2) - 4.f * s * (v.zp1 + v.zm1);
+      t += s * (v.yp2 + v.ym2) - 4.f * s * (v.yp1 + v.ym1);
+      t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
+    }
+    if (alpha > 0.f && v.shell) t += alpha * (s * v.c);
     return t;
   };
   constexpr int U = 4;

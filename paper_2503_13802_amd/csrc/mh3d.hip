@@ -178,8 +178,14 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
       if (!(d->sigma_mm[a] > 0)) return fail(MH3D_ERR_INVALID, "sigma_mm[%d] must be > 0", a);
   if (!(d->lambda >= 0)) return fail(MH3D_ERR_INVALID, "lambda must be >= 0");
   if (d->reg_kind != 0 && d->reg_kind != 1) return fail(MH3D_ERR_INVALID, "reg_kind must be 0 or 1");
-  if (d->alpha != 0.0 || d->alpha_width != 0)
-    return fail(MH3D_ERR_UNSUPPORTED, "boundary prior alpha (eq. finalR) is not built; use alpha = 0");
+  if (!(d->alpha >= 0.0) || !(d->alpha < 1e30)) return fail(MH3D_ERR_INVALID, "alpha must be finite and >= 0");
+  if (d->alpha > 0.0) {
+    const int mn = std::min(d->nx, std::min(d->ny, d->nz));
+    if (d->alpha_width < 1 || 2 * d->alpha_width > mn)
+      return fail(MH3D_ERR_INVALID, "alpha_width must be in [1, min(nx, ny, nz)/2] when alpha > 0");
+  } else if (d->alpha_width != 0) {
+    return fail(MH3D_ERR_INVALID, "alpha_width must be 0 when alpha = 0");
+  }
   if (d->pad[0] || d->pad[1] || d->pad[2])
     return fail(MH3D_ERR_UNSUPPORTED, "boundary padding is not built; use pad = 0");
 
@@ -564,6 +570,8 @@ static void fill_desc(mh3d_plan_t p) {
   v.k_first = 1;
   v.reg_kind = p->desc.reg_kind;
   v.lam = (float)p->desc.lambda;
+  v.alpha = (float)p->desc.alpha;
+  v.aw = p->desc.alpha_width;
   v.T_class = p->L.T_class;
   v.u = p->vol[4];
   v.nb_upd = update_blocks(p->g.N);

@@ -147,7 +147,7 @@ def _check(status):
 
 
 def _desc(shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=0, order_offset=0,
-          psf_ptr=None, sens_ptr=None, stream=None, alpha=0.0, pad=(0, 0, 0)):
+          psf_ptr=None, sens_ptr=None, stream=None, alpha=0.0, pad=(0, 0, 0), alpha_width=0):
     harm = (ctypes.c_int32 * len(harmonics))(*[int(k) for k in harmonics])
     d = PlanDesc()
     d.nx, d.ny, d.nz = [int(n) for n in shape]
@@ -163,7 +163,7 @@ def _desc(shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=
     d.lambda_ = float(lam)
     d.reg_kind = int(reg_kind)
     d.alpha = float(alpha)
-    d.alpha_width = 0
+    d.alpha_width = int(alpha_width)
     d.pad = (ctypes.c_int32 * 3)(*[int(x) for x in pad])
     d.stream = stream
     return d, harm
@@ -194,7 +194,7 @@ class Plan:
     """One MH3D reconstruction geometry on one GPU (see include/mh3d.h)."""
 
     def __init__(self, shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=0,
-                 order_offset=0, psf=None, sens=None, device="cuda"):
+                 order_offset=0, psf=None, sens=None, device="cuda", alpha=0.0, alpha_width=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -217,7 +217,8 @@ class Plan:
             sens_ptr = sens.data_ptr()
         self.stream = torch.cuda.current_stream(self.device)
         d, harm = _desc(self.shape, self.harmonics, a_per_mm, self.ds, sigma_mm, lam, voxel_mm, reg_kind,
-                        order_offset, psf_ptr, sens_ptr, self.stream.cuda_stream)
+                        order_offset, psf_ptr, sens_ptr, self.stream.cuda_stream, alpha=alpha,
+                        alpha_width=alpha_width)
         h = ctypes.c_void_p()
         _check(library().mh3d_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -21,6 +21,10 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert lib.mh3d_version() == 1
 
 
+def test_describe_accepts_boundary_prior():
+    assert mh3d.describe((32, 32, 32), (2, 3), 1.2, (2, 2, 2), 20.0, 1e-3, alpha=4.0, alpha_width=2)[1] == 32 ** 3
+
+
 @pytest.mark.parametrize("shape,harm,ds,sig", [
     ((32, 32, 32), (2, 3), (2, 2, 2), 20.0),
     ((96, 96, 64), tuple(range(2, 9)), (2, 2, 2), 20.0),
@@ -51,7 +55,10 @@ def test_describe_valid(shape, harm, ds, sig):
     (dict(sigma_mm=0.0), mh3d.ERR_INVALID),
     (dict(voxel_mm=0.0), mh3d.ERR_INVALID),
     (dict(reg_kind=3), mh3d.ERR_INVALID),
-    (dict(alpha=4.0), mh3d.ERR_UNSUPPORTED),                 # boundary prior not built
+    (dict(alpha=4.0), mh3d.ERR_INVALID),                     # boundary prior needs a shell depth
+    (dict(alpha=4.0, alpha_width=40), mh3d.ERR_INVALID),     # shell deeper than half the grid
+    (dict(alpha=0.0, alpha_width=2), mh3d.ERR_INVALID),
+    (dict(alpha=-1.0, alpha_width=2), mh3d.ERR_INVALID),
     (dict(pad=(4, 4, 4)), mh3d.ERR_UNSUPPORTED),             # padding not built
     (dict(shape=(18, 18, 12), ds=(3, 3, 3)), mh3d.ERR_UNSUPPORTED),  # S = 27 has no power-of-two fold split
     (dict(shape=(256, 256, 256)), mh3d.ERR_UNSUPPORTED),     # x-plane exceeds LDS

@@ -151,16 +151,16 @@ def test_user_psf_and_sensitivity_arrays_match_analytic_plan():
     assert rel_l2(x, om.adjoint_direct(h, b, r, ds)) <= TOL
 
 
-@pytest.mark.parametrize("reg_kind", [0, 1])
-def test_normal_operator(reg_kind):
+@pytest.mark.parametrize("reg_kind,alpha,width", [(0, 0.0, 0), (1, 0.0, 0), (0, 4.0, 2), (1, 2.5, 1)])
+def test_normal_operator(reg_kind, alpha, width):
     torch = torch_cuda()
-    announce("normal reg_kind=%d" % reg_kind)
+    announce("normal reg_kind=%d alpha=%g" % (reg_kind, alpha))
     shape, harm, ds, lam = (16, 12, 8), (2, 3), (2, 2, 2), 0.05
     h = om.psf_bank(shape, list(harm), 0.9)
     b = om.sensitivity(shape, 5.0)
-    op = osv.Operator(h, b, ds, lam, reg_kind=reg_kind)
+    op = osv.Operator(h, b, ds, lam, reg_kind=reg_kind, alpha=alpha, alpha_width=width)
     x = inputs.random_field(shape, 9)
-    p = _plan(shape, harm, 0.9, ds, 5.0, lam=lam, reg_kind=reg_kind)
+    p = _plan(shape, harm, 0.9, ds, 5.0, lam=lam, reg_kind=reg_kind, alpha=alpha, alpha_width=width)
     got = p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
     assert rel_l2(got, op.normal(x)) <= TOL
 

@@ -118,3 +118,26 @@ def test_workload1_converges_like_oracle():
     got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=60, tol=0.0, tau=tau)
     want, hist, _ = osv.fista(op, d, tau, max_iter=60)
     assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+
+
+def test_boundary_prior_solve_matches_oracle():
+    """eq. finalR with alpha > 0 (a 2-voxel shell): 50 updates of workload 0 against
+    the oracle at equal tau, and the power-iteration estimate of the full normal
+    operator."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    w = inputs.workload(0)
+    announce("solve with boundary prior")
+    h = om.psf_bank(w.shape, list(w.harmonics), w.a_per_mm)
+    b = om.sensitivity(w.shape, w.sigma_mm)
+    op = osv.Operator(h, b, w.ds, w.lam, alpha=4.0, alpha_width=2)
+    d = inputs.add_noise(op.A(inputs.phantom(w)), w.snr_db, inputs.noise_draw(w))
+    v0 = oph.uniform01(0, 0, w.n_voxels).reshape(w.shape)
+    lmax = osv.power_iteration(op, v0, 50)
+    tau = osv.step_size(lmax)
+    want, hist, _ = osv.fista(op, d, tau, max_iter=50)
+    p = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, alpha=4.0, alpha_width=2)
+    assert p.power_iteration(50, 0) == pytest.approx(lmax, rel=1e-5)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=50, tol=0.0, tau=tau)
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+    assert np.allclose(info["history"], hist, rtol=1e-3, atol=0)

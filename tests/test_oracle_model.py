@@ -233,3 +233,31 @@ def test_regulariser_stencil_spectrum_and_top_eigenvalue():
     assert np.allclose(om.reg_normal(chk), 48.0 * chk, rtol=0, atol=1e-13)
     assert om.reg_value(y) == pytest.approx(np.sum(y * st), rel=1e-13)
     assert np.array_equal(om.reg_normal(y, kind=1), y)
+
+
+def test_boundary_prior_mask_and_quadratic_form():
+    """eq. finalR's alpha ||P_alpha rho||^2: the shell's voxel count, and reg_normal as
+    half the gradient of reg_value (central differences), symmetric, with and without
+    the stencil."""
+    shape, w = (9, 8, 6), 2
+    m = om.boundary_mask(shape, w)
+    assert m.sum() == 9 * 8 * 6 - (9 - 4) * (8 - 4) * (6 - 4)
+    assert m[w:-w, w:-w, w:-w].sum() == 0 and m[0].all() and m[:, :, -1].all()
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(shape)
+    for kind in (0, 1):
+        g = om.reg_normal(y, kind, alpha=3.0, width=w)
+        assert om.reg_value(y, kind, 3.0, w) == pytest.approx(float(np.sum(y * g)), rel=1e-12)
+        x = rng.standard_normal(shape)
+        assert np.sum(x * om.reg_normal(y, kind, 3.0, w)) == pytest.approx(
+            np.sum(y * om.reg_normal(x, kind, 3.0, w)), rel=1e-12)
+        for _ in range(6):
+            i = tuple(int(rng.integers(n)) for n in shape)
+            e = np.zeros(shape)
+            e[i] = 1e-5
+            fd = (om.reg_value(y + e, kind, 3.0, w) - om.reg_value(y - e, kind, 3.0, w)) / 2e-5
+            assert fd == pytest.approx(2.0 * g[i], rel=1e-6, abs=1e-8)
+    # alpha acts only on the shell: a field supported inside it is unchanged
+    z = np.zeros(shape)
+    z[3:6, 3:5, 2:4] = rng.standard_normal((3, 2, 2))
+    assert np.array_equal(om.reg_normal(z, 1, 5.0, w), z)

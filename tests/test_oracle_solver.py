@@ -161,3 +161,30 @@ def test_noise_hits_target_snr():
         noise = d[k] - clean[k]
         emp = 10 * np.log10(np.mean(clean[k] ** 2) / np.mean(noise ** 2))
         assert emp == pytest.approx(snr, abs=0.3)
+
+
+def test_boundary_prior_kkt_and_background_suppression():
+    """eq. finalR with alpha > 0: the FISTA optimum satisfies the KKT conditions of the
+    full objective, and the prior lowers the density on the boundary shell (fig:alpha:
+    a larger alpha drives the background towards zero)."""
+    shape, ds, w = (6, 4, 4), (2, 1, 1), 1
+    h = om.psf_bank(shape, [2, 4], 0.9)
+    b = om.sensitivity(shape, 4.0)
+    rho_t = np.maximum(inputs.random_field(shape, 5) - 0.8, 0.0)
+    base = osv.Operator(h, b, ds, 1e-1)
+    d = base.A(rho_t) + 0.05 * inputs.random_field((2,) + om.small_shape(shape, ds), 6)
+    shell = om.boundary_mask(shape, w).astype(bool)
+    mass = {}
+    for alpha in (0.0, 4.0):
+        op = osv.Operator(h, b, ds, 1e-1, alpha=alpha, alpha_width=w)
+        dense = _dense_normal(op)
+        assert np.allclose(dense, dense.T, atol=1e-10)
+        lmax = float(np.max(np.linalg.eigvalsh(dense)))
+        rho, _, _ = osv.fista(op, d, 1.0 / lmax, max_iter=20000, tol=1e-12)
+        g = op.gradient(rho, d)
+        eps = 1e-6 * np.max(np.abs(op.gradient(np.zeros_like(rho), d)))
+        active = rho == 0
+        assert np.min(g[active]) >= -eps
+        assert np.max(np.abs(g[~active])) <= eps
+        mass[alpha] = float(rho[shell].sum())
+    assert mass[4.0] < mass[0.0]
