@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   MH3D_OK = 0,
   MH3D_ERR_INVALID = 1,       /* bad argument or geometry                          */
-  MH3D_ERR_UNSUPPORTED = 2,   /* valid per the paper but not built (padding) */
+  MH3D_ERR_UNSUPPORTED = 2,   /* valid per the paper but not built (shapes beyond the LDS budget, fold splits) */
   MH3D_ERR_OOM = 3,           /* device allocation failed                           */
   MH3D_ERR_HIP = 4,           /* a HIP runtime call failed                          */
   MH3D_ERR_NOT_CONVERGED = 5, /* solve hit max_iter before the tolerance            */
@@ -72,7 +72,11 @@ typedef struct {
   int32_t reg_kind;          /* 0: stacked periodic second differences; 1: T = I         */
   double alpha;              /* boundary prior weight (eq. finalR), >= 0; 0 = off        */
   int32_t alpha_width;       /* shell depth of P_alpha in voxels: [1, min(n)/2] if alpha > 0, else 0 */
-  int32_t pad[3];            /* boundary padding (Sec. 4.1.1); must be 0                 */
+  int32_t pad[3];            /* boundary padding (Sec. 4.1.1): voxels of the grid on each
+                                side of axis a that are modelled but not measured, a
+                                multiple of ds[a].  Volumes live on the whole (padded)
+                                grid; portraits cover its field of view only:
+                                [n_harm][(nx-2pad0)/ds0][(ny-2pad1)/ds1][(nz-2pad2)/ds2] */
   void* stream;              /* hipStream_t all calls on this plan are enqueued on        */
 } mh3d_plan_desc;
 

@@ -192,6 +192,33 @@ def adjoint_fft(h, b, r, ds, workers=None):
     return b * x
 
 
+# --------------------------------------------------------------------------- boundary padding
+def fov_offsets(pad, ds):
+    """Decimated-sample offsets of the field of view: pad[a] voxels of padding on each
+    side of axis a (a multiple of ds[a]) are modelled but not measured (Sec. 4.1.1)."""
+    for p, s in zip(pad, ds):
+        if p < 0 or p % s:
+            raise ValueError("padding must be a non-negative multiple of the decimation")
+    return tuple(p // s for p, s in zip(pad, ds))
+
+
+def crop_portraits(d, pad, ds):
+    """C: the decimated samples inside the field of view (the padded grid's samples
+    outside it are not part of the portrait data)."""
+    o = fov_offsets(pad, ds)
+    _, mx, my, mz = d.shape
+    return d[:, o[0]:mx - o[0], o[1]:my - o[1], o[2]:mz - o[2]].copy()
+
+
+def embed_portraits(r, pad, ds, small):
+    """C^T: field-of-view portraits placed in the padded grid's decimated samples,
+    zero outside."""
+    o = fov_offsets(pad, ds)
+    out = np.zeros((r.shape[0],) + tuple(small))
+    out[:, o[0]:o[0] + r.shape[1], o[1]:o[1] + r.shape[2], o[2]:o[2] + r.shape[3]] = r
+    return out
+
+
 # --------------------------------------------------------------------------- regulariser
 def second_difference(y, axis):
     """(D_a y)[i] = y[i+1] - 2 y[i] + y[i-1], periodic along one axis."""

@@ -24,10 +24,14 @@ from . import model
 class Operator:
     """Bundles the FP64 operator pieces (tier 2 FFT evaluation by default)."""
 
-    def __init__(self, h, b, ds, lam, reg_kind=0, tier=2, alpha=0.0, alpha_width=0):
+    def __init__(self, h, b, ds, lam, reg_kind=0, tier=2, alpha=0.0, alpha_width=0, pad=(0, 0, 0)):
+        """pad: boundary padding (Sec. 4.1.1) -- h, b and the volumes live on the padded
+        grid, the portraits on its field of view (A = C P H B, C the crop)."""
         self.h, self.b, self.ds = h, b, tuple(ds)
         self.lam, self.reg_kind = float(lam), reg_kind
         self.alpha, self.alpha_width = float(alpha), int(alpha_width)
+        self.pad = tuple(int(p) for p in pad)
+        self.small = model.small_shape(h.shape[1:], ds)
         self.tier = tier
 
     def reg_normal(self, x):
@@ -35,10 +39,14 @@ class Operator:
 
     def A(self, x):
         if self.tier == 1:
-            return model.forward_direct(self.h, self.b, x, self.ds)
-        return model.forward_fft(self.h, self.b, x, self.ds)
+            d = model.forward_direct(self.h, self.b, x, self.ds)
+        else:
+            d = model.forward_fft(self.h, self.b, x, self.ds)
+        return model.crop_portraits(d, self.pad, self.ds) if any(self.pad) else d
 
     def AT(self, r):
+        if any(self.pad):
+            r = model.embed_portraits(r, self.pad, self.ds, self.small)
         if self.tier == 1:
             return model.adjoint_direct(self.h, self.b, r, self.ds)
         return model.adjoint_fft(self.h, self.b, r, self.ds)

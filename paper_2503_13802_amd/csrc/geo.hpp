@@ -54,6 +54,10 @@ struct Geo {
   int lsx;                 // LDS line stride of x-transforms in the class kernels (nx + pad)
   int lsmy;                // LDS line stride of y'-transforms in the small kernels (my + pad)
   long long N, M;          // nx*ny*nz, mx*my*mz
+  int padded;              // boundary padding: the portraits cover only the field of view
+  int pxs, pys, pzs;       // field-of-view offsets in decimated samples (padding / decimation)
+  int mxf, myf, mzf;       // field-of-view portrait dims
+  long long Mf;            // mxf*myf*mzf (= M without padding)
   long long hsz;           // spectrum elements per harmonic = ncls*mx*S = plane*nx
   FastDiv f_nz, f_nzh, f_nmem, f_mzh, f_sz, f_mz, f_W, f_xb, f_S, f_mxS, f_cpwmx, f_cpwxb, f_ny, f_my;
 };

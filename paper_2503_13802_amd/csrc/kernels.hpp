@@ -667,6 +667,16 @@ __device__ void small_r2c_and_store(const Geo& g, float2* a, float2* b, const fl
   }
 }
 
+// Portrait index of element p = (xi*my + y')*mz + z' of x'-block xbi, harmonic k, in
+// the field-of-view portraits [K][mxf][myf][mzf]; -1 for a sample of the padding.
+__device__ __forceinline__ long long fov_index(const Geo& g, int k, int xbi, int p) {
+  const int r = (int)g.f_mz.div((uint32_t)p), z = p - r * g.mz;
+  const int xi = (int)g.f_my.div((uint32_t)r), y = r - xi * g.my;
+  const int xf = xbi * g.xb + xi - g.pxs, yf = y - g.pys, zf = z - g.pzs;
+  if ((unsigned)xf >= (unsigned)g.mxf || (unsigned)yf >= (unsigned)g.myf || (unsigned)zf >= (unsigned)g.mzf) return -1;
+  return (long long)k * g.Mf + ((long long)xf * g.myf + yf) * g.mzf + zf;
+}
+
 // Forward pass 3 (and, with EPI_RESID_BACK / EPI_BACK, the first adjoint pass on
 // the result).  One block per (k, x'-block).  EPI_RESID_BACK uses the volume's data
 // and is skipped once its solve is done.  LDS: tables (my + mz) + 2 * small_lds.
@@ -709,7 +719,32 @@ __global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ 
     const int r = (int)g.f_mz.div((uint32_t)p), z = p - r * g.mz;
     return 2 * ((r >> 1) * lsmz + z) + (r & 1);
   };
-  if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_BACK) {
+  if (g.padded) {
+    // boundary padding: only the field-of-view samples are data (C P); the padding's
+    // samples of the residual are zero (C^T C P)
+    if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_BACK) {
+      for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const long long di = fov_index(g, k, xbi, p);
+        const int li = lidx(p);
+        if (di >= 0) d[di] = Zf[li];
+        else if (EPI == EPI_STORE_BACK) Zf[li] = 0.f;
+      }
+    } else if constexpr (EPI == EPI_RESID) {
+      for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const long long di = fov_index(g, k, xbi, p);
+        if (di >= 0) d[di] = Zf[lidx(p)] - dmeas[di];
+      }
+    } else if constexpr (EPI == EPI_RESID_BACK) {
+      for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const long long di = fov_index(g, k, xbi, p);
+        const int li = lidx(p);
+        Zf[li] = di >= 0 ? Zf[li] - dmeas[di] : 0.f;
+      }
+    } else if constexpr (EPI == EPI_BACK) {
+      for (int p = threadIdx.x; p < n; p += blockDim.x)
+        if (fov_index(g, k, xbi, p) < 0) Zf[lidx(p)] = 0.f;
+    }
+  } else if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_BACK) {
     for (int p = threadIdx.x; p < n; p += blockDim.x) d[obase + p] = Zf[lidx(p)];
   } else if constexpr (EPI == EPI_RESID) {
     batched<8, float>(n, [&](int p) { return dmeas[obase + p]; },
@@ -747,7 +782,12 @@ __global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ 
   const long long ibase = (long long)k * g.M + (long long)xbi * g.xb * g.my * g.mz;
   float* Zf = reinterpret_cast<float*>(P0);
   const int n = rows * g.mz;
-  batched<8, float>(n, [&](int p) { return r[ibase + p]; },
+  // with boundary padding the portraits cover the field of view: C^T r is zero outside
+  batched<8, float>(n, [&](int p) {
+                      if (!g.padded) return r[ibase + p];
+                      const long long di = fov_index(g, k, xbi, p);
+                      return di >= 0 ? r[di] : 0.f;
+                    },
                     [&](int p, float v) {
                       const int rr = (int)g.f_mz.div((uint32_t)p), z = p - rr * g.mz;
                       Zf[2 * ((rr >> 1) * lsmz + z) + (rr & 1)] = v;

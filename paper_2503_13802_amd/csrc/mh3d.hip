@@ -186,8 +186,12 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   } else if (d->alpha_width != 0) {
     return fail(MH3D_ERR_INVALID, "alpha_width must be 0 when alpha = 0");
   }
-  if (d->pad[0] || d->pad[1] || d->pad[2])
-    return fail(MH3D_ERR_UNSUPPORTED, "boundary padding is not built; use pad = 0");
+  for (int a = 0; a < 3; ++a) {
+    if (d->pad[a] < 0 || d->pad[a] % d->ds[a])
+      return fail(MH3D_ERR_INVALID, "pad[%d] = %d must be a non-negative multiple of ds[%d]", a, d->pad[a], a);
+    if ((n[a] - 2 * d->pad[a]) / d->ds[a] < 2)
+      return fail(MH3D_ERR_INVALID, "the field of view along axis %d has fewer than 2 decimated samples", a);
+  }
 
   memset(&g, 0, sizeof g);
   g.nx = d->nx; g.ny = d->ny; g.nz = d->nz; g.nzh = g.nz / 2 + 1;
@@ -201,6 +205,10 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   g.npairs = (g.ny + 1) / 2;
   g.N = (long long)g.nx * g.ny * g.nz;
   g.M = (long long)g.mx * g.my * g.mz;
+  g.padded = (d->pad[0] || d->pad[1] || d->pad[2]) ? 1 : 0;
+  g.pxs = d->pad[0] / g.sx; g.pys = d->pad[1] / g.sy; g.pzs = d->pad[2] / g.sz;
+  g.mxf = g.mx - 2 * g.pxs; g.myf = g.my - 2 * g.pys; g.mzf = g.mz - 2 * g.pzs;
+  g.Mf = (long long)g.mxf * g.myf * g.mzf;
   g.hsz = (long long)g.plane * g.nx;
   g.lsy = pad_odd(g.ny);
   g.lsx = pad_odd(g.nx);
@@ -297,7 +305,7 @@ extern "C" mh3d_status mh3d_plan_describe(const mh3d_plan_desc* desc, size_t* de
   if (s != MH3D_OK) return s;
   if (device_bytes) *device_bytes = plan_bytes(g, desc->psf == nullptr);
   if (n_volume) *n_volume = g.N;
-  if (n_portrait) *n_portrait = (int64_t)g.K * g.M;
+  if (n_portrait) *n_portrait = (int64_t)g.K * g.Mf;
   return MH3D_OK;
 }
 

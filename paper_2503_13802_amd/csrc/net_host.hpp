@@ -741,10 +741,10 @@ extern "C" mh3d_status mh3d_noisy_data(mh3d_plan_t p, const float* rho, uint64_t
   HIPCHK(hipMalloc(&ms, sizeof(double) * g.K));
   HIPCHK(hipMalloc(&harm, sizeof(int) * g.K));
   HIPCHK(hipMemcpyAsync(harm, p->harm.data(), sizeof(int) * g.K, hipMemcpyHostToDevice, p->stream));
-  k_port_meansq<<<g.K, 256, 0, p->stream>>>(d, g.M, ms);
+  k_port_meansq<<<g.K, 256, 0, p->stream>>>(d, g.Mf, ms);
   mh3d_status s = last_launch("k_port_meansq");
   if (s == MH3D_OK) {
-    k_add_noise<<<grid_for((long long)g.K * g.M), 256, 0, p->stream>>>(d, g.M, g.K, ms, harm, snr2_db, decay_db, seed);
+    k_add_noise<<<grid_for((long long)g.K * g.Mf), 256, 0, p->stream>>>(d, g.Mf, g.K, ms, harm, snr2_db, decay_db, seed);
     s = last_launch("k_add_noise");
   }
   if (hipStreamSynchronize(p->stream) != hipSuccess && s == MH3D_OK) s = fail(MH3D_ERR_HIP, "noise kernel failed");

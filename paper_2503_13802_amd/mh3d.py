@@ -194,14 +194,16 @@ class Plan:
     """One MH3D reconstruction geometry on one GPU (see include/mh3d.h)."""
 
     def __init__(self, shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=0,
-                 order_offset=0, psf=None, sens=None, device="cuda", alpha=0.0, alpha_width=0):
+                 order_offset=0, psf=None, sens=None, device="cuda", alpha=0.0, alpha_width=0, pad=(0, 0, 0)):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.shape = tuple(int(n) for n in shape)
         self.harmonics = tuple(int(k) for k in harmonics)
         self.ds = tuple(int(s) for s in ds)
-        self.small = tuple(n // s for n, s in zip(self.shape, self.ds))
+        self.pad = tuple(int(q) for q in pad)
+        # portraits: the decimated samples of the field of view (all of the grid without padding)
+        self.small = tuple((n - 2 * q) // s for n, q, s in zip(self.shape, self.pad, self.ds))
         self.K = len(self.harmonics)
         self._keep = []
         psf_ptr = sens_ptr = None
@@ -218,7 +220,7 @@ class Plan:
         self.stream = torch.cuda.current_stream(self.device)
         d, harm = _desc(self.shape, self.harmonics, a_per_mm, self.ds, sigma_mm, lam, voxel_mm, reg_kind,
                         order_offset, psf_ptr, sens_ptr, self.stream.cuda_stream, alpha=alpha,
-                        alpha_width=alpha_width)
+                        alpha_width=alpha_width, pad=self.pad)
         h = ctypes.c_void_p()
         _check(library().mh3d_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

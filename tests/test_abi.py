@@ -25,6 +25,11 @@ def test_describe_accepts_boundary_prior():
     assert mh3d.describe((32, 32, 32), (2, 3), 1.2, (2, 2, 2), 20.0, 1e-3, alpha=4.0, alpha_width=2)[1] == 32 ** 3
 
 
+def test_describe_padding_shrinks_the_portraits_only():
+    nb, nv, npo = mh3d.describe((96, 96, 64), tuple(range(2, 9)), 1.2, (2, 2, 2), 20.0, 1e-3, pad=(8, 4, 6))
+    assert nv == 96 * 96 * 64 and npo == 7 * 40 * 44 * 26
+
+
 @pytest.mark.parametrize("shape,harm,ds,sig", [
     ((32, 32, 32), (2, 3), (2, 2, 2), 20.0),
     ((96, 96, 64), tuple(range(2, 9)), (2, 2, 2), 20.0),
@@ -59,7 +64,9 @@ def test_describe_valid(shape, harm, ds, sig):
     (dict(alpha=4.0, alpha_width=40), mh3d.ERR_INVALID),     # shell deeper than half the grid
     (dict(alpha=0.0, alpha_width=2), mh3d.ERR_INVALID),
     (dict(alpha=-1.0, alpha_width=2), mh3d.ERR_INVALID),
-    (dict(pad=(4, 4, 4)), mh3d.ERR_UNSUPPORTED),             # padding not built
+    (dict(pad=(3, 0, 0)), mh3d.ERR_INVALID),                 # padding not a multiple of ds
+    (dict(pad=(0, 0, 32)), mh3d.ERR_INVALID),                # empty field of view
+    (dict(pad=(-2, 0, 0)), mh3d.ERR_INVALID),
     (dict(shape=(18, 18, 12), ds=(3, 3, 3)), mh3d.ERR_UNSUPPORTED),  # S = 27 has no power-of-two fold split
     (dict(shape=(256, 256, 256)), mh3d.ERR_UNSUPPORTED),     # x-plane exceeds LDS
 ])

@@ -261,3 +261,55 @@ def test_boundary_prior_mask_and_quadratic_form():
     z = np.zeros(shape)
     z[3:6, 3:5, 2:4] = rng.standard_normal((3, 2, 2))
     assert np.array_equal(om.reg_normal(z, 1, 5.0, w), z)
+
+
+def test_padding_crop_embed_and_adjoint_identity():
+    """Boundary padding (Sec. 4.1.1): C crops the decimated samples to the field of
+    view and C^T embeds with zeros; the padded A and A^T are adjoint (FP64), both tiers
+    agree, and zero padding is the plain operator."""
+    from oracle import solver as osv
+    shape, ds, pad = (12, 12, 8), (2, 2, 2), (2, 4, 2)
+    h = om.psf_bank(shape, [2, 3], 0.9)
+    b = om.sensitivity(shape, 4.0)
+    rng = np.random.default_rng(21)
+    small = om.small_shape(shape, ds)
+    d = rng.standard_normal((2,) + small)
+    c = om.crop_portraits(d, pad, ds)
+    assert c.shape == (2, 4, 2, 2)
+    r = rng.standard_normal(c.shape)
+    assert np.sum(c * r) == pytest.approx(np.sum(d * om.embed_portraits(r, pad, ds, small)), rel=1e-13)
+    with pytest.raises(ValueError):
+        om.fov_offsets((3, 0, 0), ds)
+    op1 = osv.Operator(h, b, ds, 0.0, pad=pad, tier=1)
+    op2 = osv.Operator(h, b, ds, 0.0, pad=pad, tier=2)
+    x = rng.standard_normal(shape)
+    assert np.allclose(op1.A(x), op2.A(x), rtol=0, atol=1e-12 * np.abs(op1.A(x)).max())
+    lhs = float(np.sum(op2.A(x) * r))
+    rhs = float(np.sum(x * op2.AT(r)))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    assert np.allclose(op1.AT(r), op2.AT(r), rtol=0, atol=1e-12 * np.abs(op1.AT(r)).max())
+    plain = osv.Operator(h, b, ds, 0.0)
+    assert np.array_equal(osv.Operator(h, b, ds, 0.0, pad=(0, 0, 0)).A(x), plain.A(x))
+
+
+def test_padding_removes_wraparound():
+    """fig:bdPad: a source at the edge of the field of view leaks into the opposite
+    edge through the periodic convolution; padding the grid removes that leak, and
+    the field-of-view portraits converge as the padding grows."""
+    from oracle import solver as osv
+    fov, ds = (16, 8, 8), (2, 2, 2)
+    ports = {}
+    for p in (0, 4, 8, 16, 24):
+        shape = (fov[0] + 2 * p, fov[1], fov[2])
+        h = om.psf_bank(shape, [2, 3], 0.9)
+        b = np.ones(shape)
+        rho = np.zeros(shape)
+        rho[p + 1, 4, 4] = 1.0                # one voxel inside the left edge of the FOV
+        ports[p] = osv.Operator(h, b, ds, 0.0, pad=(p, 0, 0)).A(rho)
+    ref = ports[24]
+    err = [np.linalg.norm(ports[p] - ref) / np.linalg.norm(ref) for p in (0, 4, 8, 16)]
+    assert all(e1 > e2 for e1, e2 in zip(err, err[1:]))
+    assert err[0] > 10 * err[-1]
+    # the far (right) edge samples: large without padding, small with it
+    far = lambda d: np.abs(d[:, -1]).max() / np.abs(d).max()
+    assert far(ports[0]) > 5 * far(ports[16])
