@@ -132,6 +132,16 @@ mh3d_status mh3d_forward_adjoint(mh3d_plan_t plan, const float* rho, float* d, f
  * A^T d.  d: portraits, c: DEVICE [n_harm][nx][ny][nz]. */
 mh3d_status mh3d_backproject(mh3d_plan_t plan, const float* d, float* c);
 
+/* Multi-harmonic anti-differentiation (App. D, eq. mhadM): the closed-form native
+ * image on the portrait grid, per line along the drive axis x',
+ *   rho_N^ = sum_k c_k^{-1} conj(f^)^(k-1) d_k^ / (sum_k |f^|^(2(k-1)) + lambda),
+ * f the circulant central difference u[j+1] - u[j-1] (f^ = 2i sin(2 pi q / m')), with
+ * the derivative order k - 1 of each harmonic (plus the plan's order_offset).  d: the
+ * portraits [n_harm][mx'][my'][mz'] (field of view); c: HOST array of the n_harm
+ * portrait scales c_k, or NULL for c_k = 1; lambda > 0; out: DEVICE [mx'][my'][mz'].
+ * mx' must be 2^a 3^b.  Asynchronous on the plan's stream. */
+mh3d_status mh3d_mhad(mh3d_plan_t plan, const float* d, double lambda, const double* c, float* out);
+
 /* out = (A^T A + lambda T^T T) x, the normal operator of Sec. 4.3's stacked M. */
 mh3d_status mh3d_normal(mh3d_plan_t plan, const float* x, float* out);
 

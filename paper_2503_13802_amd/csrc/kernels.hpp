@@ -1095,6 +1095,79 @@ __global__ __launch_bounds__(256) void k_vol_finish(const VolDesc* __restrict__ 
   }
 }
 
+// ============================================================================ MHAD
+// Multi-harmonic anti-differentiation (App. D, eq. mhadM): the native image on the
+// portrait grid from the portraits, per line along the drive axis (x'):
+//   rho_N^(q) = sum_k c_k^{-1} conj(f^(q))^{k-1} d_k^(q) / (sum_k |f^(q)|^{2(k-1)} + lambda),
+// f^(q) = 2i sin(2 pi q / m) (the central difference u[j+1] - u[j-1]).  A block takes
+// CB lines (consecutive (y', z') columns, so the loads and stores are coalesced), FFTs
+// each harmonic's lines in LDS and accumulates the weighted spectra, then divides and
+// transforms back.  grid = ceil(C / CB), C = my' mz'; dynamic LDS (m + 3 CB ls) float2
+// + m floats, ls = pad_odd(m).
+struct MhadW {
+  int ord[32];        // k - 1 per harmonic
+  double cinv[32];    // 1 / c_k
+};
+
+__global__ __launch_bounds__(256) void k_mhad(const float* __restrict__ d, int K, MhadW wk, double lam, int m,
+                                              long long C, int CB, float* __restrict__ out) {
+  extern __shared__ float2 sm[];
+  const int ls = pad_odd(m);
+  float2* tw = sm;
+  float2* A0 = tw + m;
+  float2* A1 = A0 + CB * ls;
+  float2* acc = A1 + CB * ls;
+  float* den = reinterpret_cast<float*>(acc + CB * ls);
+  const long long c0 = (long long)blockIdx.x * CB;
+  const int nc = (int)(C - c0 < CB ? C - c0 : CB);
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)t / (double)m, &sn, &cs);
+    tw[t] = make_float2((float)cs, (float)-sn);
+    double sum = lam;
+    for (int i = 0; i < K; ++i) sum += pow(4.0 * sn * sn, (double)wk.ord[i]);
+    den[t] = (float)sum;
+  }
+  for (int p = threadIdx.x; p < CB * ls; p += blockDim.x) acc[p] = make_float2(0.f, 0.f);
+  for (int i = 0; i < K; ++i) {
+    __syncthreads();
+    for (int p = threadIdx.x; p < m * nc; p += blockDim.x) {
+      const int x = p / nc, c = p - x * nc;
+      A0[c * ls + x] = make_float2(d[(long long)i * m * C + (long long)x * C + c0 + c], 0.f);
+    }
+    const float2* F = fft_lines<-1>(A0, A1, tw, m, nc, ls);
+    const int n = wk.ord[i];
+    for (int p = threadIdx.x; p < m * nc; p += blockDim.x) {
+      const int c = p / m, q = p - c * m;
+      // c_k^{-1} (-2i sin)^n = c_k^{-1} (2 sin)^n (-i)^n
+      const double mag = wk.cinv[i] * pow(2.0 * sinpi(2.0 * (double)q / (double)m), (double)n);
+      float2 w;
+      switch (n & 3) {
+        case 0: w = make_float2((float)mag, 0.f); break;
+        case 1: w = make_float2(0.f, (float)-mag); break;
+        case 2: w = make_float2((float)-mag, 0.f); break;
+        default: w = make_float2(0.f, (float)mag); break;
+      }
+      const float2 v = F[c * ls + q];
+      float2& a = acc[c * ls + q];
+      a.x += w.x * v.x - w.y * v.y;
+      a.y += w.x * v.y + w.y * v.x;
+    }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < m * nc; p += blockDim.x) {
+    const int c = p / m, q = p - c * m;
+    const float inv = 1.f / den[q];
+    A0[c * ls + q] = make_float2(acc[c * ls + q].x * inv, acc[c * ls + q].y * inv);
+  }
+  const float2* G = fft_lines<+1>(A0, A1, tw, m, nc, ls);
+  const float invm = 1.f / (float)m;
+  for (int p = threadIdx.x; p < m * nc; p += blockDim.x) {
+    const int x = p / nc, c = p - x * nc;
+    out[(long long)x * C + c0 + c] = G[c * ls + x].x * invm;
+  }
+}
+
 // y^{k0} = rho^{k0} + (k0-1)/(k0+2) (rho^{k0} - rho^{k0-1}) for a (re)started solve.
 __global__ void k_fista_init(long long n, const float* __restrict__ rk, const float* __restrict__ rkm1,
                              float beta, float* __restrict__ y) {

@@ -1245,7 +1245,31 @@ extern "C" mh3d_status mh3d_profile_read(mh3d_plan_t p, mh3d_profile_data* out) 
 }
 
 // ============================================================================ warm-start network
-// ============================================================================ pass timing
+// ============================================================================ MHAD
+extern "C" mh3d_status mh3d_mhad(mh3d_plan_t p, const float* d, double lambda, const double* c, float* out) {
+  CHK(check_plan(p));
+  if (!d || !out) return fail(MH3D_ERR_INVALID, "NULL array");
+  if (!(lambda > 0.0) || !(lambda < 1e300)) return fail(MH3D_ERR_INVALID, "MHAD needs a finite lambda > 0");
+  const Geo& g = p->g;
+  const int m = g.mxf;
+  if (!is_23_smooth(m)) return fail(MH3D_ERR_UNSUPPORTED, "MHAD needs a drive-axis portrait length 2^a 3^b (got %d)", m);
+  MhadW wk;
+  memset(&wk, 0, sizeof wk);
+  for (int i = 0; i < g.K; ++i) {
+    wk.ord[i] = p->harm[i] + p->desc.order_offset - 1;
+    const double ck = c ? c[i] : 1.0;
+    if (!(ck != 0.0) || !std::isfinite(ck)) return fail(MH3D_ERR_INVALID, "c[%d] must be finite and nonzero", i);
+    wk.cinv[i] = 1.0 / ck;
+  }
+  const int ls = pad_odd(m);
+  const int CB = std::max(1, std::min(32, (int)(60 * 1024 / (24 * (size_t)ls))));
+  const long long C = (long long)g.myf * g.mzf;
+  const size_t lds = sizeof(float2) * ((size_t)m + 3 * (size_t)CB * ls) + sizeof(float) * m;
+  k_mhad<<<dim3((unsigned)((C + CB - 1) / CB)), dim3(256), lds, p->stream>>>(d, g.K, wk, lambda, m, C, CB, out);
+  return last_launch("k_mhad");
+}
+
+// ============================================================================ pass timing// ============================================================================ pass timing
 extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps, double* us) {
   CHK(check_plan(p));
   if (pass < 0 || pass > 5 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");

@@ -120,6 +120,7 @@ def library():
     lib.mh3d_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tiles), ctypes.POINTER(dbl)]
     lib.mh3d_time_pass.argtypes = [vp, i32, i32, ctypes.POINTER(dbl)]
     lib.mh3d_forward_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.mh3d_mhad.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), vp]
     lib.mh3d_last_error.restype = ctypes.c_char_p
     lib.mh3d_version.restype = i32
     for name in ("mh3d_plan_describe", "mh3d_plan", "mh3d_forward", "mh3d_adjoint", "mh3d_normal",
@@ -128,7 +129,7 @@ def library():
                  "mh3d_net_create", "mh3d_net_params", "mh3d_net_grads", "mh3d_net_forward", "mh3d_net_loss_grad",
                  "mh3d_net_adam_step", "mh3d_warm_start", "mh3d_phantom", "mh3d_noisy_data", "mh3d_backproject",
                  "mh3d_plan_set_tiles", "mh3d_plan_get_tiles", "mh3d_autotune", "mh3d_time_pass",
-                 "mh3d_forward_adjoint"):
+                 "mh3d_forward_adjoint", "mh3d_mhad"):
         getattr(lib, name).restype = st
     _lib = lib
     return lib
@@ -324,6 +325,14 @@ class Plan:
         path = None if cache_path is None else str(cache_path).encode()
         _check(library().mh3d_autotune(self._h, path, ctypes.byref(t), ctypes.byref(us)))
         return (t.E, t.cpw, t.xb, t.ps), us.value
+
+    def mhad(self, d, lam, c=None):
+        """Closed-form native image on the portrait grid (App. D)."""
+        d = self._port(d)
+        out = self.torch.empty(self.small, device=self.device)
+        cc = None if c is None else (ctypes.c_double * self.K)(*[float(v) for v in c])
+        _check(library().mh3d_mhad(self._h, _ptr(d), float(lam), cc, _ptr(out)))
+        return out
 
     def backproject(self, d, out=None):
         """Per-harmonic back-projections c_k = b (H_k^T P^T d_k), [K][X][Y][Z]."""
