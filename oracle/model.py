@@ -8,7 +8,9 @@ Sec. 4.1, eq. dN): for each harmonic k,
 where (*) is circular 3D convolution (H_k circulant, Sec. 3.2), b is a scalar
 receive sensitivity (B diagonal, Table tab:ops) and P keeps every s-th sample per
 axis (row selector, Sec. 4.1).  Arrays are C-order [x][y][z] (z fastest).  The
-drive axis is x (array axis 0).
+drive axis is x (array axis 0).  The vector model of eq. MH3Dcont / matrixModel sums
+this over the components of the PSF vector and of the sensitivity
+(``forward_vector``/``adjoint_vector``).
 
 Readings of points the paper leaves open (each is listed with its reason in the
 design notes of the repository):
@@ -190,6 +192,35 @@ def adjoint_fft(h, b, r, ds, workers=None):
     R = sfft.fftn(up, axes=(1, 2, 3), workers=w)
     x = sfft.ifftn(np.sum(np.conj(Hf) * R, axis=0), workers=w).real
     return b * x
+
+
+# --------------------------------------------------------------------------- vector model
+def forward_vector(h, b, rho, ds, tier=2):
+    """Vector model (Sec. 3.2, eq. MH3Dcont and the stacked matrix of eq. matrixModel):
+    d_k = sum_i P H_{k,i} B_i rho over the components i of the PSF vector h_k and of
+    the receive sensitivity b_1.  h: [C][K][grid], b: [C][grid]."""
+    f = forward_direct if tier == 1 else forward_fft
+    return sum(f(h[i], b[i], rho, ds) for i in range(h.shape[0]))
+
+
+def adjoint_vector(h, b, r, ds, tier=2):
+    """Adjoint of the stacked matrix: A^T r = sum_i B_i sum_k H_{k,i}^T P^T r_k."""
+    f = adjoint_direct if tier == 1 else adjoint_fft
+    return sum(f(h[i], b[i], r, ds) for i in range(h.shape[0]))
+
+
+def point_source_portraits(h, b, positions, weights, ds):
+    """Portraits of rho = sum_n w_n delta(x - x_n) as App. F builds them: each source
+    adds w_n sum_i b_i(x_n) h_{k,i}(x - x_n), the component PSFs shifted to the source
+    (periodic) and weighted by the sensitivity there; P keeps every ds-th sample.
+    h: [C][K][grid] (or [K][grid] for the scalar model with b: [grid])."""
+    if h.ndim == 4:
+        h, b = h[None], b[None]
+    full = np.zeros(h.shape[1:])
+    for (x0, y0, z0), w in zip(positions, weights):
+        for i in range(h.shape[0]):
+            full += w * b[i][x0, y0, z0] * np.roll(h[i], (x0, y0, z0), axis=(1, 2, 3))
+    return np.ascontiguousarray(full[:, ::ds[0], ::ds[1], ::ds[2]])
 
 
 # --------------------------------------------------------------------------- boundary padding

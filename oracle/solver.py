@@ -26,19 +26,24 @@ class Operator:
 
     def __init__(self, h, b, ds, lam, reg_kind=0, tier=2, alpha=0.0, alpha_width=0, pad=(0, 0, 0)):
         """pad: boundary padding (Sec. 4.1.1) -- h, b and the volumes live on the padded
-        grid, the portraits on its field of view (A = C P H B, C the crop)."""
+        grid, the portraits on its field of view (A = C P H B, C the crop).  h of shape
+        [C][K][grid] with b [C][grid] selects the vector model (sum over components)."""
         self.h, self.b, self.ds = h, b, tuple(ds)
         self.lam, self.reg_kind = float(lam), reg_kind
         self.alpha, self.alpha_width = float(alpha), int(alpha_width)
         self.pad = tuple(int(p) for p in pad)
-        self.small = model.small_shape(h.shape[1:], ds)
+        # vector model (Sec. 3.2 eq. matrixModel): h [C][K][grid] and b [C][grid]
+        self.vector = h.ndim == 5
+        self.small = model.small_shape(h.shape[-3:], ds)
         self.tier = tier
 
     def reg_normal(self, x):
         return model.reg_normal(x, self.reg_kind, self.alpha, self.alpha_width)
 
     def A(self, x):
-        if self.tier == 1:
+        if self.vector:
+            d = model.forward_vector(self.h, self.b, x, self.ds, self.tier)
+        elif self.tier == 1:
             d = model.forward_direct(self.h, self.b, x, self.ds)
         else:
             d = model.forward_fft(self.h, self.b, x, self.ds)
@@ -47,6 +52,8 @@ class Operator:
     def AT(self, r):
         if any(self.pad):
             r = model.embed_portraits(r, self.pad, self.ds, self.small)
+        if self.vector:
+            return model.adjoint_vector(self.h, self.b, r, self.ds, self.tier)
         if self.tier == 1:
             return model.adjoint_direct(self.h, self.b, r, self.ds)
         return model.adjoint_fft(self.h, self.b, r, self.ds)
@@ -100,7 +107,7 @@ def fista(op, d, tau, rho_init=None, max_iter=50, tol=None, nonneg=True,
     Runs at most ``max_iter`` updates; if ``tol`` is given, stops after the first
     update with r_k <= tol.  ``rho_prev``/``k0`` resume an interrupted run
     (state (rho^k, rho^{k-1}, k)).  Returns (rho, history of r_k, updates done)."""
-    shape = op.h.shape[1:]
+    shape = op.h.shape[-3:]
     rho = np.zeros(shape) if rho_init is None else np.array(rho_init, dtype=np.float64)
     prev = rho.copy() if rho_prev is None else np.array(rho_prev, dtype=np.float64)
     hist = []

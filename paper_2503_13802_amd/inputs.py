@@ -197,3 +197,31 @@ def random_field(shape, seed, kind="normal"):
     if kind == "uniform":
         return rng.uniform(0.0, 1.0, shape)
     return rng.standard_normal(shape)
+
+
+def vector_psfs(n_comp, n_harm, shape, seed, width_vox=2.5):
+    """Seeded synthetic component PSFs [n_comp][n_harm][nx][ny][nz]: standard normal
+    fields under a periodic Gaussian window of ``width_vox`` voxels centred at index 0
+    (compact kernels, as measured or simulated point-spread functions are)."""
+    rng = np.random.default_rng([seed, 3])
+    win = np.ones(shape)
+    for a, n in enumerate(shape):
+        i = np.arange(n)
+        w = np.minimum(i, n - i).astype(np.float64)
+        prof = np.exp(-0.5 * (w / width_vox) ** 2)
+        win = win * prof.reshape([n if b == a else 1 for b in range(3)])
+    return rng.standard_normal((n_comp, n_harm) + tuple(shape)) * win
+
+
+def vector_sensitivity(n_comp, shape, seed):
+    """Seeded smooth component sensitivities [n_comp][nx][ny][nz]: per component an
+    offset plus one random low-frequency cosine per axis."""
+    rng = np.random.default_rng([seed, 4])
+    out = np.empty((n_comp,) + tuple(shape))
+    for c in range(n_comp):
+        f = np.full(shape, rng.uniform(0.5, 1.0))
+        for a, n in enumerate(shape):
+            i = np.arange(n).reshape([n if b == a else 1 for b in range(3)])
+            f = f + rng.uniform(-0.3, 0.3) * np.cos(2 * np.pi * (i / n) * rng.integers(1, 3) + rng.uniform(0, 2 * np.pi))
+        out[c] = f
+    return out
