@@ -23,8 +23,11 @@ The cpu_baseline leg (the only one that runs the FP64 oracle) times the oracle's
 A+A^T and its reconstruction of oracle-made data, which the GPU solver repeats on the
 same data: the relative L2 difference of the two reconstructions is reported there.
 
+The vector leg times the same fused step for the vector model of eq. matrixModel on
+the workload's grid (seeded synthetic component PSFs and sensitivities, C = 1 and 3).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1|2] [--no-cpu] [--no-solve]
-                       [--no-batch] [--no-warm] [--warm-train-steps T] [--warm-eval E]
+                       [--no-batch] [--no-warm] [--no-vector] [--warm-train-steps T] [--warm-eval E]
 """
 import argparse
 import json
@@ -42,11 +45,12 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(w, compact=True):
+def algorithmic_bytes(w, compact=True, ncomp=1):
     """Per-application algorithmic bytes of A (and of A^T, the same total):
-    4N (rho) + 4N (b) + beta_H K N_c (spectra) + 4 K M (portraits), and of the
-    dominant spectral kernel: beta_H K N_c + 8 N_c (yz spectrum in) + 8 K M_c
-    (decimated spectra out), N_c = nx ny (nz/2+1), M_c = mx my (mz/2+1)."""
+    4N (rho) + 4CN (b) + beta_H C K N_c (spectra) + 4 K M (portraits), and of the
+    dominant spectral kernel: beta_H C K N_c + 8 C N_c (yz spectra in) + 8 K M_c
+    (decimated spectra out), N_c = nx ny (nz/2+1), M_c = mx my (mz/2+1), C the
+    components of the vector model (1 for the scalar model)."""
     nx, ny, nz = w.shape
     mx, my, mz = w.small_shape
     K = len(w.harmonics)
@@ -55,8 +59,9 @@ def algorithmic_bytes(w, compact=True):
     Nc = nx * ny * (nz // 2 + 1)
     Mc = mx * my * (mz // 2 + 1)
     bh = 4 if compact else 8
-    op = 4 * N + 4 * N + bh * K * Nc + 4 * K * M
-    spectral = bh * K * Nc + 8 * Nc + 8 * K * Mc
+    C = ncomp
+    op = 4 * N + 4 * C * N + bh * C * K * Nc + 4 * K * M
+    spectral = bh * C * K * Nc + 8 * C * Nc + 8 * K * Mc
     return op, spectral
 
 
@@ -196,6 +201,49 @@ SHIPPED_TILES = os.path.join(ROOT, "paper_2503_13802_amd", "tiles_gfx950.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_class_workload1.md")
 
 
+def vector_leg(w, steps, warmup, tile_cache=None):
+    """The vector model (eq. matrixModel) on the workload's grid: seeded synthetic
+    component PSFs and sensitivities for C = 1 (user spectra, complex) and C = 3;
+    fused A+A^T applications per second and the class passes' HBM rate."""
+    import torch
+    from paper_2503_13802_amd import inputs, mh3d
+    dev = torch.device("cuda:0")
+    K = len(w.harmonics)
+    out = {"grid": list(w.shape), "harmonics": list(w.harmonics), "decimation": list(w.ds),
+           "inputs": "inputs.vector_psfs / vector_sensitivity (seeded synthetic)"}
+    rho = torch.tensor(inputs.phantom(w), dtype=torch.float32, device=dev)
+    for C in (1, 3):
+        h = inputs.vector_psfs(C, K, w.shape, 7000 + C)
+        b = inputs.vector_sensitivity(C, w.shape, 7100 + C)
+        if C == 1:
+            h, b = h[0], b[0]
+        plan = mh3d.Plan(w.shape, w.harmonics, 1.0, w.ds, 1.0, w.lam, psf=torch.tensor(h, dtype=torch.float32),
+                         sens=torch.tensor(b, dtype=torch.float32))
+        tiles = plan.tiles()
+        if tile_cache is not None:
+            tiles, _ = plan.autotune(tile_cache)
+        y = torch.empty((K,) + w.small_shape, device=dev)
+        x = torch.empty(w.shape, device=dev)
+        for _ in range(warmup):
+            plan.forward_adjoint(rho, d_out=y, x_out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.forward_adjoint(rho, d_out=y, x_out=x)
+        torch.cuda.synchronize()
+        rate = steps / (time.perf_counter() - t0)
+        pass_us = {k: plan.time_pass(k, reps=100) for k in mh3d.Plan.PASSES}
+        _, spec = algorithmic_bytes(w, compact=False, ncomp=C)
+        avg_s = 0.5 * (pass_us["class_fwd"] + pass_us["class_adj"]) * 1e-6
+        out["C%d" % C] = {"applications_per_s": round(rate, 2), "tiles": list(tiles),
+                          "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
+                          "class_bytes_per_launch": spec, "class_GBps": round(spec / avg_s / 1e9, 1)}
+        log("vector C=%d: %.1f A+A^T/s, tiles %s" % (C, rate, tiles))
+        plan.close()
+    out["C3_over_C1_time"] = round(out["C1"]["applications_per_s"] / out["C3"]["applications_per_s"], 3)
+    return out
+
+
 def tile_cache_path(arg):
     """The autotuner cache: the given path, else a temp copy of the shipped one."""
     if arg:
@@ -270,6 +318,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-vector", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
     ap.add_argument("--tile-cache", default=None, help="autotuner JSON cache (default: a file in the temp dir)")
     ap.add_argument("--warm-train-steps", type=int, default=20000)
@@ -418,6 +467,9 @@ def main():
                                 "iters": info["iters"], "rel_step": info["rel_step"],
                                 "ms_per_iter": round(info2["ms_per_iter"], 4), "tau": info["tau"],
                                 "status": info["status"], "identical_rerun": bool(torch.equal(rec, rec2))}
+
+    if not args.no_vector:
+        out["vector_model"] = vector_leg(w, min(args.steps, 200), min(args.warmup, 20), tile_cache)
 
     if batch_inputs is not None:
         out["batched"] = batched_leg(batch_inputs, w.tol, w.max_iter, tile_cache)

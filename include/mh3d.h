@@ -9,6 +9,10 @@
  *                Table tab:ops (B Hadamard, H_k by FFT with precomputed spectrum,
  *                P a gather).  (*) is circular 3D convolution (H_k circulant).
  *   adjoint   rho = A^T d = b . sum_k h_k (x) (P^T d_k)   ((x): correlation)
+ *   vector    d_k = P sum_i ( h_{k,i} (*) (b_i . rho) ) over the components i of the
+ *             PSF vector and of the receive sensitivity (Sec. 3.2 eq. MH3Dcont and the
+ *             stacked matrix of eq. matrixModel; App. F), user-supplied; its adjoint
+ *             is sum_i b_i . sum_k h_{k,i} (x) (P^T d_k)
  *   solve     argmin_{rho >= 0} 1/2 ||A rho - d||^2 + 1/2 lambda ||T rho||^2
  *             -- Sec. 4.2 eq. Amodel with the second-order Tikhonov term, solved by
  *                the accelerated projected gradient of Sec. 4.3.
@@ -65,8 +69,11 @@ typedef struct {
   const int32_t* harm;       /* HOST array of harmonic indices k >= 2, strictly increasing */
   int32_t order_offset;      /* PSF uses L^(k + order_offset); 0 by default              */
   double a_per_mm;           /* Langevin argument scale a (1/mm), > 0                    */
-  const float* psf;          /* optional DEVICE [n_harm][nx][ny][nz]; NULL -> analytic    */
-  const float* sens;         /* optional DEVICE [nx][ny][nz]; NULL -> Gaussian sigma_mm  */
+  const float* psf;          /* optional DEVICE [ncomp][n_harm][nx][ny][nz]; NULL -> analytic */
+  const float* sens;         /* optional DEVICE [ncomp][nx][ny][nz]; NULL -> Gaussian sigma_mm */
+  int32_t ncomp;             /* components of the vector model (Sec. 3.2 eq. MH3Dcont /
+                                matrixModel): 0 or 1 -> scalar model; 2 or 3 -> d_k =
+                                sum_i P H_{k,i} B_i rho with psf and sens both given   */
   double sigma_mm[3];        /* Gaussian sensitivity widths (mm), peak 1 at the centre   */
   double lambda;             /* Tikhonov weight, >= 0                                    */
   int32_t reg_kind;          /* 0: stacked periodic second differences; 1: T = I         */
@@ -129,7 +136,8 @@ mh3d_status mh3d_forward_adjoint(mh3d_plan_t plan, const float* rho, float* d, f
 
 /* Per-harmonic back-projections c_k = b (H_k^T P^T d_k), the terms of A^T d before
  * the sum over harmonics (adjoint of eq. dN, one harmonic at a time); sum_k c_k =
- * A^T d.  d: portraits, c: DEVICE [n_harm][nx][ny][nz]. */
+ * A^T d.  Vector model: c_k = sum_i b_i (H_{k,i}^T P^T d_k).  d: portraits, c: DEVICE
+ * [n_harm][nx][ny][nz]. */
 mh3d_status mh3d_backproject(mh3d_plan_t plan, const float* d, float* c);
 
 /* Multi-harmonic anti-differentiation (App. D, eq. mhadM): the closed-form native
@@ -255,9 +263,10 @@ mh3d_status mh3d_noisy_data(mh3d_plan_t plan, const float* rho, uint64_t seed, d
 /* Copies internal plan data to a caller DEVICE buffer, for tests and tools.
  *   MH3D_FIELD_PROFILE   FP64 [n_harm][nx]      drive-axis profiles L^(k)(a x), raw
  *   MH3D_FIELD_ENVELOPE  FP64 [ny][nz]          transverse envelope E, raw
- *   MH3D_FIELD_SENS      FP32 [nx][ny][nz]      sensitivity b
- *   MH3D_FIELD_SPECTRUM  FP32 complex [n_harm][nx][ny][nz/2+1]  fft(h_k) (unnormalised
- *                        DFT of the unit-norm PSF), read back from the plan's layout
+ *   MH3D_FIELD_SENS      FP32 [ncomp][nx][ny][nz]      sensitivity b
+ *   MH3D_FIELD_SPECTRUM  FP32 complex [ncomp][n_harm][nx][ny][nz/2+1]  fft(h_k)
+ *                        (unnormalised DFT of the PSF; the analytic one has unit norm),
+ *                        read back from the plan's layout
  * *bytes receives the size needed; dst may be NULL to query it. */
 typedef enum {
   MH3D_FIELD_PROFILE = 0,

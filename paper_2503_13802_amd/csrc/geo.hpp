@@ -44,10 +44,11 @@ struct Geo {
   int ncls;                // classes = my*mzh
   int plane;               // complex values per x-plane of the class layout = ncls*nmem
   int K;                   // harmonics
+  int C;                   // components of the vector model (1: scalar b and h_k)
   int cpw;                 // classes per class-kernel workgroup (divides ncls)
   int E;                   // spectrum elements per thread in the class kernel (divides S)
   int xb;                  // x' planes per small-grid workgroup (divides mx)
-  int ps;                  // workgroups per x-plane in the plane passes (1 or 2)
+  int ps;                  // workgroups per x-plane in the plane passes (1 to 4)
   int npairs;              // (ny + 1)/2 row pairs of one full x-plane
   int spairs;              // (xb*my + 1)/2 row pairs of one small-grid workgroup
   int lsy;                 // LDS line stride of y-transforms in the plane kernels (ny + pad)

@@ -169,6 +169,11 @@ struct VolDesc {
   float alpha;             // boundary prior weight (eq. finalR), 0 = off
   int aw;                  // its shell depth in voxels
   int nb_upd;              // blocks of k_vol_update for this volume
+  // Vector model (components i of the PSF vector and of the sensitivity): component
+  // i's spectra at hs + i * hs_cstride elements, its sensitivity at b + i * N and its
+  // class-layout spectra at uperm + i * hsz.  ncomp = 1 is the scalar model.
+  int ncomp;
+  long long hs_cstride;
 };
 
 // Volume and local block index of this block: task table (batched launches) or
@@ -313,11 +318,15 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
   load_table(twy, vd.tw + vd.off[1], g.ny);
   float c = 1.f;
   if constexpr (SRC == SRC_SCALED) c = (float)vd.st->scale;
-  const float* __restrict__ b = vd.b;
   const long long pbase = (long long)x * g.ny * g.nz;
   const int nyz = g.ny * g.nz;
   const int lsz = pad_odd(g.nz);
   float* Zf = reinterpret_cast<float*>(P0);
+  // vector model: one transform of b_i . a per component (a raw source has one)
+  const int ncomp = (SRC == SRC_RAW) ? 1 : vd.ncomp;
+  for (int comp = 0; comp < ncomp; ++comp) {
+  if (comp) __syncthreads();   // the previous component's store still reads the LDS planes
+  const float* __restrict__ b = vd.b + (long long)comp * g.N;
   batched<8, float>(nyz, [&](int p) { return plane_source<SRC>(pbase + p, a, nullptr, b, c); },
                     [&](int p, float v) {
                       const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
@@ -330,7 +339,7 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
   float2* X = r2c_rows(P0, P1, twz, g.ny, g.nz, g.nzh, g.npairs, rc, g.f_nzh);   // X[qz][lsy]
   // column qz of the result at Y[(qz - q0) * lsy]
   float2* Y = fft_lines<-1>(X + q0 * g.lsy, (X == P0 ? P1 : P0) + q0 * g.lsy, twy, g.ny, q1 - q0, g.lsy);
-  float2* dst = vd.uperm + (long long)x * g.plane;
+  float2* dst = vd.uperm + (long long)comp * g.hsz + (long long)x * g.plane;
   for (int e = threadIdx.x; e < g.plane; e += blockDim.x) {
     const int cc = (int)g.f_nmem.div((uint32_t)e), m = e - cc * g.nmem;
     const int cy = (int)g.f_mzh.div((uint32_t)cc), cz = cc - cy * g.mzh;
@@ -347,6 +356,7 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
       v.y = -v.y;
     }
     dst[e] = v;
+  }
   }
 }
 
@@ -425,7 +435,8 @@ __device__ __forceinline__ void class_g_index(const Geo& g, int p, int c0, int& 
 
 // Forward pass 2 of one block (cpw classes).  Threads beyond vd.T_class only take
 // part in the barriers and shuffles (batched launches use the largest block size).
-template <int HC, int E>
+// VEC: vector model, vd.ncomp components (else one, and the loop folds away).
+template <int HC, int E, bool VEC = false>
 __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
   constexpr int HPF = hpf_of(HC, E);
   const Geo& g = vd.g;
@@ -446,16 +457,25 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
   const int rem = e0 - cl * per_cls;
   const int qxp = (int)g.f_S.div((uint32_t)rem);
   const int within = rem - qxp * g.S;
-  const long long hoff0 = (long long)c0 * per_cls + e0;
   const void* hs = vd.hs;
+  const int LG = g.S / E;
+  const uint32_t imag_mask = vd.imag_mask;
+  // vector model: the products of every component accumulate in F0 before the one
+  // inverse transform (the sum over i commutes with it)
+  const int ncomp = VEC ? vd.ncomp : 1;
+  for (int comp = 0; comp < ncomp; ++comp) {
+  if (comp) __syncthreads();   // the previous component's U is still being read
+  const long long hoff0 = (long long)c0 * per_cls + e0 + comp * vd.hs_cstride;
   // spectra do not depend on the data: start streaming them first
   HLoad<HC, E> hb[HPF];
 #pragma unroll
   for (int i = 0; i < HPF; ++i)
     if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
-  load_table(twx, vd.tw + vd.off[0], g.nx);
-  load_table(twm, vd.tw + vd.off[3], g.mx);
-  const float2* __restrict__ uperm = vd.uperm;
+  if (comp == 0) {
+    load_table(twx, vd.tw + vd.off[0], g.nx);
+    load_table(twm, vd.tw + vd.off[3], g.mx);
+  }
+  const float2* __restrict__ uperm = vd.uperm + (long long)comp * g.hsz;
   batched<8, float2>(g.nx * W,
                      [&](int p) {
                        const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
@@ -473,8 +493,6 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
     const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
     ur[i] = act ? U[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] : make_float2(0.f, 0.f);
   }
-  const int LG = g.S / E;
-  const uint32_t imag_mask = vd.imag_mask;
   for (int k0 = 0; k0 < g.K; k0 += HPF) {
 #pragma unroll
     for (int i = 0; i < HPF; ++i) {
@@ -496,9 +514,13 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
           acc.x += __shfl_xor(acc.x, o, 64);
           acc.y += __shfl_xor(acc.y, o, 64);
         }
-        if (act && (threadIdx.x & (LG - 1)) == 0) F0[(k * g.cpw + cl) * g.mx + qxp] = acc;
+        if (act && (threadIdx.x & (LG - 1)) == 0) {
+          float2& f = F0[(k * g.cpw + cl) * g.mx + qxp];
+          f = comp ? cadd(f, acc) : acc;
+        }
       }
     }
+  }
   }
   const float2* F = fft_lines<+1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
   float2* __restrict__ G = vd.G;
@@ -511,7 +533,7 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
 }
 
 // Adjoint pass 2 of one block.
-template <int HC, int E>
+template <int HC, int E, bool VEC = false>
 __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
   constexpr int HPF = hpf_of(HC, E);
   const Geo& g = vd.g;
@@ -531,12 +553,11 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
   const int rem = e0 - cl * per_cls;
   const int qxp = (int)g.f_S.div((uint32_t)rem);
   const int within = rem - qxp * g.S;
-  const long long hoff0 = (long long)c0 * per_cls + e0;
   const void* hs = vd.hs;
   HLoad<HC, E> hb[HPF];
 #pragma unroll
   for (int i = 0; i < HPF; ++i)
-    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + (long long)c0 * per_cls + e0);
   load_table(twx, vd.tw + vd.off[0], g.nx);
   load_table(twm, vd.tw + vd.off[3], g.mx);
   const float2* __restrict__ Gp = vd.Gp;
@@ -554,6 +575,16 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
                        F0[fo] = v;
                      });
   const float2* F = fft_lines<-1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
+  // vector model: H_{k,i}^T of every component i from the one transform of the data
+  const int ncomp = VEC ? vd.ncomp : 1;
+  for (int comp = 0; comp < ncomp; ++comp) {
+  const long long hoff0 = (long long)c0 * per_cls + e0 + comp * vd.hs_cstride;
+  if (comp) {
+    __syncthreads();   // the previous component's store still reads U0/U1
+#pragma unroll
+    for (int i = 0; i < HPF; ++i)
+      if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  }
   float2 acc[E];
 #pragma unroll
   for (int t = 0; t < E; ++t) acc[t] = make_float2(0.f, 0.f);
@@ -587,28 +618,29 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
     }
   }
   const float2* V = fft_lines<+1>(U0, U1, twx, g.nx, W, g.lsx);
-  float2* __restrict__ vperm = vd.uperm;
+  float2* __restrict__ vperm = vd.uperm + (long long)comp * g.hsz;
   for (int p = threadIdx.x; p < g.nx * W; p += blockDim.x) {
     const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
     vperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e] = V[e * g.lsx + xx];
+  }
   }
 }
 
 // Single-volume class passes, grid = ncls/cpw blocks of T_class threads.
 // check_done skips the launch once the volume's solve is done.
-template <int HC, int E>
+template <int HC, int E, bool VEC>
 __global__ __launch_bounds__(1024) void k_class_fwd(const VolDesc* __restrict__ vds, int check_done) {
   int lb;
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   if (check_done && vd.st->done) return;
-  class_fwd_body<HC, E>(vd, lb);
+  class_fwd_body<HC, E, VEC>(vd, lb);
 }
-template <int HC, int E>
+template <int HC, int E, bool VEC>
 __global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ vds, int check_done) {
   int lb;
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   if (check_done && vd.st->done) return;
-  class_adj_body<HC, E>(vd, lb);
+  class_adj_body<HC, E, VEC>(vd, lb);
 }
 
 // Batched class passes over a task table (compact spectra), the element split E
@@ -871,7 +903,11 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   const int h = lb / g.nx;
   const int x = plane_of_block(lb - h * g.nx, g.nx);
   const int j0 = h * g.npairs / g.ps, j1 = (h + 1) * g.npairs / g.ps;
-  const float2* src = vd.uperm + (long long)x * g.plane;
+  // vector model: out = sum_i b_i . v_i, the components added in order by the thread
+  // that owns the voxel
+  for (int comp = 0; comp < vd.ncomp; ++comp) {
+  if (comp) __syncthreads();   // the previous component's store still reads the LDS planes
+  const float2* src = vd.uperm + (long long)comp * g.hsz + (long long)x * g.plane;
   batched<8, float2>(g.plane, [&](int e) { return src[e]; }, [&](int e, float2 v) { P1[e] = v; });
   __syncthreads();
   for (int p = threadIdx.x; p < g.ny * g.nzh; p += blockDim.x) {
@@ -891,11 +927,17 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
     const int y = (int)g.f_nz.div((uint32_t)p), z = p - y * g.nz;
     return 2 * (((y >> 1) - j0) * lsz + z) + (y & 1);
   };
-  const float* __restrict__ b = vd.b;
+  const float* __restrict__ b = vd.b + (long long)comp * g.N;
   const long long pbase = (long long)x * g.ny * g.nz + (long long)y0 * g.nz;
   float* __restrict__ out = (OUT == OUT_U) ? vd.u : ao.out;
-  batched<8, float>((y1 - y0) * g.nz, [&](int p) { return b[pbase + p]; },
-                    [&](int p, float bv) { out[pbase + p] = bv * Xf[vidx(p + y0 * g.nz)]; });
+  if (comp == 0) {
+    batched<8, float>((y1 - y0) * g.nz, [&](int p) { return b[pbase + p]; },
+                      [&](int p, float bv) { out[pbase + p] = bv * Xf[vidx(p + y0 * g.nz)]; });
+  } else {
+    batched<8, float>((y1 - y0) * g.nz, [&](int p) { return b[pbase + p]; },
+                      [&](int p, float bv) { out[pbase + p] += bv * Xf[vidx(p + y0 * g.nz)]; });
+  }
+  }
 }
 
 // Blocks of the volume-wide update pass, each a contiguous run of whole 1024-voxel

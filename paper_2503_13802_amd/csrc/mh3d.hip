@@ -173,6 +173,9 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
       return fail(MH3D_ERR_INVALID, "derivative order k + order_offset must be in [1, 24]");
   }
   if (!d->psf && !(d->a_per_mm > 0)) return fail(MH3D_ERR_INVALID, "a_per_mm must be > 0");
+  if (d->ncomp < 0 || d->ncomp > 3) return fail(MH3D_ERR_INVALID, "ncomp must be in [0, 3]");
+  if (d->ncomp > 1 && (!d->psf || !d->sens))
+    return fail(MH3D_ERR_INVALID, "the vector model (ncomp > 1) needs user PSFs and sensitivities");
   if (!d->sens)
     for (int a = 0; a < 3; ++a)
       if (!(d->sigma_mm[a] > 0)) return fail(MH3D_ERR_INVALID, "sigma_mm[%d] must be > 0", a);
@@ -205,6 +208,7 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   g.npairs = (g.ny + 1) / 2;
   g.N = (long long)g.nx * g.ny * g.nz;
   g.M = (long long)g.mx * g.my * g.mz;
+  g.C = d->ncomp > 1 ? d->ncomp : 1;
   g.padded = (d->pad[0] || d->pad[1] || d->pad[2]) ? 1 : 0;
   g.pxs = d->pad[0] / g.sx; g.pys = d->pad[1] / g.sy; g.pzs = d->pad[2] / g.sz;
   g.mxf = g.mx - 2 * g.pxs; g.myf = g.my - 2 * g.pys; g.mzf = g.mz - 2 * g.pzs;
@@ -287,9 +291,9 @@ static mh3d_status dalloc(mh3d_plan_t p, void** ptr, size_t bytes) {
 
 static size_t plan_bytes(const Geo& g, bool compact) {
   size_t s = 0;
-  s += (size_t)g.K * g.hsz * (compact ? 4 : 8);
-  s += (size_t)g.N * 4;                               // b
-  s += (size_t)g.nx * g.plane * 8;                    // uperm
+  s += (size_t)g.C * g.K * g.hsz * (compact ? 4 : 8);
+  s += (size_t)g.C * g.N * 4;                         // b
+  s += (size_t)g.C * g.nx * g.plane * 8;              // uperm
   s += 2 * (size_t)g.K * g.mx * g.ncls * 8;           // G, Gp
   s += 5 * (size_t)g.N * 4;                           // vol
   s += (size_t)(2 * (g.nx + g.ny + g.nz) + g.mx + g.my + g.mz) * 24;
@@ -366,13 +370,17 @@ static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
   return last_launch("k_plane_fwd");
 }
 
+// HC: 0 compact (analytic) spectra, 1 complex (user) spectra, 2 complex spectra of a
+// vector-model plan (components looped inside the class passes).
 template <int HC, int E>
 static void class_fwd_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
-  k_class_fwd<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
+  k_class_fwd<HC == 0 ? 0 : 1, E, HC == 2>
+      <<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
 }
 template <int HC, int E>
 static void class_adj_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
-  k_class_adj<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
+  k_class_adj<HC == 0 ? 0 : 1, E, HC == 2>
+      <<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
 }
 
 #define E_DISPATCH(HCV, FN)                       \
@@ -389,14 +397,14 @@ static void class_adj_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
 static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk) {
   Timer t(p, KID_CLASS_FWD);
   const VolDesc* vd = p->vdd;
-  if (p->compact) { E_DISPATCH(0, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
+  if (p->compact) { E_DISPATCH(0, class_fwd_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
   return last_launch("k_class_fwd");
 }
 // vd: a single-harmonic descriptor (per-harmonic back-projection) or NULL for the plan's.
 static mh3d_status launch_class_adj(mh3d_plan_t p, int chk, const VolDesc* vd = nullptr) {
   Timer t(p, KID_CLASS_ADJ);
   if (!vd) vd = p->vdd;
-  if (p->compact) { E_DISPATCH(0, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
+  if (p->compact) { E_DISPATCH(0, class_adj_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
   return last_launch("k_class_adj");
 }
 
@@ -529,7 +537,8 @@ static mh3d_status build_spectra_user(mh3d_plan_t p) {
   const Geo& g = p->g;
   p->imag_mask = 0;
   size_t lds = sizeof(float2) * ((size_t)g.nx + 2 * (size_t)g.lsx * g.cpw * g.nmem);
-  for (int k = 0; k < g.K; ++k) {
+  // component i's spectra follow component i - 1's (vector model)
+  for (int k = 0; k < g.C * g.K; ++k) {
     CHK(launch_plane_fwd(p, SRC_RAW, p->desc.psf + (long long)k * g.N));
     k_class_hcopy<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), lds, p->ls>>>(g, k, p->uperm,
                          reinterpret_cast<float2*>(p->hs), p->tw32 + p->off[0]);
@@ -583,6 +592,8 @@ static void fill_desc(mh3d_plan_t p) {
   v.T_class = p->L.T_class;
   v.u = p->vol[4];
   v.nb_upd = update_blocks(p->g.N);
+  v.ncomp = p->g.C;
+  v.hs_cstride = (long long)p->g.K * p->g.hsz;
 }
 
 // Descriptor of harmonic k alone: the same buffers with K = 1, the spectra and the
@@ -625,10 +636,10 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   memset(p->launches, 0, sizeof p->launches);
   auto bail = [&](mh3d_status s) { mh3d_destroy(p); return s; };
   mh3d_status s;
-  const size_t hbytes = (size_t)g.K * g.hsz * (p->compact ? sizeof(float) : sizeof(float2));
+  const size_t hbytes = (size_t)g.C * g.K * g.hsz * (p->compact ? sizeof(float) : sizeof(float2));
   if ((s = dalloc(p, &p->hs, hbytes)) != MH3D_OK) return bail(s);
-  if ((s = dalloc(p, (void**)&p->b, sizeof(float) * g.N)) != MH3D_OK) return bail(s);
-  if ((s = dalloc(p, (void**)&p->uperm, sizeof(float2) * (size_t)g.nx * g.plane)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->b, sizeof(float) * g.C * g.N)) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->uperm, sizeof(float2) * (size_t)g.C * g.nx * g.plane)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->G, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->Gp, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   for (int i = 0; i < 5; ++i)
@@ -643,7 +654,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   fill_desc(p);
   if ((s = upload_desc(p)) != MH3D_OK) return bail(s);
   if (desc->sens) {
-    if (hipMemcpyAsync(p->b, desc->sens, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
+    if (hipMemcpyAsync(p->b, desc->sens, sizeof(float) * g.C * g.N, hipMemcpyDeviceToDevice, p->stream) != hipSuccess)
       return bail(fail(MH3D_ERR_HIP, "copy of the sensitivity map failed"));
   } else {
     hipLaunchKernelGGL(k_sensitivity, dim3(1024), dim3(256), 0, p->stream, g, desc->voxel_mm, desc->sigma_mm[0],
@@ -1189,8 +1200,8 @@ extern "C" mh3d_status mh3d_plan_export(mh3d_plan_t p, mh3d_field field, void* d
   switch (field) {
     case MH3D_FIELD_PROFILE: need = sizeof(double) * g.K * g.nx; break;
     case MH3D_FIELD_ENVELOPE: need = sizeof(double) * (size_t)g.ny * g.nz; break;
-    case MH3D_FIELD_SENS: need = sizeof(float) * g.N; break;
-    case MH3D_FIELD_SPECTRUM: need = sizeof(float2) * (size_t)g.K * g.nx * g.ny * g.nzh; break;
+    case MH3D_FIELD_SENS: need = sizeof(float) * g.C * g.N; break;
+    case MH3D_FIELD_SPECTRUM: need = sizeof(float2) * (size_t)g.C * g.K * g.nx * g.ny * g.nzh; break;
     default: return fail(MH3D_ERR_INVALID, "unknown field %d", (int)field);
   }
   if (bytes) *bytes = need;
@@ -1202,9 +1213,13 @@ extern "C" mh3d_status mh3d_plan_export(mh3d_plan_t p, mh3d_field field, void* d
     case MH3D_FIELD_ENVELOPE: HIPCHK(hipMemcpyAsync(dst, p->env, need, hipMemcpyDeviceToDevice, p->stream)); break;
     case MH3D_FIELD_SENS: HIPCHK(hipMemcpyAsync(dst, p->b, need, hipMemcpyDeviceToDevice, p->stream)); break;
     default:
-      hipLaunchKernelGGL(k_spectrum_export, dim3(1024), dim3(256), 0, p->stream, g, p->hs, p->imag_mask, p->compact,
-                         reinterpret_cast<float2*>(dst));
-      CHK(last_launch("k_spectrum_export"));
+      for (int c = 0; c < g.C; ++c) {
+        const size_t esz = p->compact ? sizeof(float) : sizeof(float2);
+        hipLaunchKernelGGL(k_spectrum_export, dim3(1024), dim3(256), 0, p->stream, g,
+                           (const char*)p->hs + (size_t)c * g.K * g.hsz * esz, p->imag_mask, p->compact,
+                           reinterpret_cast<float2*>(dst) + (size_t)c * g.K * g.nx * g.ny * g.nzh);
+        CHK(last_launch("k_spectrum_export"));
+      }
   }
   HIPCHK(hipStreamSynchronize(p->stream));
   return MH3D_OK;
@@ -1357,7 +1372,7 @@ static std::string tune_key(mh3d_plan_t p) {
   }
   char buf[160];
   snprintf(buf, sizeof buf, "%s|%dx%dx%d|K%d|ds%dx%dx%d|%s", arch.c_str(), p->g.nx, p->g.ny, p->g.nz, p->g.K, p->g.sx,
-           p->g.sy, p->g.sz, p->compact ? "analytic" : "user");
+           p->g.sy, p->g.sz, p->compact ? "analytic" : (p->g.C > 1 ? (p->g.C == 2 ? "user2" : "user3") : "user"));
   return buf;
 }
 

@@ -30,6 +30,7 @@ class PlanDesc(ctypes.Structure):
                 ("a_per_mm", ctypes.c_double),
                 ("psf", ctypes.c_void_p),
                 ("sens", ctypes.c_void_p),
+                ("ncomp", ctypes.c_int32),
                 ("sigma_mm", ctypes.c_double * 3),
                 ("lambda_", ctypes.c_double),
                 ("reg_kind", ctypes.c_int32),
@@ -148,7 +149,7 @@ def _check(status):
 
 
 def _desc(shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=0, order_offset=0,
-          psf_ptr=None, sens_ptr=None, stream=None, alpha=0.0, pad=(0, 0, 0), alpha_width=0):
+          psf_ptr=None, sens_ptr=None, stream=None, alpha=0.0, pad=(0, 0, 0), alpha_width=0, ncomp=0):
     harm = (ctypes.c_int32 * len(harmonics))(*[int(k) for k in harmonics])
     d = PlanDesc()
     d.nx, d.ny, d.nz = [int(n) for n in shape]
@@ -160,6 +161,7 @@ def _desc(shape, harmonics, a_per_mm, ds, sigma_mm, lam, voxel_mm=1.0, reg_kind=
     d.a_per_mm = float(a_per_mm)
     d.psf = psf_ptr
     d.sens = sens_ptr
+    d.ncomp = int(ncomp)
     d.sigma_mm = (ctypes.c_double * 3)(*np.broadcast_to(np.asarray(sigma_mm, dtype=float), (3,)))
     d.lambda_ = float(lam)
     d.reg_kind = int(reg_kind)
@@ -208,20 +210,27 @@ class Plan:
         self.K = len(self.harmonics)
         self._keep = []
         psf_ptr = sens_ptr = None
+        # vector model (Sec. 3.2 eq. matrixModel): psf [C][K][grid] with sens [C][grid]
+        self.ncomp = 1
         if psf is not None:
             psf = torch.as_tensor(psf, dtype=torch.float32, device=self.device).contiguous()
-            assert psf.shape == (self.K,) + self.shape
+            if psf.dim() == 5:
+                self.ncomp = int(psf.shape[0])
+                assert tuple(psf.shape[1:]) == (self.K,) + self.shape
+            else:
+                assert tuple(psf.shape) == (self.K,) + self.shape
             self._keep.append(psf)
             psf_ptr = psf.data_ptr()
         if sens is not None:
             sens = torch.as_tensor(sens, dtype=torch.float32, device=self.device).contiguous()
-            assert sens.shape == self.shape
+            want = ((self.ncomp,) if self.ncomp > 1 else ()) + self.shape
+            assert tuple(sens.shape) == want, (tuple(sens.shape), want)
             self._keep.append(sens)
             sens_ptr = sens.data_ptr()
         self.stream = torch.cuda.current_stream(self.device)
         d, harm = _desc(self.shape, self.harmonics, a_per_mm, self.ds, sigma_mm, lam, voxel_mm, reg_kind,
                         order_offset, psf_ptr, sens_ptr, self.stream.cuda_stream, alpha=alpha,
-                        alpha_width=alpha_width, pad=self.pad)
+                        alpha_width=alpha_width, pad=self.pad, ncomp=self.ncomp)
         h = ctypes.c_void_p()
         _check(library().mh3d_plan(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -363,9 +372,11 @@ class Plan:
         elif field == FIELD_ENVELOPE:
             t = torch.empty(self.shape[1:], dtype=torch.float64, device=self.device)
         elif field == FIELD_SENS:
-            t = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+            lead = (self.ncomp,) if self.ncomp > 1 else ()
+            t = torch.empty(lead + self.shape, dtype=torch.float32, device=self.device)
         else:
-            t = torch.empty((self.K, self.shape[0], self.shape[1], self.shape[2] // 2 + 1),
+            lead = (self.ncomp,) if self.ncomp > 1 else ()
+            t = torch.empty(lead + (self.K, self.shape[0], self.shape[1], self.shape[2] // 2 + 1),
                             dtype=torch.complex64, device=self.device)
         assert t.numel() * t.element_size() == nb.value
         _check(library().mh3d_plan_export(self._h, field, _ptr(t), ctypes.byref(nb)))

@@ -30,6 +30,28 @@ def test_describe_padding_shrinks_the_portraits_only():
     assert nv == 96 * 96 * 64 and npo == 7 * 40 * 44 * 26
 
 
+def test_describe_vector_model_scales_the_component_buffers():
+    """ncomp = 3 (Sec. 3.2 eq. matrixModel): spectra, sensitivities and the class-layout
+    spectra are held per component; portraits and volumes keep their sizes.  The
+    pointers are never dereferenced by the host-only describe."""
+    args = ((96, 96, 64), tuple(range(2, 9)), 1.2, (2, 2, 2), 20.0, 1e-3)
+    nb1, nv1, np1 = mh3d.describe(*args, psf_ptr=4096, sens_ptr=8192)
+    nb3, nv3, np3 = mh3d.describe(*args, psf_ptr=4096, sens_ptr=8192, ncomp=3)
+    n = 96 * 96 * 64
+    assert (nv3, np3) == (nv1, np1)
+    # per extra component at least its K half-spectra (complex, about N/2 values each)
+    # and its sensitivity
+    assert nb3 > nb1 + 2 * (7 * n * 4 + n * 4)
+
+
+@pytest.mark.parametrize("kw", [dict(ncomp=3), dict(ncomp=3, psf_ptr=4096), dict(ncomp=2, sens_ptr=4096),
+                                dict(ncomp=4, psf_ptr=4096, sens_ptr=8192), dict(ncomp=-1)])
+def test_describe_rejects_incomplete_vector_model(kw):
+    with pytest.raises(mh3d.MH3DError) as e:
+        mh3d.describe((32, 32, 32), (2, 3), 1.2, (2, 2, 2), 20.0, 1e-3, **kw)
+    assert e.value.status == mh3d.ERR_INVALID
+
+
 @pytest.mark.parametrize("shape,harm,ds,sig", [
     ((32, 32, 32), (2, 3), (2, 2, 2), 20.0),
     ((96, 96, 64), tuple(range(2, 9)), (2, 2, 2), 20.0),

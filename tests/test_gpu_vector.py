@@ -1,0 +1,187 @@
+"""GPU parity of the vector model (Sec. 3.2 eq. MH3Dcont and the stacked matrix of
+eq. matrixModel): d_k = sum_i P H_{k,i} B_i rho with user-supplied component PSFs and
+sensitivities, through the C ABI, against the FP64 oracle.  Tolerances as for the
+scalar model: relative L2 <= 1e-5 per FP32 application, <= 1e-4 for reconstructions."""
+import numpy as np
+import pytest
+
+from oracle import model as om
+from oracle import solver as osv
+from paper_2503_13802_amd import inputs
+from gpu_util import announce, rel_l2, torch_cuda
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _vec(shape, C, K, seed):
+    return inputs.vector_psfs(C, K, shape, seed), inputs.vector_sensitivity(C, shape, seed + 1)
+
+
+def _plan(torch, shape, harm, ds, h, b, lam=1e-3, **kw):
+    from paper_2503_13802_amd import mh3d
+    return mh3d.Plan(shape, harm, 1.0, ds, 1.0, lam, psf=torch.tensor(h, dtype=torch.float32),
+                     sens=torch.tensor(b, dtype=torch.float32), **kw)
+
+
+CASES = [
+    # shape, harmonics, ds, components
+    ((8, 8, 8), (2, 3), (2, 2, 2), 3),
+    ((12, 8, 16), (2, 3, 5), (2, 2, 4), 2),
+    ((8, 9, 8), (2, 3), (2, 3, 2), 3),                 # odd ny and odd my
+    ((18, 12, 8), (2, 3, 4), (3, 2, 2), 3),            # radix 3 along x
+    ((24, 16, 12), tuple(range(2, 9)), (1, 1, 1), 3),  # no decimation, K = 7
+    ((48, 24, 32), tuple(range(2, 13)), (2, 4, 4), 2), # K = 11, S = 32
+    ((18, 18, 8), (2, 3), (3, 3, 2), 3),               # S = 18
+]
+
+
+@pytest.mark.parametrize("shape,harm,ds,C", CASES)
+def test_vector_forward_adjoint_vs_oracle(shape, harm, ds, C):
+    torch = torch_cuda()
+    announce("vector A/AT %s ds=%s K=%d C=%d" % (shape, ds, len(harm), C))
+    h, b = _vec(shape, C, len(harm), 31)
+    rho = inputs.random_field(shape, 32)
+    small = len(harm) * int(np.prod(shape)) <= 4 * 4096
+    tier = 1 if small else 2
+    d_ref = om.forward_vector(h, b, rho, ds, tier)
+    r = inputs.random_field(d_ref.shape, 33)
+    x_ref = om.adjoint_vector(h, b, r, ds, tier)
+    p = _plan(torch, shape, harm, ds, h, b)
+    d = p.forward(torch.tensor(rho, dtype=torch.float32)).cpu().numpy()
+    x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(d, d_ref) <= TOL
+    assert rel_l2(x, x_ref) <= TOL
+    # the fused five-pass sequence gives bitwise the separate calls' results
+    dt, xt = p.forward_adjoint(torch.tensor(rho, dtype=torch.float32))
+    d1 = p.forward(torch.tensor(rho, dtype=torch.float32))
+    assert torch.equal(dt, d1)
+    assert torch.equal(xt, p.adjoint(d1))
+
+
+def test_vector_point_source_reads_component_psf():
+    """Sec. 3.2: a point source at the origin with b_1 = e_i gives the portraits
+    P h_{k,i} of that component alone."""
+    torch = torch_cuda()
+    announce("vector point source")
+    shape, harm, ds = (16, 12, 8), (2, 3, 4), (2, 2, 2)
+    h, _ = _vec(shape, 3, 3, 41)
+    rho = np.zeros(shape)
+    rho[0, 0, 0] = 1.0
+    for i in range(3):
+        b = np.zeros((3,) + shape)
+        b[i] = 1.0
+        p = _plan(torch, shape, harm, ds, h, b)
+        d = p.forward(torch.tensor(rho, dtype=torch.float32)).cpu().numpy()
+        want = h[i][:, ::ds[0], ::ds[1], ::ds[2]]
+        assert rel_l2(d, want) <= TOL
+        p.close()
+
+
+def test_vector_full_size_workload():
+    """The 96x96x64, k = 2..8 geometry with three components: full outputs against the
+    FFT oracle and sampled outputs against direct sums."""
+    torch = torch_cuda()
+    w = inputs.workload(1)
+    announce("vector full size %s C=3" % w.name)
+    h, b = _vec(w.shape, 3, len(w.harmonics), 51)
+    rho = inputs.phantom(w)
+    p = _plan(torch, w.shape, w.harmonics, w.ds, h, b)
+    d = p.forward(torch.tensor(rho, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(d, om.forward_vector(h, b, rho, w.ds)) <= TOL
+    rng = np.random.default_rng(5)
+    ent = [(int(rng.integers(len(w.harmonics))),) + tuple(int(rng.integers(m)) for m in w.small_shape)
+           for _ in range(64)]
+    direct = sum(om.forward_direct_at(h[i], b[i], rho, w.ds, ent) for i in range(3))
+    assert rel_l2([d[e] for e in ent], direct) <= TOL
+    r = inputs.noise_draw(w)
+    x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(x, om.adjoint_vector(h, b, r, w.ds)) <= TOL
+    vox = [tuple(int(rng.integers(n)) for n in w.shape) for _ in range(64)]
+    direct = sum(om.adjoint_direct_at(h[i], b[i], r, w.ds, vox) for i in range(3))
+    assert rel_l2([x[v] for v in vox], direct) <= TOL
+
+
+def test_vector_backprojection_and_spectrum_export():
+    torch = torch_cuda()
+    announce("vector backproject / export")
+    shape, harm, ds = (24, 16, 12), (2, 3, 5), (2, 2, 2)
+    h, b = _vec(shape, 3, 3, 61)
+    p = _plan(torch, shape, harm, ds, h, b)
+    r = inputs.random_field((3,) + tuple(n // s for n, s in zip(shape, ds)), 62)
+    c = p.backproject(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    for k in range(3):
+        want = sum(om.adjoint_fft(h[i][k:k + 1], b[i], r[k:k + 1], ds) for i in range(3))
+        assert rel_l2(c[k], want) <= TOL
+    x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(c.sum(axis=0), x) <= 2e-6
+    spec = p.export(3).cpu().numpy()
+    want = np.fft.rfftn(h, axes=(2, 3, 4))
+    assert spec.shape == want.shape
+    assert np.max(np.abs(spec - want)) <= 2e-6 * np.max(np.abs(want))
+    sens = p.export(2).cpu().numpy()
+    np.testing.assert_array_equal(sens, b.astype(np.float32))
+
+
+@pytest.mark.parametrize("reg_kind,alpha,width,pad", [(0, 0.0, 0, (0, 0, 0)), (0, 4.0, 2, (0, 0, 0)),
+                                                      (1, 0.0, 0, (2, 2, 2))])
+def test_vector_normal_operator(reg_kind, alpha, width, pad):
+    torch = torch_cuda()
+    announce("vector normal reg=%d alpha=%g pad=%s" % (reg_kind, alpha, pad))
+    shape, harm, ds, lam = (16, 12, 8), (2, 3), (2, 2, 2), 0.05
+    h, b = _vec(shape, 3, 2, 71)
+    op = osv.Operator(h, b, ds, lam, reg_kind=reg_kind, alpha=alpha, alpha_width=width, pad=pad)
+    x = inputs.random_field(shape, 72)
+    p = _plan(torch, shape, harm, ds, h, b, lam=lam, reg_kind=reg_kind, alpha=alpha, alpha_width=width, pad=pad)
+    got = p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(got, op.normal(x)) <= TOL
+    if any(pad):
+        d = p.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
+        assert rel_l2(d, op.A(x)) <= TOL
+
+
+def test_vector_solve_matches_oracle():
+    """Fixed-step accelerated projected gradient on the vector model, 30 updates."""
+    torch = torch_cuda()
+    announce("vector solve")
+    shape, harm, ds, lam = (16, 12, 8), (2, 3, 4), (2, 2, 2), 1e-2
+    h, b = _vec(shape, 3, 3, 81)
+    op = osv.Operator(h, b, ds, lam)
+    rho_t = np.maximum(inputs.random_field(shape, 82), 0.0)
+    d = op.A(rho_t) + 0.01 * inputs.random_field((3,) + tuple(n // s for n, s in zip(shape, ds)), 83)
+    v0 = np.ones(shape)
+    tau = 1.0 / (1.05 * osv.power_iteration(op, v0 / np.linalg.norm(v0), iters=100))
+    want, _, _ = osv.fista(op, d, tau, max_iter=30)
+    p = _plan(torch, shape, harm, ds, h, b, lam=lam)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=30, tol=0.0, tau=tau)
+    assert info["iters"] == 30
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+    # the step-size estimate of the plan agrees with the oracle's power iteration
+    lmax = p.power_iteration(100, 3)
+    assert lmax == pytest.approx(1.0 / (1.05 * tau), rel=2e-3)
+
+
+def test_vector_tiles_do_not_change_results():
+    torch = torch_cuda()
+    announce("vector tiles")
+    shape, harm, ds = (24, 16, 12), tuple(range(2, 9)), (2, 2, 2)
+    h, b = _vec(shape, 3, 7, 91)
+    rho = inputs.random_field(shape, 92)
+    want = om.forward_vector(h, b, rho, ds)
+    p = _plan(torch, shape, harm, ds, h, b)
+    for tiles in [(1, 1, 1, 1), (2, 4, 2, 2), (8, 2, 3, 1), (4, 1, 6, 3)]:
+        p.set_tiles(*tiles)
+        d = p.forward(torch.tensor(rho, dtype=torch.float32)).cpu().numpy()
+        assert rel_l2(d, want) <= TOL, tiles
+
+
+def test_vector_plan_is_rejected_by_batches():
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("vector batch rejection")
+    shape, harm, ds = (16, 12, 8), (2, 3), (2, 2, 2)
+    h, b = _vec(shape, 2, 2, 95)
+    p = _plan(torch, shape, harm, ds, h, b)
+    with pytest.raises(mh3d.MH3DError) as e:
+        mh3d.Batch([p])
+    assert e.value.status == mh3d.ERR_UNSUPPORTED
