@@ -223,6 +223,24 @@ def point_source_portraits(h, b, positions, weights, ds):
     return np.ascontiguousarray(full[:, ::ds[0], ::ds[1], ::ds[2]])
 
 
+# --------------------------------------------------------------------------- MH2D
+def stack_scans(h_scans, b_scans):
+    """MH2D (Sec. 5.2): S scans of one 2D image ([nx][1][nz], projection along y), scan s
+    with its own drive axis, PSFs h_s [K_s][grid] and receive sensitivity b_s.  The
+    portraits of all scans stacked in scan order are eq. matrixModel with one nonzero
+    block per row: component s carries b_s, and harmonic j of scan s has PSF h_s[j] in
+    component s and zero in the others.  Returns (h [S][sum K_s][grid], b [S][grid])."""
+    S = len(h_scans)
+    Ks = [h.shape[0] for h in h_scans]
+    grid = h_scans[0].shape[1:]
+    h = np.zeros((S, sum(Ks)) + grid)
+    row = 0
+    for s in range(S):
+        h[s, row:row + Ks[s]] = h_scans[s]
+        row += Ks[s]
+    return h, np.stack([np.asarray(b, dtype=np.float64) for b in b_scans])
+
+
 # --------------------------------------------------------------------------- boundary padding
 def fov_offsets(pad, ds):
     """Decimated-sample offsets of the field of view: pad[a] voxels of padding on each
@@ -258,11 +276,14 @@ def second_difference(y, axis):
 
 def boundary_mask(shape, width):
     """P_alpha^T P_alpha of the boundary prior (Sec. 4.2, eq. finalR): 1 on the voxels
-    within `width` voxels of a face of the grid, 0 elsewhere."""
+    within `width` voxels of a face of the grid, 0 elsewhere.  An axis of length 1 (the
+    projection axis of a 2D grid) has no faces."""
     m = np.zeros(shape)
     if width <= 0:
         return m
     for a, n in enumerate(shape):
+        if n == 1:
+            continue
         idx = [slice(None)] * 3
         idx[a] = slice(0, width)
         m[tuple(idx)] = 1.0

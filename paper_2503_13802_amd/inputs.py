@@ -225,3 +225,64 @@ def vector_sensitivity(n_comp, shape, seed):
             f = f + rng.uniform(-0.3, 0.3) * np.cos(2 * np.pi * (i / n) * rng.integers(1, 3) + rng.uniform(0, 2 * np.pi))
         out[c] = f
     return out
+
+
+# ----------------------------------------------------------------------------- MH2D
+@dataclass(frozen=True)
+class Workload2D:
+    """2D projection workload: image [nx][1][nz] (projection along y), one scan per
+    drive axis, each with its own harmonics, PSFs and receive sensitivity."""
+    name: str
+    shape: Tuple[int, int, int]
+    harmonics: Tuple[int, ...]          # per scan
+    drive_axes: Tuple[int, ...]         # array axis driven in each scan (0 = x, 2 = z)
+    ds: Tuple[int, int, int]
+    lam: float
+    snr_db: float = 30.0
+    n_sources: int = 24
+    max_iter: int = 5000
+    tol: float = 1e-4
+    seed: int = 6000
+
+    @property
+    def small_shape(self):
+        return tuple(n // s for n, s in zip(self.shape, self.ds))
+
+
+def mh2d_workload():
+    """Two scans of a 128 x 256 (x, z) projection image, drive along x then along z,
+    k = 2..8 each."""
+    return Workload2D("mh2d-128x256-2scans-k2..8", (128, 1, 256), tuple(range(2, 9)), (0, 2), (2, 1, 2), 1e-3)
+
+
+def spiral_phantom_2d(w: Workload2D, seed=None):
+    """Point-like sources (one pixel each, value U(0.5, 1)) along an Archimedean spiral
+    centred in the image, 1.2 turns out to 40 % of the smaller extent."""
+    rng = np.random.default_rng([w.seed if seed is None else seed, 0])
+    nx, _, nz = w.shape
+    img = np.zeros(w.shape)
+    rmax = 0.4 * min(nx, nz)
+    for j in range(w.n_sources):
+        t = (j + 0.5) / w.n_sources
+        ang = 2 * np.pi * 1.2 * t + rng.uniform(-0.05, 0.05)
+        r = rmax * t
+        x = int(round(nx / 2 + r * np.cos(ang))) % nx
+        z = int(round(nz / 2 + r * np.sin(ang))) % nz
+        img[x, 0, z] += rng.uniform(0.5, 1.0)
+    return img
+
+
+def scan_psfs(n_harm, shape, drive_axis, seed, along_vox=4.0, across_vox=1.5):
+    """Seeded synthetic harmonic PSFs of one scan [n_harm][grid]: standard normal fields
+    under a periodic Gaussian window centred at index 0, wider along the scan's drive
+    axis than across it."""
+    rng = np.random.default_rng([seed, 5])
+    win = np.ones(shape)
+    for a, n in enumerate(shape):
+        if n == 1:
+            continue
+        i = np.arange(n)
+        w = np.minimum(i, n - i).astype(np.float64)
+        width = along_vox if a == drive_axis else across_vox
+        win = win * np.exp(-0.5 * (w / width) ** 2).reshape([n if b == a else 1 for b in range(3)])
+    return rng.standard_normal((n_harm,) + tuple(shape)) * win
