@@ -25,9 +25,12 @@ same data: the relative L2 difference of the two reconstructions is reported the
 
 The vector leg times the same fused step for the vector model of eq. matrixModel on
 the workload's grid (seeded synthetic component PSFs and sensitivities, C = 1 and 3).
+The MH2D leg does the same, and a solve to r_k <= 1e-4, for the 2D projection geometry
+of Sec. 5.2 (128 x 256 image, two scans of seven harmonics).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1|2] [--no-cpu] [--no-solve]
-                       [--no-batch] [--no-warm] [--no-vector] [--warm-train-steps T] [--warm-eval E]
+                       [--no-batch] [--no-warm] [--no-vector] [--no-mh2d] [--warm-train-steps T]
+                       [--warm-eval E]
 """
 import argparse
 import json
@@ -244,6 +247,60 @@ def vector_leg(w, steps, warmup, tile_cache=None):
     return out
 
 
+def mh2d_leg(steps, warmup, tile_cache=None):
+    """The 2D projection geometry (Sec. 5.2): a 128 x 256 image, two scans (drive along
+    x, then z), k = 2..8 each, stacked as the vector model with one PSF block per
+    harmonic; seeded synthetic scan PSFs and sensitivities, spiral phantom, 30 dB noise.
+    Fused A+A^T applications per second and the time to reconstruct at r_k <= 1e-4."""
+    import numpy as np
+    import torch
+    from paper_2503_13802_amd import inputs, mh3d
+    dev = torch.device("cuda:0")
+    w = inputs.mh2d_workload()
+    K = len(w.harmonics)
+    hs = [inputs.scan_psfs(K, w.shape, ax, w.seed + ax) for ax in w.drive_axes]
+    bs = [inputs.vector_sensitivity(1, w.shape, w.seed + 10 + ax)[0] for ax in w.drive_axes]
+    psf, sens = mh3d.stack_scans(hs, bs)
+    plan = mh3d.Plan(w.shape, w.harmonics * len(hs), 1.0, w.ds, 1.0, w.lam, psf=torch.tensor(psf, device=dev),
+                     sens=torch.tensor(sens, device=dev))
+    tiles = plan.tiles()
+    if tile_cache is not None:
+        tiles, _ = plan.autotune(tile_cache)
+    rho = torch.tensor(inputs.spiral_phantom_2d(w), dtype=torch.float32, device=dev)
+    clean = plan.forward(rho).cpu().numpy().astype(np.float64)
+    xi = inputs.noise_draw(w, n_harm=clean.shape[0])
+    d = torch.tensor(inputs.add_noise(clean, [w.snr_db] * clean.shape[0], xi), dtype=torch.float32, device=dev)
+    y = torch.empty_like(d)
+    x = torch.empty_like(rho)
+    for _ in range(warmup):
+        plan.forward_adjoint(rho, d_out=y, x_out=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward_adjoint(rho, d_out=y, x_out=x)
+    torch.cuda.synchronize()
+    rate = steps / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    rec, info = plan.solve(d, max_iter=w.max_iter, tol=w.tol, tau=0.0)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rec2, info2 = plan.solve(d, max_iter=w.max_iter, tol=w.tol, tau=0.0)
+    torch.cuda.synchronize()
+    out = {"workload": w.name, "grid": list(w.shape), "scans": len(hs), "harmonics_per_scan": list(w.harmonics),
+           "decimation": list(w.ds), "lambda": w.lam, "tiles": list(tiles),
+           "inputs": "inputs.scan_psfs / vector_sensitivity / spiral_phantom_2d (seeded synthetic)",
+           "applications_per_s": round(rate, 2),
+           "kernels_us": {k: round(plan.time_pass(k, reps=100), 3) for k in mh3d.Plan.PASSES},
+           "time_to_recon": {"plain_s": round(first_s, 4), "plain_cached_step_s": round(time.perf_counter() - t0, 4),
+                             "iters": info["iters"], "rel_step": info["rel_step"],
+                             "ms_per_iter": round(info2["ms_per_iter"], 4), "status": info["status"],
+                             "identical_rerun": bool(torch.equal(rec, rec2))}}
+    log("mh2d: %.1f A+A^T/s, solve %d updates in %.3f s" % (rate, info["iters"], first_s))
+    plan.close()
+    return out
+
+
 def tile_cache_path(arg):
     """The autotuner cache: the given path, else a temp copy of the shipped one."""
     if arg:
@@ -319,6 +376,7 @@ def main():
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-vector", action="store_true")
+    ap.add_argument("--no-mh2d", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="heuristic tiles instead of the autotuner")
     ap.add_argument("--tile-cache", default=None, help="autotuner JSON cache (default: a file in the temp dir)")
     ap.add_argument("--warm-train-steps", type=int, default=20000)
@@ -470,6 +528,9 @@ def main():
 
     if not args.no_vector:
         out["vector_model"] = vector_leg(w, min(args.steps, 200), min(args.warmup, 20), tile_cache)
+
+    if not args.no_mh2d:
+        out["mh2d"] = mh2d_leg(min(args.steps, 200), min(args.warmup, 20), tile_cache)
 
     if batch_inputs is not None:
         out["batched"] = batched_leg(batch_inputs, w.tol, w.max_iter, tile_cache)

@@ -62,23 +62,31 @@ typedef struct mh3d_plan_s* mh3d_plan_t;
 
 /* Geometry and model of one reconstruction problem. */
 typedef struct {
-  int32_t nx, ny, nz;        /* grid; each of the form 2^a 3^b, 4 <= n <= 256, nz even */
+  int32_t nx, ny, nz;        /* grid; each of the form 2^a 3^b, 4 <= n <= 256, nz even;
+                                ny = 1 is a 2D image [nx][1][nz] (the projection
+                                geometry of Sec. 5.2): psf required, ds[1] = 1, pad[1] = 0 */
   double voxel_mm;           /* voxel edge (mm), > 0                                     */
   int32_t ds[3];             /* decimation per axis (P), divides the grid; nz/ds2 even   */
   int32_t n_harm;            /* number of harmonics, 1..32                               */
-  const int32_t* harm;       /* HOST array of harmonic indices k >= 2, strictly increasing */
+  const int32_t* harm;       /* HOST array of harmonic indices k >= 2; strictly increasing
+                                for the analytic PSF, any order with user PSFs (labels:
+                                the scans of a 2D acquisition repeat them)             */
   int32_t order_offset;      /* PSF uses L^(k + order_offset); 0 by default              */
   double a_per_mm;           /* Langevin argument scale a (1/mm), > 0                    */
   const float* psf;          /* optional DEVICE [ncomp][n_harm][nx][ny][nz]; NULL -> analytic */
   const float* sens;         /* optional DEVICE [ncomp][nx][ny][nz]; NULL -> Gaussian sigma_mm */
   int32_t ncomp;             /* components of the vector model (Sec. 3.2 eq. MH3Dcont /
                                 matrixModel): 0 or 1 -> scalar model; 2 or 3 -> d_k =
-                                sum_i P H_{k,i} B_i rho with psf and sens both given   */
+                                sum_i P H_{k,i} B_i rho with psf and sens both given.
+                                PSF blocks h_{k,i} that are identically zero are
+                                skipped; several scans of one image (Sec. 5.2) are this
+                                model with one nonzero block per harmonic            */
   double sigma_mm[3];        /* Gaussian sensitivity widths (mm), peak 1 at the centre   */
   double lambda;             /* Tikhonov weight, >= 0                                    */
   int32_t reg_kind;          /* 0: stacked periodic second differences; 1: T = I         */
   double alpha;              /* boundary prior weight (eq. finalR), >= 0; 0 = off        */
-  int32_t alpha_width;       /* shell depth of P_alpha in voxels: [1, min(n)/2] if alpha > 0, else 0 */
+  int32_t alpha_width;       /* shell depth of P_alpha in voxels: [1, min(n)/2] over the axes
+                                longer than 1 if alpha > 0, else 0                      */
   int32_t pad[3];            /* boundary padding (Sec. 4.1.1): voxels of the grid on each
                                 side of axis a that are modelled but not measured, a
                                 multiple of ds[a].  Volumes live on the whole (padded)

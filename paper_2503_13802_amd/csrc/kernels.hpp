@@ -27,16 +27,17 @@ namespace mh3d {
 // Class-layout index of the full-grid half-plane position (qy, qz), qz <= nz/2,
 // and whether the stored value is the conjugate.
 __device__ __forceinline__ int class_index_of(const Geo& g, int qy, int qz, bool& cj) {
-  const int qzr = qz % g.mz;
+  const int qzr = (int)g.f_mz.mod((uint32_t)qz);
   int yy = qy, zz = qz;
   cj = false;
   if (2 * qzr > g.mz) {            // stored as the conjugate of (ny - qy, nz - qz)
-    yy = (g.ny - qy) % g.ny;
+    yy = qy == 0 ? 0 : g.ny - qy;
     zz = g.nz - qz;
     cj = true;
   }
-  const int c = (yy % g.my) * g.mzh + (zz % g.mz);
-  const int m = (yy / g.my) * g.sz + (zz / g.mz);
+  const int yq = (int)g.f_my.div((uint32_t)yy), zq = (int)g.f_mz.div((uint32_t)zz);
+  const int c = (yy - yq * g.my) * g.mzh + (zz - zq * g.mz);
+  const int m = yq * g.sz + zq;
   return c * g.nmem + m;
 }
 
@@ -174,6 +175,9 @@ struct VolDesc {
   // class-layout spectra at uperm + i * hsz.  ncomp = 1 is the scalar model.
   int ncomp;
   long long hs_cstride;
+  // bit k of cmask[i]: component i of harmonic k is present (a PSF block that is
+  // identically zero is skipped: no spectrum load, no product)
+  uint32_t cmask[3];
 };
 
 // Volume and local block index of this block: task table (batched launches) or
@@ -463,14 +467,16 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
   // vector model: the products of every component accumulate in F0 before the one
   // inverse transform (the sum over i commutes with it)
   const int ncomp = VEC ? vd.ncomp : 1;
+  uint32_t before = 0;   // harmonics some earlier component has written to F0
   for (int comp = 0; comp < ncomp; ++comp) {
   if (comp) __syncthreads();   // the previous component's U is still being read
+  const uint32_t pm = VEC ? vd.cmask[comp] : ~0u;
   const long long hoff0 = (long long)c0 * per_cls + e0 + comp * vd.hs_cstride;
   // spectra do not depend on the data: start streaming them first
   HLoad<HC, E> hb[HPF];
 #pragma unroll
   for (int i = 0; i < HPF; ++i)
-    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+    if (act && i < g.K && ((pm >> i) & 1u)) hb[i].load(hs, (long long)i * g.hsz + hoff0);
   if (comp == 0) {
     load_table(twx, vd.tw + vd.off[0], g.nx);
     load_table(twm, vd.tw + vd.off[3], g.mx);
@@ -498,29 +504,36 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
     for (int i = 0; i < HPF; ++i) {
       const int k = k0 + i;
       if (k < g.K) {
+        // pk is the same for the whole block (it depends on k and the component only)
+        const bool pk = ((pm >> k) & 1u) != 0;
         float2 acc = make_float2(0.f, 0.f);
         if (act) {
-          if constexpr (HC == 0) {
+          if (pk) {
+            if constexpr (HC == 0) {
 #pragma unroll
-            for (int t = 0; t < E; ++t) { acc.x += hb[i].v[t] * ur[t].x; acc.y += hb[i].v[t] * ur[t].y; }
-            if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
-          } else {
+              for (int t = 0; t < E; ++t) { acc.x += hb[i].v[t] * ur[t].x; acc.y += hb[i].v[t] * ur[t].y; }
+              if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
+            } else {
 #pragma unroll
-            for (int t = 0; t < E; ++t) acc = cadd(acc, cmul(hb[i].v[t], ur[t]));
+              for (int t = 0; t < E; ++t) acc = cadd(acc, cmul(hb[i].v[t], ur[t]));
+            }
           }
-          if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
+          if (k + HPF < g.K && ((pm >> (k + HPF)) & 1u)) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
         }
-        for (int o = LG >> 1; o >= 1; o >>= 1) {
-          acc.x += __shfl_xor(acc.x, o, 64);
-          acc.y += __shfl_xor(acc.y, o, 64);
-        }
-        if (act && (threadIdx.x & (LG - 1)) == 0) {
-          float2& f = F0[(k * g.cpw + cl) * g.mx + qxp];
-          f = comp ? cadd(f, acc) : acc;
+        if (pk) {
+          for (int o = LG >> 1; o >= 1; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+          }
+          if (act && (threadIdx.x & (LG - 1)) == 0) {
+            float2& f = F0[(k * g.cpw + cl) * g.mx + qxp];
+            f = ((before >> k) & 1u) ? cadd(f, acc) : acc;
+          }
         }
       }
     }
   }
+  before |= pm;
   }
   const float2* F = fft_lines<+1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
   float2* __restrict__ G = vd.G;
@@ -555,9 +568,10 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
   const int within = rem - qxp * g.S;
   const void* hs = vd.hs;
   HLoad<HC, E> hb[HPF];
+  const uint32_t pm0 = VEC ? vd.cmask[0] : ~0u;
 #pragma unroll
   for (int i = 0; i < HPF; ++i)
-    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + (long long)c0 * per_cls + e0);
+    if (act && i < g.K && ((pm0 >> i) & 1u)) hb[i].load(hs, (long long)i * g.hsz + (long long)c0 * per_cls + e0);
   load_table(twx, vd.tw + vd.off[0], g.nx);
   load_table(twm, vd.tw + vd.off[3], g.mx);
   const float2* __restrict__ Gp = vd.Gp;
@@ -579,11 +593,12 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
   const int ncomp = VEC ? vd.ncomp : 1;
   for (int comp = 0; comp < ncomp; ++comp) {
   const long long hoff0 = (long long)c0 * per_cls + e0 + comp * vd.hs_cstride;
+  const uint32_t pm = VEC ? vd.cmask[comp] : ~0u;
   if (comp) {
     __syncthreads();   // the previous component's store still reads U0/U1
 #pragma unroll
     for (int i = 0; i < HPF; ++i)
-      if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+      if (act && i < g.K && ((pm >> i) & 1u)) hb[i].load(hs, (long long)i * g.hsz + hoff0);
   }
   float2 acc[E];
 #pragma unroll
@@ -594,17 +609,19 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
     for (int i = 0; i < HPF; ++i) {
       const int k = k0 + i;
       if (act && k < g.K) {
-        float2 R = F[(k * g.cpw + cl) * g.mx + qxp];
-        if constexpr (HC == 0) {
-          // conj(i h) R = -i h R
-          if ((imag_mask >> k) & 1u) R = make_float2(R.y, -R.x);
+        if ((pm >> k) & 1u) {
+          float2 R = F[(k * g.cpw + cl) * g.mx + qxp];
+          if constexpr (HC == 0) {
+            // conj(i h) R = -i h R
+            if ((imag_mask >> k) & 1u) R = make_float2(R.y, -R.x);
 #pragma unroll
-          for (int t = 0; t < E; ++t) { acc[t].x += hb[i].v[t] * R.x; acc[t].y += hb[i].v[t] * R.y; }
-        } else {
+            for (int t = 0; t < E; ++t) { acc[t].x += hb[i].v[t] * R.x; acc[t].y += hb[i].v[t] * R.y; }
+          } else {
 #pragma unroll
-          for (int t = 0; t < E; ++t) acc[t] = cadd(acc[t], cmulcj(hb[i].v[t], R));
+            for (int t = 0; t < E; ++t) acc[t] = cadd(acc[t], cmulcj(hb[i].v[t], R));
+          }
         }
-        if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
+        if (k + HPF < g.K && ((pm >> (k + HPF)) & 1u)) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
       }
     }
   }
@@ -1003,12 +1020,16 @@ __global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __res
       const uint32_t r = g.f_nz.div((uint32_t)i);
       const int z = (int)((uint32_t)i - r * (uint32_t)g.nz);
       const int y = (int)g.f_ny.mod(r), x = (int)g.f_ny.div(r);
-      v.shell = x < aw || x >= g.nx - aw || y < aw || y >= g.ny - aw || z < aw || z >= g.nz - aw;
+      // a 2D grid's projection axis (ny = 1) has no faces
+      v.shell = x < aw || x >= g.nx - aw || (g.ny > 1 && (y < aw || y >= g.ny - aw)) || z < aw || z >= g.nz - aw;
       if (!stencil) return v;
       const long long row = i - z;
-      // periodic neighbours (every axis is >= 4 long, so one wrap suffices)
+      // periodic neighbours (every axis is >= 4 long, so one wrap suffices, except the
+      // projection axis of a 2D grid: length 1, every neighbour is the voxel itself and
+      // its second differences vanish)
       auto wz = [&](int d) { int q = z + d; q += q < 0 ? g.nz : 0; q -= q >= g.nz ? g.nz : 0; return yv[row + q]; };
       auto wy = [&](int d) {
+        if (g.ny == 1) return v.c;
         int q = y + d; q += q < 0 ? g.ny : 0; q -= q >= g.ny ? g.ny : 0;
         return yv[i + (long long)(q - y) * g.nz];
       };
@@ -1394,6 +1415,19 @@ __global__ __launch_bounds__(1024) void k_class_hcopy(Geo g, int k, const float2
     const float2 v = Ul[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx];
     hs[(long long)k * g.hsz + (long long)c0 * per_cls + t] = make_float2(v.x * invN, v.y * invN);
   }
+}
+
+// Flags of the PSF blocks that are not identically zero: blockIdx.x = j selects the
+// (component, harmonic) block psf + j * N, blockIdx.y = s one of gridDim.y strided
+// shares of it; flags[j * gridDim.y + s] = any nonzero in the share.
+__global__ __launch_bounds__(256) void k_nonzero_blocks(const float* __restrict__ psf, long long N,
+                                                        int* __restrict__ flags) {
+  const float* p = psf + (long long)blockIdx.x * N;
+  const long long step = (long long)gridDim.y * blockDim.x;
+  int any = 0;
+  for (long long i = (long long)blockIdx.y * blockDim.x + threadIdx.x; i < N; i += step) any |= (p[i] != 0.f);
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) flags[blockIdx.x * gridDim.y + blockIdx.y] = any;
 }
 
 // Back from the class layout to [k][nx][ny][nzh] complex, times N (tests/tools).

@@ -138,7 +138,7 @@ static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int x
   if (ps_req > 4 || ps_req > g.nzh || ps_req > g.npairs)
     return fail(MH3D_ERR_INVALID, "ps = %d: the plane passes take 1 to 4 workgroups per plane (at most "
                 "min(nz/2+1, (ny+1)/2))", ps_req);
-  g.ps = ps_req > 0 ? ps_req : 2;
+  g.ps = ps_req > 0 ? ps_req : std::min(2, std::min(g.nzh, g.npairs));
   g.f_nz = make_fastdiv(g.nz); g.f_nzh = make_fastdiv(g.nzh); g.f_nmem = make_fastdiv(g.nmem);
   g.f_mzh = make_fastdiv(g.mzh); g.f_sz = make_fastdiv(g.sz); g.f_mz = make_fastdiv(g.mz);
   g.f_W = make_fastdiv(g.cpw * g.nmem); g.f_xb = make_fastdiv(g.xb); g.f_S = make_fastdiv(g.S);
@@ -153,14 +153,23 @@ static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int x
 static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const mh3d_tiles* tiles = nullptr) {
   if (!d) return fail(MH3D_ERR_INVALID, "descriptor is NULL");
   const int n[3] = {d->nx, d->ny, d->nz};
+  // ny = 1: a 2D image [nx][1][nz], the projection axis of the 2D geometry (Sec. 5.2)
+  const bool flat = d->ny == 1;
   for (int a = 0; a < 3; ++a) {
+    if (a == 1 && flat) {
+      if (d->ds[1] != 1) return fail(MH3D_ERR_INVALID, "a 2D grid (ny = 1) needs ds[1] = 1");
+      if (d->pad[1] != 0) return fail(MH3D_ERR_INVALID, "a 2D grid (ny = 1) has no padding along y");
+      continue;
+    }
     if (n[a] < 4 || n[a] > 256 || !is_23_smooth(n[a]))
-      return fail(MH3D_ERR_INVALID, "grid axis %d = %d must be 2^a 3^b in [4, 256]", a, n[a]);
+      return fail(MH3D_ERR_INVALID, "grid axis %d = %d must be 2^a 3^b in [4, 256] (ny may be 1)", a, n[a]);
     if (d->ds[a] < 1 || n[a] % d->ds[a])
       return fail(MH3D_ERR_INVALID, "decimation ds[%d] = %d must divide %d", a, d->ds[a], n[a]);
     if (n[a] / d->ds[a] < 2)
       return fail(MH3D_ERR_INVALID, "decimated axis %d has fewer than 2 samples", a);
   }
+  if (flat && !d->psf)
+    return fail(MH3D_ERR_INVALID, "a 2D grid (ny = 1) takes user PSFs (the analytic PSF is the 3D one)");
   if (d->nz % 2) return fail(MH3D_ERR_INVALID, "nz must be even");
   if ((d->nz / d->ds[2]) % 2) return fail(MH3D_ERR_INVALID, "nz/ds[2] must be even");
   if (!(d->voxel_mm > 0)) return fail(MH3D_ERR_INVALID, "voxel_mm must be > 0");
@@ -168,7 +177,10 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   if (!d->harm) return fail(MH3D_ERR_INVALID, "harm is NULL");
   for (int i = 0; i < d->n_harm; ++i) {
     if (d->harm[i] < 2) return fail(MH3D_ERR_INVALID, "harmonic %d < 2", d->harm[i]);
-    if (i && d->harm[i] <= d->harm[i - 1]) return fail(MH3D_ERR_INVALID, "harmonics must increase strictly");
+    // the analytic PSF is defined by k; user PSFs only label their portraits (several
+    // scans may repeat a harmonic)
+    if (!d->psf && i && d->harm[i] <= d->harm[i - 1])
+      return fail(MH3D_ERR_INVALID, "harmonics must increase strictly (analytic PSF)");
     if (d->harm[i] + d->order_offset < 1 || d->harm[i] + d->order_offset > 24)
       return fail(MH3D_ERR_INVALID, "derivative order k + order_offset must be in [1, 24]");
   }
@@ -183,7 +195,7 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   if (d->reg_kind != 0 && d->reg_kind != 1) return fail(MH3D_ERR_INVALID, "reg_kind must be 0 or 1");
   if (!(d->alpha >= 0.0) || !(d->alpha < 1e30)) return fail(MH3D_ERR_INVALID, "alpha must be finite and >= 0");
   if (d->alpha > 0.0) {
-    const int mn = std::min(d->nx, std::min(d->ny, d->nz));
+    const int mn = std::min(d->nx, flat ? d->nz : std::min(d->ny, d->nz));
     if (d->alpha_width < 1 || 2 * d->alpha_width > mn)
       return fail(MH3D_ERR_INVALID, "alpha_width must be in [1, min(nx, ny, nz)/2] when alpha > 0");
   } else if (d->alpha_width != 0) {
@@ -192,7 +204,7 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   for (int a = 0; a < 3; ++a) {
     if (d->pad[a] < 0 || d->pad[a] % d->ds[a])
       return fail(MH3D_ERR_INVALID, "pad[%d] = %d must be a non-negative multiple of ds[%d]", a, d->pad[a], a);
-    if ((n[a] - 2 * d->pad[a]) / d->ds[a] < 2)
+    if (!(a == 1 && flat) && (n[a] - 2 * d->pad[a]) / d->ds[a] < 2)
       return fail(MH3D_ERR_INVALID, "the field of view along axis %d has fewer than 2 decimated samples", a);
   }
 
@@ -243,6 +255,7 @@ struct mh3d_plan_s {
   hipStream_t cap_stream = nullptr;   // side stream used only to record graphs
   int compact;
   uint32_t imag_mask;
+  uint32_t cmask[3];           // present (component, harmonic) PSF blocks, vector model
   // device memory
   void* hs = nullptr;          // spectra in class layout
   float* b = nullptr;          // sensitivity
@@ -533,6 +546,37 @@ static mh3d_status build_spectra_analytic(mh3d_plan_t p) {
   return MH3D_OK;
 }
 
+// Vector model: which (component, harmonic) PSF blocks are not identically zero.  The
+// class passes skip the others (their products are zero).  A harmonic with no nonzero
+// block keeps component 0.
+static mh3d_status component_masks(mh3d_plan_t p) {
+  const Geo& g = p->g;
+  const uint32_t all = g.K >= 32 ? ~0u : ((1u << g.K) - 1u);
+  for (int c = 0; c < 3; ++c) p->cmask[c] = c < g.C ? all : 0u;
+  if (g.C == 1) return MH3D_OK;
+  const int nb = g.C * g.K, ns = 64;
+  int* d_flags = nullptr;
+  HIPCHK(hipMalloc(&d_flags, sizeof(int) * nb * ns));
+  k_nonzero_blocks<<<dim3(nb, ns), dim3(256), 0, p->stream>>>(p->desc.psf, g.N, d_flags);
+  mh3d_status s = last_launch("k_nonzero_blocks");
+  std::vector<int> f((size_t)nb * ns, 1);
+  if (s == MH3D_OK && (hipMemcpyAsync(f.data(), d_flags, sizeof(int) * nb * ns, hipMemcpyDeviceToHost, p->stream) !=
+                           hipSuccess ||
+                       hipStreamSynchronize(p->stream) != hipSuccess))
+    s = fail(MH3D_ERR_HIP, "reading the PSF block flags failed");
+  (void)hipFree(d_flags);
+  if (s != MH3D_OK) return s;
+  for (int c = 0; c < g.C; ++c)
+    for (int k = 0; k < g.K; ++k) {
+      int any = 0;
+      for (int q = 0; q < ns; ++q) any |= f[(size_t)(c * g.K + k) * ns + q];
+      if (!any) p->cmask[c] &= ~(1u << k);
+    }
+  const uint32_t some = p->cmask[0] | p->cmask[1] | p->cmask[2];
+  p->cmask[0] |= all & ~some;
+  return MH3D_OK;
+}
+
 static mh3d_status build_spectra_user(mh3d_plan_t p) {
   const Geo& g = p->g;
   p->imag_mask = 0;
@@ -594,6 +638,7 @@ static void fill_desc(mh3d_plan_t p) {
   v.nb_upd = update_blocks(p->g.N);
   v.ncomp = p->g.C;
   v.hs_cstride = (long long)p->g.K * p->g.hsz;
+  for (int c = 0; c < 3; ++c) v.cmask[c] = p->cmask[c];
 }
 
 // Descriptor of harmonic k alone: the same buffers with K = 1, the spectra and the
@@ -608,6 +653,7 @@ static mh3d_status upload_harmonic_descs(mh3d_plan_t p) {
     h[k].hs = (const char*)p->vdh.hs + (size_t)k * g.hsz * esz;
     h[k].Gp = p->vdh.Gp + (size_t)k * g.mx * g.ncls;
     h[k].imag_mask = (p->vdh.imag_mask >> k) & 1u;
+    for (int c = 0; c < 3; ++c) h[k].cmask[c] = (p->vdh.cmask[c] >> k) & 1u;
   }
   HIPCHK(hipMemcpyAsync(p->vdk, h.data(), sizeof(VolDesc) * g.K, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -666,6 +712,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = state_set(p, z)) != MH3D_OK) return bail(s);
   if (p->compact) s = build_spectra_analytic(p);
   else s = build_spectra_user(p);
+  if (s == MH3D_OK) s = component_masks(p);
   if (s != MH3D_OK) return bail(s);
   fill_desc(p);   // imag_mask is known now
   if ((s = upload_desc(p)) != MH3D_OK) return bail(s);

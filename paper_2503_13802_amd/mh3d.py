@@ -193,6 +193,23 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def stack_scans(psfs, sens):
+    """Arranges the scans of one 2D image (Sec. 5.2) as the vector model of
+    eq. matrixModel: scan s becomes component s with sensitivity sens[s], and its
+    harmonics' PSFs sit in component s, zero in the others (the plan skips the zero
+    blocks).  psfs: list of [K_s][nx][1][nz] arrays; returns (psf [S][sum K_s][grid],
+    sens [S][grid]) as float32 numpy arrays."""
+    S = len(psfs)
+    Ks = [int(np.shape(h)[0]) for h in psfs]
+    grid = tuple(np.shape(psfs[0])[1:])
+    psf = np.zeros((S, sum(Ks)) + grid, dtype=np.float32)
+    row = 0
+    for s in range(S):
+        psf[s, row:row + Ks[s]] = np.asarray(psfs[s], dtype=np.float32)
+        row += Ks[s]
+    return psf, np.stack([np.asarray(b, dtype=np.float32) for b in sens])
+
+
 class Plan:
     """One MH3D reconstruction geometry on one GPU (see include/mh3d.h)."""
 

@@ -52,6 +52,37 @@ def test_describe_rejects_incomplete_vector_model(kw):
     assert e.value.status == mh3d.ERR_INVALID
 
 
+def test_describe_2d_projection_grid():
+    """ny = 1: a 2D image [nx][1][nz] (Sec. 5.2) with user PSFs; two scans may repeat the
+    harmonics.  The pointers are never dereferenced by the host-only describe."""
+    harm = tuple(range(2, 9)) * 2
+    nb, nv, npo = mh3d.describe((128, 1, 256), harm, 1.0, (2, 1, 2), 20.0, 1e-3, psf_ptr=4096, sens_ptr=8192,
+                                ncomp=2)
+    assert nv == 128 * 256 and npo == 14 * 64 * 128
+    mh3d.describe((12, 1, 18), (2, 3), 1.0, (3, 1, 3), 5.0, 1e-3, psf_ptr=4096, alpha=1.0, alpha_width=6)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(),                                            # a 2D grid needs user PSFs
+    dict(psf_ptr=4096, ds=(2, 2, 2)),                  # no decimation along the projection axis
+    dict(psf_ptr=4096, pad=(2, 1, 2)),                 # no padding along it
+    dict(psf_ptr=4096, alpha=1.0, alpha_width=9),      # shell deeper than half of min(nx, nz)
+    dict(psf_ptr=4096, harmonics=(2, 3, 4), ds=(2, 1, 4)),  # nz/ds[2] odd
+])
+def test_describe_rejects_bad_2d_grids(kw):
+    args = dict(harmonics=(2, 3), a_per_mm=1.0, ds=(2, 1, 2), sigma_mm=5.0, lam=1e-3)
+    args.update(kw)
+    with pytest.raises(mh3d.MH3DError) as e:
+        mh3d.describe((12, 1, 20), args.pop("harmonics"), **args)
+    assert e.value.status == mh3d.ERR_INVALID
+
+
+def test_describe_repeated_harmonics_need_user_psfs():
+    mh3d.describe((32, 32, 32), (2, 3, 2, 3), 1.2, (2, 2, 2), 20.0, 1e-3, psf_ptr=4096)
+    with pytest.raises(mh3d.MH3DError):
+        mh3d.describe((32, 32, 32), (2, 3, 2, 3), 1.2, (2, 2, 2), 20.0, 1e-3)
+
+
 @pytest.mark.parametrize("shape,harm,ds,sig", [
     ((32, 32, 32), (2, 3), (2, 2, 2), 20.0),
     ((96, 96, 64), tuple(range(2, 9)), (2, 2, 2), 20.0),
