@@ -291,8 +291,8 @@ __device__ __forceinline__ RowCols plane_rowcols(const Geo& g) {
   return rc;
 }
 
-// Forward pass 1.  One block per x-plane.  SRC_FISTA_Y reads y^k of the volume
-// (a ignored) and is skipped once the volume's solve is done.
+// Forward pass 1.  ps blocks per x-plane and component (vector model).  SRC_FISTA_Y
+// reads y^k of the volume (a ignored) and is skipped once the volume's solve is done.
 // LDS: tables (nz + ny) + two buffers of plane_lds complex.
 template <int SRC>
 __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
@@ -313,6 +313,11 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
   float2* twy = twz + g.nz;
   float2* P0 = twy + g.ny;
   float2* P1 = P0 + pl;
+  // vector model: component comp of the plane is a workgroup of its own (components
+  // outermost; a raw source has one)
+  const int per_comp = g.ps * g.nx;
+  const int comp = (SRC == SRC_RAW) ? 0 : lb / per_comp;
+  lb -= comp * per_comp;
   // ps workgroups per plane: all of them transform every row along z, workgroup h
   // then takes the y-transforms of the columns qz in [q0, q1)
   const int h = lb / g.nx;
@@ -326,10 +331,6 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
   const int nyz = g.ny * g.nz;
   const int lsz = pad_odd(g.nz);
   float* Zf = reinterpret_cast<float*>(P0);
-  // vector model: one transform of b_i . a per component (a raw source has one)
-  const int ncomp = (SRC == SRC_RAW) ? 1 : vd.ncomp;
-  for (int comp = 0; comp < ncomp; ++comp) {
-  if (comp) __syncthreads();   // the previous component's store still reads the LDS planes
   const float* __restrict__ b = vd.b + (long long)comp * g.N;
   batched<8, float>(nyz, [&](int p) { return plane_source<SRC>(pbase + p, a, nullptr, b, c); },
                     [&](int p, float v) {
@@ -360,7 +361,6 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
       v.y = -v.y;
     }
     dst[e] = v;
-  }
   }
 }
 
@@ -921,7 +921,8 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   const int x = plane_of_block(lb - h * g.nx, g.nx);
   const int j0 = h * g.npairs / g.ps, j1 = (h + 1) * g.npairs / g.ps;
   // vector model: out = sum_i b_i . v_i, the components added in order by the thread
-  // that owns the voxel
+  // that owns the voxel (a plane workgroup fills its CU, so components in workgroups of
+  // their own would only queue behind each other)
   for (int comp = 0; comp < vd.ncomp; ++comp) {
   if (comp) __syncthreads();   // the previous component's store still reads the LDS planes
   const float2* src = vd.uperm + (long long)comp * g.hsz + (long long)x * g.plane;

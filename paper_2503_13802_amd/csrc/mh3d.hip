@@ -372,7 +372,8 @@ static mh3d_status last_launch(const char* what) {
 // ---------------------------------------------------------------------------- single-volume launchers
 static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
   Timer t(p, KID_PLANE_FWD);
-  dim3 grid(p->g.ps * p->g.nx), block(p->L.T_plane);
+  // vector model: one group of ps * nx blocks per component (a raw source has one)
+  dim3 grid((src == SRC_RAW ? 1 : p->g.C) * p->g.ps * p->g.nx), block(p->L.T_plane);
   const size_t lds = p->L.lds_plane;
   switch (src) {
     case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
