@@ -119,8 +119,8 @@ __device__ __forceinline__ void batched(int n, LD ld, ST st) {
   }
 }
 
-// x-plane handled by block b: consecutive planes go to the same XCD (blocks are
-// dealt round-robin over the 8 XCDs), so stencil neighbours share an L2.
+// x-plane (or other unit) handled by block b of nx: consecutive units go to the same
+// XCD (blocks are dealt round-robin over the 8 XCDs), so neighbours share an L2.
 __device__ __forceinline__ int plane_of_block(int b, int nx) {
   if (nx % 8) return b;
   return (b & 7) * (nx >> 3) + (b >> 3);
@@ -645,19 +645,21 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
 
 // Single-volume class passes, grid = ncls/cpw blocks of T_class threads.
 // check_done skips the launch once the volume's solve is done.
+// XCD-aware: consecutive class blocks run on one XCD, so the short runs of G, G' and
+// the class-layout spectra that neighbouring blocks share are fetched into one L2.
 template <int HC, int E, bool VEC>
 __global__ __launch_bounds__(1024) void k_class_fwd(const VolDesc* __restrict__ vds, int check_done) {
   int lb;
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   if (check_done && vd.st->done) return;
-  class_fwd_body<HC, E, VEC>(vd, lb);
+  class_fwd_body<HC, E, VEC>(vd, plane_of_block(lb, gridDim.x));
 }
 template <int HC, int E, bool VEC>
 __global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ vds, int check_done) {
   int lb;
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   if (check_done && vd.st->done) return;
-  class_adj_body<HC, E, VEC>(vd, lb);
+  class_adj_body<HC, E, VEC>(vd, plane_of_block(lb, gridDim.x));
 }
 
 // Batched class passes over a task table (compact spectra), the element split E

@@ -1031,6 +1031,18 @@ extern "C" void mh3d_batch_destroy(mh3d_batch_t b) {
   delete b;
 }
 
+// Appends the n class blocks of volume v so that the tasks one XCD runs (blocks are
+// dealt round-robin over the 8 XCDs by launch index) take consecutive classes, whose
+// short runs of G, G' and the class-layout spectra share L2 lines.
+static void push_xcd_grouped(std::vector<int2>& t, int v, int n) {
+  const size_t s = t.size();
+  t.resize(s + n);
+  int u = 0;
+  for (size_t x = 0; x < 8; ++x)
+    for (size_t i = s; i < s + (size_t)n; ++i)
+      if ((i & 7) == x) t[i] = make_int2(v, u++);
+}
+
 extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh3d_batch_t* out) {
   if (!out) return fail(MH3D_ERR_INVALID, "out is NULL");
   *out = nullptr;
@@ -1051,7 +1063,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
     // one workgroup per x-plane: the batch already fills the chip with the planes of
     // many volumes, so splitting planes would only add work
     for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
-    for (int i = 0; i < p->g.ncls / p->g.cpw; ++i) t[1].push_back(make_int2(v, i));
+    push_xcd_grouped(t[1], v, p->g.ncls / p->g.cpw);
     for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
     for (int i = 0; i < update_blocks(p->g.N); ++i) t[3].push_back(make_int2(v, i));
     t[4].push_back(make_int2(v, 0));
