@@ -148,3 +148,11 @@ def test_product_path_has_no_oracle_dependency():
     for f in list(pkg.glob("*.py")) + list(pkg.glob("csrc/*")):
         txt = f.read_text()
         assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_design_notes_list_every_entry_point():
+    """The repository notes name every function the header declares."""
+    import os
+    txt = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "DESIGN.md")).read()
+    sec = txt[txt.index("**Boundary.**"):txt.index("Conventions:")]
+    assert [f for f in mh3d.declared_functions() if f not in sec] == []
