@@ -134,7 +134,7 @@ def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
     torch.cuda.synchronize()
     log("batched leg: %d plans built" % len(plans))
     # untimed: the batch's graphs and every plan's step size (power iteration, cached
-    # per plan), then the sequential solves' graphs on the first volume
+    # per plan), then a first plain solve (kernel code loading) on the first volume
     batch = mh3d.Batch(plans)
     t0 = time.perf_counter()
     batch.solve(ds, max_iter=16, tol=0.0, tau=0.0)
