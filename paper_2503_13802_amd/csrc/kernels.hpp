@@ -960,10 +960,11 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   }
 }
 
-// Blocks of the volume-wide update pass, each a contiguous run of whole 1024-voxel
-// tiles: about 2048 voxels per block, at most 256 blocks (one per CU; their FP64
-// partials are summed by k_vol_finish).
-constexpr int UPD_THREADS = 1024;
+// Blocks of the volume-wide update pass, each a contiguous run of whole UPD_THREADS-voxel
+// tiles: about 2048 voxels per block, at most 256 blocks per volume (their FP64
+// partials are summed by k_vol_finish).  512 threads let two blocks share a CU, which
+// matters when a batch launches thousands of them.
+constexpr int UPD_THREADS = 512;
 __host__ __device__ inline int update_blocks(long long n) {
   long long b = (n + 2047) / 2048;
   return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
