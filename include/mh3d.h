@@ -138,8 +138,11 @@ mh3d_status mh3d_forward(mh3d_plan_t plan, const float* rho, float* d);
 /* rho = A^T d (adjoint of eq. dN).  d: portraits, rho: volume. */
 mh3d_status mh3d_adjoint(mh3d_plan_t plan, const float* d, float* rho);
 
-/* d = A rho and x = A^T d in one sequence of five passes: the pass that writes d also
- * starts A^T on it (the same arithmetic as mh3d_forward then mh3d_adjoint, bitwise). */
+/* d = A rho and x = A^T d in one sequence of five passes.  d is bitwise mh3d_forward's.
+ * Without boundary padding A^T starts from d's small-grid spectra as the forward class
+ * pass produced them (transforming d back would only reproduce them up to rounding), so
+ * x equals mh3d_adjoint(d) up to that rounding; with padding the pass that writes d
+ * also transforms its field-of-view crop back, bitwise as mh3d_adjoint(d). */
 mh3d_status mh3d_forward_adjoint(mh3d_plan_t plan, const float* rho, float* d, float* x);
 
 /* Per-harmonic back-projections c_k = b (H_k^T P^T d_k), the terms of A^T d before

@@ -415,6 +415,20 @@ struct HLoad<1, E> {
   }
 };
 
+// Destination of the forward class pass's decimated spectra F_k (the small-grid spectra
+// of the portraits, before their inverse transform):
+//   FWD_G          G = F  (the small-grid pass turns them into portraits)
+//   FWD_ADJ        G' = my mz F (the adjoint takes them as they are: normal operator)
+//   FWD_G_AND_ADJ  both (A then A^T: the portraits are written and A^T starts at once)
+//   FWD_RESID      G' = my mz F - G, G holding the (unnormalised) small-grid spectra of
+//                  the measured portraits (the solver's residual)
+// Without boundary padding the small-grid inverse and forward transforms between the
+// forward and the adjoint are, up to their scale my mz and to rounding, an identity on
+// these spectra (they only make the two self-conjugate columns of each spectrum
+// Hermitian, which F already is in exact arithmetic), so the adjoint can start from F.
+// With padding the crop to the field of view sits between them and the pass stays.
+enum { FWD_G = 0, FWD_ADJ = 1, FWD_G_AND_ADJ = 2, FWD_RESID = 3 };
+
 // LDS layout of the class kernels: tables (nx + mx), U0/U1 (W lines of lsx, the
 // x-transforms of the W = cpw*nmem member columns), F0/F1 (K*cpw lines of mx).
 __host__ __device__ inline size_t class_lds_elems(const Geo& g) {
@@ -440,8 +454,9 @@ __device__ __forceinline__ void class_g_index(const Geo& g, int p, int c0, int& 
 // Forward pass 2 of one block (cpw classes).  Threads beyond vd.T_class only take
 // part in the barriers and shuffles (batched launches use the largest block size).
 // VEC: vector model, vd.ncomp components (else one, and the loop folds away).
+// mode (FWD_*) selects where the decimated spectra go.
 template <int HC, int E, bool VEC = false>
-__device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
+__device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb, int mode) {
   constexpr int HPF = hpf_of(HC, E);
   const Geo& g = vd.g;
   extern __shared__ float2 lds[];
@@ -537,11 +552,20 @@ __device__ __forceinline__ void class_fwd_body(const VolDesc& vd, int lb) {
   }
   const float2* F = fft_lines<+1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
   float2* __restrict__ G = vd.G;
+  float2* __restrict__ Gp = vd.Gp;
+  // the small-grid transforms are unnormalised: their round trip scales by my mz
+  const float syz = (float)(g.my * g.mz);
   for (int p = threadIdx.x; p < g.K * g.cpw * g.mx; p += blockDim.x) {
     int fo;
     long long go;
     class_g_index(g, p, c0, fo, go);
-    G[go] = F[fo];
+    const float2 f = F[fo];
+    if (mode == FWD_G || mode == FWD_G_AND_ADJ) G[go] = f;
+    if (mode == FWD_ADJ || mode == FWD_G_AND_ADJ) Gp[go] = make_float2(syz * f.x, syz * f.y);
+    if (mode == FWD_RESID) {
+      const float2 dh = G[go];
+      Gp[go] = make_float2(syz * f.x - dh.x, syz * f.y - dh.y);
+    }
   }
 }
 
@@ -648,11 +672,11 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
 // XCD-aware: consecutive class blocks run on one XCD, so the short runs of G, G' and
 // the class-layout spectra that neighbouring blocks share are fetched into one L2.
 template <int HC, int E, bool VEC>
-__global__ __launch_bounds__(1024) void k_class_fwd(const VolDesc* __restrict__ vds, int check_done) {
+__global__ __launch_bounds__(1024) void k_class_fwd(const VolDesc* __restrict__ vds, int check_done, int mode) {
   int lb;
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   if (check_done && vd.st->done) return;
-  class_fwd_body<HC, E, VEC>(vd, plane_of_block(lb, gridDim.x));
+  class_fwd_body<HC, E, VEC>(vd, plane_of_block(lb, gridDim.x), mode);
 }
 template <int HC, int E, bool VEC>
 __global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ vds, int check_done) {
@@ -664,27 +688,31 @@ __global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ 
 
 // Batched class passes over a task table (compact spectra), the element split E
 // of each volume dispatched per block.  Volumes whose solve is done are skipped.
-#define MH3D_E_SWITCH(BODY)                 \
-  switch (vd.g.E) {                         \
-    case 8: BODY<0, 8>(vd, lb); break;      \
-    case 6: BODY<0, 6>(vd, lb); break;      \
-    case 4: BODY<0, 4>(vd, lb); break;      \
-    case 3: BODY<0, 3>(vd, lb); break;      \
-    case 2: BODY<0, 2>(vd, lb); break;      \
-    case 9: BODY<0, 9>(vd, lb); break;      \
-    default: BODY<0, 1>(vd, lb); break;     \
+#define MH3D_E_SWITCH(BODY, ...)                         \
+  switch (vd.g.E) {                                      \
+    case 8: BODY<0, 8>(vd, lb __VA_ARGS__); break;       \
+    case 6: BODY<0, 6>(vd, lb __VA_ARGS__); break;       \
+    case 4: BODY<0, 4>(vd, lb __VA_ARGS__); break;       \
+    case 3: BODY<0, 3>(vd, lb __VA_ARGS__); break;       \
+    case 2: BODY<0, 2>(vd, lb __VA_ARGS__); break;       \
+    case 9: BODY<0, 9>(vd, lb __VA_ARGS__); break;       \
+    default: BODY<0, 1>(vd, lb __VA_ARGS__); break;      \
   }
-__global__ __launch_bounds__(1024) void k_class_fwd_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks) {
+// mode: FWD_RESID (solver) or FWD_ADJ (power iteration) for volumes without padding,
+// FWD_G for padded ones (their small-grid pass crops to the field of view).
+__global__ __launch_bounds__(1024) void k_class_fwd_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                          int mode) {
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   if (vd.st->done) return;
-  MH3D_E_SWITCH(class_fwd_body)
+  const int m = vd.g.padded ? FWD_G : mode;
+  MH3D_E_SWITCH(class_fwd_body, , m)
 }
 __global__ __launch_bounds__(1024) void k_class_adj_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks) {
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   if (vd.st->done) return;
-  MH3D_E_SWITCH(class_adj_body)
+  MH3D_E_SWITCH(class_adj_body, )
 }
 #undef MH3D_E_SWITCH
 
@@ -814,7 +842,9 @@ __global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ 
 }
 
 // Adjoint pass 3: R2C of the portraits r.  One block per (k, x'-block).
-__global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ r) {
+// out: the spectra's destination (NULL: G').
+__global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ r,
+                                                   float2* __restrict__ out) {
   int lb;
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   const Geo& g = vd.g;
@@ -846,7 +876,7 @@ __global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ 
   if (rows & 1) {
     for (int z = threadIdx.x; z < g.mz; z += blockDim.x) Zf[2 * ((rows >> 1) * lsmz + z) + 1] = 0.f;
   }
-  small_r2c_and_store(g, P0, P1, twy, twz, vd.Gp, k, xbi);
+  small_r2c_and_store(g, P0, P1, twy, twz, out ? out : vd.Gp, k, xbi);
 }
 
 // ============================================================================ pass 1 adjoint

@@ -381,28 +381,29 @@ static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
 // HC: 0 compact (analytic) spectra, 1 complex (user) spectra, 2 complex spectra of a
 // vector-model plan (components looped inside the class passes).
 template <int HC, int E>
-static void class_fwd_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
+static void class_fwd_t(mh3d_plan_t p, int chk, const VolDesc* vd, int mode) {
   k_class_fwd<HC == 0 ? 0 : 1, E, HC == 2>
-      <<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
+      <<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk, mode);
 }
 template <int HC, int E>
-static void class_adj_t(mh3d_plan_t p, int chk, const VolDesc* vd) {
+static void class_adj_t(mh3d_plan_t p, int chk, const VolDesc* vd, int) {
   k_class_adj<HC == 0 ? 0 : 1, E, HC == 2>
       <<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk);
 }
 
-#define E_DISPATCH(HCV, FN)                       \
-  switch (p->g.E) {                               \
-    case 9: FN<HCV, 9>(p, chk, vd); break;            \
-    case 8: FN<HCV, 8>(p, chk, vd); break;            \
-    case 6: FN<HCV, 6>(p, chk, vd); break;            \
-    case 4: FN<HCV, 4>(p, chk, vd); break;            \
-    case 3: FN<HCV, 3>(p, chk, vd); break;            \
-    case 2: FN<HCV, 2>(p, chk, vd); break;            \
-    default: FN<HCV, 1>(p, chk, vd); break;           \
+#define E_DISPATCH(HCV, FN)                             \
+  switch (p->g.E) {                                     \
+    case 9: FN<HCV, 9>(p, chk, vd, mode); break;        \
+    case 8: FN<HCV, 8>(p, chk, vd, mode); break;        \
+    case 6: FN<HCV, 6>(p, chk, vd, mode); break;        \
+    case 4: FN<HCV, 4>(p, chk, vd, mode); break;        \
+    case 3: FN<HCV, 3>(p, chk, vd, mode); break;        \
+    case 2: FN<HCV, 2>(p, chk, vd, mode); break;        \
+    default: FN<HCV, 1>(p, chk, vd, mode); break;       \
   }
 
-static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk) {
+// mode: FWD_G, FWD_ADJ, FWD_G_AND_ADJ or FWD_RESID (where the decimated spectra go).
+static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk, int mode) {
   Timer t(p, KID_CLASS_FWD);
   const VolDesc* vd = p->vdd;
   if (p->compact) { E_DISPATCH(0, class_fwd_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
@@ -412,6 +413,7 @@ static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk) {
 static mh3d_status launch_class_adj(mh3d_plan_t p, int chk, const VolDesc* vd = nullptr) {
   Timer t(p, KID_CLASS_ADJ);
   if (!vd) vd = p->vdd;
+  const int mode = 0;
   if (p->compact) { E_DISPATCH(0, class_adj_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
   return last_launch("k_class_adj");
 }
@@ -429,9 +431,10 @@ static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d) {
   return last_launch("k_small_inv");
 }
 
-static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r) {
+// out: destination of the spectra (NULL: G', the adjoint's input).
+static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r, float2* out = nullptr) {
   Timer t(p, KID_SMALL_FWD);
-  k_small_fwd<<<dim3(p->g.K * (p->g.mx / p->g.xb)), dim3(p->L.T_small), p->L.lds_small, p->ls>>>(p->vdd, r);
+  k_small_fwd<<<dim3(p->g.K * (p->g.mx / p->g.xb)), dim3(p->L.T_small), p->L.lds_small, p->ls>>>(p->vdd, r, out);
   return last_launch("k_small_fwd");
 }
 
@@ -724,8 +727,13 @@ extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, flo
   CHK(check_plan(p));
   if (!rho || !d || !x) return fail(MH3D_ERR_INVALID, "NULL array");
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
-  CHK(launch_class_fwd(p, 0));
-  CHK(launch_small_inv(p, EPI_STORE_BACK, d));   // stores d and starts A^T on it in place
+  if (p->g.padded) {
+    CHK(launch_class_fwd(p, 0, FWD_G));
+    CHK(launch_small_inv(p, EPI_STORE_BACK, d));   // stores d and starts A^T on its cropped copy
+  } else {
+    CHK(launch_class_fwd(p, 0, FWD_G_AND_ADJ));    // A^T starts from d's spectra
+    CHK(launch_small_inv(p, EPI_STORE, d));
+  }
   CHK(launch_class_adj(p, 0));
   CHK(launch_plane_adj(p, OUT_SCALE_B, x, nullptr));
   return MH3D_OK;
@@ -735,7 +743,7 @@ extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
   CHK(check_plan(p));
   if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
-  CHK(launch_class_fwd(p, 0));
+  CHK(launch_class_fwd(p, 0, FWD_G));
   CHK(launch_small_inv(p, EPI_STORE, d));
   return MH3D_OK;
 }
@@ -763,8 +771,12 @@ extern "C" mh3d_status mh3d_backproject(mh3d_plan_t p, const float* d, float* c)
 // out = (A^T A + lambda T^T T)(s w): s from the state (1/||w|| in power iteration).
 static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out) {
   CHK(launch_plane_fwd(p, SRC_SCALED, w));
-  CHK(launch_class_fwd(p, 1));
-  CHK(launch_small_inv(p, EPI_BACK, nullptr));
+  if (p->g.padded) {
+    CHK(launch_class_fwd(p, 1, FWD_G));
+    CHK(launch_small_inv(p, EPI_BACK, nullptr));   // crop to the field of view
+  } else {
+    CHK(launch_class_fwd(p, 1, FWD_ADJ));
+  }
   CHK(launch_class_adj(p, 1));
   CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
   CHK(launch_update(p, UPD_NORMAL, out, w));
@@ -826,8 +838,12 @@ extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64
 static mh3d_status enqueue_update(mh3d_plan_t p) {
   Timer t(p, KID_SOLVE_ITER);
   CHK(launch_plane_fwd(p, SRC_FISTA_Y, nullptr));
-  CHK(launch_class_fwd(p, 1));
-  CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr));
+  if (p->g.padded) {
+    CHK(launch_class_fwd(p, 1, FWD_G));
+    CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr));   // residual on the field of view
+  } else {
+    CHK(launch_class_fwd(p, 1, FWD_RESID));   // residual spectrum against the data's, held in G
+  }
   CHK(launch_class_adj(p, 1));
   CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
   CHK(launch_update(p, UPD_FISTA, nullptr, nullptr));
@@ -863,6 +879,9 @@ static mh3d_status solve_setup(mh3d_plan_t p, const float* d, const float* rho0,
   p->vdh.hist_len = opts->max_iter;
   p->vdh.k_first = k0;
   CHK(upload_desc(p));
+  // without padding the updates form the residual spectrum F(A y) - F(d): F(d) once,
+  // held in G for the whole solve
+  if (!g.padded) CHK(launch_small_fwd(p, d, p->G));
   DevState s0;
   memset(&s0, 0, sizeof s0);
   s0.k = k0;
@@ -1027,7 +1046,9 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
     // many volumes, so splitting planes would only add work
     for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
     push_xcd_grouped(t[1], v, p->g.ncls / p->g.cpw);
-    for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
+    // the small-grid pass of the updates is needed only to crop to a field of view
+    if (p->g.padded)
+      for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
     for (int i = 0; i < update_blocks(p->g.N); ++i) t[3].push_back(make_int2(v, i));
     t[4].push_back(make_int2(v, 0));
     b->T_class = std::max(b->T_class, p->L.T_class);
@@ -1040,6 +1061,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   b->hvd.resize(n);
   for (int i = 0; i < 5; ++i) {
     b->ntask[i] = (int)t[i].size();
+    if (t[i].empty()) continue;   // no small-grid tasks when no volume is padded
     if (hipMalloc(&b->tasks[i], sizeof(int2) * t[i].size()) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch tasks"));
     if (hipMemcpy(b->tasks[i], t[i].data(), sizeof(int2) * t[i].size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(MH3D_ERR_HIP, "upload of batch tasks failed"));
@@ -1060,10 +1082,12 @@ static mh3d_status batch_upload(mh3d_batch_t b, int v) {
 static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
   k_plane_fwd<SRC_FISTA_Y><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
   CHK(last_launch("k_plane_fwd (batch)"));
-  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1], FWD_RESID);
   CHK(last_launch("k_class_fwd_batch"));
-  k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
-  CHK(last_launch("k_small_inv (batch)"));
+  if (b->ntask[2]) {
+    k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+    CHK(last_launch("k_small_inv (batch)"));
+  }
   k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
   CHK(last_launch("k_class_adj_batch"));
   AdjOut ao;
@@ -1082,10 +1106,12 @@ static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
 static mh3d_status batch_power_step(mh3d_batch_t b, hipStream_t st) {
   k_plane_fwd<SRC_SCALED><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
   CHK(last_launch("k_plane_fwd (batch power)"));
-  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1], FWD_ADJ);
   CHK(last_launch("k_class_fwd_batch (power)"));
-  k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
-  CHK(last_launch("k_small_inv (batch power)"));
+  if (b->ntask[2]) {
+    k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+    CHK(last_launch("k_small_inv (batch power)"));
+  }
   k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
   CHK(last_launch("k_class_adj_batch (power)"));
   AdjOut ao;
@@ -1307,7 +1333,7 @@ extern "C" mh3d_status mh3d_mhad(mh3d_plan_t p, const float* d, double lambda, c
   return last_launch("k_mhad");
 }
 
-// ============================================================================ pass timing// ============================================================================ pass timing
+// ============================================================================ pass timing
 extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps, double* us) {
   CHK(check_plan(p));
   if (pass < 0 || pass > 5 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");
@@ -1319,7 +1345,7 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
   auto launch = [&]() -> mh3d_status {
     switch (pass) {
       case 0: return launch_plane_fwd(p, SRC_PLAIN, p->vol[0]);
-      case 1: return launch_class_fwd(p, 0);
+      case 1: return launch_class_fwd(p, 0, FWD_G);
       case 2: return launch_small_inv(p, EPI_STORE, dtmp);
       case 3: return launch_small_fwd(p, dtmp);
       case 4: return launch_class_adj(p, 0);

@@ -52,11 +52,13 @@ def test_vector_forward_adjoint_vs_oracle(shape, harm, ds, C):
     x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
     assert rel_l2(d, d_ref) <= TOL
     assert rel_l2(x, x_ref) <= TOL
-    # the fused five-pass sequence gives bitwise the separate calls' results
+    # the fused five-pass sequence: the forward call's portraits bitwise, A^T from their
+    # spectra (the adjoint call's up to the rounding of the small-grid round trip)
     dt, xt = p.forward_adjoint(torch.tensor(rho, dtype=torch.float32))
     d1 = p.forward(torch.tensor(rho, dtype=torch.float32))
     assert torch.equal(dt, d1)
-    assert torch.equal(xt, p.adjoint(d1))
+    assert rel_l2(xt.cpu().numpy(), p.adjoint(d1).cpu().numpy()) <= 1e-6
+    assert rel_l2(xt.cpu().numpy(), om.adjoint_vector(h, b, om.forward_vector(h, b, rho, ds), ds)) <= TOL
 
 
 def test_vector_point_source_reads_component_psf():
