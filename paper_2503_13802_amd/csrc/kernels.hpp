@@ -880,13 +880,140 @@ __global__ __launch_bounds__(1024) void k_small_fwd(const VolDesc* __restrict__ 
 }
 
 // ============================================================================ pass 1 adjoint
-enum { OUT_SCALE_B = 0, OUT_U = 1 };
+enum { OUT_SCALE_B = 0, OUT_U = 1, OUT_STEP_NORMAL = 2, OUT_STEP_FISTA = 3 };
 enum { UPD_NORMAL = 1, UPD_FISTA = 2 };
 
 struct AdjOut {
   float* out;              // OUT_SCALE_B / UPD_NORMAL: result (UPD_NORMAL: NULL -> rho[(k+1) & 1])
   const float* yin;        // UPD_NORMAL: w_{t-1} (v = scale * w_{t-1}); NULL -> rho[k & 1]
 };
+
+// The 13 values of one voxel's regulariser stencil and the values its update reads.
+struct StencilVals {
+  float c, zm2, zm1, zp1, zp2, ym2, ym1, yp1, yp2, xm2, xm1, xp1, xp2, u, rk;
+  bool shell;              // on the boundary prior's shell
+};
+
+// The voxel-wise end of a solver step, after the adjoint left u = b . v (the A^T A part):
+//   UPD_NORMAL  out = u + lam T^T T (s w_prev); FP64 <s w_prev, out>, ||out||^2
+//               (power iteration: lmax, next scale 1/||out||)
+//   UPD_FISTA   g = u + lam T^T T y^k; rho^{k+1} = max(y^k - tau g, 0);
+//               y^{k+1} = rho^{k+1} + k/(k+3) (rho^{k+1} - rho^k);
+//               FP64 ||rho^{k+1} - y^k||^2, ||rho^{k+1}||^2, count of non-finite g
+// T^T T is the periodic 13-point stencil sum_a (v[+2] - 4v[+1] + 6v - 4v[-1] + v[-2])
+// of stacked second differences (reg_kind 1: T = I); neighbours are read from global
+// memory (cache resident).  Used by k_vol_update and by the adjoint plane pass that
+// finishes the step itself (OUT_STEP_*).
+template <int UPD>
+struct StepCtx {
+  const Geo& g;
+  const float* __restrict__ yv;
+  const float* __restrict__ rk;
+  float* __restrict__ out;       // UPD_NORMAL
+  float* __restrict__ rho_next;  // UPD_FISTA
+  float* __restrict__ y_next;
+  float s, lam, alpha, tau, beta1;
+  bool stencil;
+  int aw;
+  long long pl;
+  __device__ StepCtx(const VolDesc& vd, const AdjOut& ao) : g(vd.g) {
+    const int kk = vd.st->k;
+    yv = (UPD == UPD_NORMAL) ? (ao.yin ? ao.yin : vd.rho[kk & 1]) : vd.y[kk & 1];
+    rk = vd.rho[kk & 1];
+    out = (UPD == UPD_NORMAL) ? (ao.out ? ao.out : vd.rho[(kk + 1) & 1]) : nullptr;
+    rho_next = vd.rho[(kk + 1) & 1];
+    y_next = vd.y[(kk + 1) & 1];
+    s = (UPD == UPD_NORMAL) ? (float)vd.st->scale : 1.f;
+    lam = vd.lam;
+    alpha = vd.alpha;
+    tau = (float)vd.st->tau;
+    beta1 = (float)((double)kk / (kk + 3.0));      // (k+1-1)/(k+1+2)
+    stencil = vd.reg_kind == 0;
+    aw = vd.aw;
+    pl = (long long)g.ny * g.nz;
+  }
+  __device__ __forceinline__ StencilVals load(long long i, float u) const {
+    StencilVals v;
+    v.c = yv[i];
+    v.u = u;
+    v.rk = (UPD == UPD_FISTA) ? rk[i] : 0.f;
+    v.shell = false;
+    if (stencil || alpha > 0.f) {
+      const uint32_t r = g.f_nz.div((uint32_t)i);
+      const int z = (int)((uint32_t)i - r * (uint32_t)g.nz);
+      const int y = (int)g.f_ny.mod(r), x = (int)g.f_ny.div(r);
+      // a 2D grid's projection axis (ny = 1) has no faces
+      v.shell = x < aw || x >= g.nx - aw || (g.ny > 1 && (y < aw || y >= g.ny - aw)) || z < aw || z >= g.nz - aw;
+      if (!stencil) return v;
+      const long long row = i - z;
+      // periodic neighbours (every axis is >= 4 long, so one wrap suffices, except the
+      // projection axis of a 2D grid: length 1, every neighbour is the voxel itself and
+      // its second differences vanish)
+      auto wz = [&](int d) { int q = z + d; q += q < 0 ? g.nz : 0; q -= q >= g.nz ? g.nz : 0; return yv[row + q]; };
+      auto wy = [&](int d) {
+        if (g.ny == 1) return v.c;
+        int q = y + d; q += q < 0 ? g.ny : 0; q -= q >= g.ny ? g.ny : 0;
+        return yv[i + (long long)(q - y) * g.nz];
+      };
+      auto wx = [&](int d) {
+        int q = x + d; q += q < 0 ? g.nx : 0; q -= q >= g.nx ? g.nx : 0;
+        return yv[i + (long long)(q - x) * pl];
+      };
+      v.zm2 = wz(-2); v.zm1 = wz(-1); v.zp1 = wz(1); v.zp2 = wz(2);
+      v.ym2 = wy(-2); v.ym1 = wy(-1); v.yp1 = wy(1); v.yp2 = wy(2);
+      v.xm2 = wx(-2); v.xm1 = wx(-1); v.xp1 = wx(1); v.xp2 = wx(2);
+    }
+    return v;
+  }
+  // T^T T (s y) + alpha P_alpha^T P_alpha (s y).  No contraction into fused
+  // multiply-adds here or in apply: the two kernels that inline these functions then
+  // round every operation alike and finish a step bitwise identically.
+  __device__ __forceinline__ float reg(const StencilVals& v) const {
+#pragma clang fp contract(off)
+    float t;
+    if (!stencil) {
+      t = s * v.c;
+    } else {
+      t = 18.f * (s * v.c);
+      t += s * (v.zp2 + v.zm2) - 4.f * s * (v.zp1 + v.zm1);
+      t += s * (v.yp2 + v.ym2) - 4.f * s * (v.yp1 + v.ym1);
+      t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
+    }
+    if (alpha > 0.f && v.shell) t += alpha * (s * v.c);
+    return t;
+  }
+  static constexpr int NV = UPD == UPD_NORMAL ? 2 : 3;
+  // the update of voxel i and its terms of the FP64 sums
+  __device__ __forceinline__ void apply(long long i, const StencilVals& v, double* acc) const {
+#pragma clang fp contract(off)
+    if constexpr (UPD == UPD_NORMAL) {
+      const float o = v.u + lam * reg(v);
+      out[i] = o;
+      acc[0] += (double)(s * v.c) * (double)o;
+      acc[1] += (double)o * (double)o;
+    } else {
+      const float yk = v.c;
+      const float gr = v.u + lam * reg(v);
+      const float rn = fmaxf(yk - tau * gr, 0.f);
+      rho_next[i] = rn;
+      y_next[i] = rn + beta1 * (rn - v.rk);
+      const double dd = (double)rn - (double)yk;
+      acc[0] += dd * dd;
+      acc[1] += (double)rn * (double)rn;
+      if (!isfinite(gr) || !isfinite(yk)) acc[2] += 1.0;   // max(NaN, 0) would hide it
+    }
+  }
+};
+
+// The block's FP64 sums into vd.partials[NV * lb ...] (k_vol_finish reduces them).
+template <int NV>
+__device__ __forceinline__ void store_step_partials(const VolDesc& vd, double* acc, double* red, int lb) {
+  block_reduce_f64<NV>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) vd.partials[NV * lb + j] = acc[j];
+  }
+}
 
 // Deterministic grid reduction: every block writes NV partials; the last block to
 // arrive sums them in block order.  Returns true in thread 0 of the last block.
@@ -926,9 +1053,12 @@ __device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, De
 
 // Adjoint pass 1: gather the class layout into a half plane, inverse y FFT, C2R
 // along z, times the sensitivity:
-//   OUT_SCALE_B  ao.out = b . v                          (A^T)
-//   OUT_U        vd.u = b . v  (the A^T A part of a solver step; skipped once the
-//                volume's solve is done; k_vol_update finishes the step)
+//   OUT_SCALE_B      ao.out = b . v                          (A^T)
+//   OUT_U            vd.u = b . v  (the A^T A part of a solver step; skipped once the
+//                    volume's solve is done; k_vol_update finishes the step)
+//   OUT_STEP_NORMAL  the step itself on the block's voxels with u = b . v (StepCtx),
+//   OUT_STEP_FISTA   its FP64 sums in vd.partials[lb] for k_vol_finish (scalar model:
+//                    one component)
 // grid = ps * nx blocks (ps per x-plane).
 template <int OUT>
 __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
@@ -936,7 +1066,8 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   const Geo& g = vd.g;
-  if constexpr (OUT == OUT_U) {
+  constexpr bool kStep = (OUT == OUT_STEP_NORMAL || OUT == OUT_STEP_FISTA);
+  if constexpr (OUT == OUT_U || kStep) {
     if (vd.st->done) return;
   }
   extern __shared__ float2 lds[];
@@ -979,6 +1110,35 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   };
   const float* __restrict__ b = vd.b + (long long)comp * g.N;
   const long long pbase = (long long)x * g.ny * g.nz + (long long)y0 * g.nz;
+  if constexpr (kStep) {
+    // u = b . v of the block's voxels stays in registers: the step reads it there
+    constexpr int UPD = OUT == OUT_STEP_NORMAL ? UPD_NORMAL : UPD_FISTA;
+    constexpr int NV = StepCtx<UPD>::NV;
+    __shared__ double red[64];
+    const StepCtx<UPD> ctx(vd, ao);
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    const int n = (y1 - y0) * g.nz;
+    constexpr int U = 2;
+    for (int p = threadIdx.x; p < n; p += U * (int)blockDim.x) {
+      StencilVals v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int pq = p + q * (int)blockDim.x;
+        // a rounded product, as the stored u that k_vol_update reads (no contraction
+        // into the step's sums), so both ways of finishing a step agree bitwise
+        if (pq < n) v[q] = ctx.load(pbase + pq, __fmul_rn(b[pbase + pq], Xf[vidx(pq + y0 * g.nz)]));
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int pq = p + q * (int)blockDim.x;
+        if (pq < n) ctx.apply(pbase + pq, v[q], acc);
+      }
+    }
+    store_step_partials<NV>(vd, acc, red, lb);
+    return;
+  }
   float* __restrict__ out = (OUT == OUT_U) ? vd.u : ao.out;
   if (comp == 0) {
     batched<8, float>((y1 - y0) * g.nz, [&](int p) { return b[pbase + p]; },
@@ -1000,41 +1160,19 @@ __host__ __device__ inline int update_blocks(long long n) {
   return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
 }
 
-// The 13 values of one voxel's regulariser stencil and the values its update reads.
-struct StencilVals {
-  float c, zm2, zm1, zp1, zp2, ym2, ym1, yp1, yp2, xm2, xm1, xp1, xp2, u, rk;
-  bool shell;              // on the boundary prior's shell
-};
-
-// Finishes a solver step after k_plane_adj<OUT_U> left u = b . v (the A^T A part):
-//   UPD_NORMAL  out = u + lam T^T T (s w_prev); FP64 <s w_prev, out>, ||out||^2
-//               (power iteration: lmax, next scale 1/||out||)
-//   UPD_FISTA   g = u + lam T^T T y^k; rho^{k+1} = max(y^k - tau g, 0);
-//               y^{k+1} = rho^{k+1} + k/(k+3) (rho^{k+1} - rho^k);
-//               FP64 ||rho^{k+1} - y^k||^2, ||rho^{k+1}||^2, count of non-finite g
-// T^T T is the periodic 13-point stencil sum_a (v[+2] - 4v[+1] + 6v - 4v[-1] + v[-2])
-// of stacked second differences (reg_kind 1: T = I); neighbours are read from global
-// memory (cache resident).  Each block leaves its FP64 sums in vd.partials;
-// k_vol_finish reduces them and updates the state.  grid = vd.nb_upd blocks of
-// UPD_THREADS threads per volume.
+// Finishes a solver step after k_plane_adj<OUT_U> left u = b . v (see StepCtx).  Each
+// block leaves its FP64 sums in vd.partials; k_vol_finish reduces them and updates the
+// state.  grid = vd.nb_upd blocks of UPD_THREADS threads per volume.
 template <int UPD>
 __global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
                                                     AdjOut ao) {
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   const Geo& g = vd.g;
-  DevState* st = vd.st;
-  if (st->done) return;
+  if (vd.st->done) return;
   __shared__ double red[64];
-  const int kk = st->k;
-  const float* __restrict__ yv = (UPD == UPD_NORMAL) ? (ao.yin ? ao.yin : vd.rho[kk & 1]) : vd.y[kk & 1];
+  const StepCtx<UPD> ctx(vd, ao);
   const float* __restrict__ u = vd.u;
-  const float* __restrict__ rk = vd.rho[kk & 1];
-  const float s = (UPD == UPD_NORMAL) ? (float)st->scale : 1.f;
-  const float lam = vd.lam;
-  const bool stencil = vd.reg_kind == 0;
-  const float alpha = vd.alpha;
-  const int aw = vd.aw;
   const long long N = g.N;
   const int nb = vd.nb_upd;
   constexpr int T = UPD_THREADS;
@@ -1043,109 +1181,23 @@ __global__ __launch_bounds__(UPD_THREADS) void k_vol_update(const VolDesc* __res
   // wrote on that XCD, and their x-neighbours)
   const long long i0 = (long long)plane_of_block(lb, nb) * chunk;
   const long long i1 = i0 + chunk < N ? i0 + chunk : N;
-  const long long pl = (long long)g.ny * g.nz;
-  auto load = [&](long long i) {
-    StencilVals v;
-    v.c = yv[i];
-    v.u = u[i];
-    v.rk = (UPD == UPD_FISTA) ? rk[i] : 0.f;
-    v.shell = false;
-    if (stencil || alpha > 0.f) {
-      const uint32_t r = g.f_nz.div((uint32_t)i);
-      const int z = (int)((uint32_t)i - r * (uint32_t)g.nz);
-      const int y = (int)g.f_ny.mod(r), x = (int)g.f_ny.div(r);
-      // a 2D grid's projection axis (ny = 1) has no faces
-      v.shell = x < aw || x >= g.nx - aw || (g.ny > 1 && (y < aw || y >= g.ny - aw)) || z < aw || z >= g.nz - aw;
-      if (!stencil) return v;
-      const long long row = i - z;
-      // periodic neighbours (every axis is >= 4 long, so one wrap suffices, except the
-      // projection axis of a 2D grid: length 1, every neighbour is the voxel itself and
-      // its second differences vanish)
-      auto wz = [&](int d) { int q = z + d; q += q < 0 ? g.nz : 0; q -= q >= g.nz ? g.nz : 0; return yv[row + q]; };
-      auto wy = [&](int d) {
-        if (g.ny == 1) return v.c;
-        int q = y + d; q += q < 0 ? g.ny : 0; q -= q >= g.ny ? g.ny : 0;
-        return yv[i + (long long)(q - y) * g.nz];
-      };
-      auto wx = [&](int d) {
-        int q = x + d; q += q < 0 ? g.nx : 0; q -= q >= g.nx ? g.nx : 0;
-        return yv[i + (long long)(q - x) * pl];
-      };
-      v.zm2 = wz(-2); v.zm1 = wz(-1); v.zp1 = wz(1); v.zp2 = wz(2);
-      v.ym2 = wy(-2); v.ym1 = wy(-1); v.yp1 = wy(1); v.yp2 = wy(2);
-      v.xm2 = wx(-2); v.xm1 = wx(-1); v.xp1 = wx(1); v.xp2 = wx(2);
-    }
-    return v;
-  };
-  // T^T T (s y) + alpha P_alpha^T P_alpha (s y)
-  auto reg = [&](const StencilVals& v) {
-    float t;
-    if (!stencil) {
-      t = s * v.c;
-    } else {
-      t = 18.f * (s * v.c);
-      t += s * (v.zp2 + v.zm2) - 4.f * s * (v.zp1 + v.zm1);
-      t += s * (v.yp2 + v.ym2) - 4.f * s * (v.yp1 + v.ym1);
-      t += s * (v.xp2 + v.xm2) - 4.f * s * (v.xp1 + v.xm1);
-    }
-    if (alpha > 0.f && v.shell) t += alpha * (s * v.c);
-    return t;
-  };
   constexpr int U = 4;
-  if constexpr (UPD == UPD_NORMAL) {
-    float* __restrict__ out = ao.out ? ao.out : vd.rho[(kk + 1) & 1];
-    double acc[2] = {0.0, 0.0};
-    for (long long i = i0 + threadIdx.x; i < i1; i += U * T) {
-      StencilVals v[U];
+  constexpr int NV = StepCtx<UPD>::NV;
+  double acc[NV];
 #pragma unroll
-      for (int q = 0; q < U; ++q)
-        if (i + q * T < i1) v[q] = load(i + q * T);
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += U * T) {
+    StencilVals v[U];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (i + q * T >= i1) break;
-        const float o = v[q].u + lam * reg(v[q]);
-        out[i + q * T] = o;
-        acc[0] += (double)(s * v[q].c) * (double)o;
-        acc[1] += (double)o * (double)o;
-      }
-    }
-    block_reduce_f64<2>(acc, red);
-    if (threadIdx.x == 0) {
-      vd.partials[2 * lb] = acc[0];
-      vd.partials[2 * lb + 1] = acc[1];
-    }
-  } else {
-    const float tau = (float)st->tau;
-    const float beta1 = (float)((double)kk / (kk + 3.0));      // (k+1-1)/(k+1+2)
-    float* __restrict__ rho_next = vd.rho[(kk + 1) & 1];
-    float* __restrict__ y_next = vd.y[(kk + 1) & 1];
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (long long i = i0 + threadIdx.x; i < i1; i += U * T) {
-      StencilVals v[U];
+    for (int q = 0; q < U; ++q)
+      if (i + q * T < i1) v[q] = ctx.load(i + q * T, u[i + q * T]);
 #pragma unroll
-      for (int q = 0; q < U; ++q)
-        if (i + q * T < i1) v[q] = load(i + q * T);
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        if (i + q * T >= i1) break;
-        const float yk = v[q].c;
-        const float gr = v[q].u + lam * reg(v[q]);
-        const float rn = fmaxf(yk - tau * gr, 0.f);
-        rho_next[i + q * T] = rn;
-        y_next[i + q * T] = rn + beta1 * (rn - v[q].rk);
-        const double dd = (double)rn - (double)yk;
-        acc[0] += dd * dd;
-        acc[1] += (double)rn * (double)rn;
-        if (!isfinite(gr) || !isfinite(yk)) acc[2] += 1.0;   // max(NaN, 0) would hide it
-      }
-    }
-    block_reduce_f64<3>(acc, red);
-    if (threadIdx.x == 0) {
-      vd.partials[3 * lb] = acc[0];
-      vd.partials[3 * lb + 1] = acc[1];
-      vd.partials[3 * lb + 2] = acc[2];
+    for (int q = 0; q < U; ++q) {
+      if (i + q * T >= i1) break;
+      ctx.apply(i + q * T, v[q], acc);
     }
   }
+  store_step_partials<NV>(vd, acc, red, lb);
 }
 
 // Sums the block partials of k_vol_update in a fixed order (thread t takes blocks
@@ -1266,8 +1318,11 @@ __global__ __launch_bounds__(256) void k_mhad(const float* __restrict__ d, int K
 }
 
 // y^{k0} = rho^{k0} + (k0-1)/(k0+2) (rho^{k0} - rho^{k0-1}) for a (re)started solve.
+// y^{k0} = rho^{k0} + beta (rho^{k0} - rho^{k0-1}), rounded as the step forms y^{k+1}
+// (no contraction), so a resumed solve continues bitwise as the uninterrupted one.
 __global__ void k_fista_init(long long n, const float* __restrict__ rk, const float* __restrict__ rkm1,
                              float beta, float* __restrict__ y) {
+#pragma clang fp contract(off)
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const float r = rk[i];
     y[i] = r + beta * (r - rkm1[i]);

@@ -235,7 +235,8 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
   // ---- plane kernels
   L.T_plane = 1024;
   L.lds_plane = sizeof(float2) * ((size_t)g.ny + g.nz + 2 * (size_t)plane_lds(g));
-  if (L.lds_plane > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "x-plane of %dx%d does not fit in LDS", g.ny, g.nz);
+  // (+512 bytes: the block reduction of the step that the adjoint plane pass can run)
+  if (L.lds_plane + 512 > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "x-plane of %dx%d does not fit in LDS", g.ny, g.nz);
   return MH3D_OK;
 }
 
@@ -449,25 +450,39 @@ static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const floa
   ao.yin = yin;
   switch (out) {
     case OUT_SCALE_B: k_plane_adj<OUT_SCALE_B><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
+    case OUT_STEP_NORMAL: k_plane_adj<OUT_STEP_NORMAL><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
+    case OUT_STEP_FISTA: k_plane_adj<OUT_STEP_FISTA><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
     default: k_plane_adj<OUT_U><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
   }
   return last_launch("k_plane_adj");
 }
 
-static mh3d_status launch_update(mh3d_plan_t p, int upd, float* o, const float* yin) {
+// Scalar plans finish a solver step inside the adjoint plane pass (its u = b . v stays
+// in registers); vector plans, whose plane pass sums the components, run the update
+// pass after it.  The block count of the step's FP64 sums is the descriptor's nb_upd.
+static bool step_in_plane_pass(mh3d_plan_t p) { return p->g.C == 1; }
+
+// The adjoint plane pass and the rest of a solver step: out = (A^T A + lambda T^T T)(s w)
+// (UPD_NORMAL, w = yin) or one accelerated projected gradient update (UPD_FISTA).
+static mh3d_status launch_adjoint_step(mh3d_plan_t p, int upd, float* o, const float* yin) {
+  if (step_in_plane_pass(p)) {
+    CHK(launch_plane_adj(p, upd == UPD_NORMAL ? OUT_STEP_NORMAL : OUT_STEP_FISTA, o, yin));
+  } else {
+    CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
+  }
   Timer t(p, KID_UPDATE);
   AdjOut ao;
   ao.out = o;
   ao.yin = yin;
   const dim3 grid(update_blocks(p->g.N)), block(UPD_THREADS);
   if (upd == UPD_NORMAL) {
-    k_vol_update<UPD_NORMAL><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
+    if (!step_in_plane_pass(p)) k_vol_update<UPD_NORMAL><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
     k_vol_finish<UPD_NORMAL><<<1, 256, 0, p->ls>>>(p->vdd, nullptr);
   } else {
-    k_vol_update<UPD_FISTA><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
+    if (!step_in_plane_pass(p)) k_vol_update<UPD_FISTA><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
     k_vol_finish<UPD_FISTA><<<1, 256, 0, p->ls>>>(p->vdd, nullptr);
   }
-  return last_launch("k_vol_update");
+  return last_launch("k_vol_update / k_vol_finish");
 }
 
 // ---------------------------------------------------------------------------- state
@@ -630,7 +645,9 @@ static void fill_desc(mh3d_plan_t p) {
   v.aw = p->desc.alpha_width;
   v.T_class = p->L.T_class;
   v.u = p->vol[4];
-  v.nb_upd = update_blocks(p->g.N);
+  // blocks whose FP64 sums a step leaves: the adjoint plane pass's (scalar plans) or the
+  // update pass's (vector plans)
+  v.nb_upd = p->g.C == 1 ? p->g.ps * p->g.nx : update_blocks(p->g.N);
   v.ncomp = p->g.C;
   v.hs_cstride = (long long)p->g.K * p->g.hsz;
   for (int c = 0; c < 3; ++c) v.cmask[c] = p->cmask[c];
@@ -778,8 +795,7 @@ static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out
     CHK(launch_class_fwd(p, 1, FWD_ADJ));
   }
   CHK(launch_class_adj(p, 1));
-  CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
-  CHK(launch_update(p, UPD_NORMAL, out, w));
+  CHK(launch_adjoint_step(p, UPD_NORMAL, out, w));
   return MH3D_OK;
 }
 
@@ -845,8 +861,7 @@ static mh3d_status enqueue_update(mh3d_plan_t p) {
     CHK(launch_class_fwd(p, 1, FWD_RESID));   // residual spectrum against the data's, held in G
   }
   CHK(launch_class_adj(p, 1));
-  CHK(launch_plane_adj(p, OUT_U, nullptr, nullptr));
-  CHK(launch_update(p, UPD_FISTA, nullptr, nullptr));
+  CHK(launch_adjoint_step(p, UPD_FISTA, nullptr, nullptr));
   return MH3D_OK;
 }
 
@@ -990,7 +1005,7 @@ struct mh3d_batch_s {
   hipStream_t stream;
   VolDesc* vds = nullptr;            // device descriptors of all volumes
   std::vector<VolDesc> hvd;          // their host copies (plane passes at one workgroup per plane)
-  int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // plane, class, small, update, per-volume
+  int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // plane, class, small (padded volumes), -, per-volume
   int ntask[5] = {0, 0, 0, 0, 0};
   int T_class = 0;
   size_t lds_plane = 0, lds_class = 0, lds_small = 0;
@@ -1049,7 +1064,6 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
     // the small-grid pass of the updates is needed only to crop to a field of view
     if (p->g.padded)
       for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
-    for (int i = 0; i < update_blocks(p->g.N); ++i) t[3].push_back(make_int2(v, i));
     t[4].push_back(make_int2(v, 0));
     b->T_class = std::max(b->T_class, p->L.T_class);
     b->lds_plane = std::max(b->lds_plane, p->L.lds_plane);
@@ -1074,6 +1088,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
 static mh3d_status batch_upload(mh3d_batch_t b, int v) {
   b->hvd[v] = b->plans[v]->vdh;
   b->hvd[v].g.ps = 1;
+  b->hvd[v].nb_upd = b->plans[v]->g.nx;   // the step's sums: one plane-pass block per x-plane
   HIPCHK(hipMemcpyAsync(b->vds + v, &b->hvd[v], sizeof(VolDesc), hipMemcpyHostToDevice, b->stream));
   return MH3D_OK;
 }
@@ -1093,10 +1108,8 @@ static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
-  k_plane_adj<OUT_U><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  k_plane_adj<OUT_STEP_FISTA><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
   CHK(last_launch("k_plane_adj (batch)"));
-  k_vol_update<UPD_FISTA><<<dim3(b->ntask[3]), dim3(UPD_THREADS), 0, st>>>(b->vds, b->tasks[3], ao);
-  CHK(last_launch("k_vol_update (batch)"));
   k_vol_finish<UPD_FISTA><<<dim3(b->ntask[4]), dim3(256), 0, st>>>(b->vds, b->tasks[4]);
   CHK(last_launch("k_vol_finish (batch)"));
   return MH3D_OK;
@@ -1117,10 +1130,8 @@ static mh3d_status batch_power_step(mh3d_batch_t b, hipStream_t st) {
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
-  k_plane_adj<OUT_U><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  k_plane_adj<OUT_STEP_NORMAL><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
   CHK(last_launch("k_plane_adj (batch power)"));
-  k_vol_update<UPD_NORMAL><<<dim3(b->ntask[3]), dim3(UPD_THREADS), 0, st>>>(b->vds, b->tasks[3], ao);
-  CHK(last_launch("k_vol_update (batch power)"));
   k_vol_finish<UPD_NORMAL><<<dim3(b->ntask[4]), dim3(256), 0, st>>>(b->vds, b->tasks[4]);
   CHK(last_launch("k_vol_finish (batch power)"));
   return MH3D_OK;
