@@ -3,9 +3,9 @@
 A step is one application of the forward operator A followed by its adjoint A^T
 applied to A's output (Sec. 4.1 eq. dN; each accelerated-projected-gradient update of
 Sec. 4.3 costs one of each) on the workload's resident inputs: d = A rho is written to
-HBM and x = A^T d is computed by the five-pass sequence in which A^T starts from d's
-small-grid spectra as the forward class pass produced them.  The rate of the two separate
-calls (six passes) is reported beside it.  The JSON line reports A+A^T
+HBM and x = A^T d is computed by the four-pass sequence the solver's updates run, in
+which one class pass does the forward and adjoint spectral products of its alias
+classes.  The rate of the two separate calls (six passes) is reported beside it.  The JSON line reports A+A^T
 applications per second, the HBM roofline of the dominant kernel (measured with
 HIP events around its launches), the FP64 CPU oracle timed on a bounded sample of
 the same workload, and the time to reconstruct at r_k <= 1e-4 with the plain solver.
@@ -51,10 +51,13 @@ def log(msg):
 
 def algorithmic_bytes(w, compact=True, ncomp=1):
     """Per-application algorithmic bytes of A (and of A^T, the same total):
-    4N (rho) + 4CN (b) + beta_H C K N_c (spectra) + 4 K M (portraits), and of the
-    dominant spectral kernel: beta_H C K N_c + 8 C N_c (yz spectra in) + 8 K M_c
-    (decimated spectra out), N_c = nx ny (nz/2+1), M_c = mx my (mz/2+1), C the
-    components of the vector model (1 for the scalar model)."""
+    4N (rho) + 4CN (b) + beta_H C K N_c (spectra) + 4 K M (portraits); of one
+    separate class pass: beta_H C K N_c + 8 C N_c (yz spectra in) + 8 K M_c
+    (decimated spectra out); and of the fused class pass (forward and adjoint in one):
+    beta_H C K N_c (spectra, read once) + 16 C N_c (yz spectra in and out) + 8 K M_c
+    (decimated spectra out, or the data's in for the solver's residual).
+    N_c = nx ny (nz/2+1), M_c = mx my (mz/2+1), C the components of the vector model
+    (1 for the scalar model)."""
     nx, ny, nz = w.shape
     mx, my, mz = w.small_shape
     K = len(w.harmonics)
@@ -66,7 +69,20 @@ def algorithmic_bytes(w, compact=True, ncomp=1):
     C = ncomp
     op = 4 * N + 4 * C * N + bh * C * K * Nc + 4 * K * M
     spectral = bh * C * K * Nc + 8 * C * Nc + 8 * K * Mc
-    return op, spectral
+    fused = bh * C * K * Nc + 16 * C * Nc + 8 * K * Mc
+    return op, spectral, fused
+
+
+def class_roofline(pass_us, w, compact=True, ncomp=1):
+    """The dominant class kernel of the A+A^T step: the fused class pass where the plan
+    runs one, else the average of the forward and adjoint class passes.  Returns
+    (kernel label, algorithmic bytes per launch, seconds per launch)."""
+    _, spectral, fused = algorithmic_bytes(w, compact, ncomp)
+    if "class_normal" in pass_us:
+        return "class_normal (forward + adjoint spectral products and alias folds)", fused, \
+            pass_us["class_normal"] * 1e-6
+    return "class_fwd+class_adj (spectral multiply + alias fold)", spectral, \
+        0.5 * (pass_us["class_fwd"] + pass_us["class_adj"]) * 1e-6
 
 
 def cpu_baseline(w, rho, r, plan=None, budget_s=12.0):
@@ -236,11 +252,11 @@ def vector_leg(w, steps, warmup, tile_cache=None):
             plan.forward_adjoint(rho, d_out=y, x_out=x)
         torch.cuda.synchronize()
         rate = steps / (time.perf_counter() - t0)
-        pass_us = {k: plan.time_pass(k, reps=100) for k in mh3d.Plan.PASSES}
-        _, spec = algorithmic_bytes(w, compact=False, ncomp=C)
-        avg_s = 0.5 * (pass_us["class_fwd"] + pass_us["class_adj"]) * 1e-6
+        pass_us = plan.time_passes(reps=100)
+        kern, spec, avg_s = class_roofline(pass_us, w, compact=False, ncomp=C)
         out["C%d" % C] = {"applications_per_s": round(rate, 2), "tiles": list(tiles),
                           "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
+                          "class_kernel": kern.split(" ")[0],
                           "class_bytes_per_launch": spec, "class_GBps": round(spec / avg_s / 1e9, 1)}
         log("vector C=%d: %.1f A+A^T/s, tiles %s" % (C, rate, tiles))
         plan.close()
@@ -293,7 +309,7 @@ def mh2d_leg(steps, warmup, tile_cache=None):
            "decimation": list(w.ds), "lambda": w.lam, "tiles": list(tiles),
            "inputs": "inputs.scan_psfs / vector_sensitivity / spiral_phantom_2d (seeded synthetic)",
            "applications_per_s": round(rate, 2),
-           "kernels_us": {k: round(plan.time_pass(k, reps=100), 3) for k in mh3d.Plan.PASSES},
+           "kernels_us": {k: round(v, 3) for k, v in plan.time_passes(reps=100).items()},
            "time_to_recon": {"plain_s": round(first_s, 4), "plain_cached_step_s": round(cached_s, 4),
                              "iters": info["iters"], "rel_step": info["rel_step"],
                              "ms_per_iter": round(info2["ms_per_iter"], 4), "status": info["status"],
@@ -326,16 +342,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload_name, tiles):
-    """HBM bytes per class-kernel launch from the committed counter summary, if it was
-    taken on the current kernel sources, workload and tiles (else None)."""
+def stored_traffic(workload_name, tiles, kernel):
+    """HBM bytes per launch of the named class kernel from the committed counter
+    summary, if it was taken on the current kernel sources, workload and tiles (else
+    None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             for line in f:
                 if line.startswith("traffic-json: "):
                     t = json.loads(line[len("traffic-json: "):])
                     if (t["source_hash"] == kernel_source_hash() and t["workload"] == workload_name
-                            and list(t["tiles"]) == list(tiles)):
+                            and list(t["tiles"]) == list(tiles) and t["kernel"] == kernel):
                         return t
     except (OSError, ValueError, KeyError):
         pass
@@ -343,8 +360,9 @@ def stored_traffic(workload_name, tiles):
 
 
 def pmc_driver(args):
-    """Counter-run driver: tuned plan of the workload, 20 A+A^T steps, then a 256 MiB
-    device copy (the calibration kernel of known size)."""
+    """Counter-run driver: tuned plan of the workload, 20 A+A^T steps as the bench times
+    them (four passes, the fused class pass) and 20 as separate forward and adjoint calls
+    (six passes), then a 256 MiB device copy (the calibration kernel of known size)."""
     import torch
     from paper_2503_13802_amd import inputs, mh3d
     w = inputs.workload(args.workload)
@@ -356,6 +374,7 @@ def pmc_driver(args):
     y = torch.empty((len(w.harmonics),) + w.small_shape, device=dev)
     x = torch.empty(w.shape, device=dev)
     for _ in range(20):
+        plan.forward_adjoint(src, d_out=y, x_out=x)
         plan.forward(src, out=y)
         plan.adjoint(y, out=x)
     a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -363,7 +382,8 @@ def pmc_driver(args):
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    print("pmc driver: %s tiles %s, 20 A+A^T steps, 5 copies of 256 MiB" % (w.name, plan.tiles()), flush=True)
+    print("pmc driver: %s tiles %s, 20 fused and 20 separate A+A^T steps, 5 copies of 256 MiB"
+          % (w.name, plan.tiles()), flush=True)
 
 
 def main():
@@ -473,14 +493,14 @@ def main():
     wall_prof = time.perf_counter() - t0
     prof = plan.profile_read()
     plan.profile(False)
-    op_bytes, spec_bytes = algorithmic_bytes(w)
-    # the dominant kernels' launch duration: back-to-back launches between two HIP
+    op_bytes = algorithmic_bytes(w)[0]
+    # the dominant kernel's launch duration: back-to-back launches between two HIP
     # events on the plan's stream (per-launch events would add their own overhead)
-    pass_us = {k: plan.time_pass(k, reps=200) for k in mh3d.Plan.PASSES}
-    avg_s = 0.5 * (pass_us["class_fwd"] + pass_us["class_adj"]) * 1e-6
+    pass_us = plan.time_passes(reps=200)
+    kern, spec_bytes, avg_s = class_roofline(pass_us, w)
     achieved = spec_bytes / avg_s / 1e9
     kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in prof.items() if v[1]}
-    st = stored_traffic(w.name, plan.tiles())
+    st = stored_traffic(w.name, plan.tiles(), kern.split(" ")[0])
     traffic = None if st is None else st["bytes_per_launch"]
     log("kernels: " + json.dumps(kernels))
 
@@ -499,7 +519,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.shape), "harmonics": list(w.harmonics),
                    "decimation": list(w.ds), "a_per_mm": w.a_per_mm, "lambda": w.lam},
-        "roofline": {"bound": "hbm", "kernel": "class_fwd+class_adj (spectral multiply + alias fold)",
+        "roofline": {"bound": "hbm", "kernel": kern,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": spec_bytes, "avg_launch_us": round(avg_s * 1e6, 3)},

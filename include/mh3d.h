@@ -138,11 +138,13 @@ mh3d_status mh3d_forward(mh3d_plan_t plan, const float* rho, float* d);
 /* rho = A^T d (adjoint of eq. dN).  d: portraits, rho: volume. */
 mh3d_status mh3d_adjoint(mh3d_plan_t plan, const float* d, float* rho);
 
-/* d = A rho and x = A^T d in one sequence of five passes.  d is bitwise mh3d_forward's.
- * Without boundary padding A^T starts from d's small-grid spectra as the forward class
- * pass produced them (transforming d back would only reproduce them up to rounding), so
- * x equals mh3d_adjoint(d) up to that rounding; with padding the pass that writes d
- * also transforms its field-of-view crop back, bitwise as mh3d_adjoint(d). */
+/* d = A rho and x = A^T d in one sequence of passes.  d is bitwise mh3d_forward's.
+ * Without boundary padding A^T starts from the decimated spectra of d that the forward
+ * pass produced (transforming d back would only reproduce them up to rounding), so x
+ * equals mh3d_adjoint(d) up to that rounding: scalar plans run the forward and adjoint
+ * class passes as one workgroup pass (four passes in all), vector plans start the
+ * adjoint class pass from d's small-grid spectra (five).  With padding the pass that
+ * writes d also transforms its field-of-view crop back, bitwise as mh3d_adjoint(d). */
 mh3d_status mh3d_forward_adjoint(mh3d_plan_t plan, const float* rho, float* d, float* x);
 
 /* Per-harmonic back-projections c_k = b (H_k^T P^T d_k), the terms of A^T d before
@@ -196,7 +198,7 @@ typedef struct {
  * fit, or if the plan belongs to a batch.  Synchronous. */
 mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
 mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
-/* Autotuner: times one A + A^T application (HIP events) for candidate class tiles
+/* Autotuner: times one A + A^T application (mh3d_forward_adjoint, HIP events) for candidate class tiles
  * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for the
  * small-grid xb with the best class tiles, then for ps, and leaves the fastest on
  * the plan.
@@ -290,7 +292,7 @@ mh3d_status mh3d_plan_export(mh3d_plan_t plan, mh3d_field field, void* dst, size
 /* Per-kernel timing with HIP events around every launch of the plan's kernels
  * (enable = 1 starts and clears, 0 stops).  mh3d_profile_read synchronises and
  * returns the cumulative milliseconds and launch counts per kernel id, plus names. */
-#define MH3D_NKERNEL 9
+#define MH3D_NKERNEL 10
 typedef struct {
   double ms[MH3D_NKERNEL];
   int64_t launches[MH3D_NKERNEL];
@@ -299,9 +301,12 @@ typedef struct {
 mh3d_status mh3d_profile(mh3d_plan_t plan, int32_t enable);
 mh3d_status mh3d_profile_read(mh3d_plan_t plan, mh3d_profile_data* out);
 /* Average microseconds per launch of one pass (0 plane_fwd, 1 class_fwd, 2 small_inv,
- * 3 small_fwd, 4 class_adj, 5 plane_adj) over reps back-to-back launches between two
- * HIP events on the plan's stream, after one A and A^T to set its inputs.  Overwrites
- * the plan's solver volumes; profiling must be off; synchronous. */
+ * 3 small_fwd, 4 class_adj, 5 plane_adj, 6 class_normal: the forward and adjoint class
+ * passes in one, as mh3d_forward_adjoint runs them; MH3D_ERR_UNSUPPORTED for plans of
+ * the vector model or with boundary padding, which keep them apart) over reps
+ * back-to-back launches between two HIP events on the plan's stream, after one A and
+ * A^T to set its inputs.  Overwrites the plan's solver volumes; profiling must be off;
+ * synchronous. */
 mh3d_status mh3d_time_pass(mh3d_plan_t plan, int32_t pass, int32_t reps, double* us);
 
 /* One Philox4x32-10 block computed on the device (known-answer checks of the

@@ -667,6 +667,209 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
   }
 }
 
+// Forward and adjoint class passes in one (scalar model, no boundary padding), for the
+// solver's updates, the normal operator and A then A^T.  The folded spectra Fhat_k of
+// the block's classes (class_fwd_body's F0, before its inverse x' transform) stay in
+// LDS, and the adjoint starts from them: the inverse x' transform, the small-grid
+// inverse and forward transforms and the forward x' transform between the two passes
+// compose to multiplication by M = mx my mz (up to rounding), so the adjoint's decimated
+// spectra are
+//   NRM_RESID  R_k = M Fhat_k - Dt_k, Dt = the x' transform of the measured portraits'
+//              small-grid spectra (k_class_data, in G' as [k][class][qx'])
+//   NRM_PLAIN  R_k = M Fhat_k                       (normal operator)
+//   NRM_STORE  R_k = M Fhat_k, and G = the inverse x' transform of Fhat (the small-grid
+//              pass turns it into the portraits)
+// Each spectrum Hhat_k is read from HBM once: with K at most the prefetch ring's depth the
+// ring still holds all of them for the adjoint, else the adjoint's second read is of the
+// block's own recently read spectra (L2).
+enum { NRM_RESID = 0, NRM_PLAIN = 1, NRM_STORE = 2 };
+
+template <int HC, int E>
+__device__ __forceinline__ void class_normal_body(const VolDesc& vd, int lb, int mode) {
+  constexpr int HPF = hpf_of(HC, E);
+  const Geo& g = vd.g;
+  extern __shared__ float2 lds[];
+  const int W = g.cpw * g.nmem;
+  float2* twx = lds;
+  float2* twm = twx + g.nx;
+  float2* U0 = twm + g.mx;
+  float2* U1 = U0 + W * g.lsx;
+  float2* F0 = U1 + W * g.lsx;
+  float2* F1 = F0 + g.K * g.cpw * g.mx;
+  const int c0 = lb * g.cpw;
+  const bool act = (int)threadIdx.x < vd.T_class;
+  const int e0 = act ? (int)threadIdx.x * E : 0;
+  const int per_cls = g.mx * g.S;
+  const int cl = (int)g.f_mxS.div((uint32_t)e0);
+  const int rem = e0 - cl * per_cls;
+  const int qxp = (int)g.f_S.div((uint32_t)rem);
+  const int within = rem - qxp * g.S;
+  const long long hoff0 = (long long)c0 * per_cls + e0;
+  const void* hs = vd.hs;
+  const int LG = g.S / E;
+  const uint32_t imag_mask = vd.imag_mask;
+  const int KCM = g.K * g.cpw * g.mx;
+  HLoad<HC, E> hb[HPF];
+#pragma unroll
+  for (int i = 0; i < HPF; ++i)
+    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  // the data term of the block's classes (F1[(k cpw + c) mx + qx'])
+  if (mode == NRM_RESID) {
+    const float2* __restrict__ Dt = vd.Gp;
+    batched<8, float2>(KCM,
+                       [&](int p) {
+                         const int k = (int)g.f_cpwmx.div((uint32_t)p), r = p - k * g.cpw * g.mx;
+                         const int c = r / g.mx, q = r - c * g.mx;
+                         return Dt[((long long)k * g.ncls + c0 + c) * g.mx + q];
+                       },
+                       [&](int p, float2 v) { F1[p] = v; });
+  }
+  load_table(twx, vd.tw + vd.off[0], g.nx);
+  load_table(twm, vd.tw + vd.off[3], g.mx);
+  const float2* __restrict__ uperm = vd.uperm;
+  batched<8, float2>(g.nx * W,
+                     [&](int p) {
+                       const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+                       return uperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e];
+                     },
+                     [&](int p, float2 v) {
+                       const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+                       U0[e * g.lsx + xx] = v;
+                     });
+  const float2* U = fft_lines<-1>(U0, U1, twx, g.nx, W, g.lsx);
+  float2 ur[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int w = within + i;
+    const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
+    ur[i] = act ? U[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] : make_float2(0.f, 0.f);
+  }
+  // forward: Fhat_k(cl, qx') = sum over the S alias members of Hhat_k U
+  for (int k0 = 0; k0 < g.K; k0 += HPF) {
+#pragma unroll
+    for (int i = 0; i < HPF; ++i) {
+      const int k = k0 + i;
+      if (k < g.K) {
+        float2 acc = make_float2(0.f, 0.f);
+        if (act) {
+          if constexpr (HC == 0) {
+#pragma unroll
+            for (int t = 0; t < E; ++t) { acc.x += hb[i].v[t] * ur[t].x; acc.y += hb[i].v[t] * ur[t].y; }
+            if ((imag_mask >> k) & 1u) acc = make_float2(-acc.y, acc.x);
+          } else {
+#pragma unroll
+            for (int t = 0; t < E; ++t) acc = cadd(acc, cmul(hb[i].v[t], ur[t]));
+          }
+          if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
+        }
+        for (int o = LG >> 1; o >= 1; o >>= 1) {
+          acc.x += __shfl_xor(acc.x, o, 64);
+          acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (act && (threadIdx.x & (LG - 1)) == 0) F0[(k * g.cpw + cl) * g.mx + qxp] = acc;
+      }
+    }
+  }
+  __syncthreads();   // Fhat complete; U0/U1 free for the adjoint
+  // adjoint: sum_k conj(Hhat_k) R_k for each alias member, then the inverse x transform.
+  // With K <= HPF the ring still holds every harmonic's spectra.
+  if (g.K > HPF) {
+#pragma unroll
+    for (int i = 0; i < HPF; ++i)
+      if (act) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  }
+  const float Mf = (float)g.M;
+  float2 acc[E];
+#pragma unroll
+  for (int t = 0; t < E; ++t) acc[t] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < g.K; k0 += HPF) {
+#pragma unroll
+    for (int i = 0; i < HPF; ++i) {
+      const int k = k0 + i;
+      if (act && k < g.K) {
+        const int fi = (k * g.cpw + cl) * g.mx + qxp;
+        const float2 f = F0[fi];
+        float2 R = make_float2(Mf * f.x, Mf * f.y);
+        if (mode == NRM_RESID) R = csub(R, F1[fi]);
+        if constexpr (HC == 0) {
+          // conj(i h) R = -i h R
+          if ((imag_mask >> k) & 1u) R = make_float2(R.y, -R.x);
+#pragma unroll
+          for (int t = 0; t < E; ++t) { acc[t].x += hb[i].v[t] * R.x; acc[t].y += hb[i].v[t] * R.y; }
+        } else {
+#pragma unroll
+          for (int t = 0; t < E; ++t) acc[t] = cadd(acc[t], cmulcj(hb[i].v[t], R));
+        }
+        if (k + HPF < g.K) hb[i].load(hs, (long long)(k + HPF) * g.hsz + hoff0);
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int w = within + t;
+      const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
+      U0[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] = acc[t];
+    }
+  }
+  const float2* V = fft_lines<+1>(U0, U1, twx, g.nx, W, g.lsx);
+  float2* __restrict__ vperm = vd.uperm;
+  for (int p = threadIdx.x; p < g.nx * W; p += blockDim.x) {
+    const int xx = (int)g.f_W.div((uint32_t)p), e = p - xx * W;
+    vperm[(long long)xx * g.plane + (long long)c0 * g.nmem + e] = V[e * g.lsx + xx];
+  }
+  if (mode == NRM_STORE) {
+    // the portraits' small-grid spectra, as class_fwd_body writes them (F0 still holds
+    // Fhat: the adjoint only read it)
+    const float2* F = fft_lines<+1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
+    float2* __restrict__ G = vd.G;
+    for (int p = threadIdx.x; p < KCM; p += blockDim.x) {
+      int fo;
+      long long go;
+      class_g_index(g, p, c0, fo, go);
+      G[go] = F[fo];
+    }
+  }
+}
+
+// Dt = the x' transform of the measured portraits' small-grid spectra (G, as k_small_fwd
+// left them), into G' as [k][class][qx'], for class_normal_body's residual.  Same
+// blocks and LDS layout as the class passes.
+__global__ __launch_bounds__(1024) void k_class_data(const VolDesc* __restrict__ vds) {
+  const VolDesc& vd = vds[0];
+  const Geo& g = vd.g;
+  const int lb = blockIdx.x;
+  extern __shared__ float2 lds[];
+  const int W = g.cpw * g.nmem;
+  float2* twm = lds + g.nx;
+  float2* F0 = twm + g.mx + 2 * W * g.lsx;
+  float2* F1 = F0 + g.K * g.cpw * g.mx;
+  const int c0 = lb * g.cpw;
+  const int KCM = g.K * g.cpw * g.mx;
+  load_table(twm, vd.tw + vd.off[3], g.mx);
+  const float2* __restrict__ Dh = vd.G;
+  batched<8, float2>(KCM,
+                     [&](int p) {
+                       int fo;
+                       long long go;
+                       class_g_index(g, p, c0, fo, go);
+                       return Dh[go];
+                     },
+                     [&](int p, float2 v) {
+                       int fo;
+                       long long go;
+                       class_g_index(g, p, c0, fo, go);
+                       F0[fo] = v;
+                     });
+  const float2* F = fft_lines<-1>(F0, F1, twm, g.mx, g.K * g.cpw, g.mx);
+  float2* __restrict__ Dt = vd.Gp;
+  for (int p = threadIdx.x; p < KCM; p += blockDim.x) {
+    const int k = (int)g.f_cpwmx.div((uint32_t)p), r = p - k * g.cpw * g.mx;
+    const int c = r / g.mx, q = r - c * g.mx;
+    Dt[((long long)k * g.ncls + c0 + c) * g.mx + q] = F[p];
+  }
+}
+
 // Single-volume class passes, grid = ncls/cpw blocks of T_class threads.
 // check_done skips the launch once the volume's solve is done.
 // XCD-aware: consecutive class blocks run on one XCD, so the short runs of G, G' and
@@ -677,6 +880,13 @@ __global__ __launch_bounds__(1024) void k_class_fwd(const VolDesc* __restrict__ 
   const VolDesc& vd = vol_of(vds, nullptr, lb);
   if (check_done && vd.st->done) return;
   class_fwd_body<HC, E, VEC>(vd, plane_of_block(lb, gridDim.x), mode);
+}
+template <int HC, int E>
+__global__ __launch_bounds__(1024) void k_class_normal(const VolDesc* __restrict__ vds, int check_done, int mode) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, nullptr, lb);
+  if (check_done && vd.st->done) return;
+  class_normal_body<HC, E>(vd, plane_of_block(lb, gridDim.x), mode);
 }
 template <int HC, int E, bool VEC>
 __global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ vds, int check_done) {
@@ -698,15 +908,21 @@ __global__ __launch_bounds__(1024) void k_class_adj(const VolDesc* __restrict__ 
     case 9: BODY<0, 9>(vd, lb __VA_ARGS__); break;       \
     default: BODY<0, 1>(vd, lb __VA_ARGS__); break;      \
   }
-// mode: FWD_RESID (solver) or FWD_ADJ (power iteration) for volumes without padding,
-// FWD_G for padded ones (their small-grid pass crops to the field of view).
+// Padded volumes of a batch (mode FWD_G: their small-grid pass crops to the field of view).
 __global__ __launch_bounds__(1024) void k_class_fwd_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
                                                           int mode) {
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   if (vd.st->done) return;
-  const int m = vd.g.padded ? FWD_G : mode;
-  MH3D_E_SWITCH(class_fwd_body, , m)
+  MH3D_E_SWITCH(class_fwd_body, , mode)
+}
+// mode: NRM_RESID (solver) or NRM_PLAIN (power iteration); volumes without padding.
+__global__ __launch_bounds__(1024) void k_class_normal_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                             int mode) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  if (vd.st->done) return;
+  MH3D_E_SWITCH(class_normal_body, , mode)
 }
 __global__ __launch_bounds__(1024) void k_class_adj_batch(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks) {
   int lb;

@@ -242,9 +242,9 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
 
 // ============================================================================ plan
 enum { KID_PLANE_FWD = 0, KID_CLASS_FWD, KID_SMALL_INV, KID_SMALL_FWD, KID_CLASS_ADJ, KID_PLANE_ADJ, KID_AUX, KID_SOLVE_ITER,
-       KID_UPDATE };
+       KID_UPDATE, KID_CLASS_NORMAL };
 static const char* kKernelNames[MH3D_NKERNEL] = {"plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj",
-                                                  "plane_adj", "aux", "solve_iter", "vol_update"};
+                                                  "plane_adj", "aux", "solve_iter", "vol_update", "class_normal"};
 
 struct mh3d_plan_s {
   mh3d_plan_desc desc;
@@ -417,6 +417,22 @@ static mh3d_status launch_class_adj(mh3d_plan_t p, int chk, const VolDesc* vd = 
   const int mode = 0;
   if (p->compact) { E_DISPATCH(0, class_adj_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
   return last_launch("k_class_adj");
+}
+
+// Scalar plans without boundary padding run the forward and adjoint class passes of the
+// normal operator, the solver's updates and A then A^T as one (k_class_normal).
+static bool fused_class(mh3d_plan_t p) { return p->g.C == 1 && !p->g.padded; }
+
+template <int HC, int E>
+static void class_normal_t(mh3d_plan_t p, int chk, const VolDesc* vd, int mode) {
+  k_class_normal<HC, E><<<dim3(p->g.ncls / p->g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(vd, chk, mode);
+}
+// mode: NRM_RESID, NRM_PLAIN or NRM_STORE.
+static mh3d_status launch_class_normal(mh3d_plan_t p, int chk, int mode) {
+  Timer t(p, KID_CLASS_NORMAL);
+  const VolDesc* vd = p->vdd;
+  if (p->compact) { E_DISPATCH(0, class_normal_t) } else { E_DISPATCH(1, class_normal_t) }
+  return last_launch("k_class_normal");
 }
 
 static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d) {
@@ -744,14 +760,18 @@ extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, flo
   CHK(check_plan(p));
   if (!rho || !d || !x) return fail(MH3D_ERR_INVALID, "NULL array");
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
-  if (p->g.padded) {
+  if (fused_class(p)) {
+    CHK(launch_class_normal(p, 0, NRM_STORE));   // d's spectra and A^T's class pass
+    CHK(launch_small_inv(p, EPI_STORE, d));
+  } else if (p->g.padded) {
     CHK(launch_class_fwd(p, 0, FWD_G));
     CHK(launch_small_inv(p, EPI_STORE_BACK, d));   // stores d and starts A^T on its cropped copy
+    CHK(launch_class_adj(p, 0));
   } else {
     CHK(launch_class_fwd(p, 0, FWD_G_AND_ADJ));    // A^T starts from d's spectra
     CHK(launch_small_inv(p, EPI_STORE, d));
+    CHK(launch_class_adj(p, 0));
   }
-  CHK(launch_class_adj(p, 0));
   CHK(launch_plane_adj(p, OUT_SCALE_B, x, nullptr));
   return MH3D_OK;
 }
@@ -788,13 +808,17 @@ extern "C" mh3d_status mh3d_backproject(mh3d_plan_t p, const float* d, float* c)
 // out = (A^T A + lambda T^T T)(s w): s from the state (1/||w|| in power iteration).
 static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out) {
   CHK(launch_plane_fwd(p, SRC_SCALED, w));
-  if (p->g.padded) {
-    CHK(launch_class_fwd(p, 1, FWD_G));
-    CHK(launch_small_inv(p, EPI_BACK, nullptr));   // crop to the field of view
+  if (fused_class(p)) {
+    CHK(launch_class_normal(p, 1, NRM_PLAIN));
   } else {
-    CHK(launch_class_fwd(p, 1, FWD_ADJ));
+    if (p->g.padded) {
+      CHK(launch_class_fwd(p, 1, FWD_G));
+      CHK(launch_small_inv(p, EPI_BACK, nullptr));   // crop to the field of view
+    } else {
+      CHK(launch_class_fwd(p, 1, FWD_ADJ));
+    }
+    CHK(launch_class_adj(p, 1));
   }
-  CHK(launch_class_adj(p, 1));
   CHK(launch_adjoint_step(p, UPD_NORMAL, out, w));
   return MH3D_OK;
 }
@@ -854,13 +878,17 @@ extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64
 static mh3d_status enqueue_update(mh3d_plan_t p) {
   Timer t(p, KID_SOLVE_ITER);
   CHK(launch_plane_fwd(p, SRC_FISTA_Y, nullptr));
-  if (p->g.padded) {
-    CHK(launch_class_fwd(p, 1, FWD_G));
-    CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr));   // residual on the field of view
+  if (fused_class(p)) {
+    CHK(launch_class_normal(p, 1, NRM_RESID));   // against the data's spectra, held in G'
   } else {
-    CHK(launch_class_fwd(p, 1, FWD_RESID));   // residual spectrum against the data's, held in G
+    if (p->g.padded) {
+      CHK(launch_class_fwd(p, 1, FWD_G));
+      CHK(launch_small_inv(p, EPI_RESID_BACK, nullptr));   // residual on the field of view
+    } else {
+      CHK(launch_class_fwd(p, 1, FWD_RESID));   // residual spectrum against the data's, held in G
+    }
+    CHK(launch_class_adj(p, 1));
   }
-  CHK(launch_class_adj(p, 1));
   CHK(launch_adjoint_step(p, UPD_FISTA, nullptr, nullptr));
   return MH3D_OK;
 }
@@ -895,8 +923,14 @@ static mh3d_status solve_setup(mh3d_plan_t p, const float* d, const float* rho0,
   p->vdh.k_first = k0;
   CHK(upload_desc(p));
   // without padding the updates form the residual spectrum F(A y) - F(d): F(d) once,
-  // held in G for the whole solve
+  // held in G for the whole solve (the fused class pass takes it one x' transform
+  // further, into G')
   if (!g.padded) CHK(launch_small_fwd(p, d, p->G));
+  if (fused_class(p)) {
+    Timer t(p, KID_AUX);
+    k_class_data<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vdd);
+    CHK(last_launch("k_class_data"));
+  }
   DevState s0;
   memset(&s0, 0, sizeof s0);
   s0.k = k0;
@@ -1005,7 +1039,8 @@ struct mh3d_batch_s {
   hipStream_t stream;
   VolDesc* vds = nullptr;            // device descriptors of all volumes
   std::vector<VolDesc> hvd;          // their host copies (plane passes at one workgroup per plane)
-  int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // plane, class, small (padded volumes), -, per-volume
+  // plane, class (padded volumes), small (padded volumes), fused class (the others), per-volume
+  int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int ntask[5] = {0, 0, 0, 0, 0};
   int T_class = 0;
   size_t lds_plane = 0, lds_class = 0, lds_small = 0;
@@ -1060,8 +1095,9 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
     // one workgroup per x-plane: the batch already fills the chip with the planes of
     // many volumes, so splitting planes would only add work
     for (int i = 0; i < p->g.nx; ++i) t[0].push_back(make_int2(v, i));
-    push_xcd_grouped(t[1], v, p->g.ncls / p->g.cpw);
-    // the small-grid pass of the updates is needed only to crop to a field of view
+    // volumes without padding run their class passes as one; the small-grid pass of the
+    // updates is needed only to crop to a field of view
+    push_xcd_grouped(t[p->g.padded ? 1 : 3], v, p->g.ncls / p->g.cpw);
     if (p->g.padded)
       for (int i = 0; i < p->g.K * (p->g.mx / p->g.xb); ++i) t[2].push_back(make_int2(v, i));
     t[4].push_back(make_int2(v, 0));
@@ -1075,7 +1111,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
   b->hvd.resize(n);
   for (int i = 0; i < 5; ++i) {
     b->ntask[i] = (int)t[i].size();
-    if (t[i].empty()) continue;   // no small-grid tasks when no volume is padded
+    if (t[i].empty()) continue;   // e.g. no padded volume
     if (hipMalloc(&b->tasks[i], sizeof(int2) * t[i].size()) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch tasks"));
     if (hipMemcpy(b->tasks[i], t[i].data(), sizeof(int2) * t[i].size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(MH3D_ERR_HIP, "upload of batch tasks failed"));
@@ -1093,18 +1129,34 @@ static mh3d_status batch_upload(mh3d_batch_t b, int v) {
   return MH3D_OK;
 }
 
-// One update of every volume of the batch: five launches over the task tables.
+// The class passes of every volume: one fused launch for the volumes without padding,
+// then forward class pass, crop (small-grid pass) and adjoint class pass for the padded
+// ones.  mode: NRM_RESID (updates) or NRM_PLAIN (power iteration).
+static mh3d_status batch_class(mh3d_batch_t b, hipStream_t st, int mode) {
+  if (b->ntask[3]) {
+    k_class_normal_batch<<<dim3(b->ntask[3]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[3], mode);
+    CHK(last_launch("k_class_normal_batch"));
+  }
+  if (b->ntask[1]) {
+    k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1], FWD_G);
+    CHK(last_launch("k_class_fwd_batch"));
+    if (mode == NRM_RESID)
+      k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+    else
+      k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+    CHK(last_launch("k_small_inv (batch)"));
+    k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
+    CHK(last_launch("k_class_adj_batch"));
+  }
+  return MH3D_OK;
+}
+
+// One update of every volume of the batch: four launches over the task tables (six
+// when some volume is padded).
 static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
   k_plane_fwd<SRC_FISTA_Y><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
   CHK(last_launch("k_plane_fwd (batch)"));
-  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1], FWD_RESID);
-  CHK(last_launch("k_class_fwd_batch"));
-  if (b->ntask[2]) {
-    k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
-    CHK(last_launch("k_small_inv (batch)"));
-  }
-  k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
-  CHK(last_launch("k_class_adj_batch"));
+  CHK(batch_class(b, st, NRM_RESID));
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
@@ -1119,14 +1171,7 @@ static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
 static mh3d_status batch_power_step(mh3d_batch_t b, hipStream_t st) {
   k_plane_fwd<SRC_SCALED><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
   CHK(last_launch("k_plane_fwd (batch power)"));
-  k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1], FWD_ADJ);
-  CHK(last_launch("k_class_fwd_batch (power)"));
-  if (b->ntask[2]) {
-    k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
-    CHK(last_launch("k_small_inv (batch power)"));
-  }
-  k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
-  CHK(last_launch("k_class_adj_batch (power)"));
+  CHK(batch_class(b, st, NRM_PLAIN));
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
@@ -1347,7 +1392,9 @@ extern "C" mh3d_status mh3d_mhad(mh3d_plan_t p, const float* d, double lambda, c
 // ============================================================================ pass timing
 extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps, double* us) {
   CHK(check_plan(p));
-  if (pass < 0 || pass > 5 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");
+  if (pass < 0 || pass > 6 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");
+  if (pass == 6 && !fused_class(p))
+    return fail(MH3D_ERR_UNSUPPORTED, "the plan runs no fused class pass (vector model or boundary padding)");
   if (p->prof_on) return fail(MH3D_ERR_INVALID, "disable mh3d_profile before timing passes");
   float* dtmp = nullptr;
   HIPCHK(hipMalloc(&dtmp, sizeof(float) * (size_t)p->g.K * p->g.M));
@@ -1360,6 +1407,7 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
       case 2: return launch_small_inv(p, EPI_STORE, dtmp);
       case 3: return launch_small_fwd(p, dtmp);
       case 4: return launch_class_adj(p, 0);
+      case 6: return launch_class_normal(p, 0, NRM_STORE);
       default: return launch_plane_adj(p, OUT_SCALE_B, p->vol[1], nullptr);
     }
   };
@@ -1474,11 +1522,9 @@ static void tune_write(const char* path, const std::map<std::string, TuneEntry>&
 
 // Microseconds per A + A^T application with the plan's current tiles (HIP events,
 // best of two batches of 8 after 2 warm-up applications).
+// One A + A^T application as the solver's updates run it (mh3d_forward_adjoint).
 static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
-  for (int i = 0; i < 2; ++i) {
-    CHK(mh3d_forward(p, p->vol[0], dtmp));
-    CHK(mh3d_adjoint(p, dtmp, p->vol[1]));
-  }
+  for (int i = 0; i < 2; ++i) CHK(mh3d_forward_adjoint(p, p->vol[0], dtmp, p->vol[1]));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1486,10 +1532,7 @@ static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
   mh3d_status s = MH3D_OK;
   for (int r = 0; r < 2 && s == MH3D_OK; ++r) {
     (void)hipEventRecord(e0, p->stream);
-    for (int i = 0; i < 8 && s == MH3D_OK; ++i) {
-      s = mh3d_forward(p, p->vol[0], dtmp);
-      if (s == MH3D_OK) s = mh3d_adjoint(p, dtmp, p->vol[1]);
-    }
+    for (int i = 0; i < 8 && s == MH3D_OK; ++i) s = mh3d_forward_adjoint(p, p->vol[0], dtmp, p->vol[1]);
     (void)hipEventRecord(e1, p->stream);
     float ms = 0.f;
     if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)

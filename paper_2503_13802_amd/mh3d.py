@@ -17,7 +17,7 @@ HEADER = os.path.join(_ROOT, "include", "mh3d.h")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 FIELD_PROFILE, FIELD_ENVELOPE, FIELD_SENS, FIELD_SPECTRUM = range(4)
-NKERNEL = 9
+NKERNEL = 10
 
 
 class PlanDesc(ctypes.Structure):
@@ -283,7 +283,7 @@ class Plan:
         return out
 
     def forward_adjoint(self, rho, d_out=None, x_out=None):
-        """(A rho, A^T A rho) in one five-pass sequence."""
+        """(A rho, A^T A rho) in one sequence of passes (mh3d_forward_adjoint)."""
         rho = self._vol(rho)
         d = self.torch.empty((self.K,) + self.small, device=self.device) if d_out is None else d_out
         x = self.torch.empty(self.shape, device=self.device) if x_out is None else x_out
@@ -326,13 +326,25 @@ class Plan:
                "history": np.array(hist[:info.iters])}
         return rho, out
 
-    PASSES = ("plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj", "plane_adj")
+    PASSES = ("plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj", "plane_adj", "class_normal")
 
     def time_pass(self, name, reps=200):
         """Average microseconds per launch of one pass, back to back between two events."""
         us = ctypes.c_double()
         _check(library().mh3d_time_pass(self._h, self.PASSES.index(name), int(reps), ctypes.byref(us)))
         return us.value
+
+    def time_passes(self, reps=200):
+        """time_pass of every pass the plan runs: class_normal (the fused class pass) only
+        for scalar plans without boundary padding, which run it."""
+        out = {}
+        for name in self.PASSES:
+            try:
+                out[name] = self.time_pass(name, reps)
+            except MH3DError as e:
+                if e.status != ERR_UNSUPPORTED:
+                    raise
+        return out
 
     def tiles(self):
         """(E, cpw, xb, ps) tile shapes of the spectral and plane passes."""

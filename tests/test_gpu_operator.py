@@ -239,3 +239,28 @@ def test_forward_adjoint_fused_equals_separate_calls(shape, harm, ds, a, sig):
     b = om.sensitivity(shape, sig)
     want = om.adjoint_fft(h, b, om.forward_fft(h, b, x.cpu().numpy().astype(np.float64), ds), ds)
     assert rel_l2(x2.cpu().numpy(), want) <= TOL
+
+
+def test_fused_class_pass_is_the_one_that_runs():
+    """Scalar plans without padding run A then A^T and the normal operator with the fused
+    class pass (no separate class passes, no small-grid forward pass); padded plans keep
+    the separate passes, and their pass timer has no fused pass to time."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("fused class pass dispatch")
+    shape, harm, ds = (16, 12, 8), (2, 3), (2, 2, 2)
+    p = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3)
+    x = torch.tensor(inputs.random_field(shape, 3), dtype=torch.float32, device="cuda")
+    p.profile(True)
+    p.forward_adjoint(x)
+    p.normal(x)
+    prof = p.profile_read()
+    p.profile(False)
+    assert prof["class_normal"][1] == 2
+    assert prof["class_fwd"][1] == 0 and prof["class_adj"][1] == 0 and prof["small_fwd"][1] == 0
+    assert "class_normal" in p.time_passes(reps=3)
+    q = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3, pad=(2, 2, 2))
+    with pytest.raises(mh3d.MH3DError) as e:
+        q.time_pass("class_normal", 3)
+    assert e.value.status == mh3d.ERR_UNSUPPORTED
+    assert set(q.time_passes(reps=3)) == set(mh3d.Plan.PASSES) - {"class_normal"}
