@@ -141,10 +141,11 @@ mh3d_status mh3d_adjoint(mh3d_plan_t plan, const float* d, float* rho);
 /* d = A rho and x = A^T d in one sequence of passes.  d is bitwise mh3d_forward's.
  * Without boundary padding A^T starts from the decimated spectra of d that the forward
  * pass produced (transforming d back would only reproduce them up to rounding), so x
- * equals mh3d_adjoint(d) up to that rounding: scalar plans run the forward and adjoint
- * class passes as one workgroup pass (four passes in all), vector plans start the
- * adjoint class pass from d's small-grid spectra (five).  With padding the pass that
- * writes d also transforms its field-of-view crop back, bitwise as mh3d_adjoint(d). */
+ * equals mh3d_adjoint(d) up to that rounding.  Scalar plans run the forward and adjoint
+ * class passes as one workgroup pass and write d in the launch of the adjoint plane
+ * pass (three launches in all); vector plans start the adjoint class pass from d's
+ * small-grid spectra (five).  With padding the pass that writes d also transforms its
+ * field-of-view crop back, bitwise as mh3d_adjoint(d). */
 mh3d_status mh3d_forward_adjoint(mh3d_plan_t plan, const float* rho, float* d, float* x);
 
 /* Per-harmonic back-projections c_k = b (H_k^T P^T d_k), the terms of A^T d before
@@ -185,7 +186,8 @@ mh3d_status mh3d_solve(mh3d_plan_t plan, const float* d, float* rho_inout,
  * classes per workgroup in the class passes (E in {1, 2, 3, 4, 6, 8, 9} divides
  * S = ds0 ds1 ds2 with S/E a power of two <= 64; cpw divides the class count, at
  * most 1024 threads = cpw (nx/ds0) S / E), xb decimated x-planes per
- * workgroup in the small-grid passes (divides nx/ds0).  0 = built-in heuristic.
+ * workgroup in the small-grid passes (divides nx/ds0; 256 threads per x'-plane, at
+ * most 1024).  0 = built-in heuristic.
  * ps > 1 splits each x-plane over ps workgroups: all transform the whole plane along
  * its first axis, each takes a share of the second-axis transforms (at most
  * min(nz/2 + 1, (ny + 1)/2) workgroups).  Results do not depend on the tiles (only
@@ -199,11 +201,16 @@ typedef struct {
 mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
 mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
 /* Autotuner: times one A + A^T application (mh3d_forward_adjoint, HIP events) for candidate class tiles
- * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for the
- * small-grid xb with the best class tiles, then for ps, and leaves the fastest on
- * the plan.
+ * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for
+ * every pair of small-grid xb and plane split ps with the best class tiles, and leaves
+ * the fastest on the plan.  It then times the normal operator for ps = 1, 2, 4 and keeps
+ * the fastest as the plane split of the solver's passes (mh3d_normal,
+ * mh3d_power_iteration, mh3d_solve run no small-grid pass, so their best split can
+ * differ; mh3d_plan_set_tiles sets both splits to ps, and results do not depend on
+ * either).
  * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
- * kind"; a hit applies the stored tiles without timing, a miss stores the result.
+ * kind" with E, cpw, xb, ps, ps_solve (the solver's split) and us; a hit applies the
+ * stored tiles without timing, a miss stores the result.
  * tiles / us_per_application (HOST, may be NULL) receive the choice and its time.
  * Overwrites the plan's solver volumes; synchronous. */
 mh3d_status mh3d_autotune(mh3d_plan_t plan, const char* cache_path, mh3d_tiles* tiles, double* us_per_application);
@@ -292,7 +299,7 @@ mh3d_status mh3d_plan_export(mh3d_plan_t plan, mh3d_field field, void* dst, size
 /* Per-kernel timing with HIP events around every launch of the plan's kernels
  * (enable = 1 starts and clears, 0 stops).  mh3d_profile_read synchronises and
  * returns the cumulative milliseconds and launch counts per kernel id, plus names. */
-#define MH3D_NKERNEL 10
+#define MH3D_NKERNEL 11
 typedef struct {
   double ms[MH3D_NKERNEL];
   int64_t launches[MH3D_NKERNEL];
@@ -302,8 +309,10 @@ mh3d_status mh3d_profile(mh3d_plan_t plan, int32_t enable);
 mh3d_status mh3d_profile_read(mh3d_plan_t plan, mh3d_profile_data* out);
 /* Average microseconds per launch of one pass (0 plane_fwd, 1 class_fwd, 2 small_inv,
  * 3 small_fwd, 4 class_adj, 5 plane_adj, 6 class_normal: the forward and adjoint class
- * passes in one, as mh3d_forward_adjoint runs them; MH3D_ERR_UNSUPPORTED for plans of
- * the vector model or with boundary padding, which keep them apart) over reps
+ * passes in one, 7 adj_and_store: the adjoint plane pass and the small-grid inverse pass
+ * in one launch, both as mh3d_forward_adjoint runs them; 6 and 7 give
+ * MH3D_ERR_UNSUPPORTED for plans of the vector model or with boundary padding, which
+ * keep the passes apart) over reps
  * back-to-back launches between two HIP events on the plan's stream, after one A and
  * A^T to set its inputs.  Overwrites the plan's solver volumes; profiling must be off;
  * synchronous. */

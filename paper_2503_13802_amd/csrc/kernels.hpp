@@ -976,10 +976,7 @@ __device__ __forceinline__ long long fov_index(const Geo& g, int k, int xbi, int
 // the result).  One block per (k, x'-block).  EPI_RESID_BACK uses the volume's data
 // and is skipped once its solve is done.  LDS: tables (my + mz) + 2 * small_lds.
 template <int EPI>
-__global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
-                                                    float* __restrict__ d) {
-  int lb;
-  const VolDesc& vd = vol_of(vds, tasks, lb);
+__device__ __forceinline__ void small_inv_body(const VolDesc& vd, int lb, float* __restrict__ d) {
   const Geo& g = vd.g;
   if constexpr (EPI == EPI_RESID_BACK || EPI == EPI_BACK) {
     if (vd.st->done) return;
@@ -1055,6 +1052,13 @@ __global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ 
     }
     small_r2c_and_store(g, Z, Z == P0 ? P1 : P0, twy, twz, vd.Gp, k, xbi);
   }
+}
+template <int EPI>
+__global__ __launch_bounds__(1024) void k_small_inv(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    float* __restrict__ d) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  small_inv_body<EPI>(vd, lb, d);
 }
 
 // Adjoint pass 3: R2C of the portraits r.  One block per (k, x'-block).
@@ -1275,12 +1279,9 @@ __device__ __forceinline__ bool grid_reduce_last(double* v, double* partials, De
 //   OUT_STEP_NORMAL  the step itself on the block's voxels with u = b . v (StepCtx),
 //   OUT_STEP_FISTA   its FP64 sums in vd.partials[lb] for k_vol_finish (scalar model:
 //                    one component)
-// grid = ps * nx blocks (ps per x-plane).
+// grid = ps * nx blocks (ps per x-plane); lb = the block's index among them.
 template <int OUT>
-__global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
-                                                    AdjOut ao) {
-  int lb;
-  const VolDesc& vd = vol_of(vds, tasks, lb);
+__device__ __forceinline__ void plane_adj_body(const VolDesc& vd, int lb, const AdjOut& ao) {
   const Geo& g = vd.g;
   constexpr bool kStep = (OUT == OUT_STEP_NORMAL || OUT == OUT_STEP_FISTA);
   if constexpr (OUT == OUT_U || kStep) {
@@ -1364,6 +1365,25 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
                       [&](int p, float bv) { out[pbase + p] += bv * Xf[vidx(p + y0 * g.nz)]; });
   }
   }
+}
+template <int OUT>
+__global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    AdjOut ao) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  plane_adj_body<OUT>(vd, lb, ao);
+}
+
+// The two passes after the fused class pass in A then A^T, in one launch: both read only
+// what that pass wrote, so blocks [0, ps nx) run the adjoint plane pass (ao.out = b . v)
+// while the others run the small-grid inverse pass that writes the portraits d.  The
+// plane blocks come first (their XCD-aware plane order assumes block ids 0 .. ps nx - 1);
+// the small-grid blocks fill the CUs the plane blocks leave free.  blockDim = 1024.
+__global__ __launch_bounds__(1024) void k_adj_and_store(const VolDesc* __restrict__ vds, AdjOut ao, float* __restrict__ d) {
+  const VolDesc& vd = vds[0];
+  const int nplane = vd.g.ps * vd.g.nx;
+  if ((int)blockIdx.x < nplane) plane_adj_body<OUT_SCALE_B>(vd, blockIdx.x, ao);
+  else small_inv_body<EPI_STORE>(vd, blockIdx.x - nplane, d);
 }
 
 // Blocks of the volume-wide update pass, each a contiguous run of whole UPD_THREADS-voxel

@@ -144,7 +144,9 @@ static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int x
   g.f_W = make_fastdiv(g.cpw * g.nmem); g.f_xb = make_fastdiv(g.xb); g.f_S = make_fastdiv(g.S);
   g.f_mxS = make_fastdiv(g.mx * g.S); g.f_cpwmx = make_fastdiv(g.cpw * g.mx);
   g.f_cpwxb = make_fastdiv(g.cpw * g.xb); g.f_ny = make_fastdiv(g.ny); g.f_my = make_fastdiv(g.my);
-  L.T_small = 256;
+  // 256 threads per decimated x'-plane of the block (the small-grid kernels loop over
+  // blockDim, so the count only sets how much of the block's work runs side by side)
+  L.T_small = std::min(1024, 256 * g.xb);
   L.lds_small = sizeof(float2) * ((size_t)g.my + g.mz + 2 * (size_t)small_lds(g));
   if (L.lds_small > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "small-grid plane does not fit in LDS");
   return MH3D_OK;
@@ -242,9 +244,10 @@ static mh3d_status build_geo(const mh3d_plan_desc* d, Geo& g, Launch& L, const m
 
 // ============================================================================ plan
 enum { KID_PLANE_FWD = 0, KID_CLASS_FWD, KID_SMALL_INV, KID_SMALL_FWD, KID_CLASS_ADJ, KID_PLANE_ADJ, KID_AUX, KID_SOLVE_ITER,
-       KID_UPDATE, KID_CLASS_NORMAL };
+       KID_UPDATE, KID_CLASS_NORMAL, KID_ADJ_AND_STORE };
 static const char* kKernelNames[MH3D_NKERNEL] = {"plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj",
-                                                  "plane_adj", "aux", "solve_iter", "vol_update", "class_normal"};
+                                                  "plane_adj", "aux", "solve_iter", "vol_update", "class_normal",
+                                                  "adj_and_store"};
 
 struct mh3d_plan_s {
   mh3d_plan_desc desc;
@@ -273,7 +276,14 @@ struct mh3d_plan_s {
   int hist_cap = 0;
   DevState* st = nullptr;      // solver / power state
   VolDesc vdh;                 // host copy of the descriptor
-  VolDesc* vdd = nullptr;      // device descriptor
+  // device descriptors: [0] for the operator calls, [1] for the solver's passes
+  // (mh3d_normal, mh3d_power_iteration, mh3d_solve), which split each x-plane over
+  // ps_solve workgroups; vdu holds what was last uploaded
+  VolDesc* vdd = nullptr;
+  VolDesc vdu[2];
+  int ps_solve = 0;
+  VolDesc* vda = nullptr;      // the descriptor the current call's passes use, and its split
+  int psa = 0;
   VolDesc* vdk = nullptr;      // device descriptors of the single harmonics (K of them)
   int batch_refs = 0;          // batches holding this plan (tiles are frozen while > 0)
   int pi_iters = 0;            // cached step-size estimate: power iterations (0: none), seed, L
@@ -368,13 +378,13 @@ static mh3d_status last_launch(const char* what) {
 static mh3d_status launch_plane_fwd(mh3d_plan_t p, int src, const float* a) {
   Timer t(p, KID_PLANE_FWD);
   // vector model: one group of ps * nx blocks per component (a raw source has one)
-  dim3 grid((src == SRC_RAW ? 1 : p->g.C) * p->g.ps * p->g.nx), block(p->L.T_plane);
+  dim3 grid((src == SRC_RAW ? 1 : p->g.C) * p->psa * p->g.nx), block(p->L.T_plane);
   const size_t lds = p->L.lds_plane;
   switch (src) {
-    case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
-    case SRC_RAW: k_plane_fwd<SRC_RAW><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
-    case SRC_FISTA_Y: k_plane_fwd<SRC_FISTA_Y><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
-    default: k_plane_fwd<SRC_SCALED><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, a); break;
+    case SRC_PLAIN: k_plane_fwd<SRC_PLAIN><<<grid, block, lds, p->ls>>>(p->vda, nullptr, a); break;
+    case SRC_RAW: k_plane_fwd<SRC_RAW><<<grid, block, lds, p->ls>>>(p->vda, nullptr, a); break;
+    case SRC_FISTA_Y: k_plane_fwd<SRC_FISTA_Y><<<grid, block, lds, p->ls>>>(p->vda, nullptr, a); break;
+    default: k_plane_fwd<SRC_SCALED><<<grid, block, lds, p->ls>>>(p->vda, nullptr, a); break;
   }
   return last_launch("k_plane_fwd");
 }
@@ -406,14 +416,14 @@ static void class_adj_t(mh3d_plan_t p, int chk, const VolDesc* vd, int) {
 // mode: FWD_G, FWD_ADJ, FWD_G_AND_ADJ or FWD_RESID (where the decimated spectra go).
 static mh3d_status launch_class_fwd(mh3d_plan_t p, int chk, int mode) {
   Timer t(p, KID_CLASS_FWD);
-  const VolDesc* vd = p->vdd;
+  const VolDesc* vd = p->vda;
   if (p->compact) { E_DISPATCH(0, class_fwd_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_fwd_t) } else { E_DISPATCH(1, class_fwd_t) }
   return last_launch("k_class_fwd");
 }
 // vd: a single-harmonic descriptor (per-harmonic back-projection) or NULL for the plan's.
 static mh3d_status launch_class_adj(mh3d_plan_t p, int chk, const VolDesc* vd = nullptr) {
   Timer t(p, KID_CLASS_ADJ);
-  if (!vd) vd = p->vdd;
+  if (!vd) vd = p->vda;
   const int mode = 0;
   if (p->compact) { E_DISPATCH(0, class_adj_t) } else if (p->g.C > 1) { E_DISPATCH(2, class_adj_t) } else { E_DISPATCH(1, class_adj_t) }
   return last_launch("k_class_adj");
@@ -430,7 +440,7 @@ static void class_normal_t(mh3d_plan_t p, int chk, const VolDesc* vd, int mode) 
 // mode: NRM_RESID, NRM_PLAIN or NRM_STORE.
 static mh3d_status launch_class_normal(mh3d_plan_t p, int chk, int mode) {
   Timer t(p, KID_CLASS_NORMAL);
-  const VolDesc* vd = p->vdd;
+  const VolDesc* vd = p->vda;
   if (p->compact) { E_DISPATCH(0, class_normal_t) } else { E_DISPATCH(1, class_normal_t) }
   return last_launch("k_class_normal");
 }
@@ -440,10 +450,10 @@ static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d) {
   dim3 grid(p->g.K * (p->g.mx / p->g.xb)), block(p->L.T_small);
   const size_t lds = p->L.lds_small;
   switch (epi) {
-    case EPI_STORE: k_small_inv<EPI_STORE><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
-    case EPI_RESID_BACK: k_small_inv<EPI_RESID_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
-    case EPI_STORE_BACK: k_small_inv<EPI_STORE_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
-    default: k_small_inv<EPI_BACK><<<grid, block, lds, p->ls>>>(p->vdd, nullptr, d); break;
+    case EPI_STORE: k_small_inv<EPI_STORE><<<grid, block, lds, p->ls>>>(p->vda, nullptr, d); break;
+    case EPI_RESID_BACK: k_small_inv<EPI_RESID_BACK><<<grid, block, lds, p->ls>>>(p->vda, nullptr, d); break;
+    case EPI_STORE_BACK: k_small_inv<EPI_STORE_BACK><<<grid, block, lds, p->ls>>>(p->vda, nullptr, d); break;
+    default: k_small_inv<EPI_BACK><<<grid, block, lds, p->ls>>>(p->vda, nullptr, d); break;
   }
   return last_launch("k_small_inv");
 }
@@ -451,15 +461,15 @@ static mh3d_status launch_small_inv(mh3d_plan_t p, int epi, float* d) {
 // out: destination of the spectra (NULL: G', the adjoint's input).
 static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r, float2* out = nullptr) {
   Timer t(p, KID_SMALL_FWD);
-  k_small_fwd<<<dim3(p->g.K * (p->g.mx / p->g.xb)), dim3(p->L.T_small), p->L.lds_small, p->ls>>>(p->vdd, r, out);
+  k_small_fwd<<<dim3(p->g.K * (p->g.mx / p->g.xb)), dim3(p->L.T_small), p->L.lds_small, p->ls>>>(p->vda, r, out);
   return last_launch("k_small_fwd");
 }
 
 static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const float* yin,
                                     const VolDesc* vd = nullptr) {
   Timer t(p, KID_PLANE_ADJ);
-  if (!vd) vd = p->vdd;
-  dim3 grid(p->g.ps * p->g.nx), block(p->L.T_plane);
+  if (!vd) vd = p->vda;
+  dim3 grid(p->psa * p->g.nx), block(p->L.T_plane);
   const size_t lds = p->L.lds_plane;
   AdjOut ao;
   ao.out = o;
@@ -471,6 +481,18 @@ static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const floa
     default: k_plane_adj<OUT_U><<<grid, block, lds, p->ls>>>(vd, nullptr, ao); break;
   }
   return last_launch("k_plane_adj");
+}
+
+// After the fused class pass of A then A^T: the adjoint plane pass (x = A^T d) and the
+// small-grid inverse pass that writes d, as one launch of ps nx + K mx/xb blocks.
+static mh3d_status launch_adj_and_store(mh3d_plan_t p, float* d, float* x) {
+  Timer t(p, KID_ADJ_AND_STORE);
+  AdjOut ao;
+  ao.out = x;
+  ao.yin = nullptr;
+  const dim3 grid(p->psa * p->g.nx + p->g.K * (p->g.mx / p->g.xb)), block(p->L.T_plane);
+  k_adj_and_store<<<grid, block, std::max(p->L.lds_plane, p->L.lds_small), p->ls>>>(p->vda, ao, d);
+  return last_launch("k_adj_and_store");
 }
 
 // Scalar plans finish a solver step inside the adjoint plane pass (its u = b . v stays
@@ -492,11 +514,11 @@ static mh3d_status launch_adjoint_step(mh3d_plan_t p, int upd, float* o, const f
   ao.yin = yin;
   const dim3 grid(update_blocks(p->g.N)), block(UPD_THREADS);
   if (upd == UPD_NORMAL) {
-    if (!step_in_plane_pass(p)) k_vol_update<UPD_NORMAL><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
-    k_vol_finish<UPD_NORMAL><<<1, 256, 0, p->ls>>>(p->vdd, nullptr);
+    if (!step_in_plane_pass(p)) k_vol_update<UPD_NORMAL><<<grid, block, 0, p->ls>>>(p->vda, nullptr, ao);
+    k_vol_finish<UPD_NORMAL><<<1, 256, 0, p->ls>>>(p->vda, nullptr);
   } else {
-    if (!step_in_plane_pass(p)) k_vol_update<UPD_FISTA><<<grid, block, 0, p->ls>>>(p->vdd, nullptr, ao);
-    k_vol_finish<UPD_FISTA><<<1, 256, 0, p->ls>>>(p->vdd, nullptr);
+    if (!step_in_plane_pass(p)) k_vol_update<UPD_FISTA><<<grid, block, 0, p->ls>>>(p->vda, nullptr, ao);
+    k_vol_finish<UPD_FISTA><<<1, 256, 0, p->ls>>>(p->vda, nullptr);
   }
   return last_launch("k_vol_update / k_vol_finish");
 }
@@ -513,10 +535,29 @@ static mh3d_status state_set(mh3d_plan_t p, const DevState& v) {
 }
 
 static mh3d_status upload_desc(mh3d_plan_t p) {
-  HIPCHK(hipMemcpyAsync(p->vdd, &p->vdh, sizeof(VolDesc), hipMemcpyHostToDevice, p->stream));
+  p->vdu[0] = p->vdh;
+  p->vdu[1] = p->vdh;
+  p->vdu[1].g.ps = p->ps_solve;
+  p->vdu[1].nb_upd = p->g.C == 1 ? p->ps_solve * p->g.nx : update_blocks(p->g.N);
+  HIPCHK(hipMemcpyAsync(p->vdd, p->vdu, sizeof p->vdu, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return MH3D_OK;
 }
+
+// Runs the enclosing call's passes with the solver's plane split (descriptor [1]).
+struct SolverPasses {
+  mh3d_plan_t p;
+  VolDesc* vda;
+  int psa;
+  explicit SolverPasses(mh3d_plan_t q) : p(q), vda(q->vda), psa(q->psa) {
+    p->vda = p->vdd + 1;
+    p->psa = p->ps_solve;
+  }
+  ~SolverPasses() {
+    p->vda = vda;
+    p->psa = psa;
+  }
+};
 
 // ---------------------------------------------------------------------------- plan build
 static mh3d_status build_tables(mh3d_plan_t p) {
@@ -722,7 +763,9 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = dalloc(p, (void**)&p->env, sizeof(double) * (size_t)g.ny * g.nz)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->partials, sizeof(double) * 4 * 1024)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->st, sizeof(DevState))) != MH3D_OK) return bail(s);
-  if ((s = dalloc(p, (void**)&p->vdd, sizeof(VolDesc))) != MH3D_OK) return bail(s);
+  if ((s = dalloc(p, (void**)&p->vdd, 2 * sizeof(VolDesc))) != MH3D_OK) return bail(s);
+  p->vda = p->vdd;
+  p->psa = p->ps_solve = g.ps;
   if ((s = dalloc(p, (void**)&p->vdk, sizeof(VolDesc) * g.K)) != MH3D_OK) return bail(s);
   if ((s = build_tables(p)) != MH3D_OK) return bail(s);
   fill_desc(p);
@@ -762,7 +805,7 @@ extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, flo
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
   if (fused_class(p)) {
     CHK(launch_class_normal(p, 0, NRM_STORE));   // d's spectra and A^T's class pass
-    CHK(launch_small_inv(p, EPI_STORE, d));
+    return launch_adj_and_store(p, d, x);
   } else if (p->g.padded) {
     CHK(launch_class_fwd(p, 0, FWD_G));
     CHK(launch_small_inv(p, EPI_STORE_BACK, d));   // stores d and starts A^T on its cropped copy
@@ -825,6 +868,7 @@ static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out
 
 extern "C" mh3d_status mh3d_normal(mh3d_plan_t p, const float* x, float* out) {
   CHK(check_plan(p));
+  SolverPasses sp(p);
   if (!x || !out) return fail(MH3D_ERR_INVALID, "NULL array");
   DevState z;
   memset(&z, 0, sizeof z);
@@ -868,6 +912,7 @@ static mh3d_status power_iteration(mh3d_plan_t p, int iters, uint64_t seed, doub
 
 extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64_t seed, double* lmax) {
   CHK(check_plan(p));
+  SolverPasses sp(p);
   if (!lmax || iters < 1) return fail(MH3D_ERR_INVALID, "bad power-iteration arguments");
   return power_iteration(p, iters, seed, lmax);
 }
@@ -928,7 +973,7 @@ static mh3d_status solve_setup(mh3d_plan_t p, const float* d, const float* rho0,
   if (!g.padded) CHK(launch_small_fwd(p, d, p->G));
   if (fused_class(p)) {
     Timer t(p, KID_AUX);
-    k_class_data<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vdd);
+    k_class_data<<<dim3(g.ncls / g.cpw), dim3(p->L.T_class), p->L.lds_class, p->ls>>>(p->vda);
     CHK(last_launch("k_class_data"));
   }
   DevState s0;
@@ -1003,6 +1048,7 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
   CHK(check_plan(p));
   if (!d || !rho_inout) return fail(MH3D_ERR_INVALID, "NULL argument");
   CHK(validate_opts(opts));
+  SolverPasses sp(p);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1042,7 +1088,7 @@ struct mh3d_batch_s {
   // plane, class (padded volumes), small (padded volumes), fused class (the others), per-volume
   int2* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int ntask[5] = {0, 0, 0, 0, 0};
-  int T_class = 0;
+  int T_class = 0, T_small = 0;
   size_t lds_plane = 0, lds_class = 0, lds_small = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1105,6 +1151,7 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
     b->lds_plane = std::max(b->lds_plane, p->L.lds_plane);
     b->lds_class = std::max(b->lds_class, p->L.lds_class);
     b->lds_small = std::max(b->lds_small, p->L.lds_small);
+    if (p->g.padded) b->T_small = std::max(b->T_small, p->L.T_small);
   }
   auto bail = [&](mh3d_status s) { mh3d_batch_destroy(b); return s; };
   if (hipMalloc(&b->vds, sizeof(VolDesc) * n) != hipSuccess) return bail(fail(MH3D_ERR_OOM, "batch descriptors"));
@@ -1141,9 +1188,9 @@ static mh3d_status batch_class(mh3d_batch_t b, hipStream_t st, int mode) {
     k_class_fwd_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1], FWD_G);
     CHK(last_launch("k_class_fwd_batch"));
     if (mode == NRM_RESID)
-      k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+      k_small_inv<EPI_RESID_BACK><<<dim3(b->ntask[2]), dim3(b->T_small), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
     else
-      k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(256), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
+      k_small_inv<EPI_BACK><<<dim3(b->ntask[2]), dim3(b->T_small), b->lds_small, st>>>(b->vds, b->tasks[2], nullptr);
     CHK(last_launch("k_small_inv (batch)"));
     k_class_adj_batch<<<dim3(b->ntask[1]), dim3(b->T_class), b->lds_class, st>>>(b->vds, b->tasks[1]);
     CHK(last_launch("k_class_adj_batch"));
@@ -1392,8 +1439,8 @@ extern "C" mh3d_status mh3d_mhad(mh3d_plan_t p, const float* d, double lambda, c
 // ============================================================================ pass timing
 extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps, double* us) {
   CHK(check_plan(p));
-  if (pass < 0 || pass > 6 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");
-  if (pass == 6 && !fused_class(p))
+  if (pass < 0 || pass > 7 || reps < 1 || !us) return fail(MH3D_ERR_INVALID, "bad pass timing arguments");
+  if (pass >= 6 && !fused_class(p))
     return fail(MH3D_ERR_UNSUPPORTED, "the plan runs no fused class pass (vector model or boundary padding)");
   if (p->prof_on) return fail(MH3D_ERR_INVALID, "disable mh3d_profile before timing passes");
   float* dtmp = nullptr;
@@ -1408,6 +1455,7 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
       case 3: return launch_small_fwd(p, dtmp);
       case 4: return launch_class_adj(p, 0);
       case 6: return launch_class_normal(p, 0, NRM_STORE);
+      case 7: return launch_adj_and_store(p, dtmp, p->vol[1]);
       default: return launch_plane_adj(p, OUT_SCALE_B, p->vol[1], nullptr);
     }
   };
@@ -1444,6 +1492,8 @@ static mh3d_status apply_tiles(mh3d_plan_t p, const mh3d_tiles* t) {
   HIPCHK(hipStreamSynchronize(p->stream));
   p->g = g;
   p->L = L;
+  p->vda = p->vdd;
+  p->psa = p->ps_solve = g.ps;   // the solver's split follows; the autotuner may change it
   fill_desc(p);
   CHK(upload_desc(p));
   CHK(upload_harmonic_descs(p));
@@ -1482,12 +1532,13 @@ static std::string tune_key(mh3d_plan_t p) {
 }
 
 struct TuneEntry {
-  int E, cpw, xb, ps;
+  int E, cpw, xb, ps, ps_solve;
   double us;
 };
 
 // The cache is a JSON object, one entry per line:
-//   "key": {"E": e, "cpw": c, "xb": x, "ps": s, "us": t},
+//   "key": {"E": e, "cpw": c, "xb": x, "ps": s, "ps_solve": q, "us": t},
+// (entries without ps_solve take ps for it).
 // Lines that do not parse are ignored (the file is rewritten on the next store).
 static std::map<std::string, TuneEntry> tune_read(const char* path) {
   std::map<std::string, TuneEntry> m;
@@ -1497,9 +1548,14 @@ static std::map<std::string, TuneEntry> tune_read(const char* path) {
   while (fgets(line, sizeof line, f)) {
     char key[256];
     TuneEntry e;
-    if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"us\": %lf}", key, &e.E,
-               &e.cpw, &e.xb, &e.ps, &e.us) == 6)
+    if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"us\": %lf}",
+               key, &e.E, &e.cpw, &e.xb, &e.ps, &e.ps_solve, &e.us) == 7) {
       m[key] = e;
+    } else if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"us\": %lf}", key,
+                      &e.E, &e.cpw, &e.xb, &e.ps, &e.us) == 6) {
+      e.ps_solve = e.ps;
+      m[key] = e;
+    }
   }
   fclose(f);
   return m;
@@ -1512,8 +1568,9 @@ static void tune_write(const char* path, const std::map<std::string, TuneEntry>&
   fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m) {
-    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
-            kv.second.E, kv.second.cpw, kv.second.xb, kv.second.ps, kv.second.us, ++i < m.size() ? "," : "");
+    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"us\": %.3f}%s\n",
+            kv.first.c_str(), kv.second.E, kv.second.cpw, kv.second.xb, kv.second.ps, kv.second.ps_solve, kv.second.us,
+            ++i < m.size() ? "," : "");
   }
   fprintf(f, "}\n");
   fclose(f);
@@ -1545,6 +1602,32 @@ static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
   return s;
 }
 
+// Microseconds per application of the normal operator (the passes of a solver update)
+// with the plan's current solver split, timed as time_application.
+static mh3d_status time_normal(mh3d_plan_t p, double* us) {
+  for (int i = 0; i < 2; ++i) CHK(mh3d_normal(p, p->vol[0], p->vol[1]));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = 1e30;
+  mh3d_status s = MH3D_OK;
+  for (int r = 0; r < 2 && s == MH3D_OK; ++r) {
+    (void)hipEventRecord(e0, p->stream);
+    for (int i = 0; i < 8 && s == MH3D_OK; ++i) s = mh3d_normal(p, p->vol[0], p->vol[1]);
+    (void)hipEventRecord(e1, p->stream);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      s = fail(MH3D_ERR_HIP, "timing events failed");
+    best = std::min(best, 1e3 * ms / 8.0);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = best;
+  return s;
+}
+
+static bool valid_ps(const Geo& g, int ps) { return ps >= 1 && ps <= 4 && ps <= g.nzh && ps <= g.npairs; }
+
 extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d_tiles* tiles, double* us_out) {
   CHK(check_plan(p));
   if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; tune it before creating the batch");
@@ -1555,6 +1638,10 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     if (it != m.end()) {
       mh3d_tiles t{it->second.E, it->second.cpw, it->second.xb, it->second.ps};
       if (apply_tiles(p, &t) == MH3D_OK) {
+        if (valid_ps(p->g, it->second.ps_solve)) {
+          p->ps_solve = it->second.ps_solve;
+          CHK(upload_desc(p));
+        }
         if (tiles) *tiles = t;
         if (us_out) *us_out = it->second.us;
         return MH3D_OK;
@@ -1596,23 +1683,38 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
       return MH3D_OK;
     };
     for (const auto& t : cands) CHK(trial(t));
-    // phase 2: small-grid tiles xb with the best class tiles
+    // phase 2: small-grid tiles xb and workgroups per x-plane ps together, with the best
+    // class tiles (the small-grid blocks can share a launch with the plane blocks, so the
+    // best xb depends on ps)
     const mh3d_tiles cls = best;
     for (int xb : {1, 2, 4, 8, 16, 32}) {
-      if (g0.mx % xb || xb == cls.xb) continue;
-      CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb, cls.ps}));
+      if (g0.mx % xb) continue;
+      for (int ps : {1, 2, 4}) {
+        if (ps > g0.nzh || ps > g0.npairs || (xb == cls.xb && ps == cls.ps)) continue;
+        CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb, ps}));
+      }
     }
-    // phase 3: workgroups per x-plane in the plane passes
-    const mh3d_tiles sm = best;
-    for (int ps : {1, 2, 4})
-      if (ps != sm.ps && ps <= g0.nzh && ps <= g0.npairs) CHK(trial(mh3d_tiles{sm.E, sm.cpw, sm.xb, ps}));
     if (best_us >= 1e30) return fail(MH3D_ERR_UNSUPPORTED, "no tile shape could be timed");
     CHK(apply_tiles(p, &best));
+    // phase 3: the solver's plane split, timed on the normal operator (a solver update
+    // runs the same passes and no small-grid pass, so its best split can differ)
+    int best_pss = best.ps;
+    double best_nus = 1e30;
+    for (int ps : {1, 2, 4}) {
+      if (!valid_ps(p->g, ps)) continue;
+      p->ps_solve = ps;
+      CHK(upload_desc(p));
+      double us = 0;
+      CHK(time_normal(p, &us));
+      if (us < best_nus) { best_nus = us; best_pss = ps; }
+    }
+    p->ps_solve = best_pss;
+    CHK(upload_desc(p));
     if (tiles) *tiles = best;
     if (us_out) *us_out = best_us;
     if (cache_path) {
       auto m = tune_read(cache_path);
-      m[key] = TuneEntry{best.E, best.cpw, best.xb, best.ps, best_us};
+      m[key] = TuneEntry{best.E, best.cpw, best.xb, best.ps, best_pss, best_us};
       tune_write(cache_path, m);
     }
     return MH3D_OK;

@@ -17,7 +17,7 @@ HEADER = os.path.join(_ROOT, "include", "mh3d.h")
 
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_NONFINITE = range(7)
 FIELD_PROFILE, FIELD_ENVELOPE, FIELD_SENS, FIELD_SPECTRUM = range(4)
-NKERNEL = 10
+NKERNEL = 11
 
 
 class PlanDesc(ctypes.Structure):
@@ -326,7 +326,8 @@ class Plan:
                "history": np.array(hist[:info.iters])}
         return rho, out
 
-    PASSES = ("plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj", "plane_adj", "class_normal")
+    PASSES = ("plane_fwd", "class_fwd", "small_inv", "small_fwd", "class_adj", "plane_adj", "class_normal",
+              "adj_and_store")
 
     def time_pass(self, name, reps=200):
         """Average microseconds per launch of one pass, back to back between two events."""
@@ -335,8 +336,9 @@ class Plan:
         return us.value
 
     def time_passes(self, reps=200):
-        """time_pass of every pass the plan runs: class_normal (the fused class pass) only
-        for scalar plans without boundary padding, which run it."""
+        """time_pass of every pass the plan runs: class_normal (the fused class pass) and
+        adj_and_store (adjoint plane pass and small-grid inverse in one launch) only for
+        scalar plans without boundary padding, which run them."""
         out = {}
         for name in self.PASSES:
             try:

@@ -223,7 +223,7 @@ def test_deterministic_bitwise():
 @pytest.mark.parametrize("shape,harm,ds,a,sig", [CASES[1], CASES[5], CASES[10], ((96, 96, 64), tuple(range(2, 9)),
                                                                                   (2, 2, 2), 1.2, 20.0)])
 def test_forward_adjoint_fused_equals_separate_calls(shape, harm, ds, a, sig):
-    """The five-pass A-then-A^T sequence writes bitwise the forward call's portraits, and
+    """The fused A-then-A^T sequence writes bitwise the forward call's portraits, and
     its A^T, which starts from their spectra instead of transforming them back, equals
     the adjoint call's up to that round trip's rounding; both match the oracle."""
     torch = torch_cuda()
@@ -243,8 +243,9 @@ def test_forward_adjoint_fused_equals_separate_calls(shape, harm, ds, a, sig):
 
 def test_fused_class_pass_is_the_one_that_runs():
     """Scalar plans without padding run A then A^T and the normal operator with the fused
-    class pass (no separate class passes, no small-grid forward pass); padded plans keep
-    the separate passes, and their pass timer has no fused pass to time."""
+    class pass (no separate class passes, no small-grid forward pass) and write d in the
+    adjoint plane pass's launch; padded plans keep the separate passes, and their pass
+    timer has no fused pass to time."""
     torch = torch_cuda()
     from paper_2503_13802_amd import mh3d
     announce("fused class pass dispatch")
@@ -256,11 +257,30 @@ def test_fused_class_pass_is_the_one_that_runs():
     p.normal(x)
     prof = p.profile_read()
     p.profile(False)
-    assert prof["class_normal"][1] == 2
-    assert prof["class_fwd"][1] == 0 and prof["class_adj"][1] == 0 and prof["small_fwd"][1] == 0
-    assert "class_normal" in p.time_passes(reps=3)
+    assert prof["class_normal"][1] == 2 and prof["adj_and_store"][1] == 1
+    assert prof["class_fwd"][1] == 0 and prof["class_adj"][1] == 0
+    assert prof["small_fwd"][1] == 0 and prof["small_inv"][1] == 0
+    assert {"class_normal", "adj_and_store"} <= set(p.time_passes(reps=3))
     q = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3, pad=(2, 2, 2))
     with pytest.raises(mh3d.MH3DError) as e:
         q.time_pass("class_normal", 3)
     assert e.value.status == mh3d.ERR_UNSUPPORTED
-    assert set(q.time_passes(reps=3)) == set(mh3d.Plan.PASSES) - {"class_normal"}
+    assert set(q.time_passes(reps=3)) == set(mh3d.Plan.PASSES) - {"class_normal", "adj_and_store"}
+
+
+def test_forward_adjoint_launch_shapes():
+    """The launch that runs the adjoint plane pass beside the small-grid pass writing d
+    (plane blocks first, then the small-grid blocks) over several tile shapes: d bitwise
+    the forward call's, A^T as the adjoint call's up to rounding."""
+    torch = torch_cuda()
+    announce("forward_adjoint launch shapes 96x96x64")
+    shape, harm, ds = (96, 96, 64), tuple(range(2, 9)), (2, 2, 2)
+    p = _plan(shape, harm, 1.2, ds, 20.0)
+    x = torch.tensor(inputs.random_field(shape, 17), dtype=torch.float32, device="cuda")
+    for tiles in [(4, 2, 8, 1), (2, 1, 2, 4), (8, 4, 1, 2), (4, 2, 1, 2)]:
+        p.set_tiles(*tiles)
+        d1 = p.forward(x).clone()
+        x1 = p.adjoint(d1).clone()
+        d2, x2 = p.forward_adjoint(x)
+        assert torch.equal(d1, d2), tiles
+        assert rel_l2(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-6, tiles

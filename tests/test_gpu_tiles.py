@@ -84,6 +84,7 @@ def test_autotune_cache_round_trip(tmp_path):
     (key, ent), = stored.items()
     assert key.endswith("|96x96x64|K7|ds2x2x2|analytic")
     assert (ent["E"], ent["cpw"], ent["xb"], ent["ps"]) == tiles
+    assert ent["ps_solve"] in (1, 2, 4)
     # a second plan of the same geometry reads the cache without timing
     q = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam)
     tiles2, us2 = q.autotune(str(cache))
@@ -117,3 +118,35 @@ def test_batch_of_tuned_plans_reproduces_single_solves(tmp_path):
     from paper_2503_13802_amd.mh3d import MH3DError
     with pytest.raises(MH3DError):
         plans[0].set_tiles()                  # frozen while the batch holds the plan
+
+
+def test_solver_plane_split_does_not_change_results(tmp_path):
+    """The solver's passes may split x-planes over a different number of workgroups than
+    the operator calls (the cache's ps_solve).  With a fixed step and count the updates,
+    the normal operator and the power iteration's estimate do not depend on it (the
+    FP64 sums only change their block partition)."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("solver plane split")
+    shape, harm, ds = (32, 24, 16), (2, 3, 4), (2, 2, 2)
+    cache = tmp_path / "tiles.json"
+    p0 = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3)
+    p0.autotune(str(cache))
+    (key, ent), = json.loads(cache.read_text()).items()
+    rho = torch.tensor(inputs.random_field(shape, 21), dtype=torch.float32, device="cuda").abs()
+    d = p0.forward(rho)
+    x = torch.tensor(inputs.random_field(shape, 22), dtype=torch.float32, device="cuda")
+    outs = []
+    for pss in (1, 2, 4):
+        cache.write_text('{\n  "%s": {"E": %d, "cpw": %d, "xb": %d, "ps": %d, "ps_solve": %d, "us": %.3f}\n}\n'
+                         % (key, ent["E"], ent["cpw"], ent["xb"], ent["ps"], pss, ent["us"]))
+        p = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3)
+        p.autotune(str(cache))
+        rec, info = p.solve(d, max_iter=25, tol=0.0, tau=0.05)
+        assert info["iters"] == 25
+        outs.append((rec, p.normal(x), p.power_iteration(30, 1)))
+        p.close()
+    for rec, nx_, lmax in outs[1:]:
+        assert torch.equal(rec, outs[0][0])
+        assert torch.equal(nx_, outs[0][1])
+        assert lmax == pytest.approx(outs[0][2], rel=1e-12)
