@@ -295,18 +295,8 @@ __device__ __forceinline__ RowCols plane_rowcols(const Geo& g) {
 // reads y^k of the volume (a ignored) and is skipped once the volume's solve is done.
 // LDS: tables (nz + ny) + two buffers of plane_lds complex.
 template <int SRC>
-__global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
-                                                    const float* __restrict__ a) {
-  int lb;
-  const VolDesc& vd = vol_of(vds, tasks, lb);
+__device__ __forceinline__ void plane_fwd_body(const VolDesc& vd, int lb, const float* __restrict__ a) {
   const Geo& g = vd.g;
-  if constexpr (SRC == SRC_FISTA_Y || SRC == SRC_SCALED) {
-    if (vd.st->done) return;
-  }
-  if constexpr (SRC == SRC_FISTA_Y) a = vd.y[vd.st->k & 1];
-  if constexpr (SRC == SRC_SCALED) {
-    if (!a) a = vd.rho[vd.st->k & 1];
-  }
   extern __shared__ float2 lds[];
   const int pl = plane_lds(g);
   float2* twz = lds;
@@ -362,6 +352,20 @@ __global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ 
     }
     dst[e] = v;
   }
+}
+template <int SRC>
+__global__ __launch_bounds__(1024) void k_plane_fwd(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                    const float* __restrict__ a) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  if constexpr (SRC == SRC_FISTA_Y || SRC == SRC_SCALED) {
+    if (vd.st->done) return;
+  }
+  if constexpr (SRC == SRC_FISTA_Y) a = vd.y[vd.st->k & 1];
+  if constexpr (SRC == SRC_SCALED) {
+    if (!a) a = vd.rho[vd.st->k & 1];
+  }
+  plane_fwd_body<SRC>(vd, lb, a);
 }
 
 // ============================================================================ pass 2: classes
@@ -1372,6 +1376,23 @@ __global__ __launch_bounds__(1024) void k_plane_adj(const VolDesc* __restrict__ 
   int lb;
   const VolDesc& vd = vol_of(vds, tasks, lb);
   plane_adj_body<OUT>(vd, lb, ao);
+}
+
+// A solver update's adjoint plane pass and step (OUT_STEP_FISTA), then, in the same
+// workgroup, the next update's forward plane pass on the y^{k+1} the step just wrote
+// (u = b . y^{k+1}, as k_plane_fwd<SRC_FISTA_Y> forms it): a plane's forward pass needs
+// only that plane's y, so with one workgroup per x-plane (ps = 1) no other block is
+// awaited, and the next update starts at its class pass.  If this step ends the solve,
+// the extra forward pass is unused.  grid = nx blocks (ps must be 1).
+__global__ __launch_bounds__(1024) void k_step_and_fwd(const VolDesc* __restrict__ vds, const int2* __restrict__ tasks,
+                                                       AdjOut ao) {
+  int lb;
+  const VolDesc& vd = vol_of(vds, tasks, lb);
+  if (vd.st->done) return;
+  const float* ynext = vd.y[(vd.st->k + 1) & 1];
+  plane_adj_body<OUT_STEP_FISTA>(vd, lb, ao);
+  __syncthreads();   // the block's stores of y^{k+1} are visible to it; the LDS is free
+  plane_fwd_body<SRC_PLAIN>(vd, lb, ynext);
 }
 
 // The two passes after the fused class pass in A then A^T, in one launch: both read only

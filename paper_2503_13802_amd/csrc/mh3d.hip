@@ -495,6 +495,24 @@ static mh3d_status launch_adj_and_store(mh3d_plan_t p, float* d, float* x) {
   return last_launch("k_adj_and_store");
 }
 
+// Scalar plans with one workgroup per x-plane also run the next update's forward plane
+// pass in the launch of the step (k_step_and_fwd).
+static bool step_and_fwd(mh3d_plan_t p) { return p->g.C == 1 && p->psa == 1; }
+
+static mh3d_status launch_step_and_fwd(mh3d_plan_t p) {
+  {
+    Timer t(p, KID_PLANE_ADJ);
+    AdjOut ao;
+    ao.out = nullptr;
+    ao.yin = nullptr;
+    k_step_and_fwd<<<dim3(p->g.nx), dim3(p->L.T_plane), p->L.lds_plane, p->ls>>>(p->vda, nullptr, ao);
+    CHK(last_launch("k_step_and_fwd"));
+  }
+  Timer t(p, KID_UPDATE);
+  k_vol_finish<UPD_FISTA><<<1, 256, 0, p->ls>>>(p->vda, nullptr);
+  return last_launch("k_vol_finish");
+}
+
 // Scalar plans finish a solver step inside the adjoint plane pass (its u = b . v stays
 // in registers); vector plans, whose plane pass sums the components, run the update
 // pass after it.  The block count of the step's FP64 sums is the descriptor's nb_upd.
@@ -920,9 +938,11 @@ extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64
 // ============================================================================ solver
 // One accelerated projected gradient update of the plan's volume; buffers and the
 // step come from the device state, so the same launches serve every iteration.
-static mh3d_status enqueue_update(mh3d_plan_t p) {
+// first: the first update of a solve call (with k_step_and_fwd the forward plane pass of
+// every later update ran in the previous update's last launch).
+static mh3d_status enqueue_update(mh3d_plan_t p, bool first) {
   Timer t(p, KID_SOLVE_ITER);
-  CHK(launch_plane_fwd(p, SRC_FISTA_Y, nullptr));
+  if (first || !step_and_fwd(p)) CHK(launch_plane_fwd(p, SRC_FISTA_Y, nullptr));
   if (fused_class(p)) {
     CHK(launch_class_normal(p, 1, NRM_RESID));   // against the data's spectra, held in G'
   } else {
@@ -934,6 +954,7 @@ static mh3d_status enqueue_update(mh3d_plan_t p) {
     }
     CHK(launch_class_adj(p, 1));
   }
+  if (step_and_fwd(p)) return launch_step_and_fwd(p);
   CHK(launch_adjoint_step(p, UPD_FISTA, nullptr, nullptr));
   return MH3D_OK;
 }
@@ -1065,7 +1086,7 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
   int issued = 0;
   while (issued < opts->max_iter) {
     const int n = std::min(chunk, opts->max_iter - issued);
-    for (int i = 0; i < n; ++i) CHK(enqueue_update(p));
+    for (int i = 0; i < n; ++i) CHK(enqueue_update(p, issued + i == 0));
     issued += n;
     CHK(read_state(p, h));
     if (h.done) break;
@@ -1198,20 +1219,25 @@ static mh3d_status batch_class(mh3d_batch_t b, hipStream_t st, int mode) {
   return MH3D_OK;
 }
 
-// One update of every volume of the batch: four launches over the task tables (six
-// when some volume is padded).
+// One update of every volume of the batch: three launches over the task tables (five
+// when some volume is padded).  The batch runs one workgroup per x-plane, so the step's
+// launch also runs the next update's forward plane pass (k_step_and_fwd); the first
+// update of a solve call is preceded by batch_first_plane_pass.
 static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
-  k_plane_fwd<SRC_FISTA_Y><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
-  CHK(last_launch("k_plane_fwd (batch)"));
   CHK(batch_class(b, st, NRM_RESID));
   AdjOut ao;
   ao.out = nullptr;
   ao.yin = nullptr;
-  k_plane_adj<OUT_STEP_FISTA><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
-  CHK(last_launch("k_plane_adj (batch)"));
+  k_step_and_fwd<<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], ao);
+  CHK(last_launch("k_step_and_fwd (batch)"));
   k_vol_finish<UPD_FISTA><<<dim3(b->ntask[4]), dim3(256), 0, st>>>(b->vds, b->tasks[4]);
   CHK(last_launch("k_vol_finish (batch)"));
   return MH3D_OK;
+}
+
+static mh3d_status batch_first_plane_pass(mh3d_batch_t b, hipStream_t st) {
+  k_plane_fwd<SRC_FISTA_Y><<<dim3(b->ntask[0]), dim3(1024), b->lds_plane, st>>>(b->vds, b->tasks[0], nullptr);
+  return last_launch("k_plane_fwd (batch)");
 }
 
 // One power-iteration step of every volume: w_{t+1} = N (s w_t), w_t in rho[k & 1].
@@ -1314,6 +1340,7 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
   // per-volume state snapshots after each replay; the graph is replayed until every
   // volume reports done (each volume stops updating at its own r_k <= tol)
   std::vector<DevState> hs(n);
+  CHK(batch_first_plane_pass(b, b->stream));
   int issued = 0;
   while (issued < opts->max_iter) {
     HIPCHK(hipGraphLaunch(b->gexec, b->stream));
@@ -1602,28 +1629,26 @@ static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
   return s;
 }
 
-// Microseconds per application of the normal operator (the passes of a solver update)
-// with the plan's current solver split, timed as time_application.
-static mh3d_status time_normal(mh3d_plan_t p, double* us) {
-  for (int i = 0; i < 2; ++i) CHK(mh3d_normal(p, p->vol[0], p->vol[1]));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+// Microseconds per solver update with the plan's current solver split: solves of 48
+// updates with a fixed step and no stopping rule on data d from rho = 0 (the solve's
+// own stream timing, setup included), the faster of two kept.
+static mh3d_status time_updates(mh3d_plan_t p, const float* d, float* rho, double* us) {
   double best = 1e30;
-  mh3d_status s = MH3D_OK;
-  for (int r = 0; r < 2 && s == MH3D_OK; ++r) {
-    (void)hipEventRecord(e0, p->stream);
-    for (int i = 0; i < 8 && s == MH3D_OK; ++i) s = mh3d_normal(p, p->vol[0], p->vol[1]);
-    (void)hipEventRecord(e1, p->stream);
-    float ms = 0.f;
-    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-      s = fail(MH3D_ERR_HIP, "timing events failed");
-    best = std::min(best, 1e3 * ms / 8.0);
+  for (int r = 0; r < 2; ++r) {
+    HIPCHK(hipMemsetAsync(rho, 0, sizeof(float) * p->g.N, p->stream));
+    mh3d_solve_opts o;
+    memset(&o, 0, sizeof o);
+    o.max_iter = 48;
+    o.tau = 1e-3;
+    o.k0 = 1;
+    o.check_every = 48;
+    mh3d_solve_info info;
+    const mh3d_status s = mh3d_solve(p, d, rho, &o, &info);
+    if (s != MH3D_OK && s != MH3D_ERR_NOT_CONVERGED) return s;
+    best = std::min(best, 1e3 * (double)info.ms_total / o.max_iter);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   *us = best;
-  return s;
+  return MH3D_OK;
 }
 
 static bool valid_ps(const Geo& g, int ps) { return ps >= 1 && ps <= 4 && ps <= g.nzh && ps <= g.npairs; }
@@ -1651,7 +1676,12 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
   }
   const Geo g0 = p->g;
   float* dtmp = nullptr;
+  float* rtmp = nullptr;
   HIPCHK(hipMalloc(&dtmp, sizeof(float) * (size_t)g0.K * g0.M));
+  if (hipMalloc(&rtmp, sizeof(float) * g0.N) != hipSuccess) {
+    (void)hipFree(dtmp);
+    return fail(MH3D_ERR_OOM, "autotuner volume");
+  }
   (void)hipMemsetAsync(p->vol[0], 0, sizeof(float) * g0.N, p->stream);
   auto run = [&]() -> mh3d_status {
     // phase 1: class tiles (E, cpw) with the heuristic xb; per E the smallest cpw
@@ -1696,8 +1726,10 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     }
     if (best_us >= 1e30) return fail(MH3D_ERR_UNSUPPORTED, "no tile shape could be timed");
     CHK(apply_tiles(p, &best));
-    // phase 3: the solver's plane split, timed on the normal operator (a solver update
-    // runs the same passes and no small-grid pass, so its best split can differ)
+    // phase 3: the solver's plane split, timed on solver updates (which run no
+    // small-grid pass, and with ps = 1 start the next update in the step's launch, so
+    // their best split can differ); data: A applied to the sensitivity map
+    CHK(mh3d_forward(p, p->b, dtmp));
     int best_pss = best.ps;
     double best_nus = 1e30;
     for (int ps : {1, 2, 4}) {
@@ -1705,7 +1737,7 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
       p->ps_solve = ps;
       CHK(upload_desc(p));
       double us = 0;
-      CHK(time_normal(p, &us));
+      CHK(time_updates(p, dtmp, rtmp, &us));
       if (us < best_nus) { best_nus = us; best_pss = ps; }
     }
     p->ps_solve = best_pss;
@@ -1722,6 +1754,7 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
   mh3d_status s = run();
   (void)hipStreamSynchronize(p->stream);
   (void)hipFree(dtmp);
+  (void)hipFree(rtmp);
   if (s != MH3D_OK) {
     mh3d_tiles h{g0.E, g0.cpw, g0.xb, g0.ps};
     (void)apply_tiles(p, &h);
