@@ -284,3 +284,30 @@ def test_forward_adjoint_launch_shapes():
         d2, x2 = p.forward_adjoint(x)
         assert torch.equal(d1, d2), tiles
         assert rel_l2(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-6, tiles
+
+
+@pytest.mark.parametrize("tiles", [(4, 1, 0, 0), (8, 2, 0, 0)])
+def test_fused_class_pass_with_more_harmonics_than_its_ring(tiles):
+    """K = 11 exceeds the class kernels' prefetch ring (8 harmonics at E = 4, 4 at E = 8),
+    so the fused class pass reads the spectra again for its adjoint half: A then A^T, the
+    normal operator and a fixed-step solve against the oracle."""
+    torch = torch_cuda()
+    announce("fused class pass K=11 tiles %s" % (tiles,))
+    shape, harm, ds, a, sig, lam = (48, 24, 32), tuple(range(2, 13)), (2, 4, 4), 1.2, 10.0, 1e-2
+    h = om.psf_bank(shape, list(harm), a)
+    b = om.sensitivity(shape, sig)
+    op = osv.Operator(h, b, ds, lam)
+    p = _plan(shape, harm, a, ds, sig, lam=lam)
+    p.set_tiles(*tiles)
+    x = inputs.random_field(shape, 31)
+    d2, x2 = p.forward_adjoint(torch.tensor(x, dtype=torch.float32))
+    assert rel_l2(d2.cpu().numpy(), op.A(x)) <= TOL
+    assert rel_l2(x2.cpu().numpy(), om.adjoint_fft(h, b, op.A(x), ds)) <= TOL
+    assert rel_l2(p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy(), op.normal(x)) <= TOL
+    rho_t = np.maximum(inputs.random_field(shape, 32), 0.0)
+    d = op.A(rho_t) + 0.01 * inputs.random_field(d2.shape, 33)
+    tau = 1.0 / (1.05 * p.power_iteration(60, 5))
+    want, _, _ = osv.fista(op, d, tau, max_iter=20)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=20, tol=0.0, tau=tau)
+    assert info["iters"] == 20
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
