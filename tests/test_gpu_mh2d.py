@@ -163,3 +163,25 @@ def test_mh2d_backprojection():
             assert rel_l2(c[k], om.adjoint_fft(hs[s][j:j + 1], bs[s], r[k:k + 1], ds)) <= TOL
     x = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
     assert rel_l2(c.sum(axis=0), x) <= 2e-6
+
+
+@pytest.mark.parametrize("reg_kind,alpha,width", [(0, 0.0, 0), (0, 2.0, 1)])
+def test_mh2d_single_scan_normal_and_solve(reg_kind, alpha, width):
+    """One scan is a scalar plan on a 2D grid: its solver step runs in the adjoint plane
+    pass, with the stencil's neighbours along the projection axis being the voxel itself.
+    Normal operator and a 30-update solve against the oracle."""
+    torch = torch_cuda()
+    announce("mh2d one scan normal/solve reg=%d alpha=%g" % (reg_kind, alpha))
+    shape, harm, ds, lam = (32, 1, 48), (2, 3, 4), (2, 1, 2), 1e-2
+    hs, bs = _scans(shape, 3, 81, n_scans=1)
+    op = osv.Operator(hs[0], bs[0], ds, lam, reg_kind=reg_kind, alpha=alpha, alpha_width=width)
+    p = _plan(torch, shape, harm, ds, hs, bs, lam=lam, reg_kind=reg_kind, alpha=alpha, alpha_width=width)
+    x = inputs.random_field(shape, 82)
+    assert rel_l2(p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy(), op.normal(x)) <= TOL
+    rho_t = np.maximum(inputs.random_field(shape, 83), 0.0)
+    d = op.A(rho_t) + 0.01 * inputs.random_field((3, 16, 1, 24), 84)
+    tau = 1.0 / (1.05 * p.power_iteration(100, 3))
+    want, _, _ = osv.fista(op, d, tau, max_iter=30)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=30, tol=0.0, tau=tau)
+    assert info["iters"] == 30
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
