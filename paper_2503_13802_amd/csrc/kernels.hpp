@@ -1341,7 +1341,9 @@ __device__ __forceinline__ void plane_adj_body(const VolDesc& vd, int lb, const 
 #pragma unroll
     for (int j = 0; j < NV; ++j) acc[j] = 0.0;
     const int n = (y1 - y0) * g.nz;
-    constexpr int U = 2;
+    // voxels whose loads are in flight together (half a 96 x 64 plane over 1024 threads
+    // is one round; 3 measured 1.7 % faster per update than 2 at 96 x 96 x 64)
+    constexpr int U = 3;
     for (int p = threadIdx.x; p < n; p += U * (int)blockDim.x) {
       StencilVals v[U];
 #pragma unroll
