@@ -206,8 +206,9 @@ mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
  * the fastest on the plan.  It then times the normal operator for ps = 1, 2, 4 and keeps
  * the fastest as the plane split of the solver's passes (mh3d_normal,
  * mh3d_power_iteration, mh3d_solve run no small-grid pass, so their best split can
- * differ; mh3d_plan_set_tiles sets both splits to ps, and results do not depend on
- * either).
+ * differ), which the forward plane pass of mh3d_forward_adjoint also takes (its launch
+ * holds no other blocks); mh3d_plan_set_tiles sets both splits to ps, and results do not
+ * depend on either.
  * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
  * kind" with E, cpw, xb, ps, ps_solve (the solver's split) and us; a hit applies the
  * stored tiles without timing, a miss stores the result.

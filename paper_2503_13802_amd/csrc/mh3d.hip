@@ -820,11 +820,19 @@ static mh3d_status check_plan(mh3d_plan_t p) {
 extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, float* d, float* x) {
   CHK(check_plan(p));
   if (!rho || !d || !x) return fail(MH3D_ERR_INVALID, "NULL array");
-  CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
   if (fused_class(p)) {
+    {
+      // the forward plane pass has its launch to itself, as the solver's plane passes
+      // do, so it takes their split; the adjoint plane blocks share their launch with
+      // the small-grid blocks and keep the plan's
+      SolverPasses sp(p);
+      CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
+    }
     CHK(launch_class_normal(p, 0, NRM_STORE));   // d's spectra and A^T's class pass
     return launch_adj_and_store(p, d, x);
-  } else if (p->g.padded) {
+  }
+  CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
+  if (p->g.padded) {
     CHK(launch_class_fwd(p, 0, FWD_G));
     CHK(launch_small_inv(p, EPI_STORE_BACK, d));   // stores d and starts A^T on its cropped copy
     CHK(launch_class_adj(p, 0));
@@ -1742,6 +1750,8 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     }
     p->ps_solve = best_pss;
     CHK(upload_desc(p));
+    // A + A^T runs its forward plane pass with that split: its time as the plan now runs it
+    CHK(time_application(p, dtmp, &best_us));
     if (tiles) *tiles = best;
     if (us_out) *us_out = best_us;
     if (cache_path) {

@@ -121,10 +121,11 @@ def test_batch_of_tuned_plans_reproduces_single_solves(tmp_path):
 
 
 def test_solver_plane_split_does_not_change_results(tmp_path):
-    """The solver's passes may split x-planes over a different number of workgroups than
-    the operator calls (the cache's ps_solve).  With a fixed step and count the updates,
-    the normal operator and the power iteration's estimate do not depend on it (the
-    FP64 sums only change their block partition)."""
+    """The solver's passes (and the forward plane pass of A then A^T) may split x-planes
+    over a different number of workgroups than the operator calls (the cache's
+    ps_solve).  With a fixed step and count the updates, the normal operator, A then A^T
+    and the power iteration's estimate do not depend on it (the FP64 sums only change
+    their block partition)."""
     torch = torch_cuda()
     from paper_2503_13802_amd import mh3d
     announce("solver plane split")
@@ -144,9 +145,10 @@ def test_solver_plane_split_does_not_change_results(tmp_path):
         p.autotune(str(cache))
         rec, info = p.solve(d, max_iter=25, tol=0.0, tau=0.05)
         assert info["iters"] == 25
-        outs.append((rec, p.normal(x), p.power_iteration(30, 1)))
+        outs.append((rec, p.normal(x), p.power_iteration(30, 1), p.forward_adjoint(x)))
         p.close()
-    for rec, nx_, lmax in outs[1:]:
+    for rec, nx_, lmax, fa in outs[1:]:
         assert torch.equal(rec, outs[0][0])
         assert torch.equal(nx_, outs[0][1])
         assert lmax == pytest.approx(outs[0][2], rel=1e-12)
+        assert torch.equal(fa[0], outs[0][3][0]) and torch.equal(fa[1], outs[0][3][1])
