@@ -202,16 +202,18 @@ mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
 mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
 /* Autotuner: times one A + A^T application (mh3d_forward_adjoint, HIP events) for candidate class tiles
  * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for
- * every pair of small-grid xb and plane split ps with the best class tiles, and leaves
- * the fastest on the plan.  It then times the normal operator for ps = 1, 2, 4 and keeps
+ * every small-grid xb and plane split ps with the best class tiles, each with 512 and
+ * 1024 threads per workgroup in the launch that runs the adjoint plane pass beside the
+ * small-grid pass writing d, and leaves the fastest on the plan.  It then times the normal operator for ps = 1, 2, 4 and keeps
  * the fastest as the plane split of the solver's passes (mh3d_normal,
  * mh3d_power_iteration, mh3d_solve run no small-grid pass, so their best split can
  * differ), which the forward plane pass of mh3d_forward_adjoint also takes (its launch
  * holds no other blocks); mh3d_plan_set_tiles sets both splits to ps, and results do not
  * depend on either.
  * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
- * kind" with E, cpw, xb, ps, ps_solve (the solver's split) and us; a hit applies the
- * stored tiles without timing, a miss stores the result.
+ * kind" with E, cpw, xb, ps, ps_solve (the solver's split), tm (threads of that
+ * launch) and us; a hit applies the stored tiles without timing, a miss stores the
+ * result.
  * tiles / us_per_application (HOST, may be NULL) receive the choice and its time.
  * Overwrites the plan's solver volumes; synchronous. */
 mh3d_status mh3d_autotune(mh3d_plan_t plan, const char* cache_path, mh3d_tiles* tiles, double* us_per_application);

@@ -60,6 +60,9 @@ static const size_t kLdsLimit = 160 * 1024;
 
 struct Launch {
   int T_plane, T_class, T_small;
+  // threads per block of k_adj_and_store (512 or 1024; both bodies loop over blockDim):
+  // with 512 two blocks share a CU, so more small-grid blocks run beside the plane blocks
+  int T_merge;
   size_t lds_plane, lds_class, lds_small;
 };
 
@@ -147,6 +150,7 @@ static mh3d_status derive_tiles(Geo& g, Launch& L, int E_req, int cpw_req, int x
   // 256 threads per decimated x'-plane of the block (the small-grid kernels loop over
   // blockDim, so the count only sets how much of the block's work runs side by side)
   L.T_small = std::min(1024, 256 * g.xb);
+  L.T_merge = g.ps >= 2 ? 512 : 1024;   // the autotuner times both
   L.lds_small = sizeof(float2) * ((size_t)g.my + g.mz + 2 * (size_t)small_lds(g));
   if (L.lds_small > kLdsLimit) return fail(MH3D_ERR_UNSUPPORTED, "small-grid plane does not fit in LDS");
   return MH3D_OK;
@@ -490,7 +494,7 @@ static mh3d_status launch_adj_and_store(mh3d_plan_t p, float* d, float* x) {
   AdjOut ao;
   ao.out = x;
   ao.yin = nullptr;
-  const dim3 grid(p->psa * p->g.nx + p->g.K * (p->g.mx / p->g.xb)), block(p->L.T_plane);
+  const dim3 grid(p->psa * p->g.nx + p->g.K * (p->g.mx / p->g.xb)), block(p->L.T_merge);
   k_adj_and_store<<<grid, block, std::max(p->L.lds_plane, p->L.lds_small), p->ls>>>(p->vda, ao, d);
   return last_launch("k_adj_and_store");
 }
@@ -1567,13 +1571,14 @@ static std::string tune_key(mh3d_plan_t p) {
 }
 
 struct TuneEntry {
-  int E, cpw, xb, ps, ps_solve;
+  int E, cpw, xb, ps, ps_solve, tm;
   double us;
 };
 
 // The cache is a JSON object, one entry per line:
-//   "key": {"E": e, "cpw": c, "xb": x, "ps": s, "ps_solve": q, "us": t},
-// (entries without ps_solve take ps for it).
+//   "key": {"E": e, "cpw": c, "xb": x, "ps": s, "ps_solve": q, "tm": m, "us": t},
+// (entries without ps_solve take ps for it; without tm, the default threads of the
+// merged adjoint launch).
 // Lines that do not parse are ignored (the file is rewritten on the next store).
 static std::map<std::string, TuneEntry> tune_read(const char* path) {
   std::map<std::string, TuneEntry> m;
@@ -1583,8 +1588,13 @@ static std::map<std::string, TuneEntry> tune_read(const char* path) {
   while (fgets(line, sizeof line, f)) {
     char key[256];
     TuneEntry e;
-    if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"us\": %lf}",
-               key, &e.E, &e.cpw, &e.xb, &e.ps, &e.ps_solve, &e.us) == 7) {
+    e.tm = 0;
+    if (sscanf(line,
+               " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"tm\": %d, \"us\": %lf}",
+               key, &e.E, &e.cpw, &e.xb, &e.ps, &e.ps_solve, &e.tm, &e.us) == 8) {
+      m[key] = e;
+    } else if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"us\": %lf}",
+                      key, &e.E, &e.cpw, &e.xb, &e.ps, &e.ps_solve, &e.us) == 7) {
       m[key] = e;
     } else if (sscanf(line, " \"%255[^\"]\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"us\": %lf}", key,
                       &e.E, &e.cpw, &e.xb, &e.ps, &e.us) == 6) {
@@ -1603,9 +1613,9 @@ static void tune_write(const char* path, const std::map<std::string, TuneEntry>&
   fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : m) {
-    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"us\": %.3f}%s\n",
-            kv.first.c_str(), kv.second.E, kv.second.cpw, kv.second.xb, kv.second.ps, kv.second.ps_solve, kv.second.us,
-            ++i < m.size() ? "," : "");
+    fprintf(f, "  \"%s\": {\"E\": %d, \"cpw\": %d, \"xb\": %d, \"ps\": %d, \"ps_solve\": %d, \"tm\": %d, \"us\": %.3f}%s\n",
+            kv.first.c_str(), kv.second.E, kv.second.cpw, kv.second.xb, kv.second.ps, kv.second.ps_solve, kv.second.tm,
+            kv.second.us, ++i < m.size() ? "," : "");
   }
   fprintf(f, "}\n");
   fclose(f);
@@ -1675,6 +1685,7 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
           p->ps_solve = it->second.ps_solve;
           CHK(upload_desc(p));
         }
+        if (it->second.tm == 512 || it->second.tm == 1024) p->L.T_merge = it->second.tm;
         if (tiles) *tiles = t;
         if (us_out) *us_out = it->second.us;
         return MH3D_OK;
@@ -1712,28 +1723,33 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
       }
     }
     mh3d_tiles best{0, 0, 0, 0};
+    int best_tm = 0;
     double best_us = 1e30;
-    auto trial = [&](const mh3d_tiles& t) -> mh3d_status {
+    // tm: threads of the merged adjoint launch (0: the default for the tiles)
+    auto trial = [&](const mh3d_tiles& t, int tm) -> mh3d_status {
       if (apply_tiles(p, &t) != MH3D_OK) return MH3D_OK;       // shape does not fit: skip
+      if (tm) p->L.T_merge = tm;
       double us = 0;
       CHK(time_application(p, dtmp, &us));
-      if (us < best_us) { best_us = us; best = t; best.xb = p->g.xb; best.ps = p->g.ps; }
+      if (us < best_us) { best_us = us; best = t; best.xb = p->g.xb; best.ps = p->g.ps; best_tm = p->L.T_merge; }
       return MH3D_OK;
     };
-    for (const auto& t : cands) CHK(trial(t));
-    // phase 2: small-grid tiles xb and workgroups per x-plane ps together, with the best
-    // class tiles (the small-grid blocks can share a launch with the plane blocks, so the
-    // best xb depends on ps)
+    for (const auto& t : cands) CHK(trial(t, 0));
+    // phase 2: small-grid tiles xb, workgroups per x-plane ps and the merged launch's
+    // threads together, with the best class tiles (the small-grid blocks can share a
+    // launch with the plane blocks, so the best xb depends on ps and on how many blocks
+    // fit beside them)
     const mh3d_tiles cls = best;
     for (int xb : {1, 2, 4, 8, 16, 32}) {
       if (g0.mx % xb) continue;
       for (int ps : {1, 2, 4}) {
-        if (ps > g0.nzh || ps > g0.npairs || (xb == cls.xb && ps == cls.ps)) continue;
-        CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb, ps}));
+        if (ps > g0.nzh || ps > g0.npairs) continue;
+        for (int tm : {512, 1024}) CHK(trial(mh3d_tiles{cls.E, cls.cpw, xb, ps}, tm));
       }
     }
     if (best_us >= 1e30) return fail(MH3D_ERR_UNSUPPORTED, "no tile shape could be timed");
     CHK(apply_tiles(p, &best));
+    p->L.T_merge = best_tm;
     // phase 3: the solver's plane split, timed on solver updates (which run no
     // small-grid pass, and with ps = 1 start the next update in the step's launch, so
     // their best split can differ); data: A applied to the sensitivity map
@@ -1756,7 +1772,7 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     if (us_out) *us_out = best_us;
     if (cache_path) {
       auto m = tune_read(cache_path);
-      m[key] = TuneEntry{best.E, best.cpw, best.xb, best.ps, best_pss, best_us};
+      m[key] = TuneEntry{best.E, best.cpw, best.xb, best.ps, best_pss, best_tm, best_us};
       tune_write(cache_path, m);
     }
     return MH3D_OK;
