@@ -154,3 +154,29 @@ def test_solver_plane_split_does_not_change_results(tmp_path):
         assert torch.equal(nx_, outs[0][1])
         assert lmax == pytest.approx(outs[0][2], rel=1e-12)
         assert torch.equal(fa[0], outs[0][3][0]) and torch.equal(fa[1], outs[0][3][1])
+
+
+def test_cache_entries_of_earlier_formats_are_read(tmp_path):
+    """Cache lines without ps_solve / tm (earlier formats) still apply their tiles without
+    timing; the missing fields take their defaults."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("tile cache formats")
+    shape, harm, ds = (32, 24, 16), (2, 3), (2, 2, 2)
+    cache = tmp_path / "tiles.json"
+    p0 = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3)
+    p0.autotune(str(cache))
+    (key, ent), = json.loads(cache.read_text()).items()
+    x = torch.tensor(inputs.random_field(shape, 5), dtype=torch.float32, device="cuda")
+    want = p0.forward_adjoint(x)
+    lines = ['"%s": {"E": %d, "cpw": %d, "xb": %d, "ps": %d, "us": 12.345}' % (key, ent["E"], ent["cpw"], ent["xb"], ent["ps"]),
+             '"%s": {"E": %d, "cpw": %d, "xb": %d, "ps": %d, "ps_solve": %d, "us": 12.345}'
+             % (key, ent["E"], ent["cpw"], ent["xb"], ent["ps"], ent["ps_solve"])]
+    for line in lines:
+        cache.write_text("{\n  " + line + "\n}\n")
+        p = mh3d.Plan(shape, harm, 1.0, ds, 6.0, 1e-3)
+        tiles, us = p.autotune(str(cache))
+        assert tiles == (ent["E"], ent["cpw"], ent["xb"], ent["ps"]) and us == pytest.approx(12.345)
+        got = p.forward_adjoint(x)
+        assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1])
+        p.close()
