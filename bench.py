@@ -3,10 +3,11 @@
 A step is one application of the forward operator A followed by its adjoint A^T
 applied to A's output (Sec. 4.1 eq. dN; each accelerated-projected-gradient update of
 Sec. 4.3 costs one of each) on the workload's resident inputs: d = A rho is written to
-HBM and x = A^T d is computed by the four-pass sequence the solver's updates run, in
-which one class pass does the forward and adjoint spectral products of its alias
-classes.  The rate of the two separate calls (six passes) is reported beside it.  The JSON line reports A+A^T
-applications per second, the HBM roofline of the dominant kernel (measured with
+HBM and x = A^T d is computed in three launches: the forward plane pass, one class pass
+doing the forward and adjoint spectral products of its alias classes (as the solver's
+updates do), and one launch running the adjoint plane pass beside the small-grid pass
+that writes d.  The rate of the two separate calls (six launches) is reported beside
+it.  The JSON line reports A+A^T applications per second, the HBM roofline of the dominant kernel (measured with
 HIP events around its launches), the FP64 CPU oracle timed on a bounded sample of
 the same workload, and the time to reconstruct at r_k <= 1e-4 with the plain solver
 (data and the zero start image resident in HBM; the first call includes the power
@@ -365,8 +366,8 @@ def stored_traffic(workload_name, tiles, kernel):
 
 def pmc_driver(args):
     """Counter-run driver: tuned plan of the workload, 20 A+A^T steps as the bench times
-    them (four passes, the fused class pass) and 20 as separate forward and adjoint calls
-    (six passes), then a 256 MiB device copy (the calibration kernel of known size)."""
+    them (three launches, the fused class pass) and 20 as separate forward and adjoint
+    calls (six launches), then a 256 MiB device copy (the calibration kernel of known size)."""
     import torch
     from paper_2503_13802_amd import inputs, mh3d
     w = inputs.workload(args.workload)
@@ -463,7 +464,7 @@ def main():
     src = rho_t.clone()
 
     def step():
-        # d = A src and x = A^T d (five passes: A^T starts from d's small-grid spectra)
+        # d = A src and x = A^T d (three launches: A^T starts from d's decimated spectra)
         plan.forward_adjoint(src, d_out=y, x_out=x)
 
     def step_separate():

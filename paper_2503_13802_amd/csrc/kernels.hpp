@@ -1401,7 +1401,7 @@ __global__ __launch_bounds__(1024) void k_step_and_fwd(const VolDesc* __restrict
 // what that pass wrote, so blocks [0, ps nx) run the adjoint plane pass (ao.out = b . v)
 // while the others run the small-grid inverse pass that writes the portraits d.  The
 // plane blocks come first (their XCD-aware plane order assumes block ids 0 .. ps nx - 1);
-// the small-grid blocks fill the CUs the plane blocks leave free.  blockDim = 1024.
+// the small-grid blocks run beside them.  Both bodies loop over blockDim (512 or 1024).
 __global__ __launch_bounds__(1024) void k_adj_and_store(const VolDesc* __restrict__ vds, AdjOut ao, float* __restrict__ d) {
   const VolDesc& vd = vds[0];
   const int nplane = vd.g.ps * vd.g.nx;

@@ -1231,8 +1231,9 @@ static mh3d_status batch_class(mh3d_batch_t b, hipStream_t st, int mode) {
   return MH3D_OK;
 }
 
-// One update of every volume of the batch: three launches over the task tables (five
-// when some volume is padded).  The batch runs one workgroup per x-plane, so the step's
+// One update of every volume of the batch: three launches over the task tables (three
+// more when some volume is padded: its forward class, small-grid and adjoint class
+// passes).  The batch runs one workgroup per x-plane, so the step's
 // launch also runs the next update's forward plane pass (k_step_and_fwd); the first
 // update of a solve call is preceded by batch_first_plane_pass.
 static mh3d_status batch_update(mh3d_batch_t b, hipStream_t st) {
@@ -1622,9 +1623,8 @@ static void tune_write(const char* path, const std::map<std::string, TuneEntry>&
   (void)rename(tmp.c_str(), path);
 }
 
-// Microseconds per A + A^T application with the plan's current tiles (HIP events,
-// best of two batches of 8 after 2 warm-up applications).
-// One A + A^T application as the solver's updates run it (mh3d_forward_adjoint).
+// Microseconds per A + A^T application (mh3d_forward_adjoint) with the plan's current
+// tiles: HIP events, best of two batches of 8 after 2 warm-up applications.
 static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
   for (int i = 0; i < 2; ++i) CHK(mh3d_forward_adjoint(p, p->vol[0], dtmp, p->vol[1]));
   hipEvent_t e0, e1;
