@@ -68,3 +68,27 @@ def test_batch_rejects_duplicates_and_user_psf():
     with pytest.raises(mh3d.MH3DError) as e:
         mh3d.Batch([p, pu])
     assert e.value.status == mh3d.ERR_UNSUPPORTED
+
+
+def test_batch_with_more_harmonics_than_the_class_ring():
+    """A batch whose volumes have 10 and 11 harmonics (more than the class kernels'
+    prefetch ring) next to a small one: each volume equals its single-volume solve, and
+    the K = 11 volume follows the oracle."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("batch with K = 10, 11")
+    vols = [((48, 24, 32), tuple(range(2, 13)), (2, 4, 4)), ((32, 32, 32), tuple(range(2, 12)), (2, 2, 2)),
+            ((16, 12, 8), (2, 3), (2, 2, 2))]
+    plans, ds, ops = [], [], []
+    for i, (shape, harm, ds_) in enumerate(vols):
+        op, d = _volume(shape, harm, ds_, 30 + i)
+        plans.append(mh3d.Plan(shape, harm, 1.0, ds_, 6.0, 1e-3))
+        ds.append(torch.tensor(d, dtype=torch.float32))
+        ops.append(op)
+    single = [p.solve(d, max_iter=40, tol=0.0, tau=0.0, check_every=16) for p, d in zip(plans, ds)]
+    rhos, infos = mh3d.Batch(plans).solve(ds, max_iter=40, tol=0.0, tau=0.0, check_every=16)
+    for v in range(len(vols)):
+        assert infos[v]["iters"] == single[v][1]["iters"] == 40
+        assert torch.equal(rhos[v], single[v][0]), "volume %d differs from its single solve" % v
+    want, _, _ = osv.fista(ops[0], ds[0].cpu().numpy().astype(np.float64), infos[0]["tau"], max_iter=40)
+    assert rel_l2(rhos[0].cpu().numpy(), want) <= 1e-4

@@ -311,3 +311,31 @@ def test_fused_class_pass_with_more_harmonics_than_its_ring(tiles):
     got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=20, tol=0.0, tau=tau)
     assert info["iters"] == 20
     assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+
+
+@pytest.mark.parametrize("tiles", [(2, 1, 0, 0), (4, 1, 0, 0), (8, 2, 0, 0)])
+def test_user_psf_fused_class_pass(tiles):
+    """A scalar plan with user-supplied (complex-spectrum) PSFs runs the fused class pass
+    with complex spectra (a ring of 4 harmonics, so K = 6 reloads it): A then A^T, the
+    normal operator and a 20-update solve against the oracle."""
+    torch = torch_cuda()
+    announce("user psf fused class pass tiles %s" % (tiles,))
+    shape, harm, ds, lam = (32, 24, 16), (2, 3, 4, 5, 6, 7), (2, 2, 2), 1e-2
+    h = inputs.vector_psfs(1, len(harm), shape, 11)[0]
+    b = inputs.vector_sensitivity(1, shape, 12)[0]
+    op = osv.Operator(h, b, ds, lam)
+    p = _plan(shape, harm, 1.0, ds, 1.0, lam=lam, psf=torch.tensor(h, dtype=torch.float32),
+              sens=torch.tensor(b, dtype=torch.float32))
+    p.set_tiles(*tiles)
+    x = inputs.random_field(shape, 13)
+    d2, x2 = p.forward_adjoint(torch.tensor(x, dtype=torch.float32))
+    assert rel_l2(d2.cpu().numpy(), op.A(x)) <= TOL
+    assert rel_l2(x2.cpu().numpy(), om.adjoint_fft(h, b, op.A(x), ds)) <= TOL
+    assert rel_l2(p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy(), op.normal(x)) <= TOL
+    rho_t = np.maximum(inputs.random_field(shape, 14), 0.0)
+    d = op.A(rho_t) + 0.01 * inputs.random_field(d2.shape, 15)
+    tau = 1.0 / (1.05 * p.power_iteration(60, 5))
+    want, _, _ = osv.fista(op, d, tau, max_iter=20)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=20, tol=0.0, tau=tau)
+    assert info["iters"] == 20
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
