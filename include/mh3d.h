@@ -126,7 +126,9 @@ mh3d_status mh3d_plan_describe(const mh3d_plan_desc* desc, size_t* device_bytes,
                                int64_t* n_volume, int64_t* n_portrait);
 
 /* Builds a plan: validates, allocates device memory, generates the PSF spectra in
- * FP64 (analytic model) or from desc->psf, and the sensitivity map.  Synchronous. */
+ * FP64 (analytic model) or from desc->psf, and the sensitivity map.  Synchronous.
+ * A plan holds its intermediate buffers and solver state, so calls on one plan must
+ * not overlap (from several host threads); different plans are independent. */
 mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out);
 
 /* Releases the plan's device memory (synchronises its stream). NULL is a no-op. */
