@@ -2,6 +2,8 @@
 operator and power iteration against the FP64 CPU oracle, through the C ABI.
 Tolerance: relative L2 error <= 1e-5 per FP32 application (paper Sec. 4.1 eq. dN
 evaluated in FP32 against its FP64 definition)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -339,3 +341,31 @@ def test_user_psf_fused_class_pass(tiles):
     got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=20, tol=0.0, tau=tau)
     assert info["iters"] == 20
     assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+
+
+@pytest.mark.parametrize("idx", [1, 2])
+def test_full_size_fused_paths(idx):
+    """The fused paths at the full size of workloads 1 and 2 (the bench's A then A^T, the
+    normal operator of the power iteration, and solver updates) against the FFT oracle."""
+    torch = torch_cuda()
+    w = inputs.workload(idx)
+    announce("full size fused paths %s" % w.name)
+    h = om.psf_bank(w.shape, list(w.harmonics), w.a_per_mm)
+    b = om.sensitivity(w.shape, w.sigma_mm)
+    op = osv.Operator(h, b, w.ds, w.lam)
+    p = _plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, lam=w.lam)
+    p.autotune(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_13802_amd",
+                            "tiles_gfx950.json"))
+    rho = inputs.phantom(w)
+    d_ref = op.A(rho)
+    d2, x2 = p.forward_adjoint(torch.tensor(rho, dtype=torch.float32))
+    assert rel_l2(d2.cpu().numpy(), d_ref) <= TOL
+    assert rel_l2(x2.cpu().numpy(), om.adjoint_fft(h, b, d_ref, w.ds)) <= TOL
+    x = inputs.random_field(w.shape, 41)
+    assert rel_l2(p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy(), op.normal(x)) <= TOL
+    if idx == 1:
+        d = d_ref + 0.01 * float(np.abs(d_ref).max()) * inputs.random_field(d_ref.shape, 42)
+        want, _, _ = osv.fista(op, d, 0.05, max_iter=8)
+        got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=8, tol=0.0, tau=0.05)
+        assert info["iters"] == 8
+        assert rel_l2(got.cpu().numpy(), want) <= 1e-4
