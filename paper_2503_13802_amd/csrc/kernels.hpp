@@ -1498,7 +1498,8 @@ __global__ __launch_bounds__(256) void k_vol_finish(const VolDesc* __restrict__ 
       st->nonfinite = 1.0;
       st->done = 1;
     }
-    if (r <= st->tol || kk >= st->kmax) st->done = 1;
+    // tol = 0 never stops early (not even at r_k = 0): the run takes max_iter updates
+    if ((st->tol > 0.0 && r <= st->tol) || kk >= st->kmax) st->done = 1;
     st->k = kk + 1;
   }
 }

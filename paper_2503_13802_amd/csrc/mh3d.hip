@@ -581,6 +581,22 @@ struct SolverPasses {
   }
 };
 
+// Two timing events destroyed on every exit path of the call that created them.
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+  hipError_t create() {
+    hipError_t r = hipEventCreate(&e0);
+    return r != hipSuccess ? r : hipEventCreate(&e1);
+  }
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 // ---------------------------------------------------------------------------- plan build
 static mh3d_status build_tables(mh3d_plan_t p) {
   const Geo& g = p->g;
@@ -1082,10 +1098,9 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
   if (!d || !rho_inout) return fail(MH3D_ERR_INVALID, "NULL argument");
   CHK(validate_opts(opts));
   SolverPasses sp(p);
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, p->stream));
+  EventPair ev;
+  HIPCHK(ev.create());
+  HIPCHK(hipEventRecord(ev.e0, p->stream));
   double tau, lmax;
   CHK(resolve_tau(p, opts, &tau, &lmax));
   CHK(solve_setup(p, d, rho_inout, opts, tau));
@@ -1103,12 +1118,10 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
     CHK(read_state(p, h));
     if (h.done) break;
   }
-  HIPCHK(hipEventRecord(e1, p->stream));
-  HIPCHK(hipEventSynchronize(e1));
+  HIPCHK(hipEventRecord(ev.e1, p->stream));
+  HIPCHK(hipEventSynchronize(ev.e1));
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
   return finish_solve(p, rho_inout, opts, h, tau, lmax, ms, info);
 }
 
@@ -1163,6 +1176,10 @@ extern "C" mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh
     if (!plans[i]->compact) return fail(MH3D_ERR_UNSUPPORTED, "batched solves need analytic-PSF plans (plan %d)", i);
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i]) return fail(MH3D_ERR_INVALID, "plan %d appears twice in the batch", i);
+    // every volume's per-solve setup is enqueued on its own plan's stream and the batch's
+    // passes on plans[0]'s: one stream orders them
+    if (plans[i]->stream != plans[0]->stream)
+      return fail(MH3D_ERR_INVALID, "plan %d uses another stream than plan 0 (a batch runs on one stream)", i);
   }
   mh3d_batch_t b = new mh3d_batch_s();
   b->plans.assign(plans, plans + n);
@@ -1306,10 +1323,9 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
   const int n = (int)b->plans.size();
   for (int v = 0; v < n; ++v)
     if (!d[v] || !rho_inout[v]) return fail(MH3D_ERR_INVALID, "NULL array for volume %d", v);
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, b->stream));
+  EventPair ev;
+  HIPCHK(ev.create());
+  HIPCHK(hipEventRecord(ev.e0, b->stream));
   std::vector<double> tau(n, opts->tau), lmax(n, 0.0);
   if (!(opts->tau > 0)) {
     const int it = opts->power_iters > 0 ? opts->power_iters : 50;
@@ -1365,12 +1381,10 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
     for (int v = 0; v < n; ++v) all = all && hs[v].done;
     if (all) break;
   }
-  HIPCHK(hipEventRecord(e1, b->stream));
-  HIPCHK(hipEventSynchronize(e1));
+  HIPCHK(hipEventRecord(ev.e1, b->stream));
+  HIPCHK(hipEventSynchronize(ev.e1));
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
   mh3d_status worst = MH3D_OK;
   for (int v = 0; v < n; ++v) {
     mh3d_solve_info inf;
@@ -1627,22 +1641,19 @@ static void tune_write(const char* path, const std::map<std::string, TuneEntry>&
 // tiles: HIP events, best of two batches of 8 after 2 warm-up applications.
 static mh3d_status time_application(mh3d_plan_t p, float* dtmp, double* us) {
   for (int i = 0; i < 2; ++i) CHK(mh3d_forward_adjoint(p, p->vol[0], dtmp, p->vol[1]));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  EventPair ev;
+  HIPCHK(ev.create());
   double best = 1e30;
   mh3d_status s = MH3D_OK;
   for (int r = 0; r < 2 && s == MH3D_OK; ++r) {
-    (void)hipEventRecord(e0, p->stream);
+    (void)hipEventRecord(ev.e0, p->stream);
     for (int i = 0; i < 8 && s == MH3D_OK; ++i) s = mh3d_forward_adjoint(p, p->vol[0], dtmp, p->vol[1]);
-    (void)hipEventRecord(e1, p->stream);
+    (void)hipEventRecord(ev.e1, p->stream);
     float ms = 0.f;
-    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    if (hipEventSynchronize(ev.e1) != hipSuccess || hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess)
       s = fail(MH3D_ERR_HIP, "timing events failed");
     best = std::min(best, 1e3 * ms / 8.0);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   *us = best;
   return s;
 }

@@ -92,3 +92,20 @@ def test_batch_with_more_harmonics_than_the_class_ring():
         assert torch.equal(rhos[v], single[v][0]), "volume %d differs from its single solve" % v
     want, _, _ = osv.fista(ops[0], ds[0].cpu().numpy().astype(np.float64), infos[0]["tau"], max_iter=40)
     assert rel_l2(rhos[0].cpu().numpy(), want) <= 1e-4
+
+
+def test_batch_rejects_plans_on_different_streams():
+    """A batch runs its passes on plan 0's stream while each volume's setup runs on its
+    own plan's stream, so plans on two streams are rejected before anything is queued."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("batch of plans on two streams")
+    p0 = mh3d.Plan((16, 12, 8), (2, 3), 0.9, (2, 2, 2), 5.0, 1e-3)
+    side = torch.cuda.Stream()   # default priority
+    with torch.cuda.stream(side):
+        p1 = mh3d.Plan((16, 12, 8), (2, 3), 0.9, (2, 2, 2), 5.0, 1e-3)
+    with pytest.raises(mh3d.MH3DError, match="another stream"):
+        mh3d.Batch([p0, p1])
+    torch.cuda.synchronize()
+    p1.close()
+    p0.close()

@@ -80,3 +80,16 @@ def test_32_harmonics_with_skipped_blocks():
     for k in (0, 1, 30, 31):
         want = sum(om.adjoint_fft(h[i][k:k + 1], b[i], r[k:k + 1], ds) for i in range(2))
         assert rel_l2(c[k], want) <= TOL, k
+
+
+def test_zero_tolerance_never_stops_early():
+    """rel_tol = 0 means no early stop, even when r_k = 0 (zero data from rho = 0): the
+    solve runs every one of its max_iter updates, as the oracle does without a tolerance."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("zero data, tol 0")
+    p = mh3d.Plan((16, 12, 8), (2, 3), 0.9, (2, 2, 2), 5.0, 1e-3)
+    d = torch.zeros((2, 8, 6, 4), device="cuda")
+    rho, info = p.solve(d, max_iter=7, tol=0.0, tau=0.1)
+    assert info["iters"] == 7 and info["rel_step"] == 0.0
+    assert float(rho.abs().max()) == 0.0
