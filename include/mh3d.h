@@ -202,6 +202,19 @@ typedef struct {
  * fit, or if the plan belongs to a batch.  Synchronous. */
 mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
 mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
+/* Pass family of the fused sequences (mh3d_forward_adjoint, mh3d_normal,
+ * mh3d_power_iteration, mh3d_solve) -- the same operator (Sec. 4.1 eq. dN, Table
+ * tab:ops) and solver step (Sec. 4.3) either way:
+ *   1  compile-time-geometry passes, where the library has them for the plan's grid,
+ *      decimation and harmonic count (scalar model, analytic PSF, no padding): the
+ *      y-transform is split four-step between the plane and class passes, the plane
+ *      passes run one workgroup per (x-plane, y mod ds1) and the class pass keeps every
+ *      harmonic's spectra of its elements in registers.  The default.
+ *   0  the general passes (as the separate calls and batches always run).
+ * Results agree to FP32 rounding (the sums run in other orders).  request: 0 or 1 to
+ * choose (synchronous; fails if the plan belongs to a batch), -1 to only query;
+ * *active (HOST, may be NULL) receives 1 if the compile-time passes will run. */
+mh3d_status mh3d_plan_path(mh3d_plan_t plan, int32_t request, int32_t* active);
 /* Autotuner: times one A + A^T application (mh3d_forward_adjoint, HIP events) for candidate class tiles
  * (per valid E, the smallest cpw giving >= 64, 128, 256, 512 threads), then for
  * every small-grid xb and plane split ps with the best class tiles, each with 512 and

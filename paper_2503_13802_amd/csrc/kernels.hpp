@@ -688,9 +688,14 @@ __device__ __forceinline__ void class_adj_body(const VolDesc& vd, int lb) {
 // block's own recently read spectra (L2).
 enum { NRM_RESID = 0, NRM_PLAIN = 1, NRM_STORE = 2 };
 
+// The fused pass keeps every harmonic's spectra of its elements in registers when they
+// fit (compact spectra, K <= 12 at E <= 4): all loads are issued at the start and the
+// adjoint reuses them, so the pass waits on one round of spectrum loads.
+__host__ __device__ constexpr int hpf_normal(int HC, int E) { return (HC == 0 && E <= 4) ? 12 : hpf_of(HC, E); }
+
 template <int HC, int E>
 __device__ __forceinline__ void class_normal_body(const VolDesc& vd, int lb, int mode) {
-  constexpr int HPF = hpf_of(HC, E);
+  constexpr int HPF = hpf_normal(HC, E);
   const Geo& g = vd.g;
   extern __shared__ float2 lds[];
   const int W = g.cpw * g.nmem;
@@ -714,9 +719,14 @@ __device__ __forceinline__ void class_normal_body(const VolDesc& vd, int lb, int
   const uint32_t imag_mask = vd.imag_mask;
   const int KCM = g.K * g.cpw * g.mx;
   HLoad<HC, E> hb[HPF];
+  // a ring that holds every harmonic is loaded after the x transform (its registers
+  // would otherwise be live across it); a shorter ring starts streaming at once
+  constexpr bool kLate = HPF > hpf_of(HC, E);
+  if constexpr (!kLate) {
 #pragma unroll
-  for (int i = 0; i < HPF; ++i)
-    if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+    for (int i = 0; i < HPF; ++i)
+      if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
+  }
   // the data term of the block's classes (F1[(k cpw + c) mx + qx'])
   if (mode == NRM_RESID) {
     const float2* __restrict__ Dt = vd.Gp;
@@ -747,6 +757,11 @@ __device__ __forceinline__ void class_normal_body(const VolDesc& vd, int lb, int
     const int w = within + i;
     const int jx = (int)g.f_nmem.div((uint32_t)w), m = w - jx * g.nmem;
     ur[i] = act ? U[(cl * g.nmem + m) * g.lsx + qxp + jx * g.mx] : make_float2(0.f, 0.f);
+  }
+  if constexpr (kLate) {
+#pragma unroll
+    for (int i = 0; i < HPF; ++i)
+      if (act && i < g.K) hb[i].load(hs, (long long)i * g.hsz + hoff0);
   }
   // forward: Fhat_k(cl, qx') = sum over the S alias members of Hhat_k U
   for (int k0 = 0; k0 < g.K; k0 += HPF) {

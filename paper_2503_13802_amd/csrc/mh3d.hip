@@ -15,6 +15,7 @@
 
 #include "../../include/mh3d.h"
 #include "kernels.hpp"
+#include "fast.hpp"
 
 using namespace mh3d;
 
@@ -253,7 +254,11 @@ static const char* kKernelNames[MH3D_NKERNEL] = {"plane_fwd", "class_fwd", "smal
                                                   "plane_adj", "aux", "solve_iter", "vol_update", "class_normal",
                                                   "adj_and_store"};
 
+struct FastOps;
+
 struct mh3d_plan_s {
+  const FastOps* fast = nullptr;   // compile-time-geometry passes of the fused sequences (or none)
+  bool fast_on = true;             // whether the fused sequences use them (mh3d_plan_path)
   mh3d_plan_desc desc;
   std::vector<int> harm;
   Geo g;
@@ -371,6 +376,72 @@ struct Timer {
     if (p->pending.size() > 4096) drain_events(p);
   }
 };
+
+// ---------------------------------------------------------------------------- fast passes
+// Launchers of the compile-time-geometry passes (fast.hpp) of one grid, decimation and
+// tile shape.  All passes of a fused sequence come from one entry (their slot layout is
+// their own).
+struct FastOps {
+  int nx, ny, nz, sx, sy, sz, kmax;
+  int nbp, ncls_blocks, tc;
+  size_t lds_plane, lds_class;
+  void (*plane_fwd)(hipStream_t, const VolDesc*, int src, const float* a);
+  void (*cls)(hipStream_t, const VolDesc*, int mode, int chk);
+  void (*plane_adj)(hipStream_t, const VolDesc*, int out, AdjOut ao);
+  void (*adj_and_store)(hipStream_t, const VolDesc*, AdjOut ao, float* d, int nsmall, size_t lds);
+};
+
+template <class G>
+struct FastImpl {
+  static void plane_fwd(hipStream_t s, const VolDesc* vd, int src, const float* a) {
+    const dim3 grid(G::NBP), block(G::TP);
+    switch (src) {
+      case SRC_PLAIN: k_fast_plane_fwd<G, SRC_PLAIN><<<grid, block, G::LDS_PLANE, s>>>(vd, a); break;
+      case SRC_FISTA_Y: k_fast_plane_fwd<G, SRC_FISTA_Y><<<grid, block, G::LDS_PLANE, s>>>(vd, a); break;
+      default: k_fast_plane_fwd<G, SRC_SCALED><<<grid, block, G::LDS_PLANE, s>>>(vd, a); break;
+    }
+  }
+  static void cls(hipStream_t s, const VolDesc* vd, int mode, int chk) {
+    const dim3 grid(G::NCLS / G::CPW), block(G::TC);
+    switch (mode) {
+      case NRM_RESID: k_fast_class<G, NRM_RESID><<<grid, block, G::LDS_CLASS, s>>>(vd, chk); break;
+      case NRM_PLAIN: k_fast_class<G, NRM_PLAIN><<<grid, block, G::LDS_CLASS, s>>>(vd, chk); break;
+      default: k_fast_class<G, NRM_STORE><<<grid, block, G::LDS_CLASS, s>>>(vd, chk); break;
+    }
+  }
+  static void plane_adj(hipStream_t s, const VolDesc* vd, int out, AdjOut ao) {
+    const dim3 grid(G::NBP), block(G::TP);
+    if (out == OUT_STEP_NORMAL) k_fast_plane_adj<G, OUT_STEP_NORMAL><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
+    else k_fast_plane_adj<G, OUT_STEP_FISTA><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
+  }
+  static void adj_and_store(hipStream_t s, const VolDesc* vd, AdjOut ao, float* d, int nsmall, size_t lds) {
+    k_fast_adj_and_store<G><<<dim3(G::NBP + nsmall), dim3(G::TP), std::max(lds, G::LDS_PLANE), s>>>(vd, ao, d);
+  }
+  static FastOps ops() {
+    return FastOps{G::NX, G::NY, G::NZ, G::SX, G::SY, G::SZ, G::KMAX, G::NBP, G::NCLS / G::CPW, G::TC,
+                   G::LDS_PLANE, G::LDS_CLASS, &plane_fwd, &cls, &plane_adj, &adj_and_store};
+  }
+};
+
+// Grids with compile-time passes: (nx, ny, nz, sx, sy, sz, elements per thread, classes per
+// block, largest harmonic count).
+static const FastOps kFast[] = {
+    FastImpl<FastGeo<128, 128, 128, 2, 4, 4, 8, 1, 12>>::ops(),   // 128^3, k = 2..12
+    // small grids of the parity tests: every y split (1 to 4), radix 3, group widths 4 and 8
+    FastImpl<FastGeo<32, 32, 32, 2, 4, 4, 8, 1, 12>>::ops(),
+    FastImpl<FastGeo<16, 24, 16, 2, 2, 2, 1, 1, 8>>::ops(),
+    FastImpl<FastGeo<16, 16, 16, 2, 1, 2, 1, 2, 8>>::ops(),
+    FastImpl<FastGeo<24, 24, 16, 2, 3, 2, 3, 4, 8>>::ops(),
+};
+
+// The entry serving plan p (scalar model, analytic spectra, no padding), or NULL.
+static const FastOps* find_fast(const Geo& g, bool compact) {
+  if (!compact || g.C != 1 || g.padded) return nullptr;
+  for (const FastOps& f : kFast)
+    if (f.nx == g.nx && f.ny == g.ny && f.nz == g.nz && f.sx == g.sx && f.sy == g.sy && f.sz == g.sz && g.K <= f.kmax)
+      return &f;
+  return nullptr;
+}
 
 static mh3d_status last_launch(const char* what) {
   hipError_t e = hipGetLastError();
@@ -499,9 +570,48 @@ static mh3d_status launch_adj_and_store(mh3d_plan_t p, float* d, float* x) {
   return last_launch("k_adj_and_store");
 }
 
+// The fused sequences run the compile-time passes of fast.hpp when the plan has them.
+static bool use_fast(mh3d_plan_t p) { return p->fast && p->fast_on; }
+
 // Scalar plans with one workgroup per x-plane also run the next update's forward plane
 // pass in the launch of the step (k_step_and_fwd).
-static bool step_and_fwd(mh3d_plan_t p) { return p->g.C == 1 && p->psa == 1; }
+static bool step_and_fwd(mh3d_plan_t p) { return p->g.C == 1 && p->psa == 1 && !use_fast(p); }
+
+// ---- the fused sequences on the compile-time passes
+static mh3d_status fast_plane_fwd(mh3d_plan_t p, int src, const float* a) {
+  Timer t(p, KID_PLANE_FWD);
+  p->fast->plane_fwd(p->ls, p->vda, src, a);
+  return last_launch("k_fast_plane_fwd");
+}
+static mh3d_status fast_class(mh3d_plan_t p, int chk, int mode) {
+  Timer t(p, KID_CLASS_NORMAL);
+  p->fast->cls(p->ls, p->vda, mode, chk);
+  return last_launch("k_fast_class");
+}
+static mh3d_status fast_adj_and_store(mh3d_plan_t p, float* d, float* x) {
+  Timer t(p, KID_ADJ_AND_STORE);
+  AdjOut ao;
+  ao.out = x;
+  ao.yin = nullptr;
+  p->fast->adj_and_store(p->ls, p->vda, ao, d, p->g.K * (p->g.mx / p->g.xb), p->L.lds_small);
+  return last_launch("k_fast_adj_and_store");
+}
+// the adjoint plane pass that ends a step (UPD_NORMAL: out, w = yin; UPD_FISTA), then the
+// one-block finish of its FP64 sums
+static mh3d_status fast_adjoint_step(mh3d_plan_t p, int upd, float* o, const float* yin) {
+  AdjOut ao;
+  ao.out = o;
+  ao.yin = yin;
+  {
+    Timer t(p, KID_PLANE_ADJ);
+    p->fast->plane_adj(p->ls, p->vda, upd == UPD_NORMAL ? OUT_STEP_NORMAL : OUT_STEP_FISTA, ao);
+    CHK(last_launch("k_fast_plane_adj"));
+  }
+  Timer t(p, KID_UPDATE);
+  if (upd == UPD_NORMAL) k_vol_finish<UPD_NORMAL><<<1, 256, 0, p->ls>>>(p->vda, nullptr);
+  else k_vol_finish<UPD_FISTA><<<1, 256, 0, p->ls>>>(p->vda, nullptr);
+  return last_launch("k_vol_finish");
+}
 
 static mh3d_status launch_step_and_fwd(mh3d_plan_t p) {
   {
@@ -560,7 +670,7 @@ static mh3d_status upload_desc(mh3d_plan_t p) {
   p->vdu[0] = p->vdh;
   p->vdu[1] = p->vdh;
   p->vdu[1].g.ps = p->ps_solve;
-  p->vdu[1].nb_upd = p->g.C == 1 ? p->ps_solve * p->g.nx : update_blocks(p->g.N);
+  p->vdu[1].nb_upd = use_fast(p) ? p->fast->nbp : (p->g.C == 1 ? p->ps_solve * p->g.nx : update_blocks(p->g.N));
   HIPCHK(hipMemcpyAsync(p->vdd, p->vdu, sizeof p->vdu, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return MH3D_OK;
@@ -785,6 +895,7 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   p->stream = reinterpret_cast<hipStream_t>(desc->stream);
   p->ls = p->stream;
   p->compact = desc->psf ? 0 : 1;
+  p->fast = find_fast(g, p->compact);
   memset(p->ms, 0, sizeof p->ms);
   memset(p->launches, 0, sizeof p->launches);
   auto bail = [&](mh3d_status s) { mh3d_destroy(p); return s; };
@@ -840,6 +951,11 @@ static mh3d_status check_plan(mh3d_plan_t p) {
 extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, float* d, float* x) {
   CHK(check_plan(p));
   if (!rho || !d || !x) return fail(MH3D_ERR_INVALID, "NULL array");
+  if (use_fast(p)) {
+    CHK(fast_plane_fwd(p, SRC_PLAIN, rho));
+    CHK(fast_class(p, 0, NRM_STORE));   // d's spectra and A^T's class pass
+    return fast_adj_and_store(p, d, x);
+  }
   if (fused_class(p)) {
     {
       // the forward plane pass has its launch to itself, as the solver's plane passes
@@ -896,6 +1012,11 @@ extern "C" mh3d_status mh3d_backproject(mh3d_plan_t p, const float* d, float* c)
 
 // out = (A^T A + lambda T^T T)(s w): s from the state (1/||w|| in power iteration).
 static mh3d_status apply_normal_scaled(mh3d_plan_t p, const float* w, float* out) {
+  if (use_fast(p)) {
+    CHK(fast_plane_fwd(p, SRC_SCALED, w));
+    CHK(fast_class(p, 1, NRM_PLAIN));
+    return fast_adjoint_step(p, UPD_NORMAL, out, w);
+  }
   CHK(launch_plane_fwd(p, SRC_SCALED, w));
   if (fused_class(p)) {
     CHK(launch_class_normal(p, 1, NRM_PLAIN));
@@ -970,6 +1091,11 @@ extern "C" mh3d_status mh3d_power_iteration(mh3d_plan_t p, int32_t iters, uint64
 // every later update ran in the previous update's last launch).
 static mh3d_status enqueue_update(mh3d_plan_t p, bool first) {
   Timer t(p, KID_SOLVE_ITER);
+  if (use_fast(p)) {
+    CHK(fast_plane_fwd(p, SRC_FISTA_Y, nullptr));
+    CHK(fast_class(p, 1, NRM_RESID));   // against the data's spectra, held in G'
+    return fast_adjoint_step(p, UPD_FISTA, nullptr, nullptr);
+  }
   if (first || !step_and_fwd(p)) CHK(launch_plane_fwd(p, SRC_FISTA_Y, nullptr));
   if (fused_class(p)) {
     CHK(launch_class_normal(p, 1, NRM_RESID));   // against the data's spectra, held in G'
@@ -1501,7 +1627,12 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
   HIPCHK(hipMalloc(&dtmp, sizeof(float) * (size_t)p->g.K * p->g.M));
   (void)hipMemsetAsync(p->vol[0], 0, sizeof(float) * p->g.N, p->stream);
   (void)hipMemsetAsync(dtmp, 0, sizeof(float) * (size_t)p->g.K * p->g.M, p->stream);
+  const bool fast = use_fast(p);
   auto launch = [&]() -> mh3d_status {
+    // passes 0, 6 and 7 are those of A then A^T: the compile-time ones where the plan has them
+    if (fast && pass == 0) return fast_plane_fwd(p, SRC_PLAIN, p->vol[0]);
+    if (fast && pass == 6) return fast_class(p, 0, NRM_STORE);
+    if (fast && pass == 7) return fast_adj_and_store(p, dtmp, p->vol[1]);
     switch (pass) {
       case 0: return launch_plane_fwd(p, SRC_PLAIN, p->vol[0]);
       case 1: return launch_class_fwd(p, 0, FWD_G);
@@ -1517,6 +1648,7 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
   // the passes' inputs: one full A and A^T first so every intermediate buffer is set
   s = mh3d_forward(p, p->vol[0], dtmp);
   if (s == MH3D_OK) s = mh3d_adjoint(p, dtmp, p->vol[1]);
+  if (s == MH3D_OK && fast) s = mh3d_forward_adjoint(p, p->vol[0], dtmp, p->vol[1]);
   for (int i = 0; i < 3 && s == MH3D_OK; ++i) s = launch();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (s == MH3D_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -1566,6 +1698,19 @@ extern "C" mh3d_status mh3d_plan_get_tiles(mh3d_plan_t p, mh3d_tiles* tiles) {
   tiles->cpw = p->g.cpw;
   tiles->xb = p->g.xb;
   tiles->ps = p->g.ps;
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_plan_path(mh3d_plan_t p, int32_t request, int32_t* active) {
+  CHK(check_plan(p));
+  if (request < -1 || request > 1) return fail(MH3D_ERR_INVALID, "path request must be -1, 0 or 1");
+  if (request >= 0 && (request == 1) != p->fast_on) {
+    if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->fast_on = request == 1;
+    CHK(upload_desc(p));   // the solver's step sums come from the active path's blocks
+  }
+  if (active) *active = use_fast(p) ? 1 : 0;
   return MH3D_OK;
 }
 

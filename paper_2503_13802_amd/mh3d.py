@@ -104,6 +104,7 @@ def library():
     lib.mh3d_net_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int32), i32, ctypes.c_uint64, vp,
                                     ctypes.POINTER(vp)]
     lib.mh3d_backproject.argtypes = [vp, vp, vp]
+    lib.mh3d_plan_path.argtypes = [vp, i32, ctypes.POINTER(i32)]
     lib.mh3d_net_destroy.argtypes = [vp]
     lib.mh3d_net_destroy.restype = None
     lib.mh3d_net_param_count.argtypes = [vp]
@@ -357,6 +358,14 @@ class Plan:
     def set_tiles(self, E=0, cpw=0, xb=0, ps=0):
         t = Tiles(int(E), int(cpw), int(xb), int(ps))
         _check(library().mh3d_plan_set_tiles(self._h, ctypes.byref(t)))
+
+    def path(self, request=-1):
+        """Pass family of the fused sequences (mh3d_plan_path): request 1 for the
+        compile-time passes where the plan has them, 0 for the general ones, -1 to query;
+        returns 1 if the compile-time passes are active."""
+        act = ctypes.c_int32()
+        _check(library().mh3d_plan_path(self._h, int(request), ctypes.byref(act)))
+        return act.value
 
     def autotune(self, cache_path=None):
         """Times candidate tiles and keeps the fastest; returns ((E, cpw, xb, ps), us per A+A^T)."""
