@@ -61,6 +61,50 @@ struct FastGeo {
   static_assert(SY == 1 || SY == 2 || SY == 4 || SY == 3, "length-sy DFT");
 };
 
+// Stockham stages of NL lines of length N held at l*LS + p (LS odd) with consecutive
+// lanes on consecutive lines (the same butterfly of each): with an odd line stride the
+// strided stores of a stage fall in distinct banks, and the lanes of a butterfly
+// position share its twiddles (one broadcast read).
+template <int N, int R, int NS, int SGN, int NL, int LS>
+__device__ __forceinline__ void lf_stage(const float2* __restrict__ in, float2* __restrict__ out, const float2* tw) {
+  constexpr int NB = N / R;
+  constexpr int TWS = N / (NS * R);
+  constexpr int total = NL * NB;
+  for (int b = threadIdx.x; b < total; b += blockDim.x) {
+    const int l = b % NL, j = b / NL;
+    const int k = j % NS;
+    const int base = l * LS;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[base + j + r * NB];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = tw[k * r * TWS];
+        v[r] = SGN < 0 ? cmul(v[r], w) : cmulcj(w, v[r]);
+      }
+    }
+    dft<R, SGN>(v);
+    const int o = base + (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[o + r * NS] = v[r];
+  }
+}
+
+// Length-N transforms (unnormalised) of NL lines in *a, ping-ponging with *b; a barrier
+// ends each stage.  Returns the buffer holding the result.  No leading barrier.
+template <int N, int S, int NS, int SGN, int NL, int LS>
+__device__ __forceinline__ float2* lf_fft(float2* a, float2* b, const float2* tw) {
+  constexpr int R = ct_radix(N, S);
+  if constexpr (R == 0) {
+    return a;
+  } else {
+    lf_stage<N, R, NS, SGN, NL, LS>(a, b, tw);
+    __syncthreads();
+    return lf_fft<N, S + 1, NS * R, SGN, NL, LS>(b, a, tw);
+  }
+}
+
 // Plane-pass block b -> (x-plane, y0).  The blocks of one XCD (b mod 8) take a run of
 // consecutive planes with all their y0, so the sy blocks that complete one plane's slots
 // and the stencil's neighbouring planes share that XCD's L2.
@@ -109,42 +153,55 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   float2* twy = twz + G::NZ;
   float2* B0 = twy + G::MY;
   float2* B1 = B0 + G::PBUF;
-  constexpr int F4R = G::NZ / 4, F4 = G::MY * F4R, NL = (F4 + G::TP - 1) / G::TP;
+  // items (row pair j, 4 columns): rows 2j and 2j+1 of the block (y = sy*y1 + y0) become
+  // the real and imaginary parts of packed line j
+  constexpr int F4R = G::NZ / 4, F4 = G::NP * F4R, NL = (F4 + G::TP - 1) / G::TP;
   const long long pb = (long long)x * G::NY * G::NZ;
   const float* __restrict__ bs = vd.b;
-  float4 va[NL], vb[NL];
+  float4 va[NL][2], vb[NL][2];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     const int f = threadIdx.x + G::TP * i;
     if (f < F4) {
-      const int y1 = f / F4R, c4 = f - (f / F4R) * F4R;
-      const long long off = pb + (long long)(G::SY * y1 + y0) * G::NZ + 4 * c4;
-      va[i] = *reinterpret_cast<const float4*>(a + off);
-      vb[i] = *reinterpret_cast<const float4*>(bs + off);
+      const int j = f / F4R, c4 = f - (f / F4R) * F4R;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const long long off = pb + (long long)(G::SY * (2 * j + h) + y0) * G::NZ + 4 * c4;
+        va[i][h] = *reinterpret_cast<const float4*>(a + off);
+        vb[i][h] = *reinterpret_cast<const float4*>(bs + off);
+      }
     }
   }
   load_table(twz, vd.tw + vd.off[2], G::NZ);
   load_table(twy, vd.tw + vd.off[4], G::MY);
   float c = 1.f;
   if constexpr (SRC == SRC_SCALED) c = (float)vd.st->scale;
-  float* Zf = reinterpret_cast<float*>(B0);
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     const int f = threadIdx.x + G::TP * i;
     if (f < F4) {
-      const int y1 = f / F4R, c4 = f - (f / F4R) * F4R;
-      float u[4];
-      const float av[4] = {va[i].x, va[i].y, va[i].z, va[i].w};
-      const float bv[4] = {vb[i].x, vb[i].y, vb[i].z, vb[i].w};
+      const int j = f / F4R, c4 = f - (f / F4R) * F4R;
+      float u[2][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) u[q] = (SRC == SRC_SCALED) ? bv[q] * (c * av[q]) : bv[q] * av[q];
-      float* row = Zf + 2 * ((y1 >> 1) * G::LSZ + 4 * c4) + (y1 & 1);
+      for (int h = 0; h < 2; ++h) {
+        const float av[4] = {va[i][h].x, va[i][h].y, va[i][h].z, va[i][h].w};
+        const float bv[4] = {vb[i][h].x, vb[i][h].y, vb[i][h].z, vb[i][h].w};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) row[2 * q] = u[q];
+        for (int q = 0; q < 4; ++q) u[h][q] = (SRC == SRC_SCALED) ? bv[q] * (c * av[q]) : bv[q] * av[q];
+      }
+      float4* dst4 = reinterpret_cast<float4*>(B0 + j * G::LSZ + 4 * c4);
+      if constexpr (G::LSZ % 2 == 0) {
+        dst4[0] = make_float4(u[0][0], u[1][0], u[0][1], u[1][1]);
+        dst4[1] = make_float4(u[0][2], u[1][2], u[0][3], u[1][3]);
+      } else {
+        float2* d2 = B0 + j * G::LSZ + 4 * c4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d2[q] = make_float2(u[0][q], u[1][q]);
+      }
     }
   }
   __syncthreads();
-  float2* Z = ct_stages<G::NZ, 0, 1, -1>(B0, B1, twz, G::NP, G::LSZ);
+  float2* Z = lf_fft<G::NZ, 0, 1, -1, G::NP, G::LSZ>(B0, B1, twz);
   float2* X = (Z == B0) ? B1 : B0;
   // split each packed pair into its two half spectra, columns X[qz][y1]
   for (int it = threadIdx.x; it < G::NP * G::NZH; it += G::TP) {
@@ -155,7 +212,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
     X[q * G::LSY + 2 * j + 1] = make_float2(0.5f * (zq.y + zm.y), -0.5f * (zq.x - zm.x));
   }
   __syncthreads();
-  const float2* Y = ct_stages<G::MY, 0, 1, -1>(X, Z, twy, G::NZH, G::LSY);
+  const float2* Y = lf_fft<G::MY, 0, 1, -1, G::NZH, G::LSY>(X, Z, twy);
   // slots of plane x for this y0: class c, members jz (SZ consecutive complex)
   float2* __restrict__ dst = vd.uperm + (long long)x * G::PLANE + y0 * G::SZ;
   for (int c = threadIdx.x; c < G::NCLS; c += G::TP) {
@@ -212,12 +269,12 @@ __global__ __launch_bounds__(G::TC) void k_fast_class(const VolDesc* __restrict_
   const int rem = e0 - cl * (MX * S);
   const int qxp = rem / S;
   const int within = rem - qxp * S;
-  // every harmonic's spectra of this thread's elements (contiguous: [k][class][q'x][jx][member])
-  HLoad<0, E> hb[KMAX];
-  const long long hoff0 = (long long)c0 * MX * S + e0;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k)
-    if (k < K) hb[k].load(vd.hs, (long long)k * G::HSZ + hoff0);
+  // Issue order matters: vector-memory counters retire in order, so a wait for a load
+  // also waits for every load issued before it.  Small tables and the data term first,
+  // then the slot loads, then the spectra (not needed until after the x transform), so
+  // the transform runs while the spectra stream in.
+  load_table(twx, vd.tw + vd.off[0], NX);
+  load_table(twm, vd.tw + vd.off[3], MX);
   if constexpr (MODE == NRM_RESID) {
     const float2* __restrict__ Dt = vd.Gp;
     for (int p = t; p < K * CPW * MX; p += G::TC) {
@@ -225,8 +282,6 @@ __global__ __launch_bounds__(G::TC) void k_fast_class(const VolDesc* __restrict_
       F1[p] = Dt[((long long)k * G::NCLS + c0) * MX + r];
     }
   }
-  load_table(twx, vd.tw + vd.off[0], NX);
-  load_table(twm, vd.tw + vd.off[3], MX);
   if constexpr (SY > 1) {
     for (int p = t; p < CPW * SY; p += G::TC) {
       const int c = p / SY, y0 = p - c * SY;
@@ -235,26 +290,47 @@ __global__ __launch_bounds__(G::TC) void k_fast_class(const VolDesc* __restrict_
     }
     __syncthreads();
   }
-  // slots -> alias members: twiddle and length-sy DFT over y0 at each (x, jz)
+  // slots (y0, jz) of the block's classes at each x, into registers
   const float2* __restrict__ up = vd.uperm;
   constexpr int NIT = CPW * NX * SZ;
-  for (int it = t; it < NIT; it += G::TC) {
-    const int c = it / (NX * SZ), r = it - c * (NX * SZ);
-    const int xx = r / SZ, jz = r - (r / SZ) * SZ;
-    const float2* src = up + (long long)xx * G::PLANE + (long long)(c0 + c) * NMEM + jz;
-    float2 v[SY];
+  constexpr int NI = (NIT + G::TC - 1) / G::TC;
+  float2 sv[NI][SY];
 #pragma unroll
-    for (int y0 = 0; y0 < SY; ++y0) v[y0] = src[y0 * SZ];
-    if constexpr (SY > 1) {
+  for (int i = 0; i < NI; ++i) {
+    const int it = t + i * G::TC;
+    if (NIT % G::TC == 0 || it < NIT) {
+      const int c = it / (NX * SZ), r = it - c * (NX * SZ);
+      const int xx = r / SZ, jz = r - (r / SZ) * SZ;
+      const float2* src = up + (long long)xx * G::PLANE + (long long)(c0 + c) * NMEM + jz;
 #pragma unroll
-      for (int y0 = 1; y0 < SY; ++y0) v[y0] = cmul(v[y0], twc[c * SY + y0]);
-      dft<SY, -1>(v);
+      for (int y0 = 0; y0 < SY; ++y0) sv[i][y0] = src[y0 * SZ];
     }
+  }
+  // every harmonic's spectra of this thread's elements (contiguous: [k][class][q'x][jx][member])
+  HLoad<0, E> hb[KMAX];
+  const long long hoff0 = (long long)c0 * MX * S + e0;
 #pragma unroll
-    for (int jy = 0; jy < SY; ++jy) U0[(c * NMEM + jy * SZ + jz) * LSX + xx] = v[jy];
+  for (int k = 0; k < KMAX; ++k)
+    if (k < K) hb[k].load(vd.hs, (long long)k * G::HSZ + hoff0);
+  // slots -> alias members: twiddle and length-sy DFT over y0 at each (x, jz)
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int it = t + i * G::TC;
+    if (NIT % G::TC == 0 || it < NIT) {
+      const int c = it / (NX * SZ), r = it - c * (NX * SZ);
+      const int xx = r / SZ, jz = r - (r / SZ) * SZ;
+      float2* v = sv[i];
+      if constexpr (SY > 1) {
+#pragma unroll
+        for (int y0 = 1; y0 < SY; ++y0) v[y0] = cmul(v[y0], twc[c * SY + y0]);
+        dft<SY, -1>(v);
+      }
+#pragma unroll
+      for (int jy = 0; jy < SY; ++jy) U0[(c * NMEM + jy * SZ + jz) * LSX + xx] = v[jy];
+    }
   }
   __syncthreads();
-  const float2* U = ct_stages<NX, 0, 1, -1>(U0, U1, twx, W, LSX);
+  const float2* U = lf_fft<NX, 0, 1, -1, W, LSX>(U0, U1, twx);
   float2 ur[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -299,7 +375,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_class(const VolDesc* __restrict_
     U0[(cl * NMEM + m) * LSX + qxp + jx * MX] = acc[i];
   }
   __syncthreads();
-  const float2* V = ct_stages<NX, 0, 1, +1>(U0, U1, twx, W, LSX);
+  const float2* V = lf_fft<NX, 0, 1, +1, W, LSX>(U0, U1, twx);
   // alias members -> slots: inverse length-sy DFT over jy, conjugate twiddles
   float2* __restrict__ vp = vd.uperm;
   for (int it = t; it < NIT; it += G::TC) {
@@ -352,25 +428,45 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
   float2* B1 = B0 + G::PBUF;
   const int t = threadIdx.x;
   const int nt = blockDim.x;
-  // this y0's slots of every class, staged in B1 as [class][jz]
+  // this y0's slots of every class, staged in B1 as [class][jz]; every load is issued
+  // before the first is used (and, for A^T, the sensitivity rows of the output too)
+  const long long pb = (long long)x * G::NY * G::NZ;
+  const float* __restrict__ bs = vd.b;
+  constexpr int F4R = G::NZ / 4, P4 = G::NP * F4R, NB4 = (P4 + G::TP - 1) / G::TP;
+  float4 bq[kStep ? 1 : NB4][2];
   {
     const float2* __restrict__ src = vd.uperm + (long long)x * G::PLANE + y0 * G::SZ;
-    if constexpr (G::SZ % 2 == 0) {
-      constexpr int H = G::SZ / 2, N4 = G::NCLS * H;
-      batched<4, float4>(N4,
-                         [&](int p) {
-                           const int c = p / H, h = p - (p / H) * H;
-                           return *reinterpret_cast<const float4*>(src + (long long)c * G::NMEM + 2 * h);
-                         },
-                         [&](int p, float4 v) {
-                           const int c = p / H, h = p - (p / H) * H;
-                           B1[c * G::SZ + 2 * h] = make_float2(v.x, v.y);
-                           B1[c * G::SZ + 2 * h + 1] = make_float2(v.z, v.w);
-                         });
-    } else {
-      batched<4, float2>(G::NCLS * G::SZ,
-                         [&](int p) { return src[(long long)(p / G::SZ) * G::NMEM + p % G::SZ]; },
-                         [&](int p, float2 v) { B1[p] = v; });
+    static_assert(G::SZ % 2 == 0, "slots are loaded in pairs");
+    constexpr int H = G::SZ / 2, N4 = G::NCLS * H, NS4 = (N4 + G::TP - 1) / G::TP;
+    float4 sl[NS4];
+#pragma unroll
+    for (int i = 0; i < NS4; ++i) {
+      const int p = t + i * G::TP;
+      if (p < N4) {
+        const int c = p / H, h = p - (p / H) * H;
+        sl[i] = *reinterpret_cast<const float4*>(src + (long long)c * G::NMEM + 2 * h);
+      }
+    }
+    if constexpr (!kStep) {
+#pragma unroll
+      for (int i = 0; i < NB4; ++i) {
+        const int f = t + i * G::TP;
+        if (f < P4) {
+          const int j = f / F4R, c4 = f - (f / F4R) * F4R;
+          const long long o0 = pb + (long long)(G::SY * 2 * j + y0) * G::NZ + 4 * c4;
+          bq[i][0] = *reinterpret_cast<const float4*>(bs + o0);
+          bq[i][1] = *reinterpret_cast<const float4*>(bs + o0 + (long long)G::SY * G::NZ);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NS4; ++i) {
+      const int p = t + i * G::TP;
+      if (p < N4) {
+        const int c = p / H, h = p - (p / H) * H;
+        B1[c * G::SZ + 2 * h] = make_float2(sl[i].x, sl[i].y);
+        B1[c * G::SZ + 2 * h + 1] = make_float2(sl[i].z, sl[i].w);
+      }
     }
   }
   load_table(twz, vd.tw + vd.off[2], G::NZ);
@@ -393,7 +489,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
     B0[qz * G::LSY + qyp] = v;
   }
   __syncthreads();
-  float2* X = ct_stages<G::MY, 0, 1, +1>(B0, B1, twy, G::NZH, G::LSY);
+  float2* X = lf_fft<G::MY, 0, 1, +1, G::NZH, G::LSY>(B0, B1, twy);
   float2* Zb = (X == B0) ? B1 : B0;
   // C2R along z: packed rows Z[j] = X[2j] + i X[2j+1] with the Hermitian extension
   for (int it = t; it < G::NP * G::NZ; it += nt) {
@@ -407,24 +503,24 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
     Zb[j * G::LSZ + q] = make_float2(xv.x - yv.y, xv.y + yv.x);
   }
   __syncthreads();
-  const float2* Z = ct_stages<G::NZ, 0, 1, +1>(Zb, X, twz, G::NP, G::LSZ);
+  const float2* Z = lf_fft<G::NZ, 0, 1, +1, G::NP, G::LSZ>(Zb, X, twz);
   const float* Zf = reinterpret_cast<const float*>(Z);
-  const long long pb = (long long)x * G::NY * G::NZ;
-  const float* __restrict__ bs = vd.b;
-  constexpr int F4R = G::NZ / 4, F4 = G::MY * F4R;
   if constexpr (!kStep) {
+    // items (row pair j, 4 columns): packed line j holds rows 2j (real) and 2j+1 (imaginary)
     float* __restrict__ out = ao.out;
-    batched<4, float4>(F4,
-                       [&](int f) {
-                         const int y1 = f / F4R, c4 = f - (f / F4R) * F4R;
-                         return *reinterpret_cast<const float4*>(bs + pb + (long long)(G::SY * y1 + y0) * G::NZ + 4 * c4);
-                       },
-                       [&](int f, float4 bv) {
-                         const int y1 = f / F4R, c4 = f - (f / F4R) * F4R;
-                         const float* zr = Zf + 2 * ((y1 >> 1) * G::LSZ + 4 * c4) + (y1 & 1);
-                         *reinterpret_cast<float4*>(out + pb + (long long)(G::SY * y1 + y0) * G::NZ + 4 * c4) =
-                             make_float4(bv.x * zr[0], bv.y * zr[2], bv.z * zr[4], bv.w * zr[6]);
-                       });
+#pragma unroll
+    for (int i = 0; i < NB4; ++i) {
+      const int f = t + i * G::TP;
+      if (f >= P4) break;
+      const int j = f / F4R, c4 = f - (f / F4R) * F4R;
+      const long long o0 = pb + (long long)(G::SY * 2 * j + y0) * G::NZ + 4 * c4;
+      const long long o1 = o0 + (long long)G::SY * G::NZ;
+      const float4 b0 = bq[i][0], b1 = bq[i][1];
+      const float2* zr = Z + j * G::LSZ + 4 * c4;
+      const float2 z0 = zr[0], z1 = zr[1], z2 = zr[2], z3 = zr[3];
+      *reinterpret_cast<float4*>(out + o0) = make_float4(b0.x * z0.x, b0.y * z1.x, b0.z * z2.x, b0.w * z3.x);
+      *reinterpret_cast<float4*>(out + o1) = make_float4(b1.x * z0.y, b1.y * z1.y, b1.z * z2.y, b1.w * z3.y);
+    }
   } else {
     constexpr int UPD = OUT == OUT_STEP_NORMAL ? UPD_NORMAL : UPD_FISTA;
     constexpr int NV = StepCtx<UPD>::NV;
