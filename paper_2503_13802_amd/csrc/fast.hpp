@@ -1,64 +1,94 @@
 // Compile-time-geometry passes of the fused operator sequences (A then A^T, the normal
-// operator and the solver updates) for scalar plans with analytic (compact) spectra and
-// no boundary padding, on the grids listed in the dispatch table of mh3d.hip.
+// operator and the solver updates) for scalar plans with the analytic PSF and no
+// boundary padding, on the grids listed in the dispatch table of mh3d.hip.
 //
-// The operator is the same A = P H B as in kernels.hpp (Sec. 4.1 eq. dN, Table tab:ops),
-// with the 3-D FFT split differently between the passes:
+// They compute the operator A = P H B of kernels.hpp (Sec. 4.1 eq. dN, Table tab:ops)
+// through two factorisations:
 //
-//  * The y-transform is split in two (a four-step factorisation of the length-ny DFT):
-//    with y = sy*y1 + y0 and qy = q'y + my*jy,
-//        Uhat(qy) = sum_y0 w_ny^(y0 q'y) w_sy^(y0 jy) V(y0, q'y),
-//        V(y0, q'y) = sum_y1 u(sy*y1 + y0) w_my^(y1 q'y).
-//    The plane pass runs one workgroup per (x-plane, y0): it loads the my rows
-//    y = sy*y1 + y0, transforms them along z (R2C) and along y1 (length my), and stores
-//    V.  The class pass, which owns all sy aliases jy of its q'y, applies the twiddles
-//    w_ny^(y0 q'y) and the length-sy DFT over y0 as it loads.  The plane passes thus run
-//    sy times as many workgroups, each on 1/sy of a plane.
-//  * Class-layout slot (class c = (q'y, q'z), y0, jz) of x-plane x holds V(y0, q'y, qz) for
-//    qz = q'z + mz*jz <= nz/2, else conj V(y0, -q'y, nz - qz) (the Hermitian partner in the
-//    plane, as the full-transform layout of geo.hpp does), so the class pass applies the
-//    same two steps to every slot and obtains the full-grid spectrum of each alias member.
-//    The adjoint mirrors both steps: inverse length-sy DFT and conjugate twiddles in the
-//    class pass, inverse length-my DFT and C2R along z in the plane pass.
-//  * The fused class pass keeps each thread's spectrum elements of every harmonic in
-//    registers (loaded at its start, reused by the adjoint products), so it waits on one
-//    round of spectrum loads; index arithmetic is on compile-time sizes.
+//  * The analytic PSF is separable, h_k(x, y, z) = c_k L^(k)(a x) E(y, z) (Sec. 3.3
+//    eq. hkapprox), so Hhat_k(qx, qy, qz) = F_k(qx) Ehat(qy, qz).  The transverse factor
+//    is common to every harmonic: A_k u = P_x [ f_k (*)_x P_yz [ E (*)_yz u ] ].  The plane
+//    passes apply Ehat and fold the (y, z) aliases of each x-plane (P_yz in Fourier form),
+//    leaving my (mz/2 + 1) values per plane; the column pass transforms each of these
+//    columns along x, multiplies by every F_k and folds the x aliases.  The spectra are
+//    never stored: K nx + sy my (nz/2 + 1) numbers replace K nx ny (nz/2 + 1).  Ehat is
+//    real and even in qy and qz (E is even in y and z with the symmetric sampling of the
+//    even-length midpoint), F_k is real for odd derivative orders and imaginary for even.
+//  * The y-transform is split four-step: with y = sy*y1 + y0 and qy = q'y + my*jy,
+//        Uhat(qy) = sum_y0 w_ny^(y0 qy) V(y0, q'y),  V(y0, q'y) = sum_y1 u(sy*y1 + y0) w_my^(y1 q'y),
+//    so the Ehat-weighted fold over jy of one residue y0 is V(y0, q'y) times
+//        Et(y0, q'y, qz) = sum_jy w_ny^(y0 qy) Ehat(qy, qz)   (a plan-time table).
+//    Each plane workgroup takes one (x-plane, y0): it loads the my rows y = sy*y1 + y0,
+//    transforms them along z (R2C) and y1, and writes its share of the folded plane,
+//        C(y0; x, q'y, q'z) = sum_jz Et(y0, q'y, qz) V(y0, q'y, qz),  qz = q'z + mz*jz,
+//    (for qz > nz/2 the Hermitian partner conj V(y0, -q'y, nz - qz), Et even in qz); the
+//    column pass sums the sy shares.  The adjoint mirrors it: the column pass leaves Q(x,
+//    q'y, q'z) = x-transform of sum_k conj(F_k) R_k, and plane workgroup (x, y0) forms
+//    the residue's spectrum Q(x, q'y, qz mod mz) conj(Et(y0, q'y, qz)) (Q Hermitian in
+//    (q'y, q'z) for the q'z beyond mz/2), transforms it back along y1 and z (C2R) and
+//    multiplies by b.
 //
-// Each call sequence runs only these passes (the slot layout above is private to them);
-// the separate forward and adjoint calls, vector, padded and batched plans keep the
-// passes of kernels.hpp.
+// Each call sequence runs only these passes (their intermediate layouts are their own);
+// the separate forward and adjoint calls, user PSFs, vector, padded and batched plans
+// keep the passes of kernels.hpp.
 #pragma once
 #include "kernels.hpp"
 
 namespace mh3d {
 
-template <int NX_, int NY_, int NZ_, int SX_, int SY_, int SZ_, int E_, int CPW_, int KMAX_>
+// Plan-time tables of the separable passes (FP64 sums, FP32 storage):
+//   sfs[k][qx]        scale_k F_k(qx) (its real part, or its imaginary part when bit k of
+//                     imag_mask is set), the x factor of the stored spectra
+//   set[y0][q'y][qz]  Et(y0, q'y, qz) = sum_jy w_ny^(y0 qy) Ehat(qy, qz), qz <= nz/2
+__global__ void k_sep_tables(Geo g, const double2* __restrict__ fhat, const double2* __restrict__ ehat,
+                             const double* __restrict__ scale, uint32_t imag_mask,
+                             const double2* __restrict__ tw64y, float* __restrict__ sfs, float2* __restrict__ set) {
+  const int nf = g.K * g.nx;
+  const int ne = g.sy * g.my * g.nzh;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nf + ne; t += gridDim.x * blockDim.x) {
+    if (t < nf) {
+      const int k = t / g.nx;
+      const double2 f = fhat[t];
+      sfs[t] = (float)((((imag_mask >> k) & 1u) ? f.y : f.x) * scale[k]);
+    } else {
+      const int r = t - nf;
+      const int y0 = r / (g.my * g.nzh), r2 = r - y0 * (g.my * g.nzh);
+      const int qyp = r2 / g.nzh, qz = r2 - qyp * g.nzh;
+      double sr = 0.0, si = 0.0;
+      for (int jy = 0; jy < g.sy; ++jy) {
+        const int qy = qyp + jy * g.my;
+        const double2 w = tw64y[(long long)y0 * qy % g.ny];   // exp(-2 pi i y0 qy / ny)
+        const double2 e = ehat[(long long)qy * g.nzh + qz];
+        sr += w.x * e.x - w.y * e.y;
+        si += w.x * e.y + w.y * e.x;
+      }
+      set[r] = make_float2((float)sr, (float)si);
+    }
+  }
+}
+
+template <int NX_, int NY_, int NZ_, int SX_, int SY_, int SZ_, int CPC_, int KMAX_>
 struct FastGeo {
   static constexpr int NX = NX_, NY = NY_, NZ = NZ_, SX = SX_, SY = SY_, SZ = SZ_;
   static constexpr int MX = NX / SX, MY = NY / SY, MZ = NZ / SZ;
   static constexpr int NZH = NZ / 2 + 1, MZH = MZ / 2 + 1;
-  static constexpr int NMEM = SY * SZ, S = SX * SY * SZ, NCLS = MY * MZH, PLANE = NCLS * NMEM;
-  static constexpr long long HSZ = (long long)PLANE * NX;   // spectrum elements per harmonic
-  static constexpr int E = E_, CPW = CPW_, KMAX = KMAX_;
-  static constexpr int LG = S / E;                          // threads of one fold group
-  static constexpr int TC = CPW * MX * S / E;               // class-pass threads
-  static constexpr int W = CPW * NMEM;                      // member lines of a class block
+  static constexpr int NCLS = MY * MZH;                     // columns (q'y, q'z)
+  static constexpr int CPC = CPC_, KMAX = KMAX_;
+  static constexpr int TC = CPC * MX;                       // column-pass threads: one per (column, q'x)
   static constexpr int LSX = NX | 1, LSZ = NZ | 1, LSY = MY | 1;
   static constexpr int NP = MY / 2;                         // row pairs of a plane block
   static constexpr int TP = 256;                            // plane-pass threads
   static constexpr int NBP = NX * SY;                       // plane-pass blocks
-  // one plane-pass LDS buffer: packed row pairs, half-spectrum columns or the staged slots
-  static constexpr int PB0 = NP * LSZ, PB1 = NZH * LSY, PB2 = NCLS * SZ;
-  static constexpr int PBUF = PB0 > PB1 ? (PB0 > PB2 ? PB0 : PB2) : (PB1 > PB2 ? PB1 : PB2);
-  static constexpr size_t LDS_PLANE = sizeof(float2) * (NZ + MY + 2 * (size_t)PBUF);
-  static constexpr size_t LDS_CLASS = sizeof(float2) * (NX + MX + 2 * (size_t)W * LSX + 2 * (size_t)KMAX * CPW * MX
-                                                        + (size_t)CPW * SY);
+  // one plane-pass LDS buffer: packed row pairs or half-spectrum columns (+ the staged Q)
+  static constexpr int PB0 = NP * LSZ, PB1 = NZH * LSY;
+  static constexpr int PBUF = PB0 > PB1 ? PB0 : PB1;
+  static constexpr size_t LDS_PLANE = sizeof(float2) * (NZ + MY + 2 * (size_t)PBUF + NCLS);
+  static constexpr size_t LDS_COL = sizeof(float2) * (NX + MX + 2 * (size_t)CPC * LSX + 2 * (size_t)KMAX * CPC * MX);
   static_assert(MY % 2 == 0, "row pairs: my must be even");
-  static_assert((NZ % 4) == 0, "rows are loaded as float4");
-  static_assert(S % E == 0 && (LG & (LG - 1)) == 0 && LG <= 64, "fold groups are aligned lane groups");
-  static_assert(NCLS % CPW == 0, "classes per block must divide the classes");
-  static_assert(TC <= 1024, "class block too large");
-  static_assert(SY == 1 || SY == 2 || SY == 4 || SY == 3, "length-sy DFT");
+  static_assert(NZ % 4 == 0, "rows are loaded as float4");
+  static_assert(MZ % 2 == 0, "the decimated z-axis is even");
+  static_assert(NCLS % CPC == 0, "columns per block must divide the columns");
+  static_assert(TC <= 1024, "column block too large");
 };
 
 // Stockham stages of NL lines of length N held at l*LS + p (LS odd) with consecutive
@@ -106,8 +136,8 @@ __device__ __forceinline__ float2* lf_fft(float2* a, float2* b, const float2* tw
 }
 
 // Plane-pass block b -> (x-plane, y0).  The blocks of one XCD (b mod 8) take a run of
-// consecutive planes with all their y0, so the sy blocks that complete one plane's slots
-// and the stencil's neighbouring planes share that XCD's L2.
+// consecutive planes with all their y0, so the stencil's neighbouring planes and the
+// column pass's runs of x share that XCD's L2.
 template <class G>
 __device__ __forceinline__ void fast_plane_of(int b, int& x, int& y0) {
   if constexpr (G::NX % 8 == 0) {
@@ -120,22 +150,10 @@ __device__ __forceinline__ void fast_plane_of(int b, int& x, int& y0) {
   }
 }
 
-// Sum over aligned groups of LG lanes (every lane of a group gets the group's sum).
-// Lane groups of up to 16 use DPP moves inside a row; wider groups use shuffles.
-template <int LG>
-__device__ __forceinline__ float group_sum(float v) {
-  if constexpr (LG >= 2) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  if constexpr (LG >= 4) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  if constexpr (LG >= 8) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
-  if constexpr (LG >= 16) v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
-  if constexpr (LG >= 32) v += __shfl_xor(v, 16, 64);
-  if constexpr (LG >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
 // ============================================================================ plane pass (forward)
 // Block (x, y0): u = b . a on rows y = sy*y1 + y0 of plane x (a: rho, y^k or s w by SRC),
-// R2C along z, length-my DFT along y1, slots stored for the class pass.
+// R2C along z, length-my DFT along y1, then the share C(y0; x, q'y, q'z) of the folded
+// plane into cp[y0][column][x].
 template <class G, int SRC>
 __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ a) {
   const VolDesc& vd = vds[0];
@@ -153,15 +171,16 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   float2* twy = twz + G::NZ;
   float2* B0 = twy + G::MY;
   float2* B1 = B0 + G::PBUF;
-  // items (row pair j, 4 columns): rows 2j and 2j+1 of the block (y = sy*y1 + y0) become
-  // the real and imaginary parts of packed line j
+  const int t = threadIdx.x;
+  // items (row pair j, 4 columns): rows 2j and 2j+1 of the block become the real and
+  // imaginary parts of packed line j
   constexpr int F4R = G::NZ / 4, F4 = G::NP * F4R, NL = (F4 + G::TP - 1) / G::TP;
   const long long pb = (long long)x * G::NY * G::NZ;
   const float* __restrict__ bs = vd.b;
   float4 va[NL][2], vb[NL][2];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    const int f = threadIdx.x + G::TP * i;
+    const int f = t + G::TP * i;
     if (f < F4) {
       const int j = f / F4R, c4 = f - (f / F4R) * F4R;
 #pragma unroll
@@ -172,13 +191,29 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
       }
     }
   }
+  // the table Et of this y0 for the block's output columns (SZ values per column)
+  constexpr int NC = (G::NCLS + G::TP - 1) / G::TP;
+  const float2* __restrict__ et = vd.set + (long long)y0 * G::MY * G::NZH;
+  float2 ev[NC][G::SZ];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    const int c = t + G::TP * i;
+    if (c < G::NCLS) {
+      const int qyp = c / G::MZH, qzp = c - (c / G::MZH) * G::MZH;
+#pragma unroll
+      for (int jz = 0; jz < G::SZ; ++jz) {
+        const int qz = qzp + G::MZ * jz;
+        ev[i][jz] = et[qyp * G::NZH + (2 * qz <= G::NZ ? qz : G::NZ - qz)];
+      }
+    }
+  }
   load_table(twz, vd.tw + vd.off[2], G::NZ);
   load_table(twy, vd.tw + vd.off[4], G::MY);
   float c = 1.f;
   if constexpr (SRC == SRC_SCALED) c = (float)vd.st->scale;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    const int f = threadIdx.x + G::TP * i;
+    const int f = t + G::TP * i;
     if (f < F4) {
       const int j = f / F4R, c4 = f - (f / F4R) * F4R;
       float u[2][4];
@@ -189,22 +224,16 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
 #pragma unroll
         for (int q = 0; q < 4; ++q) u[h][q] = (SRC == SRC_SCALED) ? bv[q] * (c * av[q]) : bv[q] * av[q];
       }
-      float4* dst4 = reinterpret_cast<float4*>(B0 + j * G::LSZ + 4 * c4);
-      if constexpr (G::LSZ % 2 == 0) {
-        dst4[0] = make_float4(u[0][0], u[1][0], u[0][1], u[1][1]);
-        dst4[1] = make_float4(u[0][2], u[1][2], u[0][3], u[1][3]);
-      } else {
-        float2* d2 = B0 + j * G::LSZ + 4 * c4;
+      float2* d2 = B0 + j * G::LSZ + 4 * c4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d2[q] = make_float2(u[0][q], u[1][q]);
-      }
+      for (int q = 0; q < 4; ++q) d2[q] = make_float2(u[0][q], u[1][q]);
     }
   }
   __syncthreads();
   float2* Z = lf_fft<G::NZ, 0, 1, -1, G::NP, G::LSZ>(B0, B1, twz);
   float2* X = (Z == B0) ? B1 : B0;
   // split each packed pair into its two half spectra, columns X[qz][y1]
-  for (int it = threadIdx.x; it < G::NP * G::NZH; it += G::TP) {
+  for (int it = t; it < G::NP * G::NZH; it += G::TP) {
     const int j = it / G::NZH, q = it - (it / G::NZH) * G::NZH;
     const float2 zq = Z[j * G::LSZ + q];
     const float2 zm = Z[j * G::LSZ + (q == 0 ? 0 : G::NZ - q)];
@@ -213,203 +242,145 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   }
   __syncthreads();
   const float2* Y = lf_fft<G::MY, 0, 1, -1, G::NZH, G::LSY>(X, Z, twy);
-  // slots of plane x for this y0: class c, members jz (SZ consecutive complex)
-  float2* __restrict__ dst = vd.uperm + (long long)x * G::PLANE + y0 * G::SZ;
-  for (int c = threadIdx.x; c < G::NCLS; c += G::TP) {
-    const int qyp = c / G::MZH, qzp = c - (c / G::MZH) * G::MZH;
-    float2 v[G::SZ];
+  // this residue's share of the folded plane
+  float2* __restrict__ dst = vd.cp + (long long)y0 * G::NCLS * G::NX + x;
 #pragma unroll
-    for (int jz = 0; jz < G::SZ; ++jz) {
-      const int qz = qzp + G::MZ * jz;
-      if (2 * qz <= G::NZ) {
-        v[jz] = Y[qz * G::LSY + qyp];
-      } else {
-        const float2 w = Y[(G::NZ - qz) * G::LSY + (qyp == 0 ? 0 : G::MY - qyp)];
-        v[jz] = make_float2(w.x, -w.y);
+  for (int i = 0; i < NC; ++i) {
+    const int cc = t + G::TP * i;
+    if (cc < G::NCLS) {
+      const int qyp = cc / G::MZH, qzp = cc - (cc / G::MZH) * G::MZH;
+      float sx = 0.f, sy = 0.f;
+#pragma unroll
+      for (int jz = 0; jz < G::SZ; ++jz) {
+        const int qz = qzp + G::MZ * jz;
+        float2 v;
+        if (2 * qz <= G::NZ) {
+          v = Y[qz * G::LSY + qyp];
+        } else {
+          const float2 w = Y[(G::NZ - qz) * G::LSY + (qyp == 0 ? 0 : G::MY - qyp)];
+          v = make_float2(w.x, -w.y);
+        }
+        const float2 e = ev[i][jz];
+        sx += e.x * v.x - e.y * v.y;
+        sy += e.x * v.y + e.y * v.x;
       }
-    }
-    float2* o = dst + (long long)c * G::NMEM;
-    if constexpr (G::SZ % 2 == 0) {
-#pragma unroll
-      for (int jz = 0; jz < G::SZ; jz += 2)
-        *reinterpret_cast<float4*>(o + jz) = make_float4(v[jz].x, v[jz].y, v[jz + 1].x, v[jz + 1].y);
-    } else {
-#pragma unroll
-      for (int jz = 0; jz < G::SZ; ++jz) o[jz] = v[jz];
+      dst[(long long)cc * G::NX] = make_float2(sx, sy);
     }
   }
 }
 
-// ============================================================================ class pass (fused)
-// Forward products of the block's classes (spectrum Hhat_k times the alias members,
-// folded), then from those folded spectra the adjoint products (sum over k of
-// conj(Hhat_k) times the tiled residual), as class_normal_body does; mode NRM_RESID
-// subtracts the data's spectra (G'), NRM_STORE also writes the portraits' decimated
-// spectra G for the small-grid pass.
+// ============================================================================ column pass
+// Block: CPC columns (q'y, q'z), one thread per (column, q'x) owning the x aliases
+// qx = q'x + mx*jx.  Sums the sy shares of each column, transforms along x, then per
+// harmonic Fhat_k(q'x) = sum_jx F_k(qx) W(qx) (times i for imaginary F_k), the residual
+// R_k = M Fhat_k (- the data's spectrum D_k in NRM_RESID), and Q(qx) = sum_k conj(F_k(qx))
+// R_k(q'x); Q transformed back along x goes to qx[column][x] for the adjoint plane
+// pass.  NRM_STORE also writes the portraits' decimated spectra G (inverse x' transform
+// of Fhat) for the small-grid pass; M Fhat then stands for the spectra of d itself.
 template <class G, int MODE>
-__global__ __launch_bounds__(G::TC) void k_fast_class(const VolDesc* __restrict__ vds, int check_done) {
+__global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ vds, int check_done) {
   const VolDesc& vd = vds[0];
   if (check_done && vd.st->done) return;
-  constexpr int NX = G::NX, MX = G::MX, S = G::S, E = G::E, NMEM = G::NMEM, SY = G::SY, SZ = G::SZ;
-  constexpr int LSX = G::LSX, W = G::W, CPW = G::CPW, KMAX = G::KMAX;
-  const int lb = plane_of_block(blockIdx.x, gridDim.x);
-  const int c0 = lb * CPW;
+  constexpr int NX = G::NX, MX = G::MX, SX = G::SX, CPC = G::CPC, KMAX = G::KMAX, LSX = G::LSX;
+  const int c0 = blockIdx.x * CPC;
   const int K = vd.g.K;
   extern __shared__ float2 lds[];
   float2* twx = lds;
   float2* twm = twx + NX;
   float2* U0 = twm + MX;
-  float2* U1 = U0 + W * LSX;
-  float2* F0 = U1 + W * LSX;
-  float2* F1 = F0 + KMAX * CPW * MX;
-  float2* twc = F1 + KMAX * CPW * MX;   // [cl][y0]: w_ny^(y0 q'y) of each class
+  float2* U1 = U0 + CPC * LSX;
+  float2* F0 = U1 + CPC * LSX;
+  float2* F1 = F0 + KMAX * CPC * MX;
   const int t = threadIdx.x;
-  const int e0 = t * E;
-  const int cl = e0 / (MX * S);
-  const int rem = e0 - cl * (MX * S);
-  const int qxp = rem / S;
-  const int within = rem - qxp * S;
-  // Issue order matters: vector-memory counters retire in order, so a wait for a load
-  // also waits for every load issued before it.  Small tables and the data term first,
-  // then the slot loads, then the spectra (not needed until after the x transform), so
-  // the transform runs while the spectra stream in.
+  const int cl = t / MX, qxp = t - (t / MX) * MX;
+  // the shares of the block's columns: consecutive threads take consecutive x
+  constexpr int NIT = CPC * NX, NI = (NIT + G::TC - 1) / G::TC;
+  float2 sv[NI][G::SY];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int it = t + i * G::TC;
+    if (NIT % G::TC == 0 || it < NIT) {
+      const int c = it / NX, xx = it - (it / NX) * NX;
+#pragma unroll
+      for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = vd.cp[((long long)y0 * G::NCLS + c0 + c) * NX + xx];
+    }
+  }
+  // x factors of the thread's aliases and (residual) the data's spectra
+  float fs[KMAX][SX];
+  float2 dt[MODE == NRM_RESID ? KMAX : 1];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+#pragma unroll
+      for (int jx = 0; jx < SX; ++jx) fs[k][jx] = vd.sfs[k * NX + qxp + jx * MX];
+      if constexpr (MODE == NRM_RESID) dt[k] = vd.Gp[((long long)k * G::NCLS + c0 + cl) * MX + qxp];
+    }
+  }
   load_table(twx, vd.tw + vd.off[0], NX);
   load_table(twm, vd.tw + vd.off[3], MX);
-  if constexpr (MODE == NRM_RESID) {
-    const float2* __restrict__ Dt = vd.Gp;
-    for (int p = t; p < K * CPW * MX; p += G::TC) {
-      const int k = p / (CPW * MX), r = p - k * (CPW * MX);
-      F1[p] = Dt[((long long)k * G::NCLS + c0) * MX + r];
-    }
-  }
-  if constexpr (SY > 1) {
-    for (int p = t; p < CPW * SY; p += G::TC) {
-      const int c = p / SY, y0 = p - c * SY;
-      const int qyp = (c0 + c) / G::MZH;
-      twc[p] = vd.tw[vd.off[1] + (y0 * qyp) % G::NY];
-    }
-    __syncthreads();
-  }
-  // slots (y0, jz) of the block's classes at each x, into registers
-  const float2* __restrict__ up = vd.uperm;
-  constexpr int NIT = CPW * NX * SZ;
-  constexpr int NI = (NIT + G::TC - 1) / G::TC;
-  float2 sv[NI][SY];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int it = t + i * G::TC;
     if (NIT % G::TC == 0 || it < NIT) {
-      const int c = it / (NX * SZ), r = it - c * (NX * SZ);
-      const int xx = r / SZ, jz = r - (r / SZ) * SZ;
-      const float2* src = up + (long long)xx * G::PLANE + (long long)(c0 + c) * NMEM + jz;
+      const int c = it / NX, xx = it - (it / NX) * NX;
+      float2 s = sv[i][0];
 #pragma unroll
-      for (int y0 = 0; y0 < SY; ++y0) sv[i][y0] = src[y0 * SZ];
-    }
-  }
-  // every harmonic's spectra of this thread's elements (contiguous: [k][class][q'x][jx][member])
-  HLoad<0, E> hb[KMAX];
-  const long long hoff0 = (long long)c0 * MX * S + e0;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k)
-    if (k < K) hb[k].load(vd.hs, (long long)k * G::HSZ + hoff0);
-  // slots -> alias members: twiddle and length-sy DFT over y0 at each (x, jz)
-#pragma unroll
-  for (int i = 0; i < NI; ++i) {
-    const int it = t + i * G::TC;
-    if (NIT % G::TC == 0 || it < NIT) {
-      const int c = it / (NX * SZ), r = it - c * (NX * SZ);
-      const int xx = r / SZ, jz = r - (r / SZ) * SZ;
-      float2* v = sv[i];
-      if constexpr (SY > 1) {
-#pragma unroll
-        for (int y0 = 1; y0 < SY; ++y0) v[y0] = cmul(v[y0], twc[c * SY + y0]);
-        dft<SY, -1>(v);
-      }
-#pragma unroll
-      for (int jy = 0; jy < SY; ++jy) U0[(c * NMEM + jy * SZ + jz) * LSX + xx] = v[jy];
+      for (int y0 = 1; y0 < G::SY; ++y0) s = cadd(s, sv[i][y0]);
+      U0[c * LSX + xx] = s;
     }
   }
   __syncthreads();
-  const float2* U = lf_fft<NX, 0, 1, -1, W, LSX>(U0, U1, twx);
-  float2 ur[E];
+  float2* U = lf_fft<NX, 0, 1, -1, CPC, LSX>(U0, U1, twx);
+  float2 w[SX];
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int w = within + i;
-    const int jx = w / NMEM, m = w - (w / NMEM) * NMEM;
-    ur[i] = U[(cl * NMEM + m) * LSX + qxp + jx * MX];
-  }
+  for (int jx = 0; jx < SX; ++jx) w[jx] = U[cl * LSX + qxp + jx * MX];
   const uint32_t imag_mask = vd.imag_mask;
-  const bool lead = (t & (G::LG - 1)) == 0;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      float ax = 0.f, ay = 0.f;
-#pragma unroll
-      for (int i = 0; i < E; ++i) { ax += hb[k].v[i] * ur[i].x; ay += hb[k].v[i] * ur[i].y; }
-      ax = group_sum<G::LG>(ax);
-      ay = group_sum<G::LG>(ay);
-      if (lead) F0[(k * CPW + cl) * MX + qxp] = ((imag_mask >> k) & 1u) ? make_float2(-ay, ax) : make_float2(ax, ay);
-    }
-  }
-  __syncthreads();   // Fhat complete; the member lines are free
   const float Mf = (float)(G::MX * G::MY * G::MZ);
-  float2 acc[E];
+  float2 q[SX];
 #pragma unroll
-  for (int i = 0; i < E; ++i) acc[i] = make_float2(0.f, 0.f);
+  for (int jx = 0; jx < SX; ++jx) q[jx] = make_float2(0.f, 0.f);
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     if (k < K) {
-      const int fi = (k * CPW + cl) * MX + qxp;
-      const float2 f = F0[fi];
+      float fx = 0.f, fy = 0.f;
+#pragma unroll
+      for (int jx = 0; jx < SX; ++jx) { fx += fs[k][jx] * w[jx].x; fy += fs[k][jx] * w[jx].y; }
+      const bool im = (imag_mask >> k) & 1u;
+      float2 f = im ? make_float2(-fy, fx) : make_float2(fx, fy);
+      if constexpr (MODE == NRM_STORE) F0[(k * CPC + cl) * MX + qxp] = f;
       float2 R = make_float2(Mf * f.x, Mf * f.y);
-      if constexpr (MODE == NRM_RESID) R = csub(R, F1[fi]);
-      if ((imag_mask >> k) & 1u) R = make_float2(R.y, -R.x);   // conj(i h) R = -i h R
+      if constexpr (MODE == NRM_RESID) R = csub(R, dt[k]);
+      if (im) R = make_float2(R.y, -R.x);   // conj(i F) R = -i F R
 #pragma unroll
-      for (int i = 0; i < E; ++i) { acc[i].x += hb[k].v[i] * R.x; acc[i].y += hb[k].v[i] * R.y; }
+      for (int jx = 0; jx < SX; ++jx) { q[jx].x += fs[k][jx] * R.x; q[jx].y += fs[k][jx] * R.y; }
     }
   }
+  __syncthreads();   // every thread has read its aliases of U
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int w = within + i;
-    const int jx = w / NMEM, m = w - (w / NMEM) * NMEM;
-    U0[(cl * NMEM + m) * LSX + qxp + jx * MX] = acc[i];
-  }
+  for (int jx = 0; jx < SX; ++jx) U0[cl * LSX + qxp + jx * MX] = q[jx];
   __syncthreads();
-  const float2* V = lf_fft<NX, 0, 1, +1, W, LSX>(U0, U1, twx);
-  // alias members -> slots: inverse length-sy DFT over jy, conjugate twiddles
-  float2* __restrict__ vp = vd.uperm;
+  const float2* V = lf_fft<NX, 0, 1, +1, CPC, LSX>(U0, U1, twx);
+  float2* __restrict__ qo = vd.qx + (long long)c0 * NX;
   for (int it = t; it < NIT; it += G::TC) {
-    const int c = it / (NX * SZ), r = it - c * (NX * SZ);
-    const int xx = r / SZ, jz = r - (r / SZ) * SZ;
-    float2 v[SY];
-#pragma unroll
-    for (int jy = 0; jy < SY; ++jy) v[jy] = V[(c * NMEM + jy * SZ + jz) * LSX + xx];
-    if constexpr (SY > 1) {
-      dft<SY, +1>(v);
-#pragma unroll
-      for (int y0 = 1; y0 < SY; ++y0) v[y0] = cmulcj(twc[c * SY + y0], v[y0]);
-    }
-    float2* dst = vp + (long long)xx * G::PLANE + (long long)(c0 + c) * NMEM + jz;
-#pragma unroll
-    for (int y0 = 0; y0 < SY; ++y0) dst[y0 * SZ] = v[y0];
+    const int c = it / NX, xx = it - (it / NX) * NX;
+    qo[it] = V[c * LSX + xx];
   }
   if constexpr (MODE == NRM_STORE) {
-    const float2* F = ct_stages<MX, 0, 1, +1>(F0, F1, twm, K * CPW, MX);
+    const float2* F = ct_stages<MX, 0, 1, +1>(F0, F1, twm, K * CPC, MX);
     float2* __restrict__ Gs = vd.G;
-    const Geo& g = vd.g;
-    const int xb = g.xb, nxb = MX / xb;
-    for (int p = t; p < K * CPW * MX; p += G::TC) {
-      const int k = p / (CPW * MX), r = p - k * (CPW * MX);
-      const int xbi = r / (CPW * xb), r2 = r - xbi * (CPW * xb);
+    const int xb = vd.g.xb, nxb = MX / xb;
+    for (int p = t; p < K * CPC * MX; p += G::TC) {
+      const int k = p / (CPC * MX), r = p - k * (CPC * MX);
+      const int xbi = r / (CPC * xb), r2 = r - xbi * (CPC * xb);
       const int c = r2 / xb, xi = r2 - c * xb;
-      Gs[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi] = F[(k * CPW + c) * MX + xbi * xb + xi];
+      Gs[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi] = F[(k * CPC + c) * MX + xbi * xb + xi];
     }
   }
 }
 
 // ============================================================================ plane pass (adjoint)
-// Block (x, y0): gather this y0's slots into the half spectrum, inverse length-my DFT
-// along y1, C2R along z, then per voxel of rows y = sy*y1 + y0:
+// Block (x, y0): the residue's half spectrum Q(x, q'y, qz mod mz) conj(Et(y0, q'y, qz)),
+// inverse length-my DFT along y1, C2R along z, then per voxel of rows y = sy*y1 + y0:
 //   OUT_SCALE_B      ao.out = b . v
 //   OUT_STEP_NORMAL  / OUT_STEP_FISTA: the solver step with u = b . v (StepCtx), FP64
 //                    block partials in vd.partials[lb] for k_vol_finish (nb_upd = NBP).
@@ -426,73 +397,74 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
   float2* twy = twz + G::NZ;
   float2* B0 = twy + G::MY;
   float2* B1 = B0 + G::PBUF;
+  float2* Qs = B1 + G::PBUF;   // Q(x, column)
   const int t = threadIdx.x;
-  const int nt = blockDim.x;
-  // this y0's slots of every class, staged in B1 as [class][jz]; every load is issued
-  // before the first is used (and, for A^T, the sensitivity rows of the output too)
   const long long pb = (long long)x * G::NY * G::NZ;
   const float* __restrict__ bs = vd.b;
+  // every load is issued before the first is used: Q of the plane, the table Et of y0
+  // and, for A^T, the sensitivity rows of the output
+  constexpr int NQ = (G::NCLS + G::TP - 1) / G::TP;
+  float2 qv[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int c = t + i * G::TP;
+    if (c < G::NCLS) qv[i] = vd.qx[(long long)c * G::NX + x];
+  }
+  constexpr int NE = G::NZH * G::MY, NEI = (NE + G::TP - 1) / G::TP;
+  const float2* __restrict__ et = vd.set + (long long)y0 * G::MY * G::NZH;
+  float2 ev[NEI];
+#pragma unroll
+  for (int i = 0; i < NEI; ++i) {
+    const int it = t + i * G::TP;
+    if (it < NE) {
+      const int qz = it / G::MY, qyp = it - (it / G::MY) * G::MY;
+      ev[i] = et[qyp * G::NZH + qz];
+    }
+  }
   constexpr int F4R = G::NZ / 4, P4 = G::NP * F4R, NB4 = (P4 + G::TP - 1) / G::TP;
   float4 bq[kStep ? 1 : NB4][2];
-  {
-    const float2* __restrict__ src = vd.uperm + (long long)x * G::PLANE + y0 * G::SZ;
-    static_assert(G::SZ % 2 == 0, "slots are loaded in pairs");
-    constexpr int H = G::SZ / 2, N4 = G::NCLS * H, NS4 = (N4 + G::TP - 1) / G::TP;
-    float4 sl[NS4];
+  if constexpr (!kStep) {
 #pragma unroll
-    for (int i = 0; i < NS4; ++i) {
-      const int p = t + i * G::TP;
-      if (p < N4) {
-        const int c = p / H, h = p - (p / H) * H;
-        sl[i] = *reinterpret_cast<const float4*>(src + (long long)c * G::NMEM + 2 * h);
+    for (int i = 0; i < NB4; ++i) {
+      const int f = t + i * G::TP;
+      if (f < P4) {
+        const int j = f / F4R, c4 = f - (f / F4R) * F4R;
+        const long long o0 = pb + (long long)(G::SY * 2 * j + y0) * G::NZ + 4 * c4;
+        bq[i][0] = *reinterpret_cast<const float4*>(bs + o0);
+        bq[i][1] = *reinterpret_cast<const float4*>(bs + o0 + (long long)G::SY * G::NZ);
       }
     }
-    if constexpr (!kStep) {
+  }
 #pragma unroll
-      for (int i = 0; i < NB4; ++i) {
-        const int f = t + i * G::TP;
-        if (f < P4) {
-          const int j = f / F4R, c4 = f - (f / F4R) * F4R;
-          const long long o0 = pb + (long long)(G::SY * 2 * j + y0) * G::NZ + 4 * c4;
-          bq[i][0] = *reinterpret_cast<const float4*>(bs + o0);
-          bq[i][1] = *reinterpret_cast<const float4*>(bs + o0 + (long long)G::SY * G::NZ);
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < NS4; ++i) {
-      const int p = t + i * G::TP;
-      if (p < N4) {
-        const int c = p / H, h = p - (p / H) * H;
-        B1[c * G::SZ + 2 * h] = make_float2(sl[i].x, sl[i].y);
-        B1[c * G::SZ + 2 * h + 1] = make_float2(sl[i].z, sl[i].w);
-      }
-    }
+  for (int i = 0; i < NQ; ++i) {
+    const int c = t + i * G::TP;
+    if (c < G::NCLS) Qs[c] = qv[i];
   }
   load_table(twz, vd.tw + vd.off[2], G::NZ);
   load_table(twy, vd.tw + vd.off[4], G::MY);
   __syncthreads();
-  // half spectrum, columns B0[qz][q'y]: slot of the class holding (q'y, qz) directly, or
-  // the conjugate of the Hermitian partner's slot
-  for (int it = t; it < G::NZH * G::MY; it += nt) {
-    const int qz = it / G::MY, qyp = it - (it / G::MY) * G::MY;
-    const int qzr = qz % G::MZ;
-    float2 v;
-    if (2 * qzr <= G::MZ) {
-      v = B1[(qyp * G::MZH + qzr) * G::SZ + qz / G::MZ];
-    } else {
-      const int qzm = G::NZ - qz;   // the partner's member, > nz/2
-      const int cy = qyp == 0 ? 0 : G::MY - qyp;
-      const float2 w = B1[(cy * G::MZH + qzm % G::MZ) * G::SZ + qzm / G::MZ];
-      v = make_float2(w.x, -w.y);
+  // half spectrum, columns B0[qz][q'y]
+#pragma unroll
+  for (int i = 0; i < NEI; ++i) {
+    const int it = t + i * G::TP;
+    if (it < NE) {
+      const int qz = it / G::MY, qyp = it - (it / G::MY) * G::MY;
+      const int qzr = qz % G::MZ;
+      float2 qq;
+      if (2 * qzr <= G::MZ) {
+        qq = Qs[qyp * G::MZH + qzr];
+      } else {   // Q is Hermitian over (q'y, q'z)
+        const float2 w = Qs[(qyp == 0 ? 0 : G::MY - qyp) * G::MZH + (G::MZ - qzr)];
+        qq = make_float2(w.x, -w.y);
+      }
+      B0[qz * G::LSY + qyp] = cmulcj(ev[i], qq);   // conj(Et) Q
     }
-    B0[qz * G::LSY + qyp] = v;
   }
   __syncthreads();
   float2* X = lf_fft<G::MY, 0, 1, +1, G::NZH, G::LSY>(B0, B1, twy);
   float2* Zb = (X == B0) ? B1 : B0;
   // C2R along z: packed rows Z[j] = X[2j] + i X[2j+1] with the Hermitian extension
-  for (int it = t; it < G::NP * G::NZ; it += nt) {
+  for (int it = t; it < G::NP * G::NZ; it += G::TP) {
     const int j = it / G::NZ, q = it - (it / G::NZ) * G::NZ;
     const bool upper = 2 * q > G::NZ;
     const int qq = upper ? G::NZ - q : q;
@@ -560,7 +532,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_adj(const VolDesc* __restric
   fast_plane_adj_body<G, OUT>(vds[0], blockIdx.x, ao);
 }
 
-// A then A^T after k_fast_class<NRM_STORE>: blocks [0, NBP) run the adjoint plane pass
+// A then A^T after k_fast_col<NRM_STORE>: blocks [0, NBP) run the adjoint plane pass
 // (ao.out = b . v), the others the small-grid inverse pass that writes the portraits d.
 template <class G>
 __global__ __launch_bounds__(256) void k_fast_adj_and_store(const VolDesc* __restrict__ vds, AdjOut ao,

@@ -178,6 +178,14 @@ struct VolDesc {
   // bit k of cmask[i]: component i of harmonic k is present (a PSF block that is
   // identically zero is skipped: no spectrum load, no product)
   uint32_t cmask[3];
+  // Separable analytic spectra (the compile-time passes of fast.hpp): the x factors
+  // sfs[k][qx], the y-residue table set[y0][q'y][qz], and their intermediates, both in
+  // uperm's memory: cp[y0][column][x] (the plane pass's folded shares) and
+  // qx[column][x] (the column pass's output for the adjoint plane pass).
+  const float* sfs;
+  const float2* set;
+  float2* cp;
+  float2* qx;
 };
 
 // Volume and local block index of this block: task table (batched launches) or

@@ -272,6 +272,8 @@ struct mh3d_plan_s {
   void* hs = nullptr;          // spectra in class layout
   float* b = nullptr;          // sensitivity
   float2* uperm = nullptr;     // class-layout yz spectra of one volume (also adjoint V)
+  float* sfs = nullptr;        // separable spectra (analytic PSF): x factors [K][nx]
+  float2* set = nullptr;       // and the y-residue table [sy][my][nz/2 + 1]
   float2* G = nullptr;         // decimated spectra (forward)
   float2* Gp = nullptr;        // decimated spectra (adjoint)
   float* vol[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // rho[0], rho[1], y[0], y[1], u
@@ -325,6 +327,7 @@ static size_t plan_bytes(const Geo& g, bool compact) {
   s += 5 * (size_t)g.N * 4;                           // vol
   s += (size_t)(2 * (g.nx + g.ny + g.nz) + g.mx + g.my + g.mz) * 24;
   s += ((size_t)g.K * g.nx + (size_t)g.ny * g.nz) * 8;
+  if (compact) s += (size_t)g.K * g.nx * 4 + (size_t)g.sy * g.my * g.nzh * 8;   // separable factors
   return s;
 }
 
@@ -402,11 +405,11 @@ struct FastImpl {
     }
   }
   static void cls(hipStream_t s, const VolDesc* vd, int mode, int chk) {
-    const dim3 grid(G::NCLS / G::CPW), block(G::TC);
+    const dim3 grid(G::NCLS / G::CPC), block(G::TC);
     switch (mode) {
-      case NRM_RESID: k_fast_class<G, NRM_RESID><<<grid, block, G::LDS_CLASS, s>>>(vd, chk); break;
-      case NRM_PLAIN: k_fast_class<G, NRM_PLAIN><<<grid, block, G::LDS_CLASS, s>>>(vd, chk); break;
-      default: k_fast_class<G, NRM_STORE><<<grid, block, G::LDS_CLASS, s>>>(vd, chk); break;
+      case NRM_RESID: k_fast_col<G, NRM_RESID><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
+      case NRM_PLAIN: k_fast_col<G, NRM_PLAIN><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
+      default: k_fast_col<G, NRM_STORE><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
     }
   }
   static void plane_adj(hipStream_t s, const VolDesc* vd, int out, AdjOut ao) {
@@ -418,25 +421,28 @@ struct FastImpl {
     k_fast_adj_and_store<G><<<dim3(G::NBP + nsmall), dim3(G::TP), std::max(lds, G::LDS_PLANE), s>>>(vd, ao, d);
   }
   static FastOps ops() {
-    return FastOps{G::NX, G::NY, G::NZ, G::SX, G::SY, G::SZ, G::KMAX, G::NBP, G::NCLS / G::CPW, G::TC,
-                   G::LDS_PLANE, G::LDS_CLASS, &plane_fwd, &cls, &plane_adj, &adj_and_store};
+    return FastOps{G::NX, G::NY, G::NZ, G::SX, G::SY, G::SZ, G::KMAX, G::NBP, G::NCLS / G::CPC, G::TC,
+                   G::LDS_PLANE, G::LDS_COL, &plane_fwd, &cls, &plane_adj, &adj_and_store};
   }
 };
 
-// Grids with compile-time passes: (nx, ny, nz, sx, sy, sz, elements per thread, classes per
-// block, largest harmonic count).
+// Grids with compile-time passes: (nx, ny, nz, sx, sy, sz, columns per column-pass block,
+// largest harmonic count).
 static const FastOps kFast[] = {
-    FastImpl<FastGeo<128, 128, 128, 2, 4, 4, 8, 1, 12>>::ops(),   // 128^3, k = 2..12
-    // small grids of the parity tests: every y split (1 to 4), radix 3, group widths 4 and 8
-    FastImpl<FastGeo<32, 32, 32, 2, 4, 4, 8, 1, 12>>::ops(),
-    FastImpl<FastGeo<16, 24, 16, 2, 2, 2, 1, 1, 8>>::ops(),
-    FastImpl<FastGeo<16, 16, 16, 2, 1, 2, 1, 2, 8>>::ops(),
-    FastImpl<FastGeo<24, 24, 16, 2, 3, 2, 3, 4, 8>>::ops(),
+    FastImpl<FastGeo<128, 128, 128, 2, 4, 4, 4, 12>>::ops(),   // 128^3, k = 2..12
+    // small grids of the parity tests: every y split (1 to 4), radix 3 along x and y
+    FastImpl<FastGeo<32, 32, 32, 2, 4, 4, 4, 12>>::ops(),
+    FastImpl<FastGeo<16, 24, 16, 2, 2, 2, 4, 8>>::ops(),
+    FastImpl<FastGeo<16, 16, 16, 2, 1, 2, 4, 8>>::ops(),
+    FastImpl<FastGeo<24, 24, 16, 2, 3, 2, 4, 8>>::ops(),
 };
 
-// The entry serving plan p (scalar model, analytic spectra, no padding), or NULL.
+// The entry serving plan p (scalar model, analytic spectra, no padding), or NULL.  Its
+// intermediates (sy shares and one more of nx * columns) live in the class-layout
+// buffer, which holds nx * columns * sy * sz values.
 static const FastOps* find_fast(const Geo& g, bool compact) {
   if (!compact || g.C != 1 || g.padded) return nullptr;
+  if (g.sy + 1 > g.nmem) return nullptr;
   for (const FastOps& f : kFast)
     if (f.nx == g.nx && f.ny == g.ny && f.nz == g.nz && f.sx == g.sx && f.sy == g.sy && f.sz == g.sz && g.K <= f.kmax)
       return &f;
@@ -757,6 +763,9 @@ static mh3d_status build_spectra_analytic(mh3d_plan_t p) {
   CHK(last_launch("k_psf_scales"));
   hipLaunchKernelGGL(k_psf_assemble, dim3(2048), dim3(256), 0, p->stream, g, fhat, ehat, scale, p->imag_mask, 1, p->hs);
   CHK(last_launch("k_psf_assemble"));
+  hipLaunchKernelGGL(k_sep_tables, dim3(64), dim3(256), 0, p->stream, g, fhat, ehat, scale, p->imag_mask,
+                     p->tw64 + p->off[1], p->sfs, p->set);
+  CHK(last_launch("k_sep_tables"));
   HIPCHK(hipStreamSynchronize(p->stream));
   (void)hipFree(d_order); (void)hipFree(fhat); (void)hipFree(tmp); (void)hipFree(ehat);
   (void)hipFree(fn2); (void)hipFree(rows); (void)hipFree(scale);
@@ -815,7 +824,7 @@ extern "C" void mh3d_destroy(mh3d_plan_t p) {
   for (auto& e : p->pending) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
   for (auto e : p->free_events) (void)hipEventDestroy(e);
   void* bufs[] = {p->hs, p->b, p->uperm, p->G, p->Gp, p->vol[0], p->vol[1], p->vol[2], p->vol[3], p->vol[4],
-                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st, p->vdd, p->vdk, p->hist};
+                  p->tw32, p->tw64, p->prof, p->env, p->partials, p->st, p->vdd, p->vdk, p->hist, p->sfs, p->set};
   for (void* q : bufs)
     if (q) (void)hipFree(q);
   delete p;
@@ -855,6 +864,10 @@ static void fill_desc(mh3d_plan_t p) {
   v.nb_upd = p->g.C == 1 ? p->g.ps * p->g.nx : update_blocks(p->g.N);
   v.ncomp = p->g.C;
   v.hs_cstride = (long long)p->g.K * p->g.hsz;
+  v.sfs = p->sfs;
+  v.set = p->set;
+  v.cp = p->uperm;
+  v.qx = p->uperm + (size_t)p->g.sy * p->g.nx * p->g.ncls;
   for (int c = 0; c < 3; ++c) v.cmask[c] = p->cmask[c];
 }
 
@@ -904,6 +917,10 @@ extern "C" mh3d_status mh3d_plan(const mh3d_plan_desc* desc, mh3d_plan_t* out) {
   if ((s = dalloc(p, &p->hs, hbytes)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->b, sizeof(float) * g.C * g.N)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->uperm, sizeof(float2) * (size_t)g.C * g.nx * g.plane)) != MH3D_OK) return bail(s);
+  if (p->compact) {
+    if ((s = dalloc(p, (void**)&p->sfs, sizeof(float) * (size_t)g.K * g.nx)) != MH3D_OK) return bail(s);
+    if ((s = dalloc(p, (void**)&p->set, sizeof(float2) * (size_t)g.sy * g.my * g.nzh)) != MH3D_OK) return bail(s);
+  }
   if ((s = dalloc(p, (void**)&p->G, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   if ((s = dalloc(p, (void**)&p->Gp, sizeof(float2) * (size_t)g.K * g.mx * g.ncls)) != MH3D_OK) return bail(s);
   for (int i = 0; i < 5; ++i)
