@@ -202,7 +202,21 @@ typedef struct {
  * fit, or if the plan belongs to a batch.  Synchronous. */
 mh3d_status mh3d_plan_set_tiles(mh3d_plan_t plan, const mh3d_tiles* tiles);
 mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
-/* Pass family of the fused sequences (mh3d_forward_adjoint, mh3d_normal,
+/* mh3d_solve without allocation, for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc): the same
+ * updates, stopping rule and results as mh3d_solve with the same arguments, but the r_k
+ * history that mh3d_solve keeps in a buffer it allocates on first use lives in a
+ * file-scope device array of 65536 doubles (512 KiB, held by each GPU the library runs
+ * on until the process ends).  No hipMalloc, hipFree or event creation; the plan's own
+ * buffers (allocated by mh3d_plan) serve everything else.
+ * Errors: MH3D_ERR_INVALID if opts->max_iter > 65536 or pass profiling is on (it creates
+ * events), else as mh3d_solve.  info->ms_total is the call's host wall time.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * threads or streams) race, and each call overwrites the previous call's history. */
+mh3d_status mh3d_solve_static(mh3d_plan_t plan, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
+                              mh3d_solve_info* info);
+
+/* Pass family of the fused sequences/* Pass family of the fused sequences (mh3d_forward_adjoint, mh3d_normal,
  * mh3d_power_iteration, mh3d_solve) -- the same operator (Sec. 4.1 eq. dN, Table
  * tab:ops) and solver step (Sec. 4.3) either way:
  *   1  compile-time-geometry passes, where the library has them for the plan's grid,

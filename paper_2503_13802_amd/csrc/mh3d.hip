@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1141,11 +1142,11 @@ static mh3d_status ensure_hist(mh3d_plan_t p, int n) {
 }
 
 // Prepares rho^{k0}, y^{k0}, the descriptor and the state of a solve.
+// hist: device array of at least opts->max_iter doubles receiving r_k.
 static mh3d_status solve_setup(mh3d_plan_t p, const float* d, const float* rho0, const mh3d_solve_opts* opts,
-                               double tau) {
+                               double tau, double* hist) {
   const Geo& g = p->g;
   const int k0 = opts->k0;
-  CHK(ensure_hist(p, opts->max_iter));
   HIPCHK(hipMemcpyAsync(p->vol[k0 & 1], rho0, sizeof(float) * g.N, hipMemcpyDeviceToDevice, p->stream));
   {
     Timer t(p, KID_AUX);
@@ -1155,7 +1156,7 @@ static mh3d_status solve_setup(mh3d_plan_t p, const float* d, const float* rho0,
     CHK(last_launch("k_fista_init"));
   }
   p->vdh.d = d;
-  p->vdh.hist = p->hist;
+  p->vdh.hist = hist;
   p->vdh.hist_len = opts->max_iter;
   p->vdh.k_first = k0;
   CHK(upload_desc(p));
@@ -1209,14 +1210,14 @@ static mh3d_status resolve_tau(mh3d_plan_t p, const mh3d_solve_opts* opts, doubl
 }
 
 static mh3d_status finish_solve(mh3d_plan_t p, float* rho_inout, const mh3d_solve_opts* opts, const DevState& h,
-                                double tau, double lmax, float ms, mh3d_solve_info* info) {
+                                double tau, double lmax, float ms, mh3d_solve_info* info, const double* hist) {
   const int iters = h.last_k - opts->k0 + 1;
   if (iters >= 1)
     HIPCHK(hipMemcpyAsync(rho_inout, p->vol[(h.last_k + 1) & 1], sizeof(float) * p->g.N, hipMemcpyDeviceToDevice,
                           p->stream));
   if (opts->history && opts->history_len > 0 && iters > 0) {
     const int n = std::min(iters, (int)opts->history_len);
-    HIPCHK(hipMemcpyAsync(opts->history, p->hist, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipMemcpyAsync(opts->history, hist, sizeof(double) * n, hipMemcpyDeviceToHost, p->stream));
   }
   HIPCHK(hipStreamSynchronize(p->stream));
   mh3d_status status = MH3D_OK;
@@ -1235,6 +1236,23 @@ static mh3d_status finish_solve(mh3d_plan_t p, float* rho_inout, const mh3d_solv
   return status;
 }
 
+// The updates of a prepared solve: plain launches, a chunk of updates between reads of
+// the state.  (A captured graph of the chunk was measured: 1.5 % less time per update at
+// 96x96x64, but its capture and instantiation cost more than a whole solve on first use.)
+static mh3d_status run_updates(mh3d_plan_t p, const mh3d_solve_opts* opts, DevState& h) {
+  const int chunk = opts->check_every > 0 ? opts->check_every : 16;
+  memset(&h, 0, sizeof h);
+  int issued = 0;
+  while (issued < opts->max_iter) {
+    const int n = std::min(chunk, opts->max_iter - issued);
+    for (int i = 0; i < n; ++i) CHK(enqueue_update(p, issued + i == 0));
+    issued += n;
+    CHK(read_state(p, h));
+    if (h.done) break;
+  }
+  return MH3D_OK;
+}
+
 extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
                                   mh3d_solve_info* info) {
   CHK(check_plan(p));
@@ -1246,26 +1264,62 @@ extern "C" mh3d_status mh3d_solve(mh3d_plan_t p, const float* d, float* rho_inou
   HIPCHK(hipEventRecord(ev.e0, p->stream));
   double tau, lmax;
   CHK(resolve_tau(p, opts, &tau, &lmax));
-  CHK(solve_setup(p, d, rho_inout, opts, tau));
-  // Plain launches, a chunk of updates between reads of the state.  (A captured graph
-  // of the chunk was measured: 1.5 % less time per update at 96x96x64, but its capture
-  // and instantiation cost more than a whole solve on first use.)
-  const int chunk = opts->check_every > 0 ? opts->check_every : 16;
+  CHK(ensure_hist(p, opts->max_iter));
+  CHK(solve_setup(p, d, rho_inout, opts, tau, p->hist));
   DevState h;
-  memset(&h, 0, sizeof h);
-  int issued = 0;
-  while (issued < opts->max_iter) {
-    const int n = std::min(chunk, opts->max_iter - issued);
-    for (int i = 0; i < n; ++i) CHK(enqueue_update(p, issued + i == 0));
-    issued += n;
-    CHK(read_state(p, h));
-    if (h.done) break;
-  }
+  CHK(run_updates(p, opts, h));
   HIPCHK(hipEventRecord(ev.e1, p->stream));
   HIPCHK(hipEventSynchronize(ev.e1));
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
-  return finish_solve(p, rho_inout, opts, h, tau, lmax, ms, info);
+  return finish_solve(p, rho_inout, opts, h, tau, lmax, ms, info, p->hist);
+}
+
+// ---------------------------------------------------------------------------- solve without allocation
+// The r_k history of mh3d_solve_static: a file-scope device array (each GPU the library
+// runs on holds its own copy until the process ends).  Host code never passes the
+// array's name to a kernel or a copy: it resolves the device address once per device
+// (hipGetSymbolAddress, with that device current) and uses that.
+constexpr int kStaticHistory = 1 << 16;   // updates per call (512 KiB per GPU)
+static __device__ __align__(256) double scratch[kStaticHistory];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_dev;   // resolved address per device ordinal
+
+static mh3d_status static_history(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return MH3D_OK;
+}
+
+extern "C" mh3d_status mh3d_solve_static(mh3d_plan_t p, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
+                                         mh3d_solve_info* info) {
+  CHK(check_plan(p));
+  if (!d || !rho_inout) return fail(MH3D_ERR_INVALID, "NULL argument");
+  CHK(validate_opts(opts));
+  if (opts->max_iter > kStaticHistory)
+    return fail(MH3D_ERR_INVALID, "max_iter = %d exceeds the %d updates of the static history", opts->max_iter,
+                kStaticHistory);
+  if (p->prof_on) return fail(MH3D_ERR_INVALID, "pass profiling creates events: disable mh3d_profile first");
+  double* hist = nullptr;
+  CHK(static_history(&hist));
+  SolverPasses sp(p);
+  const auto t0 = std::chrono::steady_clock::now();
+  double tau, lmax;
+  CHK(resolve_tau(p, opts, &tau, &lmax));
+  CHK(solve_setup(p, d, rho_inout, opts, tau, hist));
+  DevState h;
+  CHK(run_updates(p, opts, h));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  const float ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return finish_solve(p, rho_inout, opts, h, tau, lmax, ms, info, hist);
 }
 
 // ============================================================================ batch
@@ -1490,7 +1544,8 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
   }
   for (int v = 0; v < n; ++v) {
     mh3d_plan_t p = b->plans[v];
-    CHK(solve_setup(p, d[v], rho_inout[v], opts, tau[v]));
+    CHK(ensure_hist(p, opts->max_iter));
+    CHK(solve_setup(p, d[v], rho_inout[v], opts, tau[v], p->hist));
     CHK(batch_upload(b, v));
   }
   const int chunk = opts->check_every > 0 ? opts->check_every : 16;
@@ -1534,7 +1589,7 @@ extern "C" mh3d_status mh3d_solve_batch(mh3d_batch_t b, const float* const* d, f
     mh3d_solve_opts o = *opts;
     o.history = nullptr;
     o.history_len = 0;
-    mh3d_status s = finish_solve(b->plans[v], rho_inout[v], &o, hs[v], tau[v], lmax[v], ms, &inf);
+    mh3d_status s = finish_solve(b->plans[v], rho_inout[v], &o, hs[v], tau[v], lmax[v], ms, &inf, b->plans[v]->hist);
     if (infos) infos[v] = inf;
     if (s != MH3D_OK && worst == MH3D_OK) worst = s;
   }

@@ -92,6 +92,7 @@ def library():
     lib.mh3d_normal.argtypes = [vp, vp, vp]
     lib.mh3d_power_iteration.argtypes = [vp, i32, ctypes.c_uint64, ctypes.POINTER(dbl)]
     lib.mh3d_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
+    lib.mh3d_solve_static.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
     lib.mh3d_plan_export.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.mh3d_profile.argtypes = [vp, i32]
     lib.mh3d_profile_read.argtypes = [vp, ctypes.POINTER(ProfileData)]
@@ -309,8 +310,9 @@ class Plan:
         return lm.value
 
     def solve(self, d, rho0=None, max_iter=500, tol=1e-4, tau=0.0, power_iters=50, power_seed=0,
-              rho_prev=None, k0=1, check_every=25, raise_on_not_converged=False):
-        """Returns (rho, info dict with 'history')."""
+              rho_prev=None, k0=1, check_every=25, raise_on_not_converged=False, static=False):
+        """Returns (rho, info dict with 'history').  static: call mh3d_solve_static, which
+        allocates no device memory (this wrapper still makes its own output tensor)."""
         d = self._port(d)
         rho = self.torch.zeros(self.shape, device=self.device) if rho0 is None else self._vol(rho0).clone()
         prev = None if rho_prev is None else self._vol(rho_prev)
@@ -319,7 +321,8 @@ class Plan:
                       None if prev is None else prev.data_ptr(), int(k0), int(check_every),
                       ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(max_iter))
         info = SolveInfo()
-        s = library().mh3d_solve(self._h, _ptr(d), _ptr(rho), ctypes.byref(o), ctypes.byref(info))
+        fn = library().mh3d_solve_static if static else library().mh3d_solve
+        s = fn(self._h, _ptr(d), _ptr(rho), ctypes.byref(o), ctypes.byref(info))
         if s not in (OK, ERR_NOT_CONVERGED) or (s == ERR_NOT_CONVERGED and raise_on_not_converged):
             _check(s)
         out = {"iters": info.iters, "rel_step": info.rel_step, "tau": info.tau, "lmax": info.lmax,
