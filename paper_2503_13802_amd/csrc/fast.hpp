@@ -378,6 +378,138 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   }
 }
 
+// ============================================================================ solver step
+// The end of a solver step on the block's voxels (rows y = sy*y1 + y0 of plane x), with
+// u = b . v from the packed rows Z in LDS: the same arithmetic as StepCtx (kernels.hpp),
+//   UPD_NORMAL  out = u + lam R(s w);  FP64 <s w, out>, ||out||^2
+//   UPD_FISTA   g = u + lam R(y^k); rho^{k+1} = max(y^k - tau g, 0);
+//               y^{k+1} = rho^{k+1} + k/(k+3) (rho^{k+1} - rho^k); FP64 ||rho^{k+1} - y^k||^2,
+//               ||rho^{k+1}||^2, count of non-finite g
+// with R the periodic 13-point stencil of stacked second differences (T = I for
+// reg_kind 1) plus alpha on the boundary shell.  Items are 4 consecutive voxels along z:
+// the point and its y and x neighbours are float4 loads, the z neighbours two more on
+// each side.  FP64 block partials go to vd.partials[lb] (k_vol_finish sums them).
+template <class G, int UPD>
+__device__ __forceinline__ void fast_step(const VolDesc& vd, const AdjOut& ao, const float2* __restrict__ Z, int x, int y0,
+                                          int lb) {
+  constexpr int NV = UPD == UPD_NORMAL ? 2 : 3;
+  constexpr int F4R = G::NZ / 4, NIT = G::MY * F4R;
+  constexpr long long PL = (long long)G::NY * G::NZ;
+  __shared__ double red[64];
+  const DevState* st = vd.st;
+  const int kk = st->k;
+  const float* __restrict__ yv = (UPD == UPD_NORMAL) ? (ao.yin ? ao.yin : vd.rho[kk & 1]) : vd.y[kk & 1];
+  const float* __restrict__ rk = vd.rho[kk & 1];
+  float* __restrict__ out = (UPD == UPD_NORMAL) ? (ao.out ? ao.out : vd.rho[(kk + 1) & 1]) : nullptr;
+  float* __restrict__ rho_next = vd.rho[(kk + 1) & 1];
+  float* __restrict__ y_next = vd.y[(kk + 1) & 1];
+  const float s = (UPD == UPD_NORMAL) ? (float)st->scale : 1.f;
+  const float lam = vd.lam, alpha = vd.alpha, tau = (float)st->tau;
+  const float beta1 = (float)((double)kk / (kk + 3.0));
+  const bool stencil = vd.reg_kind == 0;
+  const int aw = vd.aw;
+  const float* __restrict__ bs = vd.b;
+  double acc[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+  auto ld4 = [](const float* p) { const float4 v = *reinterpret_cast<const float4*>(p); return v; };
+  auto wrap = [](int q, int n) { return q < 0 ? q + n : (q >= n ? q - n : q); };
+  constexpr int U = 2;   // items whose loads are in flight together
+  for (int f0 = threadIdx.x; f0 < NIT; f0 += U * G::TP) {
+    float4 c[U], ym2[U], ym1[U], yp1[U], yp2[U], xm2[U], xm1[U], xp1[U], xp2[U], rv[U], bv[U];
+    float zl2[U], zl1[U], zr1[U], zr2[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int f = f0 + q * G::TP;
+      if (f >= NIT) break;
+      const int y1 = f / F4R, z0 = 4 * (f - (f / F4R) * F4R);
+      const int y = G::SY * y1 + y0;
+      const long long row = (long long)x * PL + (long long)y * G::NZ;
+      const long long i0 = row + z0;
+      c[q] = ld4(yv + i0);
+      bv[q] = ld4(bs + i0);
+      if (UPD == UPD_FISTA) rv[q] = ld4(rk + i0);
+      if (stencil) {
+        zl2[q] = yv[row + wrap(z0 - 2, G::NZ)];
+        zl1[q] = yv[row + wrap(z0 - 1, G::NZ)];
+        zr1[q] = yv[row + wrap(z0 + 4, G::NZ)];
+        zr2[q] = yv[row + wrap(z0 + 5, G::NZ)];
+        const long long pln = (long long)x * PL + z0;
+        ym2[q] = ld4(yv + pln + (long long)wrap(y - 2, G::NY) * G::NZ);
+        ym1[q] = ld4(yv + pln + (long long)wrap(y - 1, G::NY) * G::NZ);
+        yp1[q] = ld4(yv + pln + (long long)wrap(y + 1, G::NY) * G::NZ);
+        yp2[q] = ld4(yv + pln + (long long)wrap(y + 2, G::NY) * G::NZ);
+        const long long col = (long long)y * G::NZ + z0;
+        xm2[q] = ld4(yv + (long long)wrap(x - 2, G::NX) * PL + col);
+        xm1[q] = ld4(yv + (long long)wrap(x - 1, G::NX) * PL + col);
+        xp1[q] = ld4(yv + (long long)wrap(x + 1, G::NX) * PL + col);
+        xp2[q] = ld4(yv + (long long)wrap(x + 2, G::NX) * PL + col);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int f = f0 + q * G::TP;
+      if (f >= NIT) break;
+      const int y1 = f / F4R, z0 = 4 * (f - (f / F4R) * F4R);
+      const int y = G::SY * y1 + y0;
+      const long long i0 = (long long)x * PL + (long long)y * G::NZ + z0;
+      const float2* zr = Z + (y1 >> 1) * G::LSZ + z0;
+      const float cv[4] = {c[q].x, c[q].y, c[q].z, c[q].w};
+      const float zrow[8] = {zl2[q], zl1[q], c[q].x, c[q].y, c[q].z, c[q].w, zr1[q], zr2[q]};
+      const float a_ym2[4] = {ym2[q].x, ym2[q].y, ym2[q].z, ym2[q].w}, a_ym1[4] = {ym1[q].x, ym1[q].y, ym1[q].z, ym1[q].w};
+      const float a_yp1[4] = {yp1[q].x, yp1[q].y, yp1[q].z, yp1[q].w}, a_yp2[4] = {yp2[q].x, yp2[q].y, yp2[q].z, yp2[q].w};
+      const float a_xm2[4] = {xm2[q].x, xm2[q].y, xm2[q].z, xm2[q].w}, a_xm1[4] = {xm1[q].x, xm1[q].y, xm1[q].z, xm1[q].w};
+      const float a_xp1[4] = {xp1[q].x, xp1[q].y, xp1[q].z, xp1[q].w}, a_xp2[4] = {xp2[q].x, xp2[q].y, xp2[q].z, xp2[q].w};
+      const float a_b[4] = {bv[q].x, bv[q].y, bv[q].z, bv[q].w};
+      const float a_r[4] = {rv[q].x, rv[q].y, rv[q].z, rv[q].w};
+      float o4[4], n4[4], m4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma clang fp contract(off)
+        const int z = z0 + e;
+        const float vz = (y1 & 1) ? zr[e].y : zr[e].x;
+        const float u = __fmul_rn(a_b[e], vz);
+        float t;
+        if (!stencil) {
+          t = s * cv[e];
+        } else {
+          t = 18.f * (s * cv[e]);
+          t += s * (zrow[e + 4] + zrow[e]) - 4.f * s * (zrow[e + 3] + zrow[e + 1]);
+          t += s * (a_yp2[e] + a_ym2[e]) - 4.f * s * (a_yp1[e] + a_ym1[e]);
+          t += s * (a_xp2[e] + a_xm2[e]) - 4.f * s * (a_xp1[e] + a_xm1[e]);
+        }
+        if (alpha > 0.f) {
+          const bool shell = x < aw || x >= G::NX - aw || y < aw || y >= G::NY - aw || z < aw || z >= G::NZ - aw;
+          if (shell) t += alpha * (s * cv[e]);
+        }
+        if constexpr (UPD == UPD_NORMAL) {
+          const float o = u + lam * t;
+          o4[e] = o;
+          acc[0] += (double)(s * cv[e]) * (double)o;
+          acc[1] += (double)o * (double)o;
+        } else {
+          const float yk = cv[e];
+          const float gr = u + lam * t;
+          const float rn = fmaxf(yk - tau * gr, 0.f);
+          n4[e] = rn;
+          m4[e] = rn + beta1 * (rn - a_r[e]);
+          const double dd = (double)rn - (double)yk;
+          acc[0] += dd * dd;
+          acc[1] += (double)rn * (double)rn;
+          if (!isfinite(gr) || !isfinite(yk)) acc[2] += 1.0;
+        }
+      }
+      if constexpr (UPD == UPD_NORMAL) {
+        *reinterpret_cast<float4*>(out + i0) = make_float4(o4[0], o4[1], o4[2], o4[3]);
+      } else {
+        *reinterpret_cast<float4*>(rho_next + i0) = make_float4(n4[0], n4[1], n4[2], n4[3]);
+        *reinterpret_cast<float4*>(y_next + i0) = make_float4(m4[0], m4[1], m4[2], m4[3]);
+      }
+    }
+  }
+  store_step_partials<NV>(vd, acc, red, lb);
+}
+
 // ============================================================================ plane pass (adjoint)
 // Block (x, y0): the residue's half spectrum Q(x, q'y, qz mod mz) conj(Et(y0, q'y, qz)),
 // inverse length-my DFT along y1, C2R along z, then per voxel of rows y = sy*y1 + y0:
@@ -494,36 +626,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
       *reinterpret_cast<float4*>(out + o1) = make_float4(b1.x * z0.y, b1.y * z1.y, b1.z * z2.y, b1.w * z3.y);
     }
   } else {
-    constexpr int UPD = OUT == OUT_STEP_NORMAL ? UPD_NORMAL : UPD_FISTA;
-    constexpr int NV = StepCtx<UPD>::NV;
-    __shared__ double red[64];
-    const StepCtx<UPD> ctx(vd, ao);
-    double acc[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-    constexpr int n = G::MY * G::NZ;
-    constexpr int U = 3;
-    for (int p = t; p < n; p += U * G::TP) {
-      StencilVals v[U];
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int pq = p + q * G::TP;
-        if (pq < n) {
-          const int y1 = pq / G::NZ, z = pq - (pq / G::NZ) * G::NZ;
-          const long long i = pb + (long long)(G::SY * y1 + y0) * G::NZ + z;
-          v[q] = ctx.load(i, __fmul_rn(bs[i], Zf[2 * ((y1 >> 1) * G::LSZ + z) + (y1 & 1)]));
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int pq = p + q * G::TP;
-        if (pq < n) {
-          const int y1 = pq / G::NZ, z = pq - (pq / G::NZ) * G::NZ;
-          ctx.apply(pb + (long long)(G::SY * y1 + y0) * G::NZ + z, v[q], acc);
-        }
-      }
-    }
-    store_step_partials<NV>(vd, acc, red, lb);
+    fast_step<G, OUT == OUT_STEP_NORMAL ? UPD_NORMAL : UPD_FISTA>(vd, ao, Z, x, y0, lb);
   }
 }
 

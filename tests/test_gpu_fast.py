@@ -142,3 +142,34 @@ def test_path_request_validation():
     assert p.path(1) == 0
     with pytest.raises(mh3d.MH3DError):
         p.path(2)
+
+
+@pytest.mark.parametrize("reg_kind,alpha,aw", [(1, 0.0, 0), (0, 2.5, 3), (1, 1.5, 2)])
+def test_fast_step_regulariser_variants(reg_kind, alpha, aw):
+    """The compile-time step with T = I, with the boundary prior of eq. finalR (a shell of
+    aw voxels weighted alpha), and both: normal operator, power iteration against the
+    general passes, and 25 updates against the oracle."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    announce("fast step reg_kind %d alpha %g" % (reg_kind, alpha))
+    shape, ds, harm, a, sig, lam = (32, 32, 32), (2, 4, 4), (2, 3, 5, 8), 1.1, 9.0, 2e-2
+    h = om.psf_bank(shape, list(harm), a)
+    b = om.sensitivity(shape, sig)
+    op = osv.Operator(h, b, ds, lam, reg_kind=reg_kind, alpha=alpha, alpha_width=aw)
+    p = mh3d.Plan(shape, harm, a, ds, sig, lam, reg_kind=reg_kind, alpha=alpha, alpha_width=aw)
+    assert p.path() == 1
+    x = inputs.random_field(shape, 21)
+    assert rel_l2(p.normal(torch.tensor(x, dtype=torch.float32)).cpu().numpy(), op.normal(x)) <= TOL
+    l1 = p.power_iteration(30, 2)
+    p.path(0)
+    l0 = p.power_iteration(30, 2)
+    p.path(1)
+    assert abs(l1 - l0) <= 1e-5 * abs(l0)
+    rho_t = np.maximum(inputs.random_field(shape, 22), 0.0)
+    d_clean = op.A(rho_t)
+    d = d_clean + 0.01 * float(np.abs(d_clean).max()) * inputs.random_field(d_clean.shape, 23)
+    tau = osv.step_size(osv.power_iteration(op, inputs.random_field(shape, 24), 60))
+    want, _, _ = osv.fista(op, d, tau, max_iter=25)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=25, tol=0.0, tau=tau)
+    assert info["iters"] == 25
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
