@@ -270,6 +270,11 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
 }
 
 // ============================================================================ column pass
+// Modes beyond the fused ones (NRM_RESID, NRM_PLAIN, NRM_STORE of kernels.hpp): A alone
+// (the forward products and G, no adjoint) and A^T alone (R_k from the small-grid spectra
+// of the portraits that k_small_fwd left in G', no forward products).
+enum { COL_FWD = 16, COL_ADJ = 17 };
+
 // Block: CPC columns (q'y, q'z), one thread per (column, q'x) owning the x aliases
 // qx = q'x + mx*jx.  Sums the sy shares of each column, transforms along x, then per
 // harmonic Fhat_k(q'x) = sum_jx F_k(qx) W(qx) (times i for imaginary F_k), the residual
@@ -282,6 +287,8 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   const VolDesc& vd = vds[0];
   if (check_done && vd.st->done) return;
   constexpr int NX = G::NX, MX = G::MX, SX = G::SX, CPC = G::CPC, KMAX = G::KMAX, LSX = G::LSX;
+  constexpr bool kFwd = MODE != COL_ADJ, kAdj = MODE != COL_FWD;
+  constexpr bool kStoreG = MODE == NRM_STORE || MODE == COL_FWD;
   const int c0 = blockIdx.x * CPC;
   const int K = vd.g.K;
   extern __shared__ float2 lds[];
@@ -296,13 +303,25 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   // the shares of the block's columns: consecutive threads take consecutive x
   constexpr int NIT = CPC * NX, NI = (NIT + G::TC - 1) / G::TC;
   float2 sv[NI][G::SY];
+  if constexpr (kFwd) {
 #pragma unroll
-  for (int i = 0; i < NI; ++i) {
-    const int it = t + i * G::TC;
-    if (NIT % G::TC == 0 || it < NIT) {
-      const int c = it / NX, xx = it - (it / NX) * NX;
+    for (int i = 0; i < NI; ++i) {
+      const int it = t + i * G::TC;
+      if (NIT % G::TC == 0 || it < NIT) {
+        const int c = it / NX, xx = it - (it / NX) * NX;
 #pragma unroll
-      for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = vd.cp[((long long)y0 * G::NCLS + c0 + c) * NX + xx];
+        for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = vd.cp[((long long)y0 * G::NCLS + c0 + c) * NX + xx];
+      }
+    }
+  }
+  // A^T alone: the portraits' small-grid spectra G'[k][x'-block][column][x'-in-block]
+  if constexpr (MODE == COL_ADJ) {
+    const int xb = vd.g.xb, nxb = MX / xb;
+    for (int p = t; p < K * CPC * MX; p += G::TC) {
+      const int k = p / (CPC * MX), r = p - k * (CPC * MX);
+      const int c = r / MX, qq = r - c * MX;
+      const int xbi = qq / xb, xi = qq - xbi * xb;
+      F0[p] = vd.Gp[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi];
     }
   }
   // x factors of the thread's aliases and (residual) the data's spectra
@@ -318,23 +337,30 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   }
   load_table(twx, vd.tw + vd.off[0], NX);
   load_table(twm, vd.tw + vd.off[3], MX);
-#pragma unroll
-  for (int i = 0; i < NI; ++i) {
-    const int it = t + i * G::TC;
-    if (NIT % G::TC == 0 || it < NIT) {
-      const int c = it / NX, xx = it - (it / NX) * NX;
-      float2 s = sv[i][0];
-#pragma unroll
-      for (int y0 = 1; y0 < G::SY; ++y0) s = cadd(s, sv[i][y0]);
-      U0[c * LSX + xx] = s;
-    }
-  }
-  __syncthreads();
-  float2* U = lf_fft<NX, 0, 1, -1, CPC, LSX>(U0, U1, twx);
-  float2 w[SX];
-#pragma unroll
-  for (int jx = 0; jx < SX; ++jx) w[jx] = U[cl * LSX + qxp + jx * MX];
   const uint32_t imag_mask = vd.imag_mask;
+  float2 w[SX];
+  if constexpr (kFwd) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int it = t + i * G::TC;
+      if (NIT % G::TC == 0 || it < NIT) {
+        const int c = it / NX, xx = it - (it / NX) * NX;
+        float2 s = sv[i][0];
+#pragma unroll
+        for (int y0 = 1; y0 < G::SY; ++y0) s = cadd(s, sv[i][y0]);
+        U0[c * LSX + xx] = s;
+      }
+    }
+    __syncthreads();
+    float2* U = lf_fft<NX, 0, 1, -1, CPC, LSX>(U0, U1, twx);
+#pragma unroll
+    for (int jx = 0; jx < SX; ++jx) w[jx] = U[cl * LSX + qxp + jx * MX];
+  }
+  const float2* Rt = nullptr;   // A^T alone: R_k(q'x) = x' transform of the portraits' spectra
+  if constexpr (MODE == COL_ADJ) {
+    __syncthreads();
+    Rt = ct_stages<MX, 0, 1, -1>(F0, F1, twm, K * CPC, MX);
+  }
   const float Mf = (float)(G::MX * G::MY * G::MZ);
   float2 q[SX];
 #pragma unroll
@@ -342,30 +368,40 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     if (k < K) {
-      float fx = 0.f, fy = 0.f;
-#pragma unroll
-      for (int jx = 0; jx < SX; ++jx) { fx += fs[k][jx] * w[jx].x; fy += fs[k][jx] * w[jx].y; }
       const bool im = (imag_mask >> k) & 1u;
-      float2 f = im ? make_float2(-fy, fx) : make_float2(fx, fy);
-      if constexpr (MODE == NRM_STORE) F0[(k * CPC + cl) * MX + qxp] = f;
-      float2 R = make_float2(Mf * f.x, Mf * f.y);
-      if constexpr (MODE == NRM_RESID) R = csub(R, dt[k]);
-      if (im) R = make_float2(R.y, -R.x);   // conj(i F) R = -i F R
+      float2 R;
+      if constexpr (kFwd) {
+        float fx = 0.f, fy = 0.f;
 #pragma unroll
-      for (int jx = 0; jx < SX; ++jx) { q[jx].x += fs[k][jx] * R.x; q[jx].y += fs[k][jx] * R.y; }
+        for (int jx = 0; jx < SX; ++jx) { fx += fs[k][jx] * w[jx].x; fy += fs[k][jx] * w[jx].y; }
+        const float2 f = im ? make_float2(-fy, fx) : make_float2(fx, fy);
+        if constexpr (kStoreG) F0[(k * CPC + cl) * MX + qxp] = f;
+        R = make_float2(Mf * f.x, Mf * f.y);
+        if constexpr (MODE == NRM_RESID) R = csub(R, dt[k]);
+      } else {
+        R = Rt[(k * CPC + cl) * MX + qxp];
+      }
+      if constexpr (kAdj) {
+        if (im) R = make_float2(R.y, -R.x);   // conj(i F) R = -i F R
+#pragma unroll
+        for (int jx = 0; jx < SX; ++jx) { q[jx].x += fs[k][jx] * R.x; q[jx].y += fs[k][jx] * R.y; }
+      }
     }
   }
-  __syncthreads();   // every thread has read its aliases of U
+  if constexpr (kAdj) {
+    __syncthreads();   // every thread has read its aliases of U
 #pragma unroll
-  for (int jx = 0; jx < SX; ++jx) U0[cl * LSX + qxp + jx * MX] = q[jx];
-  __syncthreads();
-  const float2* V = lf_fft<NX, 0, 1, +1, CPC, LSX>(U0, U1, twx);
-  float2* __restrict__ qo = vd.qx + (long long)c0 * NX;
-  for (int it = t; it < NIT; it += G::TC) {
-    const int c = it / NX, xx = it - (it / NX) * NX;
-    qo[it] = V[c * LSX + xx];
+    for (int jx = 0; jx < SX; ++jx) U0[cl * LSX + qxp + jx * MX] = q[jx];
+    __syncthreads();
+    const float2* V = lf_fft<NX, 0, 1, +1, CPC, LSX>(U0, U1, twx);
+    float2* __restrict__ qo = vd.qx + (long long)c0 * NX;
+    for (int it = t; it < NIT; it += G::TC) {
+      const int c = it / NX, xx = it - (it / NX) * NX;
+      qo[it] = V[c * LSX + xx];
+    }
   }
-  if constexpr (MODE == NRM_STORE) {
+  if constexpr (kStoreG) {
+    __syncthreads();
     const float2* F = ct_stages<MX, 0, 1, +1>(F0, F1, twm, K * CPC, MX);
     float2* __restrict__ Gs = vd.G;
     const int xb = vd.g.xb, nxb = MX / xb;

@@ -410,13 +410,16 @@ struct FastImpl {
     switch (mode) {
       case NRM_RESID: k_fast_col<G, NRM_RESID><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
       case NRM_PLAIN: k_fast_col<G, NRM_PLAIN><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
+      case COL_FWD: k_fast_col<G, COL_FWD><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
+      case COL_ADJ: k_fast_col<G, COL_ADJ><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
       default: k_fast_col<G, NRM_STORE><<<grid, block, G::LDS_COL, s>>>(vd, chk); break;
     }
   }
   static void plane_adj(hipStream_t s, const VolDesc* vd, int out, AdjOut ao) {
     const dim3 grid(G::NBP), block(G::TP);
     if (out == OUT_STEP_NORMAL) k_fast_plane_adj<G, OUT_STEP_NORMAL><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
-    else k_fast_plane_adj<G, OUT_STEP_FISTA><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
+    else if (out == OUT_STEP_FISTA) k_fast_plane_adj<G, OUT_STEP_FISTA><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
+    else k_fast_plane_adj<G, OUT_SCALE_B><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
   }
   static void adj_and_store(hipStream_t s, const VolDesc* vd, AdjOut ao, float* d, int nsmall, size_t lds) {
     k_fast_adj_and_store<G><<<dim3(G::NBP + nsmall), dim3(G::TP), std::max(lds, G::LDS_PLANE), s>>>(vd, ao, d);
@@ -602,6 +605,19 @@ static mh3d_status fast_adj_and_store(mh3d_plan_t p, float* d, float* x) {
   ao.yin = nullptr;
   p->fast->adj_and_store(p->ls, p->vda, ao, d, p->g.K * (p->g.mx / p->g.xb), p->L.lds_small);
   return last_launch("k_fast_adj_and_store");
+}
+static mh3d_status fast_class_alone(mh3d_plan_t p, int mode) {
+  Timer t(p, mode == COL_FWD ? KID_CLASS_FWD : KID_CLASS_ADJ);
+  p->fast->cls(p->ls, p->vda, mode, 0);
+  return last_launch("k_fast_col");
+}
+static mh3d_status fast_plane_adj_out(mh3d_plan_t p, float* x) {
+  Timer t(p, KID_PLANE_ADJ);
+  AdjOut ao;
+  ao.out = x;
+  ao.yin = nullptr;
+  p->fast->plane_adj(p->ls, p->vda, OUT_SCALE_B, ao);
+  return last_launch("k_fast_plane_adj");
 }
 // the adjoint plane pass that ends a step (UPD_NORMAL: out, w = yin; UPD_FISTA), then the
 // one-block finish of its FP64 sums
@@ -1002,6 +1018,11 @@ extern "C" mh3d_status mh3d_forward_adjoint(mh3d_plan_t p, const float* rho, flo
 extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
   CHK(check_plan(p));
   if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
+  if (use_fast(p)) {
+    CHK(fast_plane_fwd(p, SRC_PLAIN, rho));
+    CHK(fast_class_alone(p, COL_FWD));
+    return launch_small_inv(p, EPI_STORE, d);
+  }
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
   CHK(launch_class_fwd(p, 0, FWD_G));
   CHK(launch_small_inv(p, EPI_STORE, d));
@@ -1011,6 +1032,11 @@ extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
 extern "C" mh3d_status mh3d_adjoint(mh3d_plan_t p, const float* d, float* rho) {
   CHK(check_plan(p));
   if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
+  if (use_fast(p)) {
+    CHK(launch_small_fwd(p, d));   // the portraits' small-grid spectra, into G'
+    CHK(fast_class_alone(p, COL_ADJ));
+    return fast_plane_adj_out(p, rho);
+  }
   CHK(launch_small_fwd(p, d));
   CHK(launch_class_adj(p, 0));
   CHK(launch_plane_adj(p, OUT_SCALE_B, rho, nullptr));
@@ -1701,8 +1727,12 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
   (void)hipMemsetAsync(dtmp, 0, sizeof(float) * (size_t)p->g.K * p->g.M, p->stream);
   const bool fast = use_fast(p);
   auto launch = [&]() -> mh3d_status {
-    // passes 0, 6 and 7 are those of A then A^T: the compile-time ones where the plan has them
+    // the compile-time passes where the plan has them (the small-grid passes 2 and 3 are
+  // the same either way)
     if (fast && pass == 0) return fast_plane_fwd(p, SRC_PLAIN, p->vol[0]);
+    if (fast && pass == 1) return fast_class_alone(p, COL_FWD);
+    if (fast && pass == 4) return fast_class_alone(p, COL_ADJ);
+    if (fast && pass == 5) return fast_plane_adj_out(p, p->vol[1]);
     if (fast && pass == 6) return fast_class(p, 0, NRM_STORE);
     if (fast && pass == 7) return fast_adj_and_store(p, dtmp, p->vol[1]);
     switch (pass) {

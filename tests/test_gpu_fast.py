@@ -48,6 +48,15 @@ def test_fast_operator_matches_direct_sums(shape, ds, harm):
     assert rel_l2(x2.cpu().numpy(), om.adjoint_direct(h, b, d_ref, ds)) <= TOL
     xt = torch.tensor(inputs.random_field(shape, 6), dtype=torch.float32)
     assert rel_l2(p.normal(xt).cpu().numpy(), op.normal(xt.cpu().numpy().astype(np.float64))) <= TOL
+    # A and A^T as separate calls (the adjoint on independent portraits)
+    assert rel_l2(p.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy(), d_ref) <= TOL
+    r = inputs.random_field(d_ref.shape, 7)
+    x1 = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(x1, om.adjoint_direct(h, b, r, ds)) <= TOL
+    # FP32 adjoint identity <A x, r> = <x, A^T r>
+    lhs = float(np.sum(p.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy().astype(np.float64) * r))
+    rhs = float(np.sum(x * x1))
+    assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(d_ref) * np.linalg.norm(r)
     # the general passes of the same plan agree to FP32 rounding
     p.path(0)
     assert p.path() == 0
