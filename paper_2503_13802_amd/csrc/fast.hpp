@@ -36,6 +36,10 @@
 
 namespace mh3d {
 
+// Intermediate layouts: cp[y0][x][column] (the plane pass's folded shares) and
+// qx[x][column] (the column pass's output), so each plane workgroup reads and writes one
+// contiguous run; the column pass takes its columns in runs of CPC.
+//
 // Plan-time tables of the separable passes (FP64 sums, FP32 storage):
 //   sfs[k][qx]        scale_k F_k(qx) (its real part, or its imaginary part when bit k of
 //                     imag_mask is set), the x factor of the stored spectra
@@ -153,7 +157,7 @@ __device__ __forceinline__ void fast_plane_of(int b, int& x, int& y0) {
 // ============================================================================ plane pass (forward)
 // Block (x, y0): u = b . a on rows y = sy*y1 + y0 of plane x (a: rho, y^k or s w by SRC),
 // R2C along z, length-my DFT along y1, then the share C(y0; x, q'y, q'z) of the folded
-// plane into cp[y0][column][x].
+// plane into cp[y0][x][column].
 template <class G, int SRC>
 __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ a) {
   const VolDesc& vd = vds[0];
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   __syncthreads();
   const float2* Y = lf_fft<G::MY, 0, 1, -1, G::NZH, G::LSY>(X, Z, twy);
   // this residue's share of the folded plane
-  float2* __restrict__ dst = vd.cp + (long long)y0 * G::NCLS * G::NX + x;
+  float2* __restrict__ dst = vd.cp + ((long long)y0 * G::NX + x) * G::NCLS;
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
     const int cc = t + G::TP * i;
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
         sx += e.x * v.x - e.y * v.y;
         sy += e.x * v.y + e.y * v.x;
       }
-      dst[(long long)cc * G::NX] = make_float2(sx, sy);
+      dst[cc] = make_float2(sx, sy);
     }
   }
 }
@@ -279,7 +283,7 @@ enum { COL_FWD = 16, COL_ADJ = 17 };
 // qx = q'x + mx*jx.  Sums the sy shares of each column, transforms along x, then per
 // harmonic Fhat_k(q'x) = sum_jx F_k(qx) W(qx) (times i for imaginary F_k), the residual
 // R_k = M Fhat_k (- the data's spectrum D_k in NRM_RESID), and Q(qx) = sum_k conj(F_k(qx))
-// R_k(q'x); Q transformed back along x goes to qx[column][x] for the adjoint plane
+// R_k(q'x); Q transformed back along x goes to qx[x][column] for the adjoint plane
 // pass.  NRM_STORE also writes the portraits' decimated spectra G (inverse x' transform
 // of Fhat) for the small-grid pass; M Fhat then stands for the spectra of d itself.
 template <class G, int MODE>
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   float2* F1 = F0 + KMAX * CPC * MX;
   const int t = threadIdx.x;
   const int cl = t / MX, qxp = t - (t / MX) * MX;
-  // the shares of the block's columns: consecutive threads take consecutive x
+  // the shares of the block's columns: consecutive threads take consecutive columns of one x
   constexpr int NIT = CPC * NX, NI = (NIT + G::TC - 1) / G::TC;
   float2 sv[NI][G::SY];
   if constexpr (kFwd) {
@@ -308,9 +312,9 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
     for (int i = 0; i < NI; ++i) {
       const int it = t + i * G::TC;
       if (NIT % G::TC == 0 || it < NIT) {
-        const int c = it / NX, xx = it - (it / NX) * NX;
+        const int xx = it / CPC, c = it - (it / CPC) * CPC;
 #pragma unroll
-        for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = vd.cp[((long long)y0 * G::NCLS + c0 + c) * NX + xx];
+        for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = vd.cp[((long long)y0 * NX + xx) * G::NCLS + c0 + c];
       }
     }
   }
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
     for (int i = 0; i < NI; ++i) {
       const int it = t + i * G::TC;
       if (NIT % G::TC == 0 || it < NIT) {
-        const int c = it / NX, xx = it - (it / NX) * NX;
+        const int xx = it / CPC, c = it - (it / CPC) * CPC;
         float2 s = sv[i][0];
 #pragma unroll
         for (int y0 = 1; y0 < G::SY; ++y0) s = cadd(s, sv[i][y0]);
@@ -394,10 +398,9 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
     for (int jx = 0; jx < SX; ++jx) U0[cl * LSX + qxp + jx * MX] = q[jx];
     __syncthreads();
     const float2* V = lf_fft<NX, 0, 1, +1, CPC, LSX>(U0, U1, twx);
-    float2* __restrict__ qo = vd.qx + (long long)c0 * NX;
     for (int it = t; it < NIT; it += G::TC) {
-      const int c = it / NX, xx = it - (it / NX) * NX;
-      qo[it] = V[c * LSX + xx];
+      const int xx = it / CPC, c = it - (it / CPC) * CPC;
+      vd.qx[(long long)xx * G::NCLS + c0 + c] = V[c * LSX + xx];
     }
   }
   if constexpr (kStoreG) {
@@ -576,7 +579,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int c = t + i * G::TP;
-    if (c < G::NCLS) qv[i] = vd.qx[(long long)c * G::NX + x];
+    if (c < G::NCLS) qv[i] = vd.qx[(long long)x * G::NCLS + c];
   }
   constexpr int NE = G::NZH * G::MY, NEI = (NE + G::TP - 1) / G::TP;
   const float2* __restrict__ et = vd.set + (long long)y0 * G::MY * G::NZH;
@@ -584,10 +587,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
 #pragma unroll
   for (int i = 0; i < NEI; ++i) {
     const int it = t + i * G::TP;
-    if (it < NE) {
-      const int qz = it / G::MY, qyp = it - (it / G::MY) * G::MY;
-      ev[i] = et[qyp * G::NZH + qz];
-    }
+    if (it < NE) ev[i] = et[it];   // [q'y][qz]
   }
   constexpr int F4R = G::NZ / 4, P4 = G::NP * F4R, NB4 = (P4 + G::TP - 1) / G::TP;
   float4 bq[kStep ? 1 : NB4][2];
@@ -616,7 +616,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
   for (int i = 0; i < NEI; ++i) {
     const int it = t + i * G::TP;
     if (it < NE) {
-      const int qz = it / G::MY, qyp = it - (it / G::MY) * G::MY;
+      const int qyp = it / G::NZH, qz = it - (it / G::NZH) * G::NZH;
       const int qzr = qz % G::MZ;
       float2 qq;
       if (2 * qzr <= G::MZ) {
