@@ -240,9 +240,9 @@ mh3d_status mh3d_plan_path(mh3d_plan_t plan, int32_t request, int32_t* active);
  * holds no other blocks); mh3d_plan_set_tiles sets both splits to ps, and results do not
  * depend on either.
  * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
- * kind" with E, cpw, xb, ps, ps_solve (the solver's split), tm (threads of that
- * launch) and us; a hit applies the stored tiles without timing, a miss stores the
- * result.
+ * kind" (plus "|compiled" for plans on the compile-time passes of mh3d_plan_path) with
+ * E, cpw, xb, ps, ps_solve (the solver's split), tm (threads of that launch) and us; a
+ * hit applies the stored tiles without timing, a miss stores the result.
  * tiles / us_per_application (HOST, may be NULL) receive the choice and its time.
  * Overwrites the plan's solver volumes; synchronous. */
 mh3d_status mh3d_autotune(mh3d_plan_t plan, const char* cache_path, mh3d_tiles* tiles, double* us_per_application);

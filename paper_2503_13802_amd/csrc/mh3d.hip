@@ -1816,7 +1816,7 @@ extern "C" mh3d_status mh3d_plan_path(mh3d_plan_t p, int32_t request, int32_t* a
   return MH3D_OK;
 }
 
-// Cache key: device architecture, grid, harmonic count, decimation, spectrum form.
+// Cache key: device architecture, grid, harmonic count, decimation, spectrum form, pass family.
 static std::string tune_key(mh3d_plan_t p) {
   int dev = 0;
   std::string arch = "unknown";
@@ -1827,8 +1827,11 @@ static std::string tune_key(mh3d_plan_t p) {
     if (c != std::string::npos) arch = arch.substr(0, c);
   }
   char buf[160];
-  snprintf(buf, sizeof buf, "%s|%dx%dx%d|K%d|ds%dx%dx%d|%s", arch.c_str(), p->g.nx, p->g.ny, p->g.nz, p->g.K, p->g.sx,
-           p->g.sy, p->g.sz, p->compact ? "analytic" : (p->g.C > 1 ? (p->g.C == 2 ? "user2" : "user3") : "user"));
+  // plans on the compile-time passes time a different A + A^T (only xb and the merged
+  // launch's threads matter there): their own entries
+  snprintf(buf, sizeof buf, "%s|%dx%dx%d|K%d|ds%dx%dx%d|%s%s", arch.c_str(), p->g.nx, p->g.ny, p->g.nz, p->g.K, p->g.sx,
+           p->g.sy, p->g.sz, p->compact ? "analytic" : (p->g.C > 1 ? (p->g.C == 2 ? "user2" : "user3") : "user"),
+           use_fast(p) ? "|compiled" : "");
   return buf;
 }
 

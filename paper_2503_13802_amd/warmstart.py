@@ -28,18 +28,22 @@ def learning_rate(j, steps, lr, lr_final=None):
 
 def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spheres=80, n_tubes=6,
           snr=(20.0, 40.0), decay_db=3.0, log=None, log_every=100, target="phantom", crops_per_sample=1,
-          solve_tol=1e-4, solve_max_iter=5000, lr_final=None):
+          solve_tol=1e-4, solve_max_iter=5000, lr_final=None, evaluate=None, eval_at=()):
     """Trains `net` on `steps` crops of phantom/portrait pairs generated on the GPU from
     the plan's forward model (sample j uses seed seed0 + j; each sample serves
     crops_per_sample consecutive steps).  target "phantom" regresses the phantom;
     "solution" regresses the plain solver's end point at solve_tol from rho = 0 (the
     point a warm-started solve converges to).  Returns the loss history (every
     log_every steps).  lr_final: cosine decay of the learning rate from lr to lr_final
-    over the steps (constant lr if None)."""
+    over the steps (constant lr if None).  evaluate(j): called before step j for every j
+    in eval_at (and after the last step if steps is in eval_at), e.g. a validation loss."""
     hist = []
+    eval_at = set(int(j) for j in eval_at)
     t0 = time.perf_counter()
     x = tgt = None
     for j in range(steps):
+        if evaluate is not None and j in eval_at:
+            evaluate(j)
         sample = j // crops_per_sample
         seed = seed0 + sample
         if j % crops_per_sample == 0:
@@ -58,7 +62,22 @@ def train(plan, net, steps, seed0=5_000_000, crop=(64, 64, 64), lr=1e-3, n_spher
             hist.append((j, loss))
             if log:
                 log("train step %d/%d loss %.4e (%.1f s)" % (j, steps, loss, time.perf_counter() - t0))
+    if evaluate is not None and steps in eval_at:
+        evaluate(steps)
     return hist
+
+
+def validation_loss(plan, net, samples):
+    """Mean over held-out (back-projection, phantom) pairs of the training loss on the
+    whole volume, mean((net(x/s) - rho/s)^2) with s = max |A^T d| (network forward only;
+    the mean runs in torch on the device)."""
+    torch = plan.torch
+    tot = 0.0
+    for x, rho in samples:
+        y = net.forward(x)
+        s = float(x.sum(dim=0).abs().max())
+        tot += float(torch.mean((y - rho / s) ** 2))
+    return tot / max(1, len(samples))
 
 
 def compare(plan, net, seeds, tol=1e-4, max_iter=5000, n_spheres=80, n_tubes=6, snr=(20.0, 40.0), decay_db=3.0):
