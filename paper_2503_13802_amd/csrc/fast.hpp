@@ -87,7 +87,14 @@ struct FastGeo {
   static constexpr int PB0 = NP * LSZ, PB1 = NZH * LSY;
   static constexpr int PBUF = PB0 > PB1 ? PB0 : PB1;
   static constexpr size_t LDS_PLANE = sizeof(float2) * (NZ + MY + 2 * (size_t)PBUF + NCLS);
-  static constexpr size_t LDS_COL = sizeof(float2) * (NX + MX + 2 * (size_t)CPC * LSX + 2 * (size_t)KMAX * CPC * MX);
+  static constexpr int LSM = MX | 1;                        // line stride of the column pass's x' lines
+  static constexpr size_t LDS_COL = sizeof(float2) * (NX + MX + 2 * (size_t)CPC * LSX + 2 * (size_t)KMAX * CPC * LSM);
+  // small-grid inverse pass: packed row pairs of xb x'-planes or half-spectrum columns
+  static constexpr int LSMY = MY | 1, LSMZ = MZ | 1;
+  static constexpr size_t small_lds(int xb) {
+    const size_t a = (size_t)((xb * MY + 1) / 2) * LSMZ, b = (size_t)xb * MZH * LSMY;
+    return sizeof(float2) * (MY + MZ + 2 * (a > b ? a : b));
+  }
   static_assert(MY % 2 == 0, "row pairs: my must be even");
   static_assert(NZ % 4 == 0, "rows are loaded as float4");
   static_assert(MZ % 2 == 0, "the decimated z-axis is even");
@@ -300,8 +307,9 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   float2* twm = twx + NX;
   float2* U0 = twm + MX;
   float2* U1 = U0 + CPC * LSX;
+  constexpr int LSM = G::LSM;
   float2* F0 = U1 + CPC * LSX;
-  float2* F1 = F0 + KMAX * CPC * MX;
+  float2* F1 = F0 + KMAX * CPC * LSM;
   const int t = threadIdx.x;
   const int cl = t / MX, qxp = t - (t / MX) * MX;
   // the shares of the block's columns: consecutive threads take consecutive columns of one x
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
       const int k = p / (CPC * MX), r = p - k * (CPC * MX);
       const int c = r / MX, qq = r - c * MX;
       const int xbi = qq / xb, xi = qq - xbi * xb;
-      F0[p] = vd.Gp[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi];
+      F0[(k * CPC + c) * LSM + qq] = vd.Gp[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi];
     }
   }
   // x factors of the thread's aliases and (residual) the data's spectra
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   const float2* Rt = nullptr;   // A^T alone: R_k(q'x) = x' transform of the portraits' spectra
   if constexpr (MODE == COL_ADJ) {
     __syncthreads();
-    Rt = ct_stages<MX, 0, 1, -1>(F0, F1, twm, K * CPC, MX);
+    Rt = lf_fft<MX, 0, 1, -1, KMAX * CPC, LSM>(F0, F1, twm);
   }
   const float Mf = (float)(G::MX * G::MY * G::MZ);
   float2 q[SX];
@@ -379,11 +387,11 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
 #pragma unroll
         for (int jx = 0; jx < SX; ++jx) { fx += fs[k][jx] * w[jx].x; fy += fs[k][jx] * w[jx].y; }
         const float2 f = im ? make_float2(-fy, fx) : make_float2(fx, fy);
-        if constexpr (kStoreG) F0[(k * CPC + cl) * MX + qxp] = f;
+        if constexpr (kStoreG) F0[(k * CPC + cl) * LSM + qxp] = f;
         R = make_float2(Mf * f.x, Mf * f.y);
         if constexpr (MODE == NRM_RESID) R = csub(R, dt[k]);
       } else {
-        R = Rt[(k * CPC + cl) * MX + qxp];
+        R = Rt[(k * CPC + cl) * LSM + qxp];
       }
       if constexpr (kAdj) {
         if (im) R = make_float2(R.y, -R.x);   // conj(i F) R = -i F R
@@ -405,14 +413,14 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   }
   if constexpr (kStoreG) {
     __syncthreads();
-    const float2* F = ct_stages<MX, 0, 1, +1>(F0, F1, twm, K * CPC, MX);
+    const float2* F = lf_fft<MX, 0, 1, +1, KMAX * CPC, LSM>(F0, F1, twm);
     float2* __restrict__ Gs = vd.G;
     const int xb = vd.g.xb, nxb = MX / xb;
     for (int p = t; p < K * CPC * MX; p += G::TC) {
       const int k = p / (CPC * MX), r = p - k * (CPC * MX);
       const int xbi = r / (CPC * xb), r2 = r - xbi * (CPC * xb);
       const int c = r2 / xb, xi = r2 - c * xb;
-      Gs[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi] = F[(k * CPC + c) * MX + xbi * xb + xi];
+      Gs[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi] = F[(k * CPC + c) * LSM + xbi * xb + xi];
     }
   }
 }
@@ -671,6 +679,79 @@ __global__ __launch_bounds__(256) void k_fast_plane_adj(const VolDesc* __restric
   fast_plane_adj_body<G, OUT>(vds[0], blockIdx.x, ao);
 }
 
+// ============================================================================ small-grid inverse
+// Block (k, x'-block of XB planes): the portraits d_k of those planes from their decimated
+// spectra G[k][x'-block][column][x'-in-block] (the column pass's output): inverse
+// length-my transform along y', C2R along z' (row pairs packed), store.  The same
+// transforms as small_inv_body<EPI_STORE> (kernels.hpp) on compile-time sizes.
+template <class G, int XB>
+__device__ __forceinline__ void fast_small_inv_body(const VolDesc& vd, int lb, float* __restrict__ d) {
+  constexpr int MY = G::MY, MZ = G::MZ, MZH = G::MZH, LSMY = G::LSMY, LSMZ = G::LSMZ;
+  constexpr int ROWS = XB * MY, NPR = (ROWS + 1) / 2, NXB = G::MX / XB;
+  constexpr size_t A0 = (size_t)NPR * LSMZ, A1 = (size_t)XB * MZH * LSMY;
+  constexpr int SB = A0 > A1 ? (int)A0 : (int)A1;
+  extern __shared__ float2 lds[];
+  float2* twy = lds;
+  float2* twz = twy + MY;
+  float2* P0 = twz + MZ;
+  float2* P1 = P0 + SB;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int k = lb / NXB, xbi = lb - (lb / NXB) * NXB;
+  const float2* __restrict__ src = vd.G + ((long long)k * NXB + xbi) * G::NCLS * XB;
+  constexpr int NS = G::NCLS * XB;
+  for (int p = t; p < NS; p += nt) {
+    const float2 v = src[p];
+    const int c = p / XB, xi = p - (p / XB) * XB;
+    const int qyp = c / MZH, qzp = c - (c / MZH) * MZH;
+    P0[(xi * MZH + qzp) * LSMY + qyp] = v;
+  }
+  load_table(twy, vd.tw + vd.off[4], MY);
+  load_table(twz, vd.tw + vd.off[5], MZ);
+  __syncthreads();
+  float2* X = lf_fft<MY, 0, 1, +1, XB * MZH, LSMY>(P0, P1, twy);
+  float2* Zb = (X == P0) ? P1 : P0;
+  // C2R along z': row r = xi my + y', pairs (2j, 2j+1) packed
+  for (int it = t; it < NPR * MZ; it += nt) {
+    const int j = it / MZ, q = it - (it / MZ) * MZ;
+    const bool upper = 2 * q > MZ;
+    const int qq = upper ? MZ - q : q;
+    const int r0 = 2 * j, r1 = 2 * j + 1;
+    float2 xv = X[((r0 / MY) * MZH + qq) * LSMY + r0 % MY];
+    float2 yv = r1 < ROWS ? X[((r1 / MY) * MZH + qq) * LSMY + r1 % MY] : make_float2(0.f, 0.f);
+    if (qq == 0 || 2 * qq == MZ) { xv.y = 0.f; yv.y = 0.f; }
+    if (upper) { xv.y = -xv.y; yv.y = -yv.y; }
+    Zb[j * LSMZ + q] = make_float2(xv.x - yv.y, xv.y + yv.x);
+  }
+  __syncthreads();
+  const float2* Z = lf_fft<MZ, 0, 1, +1, NPR, LSMZ>(Zb, X, twz);
+  // store the block's rows: d[k][xbi XB + xi][y'][z'] is one contiguous run
+  float* __restrict__ dst = d + (long long)k * G::MX * MY * MZ + (long long)xbi * XB * MY * MZ;
+  constexpr int Q4 = ROWS * MZ / 4;
+  for (int f = t; f < Q4; f += nt) {
+    const int r = f / (MZ / 4), z4 = 4 * (f - (f / (MZ / 4)) * (MZ / 4));
+    const float2* zr = Z + (r >> 1) * LSMZ + z4;
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (r & 1) ? zr[e].y : zr[e].x;
+    *reinterpret_cast<float4*>(dst + (long long)r * MZ + z4) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+template <class G>
+__device__ __forceinline__ void fast_small_inv_dispatch(const VolDesc& vd, int lb, float* __restrict__ d) {
+  switch (vd.g.xb) {
+    case 1: fast_small_inv_body<G, 1>(vd, lb, d); break;
+    case 2: fast_small_inv_body<G, 2>(vd, lb, d); break;
+    case 4: fast_small_inv_body<G, 4>(vd, lb, d); break;
+    default: fast_small_inv_body<G, 8>(vd, lb, d); break;
+  }
+}
+
+template <class G>
+__global__ __launch_bounds__(256) void k_fast_small_inv(const VolDesc* __restrict__ vds, float* __restrict__ d) {
+  fast_small_inv_dispatch<G>(vds[0], blockIdx.x, d);
+}
+
 // A then A^T after k_fast_col<NRM_STORE>: blocks [0, NBP) run the adjoint plane pass
 // (ao.out = b . v), the others the small-grid inverse pass that writes the portraits d.
 template <class G>
@@ -678,7 +759,7 @@ __global__ __launch_bounds__(256) void k_fast_adj_and_store(const VolDesc* __res
                                                             float* __restrict__ d) {
   const VolDesc& vd = vds[0];
   if ((int)blockIdx.x < G::NBP) fast_plane_adj_body<G, OUT_SCALE_B>(vd, blockIdx.x, ao);
-  else small_inv_body<EPI_STORE>(vd, blockIdx.x - G::NBP, d);
+  else fast_small_inv_dispatch<G>(vd, blockIdx.x - G::NBP, d);
 }
 
 }  // namespace mh3d

@@ -392,7 +392,8 @@ struct FastOps {
   void (*plane_fwd)(hipStream_t, const VolDesc*, int src, const float* a);
   void (*cls)(hipStream_t, const VolDesc*, int mode, int chk);
   void (*plane_adj)(hipStream_t, const VolDesc*, int out, AdjOut ao);
-  void (*adj_and_store)(hipStream_t, const VolDesc*, AdjOut ao, float* d, int nsmall, size_t lds);
+  void (*adj_and_store)(hipStream_t, const VolDesc*, AdjOut ao, float* d, int nsmall, int xb);
+  void (*small_inv)(hipStream_t, const VolDesc*, float* d, int nsmall, int xb);
 };
 
 template <class G>
@@ -421,12 +422,16 @@ struct FastImpl {
     else if (out == OUT_STEP_FISTA) k_fast_plane_adj<G, OUT_STEP_FISTA><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
     else k_fast_plane_adj<G, OUT_SCALE_B><<<grid, block, G::LDS_PLANE, s>>>(vd, ao);
   }
-  static void adj_and_store(hipStream_t s, const VolDesc* vd, AdjOut ao, float* d, int nsmall, size_t lds) {
-    k_fast_adj_and_store<G><<<dim3(G::NBP + nsmall), dim3(G::TP), std::max(lds, G::LDS_PLANE), s>>>(vd, ao, d);
+  static void adj_and_store(hipStream_t s, const VolDesc* vd, AdjOut ao, float* d, int nsmall, int xb) {
+    k_fast_adj_and_store<G><<<dim3(G::NBP + nsmall), dim3(G::TP), std::max(G::small_lds(xb), G::LDS_PLANE), s>>>(
+        vd, ao, d);
+  }
+  static void small_inv(hipStream_t s, const VolDesc* vd, float* d, int nsmall, int xb) {
+    k_fast_small_inv<G><<<dim3(nsmall), dim3(G::TP), G::small_lds(xb), s>>>(vd, d);
   }
   static FastOps ops() {
     return FastOps{G::NX, G::NY, G::NZ, G::SX, G::SY, G::SZ, G::KMAX, G::NBP, G::NCLS / G::CPC, G::TC,
-                   G::LDS_PLANE, G::LDS_COL, &plane_fwd, &cls, &plane_adj, &adj_and_store};
+                   G::LDS_PLANE, G::LDS_COL, &plane_fwd, &cls, &plane_adj, &adj_and_store, &small_inv};
   }
 };
 
@@ -581,7 +586,11 @@ static mh3d_status launch_adj_and_store(mh3d_plan_t p, float* d, float* x) {
 }
 
 // The fused sequences run the compile-time passes of fast.hpp when the plan has them.
-static bool use_fast(mh3d_plan_t p) { return p->fast && p->fast_on; }
+static bool use_fast(mh3d_plan_t p) {
+  // the compile-time small-grid pass takes x'-blocks of 1, 2, 4 or 8 planes
+  const int xb = p->g.xb;
+  return p->fast && p->fast_on && (xb == 1 || xb == 2 || xb == 4 || xb == 8);
+}
 
 // Scalar plans with one workgroup per x-plane also run the next update's forward plane
 // pass in the launch of the step (k_step_and_fwd).
@@ -603,7 +612,7 @@ static mh3d_status fast_adj_and_store(mh3d_plan_t p, float* d, float* x) {
   AdjOut ao;
   ao.out = x;
   ao.yin = nullptr;
-  p->fast->adj_and_store(p->ls, p->vda, ao, d, p->g.K * (p->g.mx / p->g.xb), p->L.lds_small);
+  p->fast->adj_and_store(p->ls, p->vda, ao, d, p->g.K * (p->g.mx / p->g.xb), p->g.xb);
   return last_launch("k_fast_adj_and_store");
 }
 static mh3d_status fast_class_alone(mh3d_plan_t p, int mode) {
@@ -1021,7 +1030,9 @@ extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
   if (use_fast(p)) {
     CHK(fast_plane_fwd(p, SRC_PLAIN, rho));
     CHK(fast_class_alone(p, COL_FWD));
-    return launch_small_inv(p, EPI_STORE, d);
+    Timer t(p, KID_SMALL_INV);
+    p->fast->small_inv(p->ls, p->vda, d, p->g.K * (p->g.mx / p->g.xb), p->g.xb);
+    return last_launch("k_fast_small_inv");
   }
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
   CHK(launch_class_fwd(p, 0, FWD_G));
