@@ -1,5 +1,6 @@
 // Warm-start 3D U-Net on gfx950: BF16 activations and weights, FP32 accumulation on
-// MFMA (v_mfma_f32_16x16x16_bf16), FP32 master weights, Adam.
+// MFMA (v_mfma_f32_16x16x32_bf16, two 16-deep reduction chunks per instruction; a
+// trailing odd chunk uses v_mfma_f32_16x16x16_bf16), FP32 master weights, Adam.
 //
 // Tensors are channels-last BF16 [X][Y][Z][Cs] with the channel stride Cs a
 // multiple of 4 (padding channels hold zeros).  Grid axes are powers of two so
@@ -19,7 +20,20 @@ namespace mh3d {
 namespace net {
 
 typedef short s4v __attribute__((ext_vector_type(4)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Two 16-deep reduction chunks in one 16x16x32 MFMA.  The instruction reads lane group g
+// (lane / 16) element j as reduction index 8g + j of A and of B; placing chunk 0's
+// slice (k = 4g + j) in elements 0..3 and chunk 1's (k = 16 + 4g + j) in 4..7 applies
+// the same permutation of the 32 reduction indices to both operands, so the result is
+// the sum of the two 16x16x16 products (in another order of the FP32 additions).
+__device__ __forceinline__ f4v mfma2(s4v a0, s4v a1, s4v b0, s4v b1, f4v c) {
+  const s8v a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+  const s8v b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
+}
 
 constexpr int NT_MAX = 7;   // output-channel tiles per wave (112 channels)
 
@@ -79,7 +93,8 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, D
   for (int t = 0; t < NT_MAX; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
   int tap = 0, ci = 4 * g;
   while (ci >= cs_in) { ci -= cs_in; ++tap; }
-  for (int kc = 0; kc < (kp >> 4); ++kc) {
+  // A slice of the current chunk (this lane's voxel, 4 reduction indices), then step
+  auto a_next = [&]() {
     s4v a = s4v{0, 0, 0, 0};
     if (nvalid && tap < ntap) {
       int dx, dy, dz;
@@ -87,16 +102,33 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, D
       const int xx = x + dx, yy = y + dy, zz = z + dz;
       if (dm.inside(xx, yy, zz)) a = *reinterpret_cast<const s4v*>(in + dm.encode(xx, yy, zz) * cs_in + ci);
     }
-    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
-#pragma unroll
-    for (int t = 0; t < NT_MAX; ++t) {
-      if (t < ntile) {
-        const s4v b = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-      }
-    }
     ci += 16;
     while (ci >= cs_in) { ci -= cs_in; ++tap; }
+    return a;
+  };
+  const int nkc = kp >> 4;
+  for (int kc = 0; kc < nkc; kc += 2) {
+    const s4v a0 = a_next();
+    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
+    if (kc + 1 < nkc) {
+      const s4v a1 = a_next();
+#pragma unroll
+      for (int t = 0; t < NT_MAX; ++t) {
+        if (t < ntile) {
+          const s4v b0 = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+          const s4v b1 = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + 16);
+          acc[t] = mfma2(a0, a1, b0, b1, acc[t]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT_MAX; ++t) {
+        if (t < ntile) {
+          const s4v b = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
   }
 #pragma unroll
   for (int t = 0; t < NT_MAX; ++t) {
@@ -148,7 +180,8 @@ __global__ __launch_bounds__(256) void k_conv_splitk(const uint16_t* __restrict_
   // k = kc*16 + 4g: start at chunk `wave`, step 4 chunks (64 k) at a time
   int tap = 0, ci = wave * 16 + 4 * g;
   while (ci >= cs_in) { ci -= cs_in; ++tap; }
-  for (int kc = wave; kc < (kp >> 4); kc += 4) {
+  // A slice of this wave's current chunk, then step to its next chunk (4 chunks on)
+  auto a_next = [&]() {
     s4v a = s4v{0, 0, 0, 0};
     if (nvalid && tap < ntap) {
       int dx, dy, dz;
@@ -156,16 +189,33 @@ __global__ __launch_bounds__(256) void k_conv_splitk(const uint16_t* __restrict_
       const int xx = x + dx, yy = y + dy, zz = z + dz;
       if (dm.inside(xx, yy, zz)) a = *reinterpret_cast<const s4v*>(in + dm.encode(xx, yy, zz) * cs_in + ci);
     }
-    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
-#pragma unroll
-    for (int t = 0; t < NT_MAX; ++t) {
-      if (t < ntile) {
-        const s4v b = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-      }
-    }
     ci += 64;
     while (ci >= cs_in) { ci -= cs_in; ++tap; }
+    return a;
+  };
+  const int nkc = kp >> 4;
+  for (int kc = wave; kc < nkc; kc += 8) {   // chunks kc and kc + 4 in one instruction
+    const s4v a0 = a_next();
+    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
+    if (kc + 4 < nkc) {
+      const s4v a1 = a_next();
+#pragma unroll
+      for (int t = 0; t < NT_MAX; ++t) {
+        if (t < ntile) {
+          const s4v b0 = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+          const s4v b1 = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + 64);
+          acc[t] = mfma2(a0, a1, b0, b1, acc[t]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < NT_MAX; ++t) {
+        if (t < ntile) {
+          const s4v b = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b, acc[t], 0, 0, 0);
+        }
+      }
+    }
   }
   if (wave) {
 #pragma unroll
@@ -237,27 +287,50 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const uint16_t* __restrict__
   int tap = 0, ci = 4 * g;
   while (ci >= cs_in) { ci -= cs_in; ++tap; }
   const int row_stride = 18 * cs_in;            // one (x, y) row of the tile
-  for (int kc = 0; kc < (kp >> 4); ++kc) {
-    s4v b[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      b[t] = *reinterpret_cast<const s4v*>(W + (long long)(t * 16 + r) * kp + kc * 16 + 4 * g);
-    // taps past 26 only meet the zero padding rows of W: their A values stay 0
-    int off = 0;
-    const bool tv = tap < 27;
-    if (tv) {
+  // LDS offset of the current chunk's A slice (taps past 26 only meet the zero padding
+  // rows of W: their A values stay 0, offset -1), then step to the next chunk
+  auto off_next = [&]() {
+    int off = -1;
+    if (tap < 27) {
       const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
       off = ((wave + dx) * 6 + dy) * row_stride + (r + dz) * cs_in + ci;
     }
-#pragma unroll
-    for (int yy = 0; yy < 4; ++yy) {
-      s4v a = s4v{0, 0, 0, 0};
-      if (tv) a = *reinterpret_cast<const s4v*>(tile + off + yy * row_stride);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[yy][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[yy][t], 0, 0, 0);
-    }
     ci += 16;
     while (ci >= cs_in) { ci -= cs_in; ++tap; }
+    return off;
+  };
+  auto a_at = [&](int off, int yy) {
+    return off >= 0 ? *reinterpret_cast<const s4v*>(tile + off + yy * row_stride) : s4v{0, 0, 0, 0};
+  };
+  const int nkc = kp >> 4;
+  for (int kc = 0; kc < nkc; kc += 2) {
+    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
+    const int off0 = off_next();
+    if (kc + 1 < nkc) {
+      const int off1 = off_next();
+      s4v b0[NT], b1[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        b0[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+        b1[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + 16);
+      }
+#pragma unroll
+      for (int yy = 0; yy < 4; ++yy) {
+        const s4v a0 = a_at(off0, yy), a1 = a_at(off1, yy);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[yy][t] = mfma2(a0, a1, b0[t], b1[t], acc[yy][t]);
+      }
+    } else {
+      s4v b[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
+#pragma unroll
+      for (int yy = 0; yy < 4; ++yy) {
+        const s4v a = a_at(off0, yy);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[yy][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[yy][t], 0, 0, 0);
+      }
+    }
   }
   // D[row = 4g + j][col = r]: voxel z0 + 4g + j of row (x0 + wave, y0 + yy), channel t*16 + r
 #pragma unroll
@@ -345,19 +418,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t* __rest
     }
     __syncthreads();
 #pragma unroll 1
-    for (int vc = 0; vc < 16; ++vc) {
+    for (int vc = 0; vc < 16; vc += 2) {   // 16-voxel rows vc and vc + 1 in one instruction
       // voxels v = vc*16 + 4*g4 + j: row (xl, yl) = (vc / 4, vc % 4), z = 4*g4 + j
-      const int rowoff = ((vc >> 2) * 6 + (vc & 3)) * 18 * cs_in + 4 * g4 * cs_in;
+      const int rowoff0 = ((vc >> 2) * 6 + (vc & 3)) * 18 * cs_in + 4 * g4 * cs_in;
+      const int rowoff1 = (((vc + 1) >> 2) * 6 + ((vc + 1) & 3)) * 18 * cs_in + 4 * g4 * cs_in;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (!bval[i]) continue;
-        const s4v a = *reinterpret_cast<const s4v*>(gT + (bco[i] * 16 + r) * 256 + vc * 16 + 4 * g4);
-        s4v b = s4v{0, 0, 0, 0};
+        const uint16_t* ar = gT + (bco[i] * 16 + r) * 256 + vc * 16 + 4 * g4;
+        const s4v a0 = *reinterpret_cast<const s4v*>(ar);
+        const s4v a1 = *reinterpret_cast<const s4v*>(ar + 16);
+        s4v b0 = s4v{0, 0, 0, 0}, b1 = s4v{0, 0, 0, 0};
         if (tval[i]) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = (short)halo[boff[i] + rowoff + j * cs_in];
+          for (int j = 0; j < 4; ++j) {
+            b0[j] = (short)halo[boff[i] + rowoff0 + j * cs_in];
+            b1[j] = (short)halo[boff[i] + rowoff1 + j * cs_in];
+          }
         }
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+        acc[i] = mfma2(a0, a1, b0, b1, acc[i]);
       }
     }
   }
@@ -394,8 +473,8 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
   int dx = 0, dy = 0, dz = 0;
   if (kvalid) tap_offset(tap, ks, dx, dy, dz);
   f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
-  for (long long nb = v0; nb < v1; nb += 16) {
-    s4v a, b;
+  // the 4 voxels of this lane group in the 16-voxel chunk at nb (zero past v1)
+  auto slices = [&](long long nb, s4v& a, s4v& b) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long n = nb + 4 * g + j;
@@ -412,7 +491,12 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
       a[j] = (short)av;
       b[j] = (short)bv;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  };
+  for (long long nb = v0; nb < v1; nb += 32) {   // two chunks per instruction (the second may be empty)
+    s4v a0, b0, a1, b1;
+    slices(nb, a0, b0);
+    slices(nb + 16, a1, b1);
+    acc = mfma2(a0, a1, b0, b1, acc);
   }
   // D[row = co 4g+j][col = k r]
 #pragma unroll
