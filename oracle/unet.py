@@ -13,6 +13,17 @@ Network (levels L = 4, widths w0..w3, 3x3x3 convolutions with zero padding 1):
 ``up2`` repeats each voxel 2x2x2 (nearest).  Convolutions are cross-correlations
 out[n] = b + sum_tap W[tap] in[n + d(tap)] (torch.nn.functional.conv3d).
 
+Storage model (``bf16=True``): the network is specified with BF16 weights,
+activations and activation gradients and FP32 (here: exact) sums.  The model rounds,
+to the nearest BF16 with ties to even (of the value's FP32 rounding):
+  values    -- the network input, every weight (biases stay unrounded), every
+               post-ReLU convolution output and every pooled tensor;
+  gradients -- of the head output, of every convolution input, of each encoder
+               output that feeds both the skip and the pool (once, after the two
+               contributions are summed) and of every tensor before upsampling
+               (after the 8 children are summed).
+Weight and bias gradients are not rounded.  With ``bf16=False`` everything is FP64.
+
 Flat parameter layout shared with the device (``param_layout``): for each layer
 in the order enc0a, enc0b, enc1a, enc1b, ..., dec0b, head: W as [Cout][tap][Cin]
 with tap = (dx+1)*9 + (dy+1)*3 + (dz+1) (a single tap for the head), then the
@@ -74,37 +85,66 @@ def pack_grads(grads, widths, in_ch=1):
     return out
 
 
-def forward(params, x, widths):
-    """x: [X, Y, Z] or [Cin, X, Y, Z] -> output [X, Y, Z], all float64."""
+def round_bf16(t):
+    """Nearest BF16 (ties to even) of the FP32 rounding of t, held in float64."""
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def _store(t):
+    """BF16 value with the gradient passed through unchanged."""
+    return t + (round_bf16(t) - t).detach()
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Identity whose backward rounds the incoming gradient to BF16."""
+
+    @staticmethod
+    def forward(ctx, t):
+        return t.view_as(t)
+
+    @staticmethod
+    def backward(ctx, g):
+        return round_bf16(g)
+
+
+def forward(params, x, widths, bf16=False):
+    """x: [X, Y, Z] or [Cin, X, Y, Z] -> output [X, Y, Z], float64 (with the BF16
+    storage model of the module docstring if bf16)."""
     L = len(widths)
+    val = _store if bf16 else (lambda t: t)
+    grad = _RoundGrad.apply if bf16 else (lambda t: t)
     h = torch.as_tensor(x, dtype=torch.float64)
     if h.dim() == 3:
         h = h[None, None]
     elif h.dim() == 4:
         h = h[None]
+    h = val(h)
 
     def conv(name, t, relu=True):
         W, b = params[name]
         k = W.shape[-1]
-        y = F.conv3d(t, W, b, padding=k // 2)
-        return torch.relu(y) if relu else y
+        y = F.conv3d(grad(t), val(W), b, padding=k // 2)
+        return val(torch.relu(y)) if relu else y
 
     skips = []
     for l in range(L):
         if l:
-            h = F.avg_pool3d(h, 2)
+            h = val(F.avg_pool3d(h, 2))
         h = conv("enc%db" % l, conv("enc%da" % l, h))
+        if l < L - 1:
+            h = grad(h)          # skip and pool gradients summed, then rounded
         skips.append(h)
     for l in range(L - 2, -1, -1):
-        up = h.repeat_interleave(2, 2).repeat_interleave(2, 3).repeat_interleave(2, 4)
+        up = grad(h).repeat_interleave(2, 2).repeat_interleave(2, 3).repeat_interleave(2, 4)
         h = torch.cat([skips[l], up], dim=1)
         h = conv("dec%db" % l, conv("dec%da" % l, h))
-    return conv("head", h, relu=False)[0, 0]
+    return grad(conv("head", h, relu=False))[0, 0]
 
 
-def loss_and_grads(flat, x, target, widths):
+def loss_and_grads(flat, x, target, widths, bf16=False):
     """MSE loss mean((net(x) - t)^2) and its gradient in the flat layout
-    (x: [X, Y, Z] or [Cin, X, Y, Z]; t: [X, Y, Z])."""
+    (x: [X, Y, Z] or [Cin, X, Y, Z]; t: [X, Y, Z]); bf16: the storage model of the
+    module docstring."""
     in_ch = 1 if np.ndim(x) == 3 else np.shape(x)[0]
     params = unpack(flat, widths, in_ch)
     leaves = {}
@@ -112,7 +152,7 @@ def loss_and_grads(flat, x, target, widths):
         W = W.clone().requires_grad_(True)
         b = b.clone().requires_grad_(True)
         leaves[k] = (W, b)
-    y = forward(leaves, x, widths)
+    y = forward(leaves, x, widths, bf16)
     t = torch.as_tensor(target, dtype=torch.float64)
     loss = torch.mean((y - t) ** 2)
     loss.backward()
