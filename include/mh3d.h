@@ -216,15 +216,20 @@ mh3d_status mh3d_plan_get_tiles(mh3d_plan_t plan, mh3d_tiles* tiles);
 mh3d_status mh3d_solve_static(mh3d_plan_t plan, const float* d, float* rho_inout, const mh3d_solve_opts* opts,
                               mh3d_solve_info* info);
 
-/* Pass family of the fused sequences/* Pass family of the fused sequences (mh3d_forward_adjoint, mh3d_normal,
- * mh3d_power_iteration, mh3d_solve) -- the same operator (Sec. 4.1 eq. dN, Table
+/* Pass family of the fused sequences (mh3d_forward_adjoint, mh3d_normal,
+ * mh3d_power_iteration, mh3d_solve) and of the separate calls mh3d_forward,
+ * mh3d_adjoint and mh3d_backproject -- the same operator (Sec. 4.1 eq. dN, Table
  * tab:ops) and solver step (Sec. 4.3) either way:
  *   1  compile-time-geometry passes, where the library has them for the plan's grid,
- *      decimation and harmonic count (scalar model, analytic PSF, no padding): the
- *      y-transform is split four-step between the plane and class passes, the plane
- *      passes run one workgroup per (x-plane, y mod ds1) and the class pass keeps every
- *      harmonic's spectra of its elements in registers.  The default.
- *   0  the general passes (as the separate calls and batches always run).
+ *      decimation and harmonic count (scalar model, analytic PSF, no padding).  The
+ *      analytic PSF is a product of an x factor per harmonic and a (y, z) factor shared
+ *      by all harmonics (Sec. 2, the PSF form), so its spectra are too: a plane pass per
+ *      (x-plane, y mod ds1) weights by b, transforms along z and y (the y-transform
+ *      split four-step with the column pass) and folds the (y, z) aliases with the
+ *      shared factor; a column pass per decimated (y, z) frequency transforms along x
+ *      and applies every harmonic's x factor and x fold; the adjoint runs the same
+ *      steps backwards.  The default.
+ *   0  the general passes (as batches always run).
  * Results agree to FP32 rounding (the sums run in other orders).  request: 0 or 1 to
  * choose (synchronous; fails if the plan belongs to a batch), -1 to only query;
  * *active (HOST, may be NULL) receives 1 if the compile-time passes will run. */

@@ -293,9 +293,11 @@ enum { COL_FWD = 16, COL_ADJ = 17 };
 // R_k(q'x); Q transformed back along x goes to qx[x][column] for the adjoint plane
 // pass.  NRM_STORE also writes the portraits' decimated spectra G (inverse x' transform
 // of Fhat) for the small-grid pass; M Fhat then stands for the spectra of d itself.
+//
+// grid.y > 1 runs one descriptor per y-block (the back-projections of single harmonics).
 template <class G, int MODE>
 __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ vds, int check_done) {
-  const VolDesc& vd = vds[0];
+  const VolDesc& vd = vds[blockIdx.y];
   if (check_done && vd.st->done) return;
   constexpr int NX = G::NX, MX = G::MX, SX = G::SX, CPC = G::CPC, KMAX = G::KMAX, LSX = G::LSX;
   constexpr bool kFwd = MODE != COL_ADJ, kAdj = MODE != COL_FWD;
@@ -674,9 +676,11 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
   }
 }
 
+// grid.y > 1 (OUT_SCALE_B only): descriptor y and output volume y of consecutive volumes.
 template <class G, int OUT>
 __global__ __launch_bounds__(256) void k_fast_plane_adj(const VolDesc* __restrict__ vds, AdjOut ao) {
-  fast_plane_adj_body<G, OUT>(vds[0], blockIdx.x, ao);
+  if constexpr (OUT == OUT_SCALE_B) ao.out += (long long)blockIdx.y * G::NX * G::NY * G::NZ;
+  fast_plane_adj_body<G, OUT>(vds[blockIdx.y], blockIdx.x, ao);
 }
 
 // ============================================================================ small-grid inverse

@@ -260,6 +260,7 @@ struct FastOps;
 struct mh3d_plan_s {
   const FastOps* fast = nullptr;   // compile-time-geometry passes of the fused sequences (or none)
   bool fast_on = true;             // whether the fused sequences use them (mh3d_plan_path)
+  bool each_batched = false;       // the single-harmonic descriptors have separate Q buffers
   mh3d_plan_desc desc;
   std::vector<int> harm;
   Geo g;
@@ -394,6 +395,9 @@ struct FastOps {
   void (*plane_adj)(hipStream_t, const VolDesc*, int out, AdjOut ao);
   void (*adj_and_store)(hipStream_t, const VolDesc*, AdjOut ao, float* d, int nsmall, int xb);
   void (*small_inv)(hipStream_t, const VolDesc*, float* d, int nsmall, int xb);
+  // A^T of nv single-harmonic descriptors at once (each with its own qx): out volumes
+  // out + v N for v < nv
+  void (*adjoint_each)(hipStream_t, const VolDesc*, int nv, float* out);
 };
 
 template <class G>
@@ -429,9 +433,17 @@ struct FastImpl {
   static void small_inv(hipStream_t s, const VolDesc* vd, float* d, int nsmall, int xb) {
     k_fast_small_inv<G><<<dim3(nsmall), dim3(G::TP), G::small_lds(xb), s>>>(vd, d);
   }
+  static void adjoint_each(hipStream_t s, const VolDesc* vd, int nv, float* out) {
+    k_fast_col<G, COL_ADJ><<<dim3(G::NCLS / G::CPC, nv), dim3(G::TC), G::LDS_COL, s>>>(vd, 0);
+    AdjOut ao;
+    ao.out = out;
+    ao.yin = nullptr;
+    k_fast_plane_adj<G, OUT_SCALE_B><<<dim3(G::NBP, nv), dim3(G::TP), G::LDS_PLANE, s>>>(vd, ao);
+  }
   static FastOps ops() {
     return FastOps{G::NX, G::NY, G::NZ, G::SX, G::SY, G::SZ, G::KMAX, G::NBP, G::NCLS / G::CPC, G::TC,
-                   G::LDS_PLANE, G::LDS_COL, &plane_fwd, &cls, &plane_adj, &adj_and_store, &small_inv};
+                   G::LDS_PLANE, G::LDS_COL, &plane_fwd, &cls, &plane_adj, &adj_and_store, &small_inv,
+                   &adjoint_each};
   }
 };
 
@@ -904,12 +916,19 @@ static mh3d_status upload_harmonic_descs(mh3d_plan_t p) {
   const Geo& g = p->g;
   std::vector<VolDesc> h(g.K, p->vdh);
   const size_t esz = p->compact ? sizeof(float) : sizeof(float2);
+  // the compile-time passes: harmonic k's x factors, and its own Q buffer when the K of
+  // them fit in the class-layout buffer (the column pass of A^T alone does not read the
+  // shares that otherwise sit there), so the K adjoints run in one launch per pass
+  const size_t nq = (size_t)g.nx * g.ncls;
+  p->each_batched = p->fast && (size_t)g.K * nq <= (size_t)g.C * g.nx * g.plane;
   for (int k = 0; k < g.K; ++k) {
     h[k].g.K = 1;
     h[k].hs = (const char*)p->vdh.hs + (size_t)k * g.hsz * esz;
     h[k].Gp = p->vdh.Gp + (size_t)k * g.mx * g.ncls;
     h[k].imag_mask = (p->vdh.imag_mask >> k) & 1u;
     for (int c = 0; c < 3; ++c) h[k].cmask[c] = (p->vdh.cmask[c] >> k) & 1u;
+    if (p->sfs) h[k].sfs = p->sfs + (size_t)k * g.nx;
+    if (p->each_batched) h[k].qx = p->uperm + (size_t)k * nq;
   }
   HIPCHK(hipMemcpyAsync(p->vdk, h.data(), sizeof(VolDesc) * g.K, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -1058,6 +1077,19 @@ extern "C" mh3d_status mh3d_backproject(mh3d_plan_t p, const float* d, float* c)
   CHK(check_plan(p));
   if (!c || !d) return fail(MH3D_ERR_INVALID, "NULL array");
   CHK(launch_small_fwd(p, d));
+  if (use_fast(p)) {
+    // column and plane passes of A^T with one descriptor per harmonic (all K at once when
+    // their Q buffers fit, else one harmonic after another through the shared one)
+    if (p->each_batched) {
+      p->fast->adjoint_each(p->ls, p->vdk, p->g.K, c);
+      return last_launch("k_fast_col / k_fast_plane_adj (per harmonic)");
+    }
+    for (int k = 0; k < p->g.K; ++k) {
+      p->fast->adjoint_each(p->ls, p->vdk + k, 1, c + (size_t)k * p->g.N);
+      CHK(last_launch("k_fast_col / k_fast_plane_adj (per harmonic)"));
+    }
+    return MH3D_OK;
+  }
   for (int k = 0; k < p->g.K; ++k) {
     CHK(launch_class_adj(p, 0, p->vdk + k));
     CHK(launch_plane_adj(p, OUT_SCALE_B, c + (size_t)k * p->g.N, nullptr, p->vdk + k));

@@ -171,6 +171,11 @@ mh3d_status launch_conv(mh3d_net_t n, const uint16_t* in, Dims dm, int cs_in, in
     else k_conv_splitk<false><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
     return last_launch("k_conv_splitk");
   }
+  if (f32 && ks == 1 && cout == 1) {   // the head: one output channel
+    k_head1<<<std::min(grid_for(N, 256), 8192), 256, 0, n->stream>>>(in, N, cs_in, cs_in, W, bias,
+                                                                   reinterpret_cast<float*>(out));
+    return last_launch("k_head1");
+  }
   const int blocks = (int)((N + 63) / 64);
   if (f32) k_conv<false, true><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, out);
   else if (relu) k_conv<true, false><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, out);
@@ -204,8 +209,14 @@ mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
                                                             nsplit, chunk);
     CHK(last_launch("k_conv_wgrad"));
   }
-  dim3 bg(std::min<long long>(1024, (N + 3) / 4), (ly.cout + 63) / 64);
-  k_bias_grad<<<bg, 256, 0, n->stream>>>(g, N, cs_g, ly.cout, n->g + ly.b_off);
+  {
+    // cs_g <= 256 channels; blocks: a multiple of cs_g / 4 (each thread keeps one channel group)
+    if (cs_g > 256 || cs_g % 4) return fail(MH3D_ERR_UNSUPPORTED, "gradient channel stride %d (at most 256)", cs_g);
+    const int cq = cs_g / 4;
+    const long long items = N * cq;
+    long long nb = std::max<long long>(1, std::min<long long>(items / (256 * 16), 1024 / cq));
+    k_bias_grad<<<(int)(nb * cq), 256, 0, n->stream>>>(g, N, cs_g, ly.cout, n->g + ly.b_off);
+  }
   CHK(last_launch("k_bias_grad"));
   if (gin) {
     // data gradient = convolution of g with the flipped, transposed weights (no bias)
@@ -220,7 +231,8 @@ mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long
   const int L = (int)n->widths.size();
   if (!n->packed) CHK(net_pack(n));
   unsigned* slot = reinterpret_cast<unsigned*>(w->scale + 4);
-  k_absmax<<<grid_for(nsrc, 256) < 1024 ? grid_for(nsrc, 256) : 1024, 256, 0, n->stream>>>(x, nsrc, n->in_ch, slot);
+  if (nsrc % 4) return fail(MH3D_ERR_INVALID, "volume size %lld is not a multiple of 4", nsrc);
+  k_absmax<<<std::min(grid_for(nsrc / 4, 256), 4096), 256, 0, n->stream>>>(x, nsrc, n->in_ch, slot);
   CHK(last_launch("k_absmax"));
   k_absmax_final<<<1, 64, 0, n->stream>>>(slot, w->scale);
   CHK(last_launch("k_absmax_final"));
@@ -245,7 +257,7 @@ mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long
     Dims dl = dims_of(*w, l);
     const int c1 = n->widths[l], c2 = n->widths[l + 1];
     const int cats = round4(c1 + c2);
-    k_upcat<<<grid_for(dl.n() * cats), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
+    k_upcat<<<grid_for(dl.n()), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
                                                             dims_of(*w, l + 1), cats, w->cat[l]);
     CHK(last_launch("k_upcat"));
     CHK(conv_fwd(n, n->layers[dec_index(L, l, 0)], w->cat[l], dl, w->da[l], true, false));

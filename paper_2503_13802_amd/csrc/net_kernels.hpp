@@ -134,15 +134,16 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ in, D
   for (int t = 0; t < NT_MAX; ++t) {
     if (t >= ntile) break;
     const int co = t * 16 + r;
+    const float bv = co < cout ? bias[co] : 0.f;   // once: the stores may alias bias for the compiler
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long nn = n0 + 4 * g + j;
       if (nn >= N) continue;
       if constexpr (OUTF32) {
-        if (co == 0) reinterpret_cast<float*>(out)[nn] = acc[t][j] + bias[0];
+        if (co == 0) reinterpret_cast<float*>(out)[nn] = acc[t][j] + bv;
       } else {
         if (co < cout) {
-          float v = acc[t][j] + bias[co];
+          float v = acc[t][j] + bv;
           if (RELU) v = fmaxf(v, 0.f);
           reinterpret_cast<uint16_t*>(out)[nn * cs_out + co] = f2bf(v);
         } else if (co < cs_out) {
@@ -231,18 +232,49 @@ __global__ __launch_bounds__(256) void k_conv_splitk(const uint16_t* __restrict_
 #pragma unroll
     for (int w = 0; w < 3; ++w) v += part[w][t][lane];
     const int co = t * 16 + r;
+    const float bv = co < cout ? bias[co] : 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long long nn = n0 + 4 * g + j;
       if (nn >= N) continue;
       if (co < cout) {
-        float o = v[j] + bias[co];
+        float o = v[j] + bv;
         if (RELU) o = fmaxf(o, 0.f);
         out[nn * cs_out + co] = f2bf(o);
       } else if (co < cs_out) {
         out[nn * cs_out + co] = 0;
       }
     }
+  }
+}
+
+// The 6 x 6 x 18 input halo of a 4 x 4 x 16 output tile at (x0, y0, z0) into LDS
+// ([voxel][cs_in], zero outside the volume), 4 channels (8 bytes) per item with z-runs
+// contiguous in global memory.  A thread's items go in batches of 8 whose loads are all
+// issued before the LDS writes (a load-then-write loop would wait on every load).
+__device__ __forceinline__ void stage_halo(uint16_t* __restrict__ tile, const uint16_t* __restrict__ in, const Dims& dm,
+                                           int cs_in, int x0, int y0, int z0) {
+  const int cq = cs_in >> 2;
+  const int nitem = 648 * cq;
+  for (int q0 = threadIdx.x; q0 < nitem; q0 += 8 * 256) {
+    s4v val[8];
+    int dst[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * 256;
+      val[u] = s4v{0, 0, 0, 0};
+      dst[u] = -1;
+      if (q < nitem) {
+        const int v = q / cq, c4 = q - v * cq;
+        const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
+        const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
+        dst[u] = v * cs_in + 4 * c4;
+        if (dm.inside(gx, gy, gz)) val[u] = *reinterpret_cast<const s4v*>(in + dm.encode(gx, gy, gz) * cs_in + 4 * c4);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (dst[u] >= 0) *reinterpret_cast<s4v*>(tile + dst[u]) = val[u];
   }
 }
 
@@ -266,17 +298,7 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const uint16_t* __restrict__
   const int ty = rest & ((1 << nyt) - 1);
   const int tx = rest >> nyt;
   const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 16;
-  // halo load, 4 channels (8 bytes) per item; z-runs are contiguous in global memory
-  const int cq = cs_in >> 2;
-  const int nitem = 648 * cq;
-  for (int q = threadIdx.x; q < nitem; q += 256) {
-    const int v = q / cq, c4 = q - v * cq;
-    const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
-    const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
-    s4v val = s4v{0, 0, 0, 0};
-    if (dm.inside(gx, gy, gz)) val = *reinterpret_cast<const s4v*>(in + dm.encode(gx, gy, gz) * cs_in + 4 * c4);
-    *reinterpret_cast<s4v*>(tile + v * cs_in + 4 * c4) = val;
-  }
+  stage_halo(tile, in, dm, cs_in, x0, y0, z0);
   __syncthreads();
   const int r = lane & 15, g = lane >> 4;
   f4v acc[4][NT];
@@ -303,33 +325,30 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const uint16_t* __restrict__
     return off >= 0 ? *reinterpret_cast<const s4v*>(tile + off + yy * row_stride) : s4v{0, 0, 0, 0};
   };
   const int nkc = kp >> 4;
+  const uint16_t* wr = W + (long long)r * kp + 4 * g;
+  // B slices of the chunk pair (kc, kc + 1), loaded one pair ahead; an odd last chunk
+  // pairs with zeros (its products add exact zeros)
+  s4v nb0[NT], nb1[NT];
+  auto load_b = [&](int kc) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      nb0[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + kc * 16);
+      nb1[t] = kc + 1 < nkc ? *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + kc * 16 + 16) : s4v{0, 0, 0, 0};
+    }
+  };
+  load_b(0);
   for (int kc = 0; kc < nkc; kc += 2) {
-    const uint16_t* wr = W + (long long)r * kp + kc * 16 + 4 * g;
+    s4v b0[NT], b1[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) { b0[t] = nb0[t]; b1[t] = nb1[t]; }
+    if (kc + 2 < nkc) load_b(kc + 2);
     const int off0 = off_next();
-    if (kc + 1 < nkc) {
-      const int off1 = off_next();
-      s4v b0[NT], b1[NT];
+    const int off1 = kc + 1 < nkc ? off_next() : -1;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        b0[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
-        b1[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + 16);
-      }
+    for (int yy = 0; yy < 4; ++yy) {
+      const s4v a0 = a_at(off0, yy), a1 = a_at(off1, yy);
 #pragma unroll
-      for (int yy = 0; yy < 4; ++yy) {
-        const s4v a0 = a_at(off0, yy), a1 = a_at(off1, yy);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[yy][t] = mfma2(a0, a1, b0[t], b1[t], acc[yy][t]);
-      }
-    } else {
-      s4v b[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp);
-#pragma unroll
-      for (int yy = 0; yy < 4; ++yy) {
-        const s4v a = a_at(off0, yy);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[yy][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[yy][t], 0, 0, 0);
-      }
+      for (int t = 0; t < NT; ++t) acc[yy][t] = mfma2(a0, a1, b0[t], b1[t], acc[yy][t]);
     }
   }
   // D[row = 4g + j][col = r]: voxel z0 + 4g + j of row (x0 + wave, y0 + yy), channel t*16 + r
@@ -338,11 +357,12 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const uint16_t* __restrict__
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + r;
+      const float bv = co < cout ? bias[co] : 0.f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const long long nn = dm.encode(x0 + wave, y0 + yy, z0 + 4 * g + j);
         if (co < cout) {
-          float v = acc[yy][t][j] + bias[co];
+          float v = acc[yy][t][j] + bv;
           if (RELU) v = fmaxf(v, 0.f);
           out[nn * cs_out + co] = f2bf(v);
         } else if (co < cs_out) {
@@ -393,7 +413,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t* __rest
   for (int i = 0; i < 4; ++i) acc[i] = f4v{0.f, 0.f, 0.f, 0.f};
   // padding rows of the transposed gradient stay zero for every tile
   for (int q = threadIdx.x; q < (ncot * 16 - cs_g) * 256; q += 256) gT[cs_g * 256 + q] = 0;
-  const int cq = cs_in >> 2, cqg = cs_g >> 2;
+  const int cqg = cs_g >> 2;
   for (int it = 0; it < tpb; ++it) {
     const int tile = blockIdx.x * tpb + it;
     if (tile >= ntiles) break;
@@ -401,20 +421,24 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t* __rest
     const int ty = rest & ((1 << nyt) - 1), tx = rest >> nyt;
     const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 16;
     __syncthreads();      // the previous tile's reads are done
-    for (int q = threadIdx.x; q < 648 * cq; q += 256) {
-      const int v = q / cq, c4 = q - v * cq;
-      const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
-      const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
-      s4v val = s4v{0, 0, 0, 0};
-      if (dm.inside(gx, gy, gz)) val = *reinterpret_cast<const s4v*>(in + dm.encode(gx, gy, gz) * cs_in + 4 * c4);
-      *reinterpret_cast<s4v*>(halo + v * cs_in + 4 * c4) = val;
-    }
-    for (int q = threadIdx.x; q < 256 * cqg; q += 256) {
-      const int v = q % 256, c4 = q / 256;
+    stage_halo(halo, in, dm, cs_in, x0, y0, z0);
+    {
+      // the tile's output gradients, transposed to [channel][voxel]: thread = voxel v,
+      // its cqg loads issued (in batches of 8) before the LDS writes
+      const int v = threadIdx.x;
       const long long nn = dm.encode(x0 + (v >> 6), y0 + ((v >> 4) & 3), z0 + (v & 15));
-      const s4v val = *reinterpret_cast<const s4v*>(gout + nn * cs_g + 4 * c4);
+      for (int c0 = 0; c0 < cqg; c0 += 8) {
+        s4v val[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) gT[(4 * c4 + j) * 256 + v] = (uint16_t)val[j];
+        for (int u = 0; u < 8; ++u)
+          if (c0 + u < cqg) val[u] = *reinterpret_cast<const s4v*>(gout + nn * cs_g + 4 * (c0 + u));
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (c0 + u < cqg) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) gT[(4 * (c0 + u) + j) * 256 + v] = (uint16_t)val[u][j];
+          }
+      }
     }
     __syncthreads();
 #pragma unroll 1
@@ -506,20 +530,30 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
   }
 }
 
-// Bias gradient gb[co] += sum_n g[n][co].  grid = (blocks, ceil(cout/64)), 256 threads.
+// Bias gradient gb[co] += sum_n g[n][co] (cs_g <= 256), 256 threads per block.
 __global__ void k_bias_grad(const uint16_t* __restrict__ gout, long long N, int cs_g, int cout, float* __restrict__ gb) {
-  __shared__ float part[256];
-  const int co = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int sub = threadIdx.x >> 6;
-  float s = 0.f;
-  if (co < cout)
-    for (long long n = (long long)blockIdx.x * 4 + sub; n < N; n += (long long)gridDim.x * 4) s += bf2f(gout[n * cs_g + co]);
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (sub == 0 && co < cout) {
-    const float t = part[threadIdx.x] + part[threadIdx.x + 64] + part[threadIdx.x + 128] + part[threadIdx.x + 192];
-    atomicAdd(&gb[co], t);
+  // items (voxel, group of 4 channels) in memory order, 8-byte loads; the grid's thread
+  // count is a multiple of cs_g / 4, so each thread always meets the same channel group
+  __shared__ float bins[256];
+  const int cq = cs_g >> 2;
+  const long long nitem = N * cq;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (int c = threadIdx.x; c < cs_g; c += blockDim.x) bins[c] = 0.f;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (long long i = i0; i < nitem; i += stride) {
+    const s4v v = *reinterpret_cast<const s4v*>(gout + 4 * i);
+    acc.x += bf2f((uint16_t)v[0]); acc.y += bf2f((uint16_t)v[1]);
+    acc.z += bf2f((uint16_t)v[2]); acc.w += bf2f((uint16_t)v[3]);
   }
+  __syncthreads();
+  const int c4 = (int)(i0 % cq);
+  atomicAdd(&bins[4 * c4 + 0], acc.x);
+  atomicAdd(&bins[4 * c4 + 1], acc.y);
+  atomicAdd(&bins[4 * c4 + 2], acc.z);
+  atomicAdd(&bins[4 * c4 + 3], acc.w);
+  __syncthreads();
+  for (int c = threadIdx.x; c < cout; c += blockDim.x) atomicAdd(&gb[c], bins[c]);
 }
 
 // FP32 channel-major volumes [C][src] / scale -> BF16 channels-last [N][cs] (crop
@@ -532,7 +566,12 @@ __global__ void k_to_bf16_crop(const float* __restrict__ x, int C, Dims src, int
     int x0, y0, z0;
     dst.decode(i, x0, y0, z0);
     const long long j = src.encode(x0 + ox, y0 + oy, z0 + oz);
-    for (int c = 0; c < cs; ++c) out[i * cs + c] = c < C ? f2bf(x[c * ns + j] * inv) : (uint16_t)0;
+    for (int c4 = 0; c4 < cs; c4 += 4) {   // cs is a multiple of 4: 8-byte stores
+      s4v v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = (short)(c4 + q < C ? f2bf(x[(c4 + q) * ns + j] * inv) : (uint16_t)0);
+      *reinterpret_cast<s4v*>(out + i * cs + c4) = v;
+    }
   }
 }
 
@@ -564,20 +603,32 @@ __global__ void k_avgpool_bwd_add(const uint16_t* __restrict__ gout, Dims dout, 
 }
 
 // out[n] = [skip[n][0:c1], coarse[n/2][0:c2], 0...] (nearest upsampling + concat).
+// One thread per fine voxel, 4 channels (8 bytes) per store; a group of 4 channels that
+// lies within one source at a 4-aligned offset is one 8-byte load (the channel strides
+// are multiples of 4), any other group is gathered channel by channel.
 __global__ void k_upcat(const uint16_t* __restrict__ skip, int cs1, int c1, const uint16_t* __restrict__ coarse, int cs2,
                         int c2, Dims df, Dims dc, int cs, uint16_t* __restrict__ out) {
-  const long long N = df.n() * cs;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
-    const long long n = i / cs;
-    const int c = (int)(i - n * cs);
-    uint16_t v = 0;
-    if (c < c1) v = skip[n * cs1 + c];
-    else if (c < c1 + c2) {
-      int x, y, z;
-      df.decode(n, x, y, z);
-      v = coarse[dc.encode(x >> 1, y >> 1, z >> 1) * cs2 + (c - c1)];
+  const long long N = df.n();
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    df.decode(n, x, y, z);
+    const uint16_t* sr = skip + n * cs1;
+    const uint16_t* cr = coarse + dc.encode(x >> 1, y >> 1, z >> 1) * cs2;
+    for (int c = 0; c < cs; c += 4) {
+      s4v v = s4v{0, 0, 0, 0};
+      if (c + 4 <= c1) {
+        v = *reinterpret_cast<const s4v*>(sr + c);
+      } else if (c >= c1 && c + 4 <= c1 + c2 && ((c - c1) & 3) == 0) {
+        v = *reinterpret_cast<const s4v*>(cr + (c - c1));
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int cc = c + q;
+          v[q] = (short)(cc < c1 ? sr[cc] : (cc < c1 + c2 ? cr[cc - c1] : (uint16_t)0));
+        }
+      }
+      *reinterpret_cast<s4v*>(out + n * cs + c) = v;
     }
-    out[i] = v;
   }
 }
 
@@ -638,13 +689,18 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
 // folded into *slot with an integer atomic max (the bit patterns of non-negative
 // floats order like their values), then k_absmax_final writes it as FP64 to *out
 // (1 if the maximum is 0) and clears the slot for the next call.
+// Items of 4 consecutive voxels (n is a multiple of 4), channels summed in order.
 __global__ void k_absmax(const float* __restrict__ x, long long n, int C, unsigned* __restrict__ slot) {
   __shared__ float part[256];
   float m = 0.f;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    float v = 0.f;
-    for (int c = 0; c < C; ++c) v += x[c * n + i];
-    m = fmaxf(m, fabsf(v));
+  const long long n4 = n >> 2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int c = 0; c < C; ++c) {
+      const float4 a = reinterpret_cast<const float4*>(x + c * n)[i];
+      v.x += a.x; v.y += a.y; v.z += a.z; v.w += a.w;
+    }
+    m = fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
   }
   part[threadIdx.x] = m;
   __syncthreads();
@@ -654,6 +710,23 @@ __global__ void k_absmax(const float* __restrict__ x, long long n, int C, unsign
   }
   if (threadIdx.x == 0) atomicMax(slot, __float_as_uint(part[0]));
 }
+// 1x1x1 convolution to one FP32 output channel (the head): y[n] = b + sum_c W[c] in[n][c],
+// W the first row of the packed BF16 forward matrix, FP32 sums.
+__global__ void k_head1(const uint16_t* __restrict__ in, long long N, int cs_in, int cin, const uint16_t* __restrict__ W,
+                        const float* __restrict__ bias, float* __restrict__ y) {
+  const float b = bias[0];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int c4 = 0; c4 < cs_in; c4 += 4) {
+      const s4v v = *reinterpret_cast<const s4v*>(in + i * cs_in + c4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (c4 + q < cin) acc += bf2f((uint16_t)v[q]) * bf2f(W[c4 + q]);
+    }
+    y[i] = acc + b;
+  }
+}
+
 __global__ void k_absmax_final(unsigned* __restrict__ slot, double* __restrict__ out) {
   if (threadIdx.x == 0) {
     const float t = __uint_as_float(*slot);

@@ -53,6 +53,12 @@ def test_fast_operator_matches_direct_sums(shape, ds, harm):
     r = inputs.random_field(d_ref.shape, 7)
     x1 = p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
     assert rel_l2(x1, om.adjoint_direct(h, b, r, ds)) <= TOL
+    # per-harmonic back-projections c_k = b H_k^T P^T r_k (all K at once where their
+    # buffers fit, one after another otherwise), and their sum is A^T r
+    c = p.backproject(torch.tensor(r, dtype=torch.float32)).cpu().numpy()
+    for k in range(len(harm)):
+        assert rel_l2(c[k], om.adjoint_fft(h[k:k + 1], b, r[k:k + 1], ds)) <= TOL, k
+    assert rel_l2(c.astype(np.float64).sum(axis=0), x1) <= 2e-6
     # FP32 adjoint identity <A x, r> = <x, A^T r>
     lhs = float(np.sum(p.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy().astype(np.float64) * r))
     rhs = float(np.sum(x * x1))
@@ -136,7 +142,14 @@ def test_fast_full_size_workload2():
     got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=8, tol=0.0, tau=0.07)
     assert info["iters"] == 8
     assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+    # the per-harmonic back-projections of the warm start's input (two of them against
+    # the oracle, all against the general passes below)
+    c1 = p.backproject(torch.tensor(d, dtype=torch.float32)).cpu().numpy()
+    for k in (0, len(w.harmonics) - 1):
+        assert rel_l2(c1[k], om.adjoint_fft(h[k:k + 1], b, d[k:k + 1], w.ds)) <= TOL, k
     p.path(0)
+    c0 = p.backproject(torch.tensor(d, dtype=torch.float32)).cpu().numpy()
+    assert rel_l2(c1, c0) <= 2e-6
     d0, x0 = p.forward_adjoint(torch.tensor(rho, dtype=torch.float32))
     assert rel_l2(d2.cpu().numpy(), d0.cpu().numpy()) <= 2e-6
     assert rel_l2(x2.cpu().numpy(), x0.cpu().numpy()) <= 2e-6

@@ -37,43 +37,68 @@ def _scale(x):
 
 
 def test_net_forward_matches_fp64_reference():
+    """Against the reference network's BF16 storage model (the network's specified
+    precision: BF16 weights and activations, FP32 sums) closely, and against its FP64
+    form within the BF16 error."""
     torch, net, flat, x, t = _setup(1)
     announce("net forward")
     y = net.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
     s = _scale(x)
-    want = unet.forward(unet.unpack(flat.astype(np.float32).astype(np.float64), WIDTHS), x / s, WIDTHS).numpy()
-    err = rel_l2(y, want)
-    print("forward rel err %.3e" % err, flush=True)
-    assert err <= 3e-2
+    params = unet.unpack(flat.astype(np.float32).astype(np.float64), WIDTHS)
+    want = unet.forward(params, x / s, WIDTHS).numpy()
+    model = unet.forward(params, x / s, WIDTHS, bf16=True).detach().numpy()
+    print("forward rel err %.3e (FP64), %.3e (BF16 storage model)" % (rel_l2(y, want), rel_l2(y, model)), flush=True)
+    assert rel_l2(y, model) <= 1e-4
+    assert rel_l2(y, want) <= 3e-2
 
 
-# BF16 activations and gradients: every rounding is ~2^-9 relative, and the ReLU
-# masks of the two sides differ where a pre-activation is within rounding of zero.
-# The weight gradient of a layer is a sum over all voxels with heavy cancellation,
-# so its relative error grows with the number of layers the gradient has crossed.
-# A structural mistake (a wrong tap, channel or transpose) gives errors near 1.
-@pytest.mark.parametrize("widths,shape,in_ch,layer_tol", [((4, 8), (16, 16, 16), 1, 5e-2),
-                                                          ((4, 8), (16, 8, 16), 5, 5e-2),
-                                                          ((4, 8, 8, 16), (32, 32, 32), 3, 0.2)])
-def test_net_gradients_match_fp64_reference(widths, shape, in_ch, layer_tol):
+# The BF16 storage model rounds exactly where the device stores BF16, so the device
+# and the model differ only by the order of the FP32 sums, which now and then moves a
+# BF16 rounding by one ulp.  On the 2-level nets that leaves them equal to about 1e-7
+# (bar 1e-4 per layer).  Through the 15 layers of the 4-level net such flips feed later
+# rounding decisions, and the device and the model become two equally valid BF16
+# realisations: each sits at the BF16 storage error from the FP64 network (the model
+# measures it: 0.8 to 3.7 per cent per layer for this seed, the first layers' weight
+# gradients being sums over all voxels with cancellation), so the bar there is 3e-2
+# against the model and twice the measured storage error (+1e-2) against FP64.  A
+# structural mistake (a wrong tap, channel or transpose) gives errors near 1.
+@pytest.mark.parametrize("widths,shape,in_ch,model_tol", [((4, 8), (16, 16, 16), 1, 1e-4),
+                                                          ((4, 8), (16, 8, 16), 5, 1e-4),
+                                                          ((4, 8, 8, 16), (32, 32, 32), 3, 3e-2)])
+def test_net_gradients_match_fp64_reference(widths, shape, in_ch, model_tol):
     torch, net, flat, x, t = _setup(2, shape=shape, widths=widths, in_ch=in_ch)
     announce("net gradients %s C=%d" % (widths, in_ch))
     loss = net.loss_grad(torch.tensor(x, dtype=torch.float32), torch.tensor(t, dtype=torch.float32))
     g = net.grads().cpu().numpy()
     s = _scale(x)
-    want_loss, want_g, _ = unet.loss_and_grads(flat.astype(np.float32).astype(np.float64), x / s, t / s, widths)
+    f32 = flat.astype(np.float32).astype(np.float64)
+    want_loss, want_g, _ = unet.loss_and_grads(f32, x / s, t / s, widths)
+    model_loss, model_g, _ = unet.loss_and_grads(f32, x / s, t / s, widths, bf16=True)
     lay, _ = unet.param_layout(widths, in_ch)
-    errs = {name: (rel_l2(g[wo:bo], want_g[wo:bo]), rel_l2(g[bo:bo + cout], want_g[bo:bo + cout]))
-            for name, cin, cout, k, wo, bo in lay}
-    print("loss %.6e vs %.6e; total grad rel err %.3e; per layer (W, b): %s"
-          % (loss, want_loss, rel_l2(g, want_g), {k: "%.3f/%.3f" % v for k, v in errs.items()}), flush=True)
+
+    def per_layer(ref):
+        return {name: (rel_l2(g[wo:bo], ref[wo:bo]), rel_l2(g[bo:bo + cout], ref[bo:bo + cout]))
+                for name, cin, cout, k, wo, bo in lay}
+
+    e_model, e_64 = per_layer(model_g), per_layer(want_g)
+    e_storage = {name: (rel_l2(model_g[wo:bo], want_g[wo:bo]), rel_l2(model_g[bo:bo + cout], want_g[bo:bo + cout]))
+                 for name, cin, cout, k, wo, bo in lay}
+    fmt = lambda d: {k: "%.4f/%.4f" % v for k, v in d.items()}
+    print("loss %.6e vs %.6e (FP64), %.6e (model); total grad rel err %.3e (FP64), %.3e (model)"
+          % (loss, want_loss, model_loss, rel_l2(g, want_g), rel_l2(g, model_g)), flush=True)
+    print("per layer (W/b) vs model: %s" % fmt(e_model), flush=True)
+    print("per layer (W/b) vs FP64: %s" % fmt(e_64), flush=True)
+    print("per layer (W/b) model vs FP64 (BF16 storage error): %s" % fmt(e_storage), flush=True)
+    assert loss == pytest.approx(model_loss, rel=2e-3)
     assert loss == pytest.approx(want_loss, rel=2e-2)
+    assert rel_l2(g, model_g) <= 1e-2
     assert rel_l2(g, want_g) <= 5e-2
     cos = float(np.dot(g, want_g) / (np.linalg.norm(g) * np.linalg.norm(want_g)))
     assert cos >= 0.998
-    for name, (ew, eb) in errs.items():
-        assert ew <= layer_tol, name
-        assert eb <= 2 * layer_tol, name
+    for name in e_model:
+        assert e_model[name][0] <= model_tol and e_model[name][1] <= model_tol, name
+        assert e_64[name][0] <= 2 * e_storage[name][0] + 1e-2, name
+        assert e_64[name][1] <= 2 * e_storage[name][1] + 1e-2, name
 
 
 def test_net_crop_uses_whole_volume_scale():
