@@ -71,7 +71,7 @@ __global__ void k_sep_tables(Geo g, const double2* __restrict__ fhat, const doub
   }
 }
 
-template <int NX_, int NY_, int NZ_, int SX_, int SY_, int SZ_, int CPC_, int KMAX_>
+template <int NX_, int NY_, int NZ_, int SX_, int SY_, int SZ_, int CPC_, int KMAX_, int TP_ = 256, int TPF_ = 256>
 struct FastGeo {
   static constexpr int NX = NX_, NY = NY_, NZ = NZ_, SX = SX_, SY = SY_, SZ = SZ_;
   static constexpr int MX = NX / SX, MY = NY / SY, MZ = NZ / SZ;
@@ -81,7 +81,8 @@ struct FastGeo {
   static constexpr int TC = CPC * MX;                       // column-pass threads: one per (column, q'x)
   static constexpr int LSX = NX | 1, LSZ = NZ | 1, LSY = MY | 1;
   static constexpr int NP = MY / 2;                         // row pairs of a plane block
-  static constexpr int TP = 256;                            // plane-pass threads
+  static constexpr int TP = TP_;                            // adjoint plane-pass threads
+  static constexpr int TPF = TPF_;                          // forward plane-pass threads
   static constexpr int NBP = NX * SY;                       // plane-pass blocks
   // one plane-pass LDS buffer: packed row pairs or half-spectrum columns (+ the staged Q)
   static constexpr int PB0 = NP * LSZ, PB1 = NZH * LSY;
@@ -166,7 +167,7 @@ __device__ __forceinline__ void fast_plane_of(int b, int& x, int& y0) {
 // R2C along z, length-my DFT along y1, then the share C(y0; x, q'y, q'z) of the folded
 // plane into cp[y0][x][column].
 template <class G, int SRC>
-__global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ a) {
+__global__ __launch_bounds__(G::TPF) void k_fast_plane_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ a) {
   const VolDesc& vd = vds[0];
   if constexpr (SRC == SRC_FISTA_Y || SRC == SRC_SCALED) {
     if (vd.st->done) return;
@@ -185,13 +186,13 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   const int t = threadIdx.x;
   // items (row pair j, 4 columns): rows 2j and 2j+1 of the block become the real and
   // imaginary parts of packed line j
-  constexpr int F4R = G::NZ / 4, F4 = G::NP * F4R, NL = (F4 + G::TP - 1) / G::TP;
+  constexpr int F4R = G::NZ / 4, F4 = G::NP * F4R, NL = (F4 + G::TPF - 1) / G::TPF;
   const long long pb = (long long)x * G::NY * G::NZ;
   const float* __restrict__ bs = vd.b;
   float4 va[NL][2], vb[NL][2];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    const int f = t + G::TP * i;
+    const int f = t + G::TPF * i;
     if (f < F4) {
       const int j = f / F4R, c4 = f - (f / F4R) * F4R;
 #pragma unroll
@@ -203,12 +204,12 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
     }
   }
   // the table Et of this y0 for the block's output columns (SZ values per column)
-  constexpr int NC = (G::NCLS + G::TP - 1) / G::TP;
+  constexpr int NC = (G::NCLS + G::TPF - 1) / G::TPF;
   const float2* __restrict__ et = vd.set + (long long)y0 * G::MY * G::NZH;
   float2 ev[NC][G::SZ];
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    const int c = t + G::TP * i;
+    const int c = t + G::TPF * i;
     if (c < G::NCLS) {
       const int qyp = c / G::MZH, qzp = c - (c / G::MZH) * G::MZH;
 #pragma unroll
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   if constexpr (SRC == SRC_SCALED) c = (float)vd.st->scale;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-    const int f = t + G::TP * i;
+    const int f = t + G::TPF * i;
     if (f < F4) {
       const int j = f / F4R, c4 = f - (f / F4R) * F4R;
       float u[2][4];
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   float2* Z = lf_fft<G::NZ, 0, 1, -1, G::NP, G::LSZ>(B0, B1, twz);
   float2* X = (Z == B0) ? B1 : B0;
   // split each packed pair into its two half spectra, columns X[qz][y1]
-  for (int it = t; it < G::NP * G::NZH; it += G::TP) {
+  for (int it = t; it < G::NP * G::NZH; it += G::TPF) {
     const int j = it / G::NZH, q = it - (it / G::NZH) * G::NZH;
     const float2 zq = Z[j * G::LSZ + q];
     const float2 zm = Z[j * G::LSZ + (q == 0 ? 0 : G::NZ - q)];
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256) void k_fast_plane_fwd(const VolDesc* __restric
   float2* __restrict__ dst = vd.cp + ((long long)y0 * G::NX + x) * G::NCLS;
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
-    const int cc = t + G::TP * i;
+    const int cc = t + G::TPF * i;
     if (cc < G::NCLS) {
       const int qyp = cc / G::MZH, qzp = cc - (cc / G::MZH) * G::MZH;
       float sx = 0.f, sy = 0.f;
@@ -678,7 +679,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
 
 // grid.y > 1 (OUT_SCALE_B only): descriptor y and output volume y of consecutive volumes.
 template <class G, int OUT>
-__global__ __launch_bounds__(256) void k_fast_plane_adj(const VolDesc* __restrict__ vds, AdjOut ao) {
+__global__ __launch_bounds__(G::TP) void k_fast_plane_adj(const VolDesc* __restrict__ vds, AdjOut ao) {
   if constexpr (OUT == OUT_SCALE_B) ao.out += (long long)blockIdx.y * G::NX * G::NY * G::NZ;
   fast_plane_adj_body<G, OUT>(vds[blockIdx.y], blockIdx.x, ao);
 }
@@ -752,14 +753,14 @@ __device__ __forceinline__ void fast_small_inv_dispatch(const VolDesc& vd, int l
 }
 
 template <class G>
-__global__ __launch_bounds__(256) void k_fast_small_inv(const VolDesc* __restrict__ vds, float* __restrict__ d) {
+__global__ __launch_bounds__(G::TP) void k_fast_small_inv(const VolDesc* __restrict__ vds, float* __restrict__ d) {
   fast_small_inv_dispatch<G>(vds[0], blockIdx.x, d);
 }
 
 // A then A^T after k_fast_col<NRM_STORE>: blocks [0, NBP) run the adjoint plane pass
 // (ao.out = b . v), the others the small-grid inverse pass that writes the portraits d.
 template <class G>
-__global__ __launch_bounds__(256) void k_fast_adj_and_store(const VolDesc* __restrict__ vds, AdjOut ao,
+__global__ __launch_bounds__(G::TP) void k_fast_adj_and_store(const VolDesc* __restrict__ vds, AdjOut ao,
                                                             float* __restrict__ d) {
   const VolDesc& vd = vds[0];
   if ((int)blockIdx.x < G::NBP) fast_plane_adj_body<G, OUT_SCALE_B>(vd, blockIdx.x, ao);

@@ -403,7 +403,7 @@ struct FastOps {
 template <class G>
 struct FastImpl {
   static void plane_fwd(hipStream_t s, const VolDesc* vd, int src, const float* a) {
-    const dim3 grid(G::NBP), block(G::TP);
+    const dim3 grid(G::NBP), block(G::TPF);
     switch (src) {
       case SRC_PLAIN: k_fast_plane_fwd<G, SRC_PLAIN><<<grid, block, G::LDS_PLANE, s>>>(vd, a); break;
       case SRC_FISTA_Y: k_fast_plane_fwd<G, SRC_FISTA_Y><<<grid, block, G::LDS_PLANE, s>>>(vd, a); break;
@@ -450,7 +450,7 @@ struct FastImpl {
 // Grids with compile-time passes: (nx, ny, nz, sx, sy, sz, columns per column-pass block,
 // largest harmonic count).
 static const FastOps kFast[] = {
-    FastImpl<FastGeo<128, 128, 128, 2, 4, 4, 4, 12>>::ops(),   // 128^3, k = 2..12
+    FastImpl<FastGeo<128, 128, 128, 2, 4, 4, 4, 12, 512, 512>>::ops(),   // 128^3, k = 2..12
     // small grids of the parity tests: every y split (1 to 4), radix 3 along x and y
     FastImpl<FastGeo<32, 32, 32, 2, 4, 4, 4, 12>>::ops(),
     FastImpl<FastGeo<16, 24, 16, 2, 2, 2, 4, 8>>::ops(),

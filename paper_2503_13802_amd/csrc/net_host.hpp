@@ -146,6 +146,36 @@ Dims dims_of(const NetWork& w, int l) { return Dims{w.lx - l, w.ly - l, w.lz - l
 // One convolution out = act(conv(in, W) + bias), BF16 channels-last output with
 // channel stride cs_out (or FP32 single-channel for the head).  3x3x3 layers with at
 // most 32 output channels on grids of at least 4 x 4 x 16 run the LDS-tiled kernel.
+// k_conv_ct for the channel strides it is compiled for (false: none, or kp does not
+// match the compile-time K).
+template <int CS>
+bool conv_ct_try(hipStream_t s, int ntile, bool relu, int blocks, const uint16_t* in, Dims dm, const uint16_t* W,
+                 int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
+  if (kp != 16 * ((27 * CS + 15) / 16) || ntile < 1 || ntile > 2) return false;
+  if (ntile == 1) {
+    if (relu) k_conv_ct<CS, 1, true><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
+    else k_conv_ct<CS, 1, false><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
+  } else {
+    if (relu) k_conv_ct<CS, 2, true><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
+    else k_conv_ct<CS, 2, false><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
+  }
+  return true;
+}
+
+bool conv_ct(hipStream_t s, int cs_in, int ntile, bool relu, int blocks, const uint16_t* in, Dims dm, const uint16_t* W,
+             int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
+  switch (cs_in) {
+    case 4: return conv_ct_try<4>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    case 8: return conv_ct_try<8>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    case 12: return conv_ct_try<12>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    case 16: return conv_ct_try<16>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    case 24: return conv_ct_try<24>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    case 32: return conv_ct_try<32>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    case 48: return conv_ct_try<48>(s, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o);
+    default: return false;
+  }
+}
+
 mh3d_status launch_conv(mh3d_net_t n, const uint16_t* in, Dims dm, int cs_in, int ks, const uint16_t* W, int kp,
                         const float* bias, int cout, int cs_out, void* out, bool relu, bool f32) {
   const long long N = 1ll << (dm.lx + dm.ly + dm.lz);
@@ -154,6 +184,8 @@ mh3d_status launch_conv(mh3d_net_t n, const uint16_t* in, Dims dm, int cs_in, in
   if (!f32 && ks == 3 && ntile <= 2 && dm.lz >= 4 && dm.ly >= 2 && dm.lx >= 2 && halo <= 64 * 1024) {
     const int blocks = (int)(N / 256);
     uint16_t* o = reinterpret_cast<uint16_t*>(out);
+    if (conv_ct(n->stream, cs_in, ntile, relu, blocks, in, dm, W, kp, bias, cout, cs_out, o))
+      return last_launch("k_conv_ct");
     if (relu) {
       if (ntile == 1) k_conv_tiled<true, 1><<<blocks, 256, halo, n->stream>>>(in, dm, cs_in, W, kp, bias, cout, cs_out, o);
       else k_conv_tiled<true, 2><<<blocks, 256, halo, n->stream>>>(in, dm, cs_in, W, kp, bias, cout, cs_out, o);
@@ -257,7 +289,7 @@ mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long
     Dims dl = dims_of(*w, l);
     const int c1 = n->widths[l], c2 = n->widths[l + 1];
     const int cats = round4(c1 + c2);
-    k_upcat<<<grid_for(dl.n()), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
+    k_upcat<<<grid_for(dl.n() * (cats / 4)), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
                                                             dims_of(*w, l + 1), cats, w->cat[l]);
     CHK(last_launch("k_upcat"));
     CHK(conv_fwd(n, n->layers[dec_index(L, l, 0)], w->cat[l], dl, w->da[l], true, false));

@@ -278,6 +278,140 @@ __device__ __forceinline__ void stage_halo(uint16_t* __restrict__ tile, const ui
   }
 }
 
+// 3x3x3 convolution on an LDS-staged tile with the input channel stride CS fixed at
+// compile time (the same implicit GEMM, tile and operands as k_conv_tiled, kp = 16
+// NKC).  Every index the reduction needs is a constant or comes from a per-block table
+// of the 4 lane groups' offsets per K chunk, so the reduction costs an LDS read of the
+// offset, the operand reads at immediate offsets and the MFMA: no tap arithmetic per
+// chunk.  The halo goes in per voxel (one contiguous CS-channel run), and the output
+// tile leaves through LDS as contiguous 16- or 8-byte pieces of each z-run.
+template <int CS, int NT, bool RELU>
+__global__ __launch_bounds__(256) void k_conv_ct(const uint16_t* __restrict__ in, Dims dm,
+                                                 const uint16_t* __restrict__ W, int kp,
+                                                 const float* __restrict__ bias, int cout, int cs_out,
+                                                 uint16_t* __restrict__ out) {
+  constexpr int NKC = (27 * CS + 15) / 16;
+  constexpr int RS = 18 * CS;                       // one (x, y) row of the halo
+  constexpr int HALO = 648 * CS;
+  constexpr int STAGE = 256 * 16 * NT;              // output staging (elements), at most
+  constexpr int TILE = ((HALO > STAGE ? HALO : STAGE) + 7) & ~7;
+  extern __shared__ uint16_t sm[];
+  uint16_t* tile = sm;
+  int* toff = reinterpret_cast<int*>(sm + TILE);   // [NKC][4] element offsets
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int nzt = dm.lz - 4, nyt = dm.ly - 2;
+  const int tz = blockIdx.x & ((1 << nzt) - 1);
+  const int rest = blockIdx.x >> nzt;
+  const int ty = rest & ((1 << nyt) - 1);
+  const int tx = rest >> nyt;
+  const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 16;
+  // reduction index k = 16 kc + 4 g + j -> (tap, channel) -> halo offset; the padding
+  // columns (tap >= 27) meet zero rows of W and read any finite halo entry (offset 0)
+  for (int i = threadIdx.x; i < NKC * 4; i += 256) {
+    const int k = 4 * i;
+    const int tap = k / CS, ci = k - (k / CS) * CS;
+    toff[i] = tap < 27 ? ((tap / 9) * 108 + ((tap / 3) % 3) * 18 + tap % 3) * CS + ci : 0;
+  }
+  // halo: voxel v = threadIdx.x + 256 u, its CS channels as CS/4 8-byte loads, all of a
+  // thread's loads issued before its LDS writes
+  {
+    constexpr int NQ = CS / 4;
+    s4v val[3][NQ];
+    long long src[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      src[u] = -1;
+      if (v < 648) {
+        const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
+        const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
+        if (dm.inside(gx, gy, gz)) src[u] = dm.encode(gx, gy, gz) * CS;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        val[u][q] = src[u] >= 0 ? *reinterpret_cast<const s4v*>(in + src[u] + 4 * q) : s4v{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int v = threadIdx.x + 256 * u;
+      if (v < 648) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) *reinterpret_cast<s4v*>(tile + v * CS + 4 * q) = val[u][q];
+      }
+    }
+  }
+  __syncthreads();
+  const int lbase = (wave * 108 + r) * CS;
+  f4v acc[4][NT];
+#pragma unroll
+  for (int yy = 0; yy < 4; ++yy)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[yy][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wr = W + (long long)r * kp + 4 * g;
+  auto pair = [&](int kc, bool two) {
+    const int o0 = lbase + toff[kc * 4 + g];
+    const int o1 = two ? lbase + toff[(kc + 1) * 4 + g] : 0;
+    s4v b0[NT], b1[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      b0[t] = *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + kc * 16);
+      b1[t] = two ? *reinterpret_cast<const s4v*>(wr + (long long)t * 16 * kp + kc * 16 + 16) : s4v{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int yy = 0; yy < 4; ++yy) {
+      const s4v a0 = *reinterpret_cast<const s4v*>(tile + o0 + yy * RS);
+      const s4v a1 = two ? *reinterpret_cast<const s4v*>(tile + o1 + yy * RS) : s4v{0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[yy][t] = mfma2(a0, a1, b0[t], b1[t], acc[yy][t]);
+    }
+  };
+#pragma unroll 4
+  for (int kc = 0; kc + 1 < NKC; kc += 2) pair(kc, true);
+  if constexpr (NKC & 1) pair(NKC - 1, false);
+  __syncthreads();   // every wave is done with the halo: its space stages the output
+  // D[row = 4g + j][col = r]: voxel z0 + 4g + j of row (x0 + wave, y0 + yy), channel t*16 + r
+  uint16_t* st = tile + wave * 64 * cs_out;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + r;
+    const float bv = co < cout ? bias[co] : 0.f;
+    if (co < cs_out) {
+#pragma unroll
+      for (int yy = 0; yy < 4; ++yy)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = acc[yy][t][j] + bv;
+          if (RELU) v = fmaxf(v, 0.f);
+          st[(yy * 16 + 4 * g + j) * cs_out + co] = co < cout ? f2bf(v) : (uint16_t)0;
+        }
+    }
+  }
+  __syncthreads();
+  // each (x, y) row of 16 voxels is a contiguous run of 16 cs_out channels in memory
+#pragma unroll
+  for (int yy = 0; yy < 4; ++yy) {
+    uint16_t* orow = out + dm.encode(x0 + wave, y0 + yy, z0) * cs_out;
+    const uint16_t* srow = st + yy * 16 * cs_out;
+    if ((cs_out & 7) == 0) {
+      for (int q = lane; q < 2 * cs_out; q += 64)
+        *reinterpret_cast<uint4*>(orow + 8 * q) = *reinterpret_cast<const uint4*>(srow + 8 * q);
+    } else {
+      for (int q = lane; q < 4 * cs_out; q += 64)
+        *reinterpret_cast<s4v*>(orow + 4 * q) = *reinterpret_cast<const s4v*>(srow + 4 * q);
+    }
+  }
+}
+
+// LDS bytes of k_conv_ct<CS, NT, *>.
+template <int CS, int NT>
+constexpr size_t conv_ct_lds() {
+  constexpr int NKC = (27 * CS + 15) / 16;
+  constexpr int HALO = 648 * CS, STAGE = 256 * 16 * NT;
+  constexpr int TILE = ((HALO > STAGE ? HALO : STAGE) + 7) & ~7;
+  return sizeof(uint16_t) * TILE + sizeof(int) * NKC * 4;
+}
+
 // 3x3x3 convolution on an LDS-staged input tile (the same implicit GEMM as k_conv).
 // A workgroup of 4 waves computes a 4 (x) x 4 (y) x 16 (z) output tile: the input
 // block with its one-voxel halo, 6 x 6 x 18 voxels x cs_in channels (zero outside
@@ -603,32 +737,33 @@ __global__ void k_avgpool_bwd_add(const uint16_t* __restrict__ gout, Dims dout, 
 }
 
 // out[n] = [skip[n][0:c1], coarse[n/2][0:c2], 0...] (nearest upsampling + concat).
-// One thread per fine voxel, 4 channels (8 bytes) per store; a group of 4 channels that
-// lies within one source at a 4-aligned offset is one 8-byte load (the channel strides
-// are multiples of 4), any other group is gathered channel by channel.
+// One thread per (fine voxel, group of 4 channels), 8-byte stores in memory order; a
+// group that lies within one source at a 4-aligned offset is one 8-byte load (the
+// channel strides are multiples of 4), any other group is gathered channel by channel.
 __global__ void k_upcat(const uint16_t* __restrict__ skip, int cs1, int c1, const uint16_t* __restrict__ coarse, int cs2,
                         int c2, Dims df, Dims dc, int cs, uint16_t* __restrict__ out) {
-  const long long N = df.n();
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+  const int cq = cs >> 2;
+  const long long N = df.n() * cq;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    const long long n = i / cq;
+    const int c = 4 * (int)(i - n * cq);
     int x, y, z;
     df.decode(n, x, y, z);
     const uint16_t* sr = skip + n * cs1;
     const uint16_t* cr = coarse + dc.encode(x >> 1, y >> 1, z >> 1) * cs2;
-    for (int c = 0; c < cs; c += 4) {
-      s4v v = s4v{0, 0, 0, 0};
-      if (c + 4 <= c1) {
-        v = *reinterpret_cast<const s4v*>(sr + c);
-      } else if (c >= c1 && c + 4 <= c1 + c2 && ((c - c1) & 3) == 0) {
-        v = *reinterpret_cast<const s4v*>(cr + (c - c1));
-      } else {
+    s4v v = s4v{0, 0, 0, 0};
+    if (c + 4 <= c1) {
+      v = *reinterpret_cast<const s4v*>(sr + c);
+    } else if (c >= c1 && c + 4 <= c1 + c2 && ((c - c1) & 3) == 0) {
+      v = *reinterpret_cast<const s4v*>(cr + (c - c1));
+    } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int cc = c + q;
-          v[q] = (short)(cc < c1 ? sr[cc] : (cc < c1 + c2 ? cr[cc - c1] : (uint16_t)0));
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int cc = c + q;
+        v[q] = (short)(cc < c1 ? sr[cc] : (cc < c1 + c2 ? cr[cc - c1] : (uint16_t)0));
       }
-      *reinterpret_cast<s4v*>(out + n * cs + c) = v;
     }
+    *reinterpret_cast<s4v*>(out + 4 * i) = v;
   }
 }
 

@@ -64,6 +64,7 @@ def test_net_forward_matches_fp64_reference():
 # structural mistake (a wrong tap, channel or transpose) gives errors near 1.
 @pytest.mark.parametrize("widths,shape,in_ch,model_tol", [((4, 8), (16, 16, 16), 1, 1e-4),
                                                           ((4, 8), (16, 8, 16), 5, 1e-4),
+                                                          ((20, 8), (16, 16, 16), 1, 1e-4),   # channel strides 20, 28
                                                           ((4, 8, 8, 16), (32, 32, 32), 3, 3e-2)])
 def test_net_gradients_match_fp64_reference(widths, shape, in_ch, model_tol):
     torch, net, flat, x, t = _setup(2, shape=shape, widths=widths, in_ch=in_ch)
