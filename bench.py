@@ -642,7 +642,7 @@ def warm_leg(train_steps, n_eval, tol, max_iter, tile_cache=None, n_val=4, n_tig
     plan = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
     if tile_cache is not None:
         plan.autotune(tile_cache)
-    net = mh3d.Net((8, 16, 32, 80), in_channels=len(w.harmonics), seed=w.seed)
+    net = mh3d.Net(WARM_WIDTHS, in_channels=len(w.harmonics), seed=w.seed)
     log("warm leg: %s, network %d parameters, training %d steps" % (w.name, net.nparam, train_steps))
     val = []
     for j in range(n_val):
@@ -740,6 +740,29 @@ def pmc_driver(args):
           % (w.name, plan.tiles(), plan.path()), flush=True)
 
 
+def net_driver(args):
+    """Trace driver for the warm-start network at the workload's shape: 20 training steps
+    on 64^3 crops (phantom, portraits, back-projections, loss and gradients, Adam) and 5
+    start images (back-projections and the forward pass over the whole volume)."""
+    import torch
+    from paper_2503_13802_amd import inputs, mh3d
+    w = inputs.workload(args.workload)
+    plan = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
+    net = mh3d.Net(WARM_WIDTHS, in_channels=len(w.harmonics), seed=0)
+    rho = plan.phantom(11)
+    d = plan.noisy_data(rho, 11, 30.0)
+    x = plan.backproject(d)
+    crop = [0, 0, 0, 64, 64, 64]
+    for _ in range(20):
+        net.loss_grad(x, rho, crop, want_loss=False)
+        net.adam_step(1e-3)
+    for _ in range(5):
+        net.warm_start(plan, d)
+    torch.cuda.synchronize()
+    print("net driver: %s, widths %s, 20 training steps on 64^3 crops, 5 start images"
+          % (w.name, list(WARM_WIDTHS)), flush=True)
+
+
 def tile_cache_path(arg):
     """The autotuner cache: the given path, else a temp copy of the shipped one."""
     if arg:
@@ -751,6 +774,8 @@ def tile_cache_path(arg):
         shutil.copyfile(SHIPPED_TILES, path)
     return path
 
+
+WARM_WIDTHS = (8, 16, 32, 80)   # the warm-start U-Net's channel widths per level (about 0.46 M parameters)
 
 PAPER_CONTEXT = {
     "source": "Table tab:runtime (Sec. 4.3): MATLAB on an NVIDIA GeForce RTX 3070 Laptop GPU, 4 harmonics, "
@@ -781,6 +806,8 @@ def main():
     ap.add_argument("--warm-eval", type=int, default=32)
     ap.add_argument("--pmc-driver", action="store_true",
                     help="only run the workload's A+A^T steps and a copy of known size (for counter runs)")
+    ap.add_argument("--net-driver", action="store_true",
+                    help="only run warm-start network training steps and start images (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only; more GPUs would each take whole volumes of a batch "
@@ -793,6 +820,9 @@ def main():
 
     if args.pmc_driver:
         pmc_driver(args)
+        return
+    if args.net_driver:
+        net_driver(args)
         return
 
     # CPU work started before the GPU is touched: the batch's host phantoms (a pool) and

@@ -287,6 +287,16 @@ __global__ __launch_bounds__(G::TPF) void k_fast_plane_fwd(const VolDesc* __rest
 // of the portraits that k_small_fwd left in G', no forward products).
 enum { COL_FWD = 16, COL_ADJ = 17 };
 
+// Column block of workgroup b: the workgroups of one XCD (b mod 8) take a run of
+// consecutive column blocks, so the blocks that share a cache line of the shares, of
+// G' and of Q read and write it through one L2.
+template <class G>
+__device__ __forceinline__ int fast_col_block(int b) {
+  constexpr int NB = G::NCLS / G::CPC;
+  if constexpr (NB % 8 == 0) return (b & 7) * (NB / 8) + (b >> 3);
+  else return b;
+}
+
 // Block: CPC columns (q'y, q'z), one thread per (column, q'x) owning the x aliases
 // qx = q'x + mx*jx.  Sums the sy shares of each column, transforms along x, then per
 // harmonic Fhat_k(q'x) = sum_jx F_k(qx) W(qx) (times i for imaginary F_k), the residual
@@ -303,7 +313,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   constexpr int NX = G::NX, MX = G::MX, SX = G::SX, CPC = G::CPC, KMAX = G::KMAX, LSX = G::LSX;
   constexpr bool kFwd = MODE != COL_ADJ, kAdj = MODE != COL_FWD;
   constexpr bool kStoreG = MODE == NRM_STORE || MODE == COL_FWD;
-  const int c0 = blockIdx.x * CPC;
+  const int c0 = fast_col_block<G>(blockIdx.x) * CPC;
   const int K = vd.g.K;
   extern __shared__ float2 lds[];
   float2* twx = lds;
