@@ -71,7 +71,8 @@ __global__ void k_sep_tables(Geo g, const double2* __restrict__ fhat, const doub
   }
 }
 
-template <int NX_, int NY_, int NZ_, int SX_, int SY_, int SZ_, int CPC_, int KMAX_, int TP_ = 256, int TPF_ = 256>
+template <int NX_, int NY_, int NZ_, int SX_, int SY_, int SZ_, int CPC_, int KMAX_, int TP_ = 256, int TPF_ = 256,
+          int LSX_ = 0, int LSZ_ = 0>
 struct FastGeo {
   static constexpr int NX = NX_, NY = NY_, NZ = NZ_, SX = SX_, SY = SY_, SZ = SZ_;
   static constexpr int MX = NX / SX, MY = NY / SY, MZ = NZ / SZ;
@@ -79,7 +80,11 @@ struct FastGeo {
   static constexpr int NCLS = MY * MZH;                     // columns (q'y, q'z)
   static constexpr int CPC = CPC_, KMAX = KMAX_;
   static constexpr int TC = CPC * MX;                       // column-pass threads: one per (column, q'x)
-  static constexpr int LSX = NX | 1, LSZ = NZ | 1, LSY = MY | 1;
+  // line strides of the x lines (column pass) and packed z lines (plane passes): odd by
+  // default; a geometry may set others where its line count per wave makes an odd stride
+  // put several lanes of a stage on one bank (with 4 x lines or 16 z lines per block a
+  // stride of 1 mod 32 complex values does; 6 and 2 mod 32 spread them)
+  static constexpr int LSX = LSX_ ? LSX_ : (NX | 1), LSZ = LSZ_ ? LSZ_ : (NZ | 1), LSY = MY | 1;
   static constexpr int NP = MY / 2;                         // row pairs of a plane block
   static constexpr int TP = TP_;                            // adjoint plane-pass threads
   static constexpr int TPF = TPF_;                          // forward plane-pass threads
