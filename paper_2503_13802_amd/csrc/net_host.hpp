@@ -162,6 +162,28 @@ bool conv_ct_try(hipStream_t s, int ntile, bool relu, int blocks, const uint16_t
   return true;
 }
 
+// k_conv_splitk8 with the output tile count as a compile-time constant.
+template <int NT>
+void splitk8_nt(hipStream_t s, bool relu, int blocks, const uint16_t* in, Dims dm, int cs_in, int ks, const uint16_t* W,
+                int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
+  if (relu) k_conv_splitk8<true, NT><<<blocks, 256, 0, s>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
+  else k_conv_splitk8<false, NT><<<blocks, 256, 0, s>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
+}
+
+void splitk8(hipStream_t s, bool relu, int ntile, int blocks, const uint16_t* in, Dims dm, int cs_in, int ks,
+             const uint16_t* W, int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
+  switch (ntile) {
+    case 1: splitk8_nt<1>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    case 2: splitk8_nt<2>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    case 3: splitk8_nt<3>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    case 4: splitk8_nt<4>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    case 5: splitk8_nt<5>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    case 6: splitk8_nt<6>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    case 7: splitk8_nt<7>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+    default: splitk8_nt<8>(s, relu, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o); break;
+  }
+}
+
 bool conv_ct(hipStream_t s, int cs_in, int ntile, bool relu, int blocks, const uint16_t* in, Dims dm, const uint16_t* W,
              int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
   switch (cs_in) {
@@ -199,6 +221,10 @@ mh3d_status launch_conv(mh3d_net_t n, const uint16_t* in, Dims dm, int cs_in, in
     // deep reduction on a small grid: split K over the block's waves
     const int blocks = (int)((N + 15) / 16);
     uint16_t* o = reinterpret_cast<uint16_t*>(out);
+    if (cs_in % 8 == 0 && ntile <= 8) {
+      splitk8(n->stream, relu, ntile, blocks, in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
+      return last_launch("k_conv_splitk8");
+    }
     if (relu) k_conv_splitk<true><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
     else k_conv_splitk<false><<<blocks, 256, 0, n->stream>>>(in, dm, cs_in, ks, W, kp, bias, cout, cs_out, o);
     return last_launch("k_conv_splitk");

@@ -38,12 +38,8 @@ __device__ __forceinline__ f4v mfma2(s4v a0, s4v a1, s4v b0, s4v b1, f4v c) {
 constexpr int NT_MAX = 7;   // output-channel tiles per wave (112 channels)
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet).
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// Nearest BF16, ties to even (gfx950's v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 struct Dims {
@@ -278,6 +274,88 @@ __device__ __forceinline__ void stage_halo(uint16_t* __restrict__ tile, const ui
   }
 }
 
+// k_conv_splitk for input channel strides divisible by 8: MFMA m takes the reduction
+// indices 32 m .. 32 m + 31, lane group g the 8 consecutive channels 32 m + 8 g .. + 7 of
+// one tap (one 16-byte gather of A, one 16-byte load of B per output tile); wave w takes
+// m = w, w + 4, ..., U of them with all their loads issued before their MFMAs.
+template <bool RELU, int NT>
+__global__ __launch_bounds__(256) void k_conv_splitk8(const uint16_t* __restrict__ in, Dims dm, int cs_in, int ks,
+                                                      const uint16_t* __restrict__ W, int kp,
+                                                      const float* __restrict__ bias, int cout, int cs_out,
+                                                      uint16_t* __restrict__ out) {
+  constexpr int U = NT <= 2 ? 4 : 2;   // loads in flight per wave: U gathers and U * NT weight slices
+  __shared__ f4v part[3][NT][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long N = dm.n();
+  const long long n0 = (long long)blockIdx.x * 16;
+  const int r = lane & 15, g = lane >> 4;
+  const long long n = n0 + r;
+  const bool nvalid = n < N;
+  int x = 0, y = 0, z = 0;
+  if (nvalid) dm.decode(n, x, y, z);
+  const int ntap = ks * ks * ks;
+  f4v acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+  // k = 32 m + 8 g for m = wave + 4 i: start, then step 128 reduction indices
+  int tap = 0, ci = 32 * wave + 8 * g;
+  while (ci >= cs_in) { ci -= cs_in; ++tap; }
+  const int nm = (kp + 31) >> 5;
+  const uint16_t* wr = W + (long long)r * kp + 8 * g;
+  for (int m0 = wave; m0 < nm; m0 += 4 * U) {
+    s8v a[U], b[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = m0 + 4 * u;
+      a[u] = s8v{0, 0, 0, 0, 0, 0, 0, 0};
+      if (m < nm && nvalid && tap < ntap) {
+        int dx, dy, dz;
+        tap_offset(tap, ks, dx, dy, dz);
+        const int xx = x + dx, yy = y + dy, zz = z + dz;
+        if (dm.inside(xx, yy, zz)) a[u] = *reinterpret_cast<const s8v*>(in + dm.encode(xx, yy, zz) * cs_in + ci);
+      }
+      const bool kin = m < nm && 32 * m + 8 * g < kp;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        b[u][t] = kin ? *reinterpret_cast<const s8v*>(wr + (long long)t * 16 * kp + 32 * m) : s8v{0, 0, 0, 0, 0, 0, 0, 0};
+      ci += 128;
+      while (ci >= cs_in) { ci -= cs_in; ++tap; }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a[u]), __builtin_bit_cast(bf8v, b[u][t]),
+                                                           acc[t], 0, 0, 0);
+  }
+  if (wave) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) part[wave - 1][t][lane] = acc[t];
+  }
+  __syncthreads();
+  if (wave) return;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    f4v v = acc[t];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) v += part[w][t][lane];
+    const int co = t * 16 + r;
+    const float bv = co < cout ? bias[co] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long nn = n0 + 4 * g + j;
+      if (nn >= N) continue;
+      if (co < cout) {
+        float o = v[j] + bv;
+        if (RELU) o = fmaxf(o, 0.f);
+        out[nn * cs_out + co] = f2bf(o);
+      } else if (co < cs_out) {
+        out[nn * cs_out + co] = 0;
+      }
+    }
+  }
+}
+
 // 3x3x3 convolution on an LDS-staged tile with the input channel stride CS fixed at
 // compile time (the same implicit GEMM, tile and operands as k_conv_tiled, kp = 16
 // NKC).  Every index the reduction needs is a constant or comes from a per-block table
@@ -308,8 +386,10 @@ __global__ __launch_bounds__(256) void k_conv_ct(const uint16_t* __restrict__ in
   const int x0 = tx * 4, y0 = ty * 4, z0 = tz * 16;
   // reduction index k = 16 kc + 4 g + j -> (tap, channel) -> halo offset; the padding
   // columns (tap >= 27) meet zero rows of W and read any finite halo entry (offset 0)
-  for (int i = threadIdx.x; i < NKC * 4; i += 256) {
-    const int k = 4 * i;
+  // (CS % 8 == 0: entry m * 4 + g holds k = 32 m + 8 g; else entry kc * 4 + g, k = 16 kc + 4 g)
+  constexpr int NTAB = CS % 8 == 0 ? 4 * ((16 * NKC + 31) / 32) : 4 * NKC;
+  for (int i = threadIdx.x; i < NTAB; i += 256) {
+    const int k = (CS % 8 == 0 ? 8 : 4) * i;
     const int tap = k / CS, ci = k - (k / CS) * CS;
     toff[i] = tap < 27 ? ((tap / 9) * 108 + ((tap / 3) % 3) * 18 + tap % 3) * CS + ci : 0;
   }
@@ -348,6 +428,30 @@ __global__ __launch_bounds__(256) void k_conv_ct(const uint16_t* __restrict__ in
   for (int yy = 0; yy < 4; ++yy)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[yy][t] = f4v{0.f, 0.f, 0.f, 0.f};
+  if constexpr (CS % 8 == 0) {
+    // lane group g takes the 8 consecutive reduction indices 32 m + 8 g .. + 7 of MFMA m:
+    // 8 channels of one tap, one 16-byte LDS read of A and one 16-byte load of B (the
+    // same index on both operands); W's padding columns (k >= 16 NKC) read as zeros
+    constexpr int KP = 16 * NKC, NM = (KP + 31) / 32;
+    const uint16_t* wr8 = W + (long long)r * KP + 8 * g;
+#pragma unroll 4
+    for (int m = 0; m < NM; ++m) {
+      const int o = lbase + toff[m * 4 + g];
+      s8v b[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        b[t] = (32 * m + 8 * g < KP) ? *reinterpret_cast<const s8v*>(wr8 + t * 16 * KP + 32 * m)
+                                     : s8v{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int yy = 0; yy < 4; ++yy) {
+        const s8v av = *reinterpret_cast<const s8v*>(tile + o + yy * RS);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[yy][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, av),
+                                                               __builtin_bit_cast(bf8v, b[t]), acc[yy][t], 0, 0, 0);
+      }
+    }
+  } else {
   const uint16_t* wr = W + (long long)r * kp + 4 * g;
   auto pair = [&](int kc, bool two) {
     const int o0 = lbase + toff[kc * 4 + g];
@@ -369,36 +473,46 @@ __global__ __launch_bounds__(256) void k_conv_ct(const uint16_t* __restrict__ in
 #pragma unroll 4
   for (int kc = 0; kc + 1 < NKC; kc += 2) pair(kc, true);
   if constexpr (NKC & 1) pair(NKC - 1, false);
+  }
   __syncthreads();   // every wave is done with the halo: its space stages the output
   // D[row = 4g + j][col = r]: voxel z0 + 4g + j of row (x0 + wave, y0 + yy), channel t*16 + r
   uint16_t* st = tile + wave * 64 * cs_out;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int co = t * 16 + r;
-    const float bv = co < cout ? bias[co] : 0.f;
+    const bool live = co < cout;
+    const float bv = live ? bias[co] : 0.f;
     if (co < cs_out) {
+      uint16_t* sl = st + 4 * g * cs_out + co;
 #pragma unroll
       for (int yy = 0; yy < 4; ++yy)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float v = acc[yy][t][j] + bv;
           if (RELU) v = fmaxf(v, 0.f);
-          st[(yy * 16 + 4 * g + j) * cs_out + co] = co < cout ? f2bf(v) : (uint16_t)0;
+          const uint16_t h = f2bf(v);
+          sl[(yy * 16 + j) * cs_out] = live ? h : (uint16_t)0;
         }
     }
   }
   __syncthreads();
-  // each (x, y) row of 16 voxels is a contiguous run of 16 cs_out channels in memory
-#pragma unroll
-  for (int yy = 0; yy < 4; ++yy) {
-    uint16_t* orow = out + dm.encode(x0 + wave, y0 + yy, z0) * cs_out;
-    const uint16_t* srow = st + yy * 16 * cs_out;
-    if ((cs_out & 7) == 0) {
-      for (int q = lane; q < 2 * cs_out; q += 64)
-        *reinterpret_cast<uint4*>(orow + 8 * q) = *reinterpret_cast<const uint4*>(srow + 8 * q);
-    } else {
-      for (int q = lane; q < 4 * cs_out; q += 64)
-        *reinterpret_cast<s4v*>(orow + 4 * q) = *reinterpret_cast<const s4v*>(srow + 4 * q);
+  // each (x, y) row of 16 voxels is a contiguous run of 16 cs_out channels in memory: the
+  // wave's 4 rows as 16-byte (8-byte) pieces, piece p of row p / per_row
+  const long long row0 = dm.encode(x0 + wave, y0, z0) * cs_out;
+  const long long ystride = (long long)cs_out << (dm.lz);   // one y step, in elements
+  if ((cs_out & 7) == 0) {
+    const int per_row = 2 * cs_out;
+    for (int p = lane; p < 4 * per_row; p += 64) {
+      const int yy = p / per_row, q = p - yy * per_row;
+      *reinterpret_cast<uint4*>(out + row0 + yy * ystride + 8 * q) =
+          *reinterpret_cast<const uint4*>(st + yy * 16 * cs_out + 8 * q);
+    }
+  } else {
+    const int per_row = 4 * cs_out;
+    for (int p = lane; p < 4 * per_row; p += 64) {
+      const int yy = p / per_row, q = p - yy * per_row;
+      *reinterpret_cast<s4v*>(out + row0 + yy * ystride + 4 * q) =
+          *reinterpret_cast<const s4v*>(st + yy * 16 * cs_out + 4 * q);
     }
   }
 }
@@ -409,7 +523,7 @@ constexpr size_t conv_ct_lds() {
   constexpr int NKC = (27 * CS + 15) / 16;
   constexpr int HALO = 648 * CS, STAGE = 256 * 16 * NT;
   constexpr int TILE = ((HALO > STAGE ? HALO : STAGE) + 7) & ~7;
-  return sizeof(uint16_t) * TILE + sizeof(int) * NKC * 4;
+  return sizeof(uint16_t) * TILE + sizeof(int) * NKC * 4;   // the table of either layout fits in NKC * 4
 }
 
 // 3x3x3 convolution on an LDS-staged input tile (the same implicit GEMM as k_conv).
