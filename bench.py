@@ -110,9 +110,10 @@ def operator_bytes(w, separable=True, ncomp=1):
 
 
 def roofline(pass_us, byte_map, kernels):
-    """The dominant kernel of the step (longest average launch in pass_us, the
-    per-launch microseconds measured in the timed steps) with its algorithmic bytes per
-    launch and its average launch duration in seconds."""
+    """The dominant kernel of the step (longest average launch in pass_us: microseconds
+    per launch over back-to-back launches of each pass between two HIP events on the
+    plan's stream, mh3d_time_pass) with its algorithmic bytes per launch and its average
+    launch duration in seconds."""
     name = max(kernels, key=lambda k: pass_us[k])
     s = pass_us[name] * 1e-6
     return name, byte_map[name], s
@@ -341,8 +342,9 @@ def operator_leg(w, steps, warmup, tile_cache, oracle_check=True):
         plan.adjoint(r, out=x2)
 
     sec = time_steps(fused, steps, warmup)
-    # per-launch durations in the timed steps: the same steps again with HIP events
-    # around every launch on the plan's stream (mh3d_profile)
+    # per-launch durations in steps like the timed ones: the same steps again with HIP
+    # events around every launch on the plan's stream (mh3d_profile); each event pair
+    # adds its own wait to the launch it brackets, so these read above the kernels
     with Quiet():
         plan.profile(True)
         for _ in range(steps):
@@ -354,7 +356,7 @@ def operator_leg(w, steps, warmup, tile_cache, oracle_check=True):
     with Quiet():
         pass_us = plan.time_passes(reps=200)
     byte_map = fast_kernel_bytes(w) if separable else general_kernel_bytes(w)
-    kern, kbytes, ks = roofline(live_us, byte_map, ["plane_fwd", "class_normal", "adj_and_store"])
+    kern, kbytes, ks = roofline(pass_us, byte_map, ["plane_fwd", "class_normal", "adj_and_store"])
     achieved = kbytes / ks / 1e9
     op_b = operator_bytes(w, separable)
     out = {"rate": 1.0 / sec, "ms_per_step": 1e3 * sec, "separate_rate": 1.0 / sec_sep,
@@ -460,8 +462,7 @@ def vector_leg(w, steps, warmup, tile_cache=None):
             ck, cb, cs = "class_fwd+class_adj", bmap["class_fwd"], 0.5 * (pass_us["class_fwd"] + pass_us["class_adj"])
         d_ref = om.forward_vector(h, b, rho, w.ds)
         out["C%d" % C] = {"applications_per_s": round(1.0 / sec, 2), "tiles": list(tiles),
-                          "kernels_us_in_step": {k: round(v, 3) for k, v in live_us.items()},
-           "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
+                          "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
                           "class_kernel": ck, "class_bytes_per_launch": cb, "class_GBps": round(cb / cs / 1e3, 1),
                           "oracle_rel_l2": {"A": rel_l2(y.cpu().numpy(), d_ref),
                                             "AT": rel_l2(x.cpu().numpy(), om.adjoint_vector(h, b, d_ref, w.ds))}}
