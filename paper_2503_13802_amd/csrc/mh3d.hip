@@ -451,6 +451,7 @@ struct FastImpl {
 // largest harmonic count).
 static const FastOps kFast[] = {
     FastImpl<FastGeo<128, 128, 128, 2, 4, 4, 4, 12, 512, 512, 134>>::ops(),   // 128^3, k = 2..12
+    FastImpl<FastGeo<96, 96, 64, 2, 2, 2, 4, 8, 512, 512>>::ops(),            // 96 x 96 x 64, k = 2..8
     // small grids of the parity tests: every y split (1 to 4), radix 3 along x and y
     FastImpl<FastGeo<32, 32, 32, 2, 4, 4, 4, 12>>::ops(),
     FastImpl<FastGeo<16, 24, 16, 2, 2, 2, 4, 8>>::ops(),

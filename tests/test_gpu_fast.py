@@ -2,10 +2,11 @@
 operator, the power iteration and solver updates) against the FP64 oracle, and against
 the general passes of the same plan (mh3d_plan_path 0).
 
-Grids: the 128^3 workload (k = 2..12, decimation 2, 4, 4) and the small grids compiled
-for these tests, which between them split y in 1, 2, 3 and 4 (the four-step split of the
-y-transform between the plane and class passes), use radix 3 along y, fold groups of 4
-and 8 lanes, and harmonic counts below and at the compiled maximum."""
+Grids: the 128^3 workload (k = 2..12, decimation 2, 4, 4), the 96 x 96 x 64 workload
+(k = 2..8, decimation 2, 2, 2) and the small grids compiled for these tests, which
+between them split y in 1, 2, 3 and 4 (the four-step split of the y-transform between
+the plane and class passes), use radix 3 along y, fold groups of 4 and 8 lanes, and
+harmonic counts below and at the compiled maximum."""
 import numpy as np
 import pytest
 
@@ -151,6 +152,52 @@ def test_fast_full_size_workload2():
     c0 = p.backproject(torch.tensor(d, dtype=torch.float32)).cpu().numpy()
     assert rel_l2(c1, c0) <= 2e-6
     d0, x0 = p.forward_adjoint(torch.tensor(rho, dtype=torch.float32))
+    assert rel_l2(d2.cpu().numpy(), d0.cpu().numpy()) <= 2e-6
+    assert rel_l2(x2.cpu().numpy(), x0.cpu().numpy()) <= 2e-6
+    assert rel_l2(n1, p.normal(xt).cpu().numpy()) <= 2e-6
+
+
+def test_fast_full_size_workload1():
+    """96 x 96 x 64, k = 2..8, decimation (2, 2, 2) (radix 3 along x and y at full size):
+    A then A^T and the separate calls against the FFT oracle, 64 sampled direct sums, the
+    normal operator, 10 solver updates; the general passes agree to FP32 rounding."""
+    torch = torch_cuda()
+    from paper_2503_13802_amd import mh3d
+    w = inputs.workload(1)
+    announce("fast full size %s" % w.name)
+    h = om.psf_bank(w.shape, list(w.harmonics), w.a_per_mm)
+    b = om.sensitivity(w.shape, w.sigma_mm)
+    op = osv.Operator(h, b, w.ds, w.lam)
+    p = mh3d.Plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, w.lam, w.voxel_mm)
+    assert p.path() == 1
+    rho = inputs.phantom(w)
+    d_ref = op.A(rho)
+    rt = torch.tensor(rho, dtype=torch.float32)
+    d2, x2 = p.forward_adjoint(rt)
+    assert rel_l2(d2.cpu().numpy(), d_ref) <= TOL
+    x_ref = om.adjoint_fft(h, b, d_ref, w.ds)
+    assert rel_l2(x2.cpu().numpy(), x_ref) <= TOL
+    assert torch.equal(p.forward(rt), d2)
+    r = inputs.random_field(d_ref.shape, 43)
+    assert rel_l2(p.adjoint(torch.tensor(r, dtype=torch.float32)).cpu().numpy(), om.adjoint_fft(h, b, r, w.ds)) <= TOL
+    rng = np.random.default_rng(12)
+    ent = [(int(rng.integers(len(w.harmonics))),) + tuple(int(rng.integers(m)) for m in w.small_shape)
+           for _ in range(64)]
+    dd = d2.cpu().numpy().astype(np.float64)
+    want = om.forward_direct_at(h, b, rho, w.ds, ent)
+    got = np.array([dd[e] for e in ent])
+    assert np.sqrt(np.mean((got - want) ** 2)) / np.sqrt(np.mean(d_ref ** 2)) <= TOL
+    x = inputs.random_field(w.shape, 44)
+    xt = torch.tensor(x, dtype=torch.float32)
+    n1 = p.normal(xt).cpu().numpy()
+    assert rel_l2(n1, op.normal(x)) <= TOL
+    d = d_ref + 0.01 * float(np.abs(d_ref).max()) * inputs.random_field(d_ref.shape, 45)
+    want, _, _ = osv.fista(op, d, 0.05, max_iter=10)
+    got, info = p.solve(torch.tensor(d, dtype=torch.float32), max_iter=10, tol=0.0, tau=0.05)
+    assert info["iters"] == 10
+    assert rel_l2(got.cpu().numpy(), want) <= 1e-4
+    p.path(0)
+    d0, x0 = p.forward_adjoint(rt)
     assert rel_l2(d2.cpu().numpy(), d0.cpu().numpy()) <= 2e-6
     assert rel_l2(x2.cpu().numpy(), x0.cpu().numpy()) <= 2e-6
     assert rel_l2(n1, p.normal(xt).cpu().numpy()) <= 2e-6

@@ -279,13 +279,17 @@ def test_forward_adjoint_launch_shapes():
     shape, harm, ds = (96, 96, 64), tuple(range(2, 9)), (2, 2, 2)
     p = _plan(shape, harm, 1.2, ds, 20.0)
     x = torch.tensor(inputs.random_field(shape, 17), dtype=torch.float32, device="cuda")
-    for tiles in [(4, 2, 8, 1), (2, 1, 2, 4), (8, 4, 1, 2), (4, 2, 1, 2)]:
-        p.set_tiles(*tiles)
-        d1 = p.forward(x).clone()
-        x1 = p.adjoint(d1).clone()
-        d2, x2 = p.forward_adjoint(x)
-        assert torch.equal(d1, d2), tiles
-        assert rel_l2(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-6, tiles
+    for path in (0, 1):   # the general passes, then the compile-time ones of this grid
+        p.path(path)
+        for tiles in [(4, 2, 8, 1), (2, 1, 2, 4), (8, 4, 1, 2), (4, 2, 1, 2)]:
+            p.set_tiles(*tiles)
+            p.path(path)
+            assert p.path() == path
+            d1 = p.forward(x).clone()
+            x1 = p.adjoint(d1).clone()
+            d2, x2 = p.forward_adjoint(x)
+            assert torch.equal(d1, d2), (path, tiles)
+            assert rel_l2(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-6, (path, tiles)
 
 
 @pytest.mark.parametrize("tiles", [(4, 1, 0, 0), (8, 2, 0, 0)])
@@ -344,9 +348,11 @@ def test_user_psf_fused_class_pass(tiles):
 
 
 @pytest.mark.parametrize("idx", [1, 2])
-def test_full_size_fused_paths(idx):
+def test_full_size_fused_paths(idx, tmp_path):
     """The fused paths at the full size of workloads 1 and 2 (the bench's A then A^T, the
-    normal operator of the power iteration, and solver updates) against the FFT oracle."""
+    normal operator of the power iteration, and solver updates) against the FFT oracle,
+    with the tiles of a copy of the shipped autotuner cache (a miss is tuned into the copy)."""
+    import shutil
     torch = torch_cuda()
     w = inputs.workload(idx)
     announce("full size fused paths %s" % w.name)
@@ -354,8 +360,10 @@ def test_full_size_fused_paths(idx):
     b = om.sensitivity(w.shape, w.sigma_mm)
     op = osv.Operator(h, b, w.ds, w.lam)
     p = _plan(w.shape, w.harmonics, w.a_per_mm, w.ds, w.sigma_mm, lam=w.lam)
-    p.autotune(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_13802_amd",
-                            "tiles_gfx950.json"))
+    cache = tmp_path / "tiles.json"
+    shutil.copyfile(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_13802_amd",
+                                 "tiles_gfx950.json"), cache)
+    p.autotune(str(cache))
     rho = inputs.phantom(w)
     d_ref = op.A(rho)
     d2, x2 = p.forward_adjoint(torch.tensor(rho, dtype=torch.float32))
