@@ -28,9 +28,11 @@
 //    (q'y, q'z) for the q'z beyond mz/2), transforms it back along y1 and z (C2R) and
 //    multiplies by b.
 //
-// Each call sequence runs only these passes (their intermediate layouts are their own);
-// the separate forward and adjoint calls, user PSFs, vector, padded and batched plans
-// keep the passes of kernels.hpp.
+// Each call sequence runs only these passes (their intermediate layouts are their own):
+// the fused sequences, the separate forward and adjoint calls and the per-harmonic
+// back-projections (the adjoint calls start from kernels.hpp's small-grid forward
+// transform of the portraits).  User PSFs, vector, padded and batched plans keep the
+// passes of kernels.hpp.
 #pragma once
 #include "kernels.hpp"
 
@@ -82,13 +84,13 @@ struct FastGeo {
   static constexpr int TC = CPC * MX;                       // column-pass threads: one per (column, q'x)
   // line strides of the x lines (column pass) and packed z lines (plane passes): odd by
   // default; a geometry may set others where its line count per wave makes an odd stride
-  // put several lanes of a stage on one bank (with 4 x lines or 16 z lines per block a
-  // stride of 1 mod 32 complex values does; 6 and 2 mod 32 spread them)
+  // put several lanes of a stage on one bank (with 4 x lines per block a stride of 1 mod
+  // 32 complex values does; 6 mod 32 spreads them)
   static constexpr int LSX = LSX_ ? LSX_ : (NX | 1), LSZ = LSZ_ ? LSZ_ : (NZ | 1), LSY = MY | 1;
   static constexpr int NP = MY / 2;                         // row pairs of a plane block
   static constexpr int TP = TP_;                            // adjoint plane-pass threads
   static constexpr int TPF = TPF_;                          // forward plane-pass threads
-  static constexpr int NBP = NX * SY;                       // plane-pass blocks
+  static constexpr int NBP = NX * SY;                       // plane-pass blocks (x-plane, y0)
   // one plane-pass LDS buffer: packed row pairs or half-spectrum columns (+ the staged Q)
   static constexpr int PB0 = NP * LSZ, PB1 = NZH * LSY;
   static constexpr int PBUF = PB0 > PB1 ? PB0 : PB1;
