@@ -142,9 +142,17 @@ __device__ __forceinline__ void lf_stage(const float2* __restrict__ in, float2* 
 
 // Length-N transforms (unnormalised) of NL lines in *a, ping-ponging with *b; a barrier
 // ends each stage.  Returns the buffer holding the result.  No leading barrier.
+// Radix of stage s: length-128 lines in groups of at least 16 (the plane passes' packed
+// z lines) take 16 then 8, one stage and one barrier fewer than 8, 8, 2 (with fewer
+// lines the radix-16 stage leaves too many lanes idle); otherwise ct_radix.
+__host__ __device__ constexpr int lf_radix(int n, int s, int nl) {
+  if (n == 128 && nl >= 16) return s == 0 ? 16 : (s == 1 ? 8 : 0);
+  return ct_radix(n, s);
+}
+
 template <int N, int S, int NS, int SGN, int NL, int LS>
 __device__ __forceinline__ float2* lf_fft(float2* a, float2* b, const float2* tw) {
-  constexpr int R = ct_radix(N, S);
+  constexpr int R = lf_radix(N, S, NL);
   if constexpr (R == 0) {
     return a;
   } else {

@@ -89,10 +89,31 @@ template <int SGN, typename C> __device__ __forceinline__ void dft8(C* v) {
   v[3] = cadd(e[3], w3o);
   v[7] = csub(e[3], w3o);
 }
+// radix 16 as two length-8 DFTs of the even and odd points and one radix-2 combination
+template <int SGN, typename C> __device__ __forceinline__ void dft16(C* v) {
+  using R = typename real_of<C>::type;
+  const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173;   // cos, sin of pi/8
+  const R r2 = (R)0.70710678118654752440;
+  C e[8], o[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { e[i] = v[2 * i]; o[i] = v[2 * i + 1]; }
+  dft8<SGN>(e);
+  dft8<SGN>(o);
+  // w^p = exp(SGN * 2 pi i p / 16), p = 0..7
+  const C w[8] = {cmk<C>((R)1, (R)0), cmk<C>(c1, (R)SGN * s1), cmk<C>(r2, (R)SGN * r2), cmk<C>(s1, (R)SGN * c1),
+                  cmk<C>((R)0, (R)SGN), cmk<C>(-s1, (R)SGN * c1), cmk<C>(-r2, (R)SGN * r2), cmk<C>(-c1, (R)SGN * s1)};
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const C t = p == 0 ? o[0] : cmul(o[p], w[p]);
+    v[p] = cadd(e[p], t);
+    v[p + 8] = csub(e[p], t);
+  }
+}
 template <int R, int SGN, typename C> __device__ __forceinline__ void dft(C* v) {
   if constexpr (R == 2) dft2<SGN>(v);
   else if constexpr (R == 3) dft3<SGN>(v);
   else if constexpr (R == 4) dft4<SGN>(v);
+  else if constexpr (R == 16) dft16<SGN>(v);
   else dft8<SGN>(v);
 }
 
