@@ -113,19 +113,18 @@ struct FastGeo {
 // Stockham stages of NL lines of length N held at l*LS + p (LS odd) with consecutive
 // lanes on consecutive lines (the same butterfly of each): with an odd line stride the
 // strided stores of a stage fall in distinct banks, and the lanes of a butterfly
-// position share its twiddles (one broadcast read).
-template <int N, int R, int NS, int SGN, int NL, int LS>
-__device__ __forceinline__ void lf_stage(const float2* __restrict__ in, float2* __restrict__ out, const float2* tw) {
+// position share its twiddles (one broadcast read).  ld(l, p) gives element p of line l.
+template <int N, int R, int NS, int SGN, int NL, int LS, class Load>
+__device__ __forceinline__ void lf_stage_ld(Load ld, float2* __restrict__ out, const float2* tw) {
   constexpr int NB = N / R;
   constexpr int TWS = N / (NS * R);
   constexpr int total = NL * NB;
   for (int b = threadIdx.x; b < total; b += blockDim.x) {
     const int l = b % NL, j = b / NL;
     const int k = j % NS;
-    const int base = l * LS;
     float2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[base + j + r * NB];
+    for (int r = 0; r < R; ++r) v[r] = ld(l, j + r * NB);
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -134,14 +133,17 @@ __device__ __forceinline__ void lf_stage(const float2* __restrict__ in, float2* 
       }
     }
     dft<R, SGN>(v);
-    const int o = base + (j / NS) * NS * R + k;
+    const int o = l * LS + (j / NS) * NS * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[o + r * NS] = v[r];
   }
 }
 
-// Length-N transforms (unnormalised) of NL lines in *a, ping-ponging with *b; a barrier
-// ends each stage.  Returns the buffer holding the result.  No leading barrier.
+template <int N, int R, int NS, int SGN, int NL, int LS>
+__device__ __forceinline__ void lf_stage(const float2* __restrict__ in, float2* __restrict__ out, const float2* tw) {
+  lf_stage_ld<N, R, NS, SGN, NL, LS>([&](int l, int p) { return in[l * LS + p]; }, out, tw);
+}
+
 // Radix of stage s: length-128 lines in groups of at least 16 (the plane passes' packed
 // z lines) take 16 then 8, one stage and one barrier fewer than 8, 8, 2 (with fewer
 // lines the radix-16 stage leaves too many lanes idle); otherwise ct_radix.
@@ -150,6 +152,8 @@ __host__ __device__ constexpr int lf_radix(int n, int s, int nl) {
   return ct_radix(n, s);
 }
 
+// Length-N transforms (unnormalised) of NL lines in *a, ping-ponging with *b; a barrier
+// ends each stage.  Returns the buffer holding the result.  No leading barrier.
 template <int N, int S, int NS, int SGN, int NL, int LS>
 __device__ __forceinline__ float2* lf_fft(float2* a, float2* b, const float2* tw) {
   constexpr int R = lf_radix(N, S, NL);
@@ -160,6 +164,17 @@ __device__ __forceinline__ float2* lf_fft(float2* a, float2* b, const float2* tw
     __syncthreads();
     return lf_fft<N, S + 1, NS * R, SGN, NL, LS>(b, a, tw);
   }
+}
+
+// The same with the first stage's inputs from ld (computed from another buffer, which
+// the first stage is the last to read): the first stage writes *a, the rest ping-pong
+// between *a and *b.
+template <int N, int SGN, int NL, int LS, class Load>
+__device__ __forceinline__ float2* lf_fft_ld(Load ld, float2* a, float2* b, const float2* tw) {
+  constexpr int R = lf_radix(N, 0, NL);
+  lf_stage_ld<N, R, 1, SGN, NL, LS>(ld, a, tw);
+  __syncthreads();
+  return lf_fft<N, 1, R, SGN, NL, LS>(a, b, tw);
 }
 
 // Plane-pass block b -> (x-plane, y0).  The blocks of one XCD (b mod 8) take a run of
@@ -259,16 +274,16 @@ __global__ __launch_bounds__(G::TPF) void k_fast_plane_fwd(const VolDesc* __rest
   __syncthreads();
   float2* Z = lf_fft<G::NZ, 0, 1, -1, G::NP, G::LSZ>(B0, B1, twz);
   float2* X = (Z == B0) ? B1 : B0;
-  // split each packed pair into its two half spectra, columns X[qz][y1]
-  for (int it = t; it < G::NP * G::NZH; it += G::TPF) {
-    const int j = it / G::NZH, q = it - (it / G::NZH) * G::NZH;
+  // the y1 transform of the half-spectrum columns (line qz, element y1): its first stage
+  // splits each packed pair into its two half spectra as it reads them
+  auto split = [&](int q, int y1) {
+    const int j = y1 >> 1;
     const float2 zq = Z[j * G::LSZ + q];
     const float2 zm = Z[j * G::LSZ + (q == 0 ? 0 : G::NZ - q)];
-    X[q * G::LSY + 2 * j] = make_float2(0.5f * (zq.x + zm.x), 0.5f * (zq.y - zm.y));
-    X[q * G::LSY + 2 * j + 1] = make_float2(0.5f * (zq.y + zm.y), -0.5f * (zq.x - zm.x));
-  }
-  __syncthreads();
-  const float2* Y = lf_fft<G::MY, 0, 1, -1, G::NZH, G::LSY>(X, Z, twy);
+    return (y1 & 1) ? make_float2(0.5f * (zq.y + zm.y), -0.5f * (zq.x - zm.x))
+                    : make_float2(0.5f * (zq.x + zm.x), 0.5f * (zq.y - zm.y));
+  };
+  const float2* Y = lf_fft_ld<G::MY, -1, G::NZH, G::LSY>(split, X, Z, twy);
   // this residue's share of the folded plane
   float2* __restrict__ dst = vd.cp + ((long long)y0 * G::NX + x) * G::NCLS;
 #pragma unroll
@@ -667,19 +682,18 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
   __syncthreads();
   float2* X = lf_fft<G::MY, 0, 1, +1, G::NZH, G::LSY>(B0, B1, twy);
   float2* Zb = (X == B0) ? B1 : B0;
-  // C2R along z: packed rows Z[j] = X[2j] + i X[2j+1] with the Hermitian extension
-  for (int it = t; it < G::NP * G::NZ; it += G::TP) {
-    const int j = it / G::NZ, q = it - (it / G::NZ) * G::NZ;
+  // C2R along z of the packed rows Z[j] = X[2j] + i X[2j+1] (Hermitian extension for
+  // qz > nz/2): the first stage of the z transform packs its inputs as it reads them
+  auto pack = [&](int j, int q) {
     const bool upper = 2 * q > G::NZ;
     const int qq = upper ? G::NZ - q : q;
     float2 xv = X[qq * G::LSY + 2 * j];
     float2 yv = X[qq * G::LSY + 2 * j + 1];
     if (qq == 0 || 2 * qq == G::NZ) { xv.y = 0.f; yv.y = 0.f; }
     if (upper) { xv.y = -xv.y; yv.y = -yv.y; }
-    Zb[j * G::LSZ + q] = make_float2(xv.x - yv.y, xv.y + yv.x);
-  }
-  __syncthreads();
-  const float2* Z = lf_fft<G::NZ, 0, 1, +1, G::NP, G::LSZ>(Zb, X, twz);
+    return make_float2(xv.x - yv.y, xv.y + yv.x);
+  };
+  const float2* Z = lf_fft_ld<G::NZ, +1, G::NP, G::LSZ>(pack, Zb, X, twz);
   const float* Zf = reinterpret_cast<const float*>(Z);
   if constexpr (!kStep) {
     // items (row pair j, 4 columns): packed line j holds rows 2j (real) and 2j+1 (imaginary)
