@@ -754,9 +754,9 @@ __device__ __forceinline__ void fast_small_inv_body(const VolDesc& vd, int lb, f
   __syncthreads();
   float2* X = lf_fft<MY, 0, 1, +1, XB * MZH, LSMY>(P0, P1, twy);
   float2* Zb = (X == P0) ? P1 : P0;
-  // C2R along z': row r = xi my + y', pairs (2j, 2j+1) packed
-  for (int it = t; it < NPR * MZ; it += nt) {
-    const int j = it / MZ, q = it - (it / MZ) * MZ;
+  // C2R along z': row r = xi my + y', pairs (2j, 2j+1) packed by the first stage of the
+  // z' transform as it reads them
+  auto pack = [&](int j, int q) {
     const bool upper = 2 * q > MZ;
     const int qq = upper ? MZ - q : q;
     const int r0 = 2 * j, r1 = 2 * j + 1;
@@ -764,10 +764,9 @@ __device__ __forceinline__ void fast_small_inv_body(const VolDesc& vd, int lb, f
     float2 yv = r1 < ROWS ? X[((r1 / MY) * MZH + qq) * LSMY + r1 % MY] : make_float2(0.f, 0.f);
     if (qq == 0 || 2 * qq == MZ) { xv.y = 0.f; yv.y = 0.f; }
     if (upper) { xv.y = -xv.y; yv.y = -yv.y; }
-    Zb[j * LSMZ + q] = make_float2(xv.x - yv.y, xv.y + yv.x);
-  }
-  __syncthreads();
-  const float2* Z = lf_fft<MZ, 0, 1, +1, NPR, LSMZ>(Zb, X, twz);
+    return make_float2(xv.x - yv.y, xv.y + yv.x);
+  };
+  const float2* Z = lf_fft_ld<MZ, +1, NPR, LSMZ>(pack, Zb, X, twz);
   // store the block's rows: d[k][xbi XB + xi][y'][z'] is one contiguous run
   float* __restrict__ dst = d + (long long)k * G::MX * MY * MZ + (long long)xbi * XB * MY * MZ;
   constexpr int Q4 = ROWS * MZ / 4;
