@@ -795,6 +795,71 @@ __global__ __launch_bounds__(G::TP) void k_fast_small_inv(const VolDesc* __restr
   fast_small_inv_dispatch<G>(vds[0], blockIdx.x, d);
 }
 
+// ============================================================================ small-grid forward
+// Block (k, x'-block of XB planes): the small-grid spectra of the portraits r of those
+// planes (A^T alone and the back-projections start here), written as k_small_fwd writes
+// them, G'[k][x'-block][column][x'-in-block]: rows packed in pairs, R2C along z' (the
+// pairs split into their half spectra by the first stage of the y' transform), the
+// length-my transform along y'.
+template <class G, int XB>
+__device__ __forceinline__ void fast_small_fwd_body(const VolDesc& vd, int lb, const float* __restrict__ r,
+                                                    float2* __restrict__ out) {
+  constexpr int MY = G::MY, MZ = G::MZ, MZH = G::MZH, LSMY = G::LSMY, LSMZ = G::LSMZ;
+  constexpr int ROWS = XB * MY, NPR = ROWS / 2, NXB = G::MX / XB;
+  constexpr size_t A0 = (size_t)NPR * LSMZ, A1 = (size_t)XB * MZH * LSMY;
+  constexpr int SB = A0 > A1 ? (int)A0 : (int)A1;
+  extern __shared__ float2 lds[];
+  float2* twy = lds;
+  float2* twz = twy + MY;
+  float2* P0 = twz + MZ;
+  float2* P1 = P0 + SB;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int k = lb / NXB, xbi = lb - (lb / NXB) * NXB;
+  // the block's rows (xi my + y') are one contiguous run of the portraits
+  const float* __restrict__ src = r + (long long)k * G::MX * MY * MZ + (long long)xbi * XB * MY * MZ;
+  constexpr int Q4 = ROWS * MZ / 4;
+  float* Pf = reinterpret_cast<float*>(P0);
+  for (int f = t; f < Q4; f += nt) {
+    const int rr = f / (MZ / 4), z4 = 4 * (f - (f / (MZ / 4)) * (MZ / 4));
+    const float4 v = *reinterpret_cast<const float4*>(src + (long long)rr * MZ + z4);
+    float* dst = Pf + 2 * ((rr >> 1) * LSMZ + z4) + (rr & 1);
+    dst[0] = v.x; dst[2] = v.y; dst[4] = v.z; dst[6] = v.w;
+  }
+  load_table(twy, vd.tw + vd.off[4], MY);
+  load_table(twz, vd.tw + vd.off[5], MZ);
+  __syncthreads();
+  float2* Z = lf_fft<MZ, 0, 1, -1, NPR, LSMZ>(P0, P1, twz);
+  float2* X = (Z == P0) ? P1 : P0;
+  // line (xi, q'z), element y': row xi my + y' of the packed pair (its real or imaginary half)
+  auto split = [&](int l, int yp) {
+    const int xi = l / MZH, q = l - (l / MZH) * MZH;
+    const int rr = xi * MY + yp, j = rr >> 1;
+    const float2 zq = Z[j * LSMZ + q];
+    const float2 zm = Z[j * LSMZ + (q == 0 ? 0 : MZ - q)];
+    return (rr & 1) ? make_float2(0.5f * (zq.y + zm.y), -0.5f * (zq.x - zm.x))
+                    : make_float2(0.5f * (zq.x + zm.x), 0.5f * (zq.y - zm.y));
+  };
+  const float2* Y = lf_fft_ld<MY, -1, XB * MZH, LSMY>(split, X, Z, twy);
+  float2* __restrict__ dst = out + ((long long)k * NXB + xbi) * G::NCLS * XB;
+  for (int p = t; p < G::NCLS * XB; p += nt) {
+    const int c = p / XB, xi = p - (p / XB) * XB;
+    const int qyp = c / MZH, qzp = c - (c / MZH) * MZH;
+    dst[p] = Y[(xi * MZH + qzp) * LSMY + qyp];
+  }
+}
+
+template <class G>
+__global__ __launch_bounds__(G::TP) void k_fast_small_fwd(const VolDesc* __restrict__ vds, const float* __restrict__ r,
+                                                        float2* __restrict__ out) {
+  const VolDesc& vd = vds[0];
+  switch (vd.g.xb) {
+    case 1: fast_small_fwd_body<G, 1>(vd, blockIdx.x, r, out); break;
+    case 2: fast_small_fwd_body<G, 2>(vd, blockIdx.x, r, out); break;
+    case 4: fast_small_fwd_body<G, 4>(vd, blockIdx.x, r, out); break;
+    default: fast_small_fwd_body<G, 8>(vd, blockIdx.x, r, out); break;
+  }
+}
+
 // A then A^T after k_fast_col<NRM_STORE>: blocks [0, NBP) run the adjoint plane pass
 // (ao.out = b . v), the others the small-grid inverse pass that writes the portraits d.
 template <class G>

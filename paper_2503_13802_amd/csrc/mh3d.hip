@@ -398,6 +398,8 @@ struct FastOps {
   // A^T of nv single-harmonic descriptors at once (each with its own qx): out volumes
   // out + v N for v < nv
   void (*adjoint_each)(hipStream_t, const VolDesc*, int nv, float* out);
+  // the portraits' small-grid spectra into G' (as k_small_fwd)
+  void (*small_fwd)(hipStream_t, const VolDesc*, const float* r, float2* out, int nsmall, int xb);
 };
 
 template <class G>
@@ -433,6 +435,9 @@ struct FastImpl {
   static void small_inv(hipStream_t s, const VolDesc* vd, float* d, int nsmall, int xb) {
     k_fast_small_inv<G><<<dim3(nsmall), dim3(G::TP), G::small_lds(xb), s>>>(vd, d);
   }
+  static void small_fwd(hipStream_t s, const VolDesc* vd, const float* r, float2* out, int nsmall, int xb) {
+    k_fast_small_fwd<G><<<dim3(nsmall), dim3(G::TP), G::small_lds(xb), s>>>(vd, r, out);
+  }
   static void adjoint_each(hipStream_t s, const VolDesc* vd, int nv, float* out) {
     k_fast_col<G, COL_ADJ><<<dim3(G::NCLS / G::CPC, nv), dim3(G::TC), G::LDS_COL, s>>>(vd, 0);
     AdjOut ao;
@@ -443,7 +448,7 @@ struct FastImpl {
   static FastOps ops() {
     return FastOps{G::NX, G::NY, G::NZ, G::SX, G::SY, G::SZ, G::KMAX, G::NBP, G::NCLS / G::CPC, G::TC,
                    G::LDS_PLANE, G::LDS_COL, &plane_fwd, &cls, &plane_adj, &adj_and_store, &small_inv,
-                   &adjoint_each};
+                   &adjoint_each, &small_fwd};
   }
 };
 
@@ -567,6 +572,15 @@ static mh3d_status launch_small_fwd(mh3d_plan_t p, const float* r, float2* out =
   k_small_fwd<<<dim3(p->g.K * (p->g.mx / p->g.xb)), dim3(p->L.T_small), p->L.lds_small, p->ls>>>(p->vda, r, out);
   return last_launch("k_small_fwd");
 }
+static bool use_fast(mh3d_plan_t p);
+// The portraits' small-grid spectra into G' for A^T alone and the back-projections: the
+// compile-time pass where the plan runs those passes
+static mh3d_status launch_small_fwd_adj(mh3d_plan_t p, const float* r) {
+  if (!use_fast(p)) return launch_small_fwd(p, r);
+  Timer t(p, KID_SMALL_FWD);
+  p->fast->small_fwd(p->ls, p->vda, r, p->Gp, p->g.K * (p->g.mx / p->g.xb), p->g.xb);
+  return last_launch("k_fast_small_fwd");
+}
 
 static mh3d_status launch_plane_adj(mh3d_plan_t p, int out, float* o, const float* yin,
                                     const VolDesc* vd = nullptr) {
@@ -632,6 +646,11 @@ static mh3d_status fast_class_alone(mh3d_plan_t p, int mode) {
   Timer t(p, mode == COL_FWD ? KID_CLASS_FWD : KID_CLASS_ADJ);
   p->fast->cls(p->ls, p->vda, mode, 0);
   return last_launch("k_fast_col");
+}
+static mh3d_status fast_small_inv(mh3d_plan_t p, float* d) {
+  Timer t(p, KID_SMALL_INV);
+  p->fast->small_inv(p->ls, p->vda, d, p->g.K * (p->g.mx / p->g.xb), p->g.xb);
+  return last_launch("k_fast_small_inv");
 }
 static mh3d_status fast_plane_adj_out(mh3d_plan_t p, float* x) {
   Timer t(p, KID_PLANE_ADJ);
@@ -1050,9 +1069,7 @@ extern "C" mh3d_status mh3d_forward(mh3d_plan_t p, const float* rho, float* d) {
   if (use_fast(p)) {
     CHK(fast_plane_fwd(p, SRC_PLAIN, rho));
     CHK(fast_class_alone(p, COL_FWD));
-    Timer t(p, KID_SMALL_INV);
-    p->fast->small_inv(p->ls, p->vda, d, p->g.K * (p->g.mx / p->g.xb), p->g.xb);
-    return last_launch("k_fast_small_inv");
+    return fast_small_inv(p, d);
   }
   CHK(launch_plane_fwd(p, SRC_PLAIN, rho));
   CHK(launch_class_fwd(p, 0, FWD_G));
@@ -1064,7 +1081,7 @@ extern "C" mh3d_status mh3d_adjoint(mh3d_plan_t p, const float* d, float* rho) {
   CHK(check_plan(p));
   if (!rho || !d) return fail(MH3D_ERR_INVALID, "NULL array");
   if (use_fast(p)) {
-    CHK(launch_small_fwd(p, d));   // the portraits' small-grid spectra, into G'
+    CHK(launch_small_fwd_adj(p, d));   // the portraits' small-grid spectra, into G'
     CHK(fast_class_alone(p, COL_ADJ));
     return fast_plane_adj_out(p, rho);
   }
@@ -1077,7 +1094,7 @@ extern "C" mh3d_status mh3d_adjoint(mh3d_plan_t p, const float* d, float* rho) {
 extern "C" mh3d_status mh3d_backproject(mh3d_plan_t p, const float* d, float* c) {
   CHK(check_plan(p));
   if (!c || !d) return fail(MH3D_ERR_INVALID, "NULL array");
-  CHK(launch_small_fwd(p, d));
+  CHK(launch_small_fwd_adj(p, d));
   if (use_fast(p)) {
     // column and plane passes of A^T with one descriptor per harmonic (all K at once when
     // their Q buffers fit, else one harmonic after another through the shared one)
@@ -1771,10 +1788,11 @@ extern "C" mh3d_status mh3d_time_pass(mh3d_plan_t p, int32_t pass, int32_t reps,
   (void)hipMemsetAsync(dtmp, 0, sizeof(float) * (size_t)p->g.K * p->g.M, p->stream);
   const bool fast = use_fast(p);
   auto launch = [&]() -> mh3d_status {
-    // the compile-time passes where the plan has them (the small-grid passes 2 and 3 are
-  // the same either way)
+    // the compile-time passes where the plan has them
     if (fast && pass == 0) return fast_plane_fwd(p, SRC_PLAIN, p->vol[0]);
     if (fast && pass == 1) return fast_class_alone(p, COL_FWD);
+    if (fast && pass == 2) return fast_small_inv(p, dtmp);
+    if (fast && pass == 3) return launch_small_fwd_adj(p, dtmp);
     if (fast && pass == 4) return fast_class_alone(p, COL_ADJ);
     if (fast && pass == 5) return fast_plane_adj_out(p, p->vol[1]);
     if (fast && pass == 6) return fast_class(p, 0, NRM_STORE);
