@@ -565,7 +565,9 @@ def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
 
     plans, ds = build()
     torch.cuda.synchronize()
-    log("batched leg: %d plans built" % len(plans))
+    # volumes whose own solves run the compile-time passes (batches run the general ones)
+    compiled = [p.path() == 1 for p in plans]
+    log("batched leg: %d plans built, %d on the compile-time passes" % (len(plans), sum(compiled)))
     batch = mh3d.Batch(plans)
     # warm-up of both forms (graph capture, kernel loading) on a second set of plans, so
     # the timed runs below start with no cached step size
@@ -600,7 +602,7 @@ def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
         rhos, infos = batch_b.solve(ds_b, max_iter=max_iter, tol=tol, tau=0.0)
         torch.cuda.synchronize()
         bat_s = time.perf_counter() - t0
-    same = all(torch.equal(r, s[0]) for r, s in zip(rhos, seq))
+    same = all(torch.equal(r, s[0]) for r, s, c in zip(rhos, seq, compiled) if not c)
     maxdiff = max(rel_l2(r.cpu().numpy(), s[0].cpu().numpy()) for r, s in zip(rhos, seq))
     iters_seq = [s[1]["iters"] for s in seq]
     iters_bat = [i["iters"] for i in infos]
@@ -611,7 +613,8 @@ def batched_leg(batch_inputs, tol, max_iter, tile_cache=None):
            "sequential_with_setup_s": round(seq_setup_s, 4), "batched_with_setup_s": round(bat_setup_s, 4),
            "speedup_with_setup": round(seq_setup_s / bat_setup_s, 3),
            "converged": conv, "iters_max": max(iters_bat), "iters_mean": round(float(np.mean(iters_bat)), 1),
-           "identical_to_sequential": bool(same), "max_rel_l2_to_sequential": maxdiff,
+           "sequential_on_compile_time_passes": sum(compiled),
+           "identical_to_sequential_on_general_passes": bool(same), "max_rel_l2_to_sequential": maxdiff,
            "iters_match": iters_seq == iters_bat,
            "note": "setup = each volume's 50-step power iteration for tau (sequential: per plan; batched: one "
                    "batched launch sequence, plus the capture of the batch's graph on its first call); the "

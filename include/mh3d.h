@@ -244,8 +244,12 @@ mh3d_status mh3d_plan_path(mh3d_plan_t plan, int32_t request, int32_t* active);
  * differ), which the forward plane pass of mh3d_forward_adjoint also takes (its launch
  * holds no other blocks); mh3d_plan_set_tiles sets both splits to ps, and results do not
  * depend on either.
+ * A plan on the compile-time passes of mh3d_plan_path takes only xb from the tiles in
+ * its own calls, but runs the general passes in a batch: it is tuned as above with those
+ * passes switched off (stored under the general key), then xb alone (1, 2, 4 or 8) on
+ * the compile-time A + A^T, which its "|compiled" entry keeps beside the general tiles.
  * cache_path (may be NULL): a JSON object keyed by "arch|grid|K|decimation|psf
- * kind" (plus "|compiled" for plans on the compile-time passes of mh3d_plan_path) with
+ * kind" (plus "|compiled" for plans on the compile-time passes) with
  * E, cpw, xb, ps, ps_solve (the solver's split), tm (threads of that launch) and us; a
  * hit applies the stored tiles without timing, a miss stores the result.
  * tiles / us_per_application (HOST, may be NULL) receive the choice and its time.
@@ -257,7 +261,9 @@ mh3d_status mh3d_autotune(mh3d_plan_t plan, const char* cache_path, mh3d_tiles* 
  * update of every volume runs as one launch per pass over a task table of
  * (volume, block) pairs, a chunk of updates is captured once as a hipGraph and
  * replayed, and each volume stops at its own r_k <= rel_tol (its blocks exit at
- * once afterwards).  Results equal mh3d_solve on each plan with the same options.
+ * once afterwards).  Results equal mh3d_solve on each plan with the same options
+ * (bitwise on the general passes; a plan whose own solves run the compile-time passes
+ * agrees to FP32 rounding).
  * A plan may belong to one batch at a time and must not be used concurrently. */
 typedef struct mh3d_batch_s* mh3d_batch_t;
 mh3d_status mh3d_batch_create(int32_t n, const mh3d_plan_t* plans, mh3d_batch_t* out);

@@ -1879,7 +1879,7 @@ extern "C" mh3d_status mh3d_plan_path(mh3d_plan_t p, int32_t request, int32_t* a
 }
 
 // Cache key: device architecture, grid, harmonic count, decimation, spectrum form, pass family.
-static std::string tune_key(mh3d_plan_t p) {
+static std::string tune_key(mh3d_plan_t p, bool compiled) {
   int dev = 0;
   std::string arch = "unknown";
   hipDeviceProp_t prop;
@@ -1889,11 +1889,11 @@ static std::string tune_key(mh3d_plan_t p) {
     if (c != std::string::npos) arch = arch.substr(0, c);
   }
   char buf[160];
-  // plans on the compile-time passes time a different A + A^T (only xb and the merged
-  // launch's threads matter there): their own entries
+  // plans on the compile-time passes time a different A + A^T (only xb matters there):
+  // their own entries
   snprintf(buf, sizeof buf, "%s|%dx%dx%d|K%d|ds%dx%dx%d|%s%s", arch.c_str(), p->g.nx, p->g.ny, p->g.nz, p->g.K, p->g.sx,
            p->g.sy, p->g.sz, p->compact ? "analytic" : (p->g.C > 1 ? (p->g.C == 2 ? "user2" : "user3") : "user"),
-           use_fast(p) ? "|compiled" : "");
+           compiled ? "|compiled" : "");
   return buf;
 }
 
@@ -1994,28 +1994,32 @@ static mh3d_status time_updates(mh3d_plan_t p, const float* d, float* rho, doubl
 
 static bool valid_ps(const Geo& g, int ps) { return ps >= 1 && ps <= 4 && ps <= g.nzh && ps <= g.npairs; }
 
-extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d_tiles* tiles, double* us_out) {
-  CHK(check_plan(p));
-  if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; tune it before creating the batch");
-  const std::string key = tune_key(p);
-  if (cache_path) {
-    const auto m = tune_read(cache_path);
-    const auto it = m.find(key);
-    if (it != m.end()) {
-      mh3d_tiles t{it->second.E, it->second.cpw, it->second.xb, it->second.ps};
-      if (apply_tiles(p, &t) == MH3D_OK) {
-        if (valid_ps(p->g, it->second.ps_solve)) {
-          p->ps_solve = it->second.ps_solve;
-          CHK(upload_desc(p));
-        }
-        if (it->second.tm == 512 || it->second.tm == 1024) p->L.T_merge = it->second.tm;
-        if (tiles) *tiles = t;
-        if (us_out) *us_out = it->second.us;
-        return MH3D_OK;
-      }
-      // a stale entry (shape rules changed): tune again below
-    }
+// Applies the cache's entry for key; false if there is none or it no longer fits the
+// shape rules (then it is tuned again).
+static bool apply_cached(mh3d_plan_t p, const char* cache_path, const std::string& key, mh3d_tiles* tiles,
+                         double* us_out) {
+  if (!cache_path) return false;
+  const auto m = tune_read(cache_path);
+  const auto it = m.find(key);
+  if (it == m.end()) return false;
+  mh3d_tiles t{it->second.E, it->second.cpw, it->second.xb, it->second.ps};
+  if (apply_tiles(p, &t) != MH3D_OK) return false;
+  if (valid_ps(p->g, it->second.ps_solve)) {
+    p->ps_solve = it->second.ps_solve;
+    if (upload_desc(p) != MH3D_OK) return false;
   }
+  if (it->second.tm == 512 || it->second.tm == 1024) p->L.T_merge = it->second.tm;
+  if (tiles) *tiles = t;
+  if (us_out) *us_out = it->second.us;
+  return true;
+}
+
+// Tiles of the general passes: the cache's entry, else timed (class tiles, then the
+// small-grid tiles, the plane split and the merged launch's threads, then the solver's
+// split) and stored.
+static mh3d_status tune_general(mh3d_plan_t p, const char* cache_path, mh3d_tiles* tiles, double* us_out) {
+  const std::string key = tune_key(p, false);
+  if (apply_cached(p, cache_path, key, tiles, us_out)) return MH3D_OK;
   const Geo g0 = p->g;
   float* dtmp = nullptr;
   float* rtmp = nullptr;
@@ -2109,6 +2113,68 @@ extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d
     (void)apply_tiles(p, &h);
   }
   return s;
+}
+
+static mh3d_status set_fast_on(mh3d_plan_t p, bool on) {
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->fast_on = on;
+  return upload_desc(p);   // the solver's step sums come from the active path's blocks
+}
+
+// Plans on the compile-time passes take only xb from the tiles in their operator calls
+// and solves, but a batch runs such a plan's volume on the general passes.  So the
+// general tiles come first (timed with the compile-time passes switched off, stored under
+// the general key), then xb alone on the compile-time A + A^T; the "|compiled" entry is
+// the general tiles with that xb (a batch's general small-grid pass runs that xb too).
+extern "C" mh3d_status mh3d_autotune(mh3d_plan_t p, const char* cache_path, mh3d_tiles* tiles, double* us_out) {
+  CHK(check_plan(p));
+  if (p->batch_refs) return fail(MH3D_ERR_INVALID, "the plan belongs to a batch; tune it before creating the batch");
+  if (!(p->fast && p->fast_on)) return tune_general(p, cache_path, tiles, us_out);
+  const std::string key = tune_key(p, true);
+  if (apply_cached(p, cache_path, key, tiles, us_out)) return MH3D_OK;
+  CHK(set_fast_on(p, false));
+  mh3d_status s = tune_general(p, cache_path, nullptr, nullptr);
+  const mh3d_status s_on = set_fast_on(p, true);
+  CHK(s);
+  CHK(s_on);
+  const mh3d_tiles gen{p->g.E, p->g.cpw, p->g.xb, p->g.ps};
+  const int pss = p->ps_solve, tm = p->L.T_merge;
+  auto with_xb = [&](int xb) -> mh3d_status {
+    mh3d_tiles t = gen;
+    t.xb = xb;
+    CHK(apply_tiles(p, &t));
+    p->ps_solve = pss;
+    p->L.T_merge = tm;
+    return upload_desc(p);
+  };
+  float* dtmp = nullptr;
+  HIPCHK(hipMalloc(&dtmp, sizeof(float) * (size_t)p->g.K * p->g.M));
+  (void)hipMemsetAsync(p->vol[0], 0, sizeof(float) * p->g.N, p->stream);
+  int best_xb = 0;
+  double best_us = 1e30;
+  for (int xb : {1, 2, 4, 8}) {
+    if (p->g.mx % xb || with_xb(xb) != MH3D_OK || !use_fast(p)) continue;
+    double us = 0;
+    s = time_application(p, dtmp, &us);
+    if (s != MH3D_OK) break;
+    if (us < best_us) { best_us = us; best_xb = xb; }
+  }
+  if (s == MH3D_OK && best_xb == 0) s = fail(MH3D_ERR_UNSUPPORTED, "no x'-block could be timed on the compile-time passes");
+  if (s == MH3D_OK) s = with_xb(best_xb);
+  (void)hipStreamSynchronize(p->stream);
+  (void)hipFree(dtmp);
+  if (s != MH3D_OK) {
+    (void)with_xb(gen.xb);
+    return s;
+  }
+  if (tiles) *tiles = mh3d_tiles{gen.E, gen.cpw, best_xb, gen.ps};
+  if (us_out) *us_out = best_us;
+  if (cache_path) {
+    auto m = tune_read(cache_path);
+    m[key] = TuneEntry{gen.E, gen.cpw, best_xb, gen.ps, pss, tm, best_us};
+    tune_write(cache_path, m);
+  }
+  return MH3D_OK;
 }
 
 #include "net_host.hpp"
