@@ -228,8 +228,8 @@ __global__ __launch_bounds__(G::TPF) void k_fast_plane_fwd(const VolDesc* __rest
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const long long off = pb + (long long)(G::SY * (2 * j + h) + y0) * G::NZ + 4 * c4;
-        va[i][h] = *reinterpret_cast<const float4*>(a + off);
-        vb[i][h] = *reinterpret_cast<const float4*>(bs + off);
+        va[i][h] = ldg(reinterpret_cast<const float4*>(a + off));
+        vb[i][h] = ldg(reinterpret_cast<const float4*>(bs + off));
       }
     }
   }
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(G::TPF) void k_fast_plane_fwd(const VolDesc* __rest
 #pragma unroll
       for (int jz = 0; jz < G::SZ; ++jz) {
         const int qz = qzp + G::MZ * jz;
-        ev[i][jz] = et[qyp * G::NZH + (2 * qz <= G::NZ ? qz : G::NZ - qz)];
+        ev[i][jz] = ldg(et + qyp * G::NZH + (2 * qz <= G::NZ ? qz : G::NZ - qz));
       }
     }
   }
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(G::TPF) void k_fast_plane_fwd(const VolDesc* __rest
         sx += e.x * v.x - e.y * v.y;
         sy += e.x * v.y + e.y * v.x;
       }
-      dst[cc] = make_float2(sx, sy);
+      stg(dst + cc, make_float2(sx, sy));
     }
   }
 }
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
       if (NIT % G::TC == 0 || it < NIT) {
         const int xx = it / CPC, c = it - (it / CPC) * CPC;
 #pragma unroll
-        for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = vd.cp[((long long)y0 * NX + xx) * G::NCLS + c0 + c];
+        for (int y0 = 0; y0 < G::SY; ++y0) sv[i][y0] = ldg(vd.cp + ((long long)y0 * NX + xx) * G::NCLS + c0 + c);
       }
     }
   }
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
       const int k = p / (CPC * MX), r = p - k * (CPC * MX);
       const int c = r / MX, qq = r - c * MX;
       const int xbi = qq / xb, xi = qq - xbi * xb;
-      F0[(k * CPC + c) * LSM + qq] = vd.Gp[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi];
+      F0[(k * CPC + c) * LSM + qq] = ldg(vd.Gp + (((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi);
     }
   }
   // x factors of the thread's aliases and (residual) the data's spectra
@@ -386,8 +386,8 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
   for (int k = 0; k < KMAX; ++k) {
     if (k < K) {
 #pragma unroll
-      for (int jx = 0; jx < SX; ++jx) fs[k][jx] = vd.sfs[k * NX + qxp + jx * MX];
-      if constexpr (MODE == NRM_RESID) dt[k] = vd.Gp[((long long)k * G::NCLS + c0 + cl) * MX + qxp];
+      for (int jx = 0; jx < SX; ++jx) fs[k][jx] = ldg(vd.sfs + k * NX + qxp + jx * MX);
+      if constexpr (MODE == NRM_RESID) dt[k] = ldg(vd.Gp + ((long long)k * G::NCLS + c0 + cl) * MX + qxp);
     }
   }
   load_table(twx, vd.tw + vd.off[0], NX);
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
     const float2* V = lf_fft<NX, 0, 1, +1, CPC, LSX>(U0, U1, twx);
     for (int it = t; it < NIT; it += G::TC) {
       const int xx = it / CPC, c = it - (it / CPC) * CPC;
-      vd.qx[(long long)xx * G::NCLS + c0 + c] = V[c * LSX + xx];
+      stg(vd.qx + (long long)xx * G::NCLS + c0 + c, V[c * LSX + xx]);
     }
   }
   if constexpr (kStoreG) {
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(G::TC) void k_fast_col(const VolDesc* __restrict__ 
       const int k = p / (CPC * MX), r = p - k * (CPC * MX);
       const int xbi = r / (CPC * xb), r2 = r - xbi * (CPC * xb);
       const int c = r2 / xb, xi = r2 - c * xb;
-      Gs[(((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi] = F[(k * CPC + c) * LSM + xbi * xb + xi];
+      stg(Gs + (((long long)k * nxb + xbi) * G::NCLS + c0 + c) * xb + xi, F[(k * CPC + c) * LSM + xbi * xb + xi]);
     }
   }
 }
@@ -502,7 +502,7 @@ __device__ __forceinline__ void fast_step(const VolDesc& vd, const AdjOut& ao, c
   double acc[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) acc[j] = 0.0;
-  auto ld4 = [](const float* p) { const float4 v = *reinterpret_cast<const float4*>(p); return v; };
+  auto ld4 = [](const float* p) { return ldg(reinterpret_cast<const float4*>(p)); };
   auto wrap = [](int q, int n) { return q < 0 ? q + n : (q >= n ? q - n : q); };
   constexpr int U = 2;   // items whose loads are in flight together
   for (int f0 = threadIdx.x; f0 < NIT; f0 += U * G::TP) {
@@ -520,10 +520,10 @@ __device__ __forceinline__ void fast_step(const VolDesc& vd, const AdjOut& ao, c
       bv[q] = ld4(bs + i0);
       if (UPD == UPD_FISTA) rv[q] = ld4(rk + i0);
       if (stencil) {
-        zl2[q] = yv[row + wrap(z0 - 2, G::NZ)];
-        zl1[q] = yv[row + wrap(z0 - 1, G::NZ)];
-        zr1[q] = yv[row + wrap(z0 + 4, G::NZ)];
-        zr2[q] = yv[row + wrap(z0 + 5, G::NZ)];
+        zl2[q] = ldg(yv + row + wrap(z0 - 2, G::NZ));
+        zl1[q] = ldg(yv + row + wrap(z0 - 1, G::NZ));
+        zr1[q] = ldg(yv + row + wrap(z0 + 4, G::NZ));
+        zr2[q] = ldg(yv + row + wrap(z0 + 5, G::NZ));
         const long long pln = (long long)x * PL + z0;
         ym2[q] = ld4(yv + pln + (long long)wrap(y - 2, G::NY) * G::NZ);
         ym1[q] = ld4(yv + pln + (long long)wrap(y - 1, G::NY) * G::NZ);
@@ -590,10 +590,10 @@ __device__ __forceinline__ void fast_step(const VolDesc& vd, const AdjOut& ao, c
         }
       }
       if constexpr (UPD == UPD_NORMAL) {
-        *reinterpret_cast<float4*>(out + i0) = make_float4(o4[0], o4[1], o4[2], o4[3]);
+        stg(reinterpret_cast<float4*>(out + i0), make_float4(o4[0], o4[1], o4[2], o4[3]));
       } else {
-        *reinterpret_cast<float4*>(rho_next + i0) = make_float4(n4[0], n4[1], n4[2], n4[3]);
-        *reinterpret_cast<float4*>(y_next + i0) = make_float4(m4[0], m4[1], m4[2], m4[3]);
+        stg(reinterpret_cast<float4*>(rho_next + i0), make_float4(n4[0], n4[1], n4[2], n4[3]));
+        stg(reinterpret_cast<float4*>(y_next + i0), make_float4(m4[0], m4[1], m4[2], m4[3]));
       }
     }
   }
@@ -630,7 +630,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int c = t + i * G::TP;
-    if (c < G::NCLS) qv[i] = vd.qx[(long long)x * G::NCLS + c];
+    if (c < G::NCLS) qv[i] = ldg(vd.qx + (long long)x * G::NCLS + c);
   }
   constexpr int NE = G::NZH * G::MY, NEI = (NE + G::TP - 1) / G::TP;
   const float2* __restrict__ et = vd.set + (long long)y0 * G::MY * G::NZH;
@@ -638,7 +638,7 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
 #pragma unroll
   for (int i = 0; i < NEI; ++i) {
     const int it = t + i * G::TP;
-    if (it < NE) ev[i] = et[it];   // [q'y][qz]
+    if (it < NE) ev[i] = ldg(et + it);   // [q'y][qz]
   }
   constexpr int F4R = G::NZ / 4, P4 = G::NP * F4R, NB4 = (P4 + G::TP - 1) / G::TP;
   float4 bq[kStep ? 1 : NB4][2];
@@ -649,8 +649,8 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
       if (f < P4) {
         const int j = f / F4R, c4 = f - (f / F4R) * F4R;
         const long long o0 = pb + (long long)(G::SY * 2 * j + y0) * G::NZ + 4 * c4;
-        bq[i][0] = *reinterpret_cast<const float4*>(bs + o0);
-        bq[i][1] = *reinterpret_cast<const float4*>(bs + o0 + (long long)G::SY * G::NZ);
+        bq[i][0] = ldg(reinterpret_cast<const float4*>(bs + o0));
+        bq[i][1] = ldg(reinterpret_cast<const float4*>(bs + o0 + (long long)G::SY * G::NZ));
       }
     }
   }
@@ -708,8 +708,8 @@ __device__ __forceinline__ void fast_plane_adj_body(const VolDesc& vd, int lb, c
       const float4 b0 = bq[i][0], b1 = bq[i][1];
       const float2* zr = Z + j * G::LSZ + 4 * c4;
       const float2 z0 = zr[0], z1 = zr[1], z2 = zr[2], z3 = zr[3];
-      *reinterpret_cast<float4*>(out + o0) = make_float4(b0.x * z0.x, b0.y * z1.x, b0.z * z2.x, b0.w * z3.x);
-      *reinterpret_cast<float4*>(out + o1) = make_float4(b1.x * z0.y, b1.y * z1.y, b1.z * z2.y, b1.w * z3.y);
+      stg(reinterpret_cast<float4*>(out + o0), make_float4(b0.x * z0.x, b0.y * z1.x, b0.z * z2.x, b0.w * z3.x));
+      stg(reinterpret_cast<float4*>(out + o1), make_float4(b1.x * z0.y, b1.y * z1.y, b1.z * z2.y, b1.w * z3.y));
     }
   } else {
     fast_step<G, OUT == OUT_STEP_NORMAL ? UPD_NORMAL : UPD_FISTA>(vd, ao, Z, x, y0, lb);
@@ -744,7 +744,7 @@ __device__ __forceinline__ void fast_small_inv_body(const VolDesc& vd, int lb, f
   const float2* __restrict__ src = vd.G + ((long long)k * NXB + xbi) * G::NCLS * XB;
   constexpr int NS = G::NCLS * XB;
   for (int p = t; p < NS; p += nt) {
-    const float2 v = src[p];
+    const float2 v = ldg(src + p);
     const int c = p / XB, xi = p - (p / XB) * XB;
     const int qyp = c / MZH, qzp = c - (c / MZH) * MZH;
     P0[(xi * MZH + qzp) * LSMY + qyp] = v;
@@ -776,7 +776,7 @@ __device__ __forceinline__ void fast_small_inv_body(const VolDesc& vd, int lb, f
     float v[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) v[e] = (r & 1) ? zr[e].y : zr[e].x;
-    *reinterpret_cast<float4*>(dst + (long long)r * MZ + z4) = make_float4(v[0], v[1], v[2], v[3]);
+    stg(reinterpret_cast<float4*>(dst + (long long)r * MZ + z4), make_float4(v[0], v[1], v[2], v[3]));
   }
 }
 
@@ -821,7 +821,7 @@ __device__ __forceinline__ void fast_small_fwd_body(const VolDesc& vd, int lb, c
   float* Pf = reinterpret_cast<float*>(P0);
   for (int f = t; f < Q4; f += nt) {
     const int rr = f / (MZ / 4), z4 = 4 * (f - (f / (MZ / 4)) * (MZ / 4));
-    const float4 v = *reinterpret_cast<const float4*>(src + (long long)rr * MZ + z4);
+    const float4 v = ldg(reinterpret_cast<const float4*>(src + (long long)rr * MZ + z4));
     float* dst = Pf + 2 * ((rr >> 1) * LSMZ + z4) + (rr & 1);
     dst[0] = v.x; dst[2] = v.y; dst[4] = v.z; dst[6] = v.w;
   }
@@ -844,7 +844,7 @@ __device__ __forceinline__ void fast_small_fwd_body(const VolDesc& vd, int lb, c
   for (int p = t; p < G::NCLS * XB; p += nt) {
     const int c = p / XB, xi = p - (p / XB) * XB;
     const int qyp = c / MZH, qzp = c - (c / MZH) * MZH;
-    dst[p] = Y[(xi * MZH + qzp) * LSMY + qyp];
+    stg(dst + p, Y[(xi * MZH + qzp) * LSMY + qyp]);
   }
 }
 

@@ -264,10 +264,45 @@ __device__ C* fft_lines(C* a, C* b, const C* tw, int n, int nlines, int ls) {
   }
 }
 
+// Global-memory loads and stores through address-space-1 pointers.  A pointer read from
+// a descriptor in memory is generic to the compiler, which then emits flat instructions;
+// those count against the LDS counter as well, so every later LDS wait (each transform
+// stage has one) would also wait for them.  HIP's vector types are classes whose copies
+// go through a generic this pointer, so the accesses use clang's native vectors.
+typedef float gvec2 __attribute__((ext_vector_type(2)));
+typedef float gvec4 __attribute__((ext_vector_type(4)));
+#define MH3D_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) { return *p; }
+__device__ __forceinline__ float ldg(const float* p) { return *(const MH3D_GLOBAL float*)p; }
+__device__ __forceinline__ float2 ldg(const float2* p) {
+  const gvec2 v = *(const MH3D_GLOBAL gvec2*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ldg(const float4* p) {
+  const gvec4 v = *(const MH3D_GLOBAL gvec4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stg(float* p, float v) { *(MH3D_GLOBAL float*)p = v; }
+__device__ __forceinline__ void stg(float2* p, float2 v) {
+  gvec2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(MH3D_GLOBAL gvec2*)p = w;
+}
+__device__ __forceinline__ void stg(float4* p, float4 v) {
+  gvec4 w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *(MH3D_GLOBAL gvec4*)p = w;
+}
+
 // Copy a length-n twiddle table from global memory into LDS (then barrier by caller).
 template <typename C>
 __device__ __forceinline__ void load_table(C* dst, const C* src, int n) {
-  for (int t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) dst[t] = ldg(src + t);
 }
 
 }  // namespace mh3d
