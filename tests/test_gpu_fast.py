@@ -104,6 +104,33 @@ def test_fast_solver_matches_oracle(shape, ds, harm):
     assert abs(info["iters"] - n_o) <= 1
 
 
+def test_fast_solver_chunks_and_resume_are_bitwise():
+    """On the compile-time passes a resumed solve equals the uninterrupted one, and a
+    tolerance stop inside a chunk of updates (the chunk's later launches see the state's
+    done flag) equals the stop with a state read after every update."""
+    torch = torch_cuda()
+    shape, ds, harm = SMALL[1]
+    announce("fast solver chunks and resume %s" % (shape,))
+    p, h, b, op = _setup(shape, ds, harm)
+    assert p.path() == 1
+    rho_t = np.maximum(inputs.random_field(shape, 17), 0.0)
+    d = op.A(rho_t)
+    d = torch.tensor(d + 0.01 * float(np.abs(d).max()) * inputs.random_field(d.shape, 18), dtype=torch.float32)
+    tau = osv.step_size(osv.power_iteration(op, inputs.random_field(shape, 19), 40))
+    full, _ = p.solve(d, max_iter=11, tol=0.0, tau=tau)
+    a, _ = p.solve(d, max_iter=6, tol=0.0, tau=tau)
+    prev, _ = p.solve(d, max_iter=5, tol=0.0, tau=tau)
+    rest, _ = p.solve(d, rho0=a, rho_prev=prev, k0=7, max_iter=5, tol=0.0, tau=tau, check_every=2)
+    assert torch.equal(full, rest)
+    r1, i1 = p.solve(d, max_iter=300, tol=2e-3, tau=tau, check_every=1)
+    n = i1["iters"]
+    assert 1 < n < 300 and (n % 5 or n % 7)
+    for every in (5, 7):
+        r, i = p.solve(d, max_iter=300, tol=2e-3, tau=tau, check_every=every)
+        assert i["iters"] == n
+        assert torch.equal(r1, r)
+
+
 def test_fast_full_size_workload2():
     """128^3, k = 2..12, decimation (2, 4, 4): A then A^T of the phantom against the FFT
     oracle (full outputs), the normal operator, and 8 solver updates; the general passes
