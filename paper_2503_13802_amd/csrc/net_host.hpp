@@ -153,12 +153,25 @@ bool conv_ct_try(hipStream_t s, int ntile, bool relu, int blocks, const uint16_t
                  int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
   if (kp != 16 * ((27 * CS + 15) / 16) || ntile < 1 || ntile > 2) return false;
   if (ntile == 1) {
-    if (relu) k_conv_ct<CS, 1, true><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
-    else k_conv_ct<CS, 1, false><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
+    if (relu) k_conv_ct<CS, 1, true><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o, nullptr);
+    else k_conv_ct<CS, 1, false><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o, nullptr);
   } else {
-    if (relu) k_conv_ct<CS, 2, true><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
-    else k_conv_ct<CS, 2, false><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o);
+    if (relu) k_conv_ct<CS, 2, true><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o, nullptr);
+    else k_conv_ct<CS, 2, false><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(in, dm, W, kp, bias, cout, cs_out, o, nullptr);
   }
+  return true;
+}
+
+// The decoder's first convolution (ReLU) on [skip, upsampled coarse] read in place, for
+// the (channel stride, skip channels) pairs compiled here; false otherwise.
+template <int CS, int C1>
+bool conv_ct_cat_try(hipStream_t s, int ntile, int blocks, const uint16_t* skip, const uint16_t* coarse, Dims dm,
+                     const uint16_t* W, int kp, const float* bias, int cout, int cs_out, uint16_t* o) {
+  if (kp != 16 * ((27 * CS + 15) / 16) || ntile < 1 || ntile > 2) return false;
+  if (ntile == 1)
+    k_conv_ct<CS, 1, true, C1><<<blocks, 256, conv_ct_lds<CS, 1>(), s>>>(skip, dm, W, kp, bias, cout, cs_out, o, coarse);
+  else
+    k_conv_ct<CS, 2, true, C1><<<blocks, 256, conv_ct_lds<CS, 2>(), s>>>(skip, dm, W, kp, bias, cout, cs_out, o, coarse);
   return true;
 }
 
@@ -245,6 +258,24 @@ mh3d_status conv_fwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
   return launch_conv(n, in, dm, ly.cs_in, ly.ks, ly.Wf, ly.kp, n->p + ly.b_off, ly.cout, ly.cs_out, out, relu, f32);
 }
 
+// The decoder's first convolution with ReLU on the concatenation of skip (c1 channels,
+// stride c1) and the coarse tensor upsampled by 2 (c2 channels, stride c2), read in
+// place where k_conv_ct is compiled for it (c1 + c2 a compiled stride, no padding
+// channels); false: the caller concatenates first.
+bool conv_fwd_cat(mh3d_net_t n, const NetLayer& ly, const uint16_t* skip, int c1, const uint16_t* coarse, int c2, Dims dm,
+                  uint16_t* out) {
+  const int ntile = (ly.cout + 15) / 16;
+  if (ly.ks != 3 || c1 % 4 || c2 % 4 || ly.cs_in != c1 + c2 || ntile > 2 || dm.lz < 4 || dm.ly < 2 || dm.lx < 2)
+    return false;
+  const int blocks = (int)((1ll << (dm.lx + dm.ly + dm.lz)) / 256);
+  const float* bias = n->p + ly.b_off;
+  bool ok = false;
+  if (c1 == 4 && c2 == 8) ok = conv_ct_cat_try<12, 4>(n->stream, ntile, blocks, skip, coarse, dm, ly.Wf, ly.kp, bias, ly.cout, ly.cs_out, out);
+  else if (c1 == 8 && c2 == 16) ok = conv_ct_cat_try<24, 8>(n->stream, ntile, blocks, skip, coarse, dm, ly.Wf, ly.kp, bias, ly.cout, ly.cs_out, out);
+  else if (c1 == 16 && c2 == 32) ok = conv_ct_cat_try<48, 16>(n->stream, ntile, blocks, skip, coarse, dm, ly.Wf, ly.kp, bias, ly.cout, ly.cs_out, out);
+  return ok;
+}
+
 // Gradients of one conv layer given the gradient g of its (pre-activation) output:
 // accumulates dW, db and writes the input gradient gin (unless null).
 mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims dm, const uint16_t* g, int cs_g,
@@ -285,7 +316,8 @@ mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
 
 // x (FP32, volume grid `src`, crop window o + dst dims) -> forward through the net;
 // result FP32 in w->y.  Scale s = max |x| over the whole source volume.
-mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long long nsrc, int ox, int oy, int oz) {
+mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long long nsrc, int ox, int oy, int oz,
+                        bool infer = false) {
   const int L = (int)n->widths.size();
   if (!n->packed) CHK(net_pack(n));
   unsigned* slot = reinterpret_cast<unsigned*>(w->scale + 4);
@@ -315,10 +347,17 @@ mh3d_status net_forward(mh3d_net_t n, NetWork* w, const float* x, Dims src, long
     Dims dl = dims_of(*w, l);
     const int c1 = n->widths[l], c2 = n->widths[l + 1];
     const int cats = round4(c1 + c2);
-    k_upcat<<<grid_for(dl.n() * (cats / 4)), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
-                                                            dims_of(*w, l + 1), cats, w->cat[l]);
-    CHK(last_launch("k_upcat"));
-    CHK(conv_fwd(n, n->layers[dec_index(L, l, 0)], w->cat[l], dl, w->da[l], true, false));
+    const NetLayer& la = n->layers[dec_index(L, l, 0)];
+    // inference reads the concatenation in place where it can (training keeps the
+    // concatenated tensor: the weight gradient reads it)
+    if (infer && conv_fwd_cat(n, la, w->es[l], c1, h, c2, dl, w->da[l])) {
+      CHK(last_launch("k_conv_ct (concatenation read in place)"));
+    } else {
+      k_upcat<<<grid_for(dl.n() * (cats / 4)), 256, 0, n->stream>>>(w->es[l], round4(c1), c1, h, round4(c2), c2, dl,
+                                                              dims_of(*w, l + 1), cats, w->cat[l]);
+      CHK(last_launch("k_upcat"));
+      CHK(conv_fwd(n, la, w->cat[l], dl, w->da[l], true, false));
+    }
     CHK(conv_fwd(n, n->layers[dec_index(L, l, 1)], w->da[l], dl, w->db[l], true, false));
     h = w->db[l];
   }
@@ -554,7 +593,7 @@ extern "C" mh3d_status mh3d_net_forward(mh3d_net_t n, const float* x, int32_t nx
   NetWork* w;
   CHK(net_work(n, nx, ny, nz, &w));
   Dims src{ilog2(nx), ilog2(ny), ilog2(nz)};
-  CHK(net_forward(n, w, x, src, (long long)nx * ny * nz, 0, 0, 0));
+  CHK(net_forward(n, w, x, src, (long long)nx * ny * nz, 0, 0, 0, true));
   HIPCHK(hipMemcpyAsync(y, w->y, sizeof(float) * (size_t)nx * ny * nz, hipMemcpyDeviceToDevice, n->stream));
   return MH3D_OK;
 }
@@ -611,7 +650,7 @@ extern "C" mh3d_status mh3d_warm_start(mh3d_plan_t p, mh3d_net_t n, const float*
   // per-harmonic back-projections c_k = b (H_k^T P^T d_k), the network's channels
   CHK(mh3d_backproject(p, d, w->xin));
   Dims src{ilog2(g.nx), ilog2(g.ny), ilog2(g.nz)};
-  CHK(net_forward(n, w, w->xin, src, g.N, 0, 0, 0));
+  CHK(net_forward(n, w, w->xin, src, g.N, 0, 0, 0, true));
   k_scale_relu<<<grid_for(g.N), 256, 0, p->stream>>>(w->y, g.N, w->scale, rho_init);
   CHK(last_launch("k_scale_relu"));
   return MH3D_OK;

@@ -363,11 +363,16 @@ __global__ __launch_bounds__(256) void k_conv_splitk8(const uint16_t* __restrict
 // offset, the operand reads at immediate offsets and the MFMA: no tap arithmetic per
 // chunk.  The halo goes in per voxel (one contiguous CS-channel run), and the output
 // tile leaves through LDS as contiguous 16- or 8-byte pieces of each z-run.
-template <int CS, int NT, bool RELU>
+// C1 > 0: the input is the decoder's concatenation [skip, upsampled coarse] read in place
+// (no concatenated copy): channels [0, C1) of voxel n from `in` (stride C1), the other
+// CS - C1 from `in2` (stride CS - C1) at the coarse voxel (x/2, y/2, z/2), the halo
+// tile holding the same values the concatenated tensor would.
+template <int CS, int NT, bool RELU, int C1 = 0>
 __global__ __launch_bounds__(256) void k_conv_ct(const uint16_t* __restrict__ in, Dims dm,
                                                  const uint16_t* __restrict__ W, int kp,
                                                  const float* __restrict__ bias, int cout, int cs_out,
-                                                 uint16_t* __restrict__ out) {
+                                                 uint16_t* __restrict__ out, const uint16_t* __restrict__ in2) {
+  static_assert(C1 % 4 == 0 && C1 < CS, "the skip channels are whole 4-channel groups");
   constexpr int NKC = (27 * CS + 15) / 16;
   constexpr int RS = 18 * CS;                       // one (x, y) row of the halo
   constexpr int HALO = 648 * CS;
@@ -396,21 +401,28 @@ __global__ __launch_bounds__(256) void k_conv_ct(const uint16_t* __restrict__ in
   // halo: voxel v = threadIdx.x + 256 u, its CS channels as CS/4 8-byte loads, all of a
   // thread's loads issued before its LDS writes
   {
-    constexpr int NQ = CS / 4;
+    constexpr int NQ = CS / 4, NQ1 = C1 / 4;
+    const Dims dc{dm.lx - 1, dm.ly - 1, dm.lz - 1};
     s4v val[3][NQ];
-    long long src[3];
+    long long src[3], src2[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       const int v = threadIdx.x + 256 * u;
       src[u] = -1;
+      src2[u] = 0;
       if (v < 648) {
         const int zl = v % 18, yl = (v / 18) % 6, xl = v / 108;
         const int gx = x0 + xl - 1, gy = y0 + yl - 1, gz = z0 + zl - 1;
-        if (dm.inside(gx, gy, gz)) src[u] = dm.encode(gx, gy, gz) * CS;
+        if (dm.inside(gx, gy, gz)) {
+          src[u] = dm.encode(gx, gy, gz) * (C1 > 0 ? C1 : CS);
+          if constexpr (C1 > 0) src2[u] = dc.encode(gx >> 1, gy >> 1, gz >> 1) * (CS - C1);
+        }
       }
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        val[u][q] = src[u] >= 0 ? *reinterpret_cast<const s4v*>(in + src[u] + 4 * q) : s4v{0, 0, 0, 0};
+      for (int q = 0; q < NQ; ++q) {
+        const uint16_t* p = (C1 > 0 && q >= NQ1) ? in2 + src2[u] + 4 * (q - NQ1) : in + src[u] + 4 * q;
+        val[u][q] = src[u] >= 0 ? *reinterpret_cast<const s4v*>(p) : s4v{0, 0, 0, 0};
+      }
     }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {

@@ -52,6 +52,23 @@ def test_net_forward_matches_fp64_reference():
     assert rel_l2(y, want) <= 3e-2
 
 
+@pytest.mark.parametrize("widths,in_ch", [((8, 16), 1), ((16, 32), 3)])
+def test_net_forward_reads_the_decoder_concatenation_in_place(widths, in_ch):
+    """Inference runs the decoder's first convolution on [skip, upsampled coarse] read in
+    place (strides 12, 24 and 48 with 4, 8 and 16 skip channels; the 4-level test net
+    covers 12): the same values as the concatenated tensor, so the output meets the
+    reference network's BF16 storage model as closely as with the concatenation."""
+    torch, net, flat, x, t = _setup(4, shape=(16, 16, 16), widths=widths, in_ch=in_ch)
+    announce("net forward, concatenation in place %s" % (widths,))
+    y = net.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
+    s = _scale(x)
+    params = unet.unpack(flat.astype(np.float32).astype(np.float64), widths, in_ch)
+    model = unet.forward(params, x / s, widths, bf16=True).detach().numpy()
+    want = unet.forward(params, x / s, widths).numpy()
+    assert rel_l2(y, model) <= 1e-4
+    assert rel_l2(y, want) <= 3e-2
+
+
 # The BF16 storage model rounds exactly where the device stores BF16, so the device
 # and the model differ only by the order of the FP32 sums, which now and then moves a
 # BF16 rounding by one ulp.  On the 2-level nets that leaves them equal to about 1e-7
