@@ -296,17 +296,23 @@ def cpu_baseline(w, rho, r, budget_s=12.0):
 
 
 # ----------------------------------------------------------------------------- GPU legs
-def time_steps(fn, steps, warmup):
+def time_steps(fn, steps, warmup, repeats=1):
+    """Seconds per step over `steps` steps after `warmup` untimed ones; with repeats > 1
+    the median of that many such loops (the secondary legs, one short loop of which can
+    catch a transient of the host or the GPU)."""
     import torch
     with Quiet():
         for _ in range(warmup):
             fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        times = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) / steps)
+        return sorted(times)[len(times) // 2]
 
 
 def operator_leg(w, steps, warmup, tile_cache, oracle_check=True):
@@ -453,7 +459,7 @@ def vector_leg(w, steps, warmup, tile_cache=None):
             tiles, _ = plan.autotune(tile_cache)
         y = torch.empty((K,) + w.small_shape, device=dev)
         x = torch.empty(w.shape, device=dev)
-        sec = time_steps(lambda: plan.forward_adjoint(src, d_out=y, x_out=x), steps, warmup)
+        sec = time_steps(lambda: plan.forward_adjoint(src, d_out=y, x_out=x), steps, warmup, repeats=3)
         pass_us = plan.time_passes(reps=100)
         bmap = general_kernel_bytes(w, compact=False, ncomp=C)
         if "class_normal" in pass_us:
@@ -461,7 +467,8 @@ def vector_leg(w, steps, warmup, tile_cache=None):
         else:
             ck, cb, cs = "class_fwd+class_adj", bmap["class_fwd"], 0.5 * (pass_us["class_fwd"] + pass_us["class_adj"])
         d_ref = om.forward_vector(h, b, rho, w.ds)
-        out["C%d" % C] = {"applications_per_s": round(1.0 / sec, 2), "tiles": list(tiles),
+        out["C%d" % C] = {"applications_per_s": round(1.0 / sec, 2), "timing": "median of 3 loops of the steps",
+                          "tiles": list(tiles),
                           "kernels_us": {k: round(v, 3) for k, v in pass_us.items()},
                           "class_kernel": ck, "class_bytes_per_launch": cb, "class_GBps": round(cb / cs / 1e3, 1),
                           "oracle_rel_l2": {"A": rel_l2(y.cpu().numpy(), d_ref),
@@ -504,7 +511,7 @@ def mh2d_leg(steps, warmup, tile_cache=None):
     src = torch.tensor(rho, dtype=torch.float32, device=dev)
     y = torch.empty_like(d)
     x = torch.empty_like(src)
-    sec = time_steps(lambda: plan.forward_adjoint(src, d_out=y, x_out=x), steps, warmup)
+    sec = time_steps(lambda: plan.forward_adjoint(src, d_out=y, x_out=x), steps, warmup, repeats=3)
     a_err = rel_l2(y.cpu().numpy(), clean)
     at_err = rel_l2(x.cpu().numpy(), op.AT(clean))
     rho_init = torch.zeros_like(src)
@@ -524,7 +531,7 @@ def mh2d_leg(steps, warmup, tile_cache=None):
     out = {"workload": w.name, "grid": list(w.shape), "scans": len(hs), "harmonics_per_scan": list(w.harmonics),
            "decimation": list(w.ds), "lambda": w.lam, "tiles": list(tiles),
            "inputs": "inputs.scan_psfs / vector_sensitivity / spiral_phantom_2d (seeded synthetic)",
-           "applications_per_s": round(1.0 / sec, 2),
+           "applications_per_s": round(1.0 / sec, 2), "timing": "median of 3 loops of the steps",
            "kernels_us": {k: round(v, 3) for k, v in plan.time_passes(reps=100).items()},
            "time_to_recon": {"plain_s": round(first_s, 4), "plain_cached_tau_s": round(cached_s, 4),
                              "iters": info["iters"], "rel_step": info["rel_step"],
