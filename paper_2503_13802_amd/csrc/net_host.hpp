@@ -292,7 +292,9 @@ mh3d_status conv_bwd(mh3d_net_t n, const NetLayer& ly, const uint16_t* in, Dims 
     k_conv_wgrad_tiled<<<grid, 256, wlds, n->stream>>>(in, dm, ly.cs_in, g, cs_g, ly.cout, ly.kp, ly.gWf, tpb);
     CHK(last_launch("k_conv_wgrad_tiled"));
   } else {
-    long long chunk = 2048;
+    // voxel ranges of 256 per wave (8 MFMA instructions): enough waves in flight on the
+    // small grids and the 1x1x1 head, whose chains are their loads' latency
+    long long chunk = 256;
     int nsplit = (int)((N + chunk - 1) / chunk);
     k_conv_wgrad<<<ncot * nkc * nsplit, 64, 0, n->stream>>>(in, dm, ly.cs_in, ly.ks, g, cs_g, ly.cout, ly.kp, ly.gWf,
                                                             nsplit, chunk);

@@ -776,11 +776,18 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
       b[j] = (short)bv;
     }
   };
-  for (long long nb = v0; nb < v1; nb += 32) {   // two chunks per instruction (the second may be empty)
-    s4v a0, b0, a1, b1;
-    slices(nb, a0, b0);
-    slices(nb + 16, a1, b1);
-    acc = mfma2(a0, a1, b0, b1, acc);
+  // two chunks per instruction (the second may be empty); the loads of U instructions are
+  // issued before their MFMAs, which run in the same order as one at a time
+  constexpr int U = 4;
+  for (long long nb = v0; nb < v1; nb += 32 * U) {
+    s4v a0[U], b0[U], a1[U], b1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      slices(nb + 32 * u, a0[u], b0[u]);
+      slices(nb + 32 * u + 16, a1[u], b1[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = mfma2(a0[u], a1[u], b0[u], b1[u], acc);
   }
   // D[row = co 4g+j][col = k r]
 #pragma unroll
