@@ -19,6 +19,9 @@ solver    Objective, power-iteration step size, accelerated projected gradient
           special cases used as pins.
 philox    Philox4x32-10 counter-based generator (Salmon et al., SC'11), used for the
           power-iteration start vector so that both sides draw the same numbers.
+mhad      The closed-form native image of App. D (eq. mhad2, eq. mhadM).
+unet      The warm-start network (not in the paper): a 3D U-Net in FP64 with an
+          optional BF16 storage model, its loss and its gradients.
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*``
 against closed forms, mpmath, finite differences, brute force or identities,
