@@ -26,7 +26,7 @@ struct NetLayer {
   long long w_off, b_off;  // offsets in the flat FP32 parameter vector
   uint16_t* Wf = nullptr;  // BF16 forward matrix
   uint16_t* Wt = nullptr;  // BF16 flipped transposed matrix
-  float* gWf = nullptr;    // FP32 gradient of the forward matrix
+  float* gWf = nullptr;    // FP32 gradient of the forward matrix (a slice of the network's gW)
 };
 
 // Activations and gradients of one grid shape.
@@ -59,6 +59,10 @@ struct mh3d_net_s {
   hipStream_t stream;
   std::map<std::tuple<int, int, int>, NetWork> work;
   bool packed = false;
+  float* gW = nullptr;           // every layer's FP32 forward-matrix gradient, one buffer
+  long long gW_len = 0;
+  PackDesc* pack = nullptr;      // device table of the layers for k_pack_all / k_unpack_all
+  int pack_blocks = 0, unpack_blocks = 0;
 };
 
 namespace {
@@ -82,11 +86,8 @@ int enc_index(int l, int ab) { return 2 * l + ab; }
 int dec_index(int L, int l, int ab) { return 2 * L + 2 * (L - 2 - l) + ab; }
 
 mh3d_status net_pack(mh3d_net_t n) {
-  for (auto& ly : n->layers) {
-    k_pack_layer<<<grid_for((long long)ly.rows_f * ly.kp + (long long)ly.rows_t * ly.kpt), 256, 0, n->stream>>>(
-        n->p + ly.w_off, ly.cin, ly.cout, ly.ks, ly.cs_in, ly.cs_out, ly.kp, ly.kpt, ly.rows_f, ly.rows_t, ly.Wf, ly.Wt);
-    CHK(last_launch("k_pack_layer"));
-  }
+  k_pack_all<<<n->pack_blocks, 256, 0, n->stream>>>(n->pack, (int)n->layers.size());
+  CHK(last_launch("k_pack_all"));
   n->packed = true;
   return MH3D_OK;
 }
@@ -430,21 +431,16 @@ mh3d_status net_backward(mh3d_net_t n, NetWork* w) {
     }
   }
   // padded forward-matrix gradients -> flat layout
-  for (auto& ly : n->layers) {
-    k_unpack_wgrad<<<grid_for((long long)ly.cout * ly.ks * ly.ks * ly.ks * ly.cin), 256, 0, n->stream>>>(
-        ly.gWf, ly.cin, ly.cout, ly.ks, ly.cs_in, ly.kp, n->g + ly.w_off);
-    CHK(last_launch("k_unpack_wgrad"));
-  }
+  k_unpack_all<<<n->unpack_blocks, 256, 0, n->stream>>>(n->pack, (int)n->layers.size());
+  CHK(last_launch("k_unpack_all"));
   return MH3D_OK;
 }
 
 mh3d_status net_zero_grads(mh3d_net_t n) {
   k_fill_f32<<<grid_for(n->nparam), 256, 0, n->stream>>>(n->g, n->nparam + 128, 0.f);
   CHK(last_launch("k_fill_f32"));
-  for (auto& ly : n->layers) {
-    k_fill_f32<<<grid_for((long long)ly.rows_f * ly.kp), 256, 0, n->stream>>>(ly.gWf, (long long)ly.rows_f * ly.kp, 0.f);
-    CHK(last_launch("k_fill_f32"));
-  }
+  k_fill_f32<<<grid_for(n->gW_len), 256, 0, n->stream>>>(n->gW, n->gW_len, 0.f);
+  CHK(last_launch("k_fill_f32"));
   return MH3D_OK;
 }
 
@@ -523,7 +519,36 @@ extern "C" mh3d_status mh3d_net_create(int32_t levels, const int32_t* widths, in
   for (auto& ly : n->layers) {
     if ((st = net_alloc((void**)&ly.Wf, sizeof(uint16_t) * (size_t)ly.rows_f * ly.kp)) != MH3D_OK) return bail(st);
     if ((st = net_alloc((void**)&ly.Wt, sizeof(uint16_t) * (size_t)ly.rows_t * ly.kpt)) != MH3D_OK) return bail(st);
-    if ((st = net_alloc((void**)&ly.gWf, sizeof(float) * (size_t)ly.rows_f * ly.kp)) != MH3D_OK) return bail(st);
+    n->gW_len += ((long long)ly.rows_f * ly.kp + 63) & ~63ll;   // 256-byte aligned slices
+  }
+  if ((st = net_alloc((void**)&n->gW, sizeof(float) * (size_t)n->gW_len)) != MH3D_OK) return bail(st);
+  {
+    // the layer table of the one-launch packing kernels (blocks per layer as one
+    // launch per layer would take, at most 1024)
+    std::vector<PackDesc> pd(n->layers.size());
+    long long goff = 0;
+    for (size_t i = 0; i < n->layers.size(); ++i) {
+      NetLayer& ly = n->layers[i];
+      ly.gWf = n->gW + goff;
+      goff += ((long long)ly.rows_f * ly.kp + 63) & ~63ll;
+      PackDesc& d = pd[i];
+      d.p = n->p + ly.w_off;
+      d.gp = n->g + ly.w_off;
+      d.Wf = ly.Wf;
+      d.Wt = ly.Wt;
+      d.gWf = ly.gWf;
+      d.cin = ly.cin; d.cout = ly.cout; d.ks = ly.ks; d.cs_in = ly.cs_in; d.cs_out = ly.cs_out;
+      d.kp = ly.kp; d.kpt = ly.kpt; d.rows_f = ly.rows_f; d.rows_t = ly.rows_t;
+      d.pb0 = n->pack_blocks;
+      d.pnb = std::min(grid_for((long long)ly.rows_f * ly.kp + (long long)ly.rows_t * ly.kpt), 1024);
+      n->pack_blocks += d.pnb;
+      d.ub0 = n->unpack_blocks;
+      d.unb = std::min(grid_for((long long)ly.cout * ly.ks * ly.ks * ly.ks * ly.cin), 1024);
+      n->unpack_blocks += d.unb;
+    }
+    if ((st = net_alloc((void**)&n->pack, sizeof(PackDesc) * pd.size())) != MH3D_OK) return bail(st);
+    if (hipMemcpy(n->pack, pd.data(), sizeof(PackDesc) * pd.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(MH3D_ERR_HIP, "network layer table upload failed"));
   }
   k_fill_f32<<<grid_for(off + 128), 256, 0, n->stream>>>(n->p, off + 128, 0.f);
   k_fill_f32<<<grid_for(off), 256, 0, n->stream>>>(n->m, off, 0.f);
@@ -552,9 +577,8 @@ extern "C" void mh3d_net_destroy(mh3d_net_t n) {
   for (auto& ly : n->layers) {
     if (ly.Wf) (void)hipFree(ly.Wf);
     if (ly.Wt) (void)hipFree(ly.Wt);
-    if (ly.gWf) (void)hipFree(ly.gWf);
   }
-  void* bufs[] = {n->p, n->g, n->m, n->v};
+  void* bufs[] = {n->p, n->g, n->m, n->v, n->gW, n->pack};
   for (void* q : bufs)
     if (q) (void)hipFree(q);
   delete n;

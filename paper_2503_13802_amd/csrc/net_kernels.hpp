@@ -1010,42 +1010,61 @@ __global__ void k_scale_relu(const float* __restrict__ y, long long n, const dou
     rho[i] = s * fmaxf(y[i], 0.f);
 }
 
+// One layer's matrices for the packing kernels, and the range of the launch's blocks
+// that serve it (every layer in one launch: blocks [b0, b0 + nb) take layer l).
+struct PackDesc {
+  const float* p;          // the layer's weights in the flat FP32 parameters
+  float* gp;               // the layer's weight gradient in the flat FP32 gradient
+  uint16_t* Wf;
+  uint16_t* Wt;
+  const float* gWf;
+  int cin, cout, ks, cs_in, cs_out, kp, kpt, rows_f, rows_t;
+  int pb0, pnb;            // blocks of k_pack_all
+  int ub0, unb;            // blocks of k_unpack_all
+};
+
 // Master FP32 layer parameters (flat layout W[co][tap][cin], bias) -> BF16 GEMM
 // matrices: forward W[co_pad][kp] with k = tap*cs_in + ci, and the flipped,
 // transposed matrix of the data gradient Wt[ci_pad][kpt] with k = tap'*cs_out + co,
-// Wt[ci][tap'][co] = W[co][ntap-1-tap'][ci].
-__global__ void k_pack_layer(const float* __restrict__ p, int cin, int cout, int ks, int cs_in, int cs_out, int kp,
-                             int kpt, int rows_f, int rows_t, uint16_t* __restrict__ Wf, uint16_t* __restrict__ Wt) {
-  const int ntap = ks * ks * ks;
-  const long long nf = (long long)rows_f * kp, nt = (long long)rows_t * kpt;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nf + nt; i += (long long)gridDim.x * blockDim.x) {
+// Wt[ci][tap'][co] = W[co][ntap-1-tap'][ci].  All nl layers in one launch.
+__global__ void k_pack_all(const PackDesc* __restrict__ ds, int nl) {
+  int l = 0;
+  while (l + 1 < nl && (int)blockIdx.x >= ds[l + 1].pb0) ++l;
+  const PackDesc& d = ds[l];
+  const int ntap = d.ks * d.ks * d.ks;
+  const long long nf = (long long)d.rows_f * d.kp, nt = (long long)d.rows_t * d.kpt;
+  for (long long i = (blockIdx.x - d.pb0) * (long long)blockDim.x + threadIdx.x; i < nf + nt;
+       i += (long long)d.pnb * blockDim.x) {
     if (i < nf) {
-      const int co = (int)(i / kp), k = (int)(i - (long long)co * kp);
-      const int tap = k / cs_in, ci = k - tap * cs_in;
+      const int co = (int)(i / d.kp), k = (int)(i - (long long)co * d.kp);
+      const int tap = k / d.cs_in, ci = k - tap * d.cs_in;
       float v = 0.f;
-      if (co < cout && tap < ntap && ci < cin) v = p[((long long)co * ntap + tap) * cin + ci];
-      Wf[i] = f2bf(v);
+      if (co < d.cout && tap < ntap && ci < d.cin) v = d.p[((long long)co * ntap + tap) * d.cin + ci];
+      d.Wf[i] = f2bf(v);
     } else {
       const long long j = i - nf;
-      const int ci = (int)(j / kpt), k = (int)(j - (long long)ci * kpt);
-      const int tp = k / cs_out, co = k - tp * cs_out;
+      const int ci = (int)(j / d.kpt), k = (int)(j - (long long)ci * d.kpt);
+      const int tp = k / d.cs_out, co = k - tp * d.cs_out;
       float v = 0.f;
-      if (ci < cin && tp < ntap && co < cout) v = p[((long long)co * ntap + (ntap - 1 - tp)) * cin + ci];
-      Wt[j] = f2bf(v);
+      if (ci < d.cin && tp < ntap && co < d.cout) v = d.p[((long long)co * ntap + (ntap - 1 - tp)) * d.cin + ci];
+      d.Wt[j] = f2bf(v);
     }
   }
 }
 
-// Gradient of the padded forward GEMM matrix back to the flat layout.
-__global__ void k_unpack_wgrad(const float* __restrict__ gWf, int cin, int cout, int ks, int cs_in, int kp,
-                               float* __restrict__ gp) {
-  const int ntap = ks * ks * ks;
-  const long long n = (long long)cout * ntap * cin;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const int ci = (int)(i % cin);
-    const long long rest = i / cin;
+// Gradient of each padded forward GEMM matrix back to the flat layout, all layers in one launch.
+__global__ void k_unpack_all(const PackDesc* __restrict__ ds, int nl) {
+  int l = 0;
+  while (l + 1 < nl && (int)blockIdx.x >= ds[l + 1].ub0) ++l;
+  const PackDesc& d = ds[l];
+  const int ntap = d.ks * d.ks * d.ks;
+  const long long n = (long long)d.cout * ntap * d.cin;
+  for (long long i = (blockIdx.x - d.ub0) * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)d.unb * blockDim.x) {
+    const int ci = (int)(i % d.cin);
+    const long long rest = i / d.cin;
     const int tap = (int)(rest % ntap), co = (int)(rest / ntap);
-    gp[i] = gWf[(long long)co * kp + tap * cs_in + ci];
+    d.gp[i] = d.gWf[(long long)co * d.kp + tap * d.cs_in + ci];
   }
 }
 
